@@ -1,0 +1,200 @@
+"""Plain FP64 CPU oracle for brute-force incoherent dedispersion.
+
+TEST INFRASTRUCTURE ONLY. This module exists to check the HIP library. Only the
+test suite, the package's smoke check and the benchmark's CPU-baseline leg may
+import it; the product path never calls it and shares no code with it.
+
+What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
+
+* Dispersion delay law, Eq. dispRelationshipEquation (Sec. "Dispersion"):
+  dt = k_DM * DM * (f_1^-2 - f_2^-2), f in MHz. The constant is the paper's
+  approximate dispersion constant, 4.15e3 s MHz^2 pc^-1 cm^3 (the exact value
+  quoted beside it is 4.148808e3; the approximation is the one the method uses).
+* Discretised delay, Eq. deltaTEq (Sec. "Direct Dedispersion"):
+  Delta_t(d, c) = round(DM(d) * k_DM * (f_c^-2 - f_ref^-2) / t_samp), f_ref the
+  top of the band. "round" is read as round-half-away-from-zero in IEEE double.
+* Direct dedispersion, Eq. bruteEquation: D[d, t] = sum_c A[c, t + Delta_t(d, c)],
+  the sum taken in FP64 over every channel, for t in [0, nsamp - maxshift).
+  maxshift = max Delta_t (Sec. 3.4 "Dedispersion", buffer sizing).
+* Per-series mean and standard deviation (population, ddof 0), the
+  normalisation of Sec. 3.5 "Signal Post-processing".
+* n-sigma thresholding into (time, DM, intensity) detections, Sec. 3.6
+  "Detection and Candidate Selection": every (d, t) with D > mean_d + k*rms_d.
+
+Pins (tests/test_oracle_pins.py): a literal triple loop on tiny inputs; exact
+rational delays (fractions.Fraction) away from ties; the paper's diagonal-DM
+formula (Sec. 6.3, 8300 = 2 * 4150) as the derivative of the delay law; the
+zero-DM row equal to the plain channel sum; linearity; impulse response;
+time-shift equivariance; closed-form statistics; the E1 S/N convention (height
+8/sqrt(1024) gives S/N 8); Gaussian-tail false-alarm counts; the paper's
+op-count convention (138e9 ops/s). No function here is "parity unpinned".
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Approximate dispersion constant of Eq. dispRelationshipEquation, in
+# s * MHz^2 * pc^-1 * cm^3 (the paper writes it as 1/2.41e-4 in ms units).
+K_DM = 4.15e3
+
+
+def reference_frequency(freq_mhz) -> float:
+    """f_ref of Eq. deltaTEq: the top of the band, i.e. the largest channel frequency."""
+    f = np.asarray(freq_mhz, dtype=np.float64)
+    return float(f.max())
+
+
+def delay_seconds(freq_mhz, dm, k_dm: float = K_DM):
+    """Continuous delay of every channel relative to f_ref, Eq. dispRelationshipEquation.
+
+    Returns a float64 array [nchan][ndm] in seconds; no rounding.
+    """
+    f = np.asarray(freq_mhz, dtype=np.float64)
+    dms = np.asarray(dm, dtype=np.float64)
+    f_ref = reference_frequency(f)
+    inv_ref = 1.0 / (f_ref * f_ref)
+    inv_c = 1.0 / (f * f)
+    return (k_dm * dms[None, :]) * (inv_c - inv_ref)[:, None]
+
+
+def delay_table(freq_mhz, dm, tsamp_s: float, k_dm: float = K_DM) -> np.ndarray:
+    """Integer delays Delta_t(d, c) of Eq. deltaTEq, laid out [nchan][ndm] (DM fastest).
+
+    Every entry is evaluated in IEEE double in the fixed order
+    x = ((k_dm * DM) * (1/(f*f) - 1/(f_ref*f_ref))) / tsamp, then rounded half
+    away from zero (x >= 0 here). The layout is the channel/DM order the paper
+    stores its shift table in (Sec. 3.4).
+    """
+    f = np.asarray(freq_mhz, dtype=np.float64)
+    dms = np.asarray(dm, dtype=np.float64)
+    if f.ndim != 1 or dms.ndim != 1 or f.size < 1 or dms.size < 1:
+        raise ValueError("need non-empty 1-D frequency and DM lists")
+    if not np.all(np.isfinite(f)) or np.any(f <= 0):
+        raise ValueError("frequencies must be finite and positive")
+    if not np.all(np.isfinite(dms)) or np.any(dms < 0):
+        raise ValueError("DMs must be finite and non-negative")
+    if not (tsamp_s > 0 and math.isfinite(tsamp_s)):
+        raise ValueError("tsamp must be finite and positive")
+    f_ref = reference_frequency(f)
+    inv_ref = 1.0 / (f_ref * f_ref)
+    out = np.empty((f.size, dms.size), dtype=np.int64)
+    for c in range(f.size):
+        diff = 1.0 / (f[c] * f[c]) - inv_ref
+        x = ((k_dm * dms) * diff) / tsamp_s
+        fl = np.floor(x)
+        out[c, :] = fl.astype(np.int64) + ((x - fl) >= 0.5)
+    if out.max() > np.iinfo(np.int32).max:
+        raise ValueError("delay exceeds int32")
+    return out.astype(np.int32)
+
+
+def max_delay(delays: np.ndarray) -> int:
+    """maxshift of Sec. 3.4: the largest delay in the table."""
+    return int(np.asarray(delays).max())
+
+
+def output_length(nsamp: int, delays: np.ndarray) -> int:
+    """Number of output samples per DM series: nsamp - maxshift (must be positive)."""
+    nout = int(nsamp) - max_delay(delays)
+    if nout <= 0:
+        raise ValueError("nsamp must exceed the maximum delay")
+    return nout
+
+
+def dedisperse_row(data: np.ndarray, delay_col: np.ndarray, nout: int) -> np.ndarray:
+    """One dedispersed series D[d, :] of Eq. bruteEquation, summed in FP64.
+
+    data is [nchan][nsamp] in any real dtype (u8 codes are summed as raw codes);
+    delay_col holds Delta_t(d, c) for every channel c of this DM trial.
+    """
+    acc = np.zeros(nout, dtype=np.float64)
+    for c in range(data.shape[0]):
+        s = int(delay_col[c])
+        np.add(acc, data[c, s:s + nout], out=acc)
+    return acc
+
+
+def dedisperse(data: np.ndarray, delays: np.ndarray, rows=None) -> np.ndarray:
+    """Every (or the selected) DM series of Eq. bruteEquation, as float64 [len(rows)][nout]."""
+    data = np.asarray(data)
+    delays = np.asarray(delays)
+    if data.ndim != 2 or delays.ndim != 2 or delays.shape[0] != data.shape[0]:
+        raise ValueError("data must be [nchan][nsamp] and delays [nchan][ndm]")
+    nout = output_length(data.shape[1], delays)
+    sel = range(delays.shape[1]) if rows is None else list(rows)
+    out = np.empty((len(sel), nout), dtype=np.float64)
+    for i, d in enumerate(sel):
+        out[i] = dedisperse_row(data, delays[:, d], nout)
+    return out
+
+
+def dedisperse_point(data: np.ndarray, delays: np.ndarray, d: int, t: int) -> float:
+    """A single output D[d, t], for sampled checks at sizes where whole rows are too slow."""
+    tot = 0.0
+    for c in range(data.shape[0]):
+        tot += float(data[c, t + int(delays[c, d])])
+    return tot
+
+
+def series_stats(series: np.ndarray):
+    """Per-series mean and population standard deviation (Sec. 3.5 normalisation)."""
+    s = np.asarray(series, dtype=np.float64)
+    mean = s.mean(axis=1)
+    rms = np.sqrt(np.mean((s - mean[:, None]) ** 2, axis=1))
+    return mean, rms
+
+
+def candidates(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, k_sigma: float,
+               row_ids=None):
+    """n-sigma detections of Sec. 3.6 in ascending (d, t) order.
+
+    Returns a dict of arrays: dm_index, t, value, snr, where value > mean + k*rms
+    strictly and snr = (value - mean) / rms.
+    """
+    s = np.asarray(series, dtype=np.float64)
+    thr = np.asarray(mean, np.float64) + k_sigma * np.asarray(rms, np.float64)
+    r, t = np.nonzero(s > thr[:, None])
+    ids = np.arange(s.shape[0]) if row_ids is None else np.asarray(row_ids)
+    value = s[r, t]
+    snr = (value - mean[r]) / rms[r]
+    return {"dm_index": ids[r].astype(np.int64), "t": t.astype(np.int64),
+            "value": value, "snr": snr}
+
+
+def threshold_margin(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, k_sigma: float):
+    """min over (d, t) of |D - (mean + k*rms)| / rms: how far every value sits from its threshold."""
+    s = np.asarray(series, dtype=np.float64)
+    thr = mean + k_sigma * rms
+    return float(np.min(np.abs(s - thr[:, None]) / rms[:, None]))
+
+
+def stream_expected(blocks, delays: np.ndarray):
+    """What a stream of consecutive blocks must return, from the one-shot definition.
+
+    The stream's input is the concatenation of the blocks (Sec. 3.4: the last
+    maxshift spectra of one buffer are carried into the next). After block j
+    (j = 0, 1, ...) the outputs that become computable are the global output
+    times [t0, t1) with t1 = (total samples received) - maxshift and t0 the
+    previous t1 (or 0); an empty range means the stream is still filling.
+    Returns a list of (t0, t1, series[ndm][t1-t0] float64) per block.
+    """
+    data = np.concatenate([np.asarray(b) for b in blocks], axis=1)
+    m = max_delay(delays)
+    full = dedisperse(data, delays)
+    res = []
+    total = 0
+    prev = 0
+    for b in blocks:
+        total += np.asarray(b).shape[1]
+        t1 = max(0, total - m)
+        t0 = prev
+        res.append((t0, t1, full[:, t0:t1]))
+        prev = t1
+    return res
+
+
+def algorithmic_adds(ndm: int, nchan: int, nout: int) -> int:
+    """The paper's op convention: one channel-sample add per DM trial (Sec. 3.9, GPU versus FPGA rates)."""
+    return int(ndm) * int(nchan) * int(nout)
