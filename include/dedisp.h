@@ -1,0 +1,217 @@
+/*
+ * dedisp.h - C ABI of the MI355X brute-force dedispersion library (libdedisp.so).
+ *
+ * What it computes (Magro 2013, "A Real-Time, GPU-Based, Non-Imaging Back-End
+ * for Radio Telescopes", Ch. 2 Sec. "Direct Dedispersion" and Ch. 3):
+ *
+ *   delays   Delta_t(d, c) = round(k_DM * DM(d) * (f_c^-2 - f_ref^-2) / t_samp),
+ *            Eq. deltaTEq with the delay law of Eq. dispRelationshipEquation,
+ *            k_DM = 4.15e3 s MHz^2 pc^-1 cm^3, f in MHz, f_ref = max_c f_c,
+ *            evaluated in IEEE double on the host, rounded half away from zero.
+ *   output   D[d][t] = sum_c A[c][t + Delta_t(d, c)], Eq. bruteEquation, for
+ *            t in [0, nout), nout = nsamp - maxdelay, maxdelay = max Delta_t
+ *            (the "maxshift" of Ch. 3 Sec. "Dedispersion").
+ *   stats    mean_d and rms_d (population standard deviation) of each series,
+ *            the normalisation of Ch. 3 Sec. "Signal Post-processing".
+ *   cands    every (d, t) with D[d][t] > mean_d + k * rms_d, Ch. 3 Sec.
+ *            "Detection and Candidate Selection", in ascending (d, t) order.
+ *
+ * Summation order (fixed, independent of tiling and of batching): channels are
+ * summed in FP32 in order inside consecutive blocks of DD_CHAN_BLOCK channels
+ * (c = 0..31, 32..63, ...); the block sums are added to the running series in
+ * block order. u8 inputs are summed as raw codes (exact in FP32 up to 2^24).
+ *
+ * Layouts: the filterbank is channel-major, time fastest ([nchan][row_stride],
+ * Ch. 3 Sec. "Dedispersion" stores data after the transpose); the output is
+ * DM-major ([ndm][out_row_stride]); delay tables are [nchan][ndm], DM fastest.
+ *
+ * Memory: every device pointer is owned by the caller. The library never
+ * allocates device memory; it asks for a workspace size and uses the caller's
+ * buffer. Host arrays passed in are copied; the caller keeps ownership.
+ *
+ * Errors: every call returns a status (0 ok, > 0 informational, < 0 error).
+ * dd_last_error() gives the calling thread's message for the last failure. No
+ * C++ exception crosses this boundary. Work is enqueued on the given HIP stream
+ * (a hipStream_t passed as void*, NULL = the null stream) and the call returns
+ * before the GPU finishes; faults inside a kernel surface at the caller's next
+ * synchronisation.
+ */
+#ifndef DEDISP_H
+#define DEDISP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DD_VERSION_MAJOR 1
+#define DD_VERSION_MINOR 0
+#define DD_CHAN_BLOCK 32
+
+/* Status codes. */
+enum {
+  DD_OK = 0,
+  DD_FILLING = 1,            /* stream push accepted, no output yet (ring still filling) */
+  DD_ERR_INVALID_ARG = -1,   /* a pointer, size or value is out of range */
+  DD_ERR_TOO_SHORT = -2,     /* nsamp <= maxdelay: no output sample can be formed */
+  DD_ERR_SEQUENCE = -3,      /* stream push out of order (seq must grow by one) */
+  DD_ERR_WORKSPACE = -4,     /* workspace (or ring) smaller than dd_plan_query asks for */
+  DD_ERR_HIP = -5,           /* a HIP runtime call failed (message in dd_last_error) */
+  DD_ERR_UNSUPPORTED = -6    /* a tuning or shape the kernels cannot take */
+};
+
+/* Input storage types. All accumulate in FP32. */
+enum { DD_F32 = 0, DD_F16 = 1, DD_U8 = 2 };
+
+typedef struct dd_plan dd_plan;
+typedef struct dd_stream dd_stream;
+
+/* Optional tile choice; zero fields take the library default. */
+typedef struct dd_tuning {
+  int32_t dms_per_wave;       /* DM trials each wavefront accumulates (4, 8 or 16) */
+  int32_t waves;              /* wavefronts per workgroup, each on its own DMs (1, 2, 4 or 8) */
+  int32_t samples_per_lane;   /* consecutive output samples per lane (4, 8 or 16) */
+  int32_t reserved;
+} dd_tuning;
+
+typedef struct dd_plan_info {
+  int32_t nchan, ndm, in_dtype, maxdelay;
+  int64_t nsamp, nout;              /* for the queried nsamp */
+  int64_t workspace_bytes;          /* for dd_dedisperse at this nsamp */
+  int64_t ring_bytes;               /* for dd_stream_create with block_nsamp = nsamp */
+  int32_t dms_per_wave, waves, samples_per_lane, max_span;  /* chosen tiles; LDS span */
+  int64_t adds;                     /* ndm * nchan * nout: the algorithmic work */
+} dd_plan_info;
+
+/* One detection: (time, DM, intensity) of Ch. 3, plus (value - mean) / rms. */
+typedef struct dd_cand {
+  int32_t dm_index;
+  int32_t reserved;
+  int64_t t;          /* output sample (stream pushes: global output time) */
+  float value;
+  float snr;
+} dd_cand;
+
+/*
+ * Build a plan (host only). freq_mhz[nchan] in any order (f_ref = the largest),
+ * dm[ndm] >= 0 in non-decreasing order, tsamp_s > 0, in_dtype one of DD_F32/DD_F16/DD_U8, tuning may
+ * be NULL. Computes the FP64 delay table (Eq. deltaTEq). Errors:
+ * DD_ERR_INVALID_ARG for nchan < 1, ndm < 1, non-finite or non-positive
+ * frequencies, tsamp <= 0, negative, non-finite or decreasing DMs, a delay above 2^31 - 1,
+ * or an unknown dtype; DD_ERR_UNSUPPORTED for a tuning outside the listed
+ * values. The plan is immutable and may be shared between threads.
+ */
+int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
+                   const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning);
+
+/* Free a plan (host memory only). NULL is a no-op. */
+void dd_plan_destroy(dd_plan* plan);
+
+/*
+ * Sizes for a given nsamp: nout, workspace bytes, ring bytes, tiles.
+ * DD_ERR_TOO_SHORT if nsamp <= maxdelay (info is still filled with maxdelay).
+ */
+int dd_plan_query(const dd_plan* plan, int64_t nsamp, dd_plan_info* info);
+
+/* Copy the delay table, [nchan][ndm] int32 DM fastest, into host_out. */
+int dd_plan_delays(const dd_plan* plan, int32_t* host_out);
+
+/*
+ * Prepare a workspace of ws_bytes (>= dd_plan_query's workspace_bytes) on the
+ * current device: uploads this plan's delay table into it on the stream. The
+ * workspace then belongs to this plan until the caller reuses the memory;
+ * dd_dedisperse reads the table from it without checking its contents.
+ */
+int dd_plan_upload(const dd_plan* plan, void* d_workspace, int64_t ws_bytes, void* stream);
+
+/*
+ * Dedisperse one buffer (Eq. bruteEquation) and, optionally, reduce the series.
+ *   d_in        [nchan][in_row_stride] elements of the plan's dtype, nsamp valid
+ *   d_out       [ndm][out_row_stride] float, nout = nsamp - maxdelay written per row
+ *   d_mean/d_rms  [ndm] float each, or both NULL to skip statistics and candidates
+ *   k_sigma     threshold in units of rms; <= 0 (or d_ncand NULL) skips candidates
+ *   d_cand      cand_cap entries; d_ncand (device int64) receives the total count.
+ *               If the count exceeds cand_cap only the first cand_cap (in (d, t)
+ *               order) are written; the caller compares *d_ncand with cand_cap.
+ *   d_workspace prepared by dd_plan_upload, ws_bytes at least the queried size
+ * Strides are in elements; in_row_stride >= nsamp, out_row_stride >= nout.
+ */
+int dd_dedisperse(const dd_plan* plan, const void* d_in, int64_t nsamp, int64_t in_row_stride,
+                  float* d_out, int64_t out_row_stride, float* d_mean, float* d_rms,
+                  float k_sigma, dd_cand* d_cand, int64_t cand_cap, int64_t* d_ncand,
+                  void* d_workspace, int64_t ws_bytes, void* stream);
+
+/*
+ * Streaming (Ch. 3 Sec. "Dedispersion": the last maxshift spectra of a buffer are
+ * carried into the next). A stream keeps a per-channel device ring of the last
+ * maxdelay + block_nsamp samples in the caller's d_ring (ring_bytes >=
+ * dd_plan_query(plan, block_nsamp).ring_bytes). The ring also holds the delay
+ * table, uploaded at creation on the given stream.
+ */
+int dd_stream_create(const dd_plan* plan, int64_t block_nsamp, void* d_ring, int64_t ring_bytes,
+                     void* stream, dd_stream** out);
+
+/*
+ * Append one block (seq = 0, 1, 2, ... in order; nsamp <= block_nsamp samples in
+ * [nchan][in_row_stride]) and dedisperse every output that became computable:
+ * global output times [*t0_out, *t0_out + *nout_out), written to d_out rows from
+ * column 0. Statistics and candidates cover those outputs only; candidate t is the
+ * global output time. Returns DD_FILLING (nothing written) while the stream holds
+ * fewer than maxdelay + 1 samples, DD_ERR_SEQUENCE for a wrong seq (nothing
+ * changes). d_out needs at least block_nsamp columns. Not thread-safe per stream.
+ */
+int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_row_stride,
+                   int64_t seq, float* d_out, int64_t out_row_stride, float* d_mean, float* d_rms,
+                   float k_sigma, dd_cand* d_cand, int64_t cand_cap, int64_t* d_ncand,
+                   void* d_workspace, int64_t ws_bytes, void* stream,
+                   int64_t* t0_out, int64_t* nout_out);
+
+/* Free a stream's host state (the ring is the caller's). NULL is a no-op. */
+void dd_stream_destroy(dd_stream* s);
+
+/*
+ * Batched launch (uneven beams in one persistent launch). Each item names a plan,
+ * an input already resident on the device, and its outputs; or a stream whose
+ * block has already been appended with dd_stream_append. All items run in one
+ * kernel launch that walks a device queue of (item, DM group, time tile) work;
+ * the results equal those of one dd_dedisperse per item, bit for bit.
+ */
+typedef struct dd_batch_item {
+  const dd_plan* plan;
+  const void* d_in;            /* [nchan][in_row_stride]; ignored for stream items */
+  int64_t nsamp, in_row_stride;
+  float* d_out;
+  int64_t out_row_stride;
+  float* d_mean;
+  float* d_rms;
+  float k_sigma;
+  int32_t reserved;
+  dd_cand* d_cand;
+  int64_t cand_cap;
+  int64_t* d_ncand;
+  void* d_plan_workspace;      /* prepared by dd_plan_upload for this item's plan */
+  dd_stream* stream_item;      /* non-NULL: dedisperse this stream's pending window */
+} dd_batch_item;
+
+/* Workspace bytes the batch needs beyond the per-item plan workspaces. */
+int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes);
+
+int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace, int64_t ws_bytes,
+                        void* stream);
+
+/* Copy a block into a stream's ring without dedispersing (the batched path's first half). */
+int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_row_stride,
+                     int64_t seq, void* stream, int64_t* t0_out, int64_t* nout_out);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* dd_last_error(void);
+
+/* "major.minor" of the library. */
+const char* dd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEDISP_H */

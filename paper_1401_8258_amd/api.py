@@ -1,0 +1,220 @@
+"""Python face of libdedisp.so: plans, one-shot dedispersion and streams on torch device memory.
+
+Every computation runs in the library's HIP kernels; this module only allocates
+device buffers with torch, passes pointers and the current HIP stream, and
+unpacks results. There is no fallback: without the built library every call
+raises LibraryMissing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+CAND_DTYPE = np.dtype([("dm_index", "<i4"), ("reserved", "<i4"), ("t", "<i8"), ("value", "<f4"),
+                       ("snr", "<f4")])
+_TORCH_DT = {torch.float32: _lib.DD_F32, torch.float16: _lib.DD_F16, torch.uint8: _lib.DD_U8}
+_NAME_DT = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}
+
+
+def _vp(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def torch_dtype(dtype) -> torch.dtype:
+    return _NAME_DT[dtype] if isinstance(dtype, str) else dtype
+
+
+@dataclasses.dataclass
+class Result:
+    out: torch.Tensor                 # [ndm][nout] float32 (a view when out_row_stride > nout)
+    mean: Optional[torch.Tensor]      # [ndm] float32
+    rms: Optional[torch.Tensor]
+    t0: int = 0                       # global output time of column 0 (streams)
+    _cand: Optional[torch.Tensor] = None
+    _ncand: Optional[torch.Tensor] = None
+    cand_cap: int = 0
+
+    def candidates(self) -> Optional[np.ndarray]:
+        """Detections as a structured numpy array (synchronises the device)."""
+        if self._ncand is None:
+            return None
+        n = int(self._ncand.item())
+        keep = min(n, self.cand_cap)
+        raw = self._cand[: keep * CAND_DTYPE.itemsize].cpu().numpy()
+        return raw.view(CAND_DTYPE)
+
+    def ncand(self) -> Optional[int]:
+        return None if self._ncand is None else int(self._ncand.item())
+
+
+class Plan:
+    """A dedispersion plan: channel frequencies (MHz), sampling time (s), DM trials, input dtype."""
+
+    def __init__(self, freq_mhz, tsamp_s: float, dm, dtype=torch.float32, tuning=None):
+        lib = _lib.load()
+        self._lib = lib
+        self.freq = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+        self.dm = np.ascontiguousarray(dm, dtype=np.float64)
+        self.tsamp = float(tsamp_s)
+        self.dtype = torch_dtype(dtype)
+        if self.dtype not in _TORCH_DT:
+            raise ValueError(f"unsupported input dtype {dtype}")
+        h = C.c_void_p()
+        tun = None
+        if tuning is not None:
+            g, w, s = tuning
+            tun = C.byref(_lib.Tuning(g, w, s, 0))
+        dbl = C.POINTER(C.c_double)
+        check(lib.dd_plan_create(C.byref(h), self.freq.ctypes.data_as(dbl), int(self.freq.size), self.tsamp,
+                                 self.dm.ctypes.data_as(dbl), int(self.dm.size), _TORCH_DT[self.dtype], tun))
+        self._h = h
+        self._ws = {}
+        info = self.query(1, allow_short=True)
+        self.maxdelay = int(info["maxdelay"])
+        self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(info["samples_per_lane"]))
+        self.max_span = int(info["max_span"])
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    @property
+    def nchan(self) -> int:
+        return int(self.freq.size)
+
+    @property
+    def ndm(self) -> int:
+        return int(self.dm.size)
+
+    def query(self, nsamp: int, allow_short: bool = False) -> dict:
+        inf = _lib.PlanInfo()
+        allow = (_lib.DD_OK, _lib.DD_ERR_TOO_SHORT) if allow_short else (_lib.DD_OK,)
+        check(self._lib.dd_plan_query(self._h, int(nsamp), C.byref(inf)), allow)
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def delays(self) -> np.ndarray:
+        out = np.empty((self.nchan, self.ndm), dtype=np.int32)
+        check(self._lib.dd_plan_delays(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
+
+    def workspace(self, nsamp: int, device=None, stream=None) -> torch.Tensor:
+        """A device workspace for nsamp-sample inputs with this plan's delay table uploaded (cached)."""
+        device = torch.device(device if device is not None else "cuda")
+        nbytes = int(self.query(nsamp, allow_short=True)["workspace_bytes"])
+        key = (device.index if device.index is not None else torch.cuda.current_device(), nbytes)
+        ws = self._ws.get(key)
+        if ws is None:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            check(self._lib.dd_plan_upload(self._h, _vp(ws), nbytes, _stream(stream)))
+            self._ws[key] = ws
+        return ws
+
+    def dedisperse(self, x: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True,
+                   out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                   stream=None) -> Result:
+        """D[d][t] = sum_c x[c][t + delay(d, c)] for t < nsamp - maxdelay (Eq. bruteEquation)."""
+        if x.dim() != 2 or x.shape[0] != self.nchan or x.dtype != self.dtype or not x.is_cuda:
+            raise ValueError(f"x must be a CUDA [nchan={self.nchan}][nsamp] {self.dtype} tensor")
+        if x.stride(1) != 1:
+            raise ValueError("x rows must be contiguous in time")
+        nsamp = int(x.shape[1])
+        nout = nsamp - self.maxdelay
+        if out is None:
+            out = torch.empty((self.ndm, max(nout, 1)), dtype=torch.float32, device=x.device)
+        ws = workspace if workspace is not None else self.workspace(nsamp, x.device, stream)
+        mean = rms = cand = ncand = None
+        if stats:
+            mean = torch.empty(self.ndm, dtype=torch.float32, device=x.device)
+            rms = torch.empty(self.ndm, dtype=torch.float32, device=x.device)
+            if k_sigma > 0:
+                cand = torch.empty(max(cand_cap, 1) * CAND_DTYPE.itemsize, dtype=torch.uint8, device=x.device)
+                ncand = torch.zeros(1, dtype=torch.int64, device=x.device)
+        check(self._lib.dd_dedisperse(self._h, _vp(x), nsamp, int(x.stride(0)), _vp(out), int(out.stride(0)),
+                                      _vp(mean), _vp(rms), float(k_sigma), _vp(cand), int(cand_cap if cand is not None else 0),
+                                      _vp(ncand), _vp(ws), int(ws.numel()), _stream(stream)))
+        return Result(out[:, :nout], mean, rms, 0, cand, ncand, cand_cap)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dd_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """A beam's stream: device ring of maxdelay + block samples per channel (Ch. 3, buffer overlap)."""
+
+    def __init__(self, plan: Plan, block_nsamp: int, device=None, stream=None):
+        self.plan = plan
+        self._lib = plan._lib
+        self.block = int(block_nsamp)
+        device = torch.device(device if device is not None else "cuda")
+        self.device = device
+        info = plan.query(self.block, allow_short=True)
+        self.ring = torch.empty(int(info["ring_bytes"]), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(int(info["workspace_bytes"]), dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        check(self._lib.dd_stream_create(plan.handle, self.block, _vp(self.ring), int(self.ring.numel()),
+                                         _stream(stream), C.byref(h)))
+        self._h = h
+        self.seq = 0
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def push(self, block: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 14, stats: bool = True,
+             out: Optional[torch.Tensor] = None, stream=None) -> Optional[Result]:
+        """Append a block; returns the newly computable outputs, or None while the ring fills."""
+        p = self.plan
+        if block.dim() != 2 or block.shape[0] != p.nchan or block.dtype != p.dtype or block.stride(1) != 1:
+            raise ValueError("block must be [nchan][n] of the plan dtype, time contiguous")
+        dev = block.device
+        if out is None:
+            out = torch.empty((p.ndm, self.block), dtype=torch.float32, device=dev)
+        mean = rms = cand = ncand = None
+        if stats:
+            mean = torch.empty(p.ndm, dtype=torch.float32, device=dev)
+            rms = torch.empty(p.ndm, dtype=torch.float32, device=dev)
+            if k_sigma > 0:
+                cand = torch.empty(max(cand_cap, 1) * CAND_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+                ncand = torch.zeros(1, dtype=torch.int64, device=dev)
+        t0 = C.c_int64()
+        n = C.c_int64()
+        rc = check(self._lib.dd_stream_push(self._h, _vp(block), int(block.shape[1]), int(block.stride(0)),
+                                            self.seq, _vp(out), int(out.stride(0)), _vp(mean), _vp(rms),
+                                            float(k_sigma), _vp(cand), int(cand_cap if cand is not None else 0),
+                                            _vp(ncand), _vp(self.ws), int(self.ws.numel()), _stream(stream),
+                                            C.byref(t0), C.byref(n)), (_lib.DD_OK, _lib.DD_FILLING))
+        self.seq += 1
+        if rc == _lib.DD_FILLING:
+            return None
+        return Result(out[:, : n.value], mean, rms, t0.value, cand, ncand, cand_cap)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dd_stream_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,75 @@
+// Internal declarations shared by the host plan code and the HIP launch code.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dedisp.h"
+
+namespace dd {
+
+// Byte alignment of every region inside a workspace or ring.
+constexpr int64_t kAlign = 256;
+// Output samples per statistics segment: the fixed reduction tree of the
+// per-series mean and standard deviation (independent of tiles and batching).
+constexpr int64_t kStatSeg = 8192;
+
+inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a * a; }
+
+struct Tiles {
+  int32_t g;   // DM trials per wavefront
+  int32_t w;   // wavefronts per workgroup (each on its own G trials)
+  int32_t s;   // output samples per lane (lane-strided by 64)
+  int32_t cc;  // channels staged into LDS per barrier pair
+};
+
+}  // namespace dd
+
+struct dd_plan {
+  int32_t nchan = 0, ndm = 0, dtype = DD_F32;
+  double tsamp = 0.0;
+  std::vector<double> freq, dm;
+  std::vector<int32_t> delays;      // [nchan][ndm], Eq. deltaTEq
+  int32_t maxdelay = 0;
+  dd::Tiles tiles{};
+  int32_t dms_per_group = 0;        // g * w
+  int32_t ngroups = 0;
+  int32_t ndm_pad = 0;              // ngroups * dms_per_group
+  std::vector<int32_t> dev_table;   // [nchan][ndm_pad]; padded trials repeat the last DM
+  int32_t max_span = 0;             // max over channels and groups of the in-group delay spread
+  uint64_t id = 0;
+};
+
+struct dd_stream {
+  const dd_plan* plan = nullptr;
+  int64_t block = 0;        // largest block accepted
+  int64_t ring_len = 0;     // R: samples per channel in the ring
+  void* ring = nullptr;     // device: [table | ring data]
+  int64_t received = 0;     // total samples appended
+  int64_t next_seq = 0;
+  int64_t emitted = 0;      // global output times already produced ([0, emitted))
+  int64_t pending_t0 = 0, pending_n = 0;  // window appended but not yet dedispersed
+};
+
+namespace dd {
+
+// Thread-local error message helpers (implemented in plan.cpp).
+int fail(int code, const std::string& msg);
+void clear_error();
+
+// Workspace layout for one dd_dedisperse call.
+struct WsLayout {
+  int64_t table_off, table_bytes;
+  int64_t part_off;    // double [ndm][nseg][2]
+  int64_t thr_off;     // double [ndm][3]: mean, rms, threshold
+  int64_t cnt_off;     // int32 [ndm][nseg]
+  int64_t offs_off;    // int64 [ndm][nseg]
+  int64_t nseg;
+  int64_t total;
+};
+WsLayout workspace_layout(const dd_plan* p, int64_t nout);
+int64_t ring_table_bytes(const dd_plan* p);
+int64_t elem_bytes(int32_t dtype);
+
+}  // namespace dd

@@ -1,0 +1,190 @@
+// Host side of the plan: validation, the FP64 delay table (Eq. deltaTEq), tile choice,
+// workspace sizing. Built with -ffp-contract=off so each double operation rounds once.
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+
+#include "dd_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+std::atomic<uint64_t> g_next_id{1};
+
+// Approximate dispersion constant of Eq. dispRelationshipEquation (s MHz^2 pc^-1 cm^3).
+constexpr double kDm = 4.15e3;
+
+bool valid_tiles(const dd::Tiles& t) {
+  auto in = [](int v, std::initializer_list<int> xs) {
+    for (int x : xs) if (v == x) return true;
+    return false;
+  };
+  return in(t.g, {4, 8, 16}) && in(t.w, {1, 2, 4, 8}) && in(t.s, {4, 8, 16}) && in(t.cc, {8});
+}
+
+}  // namespace
+
+namespace dd {
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+void clear_error() { g_err.clear(); }
+
+int64_t elem_bytes(int32_t dtype) { return dtype == DD_F32 ? 4 : dtype == DD_F16 ? 2 : 1; }
+
+WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
+  WsLayout l{};
+  l.table_off = 0;
+  l.table_bytes = (int64_t)p->nchan * p->ndm_pad * 4;
+  l.nseg = nout > 0 ? (nout + kStatSeg - 1) / kStatSeg : 1;
+  int64_t o = align_up(l.table_bytes);
+  l.part_off = o;
+  o = align_up(o + (int64_t)p->ndm * l.nseg * 16);
+  l.thr_off = o;
+  o = align_up(o + (int64_t)p->ndm * 24);  // {mean, rms, threshold} per trial
+  l.cnt_off = o;
+  o = align_up(o + (int64_t)p->ndm * l.nseg * 4);
+  l.offs_off = o;
+  o = align_up(o + (int64_t)p->ndm * l.nseg * 8 + 8);
+  l.total = o;
+  return l;
+}
+
+int64_t ring_table_bytes(const dd_plan* p) { return align_up((int64_t)p->nchan * p->ndm_pad * 4); }
+
+}  // namespace dd
+
+extern "C" {
+
+const char* dd_last_error(void) { return g_err.c_str(); }
+
+const char* dd_version(void) { return "1.0"; }
+
+int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
+                   const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning) {
+  dd::clear_error();
+  if (!out) return dd::fail(DD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!freq_mhz || !dm) return dd::fail(DD_ERR_INVALID_ARG, "freq_mhz and dm must be non-NULL");
+  if (nchan < 1 || ndm < 1) return dd::fail(DD_ERR_INVALID_ARG, "nchan and ndm must be >= 1");
+  if (!(tsamp_s > 0.0) || !std::isfinite(tsamp_s))
+    return dd::fail(DD_ERR_INVALID_ARG, "tsamp must be finite and > 0");
+  if (in_dtype != DD_F32 && in_dtype != DD_F16 && in_dtype != DD_U8)
+    return dd::fail(DD_ERR_INVALID_ARG, "unknown input dtype");
+  double fmax = 0.0;
+  for (int32_t c = 0; c < nchan; ++c) {
+    if (!std::isfinite(freq_mhz[c]) || !(freq_mhz[c] > 0.0))
+      return dd::fail(DD_ERR_INVALID_ARG, "frequencies must be finite and > 0 (channel " +
+                                              std::to_string(c) + ")");
+    if (freq_mhz[c] > fmax) fmax = freq_mhz[c];
+  }
+  for (int32_t d = 0; d < ndm; ++d) {
+    if (!std::isfinite(dm[d]) || dm[d] < 0.0)
+      return dd::fail(DD_ERR_INVALID_ARG, "DMs must be finite and >= 0 (trial " + std::to_string(d) + ")");
+    if (d > 0 && dm[d] < dm[d - 1])
+      return dd::fail(DD_ERR_INVALID_ARG, "DM trials must be in non-decreasing order");
+  }
+
+  dd::Tiles t{8, 4, 8, 8};
+  if (tuning) {
+    if (tuning->dms_per_wave) t.g = tuning->dms_per_wave;
+    if (tuning->waves) t.w = tuning->waves;
+    if (tuning->samples_per_lane) t.s = tuning->samples_per_lane;
+  }
+  if (!valid_tiles(t)) return dd::fail(DD_ERR_UNSUPPORTED, "unsupported tuning");
+
+  dd_plan* p = new (std::nothrow) dd_plan();
+  if (!p) return dd::fail(DD_ERR_INVALID_ARG, "out of host memory");
+  p->nchan = nchan;
+  p->ndm = ndm;
+  p->dtype = in_dtype;
+  p->tsamp = tsamp_s;
+  p->freq.assign(freq_mhz, freq_mhz + nchan);
+  p->dm.assign(dm, dm + ndm);
+  p->delays.resize((size_t)nchan * ndm);
+
+  // Eq. deltaTEq: x = ((k * DM) * (1/(f*f) - 1/(fr*fr))) / tsamp, round half away from zero.
+  const double inv_ref = 1.0 / (fmax * fmax);
+  int64_t maxd = 0;
+  for (int32_t c = 0; c < nchan; ++c) {
+    const double diff = 1.0 / (freq_mhz[c] * freq_mhz[c]) - inv_ref;
+    for (int32_t d = 0; d < ndm; ++d) {
+      const double x = ((kDm * dm[d]) * diff) / tsamp_s;
+      const double fl = std::floor(x);
+      const double r = fl + ((x - fl) >= 0.5 ? 1.0 : 0.0);
+      if (!(r <= (double)std::numeric_limits<int32_t>::max())) {
+        delete p;
+        return dd::fail(DD_ERR_INVALID_ARG, "delay exceeds 2^31-1 samples");
+      }
+      const int32_t v = (int32_t)r;
+      p->delays[(size_t)c * ndm + d] = v;
+      if (v > maxd) maxd = v;
+    }
+  }
+  p->maxdelay = (int32_t)maxd;
+
+  p->tiles = t;
+  p->dms_per_group = t.g * t.w;
+  p->ngroups = (ndm + p->dms_per_group - 1) / p->dms_per_group;
+  p->ndm_pad = p->ngroups * p->dms_per_group;
+  p->dev_table.resize((size_t)nchan * p->ndm_pad);
+  int32_t span = 0;
+  for (int32_t c = 0; c < nchan; ++c) {
+    const int32_t* row = &p->delays[(size_t)c * ndm];
+    int32_t* drow = &p->dev_table[(size_t)c * p->ndm_pad];
+    for (int32_t d = 0; d < p->ndm_pad; ++d) drow[d] = row[d < ndm ? d : ndm - 1];
+    for (int32_t gi = 0; gi < p->ngroups; ++gi) {
+      const int32_t sp = drow[gi * p->dms_per_group + p->dms_per_group - 1] - drow[gi * p->dms_per_group];
+      if (sp > span) span = sp;
+    }
+  }
+  p->max_span = span;
+  p->id = g_next_id.fetch_add(1);
+  *out = p;
+  return DD_OK;
+}
+
+void dd_plan_destroy(dd_plan* plan) { delete plan; }
+
+int dd_plan_query(const dd_plan* p, int64_t nsamp, dd_plan_info* info) {
+  dd::clear_error();
+  if (!p || !info) return dd::fail(DD_ERR_INVALID_ARG, "plan and info must be non-NULL");
+  std::memset(info, 0, sizeof(*info));
+  info->nchan = p->nchan;
+  info->ndm = p->ndm;
+  info->in_dtype = p->dtype;
+  info->maxdelay = p->maxdelay;
+  info->nsamp = nsamp;
+  info->dms_per_wave = p->tiles.g;
+  info->waves = p->tiles.w;
+  info->samples_per_lane = p->tiles.s;
+  info->max_span = p->max_span;
+  if (nsamp <= 0) return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be > 0");
+  const int64_t ring_len = dd::align_up(nsamp + (int64_t)p->maxdelay, 64);
+  info->ring_bytes = dd::ring_table_bytes(p) + dd::align_up(ring_len * p->nchan * dd::elem_bytes(p->dtype));
+  const int64_t nout = nsamp - p->maxdelay;
+  // sized for nsamp outputs: covers a plain call (nout < nsamp) and a stream push (<= block)
+  const dd::WsLayout l = dd::workspace_layout(p, nsamp);
+  info->workspace_bytes = l.total;
+  if (nout <= 0) {
+    info->nout = 0;
+    return dd::fail(DD_ERR_TOO_SHORT, "nsamp must exceed maxdelay (" + std::to_string(p->maxdelay) + ")");
+  }
+  info->nout = nout;
+  info->adds = (int64_t)p->ndm * p->nchan * nout;
+  return DD_OK;
+}
+
+int dd_plan_delays(const dd_plan* p, int32_t* host_out) {
+  dd::clear_error();
+  if (!p || !host_out) return dd::fail(DD_ERR_INVALID_ARG, "plan and host_out must be non-NULL");
+  std::memcpy(host_out, p->delays.data(), p->delays.size() * sizeof(int32_t));
+  return DD_OK;
+}
+
+}  // extern "C"

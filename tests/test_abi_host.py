@@ -1,0 +1,151 @@
+"""The C ABI without a GPU: every declared symbol is exported, host-only calls validate and
+the FP64 delay table matches the oracle bit for bit (Eq. deltaTEq)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import fbsynth
+from oracle import dedisp_oracle as orc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+lib_mod = pytest.importorskip("paper_1401_8258_amd._lib")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return lib_mod.load()
+    except lib_mod.LibraryMissing as e:  # the build step has not run in this checkout
+        pytest.skip(str(e))
+
+
+def _header_functions():
+    with open(os.path.join(ROOT, "include", "dedisp.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dd_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in lib_mod.SIGNATURES, n
+    assert lib.dd_version().decode() == "1.0"
+
+
+def _create(lib, freq, dm, tsamp, dtype=0, tuning=None):
+    h = C.c_void_p()
+    f = np.ascontiguousarray(freq, np.float64)
+    d = np.ascontiguousarray(dm, np.float64)
+    dbl = C.POINTER(C.c_double)
+    tun = C.byref(lib_mod.Tuning(*tuning, 0)) if tuning else None
+    rc = lib.dd_plan_create(C.byref(h), f.ctypes.data_as(dbl), f.size, tsamp, d.ctypes.data_as(dbl), d.size,
+                            dtype, tun)
+    return rc, h
+
+
+def _delays(lib, h, nchan, ndm):
+    out = np.empty((nchan, ndm), np.int32)
+    assert lib.dd_plan_delays(h, out.ctypes.data_as(C.POINTER(C.c_int32))) == 0
+    return out
+
+
+@pytest.mark.parametrize("name,nchan,f_top,bw,tsamp,step,ndm", [
+    ("64ch small", 64, 428.0, 20.0, 51.2e-6, 0.1, 128),
+    ("1024ch full", 1024, 428.0, 20.0, 51.2e-6, 0.1, 2048),
+    ("4096ch low band", 4096, 180.0, 60.0, 81.92e-6, 0.05, 4096),
+    ("256ch wide step", 256, 428.0, 20.0, 51.2e-6, 0.2, 4096),
+])
+def test_delay_table_bit_exact(lib, name, nchan, f_top, bw, tsamp, step, ndm):
+    freq = fbsynth.channel_freqs(f_top, bw / nchan, nchan)
+    dm = fbsynth.dm_trials(0.0, step, ndm)
+    rc, h = _create(lib, freq, dm, tsamp)
+    assert rc == 0
+    try:
+        got = _delays(lib, h, nchan, ndm)
+        want = orc.delay_table(freq, dm, tsamp)
+        np.testing.assert_array_equal(got, want)
+        # guard: no entry sits within 1e-9 of a rounding tie, so FP64 evaluation order cannot flip one
+        x = orc.delay_seconds(freq, dm) / tsamp
+        frac = x - np.floor(x)
+        assert np.min(np.abs(frac - 0.5)) > 1e-9
+        info = lib_mod.PlanInfo()
+        assert lib.dd_plan_query(h, 1 << 20, C.byref(info)) in (0, -2)
+        assert info.maxdelay == want.max()
+    finally:
+        lib.dd_plan_destroy(h)
+
+
+def test_known_maxdelays(lib):
+    for freq, dm, tsamp, want in [
+        (fbsynth.channel_freqs(428.0, 0.3125, 64), fbsynth.dm_trials(0, 0.1, 128), 51.2e-6, 555),
+        (fbsynth.channel_freqs(428.0, 20 / 1024, 1024), fbsynth.dm_trials(0, 0.1, 2048), 51.2e-6, 9088),
+    ]:
+        rc, h = _create(lib, freq, dm, tsamp)
+        assert rc == 0
+        info = lib_mod.PlanInfo()
+        assert lib.dd_plan_query(h, 16384 if want == 555 else 1 << 20, C.byref(info)) == 0
+        assert info.maxdelay == want
+        assert info.nout == (16384 if want == 555 else 1 << 20) - want
+        assert info.adds == info.ndm * info.nchan * info.nout
+        lib.dd_plan_destroy(h)
+
+
+def test_plan_validation_codes(lib):
+    f = [428.0, 427.0, 426.0]
+    bad = [
+        ([428.0, -1.0], [1.0], 1e-4, 0),
+        ([428.0, float("inf")], [1.0], 1e-4, 0),
+        (f, [-0.1], 1e-4, 0),
+        (f, [float("nan")], 1e-4, 0),
+        (f, [2.0, 1.0], 1e-4, 0),        # decreasing DMs
+        (f, [1.0], 0.0, 0),
+        (f, [1.0], -1.0, 0),
+        (f, [1.0], 1e-4, 7),             # unknown dtype
+        (f, [1e12], 1e-9, 0),            # delay beyond int32
+    ]
+    for freq, dm, tsamp, dt in bad:
+        rc, h = _create(lib, freq, dm, tsamp, dt)
+        assert rc == lib_mod.DD_ERR_INVALID_ARG, (freq, dm, tsamp, dt)
+        assert not h.value
+        assert len(lib.dd_last_error()) > 0
+    rc, h = _create(lib, f, [1.0], 1e-4, 0, tuning=(3, 4, 8))
+    assert rc == lib_mod.DD_ERR_UNSUPPORTED
+    rc, h = _create(lib, [], [1.0], 1e-4)
+    assert rc == lib_mod.DD_ERR_INVALID_ARG
+    lib.dd_plan_destroy(None)  # null-safe
+    lib.dd_stream_destroy(None)
+
+
+def test_query_too_short_and_sizes(lib):
+    freq = fbsynth.channel_freqs(428.0, 0.3125, 64)
+    rc, h = _create(lib, freq, fbsynth.dm_trials(0, 0.1, 128), 51.2e-6)
+    assert rc == 0
+    info = lib_mod.PlanInfo()
+    assert lib.dd_plan_query(h, 555, C.byref(info)) == lib_mod.DD_ERR_TOO_SHORT
+    assert info.maxdelay == 555 and info.nout == 0
+    assert b"maxdelay" in lib.dd_last_error()
+    assert lib.dd_plan_query(h, 556, C.byref(info)) == 0 and info.nout == 1
+    assert info.workspace_bytes >= 64 * 128 * 4
+    assert info.ring_bytes >= 64 * (556 + 555) * 4
+    # device entry points reject bad arguments before touching the GPU
+    assert lib.dd_dedisperse(h, None, 1000, 1000, None, 1000, None, None, 0.0, None, 0, None, None, 0,
+                             None) == lib_mod.DD_ERR_INVALID_ARG
+    lib.dd_plan_destroy(h)
+
+
+def test_explicit_channel_order(lib):
+    """Frequencies in any order: f_ref is the largest, each channel keeps its own delay."""
+    freq = fbsynth.channel_freqs(428.0, 0.3125, 64)
+    perm = np.random.default_rng(0).permutation(64)
+    dm = fbsynth.dm_trials(0, 0.1, 40)
+    rc, h = _create(lib, freq[perm], dm, 51.2e-6)
+    assert rc == 0
+    got = _delays(lib, h, 64, 40)
+    np.testing.assert_array_equal(got, orc.delay_table(freq, dm, 51.2e-6)[perm])
+    lib.dd_plan_destroy(h)
