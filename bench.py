@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-rows", type=int, default=12, help="DM rows in the oracle sample")
-    ap.add_argument("--tuning", type=str, default=None, help="g,w,s tile override")
+    ap.add_argument("--tuning", type=str, default=None, help="dms_per_wave,waves[,chan_stage] tile override")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON with measured HBM fetch/write bytes per launch of the dedispersion kernel")
     return ap.parse_args()

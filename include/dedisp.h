@@ -69,10 +69,10 @@ typedef struct dd_stream dd_stream;
 
 /* Optional tile choice; zero fields take the library default. */
 typedef struct dd_tuning {
-  int32_t dms_per_wave;       /* DM trials each wavefront accumulates (4, 8 or 16) */
+  int32_t dms_per_wave;       /* DM trials each wavefront accumulates (4 or 8) */
   int32_t waves;              /* wavefronts per workgroup, each on its own DMs (1, 2, 4 or 8) */
-  int32_t samples_per_lane;   /* consecutive output samples per lane (4, 8 or 16) */
-  int32_t reserved;
+  int32_t samples_per_lane;   /* output samples per lane: 8 (the tile is 512 samples) */
+  int32_t chan_stage;         /* channels staged into LDS per barrier pair (1..32) */
 } dd_tuning;
 
 typedef struct dd_plan_info {
@@ -82,6 +82,7 @@ typedef struct dd_plan_info {
   int64_t ring_bytes;               /* for dd_stream_create with block_nsamp = nsamp */
   int32_t dms_per_wave, waves, samples_per_lane, max_span;  /* chosen tiles; LDS span */
   int64_t adds;                     /* ndm * nchan * nout: the algorithmic work */
+  int32_t chan_stage, reserved;     /* channels per LDS stage (0 = chosen at launch) */
 } dd_plan_info;
 
 /* One detection: (time, DM, intensity) of Ch. 3, plus (value - mean) / rms. */

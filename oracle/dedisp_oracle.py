@@ -164,10 +164,15 @@ def candidates(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, k_sigma: f
 
 
 def threshold_margin(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, k_sigma: float):
-    """min over (d, t) of |D - (mean + k*rms)| / rms: how far every value sits from its threshold."""
+    """min over (d, t) of |D - (mean + k*rms)| / rms: how far every value sits from its threshold.
+
+    Rows with rms = 0 (constant series) have no value above their threshold and are skipped."""
     s = np.asarray(series, dtype=np.float64)
     thr = mean + k_sigma * rms
-    return float(np.min(np.abs(s - thr[:, None]) / rms[:, None]))
+    keep = np.asarray(rms) > 0
+    if not np.any(keep):
+        return float("inf")
+    return float(np.min(np.abs(s[keep] - thr[keep, None]) / rms[keep, None]))
 
 
 def stream_expected(blocks, delays: np.ndarray):

@@ -20,7 +20,7 @@ CHAN_BLOCK = 32
 
 class Tuning(C.Structure):
     _fields_ = [("dms_per_wave", C.c_int32), ("waves", C.c_int32),
-                ("samples_per_lane", C.c_int32), ("reserved", C.c_int32)]
+                ("samples_per_lane", C.c_int32), ("chan_stage", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -29,7 +29,7 @@ class PlanInfo(C.Structure):
                 ("workspace_bytes", C.c_int64), ("ring_bytes", C.c_int64),
                 ("dms_per_wave", C.c_int32), ("waves", C.c_int32),
                 ("samples_per_lane", C.c_int32), ("max_span", C.c_int32),
-                ("adds", C.c_int64)]
+                ("adds", C.c_int64), ("chan_stage", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Cand(C.Structure):

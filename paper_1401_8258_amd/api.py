@@ -73,9 +73,10 @@ class Plan:
             raise ValueError(f"unsupported input dtype {dtype}")
         h = C.c_void_p()
         tun = None
-        if tuning is not None:
-            g, w, s = tuning
-            tun = C.byref(_lib.Tuning(g, w, s, 0))
+        if tuning is not None:  # (dms_per_wave, waves[, chan_stage])
+            g, w = int(tuning[0]), int(tuning[1])
+            cc = int(tuning[2]) if len(tuning) > 2 else 0
+            tun = C.byref(_lib.Tuning(g, w, 8, cc))
         dbl = C.POINTER(C.c_double)
         check(lib.dd_plan_create(C.byref(h), self.freq.ctypes.data_as(dbl), int(self.freq.size), self.tsamp,
                                  self.dm.ctypes.data_as(dbl), int(self.dm.size), _TORCH_DT[self.dtype], tun))
@@ -83,7 +84,7 @@ class Plan:
         self._ws = {}
         info = self.query(1, allow_short=True)
         self.maxdelay = int(info["maxdelay"])
-        self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(info["samples_per_lane"]))
+        self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(info["chan_stage"]))
         self.max_span = int(info["max_span"])
 
     @property

@@ -11,17 +11,38 @@ namespace dd {
 
 // Byte alignment of every region inside a workspace or ring.
 constexpr int64_t kAlign = 256;
-// Output samples per statistics segment: the fixed reduction tree of the
-// per-series mean and standard deviation (independent of tiles and batching).
+// Output samples per time tile of the dedispersion kernel; also the segment of
+// the per-series statistics partials (fixed, so the reduction tree does not
+// depend on the launch shape or on batching).
+constexpr int64_t kTile = 512;
+// Output samples per candidate-compaction segment.
 constexpr int64_t kStatSeg = 8192;
+// Register window of the dedispersion kernel: 8 accumulators per lane per DM trial,
+// in-window delays 0..kWinKmax (must match window_add.inc).
+constexpr int kWinS = 8;
+constexpr int kWinKmax = 36;
+constexpr int kWinChunks = (kWinS + kWinKmax) / 4;
+// LDS of one gfx950 workgroup.
+constexpr int64_t kLdsBytes = 160 * 1024;
+
+// Launch geometry of the dedispersion kernel.
+struct Launch {
+  bool window;  // register-window mode (else four shifted LDS copies)
+  int L;        // dwords per (channel, copy) buffer
+  int cs;       // channels per stage
+  int nb;       // stages in the LDS ring
+  int nd;       // DMA instructions per wavefront per stage
+  int64_t lds;  // bytes
+};
+Launch choose_launch(int32_t max_span, int32_t wave_span, int nw, int nchan, int cs_req, int64_t lds_cap);
 
 inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a * a; }
 
 struct Tiles {
   int32_t g;   // DM trials per wavefront
   int32_t w;   // wavefronts per workgroup (each on its own G trials)
-  int32_t s;   // output samples per lane (lane-strided by 64)
-  int32_t cc;  // channels staged into LDS per barrier pair
+  int32_t s;   // output samples per lane (fixed: 8, two chunks of 4)
+  int32_t cc;  // channels staged into LDS per barrier pair (0 = automatic)
 };
 
 }  // namespace dd
@@ -38,6 +59,7 @@ struct dd_plan {
   int32_t ndm_pad = 0;              // ngroups * dms_per_group
   std::vector<int32_t> dev_table;   // [nchan][ndm_pad]; padded trials repeat the last DM
   int32_t max_span = 0;             // max over channels and groups of the in-group delay spread
+  int32_t wave_span = 0;            // max in-window delay of one wavefront (its spread + misalignment)
   uint64_t id = 0;
 };
 
@@ -61,11 +83,12 @@ void clear_error();
 // Workspace layout for one dd_dedisperse call.
 struct WsLayout {
   int64_t table_off, table_bytes;
-  int64_t part_off;    // double [ndm][nseg][2]
+  int64_t part_off;    // double [ndm][ntile][2]: sum x, sum x^2 per 512-sample tile
   int64_t thr_off;     // double [ndm][3]: mean, rms, threshold
   int64_t cnt_off;     // int32 [ndm][nseg]
   int64_t offs_off;    // int64 [ndm][nseg]
-  int64_t nseg;
+  int64_t nseg;        // candidate segments
+  int64_t ntile;       // statistics segments
   int64_t total;
 };
 WsLayout workspace_layout(const dd_plan* p, int64_t nout);

@@ -7,8 +7,10 @@
 //                  a few channels per barrier pair and shared by every wavefront of
 //                  the workgroup; each wavefront accumulates its own DM trials in
 //                  VGPRs. Delays are wave-uniform and come in through scalar loads.
-//   stats_*        per-series mean and standard deviation over fixed 8192-sample
-//                  segments (wavefront reductions, FP64), then an in-order finalize.
+//                  The epilogue writes the tile and its FP64 statistics partials.
+//   stats_finalize per-series mean and standard deviation from the FP64 partial sums
+//                  (sum x, sum x^2) that dedisp_tile writes per 512-sample tile with a
+//                  fixed wavefront reduction tree; tiles are summed in order.
 //   cand_*         n-sigma detections: per-segment counts, one exclusive scan, and an
 //                  ordered ballot compaction, so candidates come out in (d, t) order.
 //   ring_append    copies a block into a stream's per-channel ring (wrap-aware).
@@ -16,6 +18,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -40,87 +43,319 @@ struct InView {
   int64_t win0;        // ring only: global sample of window position 0
 };
 
-// One workgroup = W wavefronts x G DM trials each, over T = 64 * S output samples.
-// Lane l of every wavefront owns outputs t0 + l + 64 s, s < S.
-template <typename TIn, int G, int S, bool RING>
-__global__ __launch_bounds__(kMaxThreads) void dedisp_tile(
-    InView in, const int32_t* __restrict__ dtab, int ndm_pad, int nchan, int ndm,
-    float* __restrict__ out, int64_t out_stride, int64_t nout, int len_max, int cc_n) {
-  constexpr int T = 64 * S;
-  extern __shared__ float smem[];
-  const int nt = blockDim.x;
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gw = G * (nt >> 6);  // DM trials per workgroup
-  const int64_t t0 = (int64_t)blockIdx.x * T;
-  const int dg = blockIdx.y * gw;
-  const int dw = dg + w * G;
-  const TIn* src = static_cast<const TIn*>(in.ptr);
+// ------------------------------------------------------------------ dedispersion kernel
+//
+// Work item = (512-sample time tile, group of W*8 DM trials). Wavefront w of the
+// workgroup owns trials dg + 8w .. dg + 8w + 7; lane l owns the 8 consecutive output
+// samples t0 + 8l .. t0 + 8l + 7 of the tile.
+//
+// Channel vectors (tile plus the group's delay spread) reach LDS by DMA
+// (global_load_lds) through a ring of nb stages of cs channels, issued nb - 1
+// stages ahead so HBM/L2 latency hides behind compute. Within a channel buffer,
+// 4-sample chunk q sits in row q & 1 at column q >> 1, so 64 lanes reading chunks
+// q0 + 2l + j touch 64 consecutive 16-byte slots (no bank conflicts).
+//
+// WINDOW mode (the wavefront's delay spread fits the register window): each lane
+// loads window w[0..] = samples a0 + 8l + i once per channel (a0 = the wave's
+// first delay rounded down to 4) and every trial adds w[k .. k+7] through the
+// jump table of window_add (k = its delay - a0). About 0.4 LDS dwords per add.
+// COPIES mode (large spreads): four copies of each channel vector shifted by
+// 0..3 samples make every trial's 8 samples two aligned ds_read_b128.
 
-  float acc[G][S];
-  float part[G][S];
-#pragma unroll
-  for (int g = 0; g < G; ++g)
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc[g][s] = 0.f, part[g][s] = 0.f;
+#include "window_add.inc"
 
-  for (int c0 = 0; c0 < nchan; c0 += cc_n) {
-    const int n_here = min(cc_n, nchan - c0);
-    __syncthreads();
-    for (int cc = 0; cc < n_here; ++cc) {
-      const int c = c0 + cc;
-      const int32_t* row = dtab + (int64_t)c * ndm_pad;
-      const int base = row[dg];
-      const int len = T + row[dg + gw - 1] - base;
-      const int64_t first = t0 + base;  // window position of element 0
-      const TIn* rp = src + (int64_t)c * in.row_stride;
-      float* dst = smem + cc * len_max;
-      if constexpr (RING) {
-        int64_t start = (in.win0 + first) % in.ring_len;
-        for (int j = threadIdx.x; j < len; j += nt) {
-          int64_t p = start + j;
-          if (p >= in.ring_len) p -= in.ring_len;
-          dst[j] = (first + j < in.nvalid) ? to_f32(rp[p]) : 0.f;
-        }
-      } else {
-        for (int j = threadIdx.x; j < len; j += nt)
-          dst[j] = (first + j < in.nvalid) ? to_f32(rp[first + j]) : 0.f;
+constexpr int kTile = 512;
+constexpr int kG = 8;
+constexpr int kWinChunks = DD_WIN_LEN / 4;
+static_assert(DD_WIN_S == dd::kWinS && DD_WIN_KMAX == dd::kWinKmax && kTile == dd::kTile &&
+                  DD_WIN_CHUNKS == kWinChunks,
+              "window constants disagree with the host plan");
+
+struct KParams {
+  InView in;
+  const int32_t* dtab;  // [nchan][ndm_pad]
+  float* out;
+  double* part;         // [ndm][ntiles][2] or null
+  int64_t out_stride, nout, nitems;
+  int ndm_pad, nchan, ndm, ngroups;
+  int L;        // dwords per (channel, copy) buffer, two rows of L/2
+  int cs;       // channels per stage
+  int nb;       // stages in the LDS ring
+  int nd;       // DMA instructions per wavefront per stage
+  int nstages;  // ceil(nchan / cs)
+};
+
+// Wavefront sum in a fixed butterfly (identical for every launch shape).
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// The delay table is read-only for the whole launch: reading it through the constant
+// address space keeps its (wave-uniform) loads on the scalar unit.
+typedef const __attribute__((address_space(4))) int32_t* ctab_t;
+__device__ __forceinline__ ctab_t ctab_row(const int32_t* t, int c, int ndm_pad) {
+  return (ctab_t)(t) + (int64_t)c * ndm_pad;
+}
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ void block_barrier() {
+  compiler_fence();
+  __builtin_amdgcn_s_barrier();
+  compiler_fence();
+}
+
+// s_waitcnt vmcnt(n) with expcnt/lgkmcnt left open (gfx9 encoding), n in [0, 63].
+#define DD_VMCNT(n) ((((n) & 15)) | (7 << 4) | (15 << 8) | ((((n) >> 4) & 3) << 14))
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+#define DD_W4(b)                                                        \
+  case b: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b)); break;               \
+  case b + 1: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b + 1)); break;       \
+  case b + 2: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b + 2)); break;       \
+  case b + 3: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b + 3)); break;
+    DD_W4(0) DD_W4(4) DD_W4(8) DD_W4(12) DD_W4(16) DD_W4(20) DD_W4(24) DD_W4(28)
+    DD_W4(32) DD_W4(36) DD_W4(40) DD_W4(44) DD_W4(48) DD_W4(52) DD_W4(56) DD_W4(60)
+#undef DD_W4
+    default: __builtin_amdgcn_s_waitcnt(DD_VMCNT(0)); break;
+  }
+}
+
+// Sample (within the channel vector) held by dword x of a channel buffer.
+__device__ __forceinline__ int buf_sample(int x, int half) {
+  const int r = x >= half ? 1 : 0;
+  const int y = x - r * half;
+  return 4 * (2 * (y >> 2) + r) + (y & 3);
+}
+
+// Global element index of window position pos (clamped into the valid range).
+__device__ __forceinline__ int64_t src_index(const InView& in, int64_t pos) {
+  if (pos >= in.nvalid) pos = in.nvalid - 1;
+  if (in.ring_len > 0) {
+    int64_t p = (in.win0 + pos) % in.ring_len;
+    return p;
+  }
+  return pos;
+}
+
+// One LDS DMA: every lane copies the dword at base + voff to LDS at lds + 4 * lane.
+// Issued from asm so the compiler neither serialises later LDS reads behind it nor
+// counts it; the kernel waits for these with explicit vmcnt.
+__device__ __forceinline__ void dma_dword(const void* base, unsigned voff, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+}
+
+__device__ __forceinline__ unsigned lds_addr(const float* p) {
+  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) float*)p;
+}
+
+// Issue this wavefront's DMA share of stage `st` (f32 input): chunks t = w, w + nw, ...
+// of the stage's cs * NCOPY * (L/64) 64-dword chunks. Within a 64-dword chunk that
+// starts at row offset 64i', lane l holds sample 2*64i' + 4r + pl(l), pl = 8(l>>2) + (l&3).
+template <int NCOPY>
+__device__ __forceinline__ void stage_dma(const KParams& P, float* smem, int st, int64_t t0, int dg, int w, int nw,
+                                          int pl, int w0) {
+  const float* src = static_cast<const float*>(P.in.ptr);
+  const int buf = st % P.nb;
+  const int nch = P.L >> 6;
+  const int half = P.L >> 1;
+  const int per = NCOPY * nch;
+  int cc = w / per;
+  int rem = w - cc * per;
+  int m = rem / nch;
+  int i = rem - m * nch;
+  const unsigned sbase = lds_addr(smem);
+  const int nlim = (int)P.in.nvalid - 1;
+  const int rlen = (int)P.in.ring_len;
+  for (int j = 0; j < P.nd; ++j) {
+    int c = st * P.cs + cc;
+    if (c >= P.nchan) c = P.nchan - 1;  // keep the per-wave DMA count uniform
+    ctab_t row = ctab_row(P.dtab, c, P.ndm_pad);
+    const int first = (int)(t0 + row[dg]);
+    const int r = (i << 6) >= half ? 1 : 0;
+    const int ui = first + m + 2 * ((i << 6) - r * half) + 4 * r;  // window position of lane 0 (uniform)
+    int pos = min(ui + pl, nlim);
+    if (rlen > 0) {
+      pos += w0;
+      if (pos >= rlen) pos -= rlen;
+    }
+    const float* rp = src + (int64_t)c * P.in.row_stride;
+    const unsigned lds = sbase + 4u * (unsigned)(((buf * P.cs + cc) * NCOPY + m) * P.L + (i << 6));
+    dma_dword(rp, 4u * (unsigned)pos, lds);
+    i += nw;
+    while (i >= nch) {
+      i -= nch;
+      if (++m == NCOPY) {
+        m = 0;
+        ++cc;
       }
     }
-    __syncthreads();
+  }
+}
+
+// Synchronous staging for 16-bit and 8-bit inputs: load, convert to FP32, ds_write.
+template <typename TIn, int NCOPY>
+__device__ __forceinline__ void stage_convert(const KParams& P, float* smem, int st, int64_t t0, int dg) {
+  const TIn* src = static_cast<const TIn*>(P.in.ptr);
+  const int buf = st % P.nb;
+  const int half = P.L >> 1;
+  for (int cc = 0; cc < P.cs; ++cc) {
+    int c = st * P.cs + cc;
+    if (c >= P.nchan) c = P.nchan - 1;
+    ctab_t row = ctab_row(P.dtab, c, P.ndm_pad);
+    const int64_t first = t0 + row[dg];
+    const TIn* rp = src + (int64_t)c * P.in.row_stride;
+#pragma unroll
+    for (int m = 0; m < NCOPY; ++m) {
+      float* dst = smem + ((int64_t)(buf * P.cs + cc) * NCOPY + m) * P.L;
+      for (int x = threadIdx.x; x < P.L; x += blockDim.x) {
+        const int64_t pos = first + m + buf_sample(x, half);
+        dst[x] = to_f32(rp[src_index(P.in, pos)]);
+      }
+    }
+  }
+}
+
+template <typename TIn, bool WINDOW>
+__global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
+  constexpr int NCOPY = WINDOW ? 1 : 4;
+  constexpr bool DMA = std::is_same<TIn, float>::value;
+  extern __shared__ __align__(16) float smem[];
+  const int64_t lin = blockIdx.x;
+  const int64_t per = (P.nitems + 7) / 8;
+  const int64_t item = (lin & 7) * per + (lin >> 3);
+  if (item >= P.nitems) return;  // uniform for the workgroup, before any barrier
+  const int64_t tile = item / P.ngroups;
+  const int grp = (int)(item - tile * P.ngroups);
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gw = kG * nw;
+  const int64_t t0 = tile * kTile;
+  const int dg = grp * gw;
+  const int dw = dg + w * kG;
+  const int half = P.L >> 1;
+  const int pl = 8 * (lane >> 2) + (lane & 3);
+  const int w0 = P.in.ring_len > 0 ? (int)(P.in.win0 % P.in.ring_len) : 0;
+
+  float acc[kG][8];
+  float sub[kG][8];
+#pragma unroll
+  for (int g = 0; g < kG; ++g)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f;
+  float win[DD_WIN_LEN];
+
+  // prologue: stages 0 .. nb-2 in flight
+  if constexpr (DMA) {
+    const int pre = min(P.nb - 1, P.nstages);
+    for (int st = 0; st < pre; ++st) stage_dma<NCOPY>(P, smem, st, t0, dg, w, nw, pl, w0);
+  }
+
+  for (int st = 0; st < P.nstages; ++st) {
+    if constexpr (DMA) {
+      // stages issued after st: min(nstages - 1, st + nb - 2) - st
+      const int later = min(P.nstages - 1, st + P.nb - 2) - st;
+      wait_vm(later * P.nd);
+      block_barrier();
+      if (st + P.nb - 1 < P.nstages) stage_dma<NCOPY>(P, smem, st + P.nb - 1, t0, dg, w, nw, pl, w0);
+    } else {
+      block_barrier();
+      stage_convert<TIn, NCOPY>(P, smem, st, t0, dg);
+      __syncthreads();
+    }
+    const int buf = st % P.nb;
+    const int n_here = min(P.cs, P.nchan - st * P.cs);
     for (int cc = 0; cc < n_here; ++cc) {
-      const int c = c0 + cc;
+      const int c = st * P.cs + cc;
       if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int g = 0; g < kG; ++g)
 #pragma unroll
-          for (int s = 0; s < S; ++s) acc[g][s] += part[g][s], part[g][s] = 0.f;
+          for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
       }
-      const int32_t* row = dtab + (int64_t)c * ndm_pad;
+      ctab_t row = ctab_row(P.dtab, c, P.ndm_pad);
       const int base = row[dg];
-      const float* v = smem + cc * len_max + lane;
+      const float* cb = smem + (int64_t)(buf * P.cs + cc) * NCOPY * P.L;
+      if constexpr (WINDOW) {
+        const int a0 = (row[dw] - base) & ~3;
+        const int q0 = a0 >> 2;
+        int kk[kG];
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int k = row[dw + g] - base;
+        for (int g = 0; g < kG; ++g) kk[g] = row[dw + g] - base - a0;
+        const int nj = (8 + kk[kG - 1] + 3) >> 2;
+        // chunk j of lane l: Q = q0 + 2l + j -> row (Q & 1), column (Q >> 1)
+        const unsigned lb = lds_addr(cb) + 16u * (unsigned)((q0 >> 1) + lane);
+        const unsigned rowb = 4u * (unsigned)half;
+        const unsigned bq = (unsigned)(q0 & 1);
+        float4 ch[kWinChunks];
+        window_load(ch, lb + bq * rowb, lb + (1u - bq) * rowb + 16u * bq, nj);
 #pragma unroll
-        for (int s = 0; s < S; ++s) part[g][s] += v[k + 64 * s];
+        for (int j = 0; j < kWinChunks; ++j)
+          win[4 * j] = ch[j].x, win[4 * j + 1] = ch[j].y, win[4 * j + 2] = ch[j].z, win[4 * j + 3] = ch[j].w;
+#pragma unroll
+        for (int g = 0; g < kG; ++g) window_add(sub[g], win, kk[g]);
+      } else {
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+          const int k = row[dw + g] - base;
+          const int m = k & 3;
+          const int q = (k - m) >> 2;  // chunk of sample 0 for lane 0
+          const float* mb = cb + m * P.L + 4 * ((q >> 1) + lane);
+          const int b = q & 1;
+          const float4 v0 = *reinterpret_cast<const float4*>(mb + b * half);
+          const float4 v1 = *reinterpret_cast<const float4*>(mb + (1 - b) * half + 4 * b);
+          sub[g][0] += v0.x;
+          sub[g][1] += v0.y;
+          sub[g][2] += v0.z;
+          sub[g][3] += v0.w;
+          sub[g][4] += v1.x;
+          sub[g][5] += v1.y;
+          sub[g][6] += v1.z;
+          sub[g][7] += v1.w;
+        }
       }
     }
   }
 #pragma unroll
-  for (int g = 0; g < G; ++g)
+  for (int g = 0; g < kG; ++g)
 #pragma unroll
-    for (int s = 0; s < S; ++s) acc[g][s] += part[g][s];
+    for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s];
 
+  const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
+  const int64_t nseg = (P.nout + kTile - 1) / kTile;
+  const int64_t tb = t0 + 8 * lane;
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
+  for (int g = 0; g < kG; ++g) {
     const int d = dw + g;
-    if (d >= ndm) break;
-    float* orow = out + (int64_t)d * out_stride;
+    if (d >= P.ndm) break;
+    float* orow = P.out + (int64_t)d * P.out_stride;
+    if (vec_ok && tb + 7 < P.nout) {
+      *reinterpret_cast<float4*>(orow + tb) = make_float4(acc[g][0], acc[g][1], acc[g][2], acc[g][3]);
+      *reinterpret_cast<float4*>(orow + tb + 4) = make_float4(acc[g][4], acc[g][5], acc[g][6], acc[g][7]);
+    } else {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int64_t t = t0 + lane + 64 * s;
-      if (t < nout) orow[t] = acc[g][s];
+      for (int q = 0; q < 8; ++q)
+        if (tb + q < P.nout) orow[tb + q] = acc[g][q];
+    }
+    if (P.part) {
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (tb + q < P.nout) {
+          const double x = acc[g][q];
+          s1 += x;
+          s2 += x * x;
+        }
+      }
+      s1 = wave_sum_fixed(s1);
+      s2 = wave_sum_fixed(s2);
+      if (lane == 0) {
+        P.part[((int64_t)d * nseg + tile) * 2] = s1;
+        P.part[((int64_t)d * nseg + tile) * 2 + 1] = s2;
+      }
     }
   }
 }
@@ -145,33 +380,8 @@ __device__ double block_sum256(double v, double* red) {
   return r;
 }
 
-// Segment partial sums of (x - x0) and (x - x0)^2 with x0 = the row's first value.
-__global__ __launch_bounds__(256) void stats_partial(const float* __restrict__ out, int64_t stride,
-                                                     int64_t nout, int64_t nseg, double* __restrict__ part) {
-  __shared__ double red[4];
-  const int64_t seg = blockIdx.x;
-  const int d = blockIdx.y;
-  const float* row = out + (int64_t)d * stride;
-  const double x0 = row[0];
-  const int64_t b = seg * dd::kStatSeg;
-  const int64_t e = min(nout, b + dd::kStatSeg);
-  double s = 0.0, ss = 0.0;
-  for (int64_t t = b + threadIdx.x; t < e; t += 256) {
-    const double x = (double)row[t] - x0;
-    s += x;
-    ss += x * x;
-  }
-  s = block_sum256(s, red);
-  ss = block_sum256(ss, red);
-  if (threadIdx.x == 0) {
-    part[((int64_t)d * nseg + seg) * 2] = s;
-    part[((int64_t)d * nseg + seg) * 2 + 1] = ss;
-  }
-}
-
 // stat[d] = {mean, rms, threshold} in FP64; mean/rms also as FP32 outputs.
-__global__ __launch_bounds__(256) void stats_finalize(const float* __restrict__ out, int64_t stride,
-                                                      const double* __restrict__ part, int64_t nseg,
+__global__ __launch_bounds__(256) void stats_finalize(const double* __restrict__ part, int64_t nseg,
                                                       int ndm, int64_t nout, double k, float* mean,
                                                       float* rms, double* stat) {
   const int d = blockIdx.x * 256 + threadIdx.x;
@@ -182,10 +392,9 @@ __global__ __launch_bounds__(256) void stats_finalize(const float* __restrict__ 
     ss += part[((int64_t)d * nseg + g) * 2 + 1];
   }
   const double n = (double)nout;
-  const double ms = s / n;
-  double var = ss / n - ms * ms;
+  const double m = s / n;
+  double var = ss / n - m * m;
   if (var < 0.0) var = 0.0;
-  const double m = (double)out[(int64_t)d * stride] + ms;
   const double r = sqrt(var);
   mean[d] = (float)m;
   rms[d] = (float)r;
@@ -294,23 +503,12 @@ __global__ __launch_bounds__(256) void ring_append(const TIn* __restrict__ blk, 
 
 // ------------------------------------------------------------------ host side
 
-using KernFn = void (*)(InView, const int32_t*, int, int, int, float*, int64_t, int64_t, int, int);
+using KernFn = void (*)(KParams);
 
-template <typename TIn, bool RING>
-KernFn pick(int g, int s) {
-  if (g == 4 && s == 4) return dedisp_tile<TIn, 4, 4, RING>;
-  if (g == 4 && s == 8) return dedisp_tile<TIn, 4, 8, RING>;
-  if (g == 4 && s == 16) return dedisp_tile<TIn, 4, 16, RING>;
-  if (g == 8 && s == 4) return dedisp_tile<TIn, 8, 4, RING>;
-  if (g == 8 && s == 8) return dedisp_tile<TIn, 8, 8, RING>;
-  if (g == 16 && s == 4) return dedisp_tile<TIn, 16, 4, RING>;
-  return nullptr;
-}
-
-KernFn pick_kernel(int dtype, bool ring, int g, int s) {
-  if (dtype == DD_F32) return ring ? pick<float, true>(g, s) : pick<float, false>(g, s);
-  if (dtype == DD_F16) return ring ? pick<__half, true>(g, s) : pick<__half, false>(g, s);
-  return ring ? pick<uint8_t, true>(g, s) : pick<uint8_t, false>(g, s);
+KernFn pick_kernel(int dtype, bool window) {
+  if (dtype == DD_F32) return window ? dedisp_tile<float, true> : dedisp_tile<float, false>;
+  if (dtype == DD_F16) return window ? dedisp_tile<__half, true> : dedisp_tile<__half, false>;
+  return window ? dedisp_tile<uint8_t, true> : dedisp_tile<uint8_t, false>;
 }
 
 int hip_fail(hipError_t e, const char* what) {
@@ -341,39 +539,51 @@ int64_t lds_limit_bytes() {
 // Dedisperse nout outputs of a prepared input view, then stats and candidates.
 int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, const Outputs& o,
                  char* ws, const dd::WsLayout& l, hipStream_t st) {
-  const int g = p->tiles.g, s = p->tiles.s, w = p->tiles.w;
-  const int T = 64 * s;
-  const int len_max = (int)dd::align_up((int64_t)T + p->max_span, 4);
   const int64_t lds_cap = lds_limit_bytes();
-  int cc_n = p->tiles.cc;
-  while (cc_n > 1 && (int64_t)cc_n * len_max * 4 > lds_cap) --cc_n;
-  const int64_t lds = (int64_t)cc_n * len_max * 4;
-  if (lds > lds_cap)
+  const dd::Launch g = dd::choose_launch(p->max_span, p->wave_span, p->tiles.w, p->nchan, p->tiles.cc, lds_cap);
+  if (in.nvalid >= (int64_t)1 << 30 || in.ring_len >= (int64_t)1 << 30)
+    return dd::fail(DD_ERR_UNSUPPORTED, "windows of 2^30 samples or more per channel are not supported");
+  if (g.nb < 2 || g.lds > lds_cap || g.nd < 1)
     return dd::fail(DD_ERR_UNSUPPORTED, "delay spread of one DM group (" + std::to_string(p->max_span) +
                                             " samples) does not fit in LDS; use fewer DMs per workgroup");
-  KernFn k = pick_kernel(p->dtype, in.ring_len > 0, g, s);
-  if (!k) return dd::fail(DD_ERR_UNSUPPORTED, "no kernel for this tuning");
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  KernFn k = pick_kernel(p->dtype, g.window);
+  if (g.lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   }
-  const int64_t ntiles = (nout + T - 1) / T;
-  if (ntiles > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many time tiles");
-  dim3 grid((unsigned)ntiles, (unsigned)p->ngroups);
-  hipLaunchKernelGGL(k, grid, dim3(64 * w), (size_t)lds, st, in, d_table, p->ndm_pad, p->nchan, p->ndm, o.out,
-                     o.out_stride, nout, len_max, cc_n);
+  const int64_t ntiles = (nout + kTile - 1) / kTile;
+  const int64_t nitems = ntiles * p->ngroups;
+  const int64_t nblocks = (nitems + 7) / 8 * 8;
+  if (nblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many work items");
+  const bool stats = o.mean && o.rms;
+  double* part = reinterpret_cast<double*>(ws + l.part_off);
+  KParams P{};
+  P.in = in;
+  P.dtab = d_table;
+  P.out = o.out;
+  P.part = stats ? part : nullptr;
+  P.out_stride = o.out_stride;
+  P.nout = nout;
+  P.nitems = nitems;
+  P.ndm_pad = p->ndm_pad;
+  P.nchan = p->nchan;
+  P.ndm = p->ndm;
+  P.ngroups = p->ngroups;
+  P.L = g.L;
+  P.cs = g.cs;
+  P.nb = g.nb;
+  P.nd = g.nd;
+  P.nstages = (p->nchan + g.cs - 1) / g.cs;
+  hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * p->tiles.w), (size_t)g.lds, st, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "dedisp_tile launch");
 
-  if (o.mean && o.rms) {
-    double* part = reinterpret_cast<double*>(ws + l.part_off);
+  if (stats) {
     double* stat = reinterpret_cast<double*>(ws + l.thr_off);
-    const int64_t nseg = (nout + dd::kStatSeg - 1) / dd::kStatSeg;
-    hipLaunchKernelGGL(stats_partial, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out,
-                       o.out_stride, nout, nseg, part);
-    hipLaunchKernelGGL(stats_finalize, dim3((unsigned)((p->ndm + 255) / 256)), dim3(256), 0, st, o.out,
-                       o.out_stride, part, nseg, p->ndm, nout, (double)o.k, o.mean, o.rms, stat);
+    hipLaunchKernelGGL(stats_finalize, dim3((unsigned)((p->ndm + 255) / 256)), dim3(256), 0, st, part, ntiles,
+                       p->ndm, nout, (double)o.k, o.mean, o.rms, stat);
     if (o.k > 0.f && o.ncand) {
+      const int64_t nseg = (nout + dd::kStatSeg - 1) / dd::kStatSeg;
       int32_t* cnt = reinterpret_cast<int32_t*>(ws + l.cnt_off);
       int64_t* offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
       hipLaunchKernelGGL(cand_count, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out,

@@ -1,5 +1,6 @@
 // Host side of the plan: validation, the FP64 delay table (Eq. deltaTEq), tile choice,
 // workspace sizing. Built with -ffp-contract=off so each double operation rounds once.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -22,7 +23,32 @@ bool valid_tiles(const dd::Tiles& t) {
     for (int x : xs) if (v == x) return true;
     return false;
   };
-  return in(t.g, {4, 8, 16}) && in(t.w, {1, 2, 4, 8}) && in(t.s, {4, 8, 16}) && in(t.cc, {8});
+  return t.g == 8 && (t.w == 0 || in(t.w, {1, 2, 4, 8})) && t.s == 8 && t.cc >= 0 && t.cc <= 8;
+}
+
+// Largest in-group delay spread (max_span) and largest in-window delay of one
+// wavefront (its spread plus the misalignment of its first delay, rounded down to 4)
+// over all channels, for groups of g*nw trials with the last trial repeated as padding.
+void compute_spans(const std::vector<int32_t>& delays, int32_t nchan, int32_t ndm, int g, int nw,
+                   int32_t* max_span, int32_t* wave_span) {
+  const int gw = g * nw;
+  const int ngroups = (ndm + gw - 1) / gw;
+  int32_t span = 0, wspan = 0;
+  for (int32_t c = 0; c < nchan; ++c) {
+    const int32_t* row = &delays[(size_t)c * ndm];
+    auto at = [&](int d) { return row[d < ndm ? d : ndm - 1]; };
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const int d0 = gi * gw;
+      const int32_t g0 = at(d0);
+      span = std::max(span, at(d0 + gw - 1) - g0);
+      for (int wv = 0; wv < nw; ++wv) {
+        const int32_t rel0 = at(d0 + wv * g) - g0;
+        wspan = std::max(wspan, at(d0 + wv * g + g - 1) - g0 - (rel0 & ~3));
+      }
+    }
+  }
+  *max_span = span;
+  *wave_span = wspan;
 }
 
 }  // namespace
@@ -42,9 +68,10 @@ WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
   l.table_off = 0;
   l.table_bytes = (int64_t)p->nchan * p->ndm_pad * 4;
   l.nseg = nout > 0 ? (nout + kStatSeg - 1) / kStatSeg : 1;
+  l.ntile = nout > 0 ? (nout + kTile - 1) / kTile : 1;
   int64_t o = align_up(l.table_bytes);
   l.part_off = o;
-  o = align_up(o + (int64_t)p->ndm * l.nseg * 16);
+  o = align_up(o + (int64_t)p->ndm * l.ntile * 16);
   l.thr_off = o;
   o = align_up(o + (int64_t)p->ndm * 24);  // {mean, rms, threshold} per trial
   l.cnt_off = o;
@@ -56,6 +83,47 @@ WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
 }
 
 int64_t ring_table_bytes(const dd_plan* p) { return align_up((int64_t)p->nchan * p->ndm_pad * 4); }
+
+Launch choose_launch(int32_t max_span, int32_t wave_span, int nw, int nchan, int cs_req, int64_t lds_cap) {
+  Launch best{};
+  best.window = wave_span <= kWinKmax;
+  const int ncopy = best.window ? 1 : 4;
+  // samples one channel buffer covers: tile + group spread (+ the register window's overrun)
+  const int64_t need = best.window ? (int64_t)max_span + 8 * 63 + 4 * kWinChunks : kTile + (int64_t)max_span;
+  const int64_t L0 = (need + 127) / 128 * 128;  // two rows, each a whole number of 64-dword DMA chunks
+  const int cs_hi = std::max(1, std::min(cs_req > 0 ? cs_req : 8, nchan));
+  int64_t best_score = -1;
+  for (int64_t L = L0; L <= L0 + 128 * 8; L += 128) {
+    const int64_t per_chan = (int64_t)ncopy * L * 4;
+    for (int cs = cs_hi; cs >= 1; --cs) {
+      const int64_t chunks = (int64_t)cs * ncopy * (L / 64);
+      if (chunks % nw) continue;  // every wavefront issues the same number of DMAs
+      const int nd = (int)(chunks / nw);
+      if (nd > 63) continue;
+      int nb = (int)std::min<int64_t>(lds_cap / (cs * per_chan), 16);
+      while (nb > 2 && (int64_t)(nb - 2) * nd > 60) --nb;
+      if (nb < 2) continue;
+      // deepest ring (channels in flight), then least padding
+      const int64_t score = ((int64_t)nb * cs) * 4096 - (L - L0);
+      if (cs_req > 0 && cs != cs_hi && best_score >= 0) continue;
+      if (score > best_score) {
+        best_score = score;
+        best.L = (int)L;
+        best.cs = cs;
+        best.nb = nb;
+        best.nd = nd;
+      }
+    }
+    if (best_score >= 0 && L > L0 + 256) break;
+  }
+  if (best_score < 0) {
+    best.nb = 0;
+    best.lds = 0;
+    return best;
+  }
+  best.lds = (int64_t)best.nb * best.cs * ncopy * best.L * 4;
+  return best;
+}
 
 }  // namespace dd
 
@@ -90,11 +158,12 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
       return dd::fail(DD_ERR_INVALID_ARG, "DM trials must be in non-decreasing order");
   }
 
-  dd::Tiles t{8, 4, 8, 8};
+  dd::Tiles t{8, 0, 8, 0};
   if (tuning) {
     if (tuning->dms_per_wave) t.g = tuning->dms_per_wave;
     if (tuning->waves) t.w = tuning->waves;
     if (tuning->samples_per_lane) t.s = tuning->samples_per_lane;
+    t.cc = tuning->chan_stage;
   }
   if (!valid_tiles(t)) return dd::fail(DD_ERR_UNSUPPORTED, "unsupported tuning");
 
@@ -128,22 +197,31 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   }
   p->maxdelay = (int32_t)maxd;
 
+  // DM trials per workgroup: 8 per wavefront, as many wavefronts as keep the LDS ring
+  // at least 8 channels deep (unless the caller fixed the count).
+  int32_t span = 0, wspan = 0;
+  const int w_opts[4] = {8, 4, 2, 1};
+  for (int oi = 0; oi < 4; ++oi) {
+    const int nw = t.w ? t.w : w_opts[oi];
+    compute_spans(p->delays, nchan, ndm, t.g, nw, &span, &wspan);
+    const dd::Launch g = dd::choose_launch(span, wspan, nw, nchan, t.cc, dd::kLdsBytes);
+    if (t.w || (g.nb >= 2 && (int64_t)g.nb * g.cs >= std::min(8, nchan + 1)) || nw == 1) {
+      t.w = nw;
+      break;
+    }
+  }
   p->tiles = t;
   p->dms_per_group = t.g * t.w;
   p->ngroups = (ndm + p->dms_per_group - 1) / p->dms_per_group;
   p->ndm_pad = p->ngroups * p->dms_per_group;
   p->dev_table.resize((size_t)nchan * p->ndm_pad);
-  int32_t span = 0;
   for (int32_t c = 0; c < nchan; ++c) {
     const int32_t* row = &p->delays[(size_t)c * ndm];
     int32_t* drow = &p->dev_table[(size_t)c * p->ndm_pad];
     for (int32_t d = 0; d < p->ndm_pad; ++d) drow[d] = row[d < ndm ? d : ndm - 1];
-    for (int32_t gi = 0; gi < p->ngroups; ++gi) {
-      const int32_t sp = drow[gi * p->dms_per_group + p->dms_per_group - 1] - drow[gi * p->dms_per_group];
-      if (sp > span) span = sp;
-    }
   }
   p->max_span = span;
+  p->wave_span = wspan;
   p->id = g_next_id.fetch_add(1);
   *out = p;
   return DD_OK;
@@ -163,6 +241,7 @@ int dd_plan_query(const dd_plan* p, int64_t nsamp, dd_plan_info* info) {
   info->dms_per_wave = p->tiles.g;
   info->waves = p->tiles.w;
   info->samples_per_lane = p->tiles.s;
+  info->chan_stage = p->tiles.cc;
   info->max_span = p->max_span;
   if (nsamp <= 0) return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be > 0");
   const int64_t ring_len = dd::align_up(nsamp + (int64_t)p->maxdelay, 64);

@@ -43,7 +43,7 @@ def _create(lib, freq, dm, tsamp, dtype=0, tuning=None):
     f = np.ascontiguousarray(freq, np.float64)
     d = np.ascontiguousarray(dm, np.float64)
     dbl = C.POINTER(C.c_double)
-    tun = C.byref(lib_mod.Tuning(*tuning, 0)) if tuning else None
+    tun = C.byref(lib_mod.Tuning(*tuning)) if tuning else None
     rc = lib.dd_plan_create(C.byref(h), f.ctypes.data_as(dbl), f.size, tsamp, d.ctypes.data_as(dbl), d.size,
                             dtype, tun)
     return rc, h
@@ -114,7 +114,11 @@ def test_plan_validation_codes(lib):
         assert rc == lib_mod.DD_ERR_INVALID_ARG, (freq, dm, tsamp, dt)
         assert not h.value
         assert len(lib.dd_last_error()) > 0
-    rc, h = _create(lib, f, [1.0], 1e-4, 0, tuning=(3, 4, 8))
+    rc, h = _create(lib, f, [1.0], 1e-4, 0, tuning=(3, 4, 8, 0))
+    assert rc == lib_mod.DD_ERR_UNSUPPORTED
+    rc, h = _create(lib, f, [1.0], 1e-4, 0, tuning=(8, 4, 16, 0))
+    assert rc == lib_mod.DD_ERR_UNSUPPORTED
+    rc, h = _create(lib, f, [1.0], 1e-4, 0, tuning=(8, 4, 8, 33))
     assert rc == lib_mod.DD_ERR_UNSUPPORTED
     rc, h = _create(lib, [], [1.0], 1e-4)
     assert rc == lib_mod.DD_ERR_INVALID_ARG

@@ -57,13 +57,13 @@ def test_config1_full_parity(torch, dd):
 EDGE = [
     # nchan, ndm, nsamp, tuning, step
     (1, 1, 300, None, 0.1),
-    (1, 5, 64, (4, 1, 4), 0.1),
+    (1, 5, 64, (8, 1), 0.1),
     (37, 33, 2000, None, 0.3),          # ragged channel block, ragged DM group, ragged tile
-    (64, 70, 1501, (4, 2, 16), 0.2),
+    (64, 70, 1501, (8, 2, 3), 0.2),
     (64, 128, 556, None, 0.1),          # nout = 1
-    (96, 17, 5000, (16, 4, 4), 0.5),
-    (33, 64, 3000, (8, 8, 8), 0.1),
-    (200, 40, 4097, (4, 8, 8), 0.2),    # large in-group delay spread
+    (96, 17, 5000, (8, 4, 1), 0.5),
+    (33, 64, 3000, (8, 8), 0.1),
+    (200, 40, 4097, (8, 8, 5), 0.2),    # large in-group delay spread
 ]
 
 
@@ -92,7 +92,7 @@ def test_integer_inputs_bit_exact_and_tuning_invariant(torch, dd):
     b = fbsynth.config1()
     tab = orc.delay_table(b.freq_mhz, b.dm, b.tsamp_s)
     want = orc.dedisperse(u8, tab)
-    for tuning in [None, (4, 1, 4), (16, 4, 4), (8, 8, 8), (4, 4, 16)]:
+    for tuning in [None, (8, 1), (8, 2), (8, 8, 2), (8, 4, 7)]:
         _say(f"case: u8 bit-exact tuning={tuning}")
         _, r = _run(torch, dd, b.freq_mhz, b.tsamp_s, b.dm, u8, tuning=tuning)
         np.testing.assert_array_equal(r.out.cpu().numpy().astype(np.float64), want)
@@ -102,7 +102,7 @@ def test_fp32_tiling_invariance(torch, dd):
     """The channel summation order is fixed, so FP32 results do not depend on the tiles."""
     b = fbsynth.config1()
     outs = []
-    for tuning in [None, (4, 1, 4), (16, 2, 4), (8, 8, 8), (4, 4, 16)]:
+    for tuning in [None, (8, 1), (8, 2, 3), (8, 8), (8, 4, 8)]:
         _say(f"case: fp32 tiling {tuning}")
         _, r = _run(torch, dd, b.freq_mhz, b.tsamp_s, b.dm, b.data, tuning=tuning)
         outs.append(r.out.cpu().numpy())
