@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--tuning", type=str, default=None, help="dms_per_wave,waves[,chan_stage] tile override")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON with measured HBM fetch/write bytes per launch of the dedispersion kernel")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain device copy of the input (known bytes) to calibrate HBM counters")
     return ap.parse_args()
 
 
@@ -153,6 +155,12 @@ def main():
         "real_time_factor": round(nout * beam.tsamp_s / (ms_step * 1e-3), 2),
         "roofline": roof,
     }
+    if args.copy_probe:
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = int(x.numel() * x.element_size())
+        del y
     del x
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)

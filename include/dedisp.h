@@ -82,7 +82,12 @@ typedef struct dd_plan_info {
   int64_t ring_bytes;               /* for dd_stream_create with block_nsamp = nsamp */
   int32_t dms_per_wave, waves, samples_per_lane, max_span;  /* chosen tiles; LDS span */
   int64_t adds;                     /* ndm * nchan * nout: the algorithmic work */
-  int32_t chan_stage, reserved;     /* channels per LDS stage (0 = chosen at launch) */
+  int32_t chan_stage, reserved;     /* channels per LDS stage requested (0 = automatic) */
+  /* launch geometry (fixed at plan creation for 160 KB of LDS per workgroup): shifted
+     copies of each channel vector, words per copy, channels per stage, stages in the
+     LDS ring, LDS bytes per workgroup */
+  int32_t launch_copies, launch_buf, launch_stage, launch_ring;
+  int64_t launch_lds;
 } dd_plan_info;
 
 /* One detection: (time, DM, intensity) of Ch. 3, plus (value - mean) / rms. */
@@ -101,7 +106,8 @@ typedef struct dd_cand {
  * DD_ERR_INVALID_ARG for nchan < 1, ndm < 1, non-finite or non-positive
  * frequencies, tsamp <= 0, negative, non-finite or decreasing DMs, a delay above 2^31 - 1,
  * or an unknown dtype; DD_ERR_UNSUPPORTED for a tuning outside the listed
- * values. The plan is immutable and may be shared between threads.
+ * values, or when no launch geometry fits one DM group's delay spread in LDS. The plan
+ * is immutable and may be shared between threads.
  */
 int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
                    const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning);

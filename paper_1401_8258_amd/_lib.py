@@ -29,7 +29,9 @@ class PlanInfo(C.Structure):
                 ("workspace_bytes", C.c_int64), ("ring_bytes", C.c_int64),
                 ("dms_per_wave", C.c_int32), ("waves", C.c_int32),
                 ("samples_per_lane", C.c_int32), ("max_span", C.c_int32),
-                ("adds", C.c_int64), ("chan_stage", C.c_int32), ("reserved", C.c_int32)]
+                ("adds", C.c_int64), ("chan_stage", C.c_int32), ("reserved", C.c_int32),
+                ("launch_copies", C.c_int32), ("launch_buf", C.c_int32), ("launch_stage", C.c_int32),
+                ("launch_ring", C.c_int32), ("launch_lds", C.c_int64)]
 
 
 class Cand(C.Structure):

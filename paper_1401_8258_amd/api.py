@@ -45,6 +45,7 @@ class Result:
     _cand: Optional[torch.Tensor] = None
     _ncand: Optional[torch.Tensor] = None
     cand_cap: int = 0
+    _keep: object = None
 
     def candidates(self) -> Optional[np.ndarray]:
         """Detections as a structured numpy array (synchronises the device)."""
@@ -209,6 +210,24 @@ class Stream:
             return None
         return Result(out[:, : n.value], mean, rms, t0.value, cand, ncand, cand_cap)
 
+    def append(self, block: torch.Tensor, stream=None):
+        """Copy a block into the ring without dedispersing (the first half of a batched push).
+
+        Returns (t0, nout) of the window now pending, or None while the ring fills.
+        """
+        p = self.plan
+        if block.dim() != 2 or block.shape[0] != p.nchan or block.dtype != p.dtype or block.stride(1) != 1:
+            raise ValueError("block must be [nchan][n] of the plan dtype, time contiguous")
+        t0 = C.c_int64()
+        n = C.c_int64()
+        rc = check(self._lib.dd_stream_append(self._h, _vp(block), int(block.shape[1]), int(block.stride(0)),
+                                              self.seq, _stream(stream), C.byref(t0), C.byref(n)),
+                   (_lib.DD_OK, _lib.DD_FILLING))
+        self.seq += 1
+        if rc == _lib.DD_FILLING:
+            return None
+        return int(t0.value), int(n.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.dd_stream_destroy(self._h)
@@ -219,3 +238,73 @@ class Stream:
             self.close()
         except Exception:
             pass
+
+
+def _outputs(ndm: int, ncols: int, device, k_sigma: float, cand_cap: int, stats: bool):
+    out = torch.empty((ndm, max(ncols, 1)), dtype=torch.float32, device=device)
+    mean = rms = cand = ncand = None
+    if stats:
+        mean = torch.empty(ndm, dtype=torch.float32, device=device)
+        rms = torch.empty(ndm, dtype=torch.float32, device=device)
+        if k_sigma > 0:
+            cand = torch.empty(max(cand_cap, 1) * CAND_DTYPE.itemsize, dtype=torch.uint8, device=device)
+            ncand = torch.zeros(1, dtype=torch.int64, device=device)
+    return out, mean, rms, cand, ncand
+
+
+def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True, stream=None):
+    """Dedisperse several inputs in one persistent launch (dd_batch_dedisperse).
+
+    jobs: a list of (Plan, tensor) pairs and/or (Stream, (t0, nout)) pairs, the latter
+    after Stream.append returned a pending window. All plans must share the input dtype
+    and DM trials per workgroup. Returns one Result per job, equal bit for bit to the
+    one-at-a-time calls.
+    """
+    lib = _lib.load()
+    items = (_lib.BatchItem * len(jobs))()
+    keep = []
+    results = []
+    for i, (obj, arg) in enumerate(jobs):
+        it = items[i]
+        if isinstance(obj, Stream):
+            t0, n = arg
+            plan = obj.plan
+            dev = obj.device
+            out, mean, rms, cand, ncand = _outputs(plan.ndm, obj.block, dev, k_sigma, cand_cap, stats)
+            it.plan = plan.handle.value
+            it.stream_item = obj.handle.value
+            it.d_plan_workspace = obj.ws.data_ptr()
+            cols = n
+        else:
+            plan, x = obj, arg
+            if x.dim() != 2 or x.shape[0] != plan.nchan or x.dtype != plan.dtype or x.stride(1) != 1:
+                raise ValueError("each input must be [nchan][nsamp] of its plan dtype, time contiguous")
+            nsamp = int(x.shape[1])
+            cols = nsamp - plan.maxdelay
+            t0 = 0
+            out, mean, rms, cand, ncand = _outputs(plan.ndm, cols, x.device, k_sigma, cand_cap, stats)
+            ws = plan.workspace(nsamp, x.device, stream)
+            it.plan = plan.handle.value
+            it.d_in = x.data_ptr()
+            it.nsamp = nsamp
+            it.in_row_stride = int(x.stride(0))
+            it.d_plan_workspace = ws.data_ptr()
+            keep.append(ws)
+        it.d_out = out.data_ptr()
+        it.out_row_stride = int(out.stride(0))
+        it.d_mean = mean.data_ptr() if mean is not None else None
+        it.d_rms = rms.data_ptr() if rms is not None else None
+        it.k_sigma = float(k_sigma)
+        it.d_cand = cand.data_ptr() if cand is not None else None
+        it.cand_cap = int(cand_cap) if cand is not None else 0
+        it.d_ncand = ncand.data_ptr() if ncand is not None else None
+        results.append(Result(out[:, :cols], mean, rms, t0, cand, ncand, cand_cap))
+    need = C.c_int64()
+    check(lib.dd_batch_query(items, len(jobs), C.byref(need)))
+    dev = results[0].out.device
+    bws = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    check(lib.dd_batch_dedisperse(items, len(jobs), _vp(bws), int(bws.numel()), _stream(stream)))
+    keep.append(bws)
+    for r in results:
+        r._keep = keep  # device buffers stay alive until the results are dropped
+    return results

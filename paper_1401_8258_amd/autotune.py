@@ -1,0 +1,135 @@
+"""Autotuner for the dedispersion tiles (wavefronts per DM group, channels per LDS stage).
+
+The thesis tuned its kernel by sweeping accumulators per thread and threads per
+block on the target GPU (Ch. 2, Sec. Performance and Benchmarks). Here the
+tunables are the number of wavefronts (8 DM trials each) sharing one LDS ring and
+the channels staged per ring slot. ``tune`` times every candidate on seeded
+random input of the beam's shape and keeps the fastest; ``tune_batch`` picks the
+wavefront count that minimises the summed time of a set of beams (a batched
+launch needs one count for all its items), with each beam's own best stage size.
+Results are cached by (nchan, ndm, dtype, nsamp, delay-spread profile).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from .api import Plan, torch_dtype
+
+WAVES = (8, 4, 2, 1)
+STAGES = (0, 2, 4)
+
+
+def _key(freq, tsamp, dm, dtype, nsamp) -> str:
+    h = hashlib.sha1()
+    h.update(np.ascontiguousarray(freq, np.float64).tobytes())
+    h.update(np.ascontiguousarray(dm, np.float64).tobytes())
+    h.update(np.float64(tsamp).tobytes())
+    return f"{len(freq)}x{len(dm)}:{dtype}:{nsamp}:{h.hexdigest()[:16]}"
+
+
+class TuneCache:
+    def __init__(self, path: Optional[str] = None):
+        self.path = path
+        self.data: Dict[str, dict] = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.data = json.load(f)
+
+    def get(self, key):
+        return self.data.get(key)
+
+    def put(self, key, val):
+        self.data[key] = val
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.data, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+
+def synthetic_input(nchan: int, nsamp: int, dtype, seed: int = 0, device="cuda") -> torch.Tensor:
+    """Seeded random input of the beam's shape for timing (noise only)."""
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    x = torch.randn((nchan, nsamp), generator=g, device=device)
+    dt = torch_dtype(dtype)
+    if dt == torch.uint8:
+        return torch.clamp(torch.round(128.0 + 16.0 * x), 0, 255).to(torch.uint8)
+    return x.to(dt)
+
+
+def time_plan(plan: Plan, x: torch.Tensor, reps: int = 3) -> float:
+    """Milliseconds per dedispersion (kernel only, no statistics) on the current stream."""
+    nout = x.shape[1] - plan.maxdelay
+    out = torch.empty((plan.ndm, nout), dtype=torch.float32, device=x.device)
+    ws = plan.workspace(x.shape[1], x.device)
+    plan.dedisperse(x, stats=False, out=out, workspace=ws)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        plan.dedisperse(x, stats=False, out=out, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Sequence[int] = STAGES,
+         reps: int = 3, cache: Optional[TuneCache] = None, x: Optional[torch.Tensor] = None) -> dict:
+    """Best (dms_per_wave, waves, chan_stage) for one beam shape."""
+    key = _key(freq, tsamp, dm, str(dtype), nsamp) + f":{tuple(waves)}:{tuple(stages)}"
+    if cache is not None and cache.get(key):
+        return cache.get(key)
+    if x is None:
+        x = synthetic_input(len(freq), nsamp, dtype)
+    trials = []
+    for w in waves:
+        for cc in stages:
+            try:
+                plan = Plan(freq, tsamp, dm, dtype=dtype, tuning=(8, w, cc))
+                ms = time_plan(plan, x, reps)
+            except Exception as e:  # a tiling that does not fit this beam
+                trials.append({"tuning": [8, w, cc], "error": str(e)})
+                continue
+            trials.append({"tuning": [8, w, cc], "ms": ms})
+    ok = [t for t in trials if "ms" in t]
+    if not ok:
+        raise RuntimeError("no tiling fits this beam")
+    best = min(ok, key=lambda t: t["ms"])
+    res = {"tuning": best["tuning"], "ms": best["ms"], "trials": trials}
+    if cache is not None:
+        cache.put(key, res)
+    return res
+
+
+def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequence[int] = STAGES, reps: int = 2,
+               cache: Optional[TuneCache] = None, inputs: Optional[List[torch.Tensor]] = None) -> dict:
+    """One wavefront count for a batch; per beam the best stage size under it.
+
+    beams: (freq, tsamp, dm, dtype, nsamp) per beam. Returns {"waves": w, "tunings": [...],
+    "total_ms": t, "by_waves": {w: t}}.
+    """
+    per_w: Dict[int, List[dict]] = {}
+    for w in waves:
+        per_w[w] = []
+        for i, (freq, tsamp, dm, dtype, nsamp) in enumerate(beams):
+            x = inputs[i] if inputs is not None else None
+            try:
+                r = tune(freq, tsamp, dm, dtype, nsamp, waves=(w,), stages=stages, reps=reps, cache=cache, x=x)
+            except RuntimeError:
+                per_w[w] = None
+                break
+            per_w[w].append(r)
+    totals = {w: sum(r["ms"] for r in rs) for w, rs in per_w.items() if rs is not None}
+    if not totals:
+        raise RuntimeError("no common wavefront count fits every beam")
+    wbest = min(totals, key=totals.get)
+    return {"waves": wbest, "tunings": [r["tuning"] for r in per_w[wbest]], "total_ms": totals[wbest],
+            "by_waves": totals}

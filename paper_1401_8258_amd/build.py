@@ -27,9 +27,6 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    sys.path.insert(0, os.path.join(PKG, "csrc"))
-    import gen_jumptable  # writes csrc/window_add.inc (the register-window jump table)
-    gen_jumptable.main()
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + FLAGS + SRC + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -17,24 +17,18 @@ constexpr int64_t kAlign = 256;
 constexpr int64_t kTile = 512;
 // Output samples per candidate-compaction segment.
 constexpr int64_t kStatSeg = 8192;
-// Register window of the dedispersion kernel: 8 accumulators per lane per DM trial,
-// in-window delays 0..kWinKmax (must match window_add.inc).
-constexpr int kWinS = 8;
-constexpr int kWinKmax = 36;
-constexpr int kWinChunks = (kWinS + kWinKmax) / 4;
 // LDS of one gfx950 workgroup.
 constexpr int64_t kLdsBytes = 160 * 1024;
 
 // Launch geometry of the dedispersion kernel.
 struct Launch {
-  bool window;  // register-window mode (else four shifted LDS copies)
-  int L;        // dwords per (channel, copy) buffer
+  int L;        // words per (channel, copy) buffer (four copies shifted by 0..3 samples)
   int cs;       // channels per stage
   int nb;       // stages in the LDS ring
   int nd;       // DMA instructions per wavefront per stage
   int64_t lds;  // bytes
 };
-Launch choose_launch(int32_t max_span, int32_t wave_span, int nw, int nchan, int cs_req, int64_t lds_cap);
+Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap);
 
 inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -57,9 +51,11 @@ struct dd_plan {
   int32_t dms_per_group = 0;        // g * w
   int32_t ngroups = 0;
   int32_t ndm_pad = 0;              // ngroups * dms_per_group
-  std::vector<int32_t> dev_table;   // [nchan][ndm_pad]; padded trials repeat the last DM
+  // device table: [nchan][ndm_pad] LDS byte offset of each trial's first chunk inside its
+  // channel slot (padded trials repeat the last DM), then [ngroups][nchan] group first delays
+  std::vector<int32_t> dev_table;
   int32_t max_span = 0;             // max over channels and groups of the in-group delay spread
-  int32_t wave_span = 0;            // max in-window delay of one wavefront (its spread + misalignment)
+  dd::Launch launch{};               // kernel geometry (fixed at plan time: the offsets depend on it)
   uint64_t id = 0;
 };
 

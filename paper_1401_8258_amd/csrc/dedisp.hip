@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -45,44 +46,39 @@ struct InView {
 
 // ------------------------------------------------------------------ dedispersion kernel
 //
-// Work item = (512-sample time tile, group of W*8 DM trials). Wavefront w of the
-// workgroup owns trials dg + 8w .. dg + 8w + 7; lane l owns the 8 consecutive output
-// samples t0 + 8l .. t0 + 8l + 7 of the tile.
+// Work unit = (512-sample time tile, group of W*8 DM trials). Wavefront w of the
+// workgroup owns trials dg + 8w .. dg + 8w + 7; lane l owns output samples
+// t0 + 4l .. t0 + 4l + 3 and t0 + 256 + 4l .. t0 + 256 + 4l + 3 of the tile.
 //
-// Channel vectors (tile plus the group's delay spread) reach LDS by DMA
-// (global_load_lds) through a ring of nb stages of cs channels, issued nb - 1
-// stages ahead so HBM/L2 latency hides behind compute. Within a channel buffer,
-// 4-sample chunk q sits in row q & 1 at column q >> 1, so 64 lanes reading chunks
-// q0 + 2l + j touch 64 consecutive 16-byte slots (no bank conflicts).
-//
-// WINDOW mode (the wavefront's delay spread fits the register window): each lane
-// loads window w[0..] = samples a0 + 8l + i once per channel (a0 = the wave's
-// first delay rounded down to 4) and every trial adds w[k .. k+7] through the
-// jump table of window_add (k = its delay - a0). About 0.4 LDS dwords per add.
-// COPIES mode (large spreads): four copies of each channel vector shifted by
-// 0..3 samples make every trial's 8 samples two aligned ds_read_b128.
-
-#include "window_add.inc"
+// Channel vectors (tile plus the group's delay spread, Eq. channelDispersionEquation)
+// reach LDS by DMA (global_load_lds) through a ring of nb stages of cs channels,
+// issued nb - 1 stages ahead, so HBM/L2 latency hides behind compute. Each channel is
+// stored four times, shifted by 0..3 samples, so the 4-sample chunks any trial needs
+// start 16-byte aligned: a trial costs one address add and two ds_read_b128 (lanes
+// read consecutive 16-byte slots: no bank conflicts). The host precomputes, per
+// (channel, trial), the LDS byte offset of the trial's first chunk inside the
+// channel's slot; those offsets ride along with the data in every stage, so the
+// inner loop needs no scalar arithmetic at all.
 
 constexpr int kTile = 512;
 constexpr int kG = 8;
-constexpr int kWinChunks = DD_WIN_LEN / 4;
-static_assert(DD_WIN_S == dd::kWinS && DD_WIN_KMAX == dd::kWinKmax && kTile == dd::kTile &&
-                  DD_WIN_CHUNKS == kWinChunks,
-              "window constants disagree with the host plan");
+constexpr int kCopies = 4;
+static_assert(kTile == dd::kTile, "tile constant disagrees with the host plan");
 
 struct KParams {
   InView in;
-  const int32_t* dtab;  // [nchan][ndm_pad]
+  const int32_t* dtab;   // [nchan][ndm_pad] LDS byte offset of each trial's chunk in its channel slot
+  const int32_t* gbase;  // [ngroups][nchan] first delay of each group
   float* out;
-  double* part;         // [ndm][ntiles][2] or null
+  double* part;          // [ndm][ntiles][2] or null
   int64_t out_stride, nout, nitems;
   int ndm_pad, nchan, ndm, ngroups;
-  int L;        // dwords per (channel, copy) buffer, two rows of L/2
+  int L;        // words per (channel, copy) buffer
   int cs;       // channels per stage
   int nb;       // stages in the LDS ring
   int nd;       // DMA instructions per wavefront per stage
   int nstages;  // ceil(nchan / cs)
+  int nbase;    // LDS words reserved for the group's first delays (nchan rounded up to 64)
 };
 
 // Wavefront sum in a fixed butterfly (identical for every launch shape).
@@ -90,13 +86,6 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-
-// The delay table is read-only for the whole launch: reading it through the constant
-// address space keeps its (wave-uniform) loads on the scalar unit.
-typedef const __attribute__((address_space(4))) int32_t* ctab_t;
-__device__ __forceinline__ ctab_t ctab_row(const int32_t* t, int c, int ndm_pad) {
-  return (ctab_t)(t) + (int64_t)c * ndm_pad;
 }
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
@@ -123,20 +112,10 @@ __device__ __forceinline__ void wait_vm(int n) {
   }
 }
 
-// Sample (within the channel vector) held by dword x of a channel buffer.
-__device__ __forceinline__ int buf_sample(int x, int half) {
-  const int r = x >= half ? 1 : 0;
-  const int y = x - r * half;
-  return 4 * (2 * (y >> 2) + r) + (y & 3);
-}
-
-// Global element index of window position pos (clamped into the valid range).
+// Window position pos (clamped into the valid range) as an element index into the row.
 __device__ __forceinline__ int64_t src_index(const InView& in, int64_t pos) {
   if (pos >= in.nvalid) pos = in.nvalid - 1;
-  if (in.ring_len > 0) {
-    int64_t p = (in.win0 + pos) % in.ring_len;
-    return p;
-  }
+  if (in.ring_len > 0) return (in.win0 + pos) % in.ring_len;
   return pos;
 }
 
@@ -147,21 +126,61 @@ __device__ __forceinline__ void dma_dword(const void* base, unsigned voff, unsig
   asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
 }
 
-__device__ __forceinline__ unsigned lds_addr(const float* p) {
-  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) float*)p;
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
 
-// Issue this wavefront's DMA share of stage `st` (f32 input): chunks t = w, w + nw, ...
-// of the stage's cs * NCOPY * (L/64) 64-dword chunks. Within a 64-dword chunk that
-// starts at row offset 64i', lane l holds sample 2*64i' + 4r + pl(l), pl = 8(l>>2) + (l&3).
-template <int NCOPY>
-__device__ __forceinline__ void stage_dma(const KParams& P, float* smem, int st, int64_t t0, int dg, int w, int nw,
-                                          int pl, int w0) {
+// LDS layout (4-byte words): [0, nbase) the group's first delay per channel, then the
+// ring's data slots (buf, cc, copy) of L words, then its offset slots (buf, cc) of 64
+// words (the LDS offsets of the group's trials for that channel).
+__device__ __forceinline__ int data_word(const KParams& P, int buf, int cc, int m) {
+  return P.nbase + ((buf * P.cs + cc) * kCopies + m) * P.L;
+}
+__device__ __forceinline__ int offs_word(const KParams& P, int buf, int cc) {
+  return P.nbase + P.nb * P.cs * kCopies * P.L + (buf * P.cs + cc) * 64;
+}
+
+// Prologue: the group's first delay of every channel, DMA'd into LDS words [0, nchan).
+__device__ __forceinline__ void load_bases(const KParams& P, float* smem, int grp, int w, int nw, int lane) {
+  const int32_t* gb = P.gbase + (int64_t)grp * P.nchan;
+  const unsigned sbase = lds_addr(smem);
+  const int chunks = P.nbase >> 6;
+  const int per = (chunks + nw - 1) / nw;
+  for (int j = 0; j < per; ++j) {
+    int i = w + nw * j;
+    if (i >= chunks) i = chunks - 1;  // same count for every wavefront
+    const int x = min((i << 6) + lane, P.nchan - 1);
+    dma_dword(gb, 4u * (unsigned)x, sbase + 4u * (unsigned)(i << 6));
+  }
+}
+
+// The group's trial offsets for this stage's channels: wavefront w takes channels w, w + nw, ...
+__device__ __forceinline__ void stage_offsets(const KParams& P, float* smem, int st, int dg, int gw, int w, int nw,
+                                              int lane) {
+  const int buf = st % P.nb;
+  const unsigned sbase = lds_addr(smem);
+  const int per = (P.cs + nw - 1) / nw;
+  const unsigned voff = 4u * (unsigned)min(lane, gw - 1);
+  for (int j = 0; j < per; ++j) {
+    int cc = w + nw * j;
+    if (cc >= P.cs) cc = P.cs - 1;
+    int c = st * P.cs + cc;
+    if (c >= P.nchan) c = P.nchan - 1;
+    dma_dword(P.dtab + (int64_t)c * P.ndm_pad + dg, voff, sbase + 4u * (unsigned)offs_word(P, buf, cc));
+  }
+}
+
+// This wavefront's DMA share of stage `st` (f32 input): chunks t = w, w + nw, ... of the
+// stage's cs * 4 * (L/64) 64-word chunks (copy m word x holds window sample first + m + x),
+// then its offset slices.
+__device__ __forceinline__ void stage_dma(const KParams& P, float* smem, int st, int64_t t0, int dg, int gw, int w,
+                                          int nw, int lane, int w0) {
   const float* src = static_cast<const float*>(P.in.ptr);
+  const int* lds_i = reinterpret_cast<const int*>(smem);
   const int buf = st % P.nb;
   const int nch = P.L >> 6;
-  const int half = P.L >> 1;
-  const int per = NCOPY * nch;
+  const int per = kCopies * nch;
+  const int nd_data = P.nd - (P.cs + nw - 1) / nw;
   int cc = w / per;
   int rem = w - cc * per;
   int m = rem / nch;
@@ -169,66 +188,59 @@ __device__ __forceinline__ void stage_dma(const KParams& P, float* smem, int st,
   const unsigned sbase = lds_addr(smem);
   const int nlim = (int)P.in.nvalid - 1;
   const int rlen = (int)P.in.ring_len;
-  for (int j = 0; j < P.nd; ++j) {
+  for (int j = 0; j < nd_data; ++j) {
     int c = st * P.cs + cc;
     if (c >= P.nchan) c = P.nchan - 1;  // keep the per-wave DMA count uniform
-    ctab_t row = ctab_row(P.dtab, c, P.ndm_pad);
-    const int first = (int)(t0 + row[dg]);
-    const int r = (i << 6) >= half ? 1 : 0;
-    const int ui = first + m + 2 * ((i << 6) - r * half) + 4 * r;  // window position of lane 0 (uniform)
-    int pos = min(ui + pl, nlim);
+    const int first = (int)t0 + __builtin_amdgcn_readfirstlane(lds_i[c]);
+    int pos = min(first + m + (i << 6) + lane, nlim);
     if (rlen > 0) {
       pos += w0;
       if (pos >= rlen) pos -= rlen;
     }
     const float* rp = src + (int64_t)c * P.in.row_stride;
-    const unsigned lds = sbase + 4u * (unsigned)(((buf * P.cs + cc) * NCOPY + m) * P.L + (i << 6));
-    dma_dword(rp, 4u * (unsigned)pos, lds);
+    dma_dword(rp, 4u * (unsigned)pos, sbase + 4u * (unsigned)(data_word(P, buf, cc, m) + (i << 6)));
     i += nw;
     while (i >= nch) {
       i -= nch;
-      if (++m == NCOPY) {
+      if (++m == kCopies) {
         m = 0;
         ++cc;
       }
     }
   }
+  stage_offsets(P, smem, st, dg, gw, w, nw, lane);
 }
 
-// Synchronous staging for 16-bit and 8-bit inputs: load, convert to FP32, ds_write.
-template <typename TIn, int NCOPY>
-__device__ __forceinline__ void stage_convert(const KParams& P, float* smem, int st, int64_t t0, int dg) {
+// Synchronous staging for 16-bit and 8-bit inputs: load, convert to FP32, ds_write;
+// the stage's offsets by DMA, waited for here.
+template <typename TIn>
+__device__ __forceinline__ void stage_convert(const KParams& P, float* smem, int st, int64_t t0, int dg, int gw,
+                                              int w, int nw, int lane) {
   const TIn* src = static_cast<const TIn*>(P.in.ptr);
+  const int* lds_i = reinterpret_cast<const int*>(smem);
   const int buf = st % P.nb;
-  const int half = P.L >> 1;
+  stage_offsets(P, smem, st, dg, gw, w, nw, lane);
   for (int cc = 0; cc < P.cs; ++cc) {
     int c = st * P.cs + cc;
     if (c >= P.nchan) c = P.nchan - 1;
-    ctab_t row = ctab_row(P.dtab, c, P.ndm_pad);
-    const int64_t first = t0 + row[dg];
+    const int64_t first = t0 + __builtin_amdgcn_readfirstlane(lds_i[c]);
     const TIn* rp = src + (int64_t)c * P.in.row_stride;
+    float* dst = smem + data_word(P, buf, cc, 0);
+    for (int x = threadIdx.x; x < P.L + 3; x += blockDim.x) {
+      const float v = to_f32(rp[src_index(P.in, first + x)]);
+      // copy m word x - m holds window sample first + x
 #pragma unroll
-    for (int m = 0; m < NCOPY; ++m) {
-      float* dst = smem + ((int64_t)(buf * P.cs + cc) * NCOPY + m) * P.L;
-      for (int x = threadIdx.x; x < P.L; x += blockDim.x) {
-        const int64_t pos = first + m + buf_sample(x, half);
-        dst[x] = to_f32(rp[src_index(P.in, pos)]);
-      }
+      for (int m = 0; m < kCopies; ++m)
+        if (x - m >= 0 && x - m < P.L) dst[m * P.L + x - m] = v;
     }
   }
+  wait_vm(0);
 }
 
-template <typename TIn, bool WINDOW>
-__global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
-  constexpr int NCOPY = WINDOW ? 1 : 4;
+// One (time tile, DM group) work unit; every wavefront of the workgroup takes part.
+template <typename TIn>
+__device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int grp, float* smem) {
   constexpr bool DMA = std::is_same<TIn, float>::value;
-  extern __shared__ __align__(16) float smem[];
-  const int64_t lin = blockIdx.x;
-  const int64_t per = (P.nitems + 7) / 8;
-  const int64_t item = (lin & 7) * per + (lin >> 3);
-  if (item >= P.nitems) return;  // uniform for the workgroup, before any barrier
-  const int64_t tile = item / P.ngroups;
-  const int grp = (int)(item - tile * P.ngroups);
   const int nw = blockDim.x >> 6;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -236,8 +248,6 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
   const int64_t t0 = tile * kTile;
   const int dg = grp * gw;
   const int dw = dg + w * kG;
-  const int half = P.L >> 1;
-  const int pl = 8 * (lane >> 2) + (lane & 3);
   const int w0 = P.in.ring_len > 0 ? (int)(P.in.win0 % P.in.ring_len) : 0;
 
   float acc[kG][8];
@@ -246,13 +256,18 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
   for (int g = 0; g < kG; ++g)
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f;
-  float win[DD_WIN_LEN];
 
-  // prologue: stages 0 .. nb-2 in flight
+  // prologue: the group's first delays (they address every later DMA), then stages
+  // 0 .. nb-2 in flight
+  load_bases(P, smem, grp, w, nw, lane);
+  wait_vm(0);
+  block_barrier();
   if constexpr (DMA) {
     const int pre = min(P.nb - 1, P.nstages);
-    for (int st = 0; st < pre; ++st) stage_dma<NCOPY>(P, smem, st, t0, dg, w, nw, pl, w0);
+    for (int st = 0; st < pre; ++st) stage_dma(P, smem, st, t0, dg, gw, w, nw, lane, w0);
   }
+  const int* lds_i = reinterpret_cast<const int*>(smem);
+  const unsigned lane16 = 16u * (unsigned)lane;
 
   for (int st = 0; st < P.nstages; ++st) {
     if constexpr (DMA) {
@@ -260,10 +275,10 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
       const int later = min(P.nstages - 1, st + P.nb - 2) - st;
       wait_vm(later * P.nd);
       block_barrier();
-      if (st + P.nb - 1 < P.nstages) stage_dma<NCOPY>(P, smem, st + P.nb - 1, t0, dg, w, nw, pl, w0);
+      if (st + P.nb - 1 < P.nstages) stage_dma(P, smem, st + P.nb - 1, t0, dg, gw, w, nw, lane, w0);
     } else {
       block_barrier();
-      stage_convert<TIn, NCOPY>(P, smem, st, t0, dg);
+      stage_convert<TIn>(P, smem, st, t0, dg, gw, w, nw, lane);
       __syncthreads();
     }
     const int buf = st % P.nb;
@@ -276,46 +291,30 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
 #pragma unroll
           for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
       }
-      ctab_t row = ctab_row(P.dtab, c, P.ndm_pad);
-      const int base = row[dg];
-      const float* cb = smem + (int64_t)(buf * P.cs + cc) * NCOPY * P.L;
-      if constexpr (WINDOW) {
-        const int a0 = (row[dw] - base) & ~3;
-        const int q0 = a0 >> 2;
-        int kk[kG];
+      // byte offsets of this wavefront's 8 trials inside the channel slot
+      const int4* op = reinterpret_cast<const int4*>(lds_i + offs_word(P, buf, cc) + w * kG);
+      const int4 o0 = op[0];
+      const int4 o1 = op[1];
+      const int off[kG] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
+      const char* cb = reinterpret_cast<const char*>(smem + data_word(P, buf, cc, 0)) + lane16;
+      // all 16 reads of the channel first (more LDS reads in flight), then the adds
+      float4 v[2 * kG];
 #pragma unroll
-        for (int g = 0; g < kG; ++g) kk[g] = row[dw + g] - base - a0;
-        const int nj = (8 + kk[kG - 1] + 3) >> 2;
-        // chunk j of lane l: Q = q0 + 2l + j -> row (Q & 1), column (Q >> 1)
-        const unsigned lb = lds_addr(cb) + 16u * (unsigned)((q0 >> 1) + lane);
-        const unsigned rowb = 4u * (unsigned)half;
-        const unsigned bq = (unsigned)(q0 & 1);
-        float4 ch[kWinChunks];
-        window_load(ch, lb + bq * rowb, lb + (1u - bq) * rowb + 16u * bq, nj);
+      for (int g = 0; g < kG; ++g) {
+        const float4* a = reinterpret_cast<const float4*>(cb + off[g]);
+        v[2 * g] = a[0];
+        v[2 * g + 1] = a[64];
+      }
 #pragma unroll
-        for (int j = 0; j < kWinChunks; ++j)
-          win[4 * j] = ch[j].x, win[4 * j + 1] = ch[j].y, win[4 * j + 2] = ch[j].z, win[4 * j + 3] = ch[j].w;
-#pragma unroll
-        for (int g = 0; g < kG; ++g) window_add(sub[g], win, kk[g]);
-      } else {
-#pragma unroll
-        for (int g = 0; g < kG; ++g) {
-          const int k = row[dw + g] - base;
-          const int m = k & 3;
-          const int q = (k - m) >> 2;  // chunk of sample 0 for lane 0
-          const float* mb = cb + m * P.L + 4 * ((q >> 1) + lane);
-          const int b = q & 1;
-          const float4 v0 = *reinterpret_cast<const float4*>(mb + b * half);
-          const float4 v1 = *reinterpret_cast<const float4*>(mb + (1 - b) * half + 4 * b);
-          sub[g][0] += v0.x;
-          sub[g][1] += v0.y;
-          sub[g][2] += v0.z;
-          sub[g][3] += v0.w;
-          sub[g][4] += v1.x;
-          sub[g][5] += v1.y;
-          sub[g][6] += v1.z;
-          sub[g][7] += v1.w;
-        }
+      for (int g = 0; g < kG; ++g) {
+        sub[g][0] += v[2 * g].x;
+        sub[g][1] += v[2 * g].y;
+        sub[g][2] += v[2 * g].z;
+        sub[g][3] += v[2 * g].w;
+        sub[g][4] += v[2 * g + 1].x;
+        sub[g][5] += v[2 * g + 1].y;
+        sub[g][6] += v[2 * g + 1].z;
+        sub[g][7] += v[2 * g + 1].w;
       }
     }
   }
@@ -326,30 +325,33 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
 
   const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
   const int64_t nseg = (P.nout + kTile - 1) / kTile;
-  const int64_t tb = t0 + 8 * lane;
 #pragma unroll
   for (int g = 0; g < kG; ++g) {
     const int d = dw + g;
     if (d >= P.ndm) break;
     float* orow = P.out + (int64_t)d * P.out_stride;
-    if (vec_ok && tb + 7 < P.nout) {
-      *reinterpret_cast<float4*>(orow + tb) = make_float4(acc[g][0], acc[g][1], acc[g][2], acc[g][3]);
-      *reinterpret_cast<float4*>(orow + tb + 4) = make_float4(acc[g][4], acc[g][5], acc[g][6], acc[g][7]);
-    } else {
+    double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (tb + q < P.nout) orow[tb + q] = acc[g][q];
-    }
-    if (P.part) {
-      double s1 = 0.0, s2 = 0.0;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t tb = t0 + 256 * h + 4 * lane;
+      if (vec_ok && tb + 3 < P.nout) {
+        *reinterpret_cast<float4*>(orow + tb) =
+            make_float4(acc[g][4 * h], acc[g][4 * h + 1], acc[g][4 * h + 2], acc[g][4 * h + 3]);
+      } else {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 4; ++q)
+          if (tb + q < P.nout) orow[tb + q] = acc[g][4 * h + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
         if (tb + q < P.nout) {
-          const double x = acc[g][q];
+          const double x = acc[g][4 * h + q];
           s1 += x;
           s2 += x * x;
         }
       }
+    }
+    if (P.part) {
       s1 = wave_sum_fixed(s1);
       s2 = wave_sum_fixed(s2);
       if (lane == 0) {
@@ -357,6 +359,62 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
         P.part[((int64_t)d * nseg + tile) * 2 + 1] = s2;
       }
     }
+  }
+}
+
+// Plain launch: one work unit per workgroup; each XCD (workgroups lin, lin + 8, ...)
+// takes a contiguous run of units, tile-major, so the DM groups of a tile share L2.
+template <typename TIn>
+__global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
+  extern __shared__ __align__(16) float smem[];
+  const int64_t lin = blockIdx.x;
+  const int64_t per = (P.nitems + 7) / 8;
+  const int64_t item = (lin & 7) * per + (lin >> 3);
+  if (item >= P.nitems) return;  // uniform for the workgroup, before any barrier
+  const int64_t tile = item / P.ngroups;
+  const int grp = (int)(item - tile * P.ngroups);
+  tile_body<TIn>(P, tile, grp, smem);
+}
+
+// Batched persistent launch over several plans/inputs. Item i owns work units
+// [start[i], start[i+1]) of the concatenated list (tile-major, group fastest, as in the
+// plain launch). The grid is a multiple of 8 workgroups; XCD x walks the contiguous
+// range [x*per, (x+1)*per) with its workgroups striding through it, so the result of
+// every unit is the one the plain launch computes for it.
+typedef const __attribute__((address_space(4))) uint32_t* cu32_t;
+typedef const __attribute__((address_space(4))) int64_t* ci64_t;
+static_assert(sizeof(KParams) % 4 == 0, "KParams is copied as dwords");
+
+// Wave-uniform copy of a KParams record through scalar loads.
+__device__ __forceinline__ KParams load_params(const KParams* items, int i) {
+  cu32_t src = (cu32_t)(items + i);
+  uint32_t w[sizeof(KParams) / 4];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(KParams) / 4); ++k) w[k] = src[k];
+  KParams P;
+  __builtin_memcpy(&P, w, sizeof(KParams));
+  return P;
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kMaxThreads) void dedisp_batch(const KParams* items, const int64_t* start, int nitems) {
+  extern __shared__ __align__(16) float smem[];
+  ci64_t st_c = (ci64_t)start;
+  const int64_t total = st_c[nitems];
+  const int64_t nslot = gridDim.x >> 3;
+  const int64_t slot = blockIdx.x >> 3;
+  const int64_t per = (total + 7) / 8;
+  const int64_t q_lo = (int64_t)(blockIdx.x & 7) * per;
+  const int64_t q_hi = min(total, q_lo + per);
+  int it = 0;
+  for (int64_t q = q_lo + slot; q < q_hi; q += nslot) {
+    while (it + 1 < nitems && st_c[it + 1] <= q) ++it;
+    const KParams P = load_params(items, it);
+    const int64_t local = q - st_c[it];
+    const int64_t tile = local / P.ngroups;
+    const int grp = (int)(local - tile * P.ngroups);
+    block_barrier();  // the previous unit's LDS reads are done before new DMAs land
+    tile_body<TIn>(P, tile, grp, smem);
   }
 }
 
@@ -505,10 +563,10 @@ __global__ __launch_bounds__(256) void ring_append(const TIn* __restrict__ blk, 
 
 using KernFn = void (*)(KParams);
 
-KernFn pick_kernel(int dtype, bool window) {
-  if (dtype == DD_F32) return window ? dedisp_tile<float, true> : dedisp_tile<float, false>;
-  if (dtype == DD_F16) return window ? dedisp_tile<__half, true> : dedisp_tile<__half, false>;
-  return window ? dedisp_tile<uint8_t, true> : dedisp_tile<uint8_t, false>;
+KernFn pick_kernel(int dtype) {
+  if (dtype == DD_F32) return dedisp_tile<float>;
+  if (dtype == DD_F16) return dedisp_tile<__half>;
+  return dedisp_tile<uint8_t>;
 }
 
 int hip_fail(hipError_t e, const char* what) {
@@ -537,65 +595,88 @@ int64_t lds_limit_bytes() {
 }
 
 // Dedisperse nout outputs of a prepared input view, then stats and candidates.
-int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, const Outputs& o,
-                 char* ws, const dd::WsLayout& l, hipStream_t st) {
+// Kernel parameters and launch geometry for nout outputs of one plan on one input view.
+int build_params(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, const Outputs& o,
+                 char* ws, const dd::WsLayout& l, KParams* P, dd::Launch* G) {
   const int64_t lds_cap = lds_limit_bytes();
-  const dd::Launch g = dd::choose_launch(p->max_span, p->wave_span, p->tiles.w, p->nchan, p->tiles.cc, lds_cap);
+  const dd::Launch g = p->launch;
   if (in.nvalid >= (int64_t)1 << 30 || in.ring_len >= (int64_t)1 << 30)
     return dd::fail(DD_ERR_UNSUPPORTED, "windows of 2^30 samples or more per channel are not supported");
   if (g.nb < 2 || g.lds > lds_cap || g.nd < 1)
     return dd::fail(DD_ERR_UNSUPPORTED, "delay spread of one DM group (" + std::to_string(p->max_span) +
                                             " samples) does not fit in LDS; use fewer DMs per workgroup");
-  KernFn k = pick_kernel(p->dtype, g.window);
-  if (g.lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds);
+  const int64_t ntiles = (nout + kTile - 1) / kTile;
+  const bool stats = o.mean && o.rms;
+  *P = KParams{};
+  P->in = in;
+  P->dtab = d_table;
+  P->out = o.out;
+  P->part = stats ? reinterpret_cast<double*>(ws + l.part_off) : nullptr;
+  P->out_stride = o.out_stride;
+  P->nout = nout;
+  P->nitems = ntiles * p->ngroups;
+  P->ndm_pad = p->ndm_pad;
+  P->nchan = p->nchan;
+  P->ndm = p->ndm;
+  P->ngroups = p->ngroups;
+  P->L = g.L;
+  P->cs = g.cs;
+  P->nb = g.nb;
+  P->nd = g.nd;
+  P->nstages = (p->nchan + g.cs - 1) / g.cs;
+  P->nbase = (p->nchan + 63) / 64 * 64;
+  P->gbase = d_table + (int64_t)p->nchan * p->ndm_pad;
+  *G = g;
+  return DD_OK;
+}
+
+// Statistics finalize and candidate kernels for one plan's nout outputs.
+int launch_tail(const dd_plan* p, int64_t nout, const Outputs& o, char* ws, const dd::WsLayout& l, hipStream_t st) {
+  if (!(o.mean && o.rms)) return DD_OK;
+  const int64_t ntiles = (nout + kTile - 1) / kTile;
+  double* part = reinterpret_cast<double*>(ws + l.part_off);
+  double* stat = reinterpret_cast<double*>(ws + l.thr_off);
+  hipLaunchKernelGGL(stats_finalize, dim3((unsigned)((p->ndm + 255) / 256)), dim3(256), 0, st, part, ntiles,
+                     p->ndm, nout, (double)o.k, o.mean, o.rms, stat);
+  if (o.k > 0.f && o.ncand) {
+    const int64_t nseg = (nout + dd::kStatSeg - 1) / dd::kStatSeg;
+    int32_t* cnt = reinterpret_cast<int32_t*>(ws + l.cnt_off);
+    int64_t* offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
+    hipLaunchKernelGGL(cand_count, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out, o.out_stride,
+                       nout, nseg, stat, cnt);
+    hipLaunchKernelGGL(cand_scan, dim3(1), dim3(1024), 0, st, cnt, nseg * p->ndm, offs, o.ncand);
+    hipLaunchKernelGGL(cand_write, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out, o.out_stride,
+                       nout, nseg, stat, cnt, offs, o.cand, o.cand ? o.cap : 0, o.t_base);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "statistics/candidate launch");
+  return DD_OK;
+}
+
+int set_lds(const void* k, int64_t lds) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   }
-  const int64_t ntiles = (nout + kTile - 1) / kTile;
-  const int64_t nitems = ntiles * p->ngroups;
-  const int64_t nblocks = (nitems + 7) / 8 * 8;
+  return DD_OK;
+}
+
+// Dedisperse nout outputs of a prepared input view, then stats and candidates.
+int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, const Outputs& o,
+                 char* ws, const dd::WsLayout& l, hipStream_t st) {
+  KParams P;
+  dd::Launch g;
+  int rc = build_params(p, in, d_table, nout, o, ws, l, &P, &g);
+  if (rc) return rc;
+  KernFn k = pick_kernel(p->dtype);
+  rc = set_lds((const void*)k, g.lds);
+  if (rc) return rc;
+  const int64_t nblocks = (P.nitems + 7) / 8 * 8;
   if (nblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many work items");
-  const bool stats = o.mean && o.rms;
-  double* part = reinterpret_cast<double*>(ws + l.part_off);
-  KParams P{};
-  P.in = in;
-  P.dtab = d_table;
-  P.out = o.out;
-  P.part = stats ? part : nullptr;
-  P.out_stride = o.out_stride;
-  P.nout = nout;
-  P.nitems = nitems;
-  P.ndm_pad = p->ndm_pad;
-  P.nchan = p->nchan;
-  P.ndm = p->ndm;
-  P.ngroups = p->ngroups;
-  P.L = g.L;
-  P.cs = g.cs;
-  P.nb = g.nb;
-  P.nd = g.nd;
-  P.nstages = (p->nchan + g.cs - 1) / g.cs;
   hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * p->tiles.w), (size_t)g.lds, st, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "dedisp_tile launch");
-
-  if (stats) {
-    double* stat = reinterpret_cast<double*>(ws + l.thr_off);
-    hipLaunchKernelGGL(stats_finalize, dim3((unsigned)((p->ndm + 255) / 256)), dim3(256), 0, st, part, ntiles,
-                       p->ndm, nout, (double)o.k, o.mean, o.rms, stat);
-    if (o.k > 0.f && o.ncand) {
-      const int64_t nseg = (nout + dd::kStatSeg - 1) / dd::kStatSeg;
-      int32_t* cnt = reinterpret_cast<int32_t*>(ws + l.cnt_off);
-      int64_t* offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
-      hipLaunchKernelGGL(cand_count, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out,
-                         o.out_stride, nout, nseg, stat, cnt);
-      hipLaunchKernelGGL(cand_scan, dim3(1), dim3(1024), 0, st, cnt, nseg * p->ndm, offs, o.ncand);
-      hipLaunchKernelGGL(cand_write, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out,
-                         o.out_stride, nout, nseg, stat, cnt, offs, o.cand, o.cand ? o.cap : 0, o.t_base);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "statistics/candidate launch");
-  }
-  return DD_OK;
+  return launch_tail(p, nout, o, ws, l, st);
 }
 
 int check_outputs(const dd_plan* p, float* d_out, int64_t out_stride, int64_t nout, float* d_mean, float* d_rms,
@@ -743,20 +824,96 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
 
 int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes) {
   dd::clear_error();
-  (void)items;
-  (void)n;
-  if (ws_bytes) *ws_bytes = 0;
-  return dd::fail(DD_ERR_UNSUPPORTED, "batched launch not built yet");
+  if (!ws_bytes || n < 1 || !items) return dd::fail(DD_ERR_INVALID_ARG, "need items, n >= 1 and ws_bytes");
+  *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)(n + 1) * 8);
+  return DD_OK;
 }
 
 int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace, int64_t ws_bytes, void* stream) {
   dd::clear_error();
-  (void)items;
-  (void)n;
-  (void)d_workspace;
-  (void)ws_bytes;
-  (void)stream;
-  return dd::fail(DD_ERR_UNSUPPORTED, "batched launch not built yet");
+  int64_t need = 0;
+  int rc = dd_batch_query(items, n, &need);
+  if (rc) return rc;
+  if (!d_workspace || ws_bytes < need) return dd::fail(DD_ERR_WORKSPACE, "batch workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<KParams> P((size_t)n);
+  std::vector<int64_t> start((size_t)n + 1, 0);
+  std::vector<Outputs> outs((size_t)n);
+  std::vector<int64_t> nouts((size_t)n);
+  std::vector<dd::WsLayout> lays((size_t)n);
+  int32_t dtype = -1, waves = -1;
+  int64_t lds = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const dd_batch_item& it = items[i];
+    dd_stream* sp = it.stream_item;
+    const dd_plan* p = sp ? sp->plan : it.plan;
+    if (!p || !it.d_plan_workspace)
+      return dd::fail(DD_ERR_INVALID_ARG, "batch item " + std::to_string(i) + ": plan and workspace required");
+    if (dtype < 0) dtype = p->dtype, waves = p->tiles.w;
+    if (p->dtype != dtype || p->tiles.w != waves)
+      return dd::fail(DD_ERR_UNSUPPORTED, "batch items must share the input dtype and DM trials per workgroup");
+    InView in;
+    const int32_t* table;
+    int64_t nout, t_base = 0, lay_n;
+    char* ws = static_cast<char*>(it.d_plan_workspace);
+    if (sp) {
+      if (sp->pending_n <= 0)
+        return dd::fail(DD_ERR_SEQUENCE, "batch item " + std::to_string(i) + ": stream has no appended window");
+      nout = sp->pending_n;
+      t_base = sp->pending_t0;
+      in = InView{static_cast<char*>(sp->ring) + dd::ring_table_bytes(p), sp->ring_len, nout + p->maxdelay,
+                  sp->ring_len, sp->pending_t0};
+      table = static_cast<const int32_t*>(sp->ring);
+      lay_n = sp->block;
+    } else {
+      if (!it.d_in || it.nsamp <= p->maxdelay || it.in_row_stride < it.nsamp)
+        return dd::fail(it.nsamp <= p->maxdelay ? DD_ERR_TOO_SHORT : DD_ERR_INVALID_ARG,
+                        "batch item " + std::to_string(i) + ": bad input");
+      nout = it.nsamp - p->maxdelay;
+      in = InView{it.d_in, it.in_row_stride, it.nsamp, 0, 0};
+      table = reinterpret_cast<const int32_t*>(ws);
+      lay_n = it.nsamp;
+    }
+    rc = check_outputs(p, it.d_out, it.out_row_stride, nout, it.d_mean, it.d_rms, it.k_sigma, it.d_cand,
+                       it.cand_cap, it.d_ncand);
+    if (rc) return dd::fail(rc, "batch item " + std::to_string(i) + ": " + dd_last_error());
+    lays[i] = dd::workspace_layout(p, lay_n);
+    outs[i] = Outputs{it.d_out, it.out_row_stride, it.d_mean, it.d_rms, it.k_sigma, it.d_cand, it.cand_cap,
+                      it.d_ncand, t_base};
+    nouts[i] = nout;
+    dd::Launch g;
+    rc = build_params(p, in, table, nout, outs[i], ws, lays[i], &P[i], &g);
+    if (rc) return rc;
+    lds = std::max(lds, g.lds);
+    start[i + 1] = start[i] + P[i].nitems;
+  }
+  char* bw = static_cast<char*>(d_workspace);
+  KParams* dP = reinterpret_cast<KParams*>(bw);
+  int64_t* dS = reinterpret_cast<int64_t*>(bw + dd::align_up((int64_t)n * (int64_t)sizeof(KParams)));
+  hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(KParams), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dS, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch descriptors)");
+  void (*k)(const KParams*, const int64_t*, int) =
+      dtype == DD_F32 ? dedisp_batch<float> : dtype == DD_F16 ? dedisp_batch<__half> : dedisp_batch<uint8_t>;
+  rc = set_lds((const void*)k, lds);
+  if (rc) return rc;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t units = start[n];
+  // one resident workgroup per CU (the LDS ring fills a CU), rounded to whole XCD groups
+  const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, (units + 7) / 8 * 8) / 8 * 8);
+  hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * waves), (size_t)lds, st, (const KParams*)dP,
+                     (const int64_t*)dS, (int)n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "dedisp_batch launch");
+  for (int32_t i = 0; i < n; ++i) {
+    const dd_batch_item& it = items[i];
+    const dd_plan* p = it.stream_item ? it.stream_item->plan : it.plan;
+    rc = launch_tail(p, nouts[i], outs[i], static_cast<char*>(it.d_plan_workspace), lays[i], st);
+    if (rc) return rc;
+    if (it.stream_item) it.stream_item->pending_n = 0;
+  }
+  return DD_OK;
 }
 
 }  // extern "C"

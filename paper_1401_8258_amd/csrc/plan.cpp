@@ -26,29 +26,19 @@ bool valid_tiles(const dd::Tiles& t) {
   return t.g == 8 && (t.w == 0 || in(t.w, {1, 2, 4, 8})) && t.s == 8 && t.cc >= 0 && t.cc <= 8;
 }
 
-// Largest in-group delay spread (max_span) and largest in-window delay of one
-// wavefront (its spread plus the misalignment of its first delay, rounded down to 4)
-// over all channels, for groups of g*nw trials with the last trial repeated as padding.
-void compute_spans(const std::vector<int32_t>& delays, int32_t nchan, int32_t ndm, int g, int nw,
-                   int32_t* max_span, int32_t* wave_span) {
-  const int gw = g * nw;
+// Largest in-group delay spread over all channels, for groups of gw trials with the last
+// trial repeated as padding.
+int32_t compute_span(const std::vector<int32_t>& delays, int32_t nchan, int32_t ndm, int gw) {
   const int ngroups = (ndm + gw - 1) / gw;
-  int32_t span = 0, wspan = 0;
+  int32_t span = 0;
   for (int32_t c = 0; c < nchan; ++c) {
     const int32_t* row = &delays[(size_t)c * ndm];
-    auto at = [&](int d) { return row[d < ndm ? d : ndm - 1]; };
     for (int gi = 0; gi < ngroups; ++gi) {
-      const int d0 = gi * gw;
-      const int32_t g0 = at(d0);
-      span = std::max(span, at(d0 + gw - 1) - g0);
-      for (int wv = 0; wv < nw; ++wv) {
-        const int32_t rel0 = at(d0 + wv * g) - g0;
-        wspan = std::max(wspan, at(d0 + wv * g + g - 1) - g0 - (rel0 & ~3));
-      }
+      const int d0 = gi * gw, d1 = std::min(d0 + gw, (int)ndm) - 1;
+      span = std::max(span, row[d1] - row[d0]);
     }
   }
-  *max_span = span;
-  *wave_span = wspan;
+  return span;
 }
 
 }  // namespace
@@ -66,7 +56,7 @@ int64_t elem_bytes(int32_t dtype) { return dtype == DD_F32 ? 4 : dtype == DD_F16
 WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
   WsLayout l{};
   l.table_off = 0;
-  l.table_bytes = (int64_t)p->nchan * p->ndm_pad * 4;
+  l.table_bytes = (int64_t)p->dev_table.size() * 4;
   l.nseg = nout > 0 ? (nout + kStatSeg - 1) / kStatSeg : 1;
   l.ntile = nout > 0 ? (nout + kTile - 1) / kTile : 1;
   int64_t o = align_up(l.table_bytes);
@@ -82,29 +72,32 @@ WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
   return l;
 }
 
-int64_t ring_table_bytes(const dd_plan* p) { return align_up((int64_t)p->nchan * p->ndm_pad * 4); }
+int64_t ring_table_bytes(const dd_plan* p) { return align_up((int64_t)p->dev_table.size() * 4); }
 
-Launch choose_launch(int32_t max_span, int32_t wave_span, int nw, int nchan, int cs_req, int64_t lds_cap) {
+Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap) {
   Launch best{};
-  best.window = wave_span <= kWinKmax;
-  const int ncopy = best.window ? 1 : 4;
-  // samples one channel buffer covers: tile + group spread (+ the register window's overrun)
-  const int64_t need = best.window ? (int64_t)max_span + 8 * 63 + 4 * kWinChunks : kTile + (int64_t)max_span;
-  const int64_t L0 = (need + 127) / 128 * 128;  // two rows, each a whole number of 64-dword DMA chunks
+  // words one channel copy covers: tile + group spread (lane reads end at k - m + 511)
+  const int64_t need = kTile + (int64_t)max_span;
+  const int64_t L0 = (need + 63) / 64 * 64;  // whole 64-word DMA chunks
+  // LDS besides the ring: the group's first delay for every channel (padded to 64)
+  const int64_t base_bytes = ((int64_t)nchan + 63) / 64 * 64 * 4;
+  const int64_t ring_cap = lds_cap - base_bytes;
   const int cs_hi = std::max(1, std::min(cs_req > 0 ? cs_req : 8, nchan));
   int64_t best_score = -1;
-  for (int64_t L = L0; L <= L0 + 128 * 8; L += 128) {
-    const int64_t per_chan = (int64_t)ncopy * L * 4;
+  for (int64_t L = L0; L <= L0 + 64 * 8; L += 64) {
+    // a channel's slot: four shifted copies plus the group's 64 trial offsets
+    const int64_t per_chan = 4 * L * 4 + 64 * 4;
     for (int cs = cs_hi; cs >= 1; --cs) {
-      const int64_t chunks = (int64_t)cs * ncopy * (L / 64);
+      const int64_t chunks = (int64_t)cs * 4 * (L / 64);
       if (chunks % nw) continue;  // every wavefront issues the same number of DMAs
-      const int nd = (int)(chunks / nw);
-      if (nd > 63) continue;
-      int nb = (int)std::min<int64_t>(lds_cap / (cs * per_chan), 16);
+      const int nd = (int)(chunks / nw) + (cs + nw - 1) / nw;  // + offset slices
+      if (ring_cap < cs * per_chan * 2) continue;
+      int nb = (int)std::min<int64_t>(ring_cap / (cs * per_chan), 16);
+      // with later stages in flight the wait counts them (vmcnt <= 63); a two-stage ring
+      // always waits for everything, so any DMA count is legal there
       while (nb > 2 && (int64_t)(nb - 2) * nd > 60) --nb;
       if (nb < 2) continue;
-      // deepest ring (channels in flight), then least padding
-      const int64_t score = ((int64_t)nb * cs) * 4096 - (L - L0);
+      const int64_t score = ((int64_t)nb * cs) * 4096 - (L - L0);  // deepest ring, then least padding
       if (cs_req > 0 && cs != cs_hi && best_score >= 0) continue;
       if (score > best_score) {
         best_score = score;
@@ -114,14 +107,10 @@ Launch choose_launch(int32_t max_span, int32_t wave_span, int nw, int nchan, int
         best.nd = nd;
       }
     }
-    if (best_score >= 0 && L > L0 + 256) break;
+    if (best_score >= 0 && L > L0 + 128) break;
   }
-  if (best_score < 0) {
-    best.nb = 0;
-    best.lds = 0;
-    return best;
-  }
-  best.lds = (int64_t)best.nb * best.cs * ncopy * best.L * 4;
+  if (best_score < 0) return Launch{};
+  best.lds = base_bytes + (int64_t)best.nb * best.cs * (4 * (int64_t)best.L * 4 + 64 * 4);
   return best;
 }
 
@@ -199,29 +188,48 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
 
   // DM trials per workgroup: 8 per wavefront, as many wavefronts as keep the LDS ring
   // at least 8 channels deep (unless the caller fixed the count).
-  int32_t span = 0, wspan = 0;
+  int32_t span = 0;
+  dd::Launch lg{};
   const int w_opts[4] = {8, 4, 2, 1};
   for (int oi = 0; oi < 4; ++oi) {
     const int nw = t.w ? t.w : w_opts[oi];
-    compute_spans(p->delays, nchan, ndm, t.g, nw, &span, &wspan);
-    const dd::Launch g = dd::choose_launch(span, wspan, nw, nchan, t.cc, dd::kLdsBytes);
-    if (t.w || (g.nb >= 2 && (int64_t)g.nb * g.cs >= std::min(8, nchan + 1)) || nw == 1) {
+    span = compute_span(p->delays, nchan, ndm, t.g * nw);
+    lg = dd::choose_launch(span, nw, nchan, t.cc, dd::kLdsBytes);
+    if (t.w || (lg.nb >= 2 && (int64_t)lg.nb * lg.cs >= std::min(8, nchan + 1)) || nw == 1) {
       t.w = nw;
       break;
     }
   }
+  if (lg.nb < 2) {
+    delete p;
+    return dd::fail(DD_ERR_UNSUPPORTED, "delay spread of one DM group (" + std::to_string(span) +
+                                            " samples) does not fit in LDS; use fewer DMs per workgroup");
+  }
   p->tiles = t;
+  p->launch = lg;
   p->dms_per_group = t.g * t.w;
   p->ngroups = (ndm + p->dms_per_group - 1) / p->dms_per_group;
   p->ndm_pad = p->ngroups * p->dms_per_group;
-  p->dev_table.resize((size_t)nchan * p->ndm_pad);
+  p->max_span = span;
+  // device table: per (channel, trial) the LDS byte offset of the trial's first 4-sample
+  // chunk inside the channel slot: relative delay k to the group's first trial is read
+  // from copy m = k & 3 at word k - m; then [ngroups][nchan] the groups' first delays
+  p->dev_table.resize((size_t)nchan * p->ndm_pad + (size_t)p->ngroups * nchan);
+  int32_t* gb = &p->dev_table[(size_t)nchan * p->ndm_pad];
   for (int32_t c = 0; c < nchan; ++c) {
     const int32_t* row = &p->delays[(size_t)c * ndm];
     int32_t* drow = &p->dev_table[(size_t)c * p->ndm_pad];
-    for (int32_t d = 0; d < p->ndm_pad; ++d) drow[d] = row[d < ndm ? d : ndm - 1];
+    for (int32_t gi = 0; gi < p->ngroups; ++gi) {
+      const int32_t base = row[gi * p->dms_per_group];
+      gb[(size_t)gi * nchan + c] = base;
+      for (int32_t j = 0; j < p->dms_per_group; ++j) {
+        const int32_t d = gi * p->dms_per_group + j;
+        const int32_t k = row[d < ndm ? d : ndm - 1] - base;
+        const int32_t m = k & 3;
+        drow[d] = 4 * (m * lg.L + (k - m));
+      }
+    }
   }
-  p->max_span = span;
-  p->wave_span = wspan;
   p->id = g_next_id.fetch_add(1);
   *out = p;
   return DD_OK;
@@ -243,6 +251,11 @@ int dd_plan_query(const dd_plan* p, int64_t nsamp, dd_plan_info* info) {
   info->samples_per_lane = p->tiles.s;
   info->chan_stage = p->tiles.cc;
   info->max_span = p->max_span;
+  info->launch_copies = 4;
+  info->launch_buf = p->launch.L;
+  info->launch_stage = p->launch.cs;
+  info->launch_ring = p->launch.nb;
+  info->launch_lds = p->launch.lds;
   if (nsamp <= 0) return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be > 0");
   const int64_t ring_len = dd::align_up(nsamp + (int64_t)p->maxdelay, 64);
   info->ring_bytes = dd::ring_table_bytes(p) + dd::align_up(ring_len * p->nchan * dd::elem_bytes(p->dtype));

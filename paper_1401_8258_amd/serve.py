@@ -1,0 +1,265 @@
+"""Streaming server: many beams' blocks, device-resident overlap rings, continuous batching.
+
+The thesis's pipeline (Ch. 3, Sec. Pipeline Overview) runs one processing thread
+per beam and carries the last maxshift spectra of every buffer into the next
+(Ch. 3, Sec. Dedispersion). Here one scheduler feeds the GPU instead:
+
+* admission: a beam is admitted when its device footprint (ring with the
+  overlap, workspace, output block) fits in the HBM budget; beams that do not
+  fit wait in a bounded queue (admitted as admitted beams finish) or are
+  rejected when the queue is full;
+* continuous batching: at every scheduling point all blocks that have arrived
+  for admitted beams (in per-beam sequence order) form one launch; blocks that
+  arrive while a launch is on the GPU join the next one, and up to
+  ``max_inflight`` launches overlap on the device;
+* accounting: per block latency = completion - arrival against the real-time
+  deadline (one block duration), blocks/s, real-time factor, p50/p99.
+
+The executor does the device work. ``LibraryExecutor`` appends each block to its
+beam's ring (dd_stream_append) and dedisperses the whole batch in one batched
+launch (dd_batch_dedisperse); tests drive the scheduler with a fake executor.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import heapq
+import time
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class BeamSpec:
+    name: str
+    freq_mhz: np.ndarray
+    tsamp_s: float
+    dm: np.ndarray
+    dtype: str              # "u8", "f16" or "f32"
+    block: int              # samples per block
+    k_sigma: float = 6.0
+
+    @property
+    def block_s(self) -> float:
+        return self.block * self.tsamp_s
+
+
+@dataclasses.dataclass(order=True)
+class Block:
+    arrival: float
+    beam: int = dataclasses.field(compare=False)
+    seq: int = dataclasses.field(compare=False)
+    data: object = dataclasses.field(compare=False, default=None)
+
+
+@dataclasses.dataclass
+class BlockResult:
+    beam: int
+    seq: int
+    arrival: float
+    done: float
+    t0: int
+    nout: int
+    ncand: int
+    filling: bool
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Executor:
+    """Device side of the server (interface)."""
+
+    def footprint(self, spec: BeamSpec) -> int:          # bytes a beam keeps on the device
+        raise NotImplementedError
+
+    def open(self, beam: int, spec: BeamSpec) -> None:    # allocate the beam's ring/workspace
+        raise NotImplementedError
+
+    def close(self, beam: int) -> None:
+        raise NotImplementedError
+
+    def submit(self, blocks: List[Block]):                # enqueue one batched launch; returns a handle
+        raise NotImplementedError
+
+    def done(self, handle) -> bool:                       # non-blocking completion check
+        raise NotImplementedError
+
+    def results(self, handle) -> List[dict]:              # per block: t0, nout, ncand, filling (after done)
+        raise NotImplementedError
+
+
+@dataclasses.dataclass
+class ServeStats:
+    admitted: int = 0
+    queued: int = 0
+    rejected: int = 0
+    launches: int = 0
+    blocks: int = 0
+    fill_blocks: int = 0
+    deadline_misses: int = 0
+    wall_s: float = 0.0
+    data_s: float = 0.0
+    latencies: List[float] = dataclasses.field(default_factory=list)
+    batch_sizes: List[int] = dataclasses.field(default_factory=list)
+
+    def summary(self) -> dict:
+        lat = np.asarray(self.latencies) if self.latencies else np.zeros(1)
+        return {
+            "admitted_beams": self.admitted, "queued_beams": self.queued, "rejected_beams": self.rejected,
+            "launches": self.launches, "blocks": self.blocks, "fill_blocks": self.fill_blocks,
+            "blocks_per_s": self.blocks / self.wall_s if self.wall_s > 0 else 0.0,
+            "real_time_factor": self.data_s / self.wall_s if self.wall_s > 0 else 0.0,
+            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+            "latency_max_s": float(lat.max()), "deadline_misses": self.deadline_misses,
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+        }
+
+
+class Server:
+    """Admission by HBM budget plus continuous batching over a simulated arrival schedule.
+
+    ``clock`` returns seconds (wall clock by default); ``sleep`` waits. Arrival times
+    are in the same clock, relative to ``start``.
+    """
+
+    def __init__(self, specs: Sequence[BeamSpec], executor: Executor, hbm_budget: int,
+                 max_queue: int = 1 << 30, max_inflight: int = 2, max_batch: int = 1 << 30,
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+        self.specs = list(specs)
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_queue = max_queue
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch
+        self.clock = clock
+        self.sleep = sleep
+        self.used = 0
+        self.active: Dict[int, int] = {}         # beam -> footprint
+        self.waiting: collections.deque = collections.deque()
+        self.rejected: List[int] = []
+        self.stats = ServeStats()
+        self.results: List[BlockResult] = []
+
+    # ---------------------------------------------------------------- admission
+    def request(self, beam: int) -> str:
+        """Ask to admit a beam: 'admitted', 'queued' or 'rejected'."""
+        need = self.ex.footprint(self.specs[beam])
+        if need > self.budget:
+            self.rejected.append(beam)
+            self.stats.rejected += 1
+            return "rejected"
+        if self.used + need <= self.budget and not self.waiting:
+            self._admit(beam, need)
+            return "admitted"
+        if len(self.waiting) >= self.max_queue:
+            self.rejected.append(beam)
+            self.stats.rejected += 1
+            return "rejected"
+        self.waiting.append(beam)
+        self.stats.queued += 1
+        return "queued"
+
+    def _admit(self, beam: int, need: int) -> None:
+        self.ex.open(beam, self.specs[beam])
+        self.active[beam] = need
+        self.used += need
+        self.stats.admitted += 1
+
+    def release(self, beam: int) -> None:
+        """A beam finished: free its memory and admit waiting beams in order while they fit."""
+        need = self.active.pop(beam)
+        self.ex.close(beam)
+        self.used -= need
+        while self.waiting:
+            b = self.waiting[0]
+            nb = self.ex.footprint(self.specs[b])
+            if self.used + nb > self.budget:
+                break
+            self.waiting.popleft()
+            self._admit(b, nb)
+
+    # ---------------------------------------------------------------- serving loop
+    def run(self, schedule: List[Block], fill: Optional[Callable[[int], bool]] = None) -> ServeStats:
+        """Serve every block of ``schedule`` (arrival times relative to the start).
+
+        Blocks of beams that are not admitted wait until their beam is. ``fill(beam)``
+        tells whether a block result belongs to the ring fill (excluded from latency).
+        """
+        pending = list(schedule)
+        heapq.heapify(pending)
+        ready: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
+        next_seq: Dict[int, int] = collections.defaultdict(int)
+        inflight: collections.deque = collections.deque()
+        start = self.clock()
+        data_s = 0.0
+        while pending or any(ready.values()) or inflight:
+            now = self.clock() - start
+            while pending and pending[0].arrival <= now:
+                b = heapq.heappop(pending)
+                ready[b.beam].append(b)
+            # retire finished launches (in order)
+            while inflight and self.ex.done(inflight[0][0]):
+                h, blocks = inflight.popleft()
+                t_done = self.clock() - start
+                for blk, r in zip(blocks, self.ex.results(h)):
+                    br = BlockResult(blk.beam, blk.seq, blk.arrival, t_done, r["t0"], r["nout"], r["ncand"],
+                                     r["filling"])
+                    self.results.append(br)
+                    self.stats.blocks += 1
+                    data_s += self.specs[blk.beam].block_s
+                    if br.filling or (fill is not None and fill(blk.beam)):
+                        self.stats.fill_blocks += 1
+                        continue
+                    self.stats.latencies.append(br.latency)
+                    if br.latency > self.specs[blk.beam].block_s:
+                        self.stats.deadline_misses += 1
+            # form the next launch from every ready block of an admitted beam
+            if len(inflight) < self.max_inflight:
+                batch: List[Block] = []
+                for beam in sorted(ready):
+                    if beam not in self.active:
+                        continue
+                    q = ready[beam]
+                    # one block per beam per launch: a ring holds one pending window
+                    if q and q[0].seq == next_seq[beam] and len(batch) < self.max_batch:
+                        batch.append(q.popleft())
+                        next_seq[beam] += 1
+                if batch:
+                    h = self.ex.submit(batch)
+                    inflight.append((h, batch))
+                    self.stats.launches += 1
+                    self.stats.batch_sizes.append(len(batch))
+                    continue
+            # nothing to launch: wait for the next arrival or completion
+            if inflight:
+                self.sleep(2e-4)
+            elif pending:
+                wait = pending[0].arrival - (self.clock() - start)
+                if wait > 0:
+                    self.sleep(min(wait, 0.05))
+            elif any(ready.values()):
+                # ready blocks whose beams are not admitted and nothing in flight: cannot progress
+                if not any(b in self.active for b in ready if ready[b]):
+                    break
+        self.stats.wall_s = self.clock() - start
+        self.stats.data_s = data_s
+        return self.stats
+
+
+def poisson_schedule(specs: Sequence[BeamSpec], n_blocks: int, seed: int = 5, jitter_mean_s: float = 0.1,
+                     phases=None, make_data: Optional[Callable[[int, int], object]] = None,
+                     time_scale: float = 1.0) -> List[Block]:
+    """arrival_k = (k * T + phase + J_k) * time_scale with J_k ~ Exp(mean) truncated below T."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, sp in enumerate(specs):
+        T = sp.block_s
+        ph = float(phases[i]) if phases is not None else float(rng.uniform(0.0, T))
+        j = np.minimum(rng.exponential(jitter_mean_s, size=n_blocks), np.nextafter(T, 0.0))
+        for k in range(n_blocks):
+            data = make_data(i, k) if make_data else None
+            out.append(Block((k * T + ph + float(j[k])) * time_scale, i, k, data))
+    return out

@@ -153,3 +153,32 @@ def test_explicit_channel_order(lib):
     got = _delays(lib, h, 64, 40)
     np.testing.assert_array_equal(got, orc.delay_table(freq, dm, 51.2e-6)[perm])
     lib.dd_plan_destroy(h)
+
+
+def _launch_ok(lib, freq, dm, tsamp, dtype=0, tuning=None, nsamp=1 << 20):
+    rc, h = _create(lib, freq, dm, tsamp, dtype, tuning)
+    assert rc == 0, lib.dd_last_error()
+    info = lib_mod.PlanInfo()
+    lib.dd_plan_query(h, nsamp, C.byref(info))
+    lib.dd_plan_destroy(h)
+    return info
+
+
+def test_every_workload_has_a_launch_geometry(lib):
+    """Each plan the tests and the benchmark build must have a ring that fits in LDS."""
+    cases = []
+    b1 = fbsynth.config1()
+    cases.append((b1.freq_mhz, b1.dm, b1.tsamp_s, 0, None))
+    f2 = fbsynth.channel_freqs(428.0, 20 / 1024, 1024)
+    cases.append((f2, fbsynth.dm_trials(0, 0.1, 2048), 51.2e-6, 0, None))
+    for scale, tun in [(1.0, None), (1 / 64, (8, 2, 8, 0)), (1 / 16, (8, 1, 8, 0))]:
+        for sp in fbsynth.config4_specs(scale=scale):
+            f = fbsynth.channel_freqs(sp["f_top"], sp["bw"] / sp["nchan"], sp["nchan"])
+            cases.append((f, fbsynth.dm_trials(sp["dm0"], sp["step"], sp["ndm"]), sp["tsamp"], 2, tun))
+    for sp in fbsynth.config5_specs()[::8]:
+        f = fbsynth.channel_freqs(sp["f_top"], sp["bw"] / sp["nchan"], sp["nchan"])
+        cases.append((f, fbsynth.dm_trials(sp["dm0"], sp["step"], sp["ndm"]), sp["tsamp"], 2, None))
+    for freq, dm, tsamp, dt, tun in cases:
+        info = _launch_ok(lib, freq, dm, tsamp, dt, tun)
+        assert info.launch_ring >= 2 and 0 < info.launch_lds <= 160 * 1024, (len(freq), len(dm), tun)
+        assert info.launch_buf % 64 == 0 and info.launch_copies == 4

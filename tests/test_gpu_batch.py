@@ -1,0 +1,105 @@
+"""Batched persistent launch against one-at-a-time calls (bit for bit) and the oracle."""
+import numpy as np
+import pytest
+
+import fbsynth
+from oracle import dedisp_oracle as orc
+from tests.gpu_util import assert_rows_close, compare_candidates, cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return cuda()
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_1401_8258_amd as dd
+    dd.load_library()
+    return dd
+
+
+def _beams(scale, dtype="u8", seed=4):
+    specs = fbsynth.config4_specs(seed=seed, scale=scale)
+    out = []
+    for sp in specs:
+        rng = np.random.default_rng(sp["seed"])
+        b = fbsynth.make_beam(sp["name"], sp["nchan"], sp["f_top"], sp["bw"], sp["tsamp"], sp["dm0"], sp["step"],
+                              sp["ndm"], sp["nsamp"], rng, sp["npulse"], storage=dtype)
+        out.append(b)
+    return out
+
+
+def test_batch_equals_single_calls_uneven_u8(torch, dd):
+    print("case: batch of uneven u8 beams", flush=True)
+    beams = _beams(scale=1 / 64)[:8]
+    tuning = (8, 2)
+    plans = [dd.Plan(b.freq_mhz, b.tsamp_s, b.dm, dtype="u8", tuning=tuning) for b in beams]
+    xs = [torch.from_numpy(b.data).cuda() for b in beams]
+    singles = [p.dedisperse(x, k_sigma=6.0) for p, x in zip(plans, xs)]
+    batched = dd.batch_dedisperse(list(zip(plans, xs)), k_sigma=6.0)
+    torch.cuda.synchronize()
+    for b, p, s1, s2 in zip(beams, plans, singles, batched):
+        o1, o2 = s1.out.cpu().numpy(), s2.out.cpu().numpy()
+        np.testing.assert_array_equal(o1, o2)
+        np.testing.assert_array_equal(s1.mean.cpu().numpy(), s2.mean.cpu().numpy())
+        np.testing.assert_array_equal(s1.rms.cpu().numpy(), s2.rms.cpu().numpy())
+        c1, c2 = s1.candidates(), s2.candidates()
+        np.testing.assert_array_equal(c1, c2)
+        # and against the oracle: u8 codes sum exactly
+        tab = orc.delay_table(b.freq_mhz, b.dm, b.tsamp_s)
+        rows = [0, b.ndm // 2, b.ndm - 1]
+        want = orc.dedisperse(b.data, tab, rows=rows)
+        np.testing.assert_array_equal(o2[rows].astype(np.float64), want)
+
+
+def test_batch_f32_mixed_shapes(torch, dd):
+    print("case: batch of f32 beams", flush=True)
+    rng = np.random.default_rng(3)
+    jobs, refs = [], []
+    for nchan, ndm, nsamp, step in [(64, 100, 6000, 0.1), (128, 40, 9000, 0.3), (32, 300, 4000, 0.05)]:
+        freq = fbsynth.channel_freqs(428.0, 20.0 / nchan, nchan)
+        dm = fbsynth.dm_trials(0.0, step, ndm)
+        x = rng.standard_normal((nchan, nsamp)).astype(np.float32)
+        p = dd.Plan(freq, 51.2e-6, dm, tuning=(8, 4))
+        jobs.append((p, torch.from_numpy(x).cuda()))
+        refs.append((freq, dm, x))
+    res = dd.batch_dedisperse(jobs, k_sigma=4.0)
+    torch.cuda.synchronize()
+    for (p, x), r, (freq, dm, xh) in zip(jobs, res, refs):
+        s = p.dedisperse(x, k_sigma=4.0)
+        np.testing.assert_array_equal(s.out.cpu().numpy(), r.out.cpu().numpy())
+        tab = orc.delay_table(freq, dm, 51.2e-6)
+        want = orc.dedisperse(xh, tab)
+        mean, rms = orc.series_stats(want)
+        assert_rows_close(r.out.cpu().numpy(), want, rms, what="batch f32")
+        if orc.threshold_margin(want, mean, rms, 4.0) > 5e-5:
+            compare_candidates(r.candidates(), want, mean, rms, 4.0)
+
+
+def test_batched_stream_windows_equal_push(torch, dd):
+    print("case: batched stream windows", flush=True)
+    rng = np.random.default_rng(8)
+    freq = fbsynth.channel_freqs(428.0, 20.0 / 64, 64)
+    dm = fbsynth.dm_trials(0.0, 0.2, 64)
+    block = 600
+    nblk = 6
+    data = [rng.integers(0, 256, size=(64, block * nblk)).astype(np.uint8) for _ in range(3)]
+    plan = dd.Plan(freq, 51.2e-6, dm, dtype="u8", tuning=(8, 4))
+    pushed = [dd.Stream(plan, block) for _ in range(3)]
+    batched = [dd.Stream(plan, block) for _ in range(3)]
+    for k in range(nblk):
+        blocks = [torch.from_numpy(np.ascontiguousarray(d[:, k * block:(k + 1) * block])).cuda() for d in data]
+        want = [s.push(b, k_sigma=3.0) for s, b in zip(pushed, blocks)]
+        wins = [s.append(b) for s, b in zip(batched, blocks)]
+        assert all((w is None) == (r is None) for w, r in zip(wins, want))
+        if wins[0] is None:
+            continue
+        got = dd.batch_dedisperse(list(zip(batched, wins)), k_sigma=3.0)
+        torch.cuda.synchronize()
+        for g, r in zip(got, want):
+            assert g.t0 == r.t0
+            np.testing.assert_array_equal(g.out.cpu().numpy(), r.out.cpu().numpy())
+            np.testing.assert_array_equal(g.candidates(), r.candidates())
