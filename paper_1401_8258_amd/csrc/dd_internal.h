@@ -19,11 +19,14 @@ constexpr int64_t kTile = 512;
 constexpr int64_t kStatSeg = 8192;
 // LDS of one gfx950 workgroup.
 constexpr int64_t kLdsBytes = 160 * 1024;
+// Most DMA instructions one wavefront issues per stage (its descriptor table spans two
+// 64-lane registers).
+constexpr int kMaxDma = 128;
 
 // Launch geometry of the dedispersion kernel.
 struct Launch {
   int L;        // words per (channel, copy) buffer (four copies shifted by 0..3 samples)
-  int cs;       // channels per stage
+  int cs;       // channels per stage (a divisor of the wavefront count)
   int nb;       // stages in the LDS ring
   int nd;       // DMA instructions per wavefront per stage
   int64_t lds;  // bytes

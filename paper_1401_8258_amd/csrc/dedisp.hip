@@ -30,10 +30,6 @@ namespace {
 
 constexpr int kMaxThreads = 512;
 
-__device__ __forceinline__ float to_f32(float x) { return x; }
-__device__ __forceinline__ float to_f32(__half x) { return __half2float(x); }
-__device__ __forceinline__ float to_f32(uint8_t x) { return (float)x; }
-
 // Input view: linear rows, or a per-channel ring of ring_len samples in which
 // window position p lives at (win0 + p) mod ring_len.
 struct InView {
@@ -52,18 +48,25 @@ struct InView {
 //
 // Channel vectors (tile plus the group's delay spread, Eq. channelDispersionEquation)
 // reach LDS by DMA (global_load_lds) through a ring of nb stages of cs channels,
-// issued nb - 1 stages ahead, so HBM/L2 latency hides behind compute. Each channel is
-// stored four times, shifted by 0..3 samples, so the 4-sample chunks any trial needs
-// start 16-byte aligned: a trial costs one address add and two ds_read_b128 (lanes
-// read consecutive 16-byte slots: no bank conflicts). The host precomputes, per
-// (channel, trial), the LDS byte offset of the trial's first chunk inside the
-// channel's slot; those offsets ride along with the data in every stage, so the
-// inner loop needs no scalar arithmetic at all.
+// issued nb - 1 stages ahead, so HBM/L2 latency hides behind compute. Every sample
+// lands in a 32-bit LDS word (the byte and short DMA forms zero-extend 8- and 16-bit
+// inputs on the way), and each channel is stored four times, shifted by 0..3 samples,
+// so the 4-sample chunks any trial needs start 16-byte aligned: a trial costs an
+// address add and two ds_read_b128 (lanes read consecutive 16-byte slots: no bank
+// conflicts). The host precomputes, per (channel, trial), the byte offset of the
+// trial's first chunk inside the channel's slot; those offsets travel with the data.
+//
+// A stage's channels are split between the wavefronts (nw / cs of them per channel),
+// so all DMAs a wavefront issues in a stage address one channel: its first delay is a
+// scalar load and the per-DMA work is two lane reads of a descriptor table plus one
+// add. Nothing on the DMA path waits for LDS.
 
 constexpr int kTile = 512;
 constexpr int kG = 8;
 constexpr int kCopies = 4;
+constexpr int kMaxDma = 128;  // DMA instructions per wavefront per stage (two descriptor registers)
 static_assert(kTile == dd::kTile, "tile constant disagrees with the host plan");
+static_assert(kMaxDma == dd::kMaxDma, "DMA limit disagrees with the host plan");
 
 struct KParams {
   InView in;
@@ -74,12 +77,14 @@ struct KParams {
   int64_t out_stride, nout, nitems;
   int ndm_pad, nchan, ndm, ngroups;
   int L;        // words per (channel, copy) buffer
-  int cs;       // channels per stage
+  int cs;       // channels per stage (divides the wavefront count)
   int nb;       // stages in the LDS ring
   int nd;       // DMA instructions per wavefront per stage
   int nstages;  // ceil(nchan / cs)
-  int nbase;    // LDS words reserved for the group's first delays (nchan rounded up to 64)
+  int pad_;
 };
+
+typedef const __attribute__((address_space(4))) int32_t* ci32_t;
 
 // Wavefront sum in a fixed butterfly (identical for every launch shape).
 __device__ __forceinline__ double wave_sum_fixed(double v) {
@@ -112,135 +117,106 @@ __device__ __forceinline__ void wait_vm(int n) {
   }
 }
 
-// Window position pos (clamped into the valid range) as an element index into the row.
-__device__ __forceinline__ int64_t src_index(const InView& in, int64_t pos) {
-  if (pos >= in.nvalid) pos = in.nvalid - 1;
-  if (in.ring_len > 0) return (in.win0 + pos) % in.ring_len;
-  return pos;
-}
-
-// One LDS DMA: every lane copies the dword at base + voff to LDS at lds + 4 * lane.
-// Issued from asm so the compiler neither serialises later LDS reads behind it nor
-// counts it; the kernel waits for these with explicit vmcnt.
-__device__ __forceinline__ void dma_dword(const void* base, unsigned voff, unsigned lds) {
-  asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+// One LDS DMA: lane i copies the element at base + voff into the 32-bit LDS word at
+// lds + 4i (zero-extended for 1- and 2-byte elements). Issued from asm so the compiler
+// neither serialises later LDS reads behind it nor counts it; the kernel waits for these
+// with explicit vmcnt.
+template <int EB>
+__device__ __forceinline__ void dma(const void* base, unsigned voff, unsigned lds) {
+  if constexpr (EB == 4)
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+  else if constexpr (EB == 2)
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_ushort %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+  else
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_ubyte %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
 }
 
 __device__ __forceinline__ unsigned lds_addr(const void* p) {
   return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
 
-// LDS layout (4-byte words): [0, nbase) the group's first delay per channel, then the
-// ring's data slots (buf, cc, copy) of L words, then its offset slots (buf, cc) of 64
-// words (the LDS offsets of the group's trials for that channel).
-__device__ __forceinline__ int data_word(const KParams& P, int buf, int cc, int m) {
-  return P.nbase + ((buf * P.cs + cc) * kCopies + m) * P.L;
-}
-__device__ __forceinline__ int offs_word(const KParams& P, int buf, int cc) {
-  return P.nbase + P.nb * P.cs * kCopies * P.L + (buf * P.cs + cc) * 64;
+// LDS layout (4-byte words): the ring's channel slots (buf, cc), each holding the four
+// shifted copies (copy m word x = window sample first + m + x) followed by 64 words of
+// trial offsets (the LDS byte offsets of the group's trials for that channel).
+__device__ __forceinline__ int slot_word(const KParams& P, int buf, int cc) {
+  return (buf * P.cs + cc) * (kCopies * P.L + 64);
 }
 
-// Prologue: the group's first delay of every channel, DMA'd into LDS words [0, nchan).
-__device__ __forceinline__ void load_bases(const KParams& P, float* smem, int grp, int w, int nw, int lane) {
-  const int32_t* gb = P.gbase + (int64_t)grp * P.nchan;
-  const unsigned sbase = lds_addr(smem);
-  const int chunks = P.nbase >> 6;
-  const int per = (chunks + nw - 1) / nw;
-  for (int j = 0; j < per; ++j) {
-    int i = w + nw * j;
-    if (i >= chunks) i = chunks - 1;  // same count for every wavefront
-    const int x = min((i << 6) + lane, P.nchan - 1);
-    dma_dword(gb, 4u * (unsigned)x, sbase + 4u * (unsigned)(i << 6));
-  }
-}
-
-// The group's trial offsets for this stage's channels: wavefront w takes channels w, w + nw, ...
-__device__ __forceinline__ void stage_offsets(const KParams& P, float* smem, int st, int dg, int gw, int w, int nw,
-                                              int lane) {
-  const int buf = st % P.nb;
-  const unsigned sbase = lds_addr(smem);
-  const int per = (P.cs + nw - 1) / nw;
-  const unsigned voff = 4u * (unsigned)min(lane, gw - 1);
-  for (int j = 0; j < per; ++j) {
-    int cc = w + nw * j;
-    if (cc >= P.cs) cc = P.cs - 1;
-    int c = st * P.cs + cc;
-    if (c >= P.nchan) c = P.nchan - 1;
-    dma_dword(P.dtab + (int64_t)c * P.ndm_pad + dg, voff, sbase + 4u * (unsigned)offs_word(P, buf, cc));
-  }
-}
-
-// This wavefront's DMA share of stage `st` (f32 input): chunks t = w, w + nw, ... of the
-// stage's cs * 4 * (L/64) 64-word chunks (copy m word x holds window sample first + m + x),
-// then its offset slices.
-__device__ __forceinline__ void stage_dma(const KParams& P, float* smem, int st, int64_t t0, int dg, int gw, int w,
-                                          int nw, int lane, int w0) {
-  const float* src = static_cast<const float*>(P.in.ptr);
-  const int* lds_i = reinterpret_cast<const int*>(smem);
-  const int buf = st % P.nb;
+// A wavefront's DMA chunks of its stage channel: r = sub, sub + wpc, ... (clamped to the
+// last chunk, which keeps the per-wavefront count uniform). Chunk r < 4 * L/64 is copy
+// m = r / (L/64), 64-word piece i = r % (L/64); the last chunk is the offsets. Lane j of
+// (rel, ldw) describes chunk j (rel = source sample offset from the channel's first
+// sample, or -1 for the offsets; ldw = LDS word inside the slot).
+struct DmaDesc {
+  int rel[2], ldw[2];
+};
+__device__ __forceinline__ DmaDesc make_desc(const KParams& P, int sub, int wpc, int lane) {
   const int nch = P.L >> 6;
-  const int per = kCopies * nch;
-  const int nd_data = P.nd - (P.cs + nw - 1) / nw;
-  int cc = w / per;
-  int rem = w - cc * per;
-  int m = rem / nch;
-  int i = rem - m * nch;
-  const unsigned sbase = lds_addr(smem);
+  const int nchunk = kCopies * nch + 1;
+  DmaDesc d;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = min(sub + wpc * (lane + 64 * h), nchunk - 1);
+    const int m = r / nch;
+    const int i = r - m * nch;
+    d.rel[h] = m < kCopies ? m + 64 * i : -1;
+    d.ldw[h] = m < kCopies ? m * P.L + 64 * i : kCopies * P.L;
+  }
+  return d;
+}
+
+// One descriptor: the offsets chunk (rel < 0) or 64 consecutive window positions
+// q .. q + 63, clamped to the last valid position and, on a ring, wrapped.
+template <int EB, bool RING>
+__device__ __forceinline__ void dma_chunk(const char* rp, const int32_t* orow, int rel, unsigned m0, int first,
+                                          int nlim, int w0, int rlen, int lane, int gw) {
+  if (rel < 0) {
+    dma<4>(orow, 4u * (unsigned)min(lane, gw - 1), m0);
+    return;
+  }
+  unsigned pos = (unsigned)min(first + rel + lane, nlim);
+  if constexpr (RING) {
+    pos += (unsigned)w0;
+    pos = min(pos, pos - (unsigned)rlen);  // pos - rlen wraps above pos unless pos >= rlen
+  }
+  dma<EB>(rp, (unsigned)EB * pos, m0);
+}
+
+// This wavefront's DMAs for stage sd: its channel's chunks, then (as one of them) the
+// group's trial offsets for the channel.
+template <int EB, bool RING>
+__device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, unsigned sbase, int sd, int cc_w,
+                                          int64_t t0, int grp, int dg, int gw, int lane, int w0) {
+  int c = sd * P.cs + cc_w;
+  if (c >= P.nchan) c = P.nchan - 1;  // keeps the per-wavefront DMA count uniform
+  const ci32_t gb = (ci32_t)(P.gbase + (int64_t)grp * P.nchan);
+  const int first = (int)t0 + gb[c];
+  const char* rp = static_cast<const char*>(P.in.ptr) + (int64_t)c * P.in.row_stride * EB;
+  const int32_t* orow = P.dtab + (int64_t)c * P.ndm_pad + dg;
+  const unsigned slot = sbase + 4u * (unsigned)slot_word(P, sd % P.nb, cc_w);
   const int nlim = (int)P.in.nvalid - 1;
   const int rlen = (int)P.in.ring_len;
-  for (int j = 0; j < nd_data; ++j) {
-    int c = st * P.cs + cc;
-    if (c >= P.nchan) c = P.nchan - 1;  // keep the per-wave DMA count uniform
-    const int first = (int)t0 + __builtin_amdgcn_readfirstlane(lds_i[c]);
-    int pos = min(first + m + (i << 6) + lane, nlim);
-    if (rlen > 0) {
-      pos += w0;
-      if (pos >= rlen) pos -= rlen;
-    }
-    const float* rp = src + (int64_t)c * P.in.row_stride;
-    dma_dword(rp, 4u * (unsigned)pos, sbase + 4u * (unsigned)(data_word(P, buf, cc, m) + (i << 6)));
-    i += nw;
-    while (i >= nch) {
-      i -= nch;
-      if (++m == kCopies) {
-        m = 0;
-        ++cc;
-      }
-    }
+  const int n0 = min(P.nd, 64);
+  for (int j = 0; j < n0; ++j) {
+    const int rel = __builtin_amdgcn_readlane(D.rel[0], j);
+    const int ldw = __builtin_amdgcn_readlane(D.ldw[0], j);
+    dma_chunk<EB, RING>(rp, orow, rel, slot + 4u * (unsigned)ldw, first, nlim, w0, rlen, lane, gw);
   }
-  stage_offsets(P, smem, st, dg, gw, w, nw, lane);
-}
-
-// Synchronous staging for 16-bit and 8-bit inputs: load, convert to FP32, ds_write;
-// the stage's offsets by DMA, waited for here.
-template <typename TIn>
-__device__ __forceinline__ void stage_convert(const KParams& P, float* smem, int st, int64_t t0, int dg, int gw,
-                                              int w, int nw, int lane) {
-  const TIn* src = static_cast<const TIn*>(P.in.ptr);
-  const int* lds_i = reinterpret_cast<const int*>(smem);
-  const int buf = st % P.nb;
-  stage_offsets(P, smem, st, dg, gw, w, nw, lane);
-  for (int cc = 0; cc < P.cs; ++cc) {
-    int c = st * P.cs + cc;
-    if (c >= P.nchan) c = P.nchan - 1;
-    const int64_t first = t0 + __builtin_amdgcn_readfirstlane(lds_i[c]);
-    const TIn* rp = src + (int64_t)c * P.in.row_stride;
-    float* dst = smem + data_word(P, buf, cc, 0);
-    for (int x = threadIdx.x; x < P.L + 3; x += blockDim.x) {
-      const float v = to_f32(rp[src_index(P.in, first + x)]);
-      // copy m word x - m holds window sample first + x
-#pragma unroll
-      for (int m = 0; m < kCopies; ++m)
-        if (x - m >= 0 && x - m < P.L) dst[m * P.L + x - m] = v;
-    }
+  for (int j = 64; j < P.nd; ++j) {
+    const int rel = __builtin_amdgcn_readlane(D.rel[1], j - 64);
+    const int ldw = __builtin_amdgcn_readlane(D.ldw[1], j - 64);
+    dma_chunk<EB, RING>(rp, orow, rel, slot + 4u * (unsigned)ldw, first, nlim, w0, rlen, lane, gw);
   }
-  wait_vm(0);
 }
 
 // One (time tile, DM group) work unit; every wavefront of the workgroup takes part.
-template <typename TIn>
-__device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int grp, float* smem) {
-  constexpr bool DMA = std::is_same<TIn, float>::value;
+// 8-bit input sums exactly in 32-bit integers; 16- and 32-bit input sum in FP32 with a
+// sub-sum folded into the accumulator every DD_CHAN_BLOCK channels (fixed order in c).
+template <typename TIn, bool RING>
+__device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, int grp, float* smem) {
+  constexpr int EB = (int)sizeof(TIn);
+  constexpr bool U8 = std::is_same<TIn, uint8_t>::value;
+  constexpr bool F16 = std::is_same<TIn, __half>::value;
   const int nw = blockDim.x >> 6;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -249,79 +225,82 @@ __device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int gr
   const int dg = grp * gw;
   const int dw = dg + w * kG;
   const int w0 = P.in.ring_len > 0 ? (int)(P.in.win0 % P.in.ring_len) : 0;
+  const int wpc = nw / P.cs;
+  const int cc_w = w / wpc;
+  const DmaDesc D = make_desc(P, w - cc_w * wpc, wpc, lane);
+  const unsigned sbase = lds_addr(smem);
 
   float acc[kG][8];
   float sub[kG][8];
+  uint32_t iacc[kG][8];
 #pragma unroll
   for (int g = 0; g < kG; ++g)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f;
+    for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f, iacc[g][s] = 0u;
 
-  // prologue: the group's first delays (they address every later DMA), then stages
-  // 0 .. nb-2 in flight
-  load_bases(P, smem, grp, w, nw, lane);
-  wait_vm(0);
-  block_barrier();
-  if constexpr (DMA) {
-    const int pre = min(P.nb - 1, P.nstages);
-    for (int st = 0; st < pre; ++st) stage_dma(P, smem, st, t0, dg, gw, w, nw, lane, w0);
-  }
+  // prologue: stages 0 .. nb-2 in flight
+  const int pre = min(P.nb - 1, P.nstages);
+  for (int sd = 0; sd < pre; ++sd) stage_dma<EB, RING>(P, D, sbase, sd, cc_w, t0, grp, dg, gw, lane, w0);
   const int* lds_i = reinterpret_cast<const int*>(smem);
   const unsigned lane16 = 16u * (unsigned)lane;
+  const int offw = kCopies * P.L + w * kG;  // this wavefront's 8 offsets inside a slot
 
   for (int st = 0; st < P.nstages; ++st) {
-    if constexpr (DMA) {
-      // stages issued after st: min(nstages - 1, st + nb - 2) - st
-      const int later = min(P.nstages - 1, st + P.nb - 2) - st;
-      wait_vm(later * P.nd);
-      block_barrier();
-      if (st + P.nb - 1 < P.nstages) stage_dma(P, smem, st + P.nb - 1, t0, dg, gw, w, nw, lane, w0);
-    } else {
-      block_barrier();
-      stage_convert<TIn>(P, smem, st, t0, dg, gw, w, nw, lane);
-      __syncthreads();
-    }
+    // stages issued after st: min(nstages - 1, st + nb - 2) - st
+    const int later = min(P.nstages - 1, st + P.nb - 2) - st;
+    wait_vm(later * P.nd);
+    block_barrier();
+    if (st + P.nb - 1 < P.nstages) stage_dma<EB, RING>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0);
     const int buf = st % P.nb;
     const int n_here = min(P.cs, P.nchan - st * P.cs);
+    const int4* op = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, 0) + offw);
+    int4 o0 = op[0], o1 = op[1];
     for (int cc = 0; cc < n_here; ++cc) {
       const int c = st * P.cs + cc;
-      if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
+      if constexpr (!U8) {
+        if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
 #pragma unroll
-        for (int g = 0; g < kG; ++g)
+          for (int g = 0; g < kG; ++g)
 #pragma unroll
-          for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
+            for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
+        }
       }
-      // byte offsets of this wavefront's 8 trials inside the channel slot
-      const int4* op = reinterpret_cast<const int4*>(lds_i + offs_word(P, buf, cc) + w * kG);
-      const int4 o0 = op[0];
-      const int4 o1 = op[1];
       const int off[kG] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
-      const char* cb = reinterpret_cast<const char*>(smem + data_word(P, buf, cc, 0)) + lane16;
-      // all 16 reads of the channel first (more LDS reads in flight), then the adds
-      float4 v[2 * kG];
+      const char* cb = reinterpret_cast<const char*>(lds_i + slot_word(P, buf, cc)) + lane16;
+      // all 16 reads of the channel first (more LDS reads in flight), then the next
+      // channel's offsets, then the adds
+      uint4 v[2 * kG];
 #pragma unroll
       for (int g = 0; g < kG; ++g) {
-        const float4* a = reinterpret_cast<const float4*>(cb + off[g]);
+        const uint4* a = reinterpret_cast<const uint4*>(cb + off[g]);
         v[2 * g] = a[0];
         v[2 * g + 1] = a[64];
       }
+      if (cc + 1 < n_here) {
+        const int4* np = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, cc + 1) + offw);
+        o0 = np[0];
+        o1 = np[1];
+      }
 #pragma unroll
       for (int g = 0; g < kG; ++g) {
-        sub[g][0] += v[2 * g].x;
-        sub[g][1] += v[2 * g].y;
-        sub[g][2] += v[2 * g].z;
-        sub[g][3] += v[2 * g].w;
-        sub[g][4] += v[2 * g + 1].x;
-        sub[g][5] += v[2 * g + 1].y;
-        sub[g][6] += v[2 * g + 1].z;
-        sub[g][7] += v[2 * g + 1].w;
+        const uint32_t x[8] = {v[2 * g].x,     v[2 * g].y,     v[2 * g].z,     v[2 * g].w,
+                               v[2 * g + 1].x, v[2 * g + 1].y, v[2 * g + 1].z, v[2 * g + 1].w};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          if constexpr (U8)
+            iacc[g][s] += x[s];
+          else if constexpr (F16)
+            sub[g][s] += __half2float(__ushort_as_half((unsigned short)x[s]));
+          else
+            sub[g][s] += __uint_as_float(x[s]);
+        }
       }
     }
   }
 #pragma unroll
   for (int g = 0; g < kG; ++g)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s];
+    for (int s = 0; s < 8; ++s) acc[g][s] = U8 ? (float)iacc[g][s] : acc[g][s] + sub[g][s];
 
   const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
   const int64_t nseg = (P.nout + kTile - 1) / kTile;
@@ -360,6 +339,14 @@ __device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int gr
       }
     }
   }
+}
+
+template <typename TIn>
+__device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int grp, float* smem) {
+  if (P.in.ring_len > 0)
+    tile_body_impl<TIn, true>(P, tile, grp, smem);
+  else
+    tile_body_impl<TIn, false>(P, tile, grp, smem);
 }
 
 // Plain launch: one work unit per workgroup; each XCD (workgroups lin, lin + 8, ...)
@@ -624,7 +611,6 @@ int build_params(const dd_plan* p, const InView& in, const int32_t* d_table, int
   P->nb = g.nb;
   P->nd = g.nd;
   P->nstages = (p->nchan + g.cs - 1) / g.cs;
-  P->nbase = (p->nchan + 63) / 64 * 64;
   P->gbase = d_table + (int64_t)p->nchan * p->ndm_pad;
   *G = g;
   return DD_OK;

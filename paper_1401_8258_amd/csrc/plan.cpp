@@ -76,41 +76,35 @@ int64_t ring_table_bytes(const dd_plan* p) { return align_up((int64_t)p->dev_tab
 
 Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap) {
   Launch best{};
+  (void)nchan;
   // words one channel copy covers: tile + group spread (lane reads end at k - m + 511)
-  const int64_t need = kTile + (int64_t)max_span;
-  const int64_t L0 = (need + 63) / 64 * 64;  // whole 64-word DMA chunks
-  // LDS besides the ring: the group's first delay for every channel (padded to 64)
-  const int64_t base_bytes = ((int64_t)nchan + 63) / 64 * 64 * 4;
-  const int64_t ring_cap = lds_cap - base_bytes;
-  const int cs_hi = std::max(1, std::min(cs_req > 0 ? cs_req : 8, nchan));
+  const int64_t L = (kTile + (int64_t)max_span + 63) / 64 * 64;  // whole 64-word DMA chunks
+  // a channel's slot: four shifted copies plus the group's 64 trial offsets
+  const int64_t per_chan = (4 * L + 64) * 4;
+  const int64_t nchunk = 4 * (L / 64) + 1;
+  const int cs_hi = cs_req > 0 ? std::min(cs_req, nw) : nw;
   int64_t best_score = -1;
-  for (int64_t L = L0; L <= L0 + 64 * 8; L += 64) {
-    // a channel's slot: four shifted copies plus the group's 64 trial offsets
-    const int64_t per_chan = 4 * L * 4 + 64 * 4;
-    for (int cs = cs_hi; cs >= 1; --cs) {
-      const int64_t chunks = (int64_t)cs * 4 * (L / 64);
-      if (chunks % nw) continue;  // every wavefront issues the same number of DMAs
-      const int nd = (int)(chunks / nw) + (cs + nw - 1) / nw;  // + offset slices
-      if (ring_cap < cs * per_chan * 2) continue;
-      int nb = (int)std::min<int64_t>(ring_cap / (cs * per_chan), 16);
-      // with later stages in flight the wait counts them (vmcnt <= 63); a two-stage ring
-      // always waits for everything, so any DMA count is legal there
-      while (nb > 2 && (int64_t)(nb - 2) * nd > 60) --nb;
-      if (nb < 2) continue;
-      const int64_t score = ((int64_t)nb * cs) * 4096 - (L - L0);  // deepest ring, then least padding
-      if (cs_req > 0 && cs != cs_hi && best_score >= 0) continue;
-      if (score > best_score) {
-        best_score = score;
-        best.L = (int)L;
-        best.cs = cs;
-        best.nb = nb;
-        best.nd = nd;
-      }
+  for (int cs = cs_hi; cs >= 1; --cs) {
+    if (nw % cs) continue;  // each stage channel gets nw / cs whole wavefronts
+    const int64_t nd = (nchunk + nw / cs - 1) / (nw / cs);
+    if (nd > kMaxDma) continue;
+    int nb = (int)std::min<int64_t>(lds_cap / (cs * per_chan), 16);
+    // with later stages in flight the wait counts them (vmcnt <= 63); a two-stage ring
+    // always waits for everything, so any DMA count is legal there
+    while (nb > 2 && (int64_t)(nb - 2) * nd > 63) --nb;
+    if (nb < 2) continue;
+    if (cs_req > 0 && best_score >= 0) break;  // an explicit request takes the largest fitting divisor
+    const int64_t score = (int64_t)nb * cs * 16 + cs;  // most channels in flight, then fewest barriers
+    if (score > best_score) {
+      best_score = score;
+      best.L = (int)L;
+      best.cs = cs;
+      best.nb = nb;
+      best.nd = (int)nd;
     }
-    if (best_score >= 0 && L > L0 + 128) break;
   }
   if (best_score < 0) return Launch{};
-  best.lds = base_bytes + (int64_t)best.nb * best.cs * (4 * (int64_t)best.L * 4 + 64 * 4);
+  best.lds = (int64_t)best.nb * best.cs * per_chan;
   return best;
 }
 
