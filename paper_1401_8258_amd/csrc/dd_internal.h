@@ -22,6 +22,9 @@ constexpr int64_t kLdsBytes = 160 * 1024;
 // Most DMA instructions one wavefront issues per stage (its descriptor table spans two
 // 64-lane registers).
 constexpr int kMaxDma = 128;
+// Most 16-byte DMAs one wavefront issues per stage for FP32 input (one descriptor
+// register each); beyond that the 4-byte form is used.
+constexpr int kMaxX4 = 16;
 
 // Launch geometry of the dedispersion kernel.
 struct Launch {
@@ -29,9 +32,10 @@ struct Launch {
   int cs;       // channels per stage (a divisor of the wavefront count)
   int nb;       // stages in the LDS ring
   int nd;       // DMA instructions per wavefront per stage
+  int x4;       // FP32 data arrives by 16-byte DMAs
   int64_t lds;  // bytes
 };
-Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap);
+Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap, int elem_bytes);
 
 inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -66,6 +70,7 @@ struct dd_stream {
   const dd_plan* plan = nullptr;
   int64_t block = 0;        // largest block accepted
   int64_t ring_len = 0;     // R: samples per channel in the ring
+  int64_t ring_row = 0;     // R + mirror: a channel row; [R, ring_row) repeats [0, ring_row - R)
   void* ring = nullptr;     // device: [table | ring data]
   int64_t received = 0;     // total samples appended
   int64_t next_seq = 0;
@@ -92,6 +97,10 @@ struct WsLayout {
 };
 WsLayout workspace_layout(const dd_plan* p, int64_t nout);
 int64_t ring_table_bytes(const dd_plan* p);
+// Samples after a ring row's R that mirror its start, so no channel window the kernel
+// reads (at most launch.L + 3 samples from any start in [0, R)) wraps.
+inline int64_t ring_mirror(const dd_plan* p) { return (int64_t)p->launch.L + 64; }
+inline int64_t ring_len_for(const dd_plan* p, int64_t block) { return align_up(block + (int64_t)p->maxdelay, 64); }
 int64_t elem_bytes(int32_t dtype);
 
 }  // namespace dd

@@ -31,10 +31,12 @@ namespace {
 constexpr int kMaxThreads = 512;
 
 // Input view: linear rows, or a per-channel ring of ring_len samples in which
-// window position p lives at (win0 + p) mod ring_len.
+// window position p lives at (win0 + p) mod ring_len. A ring row continues past
+// ring_len with a mirror of its start, so a window read from any start in
+// [0, ring_len) is contiguous.
 struct InView {
   const void* ptr;
-  int64_t row_stride;  // elements between channel rows
+  int64_t row_stride;  // elements between channel rows (ring: ring_len + mirror)
   int64_t nvalid;      // window positions [0, nvalid) hold data
   int64_t ring_len;    // 0 for linear input
   int64_t win0;        // ring only: global sample of window position 0
@@ -65,8 +67,10 @@ constexpr int kTile = 512;
 constexpr int kG = 8;
 constexpr int kCopies = 4;
 constexpr int kMaxDma = 128;  // DMA instructions per wavefront per stage (two descriptor registers)
+constexpr int kMaxX4 = 16;    // 16-byte DMAs per wavefront per stage (one descriptor register each)
 static_assert(kTile == dd::kTile, "tile constant disagrees with the host plan");
 static_assert(kMaxDma == dd::kMaxDma, "DMA limit disagrees with the host plan");
+static_assert(kMaxX4 == dd::kMaxX4, "16-byte DMA limit disagrees with the host plan");
 
 struct KParams {
   InView in;
@@ -81,7 +85,7 @@ struct KParams {
   int nb;       // stages in the LDS ring
   int nd;       // DMA instructions per wavefront per stage
   int nstages;  // ceil(nchan / cs)
-  int pad_;
+  int x4;       // FP32 input: copies arrive by 16-byte DMAs (nd counts those)
 };
 
 typedef const __attribute__((address_space(4))) int32_t* ci32_t;
@@ -131,6 +135,11 @@ __device__ __forceinline__ void dma(const void* base, unsigned voff, unsigned ld
     asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_ubyte %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
 }
 
+// 16-byte LDS DMA: lane i copies 4 dwords from base + voff (4-byte aligned) to lds + 16i.
+__device__ __forceinline__ void dma_x4(const void* base, unsigned voff, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+}
+
 __device__ __forceinline__ unsigned lds_addr(const void* p) {
   return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
 }
@@ -142,70 +151,121 @@ __device__ __forceinline__ int slot_word(const KParams& P, int buf, int cc) {
   return (buf * P.cs + cc) * (kCopies * P.L + 64);
 }
 
+// Copy m, word x of a channel slot holds window sample first + m + x; slot word y of the
+// 4L data words is (m, x) = divmod(y, L). rel(y) = m + x is its offset from `first`.
+__device__ __forceinline__ int slot_rel(int y, int L) {
+  const int m = (y >= L) + (y >= 2 * L) + (y >= 3 * L);
+  return y - m * (L - 1);
+}
+
 // A wavefront's DMA chunks of its stage channel: r = sub, sub + wpc, ... (clamped to the
-// last chunk, which keeps the per-wavefront count uniform). Chunk r < 4 * L/64 is copy
-// m = r / (L/64), 64-word piece i = r % (L/64); the last chunk is the offsets. Lane j of
-// (rel, ldw) describes chunk j (rel = source sample offset from the channel's first
-// sample, or -1 for the offsets; ldw = LDS word inside the slot).
+// last chunk, which keeps the per-wavefront count uniform).
+//  x1 form (any input): chunk r < 4 * L/64 covers slot words 64r .. 64r + 63 (lane l:
+//    word 64r + l); the last chunk is the trial offsets. Lane j of (rel, ldw) describes
+//    chunk j: rel = source offset of its lane 0 from `first` (-1: offsets), ldw = slot word.
+//  x4 form (FP32): chunk r < L/64 covers slot words 256r .. 256r + 255 (lane l: words
+//    256r + 4l .. + 3, which never straddle two copies since L is a multiple of 64);
+//    relx[j] is this lane's source offset for chunk j. The offsets come as one more x1 DMA.
 struct DmaDesc {
   int rel[2], ldw[2];
+  int relx[kMaxX4];
 };
-__device__ __forceinline__ DmaDesc make_desc(const KParams& P, int sub, int wpc, int lane) {
+__device__ __forceinline__ void make_desc(const KParams& P, int sub, int wpc, int lane, DmaDesc* d) {
   const int nch = P.L >> 6;
+  if (P.x4) {
+#pragma unroll
+    for (int j = 0; j < kMaxX4; ++j) {
+      const int r = min(sub + wpc * j, nch - 1);
+      d->relx[j] = slot_rel(256 * r + 4 * lane, P.L);
+    }
+    d->rel[0] = d->rel[1] = d->ldw[0] = d->ldw[1] = 0;
+    return;
+  }
   const int nchunk = kCopies * nch + 1;
-  DmaDesc d;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int r = min(sub + wpc * (lane + 64 * h), nchunk - 1);
-    const int m = r / nch;
-    const int i = r - m * nch;
-    d.rel[h] = m < kCopies ? m + 64 * i : -1;
-    d.ldw[h] = m < kCopies ? m * P.L + 64 * i : kCopies * P.L;
+    d->rel[h] = r < kCopies * nch ? slot_rel(64 * r, P.L) : -1;
+    d->ldw[h] = 64 * r;
   }
-  return d;
+#pragma unroll
+  for (int j = 0; j < kMaxX4; ++j) d->relx[j] = 0;
 }
 
-// One descriptor: the offsets chunk (rel < 0) or 64 consecutive window positions
-// q .. q + 63, clamped to the last valid position and, on a ring, wrapped.
+// One x1 chunk: the offsets (rel < 0), or 64 slot words from source offset rel + lane (a
+// 64-word chunk lies inside one copy, L being a multiple of 64).
 template <int EB, bool RING>
-__device__ __forceinline__ void dma_chunk(const char* rp, const int32_t* orow, int rel, unsigned m0, int first,
-                                          int nlim, int w0, int rlen, int lane, int gw) {
+__device__ __forceinline__ void dma_chunk(const char* rp, const int32_t* orow, int rel, int ldw, unsigned slot,
+                                          int start, int nlim, int lane, int gw) {
+  const unsigned m0 = slot + 4u * (unsigned)ldw;
   if (rel < 0) {
     dma<4>(orow, 4u * (unsigned)min(lane, gw - 1), m0);
     return;
   }
-  unsigned pos = (unsigned)min(first + rel + lane, nlim);
-  if constexpr (RING) {
-    pos += (unsigned)w0;
-    pos = min(pos, pos - (unsigned)rlen);  // pos - rlen wraps above pos unless pos >= rlen
-  }
-  dma<EB>(rp, (unsigned)EB * pos, m0);
+  int pos = start + rel + lane;
+  if constexpr (!RING) pos = min(pos, nlim);
+  dma<EB>(rp, (unsigned)(EB * pos), m0);
 }
 
-// This wavefront's DMAs for stage sd: its channel's chunks, then (as one of them) the
-// group's trial offsets for the channel.
+// This wavefront's DMAs for stage sd: its channel's chunks and the group's trial offsets
+// for that channel. `start` is the row index of window position `first`: on a ring,
+// (win0 + first) mod ring_len, and the mirror keeps the whole window contiguous.
 template <int EB, bool RING>
 __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, unsigned sbase, int sd, int cc_w,
-                                          int64_t t0, int grp, int dg, int gw, int lane, int w0) {
+                                          int64_t t0, int grp, int dg, int gw, int lane, int w0, int sub, int wpc) {
   int c = sd * P.cs + cc_w;
   if (c >= P.nchan) c = P.nchan - 1;  // keeps the per-wavefront DMA count uniform
   const ci32_t gb = (ci32_t)(P.gbase + (int64_t)grp * P.nchan);
   const int first = (int)t0 + gb[c];
+  int start = first;
+  if constexpr (RING) {
+    start += w0;
+    if (start >= (int)P.in.ring_len) start -= (int)P.in.ring_len;
+  }
   const char* rp = static_cast<const char*>(P.in.ptr) + (int64_t)c * P.in.row_stride * EB;
   const int32_t* orow = P.dtab + (int64_t)c * P.ndm_pad + dg;
   const unsigned slot = sbase + 4u * (unsigned)slot_word(P, sd % P.nb, cc_w);
   const int nlim = (int)P.in.nvalid - 1;
-  const int rlen = (int)P.in.ring_len;
+  if constexpr (EB == 4) {
+    if (P.x4) {
+      const int nch = P.L >> 6;
+      const int njx = P.nd - 1;
+      // the window's last sample is first + L + 2 (copy 3, word L - 1)
+      if (RING || first + P.L + 2 <= nlim) {
+#pragma unroll
+        for (int j = 0; j < kMaxX4; ++j) {
+          if (j < njx) {
+            const int r = min(sub + wpc * j, nch - 1);
+            dma_x4(rp, 4u * (unsigned)(start + D.relx[j]), slot + 1024u * (unsigned)r);
+          }
+        }
+      } else {
+        // data ends inside this window: per-lane clamped 4-byte DMAs (four per chunk),
+        // then wait for them so the vmcnt bookkeeping of later stages stays exact
+        for (int j = 0; j < njx; ++j) {
+          const int r = min(sub + wpc * j, nch - 1);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int y = 256 * r + 64 * k;
+            dma<4>(rp, 4u * (unsigned)min(first + slot_rel(y + lane, P.L), nlim), slot + 4u * (unsigned)y);
+          }
+        }
+        wait_vm(0);
+      }
+      dma<4>(orow, 4u * (unsigned)min(lane, gw - 1), slot + 4u * (unsigned)(kCopies * P.L));
+      return;
+    }
+  }
   const int n0 = min(P.nd, 64);
   for (int j = 0; j < n0; ++j) {
     const int rel = __builtin_amdgcn_readlane(D.rel[0], j);
     const int ldw = __builtin_amdgcn_readlane(D.ldw[0], j);
-    dma_chunk<EB, RING>(rp, orow, rel, slot + 4u * (unsigned)ldw, first, nlim, w0, rlen, lane, gw);
+    dma_chunk<EB, RING>(rp, orow, rel, ldw, slot, start, nlim, lane, gw);
   }
   for (int j = 64; j < P.nd; ++j) {
     const int rel = __builtin_amdgcn_readlane(D.rel[1], j - 64);
     const int ldw = __builtin_amdgcn_readlane(D.ldw[1], j - 64);
-    dma_chunk<EB, RING>(rp, orow, rel, slot + 4u * (unsigned)ldw, first, nlim, w0, rlen, lane, gw);
+    dma_chunk<EB, RING>(rp, orow, rel, ldw, slot, start, nlim, lane, gw);
   }
 }
 
@@ -227,7 +287,9 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
   const int w0 = P.in.ring_len > 0 ? (int)(P.in.win0 % P.in.ring_len) : 0;
   const int wpc = nw / P.cs;
   const int cc_w = w / wpc;
-  const DmaDesc D = make_desc(P, w - cc_w * wpc, wpc, lane);
+  const int wsub = w - cc_w * wpc;
+  DmaDesc D;
+  make_desc(P, wsub, wpc, lane, &D);
   const unsigned sbase = lds_addr(smem);
 
   float acc[kG][8];
@@ -240,7 +302,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
 
   // prologue: stages 0 .. nb-2 in flight
   const int pre = min(P.nb - 1, P.nstages);
-  for (int sd = 0; sd < pre; ++sd) stage_dma<EB, RING>(P, D, sbase, sd, cc_w, t0, grp, dg, gw, lane, w0);
+  for (int sd = 0; sd < pre; ++sd) stage_dma<EB, RING>(P, D, sbase, sd, cc_w, t0, grp, dg, gw, lane, w0, wsub, wpc);
   const int* lds_i = reinterpret_cast<const int*>(smem);
   const unsigned lane16 = 16u * (unsigned)lane;
   const int offw = kCopies * P.L + w * kG;  // this wavefront's 8 offsets inside a slot
@@ -250,7 +312,8 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
     const int later = min(P.nstages - 1, st + P.nb - 2) - st;
     wait_vm(later * P.nd);
     block_barrier();
-    if (st + P.nb - 1 < P.nstages) stage_dma<EB, RING>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0);
+    if (st + P.nb - 1 < P.nstages) stage_dma<EB, RING>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0, wsub,
+                                                      wpc);
     const int buf = st % P.nb;
     const int n_here = min(P.cs, P.nchan - st * P.cs);
     const int4* op = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, 0) + offw);
@@ -533,16 +596,22 @@ __global__ __launch_bounds__(256) void cand_write(const float* __restrict__ out,
   }
 }
 
+// Row c of the ring holds sample t at (t mod ring_len); positions below `mirror` are
+// also written at ring_len + position, so any window of up to `mirror` samples starting
+// in [0, ring_len) reads contiguously.
 template <typename TIn>
 __global__ __launch_bounds__(256) void ring_append(const TIn* __restrict__ blk, int64_t in_stride, int64_t n,
-                                                   TIn* __restrict__ ring, int64_t ring_len, int64_t pos0) {
+                                                   TIn* __restrict__ ring, int64_t ring_row, int64_t ring_len,
+                                                   int64_t mirror, int64_t pos0) {
   const int c = blockIdx.y;
   const TIn* s = blk + (int64_t)c * in_stride;
-  TIn* r = ring + (int64_t)c * ring_len;
+  TIn* r = ring + (int64_t)c * ring_row;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
     int64_t p = pos0 + j;
     if (p >= ring_len) p -= ring_len;
-    r[p] = s[j];
+    const TIn v = s[j];
+    r[p] = v;
+    if (p < mirror) r[ring_len + p] = v;
   }
 }
 
@@ -611,6 +680,7 @@ int build_params(const dd_plan* p, const InView& in, const int32_t* d_table, int
   P->nb = g.nb;
   P->nd = g.nd;
   P->nstages = (p->nchan + g.cs - 1) / g.cs;
+  P->x4 = g.x4;
   P->gbase = d_table + (int64_t)p->nchan * p->ndm_pad;
   *G = g;
   return DD_OK;
@@ -727,7 +797,8 @@ int dd_stream_create(const dd_plan* p, int64_t block_nsamp, void* d_ring, int64_
   if (!s) return dd::fail(DD_ERR_INVALID_ARG, "out of host memory");
   s->plan = p;
   s->block = block_nsamp;
-  s->ring_len = dd::align_up(block_nsamp + (int64_t)p->maxdelay, 64);
+  s->ring_len = dd::ring_len_for(p, block_nsamp);
+  s->ring_row = s->ring_len + dd::ring_mirror(p);
   s->ring = d_ring;
   hipError_t e = hipMemcpyAsync(d_ring, p->dev_table.data(), p->dev_table.size() * 4, hipMemcpyHostToDevice,
                                 static_cast<hipStream_t>(stream));
@@ -755,18 +826,21 @@ int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t i
   const dd_plan* p = s->plan;
   char* ring = static_cast<char*>(s->ring) + dd::ring_table_bytes(p);
   const int64_t pos0 = s->received % s->ring_len;
+  const int64_t mirror = s->ring_row - s->ring_len;
   const unsigned gx = (unsigned)std::min<int64_t>((nsamp + 255) / 256, 1024);
   dim3 grid(gx, (unsigned)p->nchan);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == DD_F32)
     hipLaunchKernelGGL(ring_append<float>, grid, dim3(256), 0, st, static_cast<const float*>(d_block), in_row_stride,
-                       nsamp, reinterpret_cast<float*>(ring), s->ring_len, pos0);
+                       nsamp, reinterpret_cast<float*>(ring), s->ring_row, s->ring_len, mirror, pos0);
   else if (p->dtype == DD_F16)
     hipLaunchKernelGGL(ring_append<__half>, grid, dim3(256), 0, st, static_cast<const __half*>(d_block),
-                       in_row_stride, nsamp, reinterpret_cast<__half*>(ring), s->ring_len, pos0);
+                       in_row_stride, nsamp, reinterpret_cast<__half*>(ring), s->ring_row, s->ring_len, mirror,
+                       pos0);
   else
     hipLaunchKernelGGL(ring_append<uint8_t>, grid, dim3(256), 0, st, static_cast<const uint8_t*>(d_block),
-                       in_row_stride, nsamp, reinterpret_cast<uint8_t*>(ring), s->ring_len, pos0);
+                       in_row_stride, nsamp, reinterpret_cast<uint8_t*>(ring), s->ring_row, s->ring_len, mirror,
+                       pos0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "ring_append launch");
   s->received += nsamp;
@@ -798,7 +872,7 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
   rc = dd_stream_append(s, d_block, nsamp, in_row_stride, seq, stream, &t0, &n);
   if (rc != DD_OK) return rc;
   s->pending_n = 0;
-  InView in{static_cast<char*>(s->ring) + dd::ring_table_bytes(p), s->ring_len, n + p->maxdelay, s->ring_len, t0};
+  InView in{static_cast<char*>(s->ring) + dd::ring_table_bytes(p), s->ring_row, n + p->maxdelay, s->ring_len, t0};
   Outputs o{d_out, out_row_stride, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand, t0};
   rc = run_pipeline(p, in, static_cast<const int32_t*>(s->ring), n, o, static_cast<char*>(d_workspace), l,
                     static_cast<hipStream_t>(stream));
@@ -847,7 +921,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
         return dd::fail(DD_ERR_SEQUENCE, "batch item " + std::to_string(i) + ": stream has no appended window");
       nout = sp->pending_n;
       t_base = sp->pending_t0;
-      in = InView{static_cast<char*>(sp->ring) + dd::ring_table_bytes(p), sp->ring_len, nout + p->maxdelay,
+      in = InView{static_cast<char*>(sp->ring) + dd::ring_table_bytes(p), sp->ring_row, nout + p->maxdelay,
                   sp->ring_len, sp->pending_t0};
       table = static_cast<const int32_t*>(sp->ring);
       lay_n = sp->block;

@@ -74,7 +74,7 @@ WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
 
 int64_t ring_table_bytes(const dd_plan* p) { return align_up((int64_t)p->dev_table.size() * 4); }
 
-Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap) {
+Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap, int elem_bytes) {
   Launch best{};
   (void)nchan;
   // words one channel copy covers: tile + group spread (lane reads end at k - m + 511)
@@ -86,7 +86,12 @@ Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t ld
   int64_t best_score = -1;
   for (int cs = cs_hi; cs >= 1; --cs) {
     if (nw % cs) continue;  // each stage channel gets nw / cs whole wavefronts
-    const int64_t nd = (nchunk + nw / cs - 1) / (nw / cs);
+    const int wpc = nw / cs;
+    // FP32: 256-word chunks by 16-byte DMAs plus one offsets DMA; otherwise 64-word
+    // chunks (the last one the offsets), split over the channel's wavefronts
+    const int64_t njx = (L / 64 + wpc - 1) / wpc;
+    const int x4 = elem_bytes == 4 && njx <= kMaxX4;
+    const int64_t nd = x4 ? njx + 1 : (nchunk + wpc - 1) / wpc;
     if (nd > kMaxDma) continue;
     int nb = (int)std::min<int64_t>(lds_cap / (cs * per_chan), 16);
     // with later stages in flight the wait counts them (vmcnt <= 63); a two-stage ring
@@ -101,6 +106,7 @@ Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t ld
       best.cs = cs;
       best.nb = nb;
       best.nd = (int)nd;
+      best.x4 = x4;
     }
   }
   if (best_score < 0) return Launch{};
@@ -188,7 +194,7 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   for (int oi = 0; oi < 4; ++oi) {
     const int nw = t.w ? t.w : w_opts[oi];
     span = compute_span(p->delays, nchan, ndm, t.g * nw);
-    lg = dd::choose_launch(span, nw, nchan, t.cc, dd::kLdsBytes);
+    lg = dd::choose_launch(span, nw, nchan, t.cc, dd::kLdsBytes, (int)dd::elem_bytes(in_dtype));
     if (t.w || (lg.nb >= 2 && (int64_t)lg.nb * lg.cs >= std::min(8, nchan + 1)) || nw == 1) {
       t.w = nw;
       break;
@@ -251,8 +257,8 @@ int dd_plan_query(const dd_plan* p, int64_t nsamp, dd_plan_info* info) {
   info->launch_ring = p->launch.nb;
   info->launch_lds = p->launch.lds;
   if (nsamp <= 0) return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be > 0");
-  const int64_t ring_len = dd::align_up(nsamp + (int64_t)p->maxdelay, 64);
-  info->ring_bytes = dd::ring_table_bytes(p) + dd::align_up(ring_len * p->nchan * dd::elem_bytes(p->dtype));
+  const int64_t ring_row = dd::ring_len_for(p, nsamp) + dd::ring_mirror(p);
+  info->ring_bytes = dd::ring_table_bytes(p) + dd::align_up(ring_row * p->nchan * dd::elem_bytes(p->dtype));
   const int64_t nout = nsamp - p->maxdelay;
   // sized for nsamp outputs: covers a plain call (nout < nsamp) and a stream push (<= block)
   const dd::WsLayout l = dd::workspace_layout(p, nsamp);
