@@ -22,11 +22,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 2.4 GHz. FP32 vector peak 157.3 TFLOP/s counts a fused multiply-add as
-# two flops on 128 lanes/clk/CU (packed FP32); an add is one flop on one lane-slot.
-PEAK_ADD_TFLOPS = 256 * 2.4e9 * 128 / 1e12          # 78.6e12 adds/s
-PEAK_ADD_UNPACKED_TFLOPS = 256 * 2.4e9 * 64 / 1e12  # 39.3e12 adds/s
+# MI355X: 256 CUs x 2.4 GHz. The FP32 vector peak of 157.3 TFLOP/s counts a fused
+# multiply-add as two flops on 128 lanes/clk/CU; an add is one flop per lane, so the
+# add roofline is 256 x 2.4e9 x 128 = 78.6e12 adds/s (v_add_f32 issues at that rate).
+PEAK_ADD_TFLOPS = 256 * 2.4e9 * 128 / 1e12
+# The kernel's own ceiling: every add consumes one 4-byte LDS word, and ds_read_b128
+# delivers ~221 B/clk/CU, so at most 256 x 2.4e9 x 221 / 4 = 33.9e12 adds/s.
+LDS_CEILING_TADDS = 256 * 2.4e9 * 221 / 4 / 1e12
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dedisp_tile_full_fp32_1024ch_2048dm_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1401_8258_amd", "csrc", "dedisp.hip")
 
 
 def parse():
@@ -37,8 +42,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-rows", type=int, default=12, help="DM rows in the oracle sample")
     ap.add_argument("--tuning", type=str, default=None, help="dms_per_wave,waves[,chan_stage] tile override")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON with measured HBM fetch/write bytes per launch of the dedispersion kernel")
+    ap.add_argument("--traffic", type=str, default=TRAFFIC_FILE,
+                    help="JSON with measured HBM fetch/write bytes per launch of the dedispersion kernel "
+                         "(used only while the kernel source is the one it was measured on)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the input (known bytes) to calibrate HBM counters")
     return ap.parse_args()
@@ -130,15 +136,24 @@ def main():
 
     adds = beam.ndm * beam.nchan * nout
     achieved = adds / (ms_kernel * 1e-3) / 1e12
-    traffic = None
+    traffic, traffic_note = None, "no counter record"
     if args.traffic and os.path.exists(args.traffic):
+        from paper_1401_8258_amd.profiling import source_digest
         with open(args.traffic) as f:
-            traffic = json.load(f)
+            rec = json.load(f)
+        if rec.get("kernel_source_sha256") == source_digest(KERNEL_SOURCE):
+            traffic = rec["hbm_bytes_per_launch"]
+            traffic_note = (f"FETCH_SIZE x {rec['fetch_scale']} + WRITE_SIZE x {rec['write_scale']} "
+                            f"(copy-kernel calibration), {os.path.relpath(args.traffic, ROOT)}")
+        else:
+            traffic_note = "kernel changed since the counters were taken"
+    algo_bytes = beam.nchan * nsamp * 4 + beam.ndm * nout * 4
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ADD_TFLOPS, 2),
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_ADD_TFLOPS, 4), "traffic": traffic,
+            "traffic_note": traffic_note, "algorithmic_bytes": algo_bytes,
             "kernel": "dedisp_tile", "kernel_ms": round(ms_kernel, 3),
-            "frac_of_unpacked_fp32_add_peak": round(achieved / PEAK_ADD_UNPACKED_TFLOPS, 4),
-            "algorithmic_hbm_gbs": round((beam.nchan * nsamp * 4 + beam.ndm * nout * 4) / (ms_kernel * 1e-3) / 1e9, 1)}
+            "frac_of_lds_ceiling": round(achieved / LDS_CEILING_TADDS, 4),
+            "algorithmic_hbm_gbs": round(algo_bytes / (ms_kernel * 1e-3) / 1e9, 1)}
 
     res = {
         "metric": "DM-trial*samples/s",

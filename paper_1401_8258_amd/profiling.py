@@ -1,0 +1,91 @@
+"""Turn rocprofv3 counter CSVs into the HBM traffic record that bench.py reports.
+
+Usage (after two counter runs of the same command, one with ``--pmc FETCH_SIZE`` and
+one with ``--pmc WRITE_SIZE``, each also running one plain device copy of known size):
+
+    python -m paper_1401_8258_amd.profiling traffic \
+        --fetch <dir>/bench_counter_collection.csv --write <dir>/bench_counter_collection.csv \
+        --kernel dedisp_tile --copy-bytes N --source paper_1401_8258_amd/csrc/dedisp.hip \
+        --out profiles/<kernel>_<workload>_traffic.json
+
+FETCH_SIZE and WRITE_SIZE are KiB per dispatch summed over the L2 channels. Each is
+scaled by bytes / counter of the copy kernel (``__amd_rocclr_copyBuffer``) of the same
+run, which moves ``copy-bytes`` in each direction. The record stores the SHA-256 of the
+kernel source, so a reader can tell when the kernel has changed since the counters were
+taken.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import statistics
+import sys
+
+
+def source_digest(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _rows(path: str, counter: str):
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                yield r["Kernel_Name"], float(r["Counter_Value"])
+
+
+def _kernel_and_copy(path: str, counter: str, kernel: str):
+    ks, cs = [], []
+    for name, v in _rows(path, counter):
+        if kernel in name:
+            ks.append(v)
+        elif "copyBuffer" in name:
+            cs.append(v)
+    if not ks:
+        raise SystemExit(f"{path}: no {counter} rows for a kernel named like {kernel!r}")
+    if not cs:
+        raise SystemExit(f"{path}: no copy-kernel rows to calibrate {counter}")
+    return ks, max(cs)  # the big copy (the probe); small copies are argument uploads
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, source: str) -> dict:
+    fk, fc = _kernel_and_copy(fetch_csv, "FETCH_SIZE", kernel)
+    wk, wc = _kernel_and_copy(write_csv, "WRITE_SIZE", kernel)
+    f_scale = copy_bytes / (fc * 1024.0)
+    w_scale = copy_bytes / (wc * 1024.0)
+    fetch = statistics.mean(fk) * 1024.0 * f_scale
+    write = statistics.mean(wk) * 1024.0 * w_scale
+    return {
+        "kernel": kernel,
+        "hbm_bytes_per_launch": round(fetch + write),
+        "fetch_bytes": round(fetch), "write_bytes": round(write),
+        "fetch_kib_raw": statistics.mean(fk), "write_kib_raw": statistics.mean(wk),
+        "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+        "copy_bytes": copy_bytes, "launches": len(fk),
+        "kernel_source_sha256": source_digest(source),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_1401_8258_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--source", required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.source)
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    json.dump(rec, sys.stdout, indent=1)
+    print()
+
+
+if __name__ == "__main__":
+    main()
