@@ -252,13 +252,21 @@ def _outputs(ndm: int, ncols: int, device, k_sigma: float, cand_cap: int, stats:
     return out, mean, rms, cand, ncand
 
 
-def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True, stream=None):
+def alloc_outputs(ndm: int, ncols: int, device, k_sigma: float = 0.0, cand_cap: int = 1 << 16,
+                  stats: bool = True):
+    """Output buffers (out, mean, rms, cand, ncand) for one job, for reuse across calls."""
+    return _outputs(ndm, ncols, device, k_sigma, cand_cap, stats)
+
+
+def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True, stream=None,
+                     outputs=None):
     """Dedisperse several inputs in one persistent launch (dd_batch_dedisperse).
 
     jobs: a list of (Plan, tensor) pairs and/or (Stream, (t0, nout)) pairs, the latter
     after Stream.append returned a pending window. All plans must share the input dtype
-    and DM trials per workgroup. Returns one Result per job, equal bit for bit to the
-    one-at-a-time calls.
+    and DM trials per workgroup. ``outputs`` optionally gives, per job, buffers from
+    alloc_outputs (with ``stats`` and ``k_sigma`` matching) to write into instead of new
+    ones. Returns one Result per job, equal bit for bit to the one-at-a-time calls.
     """
     lib = _lib.load()
     items = (_lib.BatchItem * len(jobs))()
@@ -266,11 +274,12 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
     results = []
     for i, (obj, arg) in enumerate(jobs):
         it = items[i]
+        given = outputs[i] if outputs is not None else None
         if isinstance(obj, Stream):
             t0, n = arg
             plan = obj.plan
             dev = obj.device
-            out, mean, rms, cand, ncand = _outputs(plan.ndm, obj.block, dev, k_sigma, cand_cap, stats)
+            out, mean, rms, cand, ncand = given or _outputs(plan.ndm, obj.block, dev, k_sigma, cand_cap, stats)
             it.plan = plan.handle.value
             it.stream_item = obj.handle.value
             it.d_plan_workspace = obj.ws.data_ptr()
@@ -282,7 +291,7 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
             nsamp = int(x.shape[1])
             cols = nsamp - plan.maxdelay
             t0 = 0
-            out, mean, rms, cand, ncand = _outputs(plan.ndm, cols, x.device, k_sigma, cand_cap, stats)
+            out, mean, rms, cand, ncand = given or _outputs(plan.ndm, cols, x.device, k_sigma, cand_cap, stats)
             ws = plan.workspace(nsamp, x.device, stream)
             it.plan = plan.handle.value
             it.d_in = x.data_ptr()
@@ -290,6 +299,8 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
             it.in_row_stride = int(x.stride(0))
             it.d_plan_workspace = ws.data_ptr()
             keep.append(ws)
+        if out.shape[0] != plan.ndm or out.shape[1] < cols:
+            raise ValueError(f"job {i}: output buffer smaller than [ndm][{cols}]")
         it.d_out = out.data_ptr()
         it.out_row_stride = int(out.stride(0))
         it.d_mean = mean.data_ptr() if mean is not None else None

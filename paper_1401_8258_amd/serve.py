@@ -249,6 +249,117 @@ class Server:
         return self.stats
 
 
+class LibraryExecutor(Executor):
+    """Device side on libdedisp: one Stream (device ring with the maxdelay overlap) per
+    admitted beam, and per submitted set of blocks one batched launch per group of beams
+    that share the input dtype and wavefronts per workgroup.
+
+    Each beam owns two output sets (dedispersed block, mean, rms, candidates), used by
+    alternate blocks, so a block's results stay intact while the next block of the same
+    beam is already queued behind it. ``keep`` stores copies of every result (for tests).
+    """
+
+    def __init__(self, k_sigma: float = 6.0, cand_cap: int = 1 << 14, device="cuda", stream=None,
+                 tunings: Optional[Dict[str, tuple]] = None, keep: bool = False):
+        import torch
+
+        from . import api
+        self._torch = torch
+        self._api = api
+        self.k_sigma = float(k_sigma)
+        self.cand_cap = int(cand_cap)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.tunings = dict(tunings or {})
+        self.keep = keep
+        self.kept: Dict[tuple, dict] = {}
+        self._plans: Dict[str, object] = {}
+        self._beams: Dict[int, dict] = {}
+
+    def plan(self, spec: BeamSpec):
+        p = self._plans.get(spec.name)
+        if p is None:
+            p = self._api.Plan(spec.freq_mhz, spec.tsamp_s, spec.dm, dtype=spec.dtype,
+                               tuning=self.tunings.get(spec.name))
+            self._plans[spec.name] = p
+        return p
+
+    def footprint(self, spec: BeamSpec) -> int:
+        p = self.plan(spec)
+        q = p.query(spec.block, allow_short=True)
+        outs = p.ndm * spec.block * 4 + 2 * p.ndm * 4 + self.cand_cap * 24 + 8
+        return int(q["ring_bytes"] + q["workspace_bytes"] + 2 * outs)
+
+    def open(self, beam: int, spec: BeamSpec) -> None:
+        p = self.plan(spec)
+        st = self._api.Stream(p, spec.block, device=self.device, stream=self.stream)
+        outs = [self._api.alloc_outputs(p.ndm, spec.block, self.device, self.k_sigma, self.cand_cap)
+                for _ in range(2)]
+        self._beams[beam] = {"stream": st, "outs": outs, "n": 0, "spec": spec}
+
+    def close(self, beam: int) -> None:
+        self._beams.pop(beam, None)
+
+    def prefill(self, beam: int, blocks) -> int:
+        """Append blocks without dedispersing (fast-forward a ring past its fill); returns how
+        many blocks were still filling. Must precede the beam's first submitted block."""
+        b = self._beams[beam]
+        filling = 0
+        for x in blocks:
+            w = b["stream"].append(x, stream=self.stream)
+            if w is None:
+                filling += 1
+            else:
+                raise ValueError("prefill went past the ring fill; use fewer blocks")
+        return filling
+
+    def submit(self, blocks: List[Block]):
+        pend = []
+        for blk in blocks:
+            b = self._beams[blk.beam]
+            pend.append(b["stream"].append(blk.data, stream=self.stream))
+        groups: Dict[tuple, List[int]] = collections.defaultdict(list)
+        for i, (blk, w) in enumerate(zip(blocks, pend)):
+            if w is not None:
+                plan = self._beams[blk.beam]["stream"].plan
+                groups[(plan.dtype, plan.tiles[1])].append(i)
+        res: List[object] = [None] * len(blocks)
+        for idx in groups.values():
+            jobs, outs = [], []
+            for i in idx:
+                b = self._beams[blocks[i].beam]
+                jobs.append((b["stream"], pend[i]))
+                outs.append(b["outs"][b["n"] & 1])
+            rs = self._api.batch_dedisperse(jobs, k_sigma=self.k_sigma, cand_cap=self.cand_cap, stream=self.stream,
+                                            outputs=outs)
+            for i, r in zip(idx, rs):
+                res[i] = r
+        for blk, w in zip(blocks, pend):
+            if w is not None:
+                self._beams[blk.beam]["n"] += 1
+        ev = self._torch.cuda.Event()
+        ev.record(self.stream)
+        return ev, list(blocks), res
+
+    def done(self, handle) -> bool:
+        return handle[0].query()
+
+    def results(self, handle) -> List[dict]:
+        _, blocks, res = handle
+        out = []
+        for blk, r in zip(blocks, res):
+            if r is None:
+                out.append({"t0": 0, "nout": 0, "ncand": 0, "filling": True})
+                continue
+            n = int(r.ncand()) if r._ncand is not None else 0
+            out.append({"t0": int(r.t0), "nout": int(r.out.shape[1]), "ncand": n, "filling": False})
+            if self.keep:
+                self.kept[(blk.beam, blk.seq)] = {
+                    "t0": int(r.t0), "out": r.out.clone(), "mean": r.mean.clone(), "rms": r.rms.clone(),
+                    "cand": r.candidates()}
+        return out
+
+
 def poisson_schedule(specs: Sequence[BeamSpec], n_blocks: int, seed: int = 5, jitter_mean_s: float = 0.1,
                      phases=None, make_data: Optional[Callable[[int, int], object]] = None,
                      time_scale: float = 1.0) -> List[Block]:
