@@ -47,6 +47,13 @@ def parse():
                          "(used only while the kernel source is the one it was measured on)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the input (known bytes) to calibrate HBM counters")
+    ap.add_argument("--mode", choices=("plain", "batch", "serve"), default="plain",
+                    help="plain: the full-size FP32 workload (default); batch: 16 uneven u8 beams in one "
+                         "persistent launch; serve: 64 streaming u8 beams with continuous batching")
+    ap.add_argument("--serve-blocks", type=int, default=4,
+                    help="1 s blocks per beam in the serving run (plain mode appends a serving summary "
+                         "when > 0)")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serving admission budget")
     return ap.parse_args()
 
 
@@ -62,6 +69,113 @@ def cpu_baseline(beam, rows):
     return {"value": len(sel) * nout / dt, "unit": "DM-trial*samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(sel)} of {beam.ndm} DM rows (evenly spaced) x {nout} output samples x "
                       f"{beam.nchan} channels, FP64 NumPy, single thread; {dt:.1f} s"}
+
+
+def serve_run(nblocks, budget_bytes, seed=5):
+    """Config-5 serving: 48 x 1024-ch and 16 x 4096-ch u8 beams, 1 s blocks, Poisson arrival
+    jitter, rings prefilled past their fill, then real-time arrivals for nblocks blocks."""
+    import torch
+
+    import fbsynth
+    from paper_1401_8258_amd import serve
+
+    specs5 = fbsynth.config5_specs(seed=seed)
+    specs = [serve.BeamSpec(sp["name"], fbsynth.channel_freqs(sp["f_top"], sp["bw"] / sp["nchan"], sp["nchan"]),
+                            sp["tsamp"], fbsynth.dm_trials(sp["dm0"], sp["step"], sp["ndm"]), "u8", sp["block"],
+                            k_sigma=6.0) for sp in specs5]
+    ex = serve.LibraryExecutor(k_sigma=6.0, cand_cap=1 << 14)
+    srv = serve.Server(specs, ex, hbm_budget=budget_bytes, max_inflight=2)
+    admitted = [i for i in range(len(specs)) if srv.request(i) == "admitted"]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    pool = {}
+    for sp in specs:
+        key = (len(sp.freq_mhz), sp.block)
+        if key not in pool:  # N(128, 16) codes, three distinct blocks per shape
+            pool[key] = [torch.clamp(torch.round(128.0 + 16.0 * torch.randn(key, generator=g, device="cuda")),
+                                     0, 255).to(torch.uint8) for _ in range(3)]
+    nfill = {}
+    for i in admitted:
+        sp = specs[i]
+        nf = ex.plan(sp).maxdelay // sp.block  # blocks after which the ring still holds <= maxdelay samples
+        key = (len(sp.freq_mhz), sp.block)
+        ex.prefill(i, [pool[key][k % 3] for k in range(nf)])
+        nfill[i] = nf
+    torch.cuda.synchronize()
+    sched = serve.poisson_schedule(specs, nblocks, seed=seed, jitter_mean_s=0.1,
+                                   phases=[sp["phase_s"] for sp in specs5],
+                                   make_data=lambda i, k: pool[(len(specs[i].freq_mhz), specs[i].block)][
+                                       (nfill.get(i, 0) + k) % 3])
+    sched = [b for b in sched if b.beam in srv.active]
+    st = srv.run(sched)
+    out = st.summary()
+    out.update({"beams": len(specs), "blocks_per_beam": nblocks,
+                "workload": "48 x 1024-ch (408-428 MHz, 51.2 us, 2048 DMs) + 16 x 4096-ch (120-180 MHz, "
+                            "81.92 us, 4096 DMs step 0.05) u8 beams, 1 s blocks, Poisson arrival jitter "
+                            "(mean 0.1 s), rings prefilled", "hbm_budget_gb": budget_bytes / 1e9})
+    return out
+
+
+def batch_run(reps):
+    """Config-4 batch: 16 uneven u8 beams (N(128,16) codes drawn on the device), tiles from
+    the autotuner, one persistent launch, against the beams one at a time."""
+    import torch
+
+    import fbsynth
+    import paper_1401_8258_amd as dd
+    from paper_1401_8258_amd import autotune
+
+    specs = fbsynth.config4_specs()
+    beams, xs = [], []
+    for i, sp in enumerate(specs):
+        freq = fbsynth.channel_freqs(sp["f_top"], sp["bw"] / sp["nchan"], sp["nchan"])
+        dms = fbsynth.dm_trials(sp["dm0"], sp["step"], sp["ndm"])
+        beams.append((freq, sp["tsamp"], dms, "u8", sp["nsamp"]))
+        xs.append(autotune.synthetic_input(sp["nchan"], sp["nsamp"], "u8", seed=i))
+    t_tune = time.perf_counter()
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    tb = autotune.tune_batch(beams, waves=(8, 4, 2, 1), stages=(0,), reps=1, inputs=xs, log=log)
+    t_tune = time.perf_counter() - t_tune
+    plans = [dd.Plan(f, ts, dm, dtype="u8", tuning=tuple(t)) for (f, ts, dm, _, _), t in zip(beams, tb["tunings"])]
+    outs = [dd.api.alloc_outputs(p.ndm, x.shape[1] - p.maxdelay, x.device, 6.0, 1 << 16) for p, x in zip(plans, xs)]
+    jobs = list(zip(plans, xs))
+
+    def batched():
+        dd.batch_dedisperse(jobs, k_sigma=6.0, cand_cap=1 << 16, outputs=outs)
+
+    def singles(ps):
+        for p, x, o in zip(ps, xs, outs):
+            dd.batch_dedisperse([(p, x)], k_sigma=6.0, cand_cap=1 << 16, outputs=[o])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_batch = timed(batched)
+    # each beam alone with its own best tiles (any wavefront count)
+    log("batch: per-beam best tiles")
+    best = [autotune.tune(*b, waves=(8, 4, 2, 1), stages=(0,), reps=1, x=x)["tuning"] for b, x in zip(beams, xs)]
+    own = [dd.Plan(f, ts, dm, dtype="u8", tuning=tuple(t)) for (f, ts, dm, _, _), t in zip(beams, best)]
+    ms_own = timed(lambda: singles(own))
+    ms_same = timed(lambda: singles(plans))
+    trials_samples = sum(p.ndm * (x.shape[1] - p.maxdelay) for p, x in zip(plans, xs))
+    adds = sum(p.ndm * p.nchan * (x.shape[1] - p.maxdelay) for p, x in zip(plans, xs))
+    return {"metric": "DM-trial*samples/s", "value": trials_samples / (ms_batch * 1e-3),
+            "unit": "DM-trial*samples/s", "n_gpus": 1, "steps": reps, "ms_per_step": round(ms_batch, 3),
+            "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "16 uneven u8 beams (nchan 256/512/1024/4096, 500-4096 DMs, nsamp 2^16-2^19) "
+                                   "in one persistent launch, stats + 6-sigma candidates",
+                       "common_waves": tb["waves"], "tunings": tb["tunings"], "tune_s": round(t_tune, 1)},
+            "adds_per_s": adds / (ms_batch * 1e-3),
+            "one_at_a_time_same_tiles_ms": round(ms_same, 3),
+            "one_at_a_time_own_best_tiles_ms": round(ms_own, 3), "own_best_tilings": best}
 
 
 def main():
@@ -80,6 +194,15 @@ def main():
     from paper_1401_8258_amd import _lib
 
     dd.load_library()
+    if args.mode == "batch":
+        print(json.dumps(batch_run(args.steps)), flush=True)
+        return
+    if args.mode == "serve":
+        res = serve_run(max(args.serve_blocks, 1), int(args.hbm_budget_gb * 1e9))
+        print(json.dumps({"metric": "blocks/s", "value": res["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "u8", "data": "synthetic", "serving": res}),
+              flush=True)
+        return
     print("bench: generating workload", file=sys.stderr, flush=True)
     beam = fbsynth.config2()
     tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
@@ -177,6 +300,11 @@ def main():
         res["copy_probe_bytes"] = int(x.numel() * x.element_size())
         del y
     del x
+    del out
+    if args.serve_blocks > 0:
+        print("bench: serving run", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        res["serving"] = serve_run(args.serve_blocks, int(args.hbm_budget_gb * 1e9))
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(beam, args.cpu_rows)

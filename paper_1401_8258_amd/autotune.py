@@ -110,7 +110,8 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
 
 
 def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequence[int] = STAGES, reps: int = 2,
-               cache: Optional[TuneCache] = None, inputs: Optional[List[torch.Tensor]] = None) -> dict:
+               cache: Optional[TuneCache] = None, inputs: Optional[List[torch.Tensor]] = None,
+               log=None) -> dict:
     """One wavefront count for a batch; per beam the best stage size under it.
 
     beams: (freq, tsamp, dm, dtype, nsamp) per beam. Returns {"waves": w, "tunings": [...],
@@ -127,6 +128,8 @@ def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequenc
                 per_w[w] = None
                 break
             per_w[w].append(r)
+            if log is not None:
+                log(f"tune: waves {w} beam {i}: {r['tuning']} {r['ms']:.2f} ms")
     totals = {w: sum(r["ms"] for r in rs) for w, rs in per_w.items() if rs is not None}
     if not totals:
         raise RuntimeError("no common wavefront count fits every beam")

@@ -28,7 +28,8 @@ constexpr int kMaxX4 = 16;
 
 // Launch geometry of the dedispersion kernel.
 struct Launch {
-  int L;        // words per (channel, copy) buffer (four copies shifted by 0..3 samples)
+  int L;        // samples per (channel, copy) buffer (four copies shifted by 0..3 samples);
+                // 32-bit words for 16/32-bit input, bytes for 8-bit input
   int cs;       // channels per stage (a divisor of the wavefront count)
   int nb;       // stages in the LDS ring
   int nd;       // DMA instructions per wavefront per stage
@@ -91,6 +92,8 @@ struct WsLayout {
   int64_t thr_off;     // double [ndm][3]: mean, rms, threshold
   int64_t cnt_off;     // int32 [ndm][nseg]
   int64_t offs_off;    // int64 [ndm][nseg]
+  int64_t tail_off;    // 8-bit input: copy of the last tail_bytes of the input, then as many
+  int64_t tail_bytes;  // bytes of padding (a window starting in the copy reads at most that far)
   int64_t nseg;        // candidate segments
   int64_t ntile;       // statistics segments
   int64_t total;

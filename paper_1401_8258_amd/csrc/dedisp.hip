@@ -86,6 +86,11 @@ struct KParams {
   int nd;       // DMA instructions per wavefront per stage
   int nstages;  // ceil(nchan / cs)
   int x4;       // FP32 input: copies arrive by 16-byte DMAs (nd counts those)
+  // 8-bit linear input: a channel window that would read past the end of the input
+  // (byte in_bytes of the whole [nchan][row_stride] array) reads from `tail`, a copy of
+  // input bytes [tail_base, in_bytes) followed by in_bytes - tail_base bytes of padding
+  const uint8_t* tail;
+  int64_t tail_base, in_bytes;
 };
 
 typedef const __attribute__((address_space(4))) int32_t* ci32_t;
@@ -269,6 +274,49 @@ __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, un
   }
 }
 
+// Epilogue: the tile's sums to the output rows (float4 stores when aligned) and the
+// tile's FP64 statistics partials (fixed wavefront reduction tree).
+__device__ __forceinline__ void store_tile(const KParams& P, const float (&acc)[kG][8], int dw, int64_t t0,
+                                           int64_t tile, int lane) {
+  const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
+  const int64_t nseg = (P.nout + kTile - 1) / kTile;
+#pragma unroll
+  for (int g = 0; g < kG; ++g) {
+    const int d = dw + g;
+    if (d >= P.ndm) break;
+    float* orow = P.out + (int64_t)d * P.out_stride;
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t tb = t0 + 256 * h + 4 * lane;
+      if (vec_ok && tb + 3 < P.nout) {
+        *reinterpret_cast<float4*>(orow + tb) =
+            make_float4(acc[g][4 * h], acc[g][4 * h + 1], acc[g][4 * h + 2], acc[g][4 * h + 3]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (tb + q < P.nout) orow[tb + q] = acc[g][4 * h + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (tb + q < P.nout) {
+          const double x = acc[g][4 * h + q];
+          s1 += x;
+          s2 += x * x;
+        }
+      }
+    }
+    if (P.part) {
+      s1 = wave_sum_fixed(s1);
+      s2 = wave_sum_fixed(s2);
+      if (lane == 0) {
+        P.part[((int64_t)d * nseg + tile) * 2] = s1;
+        P.part[((int64_t)d * nseg + tile) * 2 + 1] = s2;
+      }
+    }
+  }
+}
+
 // One (time tile, DM group) work unit; every wavefront of the workgroup takes part.
 // 8-bit input sums exactly in 32-bit integers; 16- and 32-bit input sum in FP32 with a
 // sub-sum folded into the accumulator every DD_CHAN_BLOCK channels (fixed order in c).
@@ -365,51 +413,200 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc[g][s] = U8 ? (float)iacc[g][s] : acc[g][s] + sub[g][s];
 
-  const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
-  const int64_t nseg = (P.nout + kTile - 1) / kTile;
+  store_tile(P, acc, dw, t0, tile, lane);
+}
+
+// ------------------------------------------------------------------ 8-bit input
+//
+// Samples stay bytes in LDS: each channel slot holds four copies of L bytes, copy m
+// byte x = window sample first + m + x, filled by 1024-byte (16 bytes per lane) and
+// 256-byte DMAs straight from the byte stream (sources need no alignment), then 256
+// bytes of trial offsets. A trial reads one dword per half: lane l takes samples
+// 4l .. 4l + 3 (and 256 + 4l ..) from copy k & 3 at a dword-aligned address, lanes on
+// consecutive dwords. v_perm splits the dword into the 16-bit pairs (s0, s2) and
+// (s1, s3), which add with plain 32-bit adds; every 256 channels (255 x 256 < 2^16) the
+// pairs fold into 32-bit accumulators, so the sums are exact integers.
+
+// Chunk descriptors of one wavefront for its stage channel (lane j: chunk j): rel =
+// source byte offset from `first` (-1 for the offsets), lds = byte offset inside the
+// slot, with bit 30 set for a 1024-byte chunk.
+struct DescU8 {
+  int rel[2], lds[2];
+};
+__device__ __forceinline__ DescU8 make_desc_u8(const KParams& P, int sub, int wpc, int lane) {
+  const int n4 = P.L >> 10, n1 = (P.L & 1023) >> 8;
+  const int per = n4 + n1;  // chunks per copy
+  const int nchunk = 4 * per + 1;
+  DescU8 d;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = min(sub + wpc * (lane + 64 * h), nchunk - 1);
+    const int m = r / per;
+    const int i = r - m * per;
+    if (m >= 4) {
+      d.rel[h] = -1;
+      d.lds[h] = 4 * P.L;
+    } else if (i < n4) {
+      d.rel[h] = m + 1024 * i;
+      d.lds[h] = (m * P.L + 1024 * i) | (1 << 30);
+    } else {
+      const int b = 1024 * n4 + 256 * (i - n4);
+      d.rel[h] = m + b;
+      d.lds[h] = m * P.L + b;
+    }
+  }
+  return d;
+}
+
+template <bool RING>
+__device__ __forceinline__ void stage_dma_u8(const KParams& P, const DescU8& D, unsigned sbase, int sd, int cc_w,
+                                             int64_t t0, int grp, int dg, int gw, int lane, int w0) {
+  int c = sd * P.cs + cc_w;
+  if (c >= P.nchan) c = P.nchan - 1;  // keeps the per-wavefront DMA count uniform
+  const ci32_t gb = (ci32_t)(P.gbase + (int64_t)grp * P.nchan);
+  const int first = (int)t0 + gb[c];
+  const char* rp;
+  int pos0;
+  if constexpr (RING) {
+    pos0 = first + w0;
+    if (pos0 >= (int)P.in.ring_len) pos0 -= (int)P.in.ring_len;
+    rp = static_cast<const char*>(P.in.ptr) + (int64_t)c * P.in.row_stride;
+  } else {
+    // the DMAs read bytes first .. first + L + 2 of the row (+ up to 15 inside a chunk)
+    const int64_t g0 = (int64_t)c * P.in.row_stride + first;
+    if (g0 + P.L + 18 > P.in_bytes) {
+      rp = reinterpret_cast<const char*>(P.tail);
+      pos0 = (int)(g0 - P.tail_base);
+    } else {
+      rp = static_cast<const char*>(P.in.ptr) + (int64_t)c * P.in.row_stride;
+      pos0 = first;
+    }
+  }
+  const int32_t* orow = P.dtab + (int64_t)c * P.ndm_pad + dg;
+  const unsigned slot = sbase + (unsigned)((sd % P.nb) * P.cs + cc_w) * (unsigned)(4 * P.L + 256);
+  for (int j = 0; j < P.nd; ++j) {
+    const int h = j >> 6;
+    const int rel = __builtin_amdgcn_readlane(h ? D.rel[1] : D.rel[0], j & 63);
+    const int ld = __builtin_amdgcn_readlane(h ? D.lds[1] : D.lds[0], j & 63);
+    const unsigned m0 = slot + (unsigned)(ld & ~(1 << 30));
+    if (rel < 0)
+      dma<4>(orow, 4u * (unsigned)min(lane, gw - 1), m0);
+    else if (ld & (1 << 30))
+      dma_x4(rp, (unsigned)(pos0 + rel + 16 * lane), m0);
+    else
+      dma<4>(rp, (unsigned)(pos0 + rel + 4 * lane), m0);
+  }
+}
+
+template <bool RING>
+__device__ __forceinline__ void tile_body_u8(const KParams& P, int64_t tile, int grp, float* smem) {
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gw = kG * nw;
+  const int64_t t0 = tile * kTile;
+  const int dg = grp * gw;
+  const int dw = dg + w * kG;
+  const int w0 = P.in.ring_len > 0 ? (int)(P.in.win0 % P.in.ring_len) : 0;
+  const int wpc = nw / P.cs;
+  const int cc_w = w / wpc;
+  const DescU8 D = make_desc_u8(P, w - cc_w * wpc, wpc, lane);
+  const unsigned sbase = lds_addr(smem);
+  const int slot_b = 4 * P.L + 256;  // bytes per channel slot
+
+  uint32_t pr[kG][4];   // [g][2h + {0: (s0, s2), 1: (s1, s3)}] 16-bit pair sums
+  uint32_t acc[kG][8];  // [g][4h + j]
 #pragma unroll
   for (int g = 0; g < kG; ++g) {
-    const int d = dw + g;
-    if (d >= P.ndm) break;
-    float* orow = P.out + (int64_t)d * P.out_stride;
-    double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t tb = t0 + 256 * h + 4 * lane;
-      if (vec_ok && tb + 3 < P.nout) {
-        *reinterpret_cast<float4*>(orow + tb) =
-            make_float4(acc[g][4 * h], acc[g][4 * h + 1], acc[g][4 * h + 2], acc[g][4 * h + 3]);
-      } else {
+    for (int q = 0; q < 4; ++q) pr[g][q] = 0u;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (tb + q < P.nout) orow[tb + q] = acc[g][4 * h + q];
+    for (int s = 0; s < 8; ++s) acc[g][s] = 0u;
+  }
+  auto fold = [&]() {
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t a = pr[g][2 * h], b = pr[g][2 * h + 1];
+        acc[g][4 * h] += a & 0xffffu;
+        acc[g][4 * h + 2] += a >> 16;
+        acc[g][4 * h + 1] += b & 0xffffu;
+        acc[g][4 * h + 3] += b >> 16;
+        pr[g][2 * h] = 0u;
+        pr[g][2 * h + 1] = 0u;
+      }
+    }
+  };
+
+  const int pre = min(P.nb - 1, P.nstages);
+  for (int sd = 0; sd < pre; ++sd) stage_dma_u8<RING>(P, D, sbase, sd, cc_w, t0, grp, dg, gw, lane, w0);
+  const char* lds_c = reinterpret_cast<const char*>(smem);
+  const unsigned lane4 = 4u * (unsigned)lane;
+  const int offb = 4 * P.L + 4 * kG * w;  // this wavefront's 8 offsets inside a slot (bytes)
+
+  for (int st = 0; st < P.nstages; ++st) {
+    const int later = min(P.nstages - 1, st + P.nb - 2) - st;
+    wait_vm(later * P.nd);
+    block_barrier();
+    if (st + P.nb - 1 < P.nstages)
+      stage_dma_u8<RING>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0);
+    const int buf = st % P.nb;
+    const int n_here = min(P.cs, P.nchan - st * P.cs);
+    const char* sl = lds_c + buf * P.cs * slot_b;
+    const int4* op = reinterpret_cast<const int4*>(sl + offb);
+    int4 o0 = op[0], o1 = op[1];
+    for (int cc = 0; cc < n_here; ++cc) {
+      const int c = st * P.cs + cc;
+      if ((c & 255) == 0 && c != 0) fold();
+      const int off[kG] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
+      const char* cb = sl + cc * slot_b + lane4;
+      uint32_t v[2 * kG];
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const uint32_t* a = reinterpret_cast<const uint32_t*>(cb + off[g]);
+        v[2 * g] = a[0];
+        v[2 * g + 1] = a[64];
+      }
+      if (cc + 1 < n_here) {
+        const int4* np = reinterpret_cast<const int4*>(sl + (cc + 1) * slot_b + offb);
+        o0 = np[0];
+        o1 = np[1];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (tb + q < P.nout) {
-          const double x = acc[g][4 * h + q];
-          s1 += x;
-          s2 += x * x;
+      for (int g = 0; g < kG; ++g) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t d = v[2 * g + h];
+          pr[g][2 * h] += __builtin_amdgcn_perm(d, d, 0x0c020c00u);      // (s0, s2)
+          pr[g][2 * h + 1] += __builtin_amdgcn_perm(d, d, 0x0c030c01u);  // (s1, s3)
         }
       }
     }
-    if (P.part) {
-      s1 = wave_sum_fixed(s1);
-      s2 = wave_sum_fixed(s2);
-      if (lane == 0) {
-        P.part[((int64_t)d * nseg + tile) * 2] = s1;
-        P.part[((int64_t)d * nseg + tile) * 2 + 1] = s2;
-      }
-    }
   }
+  fold();
+
+  float facc[kG][8];
+#pragma unroll
+  for (int g = 0; g < kG; ++g)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) facc[g][s] = (float)acc[g][s];
+  store_tile(P, facc, dw, t0, tile, lane);
 }
 
 template <typename TIn>
 __device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int grp, float* smem) {
-  if (P.in.ring_len > 0)
-    tile_body_impl<TIn, true>(P, tile, grp, smem);
-  else
-    tile_body_impl<TIn, false>(P, tile, grp, smem);
+  if constexpr (std::is_same<TIn, uint8_t>::value) {
+    if (P.in.ring_len > 0)
+      tile_body_u8<true>(P, tile, grp, smem);
+    else
+      tile_body_u8<false>(P, tile, grp, smem);
+  } else {
+    if (P.in.ring_len > 0)
+      tile_body_impl<TIn, true>(P, tile, grp, smem);
+    else
+      tile_body_impl<TIn, false>(P, tile, grp, smem);
+  }
 }
 
 // Plain launch: one work unit per workgroup; each XCD (workgroups lin, lin + 8, ...)
@@ -681,8 +878,24 @@ int build_params(const dd_plan* p, const InView& in, const int32_t* d_table, int
   P->nd = g.nd;
   P->nstages = (p->nchan + g.cs - 1) / g.cs;
   P->x4 = g.x4;
+  if (p->dtype == DD_U8 && in.ring_len == 0) {
+    P->in_bytes = (int64_t)(p->nchan - 1) * in.row_stride + in.nvalid;
+    P->tail_base = std::max<int64_t>(0, P->in_bytes - l.tail_bytes);
+    P->tail = reinterpret_cast<const uint8_t*>(ws + l.tail_off);
+  }
   P->gbase = d_table + (int64_t)p->nchan * p->ndm_pad;
   *G = g;
+  return DD_OK;
+}
+
+// 8-bit linear input: the last input bytes go to the workspace copy that windows reaching
+// past the end of the input read instead (enqueued before the dedispersion launch).
+int copy_tail(const KParams& P, hipStream_t st) {
+  if (!P.tail) return DD_OK;
+  const char* src = static_cast<const char*>(P.in.ptr) + P.tail_base;
+  hipError_t e = hipMemcpyAsync(const_cast<uint8_t*>(P.tail), src, (size_t)(P.in_bytes - P.tail_base),
+                                hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (input tail)");
   return DD_OK;
 }
 
@@ -726,6 +939,8 @@ int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int
   if (rc) return rc;
   KernFn k = pick_kernel(p->dtype);
   rc = set_lds((const void*)k, g.lds);
+  if (rc) return rc;
+  rc = copy_tail(P, st);
   if (rc) return rc;
   const int64_t nblocks = (P.nitems + 7) / 8 * 8;
   if (nblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many work items");
@@ -943,6 +1158,8 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     nouts[i] = nout;
     dd::Launch g;
     rc = build_params(p, in, table, nout, outs[i], ws, lays[i], &P[i], &g);
+    if (rc) return rc;
+    rc = copy_tail(P[i], st);
     if (rc) return rc;
     lds = std::max(lds, g.lds);
     start[i + 1] = start[i] + P[i].nitems;

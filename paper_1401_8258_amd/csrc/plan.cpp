@@ -68,13 +68,50 @@ WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
   o = align_up(o + (int64_t)p->ndm * l.nseg * 4);
   l.offs_off = o;
   o = align_up(o + (int64_t)p->ndm * l.nseg * 8 + 8);
+  l.tail_off = o;
+  l.tail_bytes = p->dtype == DD_U8 ? (int64_t)p->launch.L + 64 : 0;
+  o = align_up(o + 2 * l.tail_bytes);
   l.total = o;
   return l;
 }
 
 int64_t ring_table_bytes(const dd_plan* p) { return align_up((int64_t)p->dev_table.size() * 4); }
 
+// 8-bit input keeps its samples as bytes in LDS: four byte-shifted copies of L bytes
+// (L a multiple of 256), filled by 1024-byte and 256-byte DMAs, plus 256 bytes of offsets.
+Launch choose_launch_u8(int32_t max_span, int nw, int cs_req, int64_t lds_cap) {
+  Launch best{};
+  const int64_t L = (kTile + (int64_t)max_span + 255) / 256 * 256;
+  const int64_t per_chan = 4 * L + 256;
+  const int64_t nchunk = 4 * (L / 1024 + (L % 1024) / 256) + 1;
+  const int cs_hi = cs_req > 0 ? std::min(cs_req, nw) : nw;
+  int64_t best_score = -1;
+  for (int cs = cs_hi; cs >= 1; --cs) {
+    if (nw % cs) continue;
+    const int wpc = nw / cs;
+    const int64_t nd = (nchunk + wpc - 1) / wpc;
+    if (nd > kMaxDma) continue;
+    int nb = (int)std::min<int64_t>(lds_cap / (cs * per_chan), 16);
+    while (nb > 2 && (int64_t)(nb - 2) * nd > 63) --nb;
+    if (nb < 2) continue;
+    if (cs_req > 0 && best_score >= 0) break;
+    const int64_t score = (int64_t)std::min(nb * cs, 24) * 64 + cs;  // deep enough, then fewest barriers
+    if (score > best_score) {
+      best_score = score;
+      best.L = (int)L;
+      best.cs = cs;
+      best.nb = nb;
+      best.nd = (int)nd;
+      best.x4 = 1;
+    }
+  }
+  if (best_score < 0) return Launch{};
+  best.lds = (int64_t)best.nb * best.cs * per_chan;
+  return best;
+}
+
 Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap, int elem_bytes) {
+  if (elem_bytes == 1) return choose_launch_u8(max_span, nw, cs_req, lds_cap);
   Launch best{};
   (void)nchan;
   // words one channel copy covers: tile + group spread (lane reads end at k - m + 511)
@@ -226,7 +263,8 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
         const int32_t d = gi * p->dms_per_group + j;
         const int32_t k = row[d < ndm ? d : ndm - 1] - base;
         const int32_t m = k & 3;
-        drow[d] = 4 * (m * lg.L + (k - m));
+        // byte offset: 32-bit words for 16/32-bit input, bytes for 8-bit input
+        drow[d] = in_dtype == DD_U8 ? m * lg.L + (k - m) : 4 * (m * lg.L + (k - m));
       }
     }
   }
