@@ -623,11 +623,12 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
   tile_body<TIn>(P, tile, grp, smem);
 }
 
-// Batched persistent launch over several plans/inputs. Item i owns work units
-// [start[i], start[i+1]) of the concatenated list (tile-major, group fastest, as in the
-// plain launch). The grid is a multiple of 8 workgroups; XCD x walks the contiguous
-// range [x*per, (x+1)*per) with its workgroups striding through it, so the result of
-// every unit is the one the plain launch computes for it.
+// Batched persistent launch over several plans/inputs. XCD x (workgroups x, x + 8, ...)
+// takes time tiles x, x + 8, x + 16, ... of every item, each with all its DM groups, so
+// every XCD gets an even share of every item, however uneven the items are, and the
+// groups of a tile still share that XCD's L2. start[x * (n + 1) + i] is the first of
+// XCD x's units that belongs to item i (units of an item: tile-major, group fastest).
+// The result of every unit is the one the plain launch computes for it.
 typedef const __attribute__((address_space(4))) uint32_t* cu32_t;
 typedef const __attribute__((address_space(4))) int64_t* ci64_t;
 static_assert(sizeof(KParams) % 4 == 0, "KParams is copied as dwords");
@@ -646,22 +647,19 @@ __device__ __forceinline__ KParams load_params(const KParams* items, int i) {
 template <typename TIn>
 __global__ __launch_bounds__(kMaxThreads) void dedisp_batch(const KParams* items, const int64_t* start, int nitems) {
   extern __shared__ __align__(16) float smem[];
-  ci64_t st_c = (ci64_t)start;
+  const int x = blockIdx.x & 7;
+  ci64_t st_c = (ci64_t)(start + (int64_t)x * (nitems + 1));
   const int64_t total = st_c[nitems];
   const int64_t nslot = gridDim.x >> 3;
-  const int64_t slot = blockIdx.x >> 3;
-  const int64_t per = (total + 7) / 8;
-  const int64_t q_lo = (int64_t)(blockIdx.x & 7) * per;
-  const int64_t q_hi = min(total, q_lo + per);
   int it = 0;
-  for (int64_t q = q_lo + slot; q < q_hi; q += nslot) {
+  for (int64_t q = blockIdx.x >> 3; q < total; q += nslot) {
     while (it + 1 < nitems && st_c[it + 1] <= q) ++it;
     const KParams P = load_params(items, it);
     const int64_t local = q - st_c[it];
-    const int64_t tile = local / P.ngroups;
-    const int grp = (int)(local - tile * P.ngroups);
+    const int64_t tl = local / P.ngroups;
+    const int grp = (int)(local - tl * P.ngroups);
     block_barrier();  // the previous unit's LDS reads are done before new DMAs land
-    tile_body<TIn>(P, tile, grp, smem);
+    tile_body<TIn>(P, x + 8 * tl, grp, smem);
   }
 }
 
@@ -1100,7 +1098,7 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
 int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes) {
   dd::clear_error();
   if (!ws_bytes || n < 1 || !items) return dd::fail(DD_ERR_INVALID_ARG, "need items, n >= 1 and ws_bytes");
-  *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)(n + 1) * 8);
+  *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * (n + 1) * 8);
   return DD_OK;
 }
 
@@ -1112,7 +1110,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   if (!d_workspace || ws_bytes < need) return dd::fail(DD_ERR_WORKSPACE, "batch workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<KParams> P((size_t)n);
-  std::vector<int64_t> start((size_t)n + 1, 0);
+  std::vector<int64_t> start((size_t)8 * (n + 1), 0);  // [xcd][item]
   std::vector<Outputs> outs((size_t)n);
   std::vector<int64_t> nouts((size_t)n);
   std::vector<dd::WsLayout> lays((size_t)n);
@@ -1162,7 +1160,16 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     rc = copy_tail(P[i], st);
     if (rc) return rc;
     lds = std::max(lds, g.lds);
-    start[i + 1] = start[i] + P[i].nitems;
+  }
+  int64_t units = 0;
+  for (int x = 0; x < 8; ++x) {
+    int64_t* sx = &start[(size_t)x * (n + 1)];
+    for (int32_t i = 0; i < n; ++i) {
+      const int64_t ntiles = P[i].nitems / P[i].ngroups;
+      const int64_t mine = ntiles > x ? (ntiles - x + 7) / 8 : 0;  // tiles x, x + 8, ...
+      sx[i + 1] = sx[i] + mine * P[i].ngroups;
+    }
+    units = std::max(units, sx[n]);
   }
   char* bw = static_cast<char*>(d_workspace);
   KParams* dP = reinterpret_cast<KParams*>(bw);
@@ -1176,9 +1183,9 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   if (rc) return rc;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t units = start[n];
-  // one resident workgroup per CU (the LDS ring fills a CU), rounded to whole XCD groups
-  const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, (units + 7) / 8 * 8) / 8 * 8);
+  // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
+  // `units` is the largest per-XCD share
+  const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, units * 8) / 8 * 8);
   hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * waves), (size_t)lds, st, (const KParams*)dP,
                      (const int64_t*)dS, (int)n);
   e = hipGetLastError();
