@@ -19,9 +19,9 @@ constexpr int64_t kTile = 512;
 constexpr int64_t kStatSeg = 8192;
 // LDS of one gfx950 workgroup.
 constexpr int64_t kLdsBytes = 160 * 1024;
-// Most DMA instructions one wavefront issues per stage (its descriptor table spans two
+// Most DMA instructions one wavefront issues per stage (its descriptor table spans four
 // 64-lane registers).
-constexpr int kMaxDma = 128;
+constexpr int kMaxDma = 256;
 // Most 16-byte DMAs one wavefront issues per stage for FP32 input (one descriptor
 // register each); beyond that the 4-byte form is used.
 constexpr int kMaxX4 = 16;

@@ -66,7 +66,7 @@ struct InView {
 constexpr int kTile = 512;
 constexpr int kG = 8;
 constexpr int kCopies = 4;
-constexpr int kMaxDma = 128;  // DMA instructions per wavefront per stage (two descriptor registers)
+constexpr int kMaxDma = 256;  // DMA instructions per wavefront per stage (four descriptor registers)
 constexpr int kMaxX4 = 16;    // 16-byte DMAs per wavefront per stage (one descriptor register each)
 static_assert(kTile == dd::kTile, "tile constant disagrees with the host plan");
 static_assert(kMaxDma == dd::kMaxDma, "DMA limit disagrees with the host plan");
@@ -172,7 +172,7 @@ __device__ __forceinline__ int slot_rel(int y, int L) {
 //    256r + 4l .. + 3, which never straddle two copies since L is a multiple of 64);
 //    relx[j] is this lane's source offset for chunk j. The offsets come as one more x1 DMA.
 struct DmaDesc {
-  int rel[2], ldw[2];
+  int rel[4], ldw[4];
   int relx[kMaxX4];
 };
 __device__ __forceinline__ void make_desc(const KParams& P, int sub, int wpc, int lane, DmaDesc* d) {
@@ -188,7 +188,7 @@ __device__ __forceinline__ void make_desc(const KParams& P, int sub, int wpc, in
   }
   const int nchunk = kCopies * nch + 1;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < 4; ++h) {
     const int r = min(sub + wpc * (lane + 64 * h), nchunk - 1);
     d->rel[h] = r < kCopies * nch ? slot_rel(64 * r, P.L) : -1;
     d->ldw[h] = 64 * r;
@@ -261,16 +261,14 @@ __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, un
       return;
     }
   }
-  const int n0 = min(P.nd, 64);
-  for (int j = 0; j < n0; ++j) {
-    const int rel = __builtin_amdgcn_readlane(D.rel[0], j);
-    const int ldw = __builtin_amdgcn_readlane(D.ldw[0], j);
-    dma_chunk<EB, RING>(rp, orow, rel, ldw, slot, start, nlim, lane, gw);
-  }
-  for (int j = 64; j < P.nd; ++j) {
-    const int rel = __builtin_amdgcn_readlane(D.rel[1], j - 64);
-    const int ldw = __builtin_amdgcn_readlane(D.ldw[1], j - 64);
-    dma_chunk<EB, RING>(rp, orow, rel, ldw, slot, start, nlim, lane, gw);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int n = min(P.nd - 64 * h, 64);
+    for (int j = 0; j < n; ++j) {
+      const int rel = __builtin_amdgcn_readlane(D.rel[h], j);
+      const int ldw = __builtin_amdgcn_readlane(D.ldw[h], j);
+      dma_chunk<EB, RING>(rp, orow, rel, ldw, slot, start, nlim, lane, gw);
+    }
   }
 }
 
@@ -431,7 +429,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
 // source byte offset from `first` (-1 for the offsets), lds = byte offset inside the
 // slot, with bit 30 set for a 1024-byte chunk.
 struct DescU8 {
-  int rel[2], lds[2];
+  int rel[4], lds[4];
 };
 __device__ __forceinline__ DescU8 make_desc_u8(const KParams& P, int sub, int wpc, int lane) {
   const int n4 = P.L >> 10, n1 = (P.L & 1023) >> 8;
@@ -439,7 +437,7 @@ __device__ __forceinline__ DescU8 make_desc_u8(const KParams& P, int sub, int wp
   const int nchunk = 4 * per + 1;
   DescU8 d;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < 4; ++h) {
     const int r = min(sub + wpc * (lane + 64 * h), nchunk - 1);
     const int m = r / per;
     const int i = r - m * per;
@@ -484,17 +482,20 @@ __device__ __forceinline__ void stage_dma_u8(const KParams& P, const DescU8& D, 
   }
   const int32_t* orow = P.dtab + (int64_t)c * P.ndm_pad + dg;
   const unsigned slot = sbase + (unsigned)((sd % P.nb) * P.cs + cc_w) * (unsigned)(4 * P.L + 256);
-  for (int j = 0; j < P.nd; ++j) {
-    const int h = j >> 6;
-    const int rel = __builtin_amdgcn_readlane(h ? D.rel[1] : D.rel[0], j & 63);
-    const int ld = __builtin_amdgcn_readlane(h ? D.lds[1] : D.lds[0], j & 63);
-    const unsigned m0 = slot + (unsigned)(ld & ~(1 << 30));
-    if (rel < 0)
-      dma<4>(orow, 4u * (unsigned)min(lane, gw - 1), m0);
-    else if (ld & (1 << 30))
-      dma_x4(rp, (unsigned)(pos0 + rel + 16 * lane), m0);
-    else
-      dma<4>(rp, (unsigned)(pos0 + rel + 4 * lane), m0);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int n = min(P.nd - 64 * h, 64);
+    for (int j = 0; j < n; ++j) {
+      const int rel = __builtin_amdgcn_readlane(D.rel[h], j);
+      const int ld = __builtin_amdgcn_readlane(D.lds[h], j);
+      const unsigned m0 = slot + (unsigned)(ld & ~(1 << 30));
+      if (rel < 0)
+        dma<4>(orow, 4u * (unsigned)min(lane, gw - 1), m0);
+      else if (ld & (1 << 30))
+        dma_x4(rp, (unsigned)(pos0 + rel + 16 * lane), m0);
+      else
+        dma<4>(rp, (unsigned)(pos0 + rel + 4 * lane), m0);
+    }
   }
 }
 
