@@ -19,7 +19,8 @@
  * Summation order (fixed, independent of tiling and of batching): channels are
  * summed in FP32 in order inside consecutive blocks of DD_CHAN_BLOCK channels
  * (c = 0..31, 32..63, ...); the block sums are added to the running series in
- * block order. u8 inputs are summed as raw codes (exact in FP32 up to 2^24).
+ * block order. u8 inputs are summed as raw codes in 32-bit integers (exact; the
+output is that integer as FP32, exact below 2^24).
  *
  * Layouts: the filterbank is channel-major, time fastest ([nchan][row_stride],
  * Ch. 3 Sec. "Dedispersion" stores data after the transpose); the output is
@@ -69,10 +70,11 @@ typedef struct dd_stream dd_stream;
 
 /* Optional tile choice; zero fields take the library default. */
 typedef struct dd_tuning {
-  int32_t dms_per_wave;       /* DM trials each wavefront accumulates (4 or 8) */
+  int32_t dms_per_wave;       /* DM trials each wavefront accumulates: 8 */
   int32_t waves;              /* wavefronts per workgroup, each on its own DMs (1, 2, 4 or 8) */
   int32_t samples_per_lane;   /* output samples per lane: 8 (the tile is 512 samples) */
-  int32_t chan_stage;         /* channels staged into LDS per barrier pair (1..32) */
+  int32_t chan_stage;         /* channels per LDS stage (0..8; rounded down to a divisor of
+                                 waves; 0 = automatic) */
 } dd_tuning;
 
 typedef struct dd_plan_info {
@@ -84,8 +86,9 @@ typedef struct dd_plan_info {
   int64_t adds;                     /* ndm * nchan * nout: the algorithmic work */
   int32_t chan_stage, reserved;     /* channels per LDS stage requested (0 = automatic) */
   /* launch geometry (fixed at plan creation for 160 KB of LDS per workgroup): shifted
-     copies of each channel vector, words per copy, channels per stage, stages in the
-     LDS ring, LDS bytes per workgroup */
+     copies of each channel vector, samples per copy (32-bit words for 16/32-bit input,
+     bytes for 8-bit input), channels per stage, stages in the LDS ring, LDS bytes per
+     workgroup */
   int32_t launch_copies, launch_buf, launch_stage, launch_ring;
   int64_t launch_lds;
 } dd_plan_info;
@@ -152,9 +155,10 @@ int dd_dedisperse(const dd_plan* plan, const void* d_in, int64_t nsamp, int64_t 
 /*
  * Streaming (Ch. 3 Sec. "Dedispersion": the last maxshift spectra of a buffer are
  * carried into the next). A stream keeps a per-channel device ring of the last
- * maxdelay + block_nsamp samples in the caller's d_ring (ring_bytes >=
- * dd_plan_query(plan, block_nsamp).ring_bytes). The ring also holds the delay
- * table, uploaded at creation on the given stream.
+ * maxdelay + block_nsamp samples (rounded up to 64), each row followed by a mirror of
+ * its first launch_buf + 64 samples so that no channel window wraps, in the caller's
+ * d_ring (ring_bytes >= dd_plan_query(plan, block_nsamp).ring_bytes). The ring also
+ * holds the delay table, uploaded at creation on the given stream.
  */
 int dd_stream_create(const dd_plan* plan, int64_t block_nsamp, void* d_ring, int64_t ring_bytes,
                      void* stream, dd_stream** out);

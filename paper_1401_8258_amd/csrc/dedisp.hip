@@ -3,17 +3,19 @@
 // Kernels (all wave64):
 //   dedisp_tile    Eq. bruteEquation over one (DM group, time tile) per workgroup.
 //                  The channel vectors a group needs (Eq. channelDispersionEquation:
-//                  tile length plus the in-group delay spread) are staged HBM -> LDS
-//                  a few channels per barrier pair and shared by every wavefront of
-//                  the workgroup; each wavefront accumulates its own DM trials in
-//                  VGPRs. Delays are wave-uniform and come in through scalar loads.
-//                  The epilogue writes the tile and its FP64 statistics partials.
+//                  tile length plus the in-group delay spread) reach LDS by DMA through
+//                  a ring of stages and are shared by every wavefront of the workgroup;
+//                  each wavefront accumulates its own DM trials in VGPRs. Per-trial
+//                  delays arrive as precomputed LDS offsets with the data. 16/32-bit
+//                  input is staged as 32-bit words, 8-bit input as bytes (own tile
+//                  body). The epilogue writes the tile and its FP64 statistics partials.
+//   dedisp_batch   the same tile bodies in one persistent launch over many inputs.
 //   stats_finalize per-series mean and standard deviation from the FP64 partial sums
 //                  (sum x, sum x^2) that dedisp_tile writes per 512-sample tile with a
 //                  fixed wavefront reduction tree; tiles are summed in order.
 //   cand_*         n-sigma detections: per-segment counts, one exclusive scan, and an
 //                  ordered ballot compaction, so candidates come out in (d, t) order.
-//   ring_append    copies a block into a stream's per-channel ring (wrap-aware).
+//   ring_append    copies a block into a stream's per-channel ring and its mirror.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
@@ -315,14 +317,14 @@ __device__ __forceinline__ void store_tile(const KParams& P, const float (&acc)[
   }
 }
 
-// One (time tile, DM group) work unit; every wavefront of the workgroup takes part.
-// 8-bit input sums exactly in 32-bit integers; 16- and 32-bit input sum in FP32 with a
-// sub-sum folded into the accumulator every DD_CHAN_BLOCK channels (fixed order in c).
+// One (time tile, DM group) work unit for 16- and 32-bit input; every wavefront of the
+// workgroup takes part. Sums are FP32 with a sub-sum folded into the accumulator every
+// DD_CHAN_BLOCK channels (fixed order in c).
 template <typename TIn, bool RING>
 __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, int grp, float* smem) {
   constexpr int EB = (int)sizeof(TIn);
-  constexpr bool U8 = std::is_same<TIn, uint8_t>::value;
   constexpr bool F16 = std::is_same<TIn, __half>::value;
+  static_assert(EB >= 2, "8-bit input has its own tile body");
   const int nw = blockDim.x >> 6;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -340,11 +342,10 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
 
   float acc[kG][8];
   float sub[kG][8];
-  uint32_t iacc[kG][8];
 #pragma unroll
   for (int g = 0; g < kG; ++g)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f, iacc[g][s] = 0u;
+    for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f;
 
   // prologue: stages 0 .. nb-2 in flight
   const int pre = min(P.nb - 1, P.nstages);
@@ -366,13 +367,11 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
     int4 o0 = op[0], o1 = op[1];
     for (int cc = 0; cc < n_here; ++cc) {
       const int c = st * P.cs + cc;
-      if constexpr (!U8) {
-        if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
+      if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
 #pragma unroll
-          for (int g = 0; g < kG; ++g)
+        for (int g = 0; g < kG; ++g)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
-        }
+          for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
       }
       const int off[kG] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
       const char* cb = reinterpret_cast<const char*>(lds_i + slot_word(P, buf, cc)) + lane16;
@@ -396,9 +395,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
                                v[2 * g + 1].x, v[2 * g + 1].y, v[2 * g + 1].z, v[2 * g + 1].w};
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          if constexpr (U8)
-            iacc[g][s] += x[s];
-          else if constexpr (F16)
+          if constexpr (F16)
             sub[g][s] += __half2float(__ushort_as_half((unsigned short)x[s]));
           else
             sub[g][s] += __uint_as_float(x[s]);
@@ -409,7 +406,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
 #pragma unroll
   for (int g = 0; g < kG; ++g)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[g][s] = U8 ? (float)iacc[g][s] : acc[g][s] + sub[g][s];
+    for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s];
 
   store_tile(P, acc, dw, t0, tile, lane);
 }
