@@ -418,7 +418,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
 // 256-byte DMAs straight from the byte stream (sources need no alignment), then 256
 // bytes of trial offsets. A trial reads one dword per half: lane l takes samples
 // 4l .. 4l + 3 (and 256 + 4l ..) from copy k & 3 at a dword-aligned address, lanes on
-// consecutive dwords. v_perm splits the dword into the 16-bit pairs (s0, s2) and
+// consecutive dwords. Masks split the dword into the 16-bit pairs (s0, s2) and
 // (s1, s3), which add with plain 32-bit adds; every 256 channels (255 x 256 < 2^16) the
 // pairs fold into 32-bit accumulators, so the sums are exact integers.
 
@@ -575,9 +575,10 @@ __device__ __forceinline__ void tile_body_u8(const KParams& P, int64_t tile, int
       for (int g = 0; g < kG; ++g) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+          // full-rate mask and shift (v_perm issues at half rate)
           const uint32_t d = v[2 * g + h];
-          pr[g][2 * h] += __builtin_amdgcn_perm(d, d, 0x0c020c00u);      // (s0, s2)
-          pr[g][2 * h + 1] += __builtin_amdgcn_perm(d, d, 0x0c030c01u);  // (s1, s3)
+          pr[g][2 * h] += d & 0x00ff00ffu;             // (s0, s2)
+          pr[g][2 * h + 1] += (d >> 8) & 0x00ff00ffu;  // (s1, s3)
         }
       }
     }
