@@ -100,6 +100,7 @@ class ServeStats:
     blocks: int = 0
     fill_blocks: int = 0
     deadline_misses: int = 0
+    admitted_in_run: int = 0   # beams admitted while the run was going (freed slots and memory)
     wall_s: float = 0.0
     data_s: float = 0.0
     latencies: List[float] = dataclasses.field(default_factory=list)
@@ -114,6 +115,7 @@ class ServeStats:
             "real_time_factor": self.data_s / self.wall_s if self.wall_s > 0 else 0.0,
             "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
             "latency_max_s": float(lat.max()), "deadline_misses": self.deadline_misses,
+            "admitted_in_run": self.admitted_in_run,
             "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
         }
 
@@ -182,14 +184,19 @@ class Server:
             self._admit(b, nb)
 
     # ---------------------------------------------------------------- serving loop
-    def run(self, schedule: List[Block], fill: Optional[Callable[[int], bool]] = None) -> ServeStats:
+    def run(self, schedule: List[Block], fill: Optional[Callable[[int], bool]] = None,
+            release_done: bool = False) -> ServeStats:
         """Serve every block of ``schedule`` (arrival times relative to the start).
 
         Blocks of beams that are not admitted wait until their beam is. ``fill(beam)``
         tells whether a block result belongs to the ring fill (excluded from latency).
+        With ``release_done`` a beam is released as soon as its last scheduled block
+        has completed, which admits waiting beams while the others keep streaming;
+        their queued blocks count their wait in their latency.
         """
         pending = list(schedule)
         heapq.heapify(pending)
+        left: Dict[int, int] = collections.Counter(b.beam for b in schedule)
         ready: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
         next_seq: Dict[int, int] = collections.defaultdict(int)
         inflight: collections.deque = collections.deque()
@@ -216,6 +223,12 @@ class Server:
                     self.stats.latencies.append(br.latency)
                     if br.latency > self.specs[blk.beam].block_s:
                         self.stats.deadline_misses += 1
+                for blk in blocks:
+                    left[blk.beam] -= 1
+                    if release_done and left[blk.beam] == 0 and blk.beam in self.active:
+                        before = len(self.active)
+                        self.release(blk.beam)
+                        self.stats.admitted_in_run += len(self.active) - before + 1
             # form the next launch from every ready block of an admitted beam
             if len(inflight) < self.max_inflight:
                 batch: List[Block] = []

@@ -106,3 +106,37 @@ def test_footprint_and_admission(torch):
     assert srv.request(3) == "rejected"
     srv.release(0)
     assert 2 in srv.active or fps[2] > fps[0]
+
+
+def test_queued_beam_admitted_mid_run_equals_alone(torch):
+    import paper_1401_8258_amd as dd
+    dd.load_library()
+    specs = _specs()
+    nblocks = 3
+    host = [_blocks(sp, nblocks, 200 + i) for i, sp in enumerate(specs)]
+    dev = [[torch.from_numpy(b).cuda() for b in bs] for bs in host]
+    alone = {}
+    for i, sp in enumerate(specs):
+        st = dd.Stream(dd.Plan(sp.freq_mhz, sp.tsamp_s, sp.dm, dtype="u8"), sp.block)
+        for k, x in enumerate(dev[i]):
+            r = st.push(x, k_sigma=sp.k_sigma)
+            if r is not None:
+                alone[(i, k)] = r.out.cpu().numpy()
+    torch.cuda.synchronize()
+    print("case: beam 2 queued by the HBM budget, admitted when beam 0 finishes", flush=True)
+    ex = serve.LibraryExecutor(k_sigma=6.0, keep=True)
+    fps = [ex.footprint(sp) for sp in specs]
+    srv = serve.Server(specs, ex, hbm_budget=fps[0] + fps[1] + min(fps[2] - 1, fps[0] - 1), max_inflight=2)
+    assert [srv.request(i) for i in range(3)] == ["admitted", "admitted", "queued"]
+    # beam 0 gets one block, so it finishes first and frees its memory for beam 2
+    sched = [b for b in serve.poisson_schedule(specs, nblocks, seed=9, jitter_mean_s=0.01,
+                                               phases=[0.0, 0.001, 0.002],
+                                               make_data=lambda i, k: dev[i][k], time_scale=0.02)
+             if not (b.beam == 0 and b.seq > 0)]
+    st = srv.run(sched, release_done=True)
+    torch.cuda.synchronize()
+    assert st.admitted_in_run == 1 and not srv.active
+    want = {key: v for key, v in alone.items() if not (key[0] == 0 and key[1] > 0)}
+    assert set(ex.kept) == set(want)
+    for key, out in want.items():
+        np.testing.assert_array_equal(ex.kept[key]["out"].cpu().numpy(), out)

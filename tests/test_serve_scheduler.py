@@ -130,3 +130,25 @@ def test_blocks_wait_for_admission():
     st = srv.run([Block(0.0, 0, 0), Block(0.0, 1, 0)])
     # beam 1 never got memory: its block is still unserved, beam 0's was served
     assert [r.beam for r in srv.results] == [0]
+
+
+def test_waiting_beam_admitted_when_memory_frees_during_run():
+    vc = VClock()
+    specs = _specs(3)
+    ex = FakeExecutor(vc, foot=100)
+    srv = Server(specs, ex, hbm_budget=200, clock=vc.clock, sleep=vc.sleep)
+    assert [srv.request(i) for i in range(3)] == ["admitted", "admitted", "queued"]
+    # beam 0 streams 2 blocks, beam 1 six, beam 2 (queued) four from the start
+    sched = ([Block(k * 1.0, 0, k) for k in range(2)] + [Block(k * 1.0, 1, k) for k in range(6)]
+             + [Block(k * 1.0, 2, k) for k in range(4)])
+    st = srv.run(sched, release_done=True)
+    assert st.blocks == 12 and st.admitted == 3 and st.admitted_in_run == 1
+    assert ex.opened == [0, 1, 2] and sorted(ex.closed) == [0, 1, 2]
+    # beam 2 could only start after beam 0's last block completed (~t = 1 s)
+    first2 = min(r.done for r in srv.results if r.beam == 2)
+    last0 = max(r.done for r in srv.results if r.beam == 0)
+    assert first2 >= last0
+    # its blocks keep their order and all complete
+    seqs = [r.seq for r in srv.results if r.beam == 2]
+    assert seqs == sorted(seqs) == [0, 1, 2, 3]
+    assert srv.used == 0 and not srv.active
