@@ -71,10 +71,15 @@ typedef struct dd_stream dd_stream;
 /* Optional tile choice; zero fields take the library default. */
 typedef struct dd_tuning {
   int32_t dms_per_wave;       /* DM trials each wavefront accumulates: 8 */
-  int32_t waves;              /* wavefronts per workgroup, each on its own DMs (1, 2, 4 or 8) */
+  int32_t waves;              /* computing wavefronts per workgroup, each on its own DMs
+                                 (1..8, at most 8 - producer_waves) */
   int32_t samples_per_lane;   /* output samples per lane: 8 (the tile is 512 samples) */
-  int32_t chan_stage;         /* channels per LDS stage (0..8; rounded down to a divisor of
-                                 waves; 0 = automatic) */
+  int32_t chan_stage;         /* channels per LDS stage (0..8; without a producer rounded
+                                 down to a divisor of waves; 0 = automatic) */
+  int32_t producer_waves;     /* wavefronts that only move input into LDS, FP32 input only:
+                                 0 or -1 none (every wavefront issues its share of the DMAs),
+                                 1 or 2 (waves + producer_waves <= 8; DD_ERR_UNSUPPORTED when
+                                 a group's channel windows exceed 1024 words) */
 } dd_tuning;
 
 typedef struct dd_plan_info {
@@ -84,7 +89,8 @@ typedef struct dd_plan_info {
   int64_t ring_bytes;               /* for dd_stream_create with block_nsamp = nsamp */
   int32_t dms_per_wave, waves, samples_per_lane, max_span;  /* chosen tiles; LDS span */
   int64_t adds;                     /* ndm * nchan * nout: the algorithmic work */
-  int32_t chan_stage, reserved;     /* channels per LDS stage requested (0 = automatic) */
+  int32_t chan_stage;               /* channels per LDS stage requested (0 = automatic) */
+  int32_t producer_waves;           /* chosen: wavefronts that only issue the LDS DMAs */
   /* launch geometry (fixed at plan creation for 160 KB of LDS per workgroup): shifted
      copies of each channel vector, samples per copy (32-bit words for 16/32-bit input,
      bytes for 8-bit input), channels per stage, stages in the LDS ring, LDS bytes per

@@ -20,7 +20,8 @@ CHAN_BLOCK = 32
 
 class Tuning(C.Structure):
     _fields_ = [("dms_per_wave", C.c_int32), ("waves", C.c_int32),
-                ("samples_per_lane", C.c_int32), ("chan_stage", C.c_int32)]
+                ("samples_per_lane", C.c_int32), ("chan_stage", C.c_int32),
+                ("producer_waves", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -29,7 +30,7 @@ class PlanInfo(C.Structure):
                 ("workspace_bytes", C.c_int64), ("ring_bytes", C.c_int64),
                 ("dms_per_wave", C.c_int32), ("waves", C.c_int32),
                 ("samples_per_lane", C.c_int32), ("max_span", C.c_int32),
-                ("adds", C.c_int64), ("chan_stage", C.c_int32), ("reserved", C.c_int32),
+                ("adds", C.c_int64), ("chan_stage", C.c_int32), ("producer_waves", C.c_int32),
                 ("launch_copies", C.c_int32), ("launch_buf", C.c_int32), ("launch_stage", C.c_int32),
                 ("launch_ring", C.c_int32), ("launch_lds", C.c_int64)]
 

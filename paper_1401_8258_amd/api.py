@@ -74,10 +74,11 @@ class Plan:
             raise ValueError(f"unsupported input dtype {dtype}")
         h = C.c_void_p()
         tun = None
-        if tuning is not None:  # (dms_per_wave, waves[, chan_stage])
+        if tuning is not None:  # (dms_per_wave, waves[, chan_stage[, producer_waves]])
             g, w = int(tuning[0]), int(tuning[1])
             cc = int(tuning[2]) if len(tuning) > 2 else 0
-            tun = C.byref(_lib.Tuning(g, w, 8, cc))
+            pw = int(tuning[3]) if len(tuning) > 3 else 0
+            tun = C.byref(_lib.Tuning(g, w, 8, cc, pw))
         dbl = C.POINTER(C.c_double)
         check(lib.dd_plan_create(C.byref(h), self.freq.ctypes.data_as(dbl), int(self.freq.size), self.tsamp,
                                  self.dm.ctypes.data_as(dbl), int(self.dm.size), _TORCH_DT[self.dtype], tun))
@@ -86,6 +87,7 @@ class Plan:
         info = self.query(1, allow_short=True)
         self.maxdelay = int(info["maxdelay"])
         self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(info["chan_stage"]))
+        self.producer_waves = int(info["producer_waves"])
         self.max_span = int(info["max_span"])
 
     @property

@@ -30,13 +30,18 @@ constexpr int kMaxX4 = 16;
 struct Launch {
   int L;        // samples per (channel, copy) buffer (four copies shifted by 0..3 samples);
                 // 32-bit words for 16/32-bit input, bytes for 8-bit input
-  int cs;       // channels per stage (a divisor of the wavefront count)
+  int cs;       // channels per stage (a divisor of the wavefront count unless prod > 0)
   int nb;       // stages in the LDS ring
-  int nd;       // DMA instructions per wavefront per stage
+  int nd;       // DMA instructions per stage channel share: per wavefront per stage, or
+                // with a producer per channel
   int x4;       // FP32 data arrives by 16-byte DMAs
   int64_t lds;  // bytes
+  int prod;     // wavefronts that only issue DMAs (0: every wavefront issues its share)
+  int ndw;      // DMA instructions per issuing wavefront per stage (the vmcnt unit)
 };
 Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap, int elem_bytes);
+// FP32 input with nprod producer wavefronts issuing whole channels; nb = 0 if nothing fits.
+Launch choose_launch_prod(int32_t max_span, int nchan, int cs_req, int64_t lds_cap, int nprod);
 
 inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -45,6 +50,7 @@ struct Tiles {
   int32_t w;   // wavefronts per workgroup (each on its own G trials)
   int32_t s;   // output samples per lane (fixed: 8, two chunks of 4)
   int32_t cc;  // channels staged into LDS per barrier pair (0 = automatic)
+  int32_t pw;  // producer wavefronts requested: -1 none, 0 automatic, 1 one
 };
 
 }  // namespace dd

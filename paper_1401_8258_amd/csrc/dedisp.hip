@@ -83,11 +83,14 @@ struct KParams {
   int64_t out_stride, nout, nitems;
   int ndm_pad, nchan, ndm, ngroups;
   int L;        // words per (channel, copy) buffer
-  int cs;       // channels per stage (divides the wavefront count)
+  int cs;       // channels per stage (divides nw unless a producer issues the DMAs)
   int nb;       // stages in the LDS ring
-  int nd;       // DMA instructions per wavefront per stage
+  int nd;       // DMA instructions per wavefront per stage; with a producer, per channel
   int nstages;  // ceil(nchan / cs)
   int x4;       // FP32 input: copies arrive by 16-byte DMAs (nd counts those)
+  int nw;       // computing wavefronts (8 DM trials each)
+  int nprod;    // wavefronts after those that only issue DMAs (0, 1 or 2)
+  int ndw;      // DMA instructions per issuing wavefront per stage (the vmcnt unit)
   // 8-bit linear input: a channel window that would read past the end of the input
   // (byte in_bytes of the whole [nchan][row_stride] array) reads from `tail`, a copy of
   // input bytes [tail_base, in_bytes) followed by in_bytes - tail_base bytes of padding
@@ -325,7 +328,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
   constexpr int EB = (int)sizeof(TIn);
   constexpr bool F16 = std::is_same<TIn, __half>::value;
   static_assert(EB >= 2, "8-bit input has its own tile body");
-  const int nw = blockDim.x >> 6;
+  const int nw = P.nw;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gw = kG * nw;
@@ -357,7 +360,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
   for (int st = 0; st < P.nstages; ++st) {
     // stages issued after st: min(nstages - 1, st + nb - 2) - st
     const int later = min(P.nstages - 1, st + P.nb - 2) - st;
-    wait_vm(later * P.nd);
+    wait_vm(later * P.ndw);
     block_barrier();
     if (st + P.nb - 1 < P.nstages) stage_dma<EB, RING>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0, wsub,
                                                       wpc);
@@ -498,7 +501,7 @@ __device__ __forceinline__ void stage_dma_u8(const KParams& P, const DescU8& D, 
 
 template <bool RING>
 __device__ __forceinline__ void tile_body_u8(const KParams& P, int64_t tile, int grp, float* smem) {
-  const int nw = blockDim.x >> 6;
+  const int nw = P.nw;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gw = kG * nw;
@@ -545,7 +548,7 @@ __device__ __forceinline__ void tile_body_u8(const KParams& P, int64_t tile, int
 
   for (int st = 0; st < P.nstages; ++st) {
     const int later = min(P.nstages - 1, st + P.nb - 2) - st;
-    wait_vm(later * P.nd);
+    wait_vm(later * P.ndw);
     block_barrier();
     if (st + P.nb - 1 < P.nstages)
       stage_dma_u8<RING>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0);
@@ -593,6 +596,101 @@ __device__ __forceinline__ void tile_body_u8(const KParams& P, int64_t tile, int
   store_tile(P, facc, dw, t0, tile, lane);
 }
 
+// ------------------------------------------------------------------ FP32 with a producer
+//
+// Wavefronts nw .. nw + nprod - 1 issue every DMA of every stage, whole channels in stage
+// order (producer i takes stage channels i, i + nprod, ...: the four copies as L/64
+// 16-byte DMAs, then the trial offsets), and wait for them; wavefronts 0 .. nw-1 only
+// compute. The ring keeps at most 63 DMAs per producer in flight, so a producer never
+// stalls on its own vmcnt when it issues. All of them meet at one barrier per stage: before it
+// stage st has landed and stage st - 1 has been read, after it the producer refills the
+// slot of stage st - 1 with stage st + nb - 1. Issuing waits for the DMA path (about
+// 60 bytes per clock per CU), and here only the producer waits, while the computing
+// wavefronts keep the LDS busy. The sums are those of the all-wavefront form: same
+// offsets, same channel order, same DD_CHAN_BLOCK folding.
+template <bool RING>
+__device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, int grp, float* smem) {
+  const int nw = P.nw;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gw = kG * nw;
+  const int64_t t0 = tile * kTile;
+  const int dg = grp * gw;
+  const unsigned sbase = lds_addr(smem);
+  if (w >= nw) {
+    const int pi = w - nw;  // producer pi takes stage channels pi, pi + nprod, ...
+    const int w0 = P.in.ring_len > 0 ? (int)(P.in.win0 % P.in.ring_len) : 0;
+    DmaDesc D;
+    make_desc(P, 0, 1, lane, &D);
+    const int pre = min(P.nb - 1, P.nstages);
+    for (int sd = 0; sd < pre; ++sd)
+      for (int cc = pi; cc < P.cs; cc += P.nprod)
+        stage_dma<4, RING>(P, D, sbase, sd, cc, t0, grp, dg, gw, lane, w0, 0, 1);
+    for (int st = 0; st < P.nstages; ++st) {
+      const int later = min(P.nstages - 1, st + P.nb - 2) - st;
+      wait_vm(later * P.ndw);
+      block_barrier();
+      const int sd = st + P.nb - 1;
+      if (sd < P.nstages)
+        for (int cc = pi; cc < P.cs; cc += P.nprod)
+          stage_dma<4, RING>(P, D, sbase, sd, cc, t0, grp, dg, gw, lane, w0, 0, 1);
+    }
+    return;
+  }
+  const int dw = dg + w * kG;
+  float acc[kG][8];
+  float sub[kG][8];
+#pragma unroll
+  for (int g = 0; g < kG; ++g)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f;
+  const int* lds_i = reinterpret_cast<const int*>(smem);
+  const unsigned lane16 = 16u * (unsigned)lane;
+  const int offw = kCopies * P.L + w * kG;  // this wavefront's 8 offsets inside a slot
+  for (int st = 0; st < P.nstages; ++st) {
+    block_barrier();
+    const int buf = st % P.nb;
+    const int n_here = min(P.cs, P.nchan - st * P.cs);
+    const int4* op = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, 0) + offw);
+    int4 o0 = op[0], o1 = op[1];
+    for (int cc = 0; cc < n_here; ++cc) {
+      const int c = st * P.cs + cc;
+      if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
+#pragma unroll
+        for (int g = 0; g < kG; ++g)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
+      }
+      const int off[kG] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
+      const char* cb = reinterpret_cast<const char*>(lds_i + slot_word(P, buf, cc)) + lane16;
+      uint4 v[2 * kG];
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const uint4* a = reinterpret_cast<const uint4*>(cb + off[g]);
+        v[2 * g] = a[0];
+        v[2 * g + 1] = a[64];
+      }
+      if (cc + 1 < n_here) {
+        const int4* np = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, cc + 1) + offw);
+        o0 = np[0];
+        o1 = np[1];
+      }
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const uint32_t x[8] = {v[2 * g].x,     v[2 * g].y,     v[2 * g].z,     v[2 * g].w,
+                               v[2 * g + 1].x, v[2 * g + 1].y, v[2 * g + 1].z, v[2 * g + 1].w};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) sub[g][s] += __uint_as_float(x[s]);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < kG; ++g)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s];
+  store_tile(P, acc, dw, t0, tile, lane);
+}
+
 template <typename TIn>
 __device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int grp, float* smem) {
   if constexpr (std::is_same<TIn, uint8_t>::value) {
@@ -600,6 +698,11 @@ __device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int gr
       tile_body_u8<true>(P, tile, grp, smem);
     else
       tile_body_u8<false>(P, tile, grp, smem);
+  } else if (std::is_same<TIn, float>::value && P.nprod > 0) {
+    if (P.in.ring_len > 0)
+      tile_body_prod<true>(P, tile, grp, smem);
+    else
+      tile_body_prod<false>(P, tile, grp, smem);
   } else {
     if (P.in.ring_len > 0)
       tile_body_impl<TIn, true>(P, tile, grp, smem);
@@ -875,6 +978,9 @@ int build_params(const dd_plan* p, const InView& in, const int32_t* d_table, int
   P->nd = g.nd;
   P->nstages = (p->nchan + g.cs - 1) / g.cs;
   P->x4 = g.x4;
+  P->nw = p->tiles.w;
+  P->nprod = g.prod;
+  P->ndw = g.ndw;
   if (p->dtype == DD_U8 && in.ring_len == 0) {
     P->in_bytes = (int64_t)(p->nchan - 1) * in.row_stride + in.nvalid;
     P->tail_base = std::max<int64_t>(0, P->in_bytes - l.tail_bytes);
@@ -941,7 +1047,7 @@ int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int
   if (rc) return rc;
   const int64_t nblocks = (P.nitems + 7) / 8 * 8;
   if (nblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many work items");
-  hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * p->tiles.w), (size_t)g.lds, st, P);
+  hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (P.nw + P.nprod)), (size_t)g.lds, st, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "dedisp_tile launch");
   return launch_tail(p, nout, o, ws, l, st);
@@ -1113,7 +1219,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   std::vector<Outputs> outs((size_t)n);
   std::vector<int64_t> nouts((size_t)n);
   std::vector<dd::WsLayout> lays((size_t)n);
-  int32_t dtype = -1, waves = -1;
+  int32_t dtype = -1, waves = -1, prod = -1;
   int64_t lds = 0;
   for (int32_t i = 0; i < n; ++i) {
     const dd_batch_item& it = items[i];
@@ -1121,9 +1227,10 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     const dd_plan* p = sp ? sp->plan : it.plan;
     if (!p || !it.d_plan_workspace)
       return dd::fail(DD_ERR_INVALID_ARG, "batch item " + std::to_string(i) + ": plan and workspace required");
-    if (dtype < 0) dtype = p->dtype, waves = p->tiles.w;
-    if (p->dtype != dtype || p->tiles.w != waves)
-      return dd::fail(DD_ERR_UNSUPPORTED, "batch items must share the input dtype and DM trials per workgroup");
+    if (dtype < 0) dtype = p->dtype, waves = p->tiles.w, prod = p->launch.prod;
+    if (p->dtype != dtype || p->tiles.w != waves || p->launch.prod != prod)
+      return dd::fail(DD_ERR_UNSUPPORTED, "batch items must share the input dtype, the DM trials per workgroup "
+                                          "and the producer wavefront count");
     InView in;
     const int32_t* table;
     int64_t nout, t_base = 0, lay_n;
@@ -1185,7 +1292,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
   // `units` is the largest per-XCD share
   const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, units * 8) / 8 * 8);
-  hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * waves), (size_t)lds, st, (const KParams*)dP,
+  hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (waves + prod)), (size_t)lds, st, (const KParams*)dP,
                      (const int64_t*)dS, (int)n);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "dedisp_batch launch");

@@ -23,7 +23,8 @@ bool valid_tiles(const dd::Tiles& t) {
     for (int x : xs) if (v == x) return true;
     return false;
   };
-  return t.g == 8 && (t.w == 0 || in(t.w, {1, 2, 4, 8})) && t.s == 8 && t.cc >= 0 && t.cc <= 8;
+  return t.g == 8 && t.w >= 0 && t.w <= 8 && t.s == 8 && t.cc >= 0 && t.cc <= 8 && in(t.pw, {-1, 0, 1, 2}) &&
+         !(t.pw > 0 && t.w + t.pw > 8);
 }
 
 // Largest in-group delay spread over all channels, for groups of gw trials with the last
@@ -107,6 +108,7 @@ Launch choose_launch_u8(int32_t max_span, int nw, int cs_req, int64_t lds_cap) {
   }
   if (best_score < 0) return Launch{};
   best.lds = (int64_t)best.nb * best.cs * per_chan;
+  best.ndw = best.nd;
   return best;
 }
 
@@ -148,6 +150,48 @@ Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t ld
   }
   if (best_score < 0) return Launch{};
   best.lds = (int64_t)best.nb * best.cs * per_chan;
+  best.ndw = best.nd;
+  return best;
+}
+
+// FP32 input, one producer wavefront: it issues every channel of a stage whole (the four
+// copies as L/64 16-byte DMAs, then the offsets), so any stage width works, and the
+// computing wavefronts never wait on a DMA issue. A channel's copies must fit the 16
+// per-lane descriptors (L <= 1024 words).
+Launch choose_launch_prod(int32_t max_span, int nchan, int cs_req, int64_t lds_cap, int nprod) {
+  Launch best{};
+  const int64_t L = (kTile + (int64_t)max_span + 63) / 64 * 64;
+  if (L / 64 > kMaxX4) return best;
+  const int64_t per_chan = (4 * L + 64) * 4;
+  const int nd = (int)(L / 64) + 1;
+  // at least one channel per producer (stage channels past the last repeat it)
+  const int cs_hi = cs_req > 0 ? cs_req : std::max(nprod, std::min(8, nchan));
+  int64_t best_score = -1;
+  for (int cs = cs_hi; cs >= 1; --cs) {
+    if (cs % nprod) continue;  // each producer takes cs / nprod whole channels
+    const int64_t ndw = (int64_t)(cs / nprod) * nd;
+    int nb = (int)std::min<int64_t>(lds_cap / (cs * per_chan), 16);
+    // every DMA of the nb - 1 stages ahead is in flight at once: a wavefront issues at
+    // most 63 before it stalls (vmcnt), so the producer never waits to issue
+    while (nb > 2 && (int64_t)(nb - 1) * ndw > 63) --nb;
+    if (nb < 2 || ndw > 63) continue;
+    if (cs_req > 0 && best_score >= 0) break;
+    // a stage of slack for the DMAs (three or more stages), then the most channels in
+    // flight, then the fewest barriers
+    const int64_t score = (nb >= 3 ? (int64_t)1 << 20 : 0) + (int64_t)nb * cs * 16 + cs;
+    if (score > best_score) {
+      best_score = score;
+      best.L = (int)L;
+      best.cs = cs;
+      best.nb = nb;
+      best.nd = nd;
+      best.ndw = (int)ndw;
+    }
+  }
+  if (best_score < 0) return Launch{};
+  best.x4 = 1;
+  best.prod = nprod;
+  best.lds = (int64_t)best.nb * best.cs * per_chan;
   return best;
 }
 
@@ -184,14 +228,17 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
       return dd::fail(DD_ERR_INVALID_ARG, "DM trials must be in non-decreasing order");
   }
 
-  dd::Tiles t{8, 0, 8, 0};
+  dd::Tiles t{8, 0, 8, 0, 0};
   if (tuning) {
     if (tuning->dms_per_wave) t.g = tuning->dms_per_wave;
     if (tuning->waves) t.w = tuning->waves;
     if (tuning->samples_per_lane) t.s = tuning->samples_per_lane;
     t.cc = tuning->chan_stage;
+    t.pw = tuning->producer_waves;
   }
   if (!valid_tiles(t)) return dd::fail(DD_ERR_UNSUPPORTED, "unsupported tuning");
+  if (t.pw > 0 && in_dtype != DD_F32)
+    return dd::fail(DD_ERR_UNSUPPORTED, "producer wavefronts are available for FP32 input only");
 
   dd_plan* p = new (std::nothrow) dd_plan();
   if (!p) return dd::fail(DD_ERR_INVALID_ARG, "out of host memory");
@@ -224,11 +271,30 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   p->maxdelay = (int32_t)maxd;
 
   // DM trials per workgroup: 8 per wavefront, as many wavefronts as keep the LDS ring
-  // at least 8 channels deep (unless the caller fixed the count).
+  // at least 8 channels deep (unless the caller fixed the count). Producer wavefronts
+  // only when asked for: with every wavefront issuing its share, more DMAs are in flight
+  // per CU (at most 63 per wavefront), which measured at least as fast on the full FP32
+  // workload.
   int32_t span = 0;
   dd::Launch lg{};
+  bool placed = false;
+  if (in_dtype == DD_F32 && t.pw > 0) {
+    const int wp_opts[5] = {6, 4, 3, 2, 1};
+    for (int oi = 0; oi < 5 && !placed; ++oi) {
+      const int nw = t.w ? t.w : std::min(wp_opts[oi], 8 - t.pw);
+      const int32_t sp = compute_span(p->delays, nchan, ndm, t.g * nw);
+      const dd::Launch l = dd::choose_launch_prod(sp, nchan, t.cc, dd::kLdsBytes, t.pw);
+      if (l.nb >= 2) t.w = nw, span = sp, lg = l, placed = true;  // the most wavefronts that fit
+      if (t.w) break;
+    }
+    if (!placed) {
+      delete p;
+      return dd::fail(DD_ERR_UNSUPPORTED, "one DM group's windows do not fit the producer wavefronts' "
+                                          "16-byte DMAs; use fewer DMs per workgroup or no producer");
+    }
+  }
   const int w_opts[4] = {8, 4, 2, 1};
-  for (int oi = 0; oi < 4; ++oi) {
+  for (int oi = 0; oi < 4 && !placed; ++oi) {
     const int nw = t.w ? t.w : w_opts[oi];
     span = compute_span(p->delays, nchan, ndm, t.g * nw);
     lg = dd::choose_launch(span, nw, nchan, t.cc, dd::kLdsBytes, (int)dd::elem_bytes(in_dtype));
@@ -288,6 +354,7 @@ int dd_plan_query(const dd_plan* p, int64_t nsamp, dd_plan_info* info) {
   info->waves = p->tiles.w;
   info->samples_per_lane = p->tiles.s;
   info->chan_stage = p->tiles.cc;
+  info->producer_waves = p->launch.prod;
   info->max_span = p->max_span;
   info->launch_copies = 4;
   info->launch_buf = p->launch.L;

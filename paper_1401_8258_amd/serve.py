@@ -335,7 +335,7 @@ class LibraryExecutor(Executor):
         for i, (blk, w) in enumerate(zip(blocks, pend)):
             if w is not None:
                 plan = self._beams[blk.beam]["stream"].plan
-                groups[(plan.dtype, plan.tiles[1])].append(i)
+                groups[(plan.dtype, plan.tiles[1], plan.producer_waves)].append(i)
         res: List[object] = [None] * len(blocks)
         for idx in groups.values():
             jobs, outs = [], []

@@ -182,3 +182,40 @@ def test_every_workload_has_a_launch_geometry(lib):
         info = _launch_ok(lib, freq, dm, tsamp, dt, tun)
         assert info.launch_ring >= 2 and 0 < info.launch_lds <= 160 * 1024, (len(freq), len(dm), tun)
         assert info.launch_buf % 64 == 0 and info.launch_copies == 4
+
+
+def test_producer_wavefront_plans(lib):
+    """Producer wavefronts (FP32 only, opt-in): tuning checks and the ring bounds they need.
+
+    Each producer issues whole stage channels: L/64 16-byte DMAs for the four copies and
+    one for the trial offsets, so (cs / producers) * (L/64 + 1) per stage, and with nb - 1
+    stages ahead no more than the 63 a wavefront can have outstanding.
+    """
+    freq = fbsynth.channel_freqs(428.0, 20 / 1024, 1024)
+    dm = fbsynth.dm_trials(0, 0.1, 2048)
+    plain = _launch_ok(lib, freq, dm, 51.2e-6)
+    assert plain.producer_waves == 0 and plain.waves == 8  # the default issues from every wavefront
+    for pw in (1, 2):
+        info = _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 0, 8, 0, pw))
+        assert info.producer_waves == pw and info.waves + pw <= 8
+        assert info.launch_stage % pw == 0 and info.launch_buf % 64 == 0 and info.launch_buf // 64 <= 16
+        ndw = info.launch_stage // pw * (info.launch_buf // 64 + 1)
+        assert (info.launch_ring - 1) * ndw <= 63 and info.launch_ring >= 2
+        assert info.launch_lds == info.launch_ring * info.launch_stage * (4 * info.launch_buf + 64) * 4
+        assert info.launch_lds <= 160 * 1024
+    # explicit shapes
+    info = _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 6, 8, 6, 2))
+    assert (info.waves, info.producer_waves, info.launch_stage, info.launch_ring) == (6, 2, 6, 2)
+    for bad in [(8, 7, 8, 0, 2), (8, 8, 8, 0, 1), (8, 0, 8, 0, 3)]:
+        rc, _ = _create(lib, freq, dm, 51.2e-6, 0, bad)
+        assert rc == lib_mod.DD_ERR_UNSUPPORTED, bad
+    for dt in (1, 2):  # FP16 and u8 input take no producer
+        rc, _ = _create(lib, freq, dm, 51.2e-6, dt, (8, 0, 8, 0, 1))
+        assert rc == lib_mod.DD_ERR_UNSUPPORTED and b"FP32" in lib.dd_last_error()
+    # one channel, two producers: the stage repeats the channel for the second producer
+    info = _launch_ok(lib, [400.0], [0.0, 1.0], 51.2e-6, 0, (8, 0, 8, 0, 2))
+    assert info.producer_waves == 2 and info.launch_stage == 2
+    # windows wider than 1024 words cannot go through the 16 per-lane descriptors
+    rc, _ = _create(lib, fbsynth.channel_freqs(428.0, 3.75, 16), fbsynth.dm_trials(0, 2.0, 64), 51.2e-6, 0,
+                    (8, 0, 8, 0, 1))
+    assert rc == lib_mod.DD_ERR_UNSUPPORTED
