@@ -180,15 +180,15 @@ struct DmaDesc {
   int rel[4], ldw[4];
   int relx[kMaxX4];
 };
+template <bool X4>
 __device__ __forceinline__ void make_desc(const KParams& P, int sub, int wpc, int lane, DmaDesc* d) {
   const int nch = P.L >> 6;
-  if (P.x4) {
+  if constexpr (X4) {
 #pragma unroll
     for (int j = 0; j < kMaxX4; ++j) {
       const int r = min(sub + wpc * j, nch - 1);
       d->relx[j] = slot_rel(256 * r + 4 * lane, P.L);
     }
-    d->rel[0] = d->rel[1] = d->ldw[0] = d->ldw[1] = 0;
     return;
   }
   const int nchunk = kCopies * nch + 1;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void dma_chunk(const char* rp, const int32_t* orow, i
 // This wavefront's DMAs for stage sd: its channel's chunks and the group's trial offsets
 // for that channel. `start` is the row index of window position `first`: on a ring,
 // (win0 + first) mod ring_len, and the mirror keeps the whole window contiguous.
-template <int EB, bool RING>
+template <int EB, bool RING, bool X4>
 __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, unsigned sbase, int sd, int cc_w,
                                           int64_t t0, int grp, int dg, int gw, int lane, int w0, int sub, int wpc) {
   int c = sd * P.cs + cc_w;
@@ -236,8 +236,9 @@ __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, un
   const int32_t* orow = P.dtab + (int64_t)c * P.ndm_pad + dg;
   const unsigned slot = sbase + 4u * (unsigned)slot_word(P, sd % P.nb, cc_w);
   const int nlim = (int)P.in.nvalid - 1;
-  if constexpr (EB == 4) {
-    if (P.x4) {
+  if constexpr (X4) {
+    static_assert(EB == 4, "16-byte DMAs carry FP32 input");
+    {
       const int nch = P.L >> 6;
       const int njx = P.nd - 1;
       // the window's last sample is first + L + 2 (copy 3, word L - 1)
@@ -263,16 +264,16 @@ __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, un
         wait_vm(0);
       }
       dma<4>(orow, 4u * (unsigned)min(lane, gw - 1), slot + 4u * (unsigned)(kCopies * P.L));
-      return;
     }
-  }
+  } else {
 #pragma unroll
-  for (int h = 0; h < 4; ++h) {
-    const int n = min(P.nd - 64 * h, 64);
-    for (int j = 0; j < n; ++j) {
-      const int rel = __builtin_amdgcn_readlane(D.rel[h], j);
-      const int ldw = __builtin_amdgcn_readlane(D.ldw[h], j);
-      dma_chunk<EB, RING>(rp, orow, rel, ldw, slot, start, nlim, lane, gw);
+    for (int h = 0; h < 4; ++h) {
+      const int n = min(P.nd - 64 * h, 64);
+      for (int j = 0; j < n; ++j) {
+        const int rel = __builtin_amdgcn_readlane(D.rel[h], j);
+        const int ldw = __builtin_amdgcn_readlane(D.ldw[h], j);
+        dma_chunk<EB, RING>(rp, orow, rel, ldw, slot, start, nlim, lane, gw);
+      }
     }
   }
 }
@@ -323,7 +324,7 @@ __device__ __forceinline__ void store_tile(const KParams& P, const float (&acc)[
 // One (time tile, DM group) work unit for 16- and 32-bit input; every wavefront of the
 // workgroup takes part. Sums are FP32 with a sub-sum folded into the accumulator every
 // DD_CHAN_BLOCK channels (fixed order in c).
-template <typename TIn, bool RING>
+template <typename TIn, bool RING, bool X4>
 __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, int grp, float* smem) {
   constexpr int EB = (int)sizeof(TIn);
   constexpr bool F16 = std::is_same<TIn, __half>::value;
@@ -340,7 +341,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
   const int cc_w = w / wpc;
   const int wsub = w - cc_w * wpc;
   DmaDesc D;
-  make_desc(P, wsub, wpc, lane, &D);
+  make_desc<X4>(P, wsub, wpc, lane, &D);
   const unsigned sbase = lds_addr(smem);
 
   float acc[kG][8];
@@ -352,7 +353,7 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
 
   // prologue: stages 0 .. nb-2 in flight
   const int pre = min(P.nb - 1, P.nstages);
-  for (int sd = 0; sd < pre; ++sd) stage_dma<EB, RING>(P, D, sbase, sd, cc_w, t0, grp, dg, gw, lane, w0, wsub, wpc);
+  for (int sd = 0; sd < pre; ++sd) stage_dma<EB, RING, X4>(P, D, sbase, sd, cc_w, t0, grp, dg, gw, lane, w0, wsub, wpc);
   const int* lds_i = reinterpret_cast<const int*>(smem);
   const unsigned lane16 = 16u * (unsigned)lane;
   const int offw = kCopies * P.L + w * kG;  // this wavefront's 8 offsets inside a slot
@@ -362,8 +363,8 @@ __device__ __forceinline__ void tile_body_impl(const KParams& P, int64_t tile, i
     const int later = min(P.nstages - 1, st + P.nb - 2) - st;
     wait_vm(later * P.ndw);
     block_barrier();
-    if (st + P.nb - 1 < P.nstages) stage_dma<EB, RING>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0, wsub,
-                                                      wpc);
+    if (st + P.nb - 1 < P.nstages)
+      stage_dma<EB, RING, X4>(P, D, sbase, st + P.nb - 1, cc_w, t0, grp, dg, gw, lane, w0, wsub, wpc);
     const int buf = st % P.nb;
     const int n_here = min(P.cs, P.nchan - st * P.cs);
     const int4* op = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, 0) + offw);
@@ -621,11 +622,11 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
     const int pi = w - nw;  // producer pi takes stage channels pi, pi + nprod, ...
     const int w0 = P.in.ring_len > 0 ? (int)(P.in.win0 % P.in.ring_len) : 0;
     DmaDesc D;
-    make_desc(P, 0, 1, lane, &D);
+    make_desc<true>(P, 0, 1, lane, &D);
     const int pre = min(P.nb - 1, P.nstages);
     for (int sd = 0; sd < pre; ++sd)
       for (int cc = pi; cc < P.cs; cc += P.nprod)
-        stage_dma<4, RING>(P, D, sbase, sd, cc, t0, grp, dg, gw, lane, w0, 0, 1);
+        stage_dma<4, RING, true>(P, D, sbase, sd, cc, t0, grp, dg, gw, lane, w0, 0, 1);
     for (int st = 0; st < P.nstages; ++st) {
       const int later = min(P.nstages - 1, st + P.nb - 2) - st;
       wait_vm(later * P.ndw);
@@ -633,7 +634,7 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
       const int sd = st + P.nb - 1;
       if (sd < P.nstages)
         for (int cc = pi; cc < P.cs; cc += P.nprod)
-          stage_dma<4, RING>(P, D, sbase, sd, cc, t0, grp, dg, gw, lane, w0, 0, 1);
+          stage_dma<4, RING, true>(P, D, sbase, sd, cc, t0, grp, dg, gw, lane, w0, 0, 1);
     }
     return;
   }
@@ -691,29 +692,41 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
   store_tile(P, acc, dw, t0, tile, lane);
 }
 
-template <typename TIn>
-__device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int grp, float* smem) {
+// How a kernel instantiation moves input into LDS. Each instantiation carries only the
+// DMA code it runs (the 4-byte form's descriptor tables and loop would cost the 16-byte
+// form registers); kAny picks per item, for batches that mix the two.
+enum Form { kX1 = 0, kX4 = 1, kProd = 2, kAny = 3 };
+
+template <typename TIn, bool RING, int F>
+__device__ __forceinline__ void tile_body_ring(const KParams& P, int64_t tile, int grp, float* smem) {
   if constexpr (std::is_same<TIn, uint8_t>::value) {
-    if (P.in.ring_len > 0)
-      tile_body_u8<true>(P, tile, grp, smem);
+    tile_body_u8<RING>(P, tile, grp, smem);
+  } else if constexpr (F == kProd) {
+    static_assert(std::is_same<TIn, float>::value, "producer wavefronts carry FP32 input");
+    tile_body_prod<RING>(P, tile, grp, smem);
+  } else if constexpr (F == kX4) {
+    tile_body_impl<TIn, RING, true>(P, tile, grp, smem);
+  } else if constexpr (F == kAny && std::is_same<TIn, float>::value) {
+    if (P.x4)
+      tile_body_impl<TIn, RING, true>(P, tile, grp, smem);
     else
-      tile_body_u8<false>(P, tile, grp, smem);
-  } else if (std::is_same<TIn, float>::value && P.nprod > 0) {
-    if (P.in.ring_len > 0)
-      tile_body_prod<true>(P, tile, grp, smem);
-    else
-      tile_body_prod<false>(P, tile, grp, smem);
+      tile_body_impl<TIn, RING, false>(P, tile, grp, smem);
   } else {
-    if (P.in.ring_len > 0)
-      tile_body_impl<TIn, true>(P, tile, grp, smem);
-    else
-      tile_body_impl<TIn, false>(P, tile, grp, smem);
+    tile_body_impl<TIn, RING, false>(P, tile, grp, smem);
   }
+}
+
+template <typename TIn, int F>
+__device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int grp, float* smem) {
+  if (P.in.ring_len > 0)
+    tile_body_ring<TIn, true, F>(P, tile, grp, smem);
+  else
+    tile_body_ring<TIn, false, F>(P, tile, grp, smem);
 }
 
 // Plain launch: one work unit per workgroup; each XCD (workgroups lin, lin + 8, ...)
 // takes a contiguous run of units, tile-major, so the DM groups of a tile share L2.
-template <typename TIn>
+template <typename TIn, int F>
 __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
   extern __shared__ __align__(16) float smem[];
   const int64_t lin = blockIdx.x;
@@ -722,7 +735,7 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
   if (item >= P.nitems) return;  // uniform for the workgroup, before any barrier
   const int64_t tile = item / P.ngroups;
   const int grp = (int)(item - tile * P.ngroups);
-  tile_body<TIn>(P, tile, grp, smem);
+  tile_body<TIn, F>(P, tile, grp, smem);
 }
 
 // Batched persistent launch over several plans/inputs. XCD x (workgroups x, x + 8, ...)
@@ -746,7 +759,7 @@ __device__ __forceinline__ KParams load_params(const KParams* items, int i) {
   return P;
 }
 
-template <typename TIn>
+template <typename TIn, int F>
 __global__ __launch_bounds__(kMaxThreads) void dedisp_batch(const KParams* items, const int64_t* start, int nitems) {
   extern __shared__ __align__(16) float smem[];
   const int x = blockIdx.x & 7;
@@ -761,7 +774,7 @@ __global__ __launch_bounds__(kMaxThreads) void dedisp_batch(const KParams* items
     const int64_t tl = local / P.ngroups;
     const int grp = (int)(local - tl * P.ngroups);
     block_barrier();  // the previous unit's LDS reads are done before new DMAs land
-    tile_body<TIn>(P, x + 8 * tl, grp, smem);
+    tile_body<TIn, F>(P, x + 8 * tl, grp, smem);
   }
 }
 
@@ -916,10 +929,25 @@ __global__ __launch_bounds__(256) void ring_append(const TIn* __restrict__ blk, 
 
 using KernFn = void (*)(KParams);
 
-KernFn pick_kernel(int dtype) {
-  if (dtype == DD_F32) return dedisp_tile<float>;
-  if (dtype == DD_F16) return dedisp_tile<__half>;
-  return dedisp_tile<uint8_t>;
+KernFn pick_kernel(int dtype, const KParams& P) {
+  if (dtype == DD_F32)
+    return P.nprod > 0 ? dedisp_tile<float, kProd> : P.x4 ? dedisp_tile<float, kX4> : dedisp_tile<float, kX1>;
+  if (dtype == DD_F16) return dedisp_tile<__half, kX1>;
+  return dedisp_tile<uint8_t, kX1>;
+}
+
+using BatchFn = void (*)(const KParams*, const int64_t*, int);
+
+// form: kX1, kX4 or kProd when every item has it, else kAny (FP32 items that differ in x4)
+BatchFn pick_batch_kernel(int dtype, int form) {
+  if (dtype == DD_F32) {
+    if (form == kProd) return dedisp_batch<float, kProd>;
+    if (form == kX4) return dedisp_batch<float, kX4>;
+    if (form == kX1) return dedisp_batch<float, kX1>;
+    return dedisp_batch<float, kAny>;
+  }
+  if (dtype == DD_F16) return dedisp_batch<__half, kX1>;
+  return dedisp_batch<uint8_t, kX1>;
 }
 
 int hip_fail(hipError_t e, const char* what) {
@@ -1040,7 +1068,7 @@ int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int
   dd::Launch g;
   int rc = build_params(p, in, d_table, nout, o, ws, l, &P, &g);
   if (rc) return rc;
-  KernFn k = pick_kernel(p->dtype);
+  KernFn k = pick_kernel(p->dtype, P);
   rc = set_lds((const void*)k, g.lds);
   if (rc) return rc;
   rc = copy_tail(P, st);
@@ -1283,8 +1311,12 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(KParams), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(dS, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch descriptors)");
-  void (*k)(const KParams*, const int64_t*, int) =
-      dtype == DD_F32 ? dedisp_batch<float> : dtype == DD_F16 ? dedisp_batch<__half> : dedisp_batch<uint8_t>;
+  int form = -1;
+  for (int32_t i = 0; i < n; ++i) {
+    const int f = P[i].nprod > 0 ? kProd : P[i].x4 ? kX4 : kX1;
+    form = form < 0 || form == f ? f : kAny;  // producer counts already agree across items
+  }
+  BatchFn k = pick_batch_kernel(dtype, form);
   rc = set_lds((const void*)k, lds);
   if (rc) return rc;
   int dev = 0, ncu = 256;
