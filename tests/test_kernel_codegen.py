@@ -48,10 +48,17 @@ def test_no_packed_fp32_and_no_scratch(device_code):
         assert int(m.group(1)) == 0
 
 
-def test_inner_loop_has_no_scalar_work_per_trial(device_code):
+# FP32 kernels by DMA form: 16-byte DMAs from every wavefront, and producer wavefronts
+FP32_KERNELS = ["_ZN12_GLOBAL__N_111dedisp_tileIfLi1EEEvNS_7KParamsE",
+                "_ZN12_GLOBAL__N_111dedisp_tileIfLi2EEEvNS_7KParamsE"]
+
+
+@pytest.mark.parametrize("sym", FP32_KERNELS)
+def test_inner_loop_has_no_scalar_work_per_trial(device_code, sym):
     """Per channel each wavefront does 8 trials x (1 address add + 2 ds_read_b128 + 8 adds)."""
     asm, _ = device_code
-    body = asm.split("_ZN12_GLOBAL__N_111dedisp_tileIfEEvNS_7KParamsE:", 1)[1].split("s_endpgm", 1)[0]
+    assert sym + ":" in asm
+    body = asm.split(sym + ":", 1)[1].split("s_endpgm", 1)[0]
     n_b128 = len(re.findall(r"ds_read_b128", body))
     n_add = len(re.findall(r"v_add_f32_e32", body))
     assert n_b128 >= 16 and n_add >= 64
