@@ -289,7 +289,7 @@ def main():
         "config": {"workload": "plain brute-force dedispersion, full size: FP32 1024 ch 408-428 MHz, "
                                "tsamp 51.2 us, nsamp 2^20, 2048 DMs 0-204.7 step 0.1, stats + 6-sigma candidates",
                    "nchan": beam.nchan, "nsamp": nsamp, "ndm": beam.ndm, "nout": nout,
-                   "tiles": list(plan.tiles), "candidates_found": n_found},
+                   "tiles": list(plan.tiles), "producer_waves": plan.producer_waves, "candidates_found": n_found},
         "real_time_factor": round(nout * beam.tsamp_s / (ms_step * 1e-3), 2),
         "roofline": roof,
     }

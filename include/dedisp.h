@@ -77,9 +77,11 @@ typedef struct dd_tuning {
   int32_t chan_stage;         /* channels per LDS stage (0..8; without a producer rounded
                                  down to a divisor of waves; 0 = automatic) */
   int32_t producer_waves;     /* wavefronts that only move input into LDS, FP32 input only:
-                                 0 or -1 none (every wavefront issues its share of the DMAs),
-                                 1 or 2 (waves + producer_waves <= 8; DD_ERR_UNSUPPORTED when
-                                 a group's channel windows exceed 1024 words) */
+                                 0 automatic (two for FP32 input when one DM group's channel
+                                 windows fit 1024 words and waves allows, else none), -1 none
+                                 (every wavefront issues its share of the DMAs), 1..4
+                                 (waves + producer_waves <= 8; DD_ERR_UNSUPPORTED when the
+                                 windows do not fit) */
 } dd_tuning;
 
 typedef struct dd_plan_info {

@@ -23,7 +23,7 @@ bool valid_tiles(const dd::Tiles& t) {
     for (int x : xs) if (v == x) return true;
     return false;
   };
-  return t.g == 8 && t.w >= 0 && t.w <= 8 && t.s == 8 && t.cc >= 0 && t.cc <= 8 && in(t.pw, {-1, 0, 1, 2}) &&
+  return t.g == 8 && t.w >= 0 && t.w <= 8 && t.s == 8 && t.cc >= 0 && t.cc <= 8 && in(t.pw, {-1, 0, 1, 2, 3, 4}) &&
          !(t.pw > 0 && t.w + t.pw > 8);
 }
 
@@ -176,9 +176,9 @@ Launch choose_launch_prod(int32_t max_span, int nchan, int cs_req, int64_t lds_c
     while (nb > 2 && (int64_t)(nb - 1) * ndw > 63) --nb;
     if (nb < 2 || ndw > 63) continue;
     if (cs_req > 0 && best_score >= 0) break;
-    // a stage of slack for the DMAs (three or more stages), then the most channels in
-    // flight, then the fewest barriers
-    const int64_t score = (nb >= 3 ? (int64_t)1 << 20 : 0) + (int64_t)nb * cs * 16 + cs;
+    // the fewest barriers, then the deepest ring: the producers keep their DMAs ahead of
+    // the computing wavefronts, so a double buffer of wide stages measured fastest
+    const int64_t score = (int64_t)cs * 64 + nb;
     if (score > best_score) {
       best_score = score;
       best.L = (int)L;
@@ -270,28 +270,30 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   }
   p->maxdelay = (int32_t)maxd;
 
-  // DM trials per workgroup: 8 per wavefront, as many wavefronts as keep the LDS ring
-  // at least 8 channels deep (unless the caller fixed the count). Producer wavefronts
-  // only when asked for: with every wavefront issuing its share, more DMAs are in flight
-  // per CU (at most 63 per wavefront), which measured at least as fast on the full FP32
-  // workload.
+  // FP32 input: by default two producer wavefronts issue every LDS DMA beside six
+  // computing ones (the fastest split measured on the full FP32 workload), when one DM
+  // group's channel windows fit their 16-byte DMAs. Otherwise, and for other input:
+  // 8 DM trials per wavefront, as many wavefronts as keep the LDS ring at least 8
+  // channels deep (unless the caller fixed the count).
   int32_t span = 0;
   dd::Launch lg{};
   bool placed = false;
-  if (in_dtype == DD_F32 && t.pw > 0) {
+  const int npw = t.pw > 0 ? t.pw : (t.pw == 0 && in_dtype == DD_F32 && t.w + 2 <= 8) ? 2 : 0;
+  if (in_dtype == DD_F32 && npw > 0) {
     const int wp_opts[5] = {6, 4, 3, 2, 1};
     for (int oi = 0; oi < 5 && !placed; ++oi) {
-      const int nw = t.w ? t.w : std::min(wp_opts[oi], 8 - t.pw);
+      const int nw = t.w ? t.w : std::min(wp_opts[oi], 8 - npw);
       const int32_t sp = compute_span(p->delays, nchan, ndm, t.g * nw);
-      const dd::Launch l = dd::choose_launch_prod(sp, nchan, t.cc, dd::kLdsBytes, t.pw);
+      const dd::Launch l = dd::choose_launch_prod(sp, nchan, t.cc, dd::kLdsBytes, npw);
       if (l.nb >= 2) t.w = nw, span = sp, lg = l, placed = true;  // the most wavefronts that fit
       if (t.w) break;
     }
-    if (!placed) {
+    if (!placed && t.pw > 0) {
       delete p;
       return dd::fail(DD_ERR_UNSUPPORTED, "one DM group's windows do not fit the producer wavefronts' "
                                           "16-byte DMAs; use fewer DMs per workgroup or no producer");
     }
+    if (!placed && !(tuning && tuning->waves)) t.w = 0;  // automatic: fall back to the other form
   }
   const int w_opts[4] = {8, 4, 2, 1};
   for (int oi = 0; oi < 4 && !placed; ++oi) {

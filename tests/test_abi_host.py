@@ -193,9 +193,14 @@ def test_producer_wavefront_plans(lib):
     """
     freq = fbsynth.channel_freqs(428.0, 20 / 1024, 1024)
     dm = fbsynth.dm_trials(0, 0.1, 2048)
-    plain = _launch_ok(lib, freq, dm, 51.2e-6)
-    assert plain.producer_waves == 0 and plain.waves == 8  # the default issues from every wavefront
-    for pw in (1, 2):
+    auto = _launch_ok(lib, freq, dm, 51.2e-6)
+    assert (auto.waves, auto.producer_waves, auto.launch_stage, auto.launch_ring) == (6, 2, 6, 2)
+    plain = _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 0, 8, 0, -1))
+    assert plain.producer_waves == 0 and plain.waves == 8  # every wavefront issues its share
+    assert _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 8, 8, 0, 0)).producer_waves == 0  # no room beside 8
+    for dt in (1, 2):
+        assert _launch_ok(lib, freq, dm, 51.2e-6, dt).producer_waves == 0
+    for pw in (1, 2, 3, 4):
         info = _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 0, 8, 0, pw))
         assert info.producer_waves == pw and info.waves + pw <= 8
         assert info.launch_stage % pw == 0 and info.launch_buf % 64 == 0 and info.launch_buf // 64 <= 16
@@ -206,7 +211,7 @@ def test_producer_wavefront_plans(lib):
     # explicit shapes
     info = _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 6, 8, 6, 2))
     assert (info.waves, info.producer_waves, info.launch_stage, info.launch_ring) == (6, 2, 6, 2)
-    for bad in [(8, 7, 8, 0, 2), (8, 8, 8, 0, 1), (8, 0, 8, 0, 3)]:
+    for bad in [(8, 7, 8, 0, 2), (8, 8, 8, 0, 1), (8, 5, 8, 0, 4), (8, 0, 8, 0, 5)]:
         rc, _ = _create(lib, freq, dm, 51.2e-6, 0, bad)
         assert rc == lib_mod.DD_ERR_UNSUPPORTED, bad
     for dt in (1, 2):  # FP16 and u8 input take no producer
@@ -215,7 +220,9 @@ def test_producer_wavefront_plans(lib):
     # one channel, two producers: the stage repeats the channel for the second producer
     info = _launch_ok(lib, [400.0], [0.0, 1.0], 51.2e-6, 0, (8, 0, 8, 0, 2))
     assert info.producer_waves == 2 and info.launch_stage == 2
-    # windows wider than 1024 words cannot go through the 16 per-lane descriptors
-    rc, _ = _create(lib, fbsynth.channel_freqs(428.0, 3.75, 16), fbsynth.dm_trials(0, 2.0, 64), 51.2e-6, 0,
-                    (8, 0, 8, 0, 1))
+    # windows wider than 1024 words cannot go through the 16 per-lane descriptors: an
+    # explicit request fails, the automatic choice falls back to every wavefront issuing
+    wide_f, wide_dm = fbsynth.channel_freqs(428.0, 3.75, 16), fbsynth.dm_trials(0, 2.0, 64)
+    rc, _ = _create(lib, wide_f, wide_dm, 51.2e-6, 0, (8, 0, 8, 0, 1))
     assert rc == lib_mod.DD_ERR_UNSUPPORTED
+    assert _launch_ok(lib, wide_f, wide_dm, 51.2e-6).producer_waves == 0

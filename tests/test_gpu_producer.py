@@ -1,5 +1,5 @@
-"""FP32 with producer wavefronts (opt-in tuning): one or two wavefronts issue every LDS
-DMA while the others only compute. Results must equal the oracle to the FP32 tolerance on
+"""FP32 with producer wavefronts (the default for FP32 input, two of them; here also one):
+these wavefronts issue every LDS DMA while the others only compute. Results must equal the oracle to the FP32 tolerance on
 the edge shapes, on ragged stream pushes (ring input), and in a batched launch, where they
 must also equal the plan's own single calls bit for bit. Each case prints its shape first.
 """
