@@ -648,13 +648,50 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
   const int* lds_i = reinterpret_cast<const int*>(smem);
   const unsigned lane16 = 16u * (unsigned)lane;
   const int offw = kCopies * P.L + w * kG;  // this wavefront's 8 offsets inside a slot
+  const int slot_bytes = 4 * (kCopies * P.L + 64);
+  // A channel's trials are read and added in two halves (trials 0-3, 4-7): the next
+  // channel's first half is read while this channel's second half is added, so eight
+  // LDS reads stay in flight during the adds; the trial offsets are read two channels
+  // ahead. Each sum still takes its channels in order.
+  auto read_half = [&](const char* cb, const int4 o, uint4 (&v)[kG]) {
+    const int off[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint4* a = reinterpret_cast<const uint4*>(cb + off[t]);
+      v[2 * t] = a[0];
+      v[2 * t + 1] = a[64];
+    }
+  };
+  auto add_half = [&](const uint4 (&v)[kG], int g0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t x[8] = {v[2 * t].x,     v[2 * t].y,     v[2 * t].z,     v[2 * t].w,
+                             v[2 * t + 1].x, v[2 * t + 1].y, v[2 * t + 1].z, v[2 * t + 1].w};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) sub[g0 + t][s] += __uint_as_float(x[s]);
+    }
+    // the half's sums exist before any later LDS read issues: the next reads then reuse
+    // these registers instead of taking a second set
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      asm volatile("" : "+v"(sub[g0 + t][0]), "+v"(sub[g0 + t][1]), "+v"(sub[g0 + t][2]), "+v"(sub[g0 + t][3]),
+                   "+v"(sub[g0 + t][4]), "+v"(sub[g0 + t][5]), "+v"(sub[g0 + t][6]), "+v"(sub[g0 + t][7])
+                   :
+                   : "memory");
+  };
   for (int st = 0; st < P.nstages; ++st) {
     block_barrier();
     const int buf = st % P.nb;
     const int n_here = min(P.cs, P.nchan - st * P.cs);
+    const char* cb0 = reinterpret_cast<const char*>(lds_i + slot_word(P, buf, 0)) + lane16;
     const int4* op = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, 0) + offw);
-    int4 o0 = op[0], o1 = op[1];
-    for (int cc = 0; cc < n_here; ++cc) {
+    const int last = n_here - 1;
+    auto offsets = [&](int cc, int4& a, int4& b) {  // offsets of stage channel min(cc, last)
+      const int4* q = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, min(cc, last)) + offw);
+      a = q[0];
+      b = q[1];
+    };
+    auto fold = [&](int cc) {
       const int c = st * P.cs + cc;
       if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
 #pragma unroll
@@ -662,28 +699,30 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
 #pragma unroll
           for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
       }
-      const int off[kG] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
-      const char* cb = reinterpret_cast<const char*>(lds_i + slot_word(P, buf, cc)) + lane16;
-      uint4 v[2 * kG];
-#pragma unroll
-      for (int g = 0; g < kG; ++g) {
-        const uint4* a = reinterpret_cast<const uint4*>(cb + off[g]);
-        v[2 * g] = a[0];
-        v[2 * g + 1] = a[64];
-      }
-      if (cc + 1 < n_here) {
-        const int4* np = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, cc + 1) + offw);
-        o0 = np[0];
-        o1 = np[1];
-      }
-#pragma unroll
-      for (int g = 0; g < kG; ++g) {
-        const uint32_t x[8] = {v[2 * g].x,     v[2 * g].y,     v[2 * g].z,     v[2 * g].w,
-                               v[2 * g + 1].x, v[2 * g + 1].y, v[2 * g + 1].z, v[2 * g + 1].w};
-#pragma unroll
-        for (int s = 0; s < 8; ++s) sub[g][s] += __uint_as_float(x[s]);
-      }
+    };
+    int4 oa, ob, na, nb;  // offsets of the channel being read, of the next one
+    offsets(0, oa, ob);
+    uint4 va[kG], vb[kG];
+    read_half(cb0, oa, va);
+    offsets(1, na, nb);
+    read_half(cb0, ob, vb);
+    // every iteration issues the same LDS reads (no branch around them), so each wait
+    // counts exactly the reads issued after the data it needs; the last channel is peeled
+    for (int cc = 0; cc < last; ++cc) {
+      fold(cc);
+      const char* cbn = cb0 + (cc + 1) * slot_bytes;
+      int4 na2, nb2;
+      add_half(va, 0);
+      read_half(cbn, na, va);
+      offsets(cc + 2, na2, nb2);
+      add_half(vb, 4);
+      read_half(cbn, nb, vb);
+      na = na2;
+      nb = nb2;
     }
+    fold(last);
+    add_half(va, 0);
+    add_half(vb, 4);
   }
 #pragma unroll
   for (int g = 0; g < kG; ++g)
