@@ -240,7 +240,10 @@ __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, un
     static_assert(EB == 4, "16-byte DMAs carry FP32 input");
     {
       const int nch = P.L >> 6;
-      const int njx = P.nd - 1;
+      int njx = P.nd - 1;
+      // opaque per call: the 16 tests j < njx stay scalar compares here instead of being
+      // hoisted out of the stage loop as 16 live SGPR-pair masks
+      asm volatile("" : "+s"(njx));
       // the window's last sample is first + L + 2 (copy 3, word L - 1)
       if (RING || first + P.L + 2 <= nlim) {
 #pragma unroll
