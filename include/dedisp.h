@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define DD_VERSION_MAJOR 1
-#define DD_VERSION_MINOR 0
+#define DD_VERSION_MINOR 1  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves */
 #define DD_CHAN_BLOCK 32
 
 /* Status codes. */

@@ -7,4 +7,4 @@ streams.
 from ._lib import LibraryMissing, DedispError, load as load_library  # noqa: F401
 from .api import Plan, Stream, Result, CAND_DTYPE, batch_dedisperse  # noqa: F401
 
-__version__ = "1.0"
+__version__ = "1.1"

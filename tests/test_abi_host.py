@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
         assert n in lib_mod.SIGNATURES, n
-    assert lib.dd_version().decode() == "1.0"
+    assert lib.dd_version().decode() == "1.1"
 
 
 def _create(lib, freq, dm, tsamp, dtype=0, tuning=None):
