@@ -4,11 +4,14 @@
 //   dedisp_tile    Eq. bruteEquation over one (DM group, time tile) per workgroup.
 //                  The channel vectors a group needs (Eq. channelDispersionEquation:
 //                  tile length plus the in-group delay spread) reach LDS by DMA through
-//                  a ring of stages and are shared by every wavefront of the workgroup;
-//                  each wavefront accumulates its own DM trials in VGPRs. Per-trial
+//                  a ring of stages and are shared by every computing wavefront of the
+//                  workgroup; each accumulates its own DM trials in VGPRs. Per-trial
 //                  delays arrive as precomputed LDS offsets with the data. 16/32-bit
 //                  input is staged as 32-bit words, 8-bit input as bytes (own tile
-//                  body). The epilogue writes the tile and its FP64 statistics partials.
+//                  body). One instantiation per DMA form: 4-byte DMAs, 16-byte DMAs
+//                  issued by every wavefront, or producer wavefronts that issue them
+//                  all (the FP32 default). The epilogue writes the tile and its FP64
+//                  statistics partials.
 //   dedisp_batch   the same tile bodies in one persistent launch over many inputs.
 //   stats_finalize per-series mean and standard deviation from the FP64 partial sums
 //                  (sum x, sum x^2) that dedisp_tile writes per 512-sample tile with a
@@ -89,7 +92,7 @@ struct KParams {
   int nstages;  // ceil(nchan / cs)
   int x4;       // FP32 input: copies arrive by 16-byte DMAs (nd counts those)
   int nw;       // computing wavefronts (8 DM trials each)
-  int nprod;    // wavefronts after those that only issue DMAs (0, 1 or 2)
+  int nprod;    // wavefronts after those that only issue DMAs (0: none, else 1..4)
   int ndw;      // DMA instructions per issuing wavefront per stage (the vmcnt unit)
   // 8-bit linear input: a channel window that would read past the end of the input
   // (byte in_bytes of the whole [nchan][row_stride] array) reads from `tail`, a copy of
@@ -600,16 +603,16 @@ __device__ __forceinline__ void tile_body_u8(const KParams& P, int64_t tile, int
   store_tile(P, facc, dw, t0, tile, lane);
 }
 
-// ------------------------------------------------------------------ FP32 with a producer
+// ------------------------------------------------------------------ FP32 with producers
 //
 // Wavefronts nw .. nw + nprod - 1 issue every DMA of every stage, whole channels in stage
 // order (producer i takes stage channels i, i + nprod, ...: the four copies as L/64
 // 16-byte DMAs, then the trial offsets), and wait for them; wavefronts 0 .. nw-1 only
 // compute. The ring keeps at most 63 DMAs per producer in flight, so a producer never
-// stalls on its own vmcnt when it issues. All of them meet at one barrier per stage: before it
-// stage st has landed and stage st - 1 has been read, after it the producer refills the
-// slot of stage st - 1 with stage st + nb - 1. Issuing waits for the DMA path (about
-// 60 bytes per clock per CU), and here only the producer waits, while the computing
+// stalls on its own vmcnt when it issues. All of them meet at one barrier per stage:
+// before it stage st has landed and stage st - 1 has been read, after it the producers
+// refill the slot of stage st - 1 with stage st + nb - 1. A wavefront that issues DMAs
+// stalls until the DMA path takes them; here only the producers do, while the computing
 // wavefronts keep the LDS busy. The sums are those of the all-wavefront form: same
 // offsets, same channel order, same DD_CHAN_BLOCK folding.
 template <bool RING>
