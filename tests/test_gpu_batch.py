@@ -103,3 +103,34 @@ def test_batched_stream_windows_equal_push(torch, dd):
             assert g.t0 == r.t0
             np.testing.assert_array_equal(g.out.cpu().numpy(), r.out.cpu().numpy())
             np.testing.assert_array_equal(g.candidates(), r.candidates())
+
+
+def test_batch_mixed_dma_forms_and_f16(torch, dd):
+    """FP32 items whose plans differ in DMA form (16-byte DMAs for narrow windows, 4-byte
+    DMAs for windows too wide for the 16 descriptors) share one launch through the kernel
+    that picks the form per item; FP16 items batch through their own kernel."""
+    rng = np.random.default_rng(21)
+    shapes = [(64, 0.3125, 128, 0.1, 6000), (16, 3.75, 64, 2.0, 40000)]  # narrow, wide band
+    for dtype in ("f32", "f16"):
+        print(f"case: batch of {dtype} items, narrow and wide-band windows", flush=True)
+        jobs, refs = [], []
+        for nchan, df, ndm, step, nsamp in shapes:
+            freq = fbsynth.channel_freqs(428.0, df, nchan)
+            dm = fbsynth.dm_trials(0.0, step, ndm)
+            x = fbsynth.noise(rng, nchan, nsamp)
+            x = fbsynth.to_f16(x) if dtype == "f16" else x
+            p = dd.Plan(freq, 51.2e-6, dm, dtype=dtype, tuning=(8, 1, 0, -1))
+            jobs.append((p, torch.from_numpy(np.ascontiguousarray(x)).cuda()))
+            refs.append((freq, dm, x))
+        if dtype == "f32":
+            launch = [p.query(x.shape[1])["launch_buf"] for p, x in jobs]
+            assert launch[0] // 64 <= 16 < launch[1] // 64, launch  # one item of each DMA form
+        res = dd.batch_dedisperse(jobs, k_sigma=4.0)
+        torch.cuda.synchronize()
+        for (p, x), r, (freq, dm, xh) in zip(jobs, res, refs):
+            s = p.dedisperse(x, k_sigma=4.0)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(s.out.cpu().numpy(), r.out.cpu().numpy())
+            want = orc.dedisperse(xh, orc.delay_table(freq, dm, 51.2e-6))
+            _, rms = orc.series_stats(want)
+            assert_rows_close(r.out.cpu().numpy(), want, rms, what=f"batch {dtype}")
