@@ -20,6 +20,9 @@ What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
   normalisation of Sec. 3.5 "Signal Post-processing".
 * n-sigma thresholding into (time, DM, intensity) detections, Sec. 3.6
   "Detection and Candidate Selection": every (d, t) with D > mean_d + k*rms_d.
+* Detrending and normalisation, Sec. 3.5 "Signal Post-processing": subtract from each
+  dedispersed series its least-squares line (linear regression over the sample index),
+  then optionally divide by the residual's population standard deviation.
 
 Pins (tests/test_oracle_pins.py): a literal triple loop on tiny inputs; exact
 rational delays (fractions.Fraction) away from ties; the paper's diagonal-DM
@@ -27,7 +30,10 @@ formula (Sec. 6.3, 8300 = 2 * 4150) as the derivative of the delay law; the
 zero-DM row equal to the plain channel sum; linearity; impulse response;
 time-shift equivariance; closed-form statistics; the E1 S/N convention (height
 8/sqrt(1024) gives S/N 8); Gaussian-tail false-alarm counts; the paper's
-op-count convention (138e9 ops/s). No function here is "parity unpinned".
+op-count convention (138e9 ops/s). Detrending (tests/test_oracle_detrend.py): a pure
+line vanishes; the residual satisfies the normal equations; numpy.polyfit's residual;
+invariance under adding a line; unit population RMS after normalisation. No function
+here is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -144,6 +150,32 @@ def series_stats(series: np.ndarray):
     mean = s.mean(axis=1)
     rms = np.sqrt(np.mean((s - mean[:, None]) ** 2, axis=1))
     return mean, rms
+
+
+def detrend(series: np.ndarray, normalise: bool = False):
+    """Detrending and normalisation of Sec. 3.5 "Signal Post-processing", in FP64.
+
+    Each row x_t (t = 0 .. n-1) loses its least-squares line a + b*t: with
+    tbar = (n-1)/2 and S_tt = sum (t - tbar)^2 = n(n^2-1)/12, b = sum (t - tbar) x_t / S_tt
+    and a = mean(x) - b*tbar (a single sample keeps b = 0). With normalise, the residual
+    is divided by its population standard deviation, unless that is 0. Returns (series,
+    rms of the residual per row).
+    """
+    x = np.atleast_2d(np.asarray(series, dtype=np.float64))
+    n = x.shape[1]
+    t = np.arange(n, dtype=np.float64)
+    tbar = (n - 1) / 2.0
+    if n > 1:
+        s_tt = n * (n * n - 1) / 12.0
+        b = ((t - tbar)[None, :] * x).sum(axis=1) / s_tt
+    else:
+        b = np.zeros(x.shape[0])
+    a = x.mean(axis=1) - b * tbar
+    y = x - (a[:, None] + b[:, None] * t[None, :])
+    rms = np.sqrt(np.mean(y * y, axis=1))
+    if normalise:
+        y = np.where(rms[:, None] > 0, y / np.where(rms > 0, rms, 1.0)[:, None], y)
+    return y, rms
 
 
 def candidates(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, k_sigma: float,
