@@ -278,6 +278,23 @@ def main():
             "frac_of_lds_ceiling": round(achieved / LDS_CEILING_TADDS, 4),
             "algorithmic_hbm_gbs": round(algo_bytes / (ms_kernel * 1e-3) / 1e9, 1)}
 
+    # detrending and normalisation of the dedispersed series (Sec. 3.5, downstream of the
+    # step and not part of it): an HBM-bound kernel reading the output twice and writing
+    # it once; algorithmic bytes are one read and one write
+    print("bench: detrend timing", file=sys.stderr, flush=True)
+    _lib.check(lib.dd_detrend(vp(out), beam.ndm, nout, nout, 1, vp(rms), st))
+    e0.record(stream)
+    for _ in range(3):
+        _lib.check(lib.dd_detrend(vp(out), beam.ndm, nout, nout, 1, vp(rms), st))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_dt = e0.elapsed_time(e1) / 3
+    dt_bytes = 2 * beam.ndm * nout * 4
+    detrend = {"kernel": "detrend_rows", "ms": round(ms_dt, 3), "bound": "hbm", "unit": "GB/s",
+               "achieved": round(dt_bytes / (ms_dt * 1e-3) / 1e9, 1), "peak": 8000.0,
+               "frac": round(dt_bytes / (ms_dt * 1e-3) / 1e9 / 8000.0, 4), "algorithmic_bytes": dt_bytes,
+               "bytes_moved": 3 * beam.ndm * nout * 4}
+
     res = {
         "metric": "DM-trial*samples/s",
         "value": beam.ndm * nout / (ms_step * 1e-3),
@@ -292,6 +309,7 @@ def main():
                    "tiles": list(plan.tiles), "producer_waves": plan.producer_waves, "candidates_found": n_found},
         "real_time_factor": round(nout * beam.tsamp_s / (ms_step * 1e-3), 2),
         "roofline": roof,
+        "detrend": detrend,
     }
     if args.copy_probe:
         y = torch.empty_like(x)

@@ -223,6 +223,21 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
 int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_row_stride,
                      int64_t seq, void* stream, int64_t* t0_out, int64_t* nout_out);
 
+/*
+ * Detrending and normalisation of dedispersed series, Ch. 3 Sec. "Signal
+ * Post-processing": each of the nrows series in d_series ([nrows][row_stride] FP32,
+ * device, caller-owned; the first n samples of a row are the series) loses its
+ * least-squares line a + b*t over t = 0..n-1, in place. With normalise != 0 the residual
+ * is then divided by its population standard deviation (a zero deviation leaves the zero
+ * residual). d_rms (device [nrows] FP32, may be NULL) receives each residual's standard
+ * deviation (from FP64 sums of x, x^2 and t*x: sum (x - mean)^2 - b^2 sum (t - tbar)^2).
+ * Sums are FP64 in a fixed order, so results depend on the input only; one sample gives
+ * a zero residual. Enqueued on `stream`. Errors: DD_ERR_INVALID_ARG for a
+ * NULL series, nrows < 1, n < 1 or row_stride < n.
+ */
+int dd_detrend(float* d_series, int64_t nrows, int64_t n, int64_t row_stride, int32_t normalise,
+               float* d_rms, void* stream);
+
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dd_last_error(void);
 

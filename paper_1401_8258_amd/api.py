@@ -321,3 +321,17 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
     for r in results:
         r._keep = keep  # device buffers stay alive until the results are dropped
     return results
+
+
+def detrend(series: torch.Tensor, normalise: bool = True, stream=None) -> torch.Tensor:
+    """Subtract each row's least-squares line in place (dd_detrend, Sec. 3.5 "Signal
+    Post-processing"); with normalise, divide by the residual's population standard
+    deviation. series: [nrows][n] float32 on the device, rows may be strided. Returns the
+    residuals' standard deviations, [nrows] float32 on the device."""
+    if series.dim() != 2 or series.dtype != torch.float32 or not series.is_cuda or series.stride(1) != 1:
+        raise ValueError("series must be a [nrows][n] float32 device tensor, time contiguous")
+    lib = _lib.load()
+    rms = torch.empty(series.shape[0], dtype=torch.float32, device=series.device)
+    check(lib.dd_detrend(_vp(series), int(series.shape[0]), int(series.shape[1]), int(series.stride(0)),
+                         1 if normalise else 0, _vp(rms), _stream(stream)))
+    return rms

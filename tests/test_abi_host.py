@@ -124,6 +124,10 @@ def test_plan_validation_codes(lib):
     assert rc == lib_mod.DD_ERR_INVALID_ARG
     lib.dd_plan_destroy(None)  # null-safe
     lib.dd_stream_destroy(None)
+    # detrending rejects bad shapes before any launch
+    assert lib.dd_detrend(None, 1, 1, 1, 0, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    for nrows, n, stride in [(0, 5, 5), (1, 0, 5), (2, 6, 5)]:
+        assert lib.dd_detrend(C.c_void_p(256), nrows, n, stride, 1, None, None) == lib_mod.DD_ERR_INVALID_ARG
 
 
 def test_query_too_short_and_sizes(lib):
