@@ -27,16 +27,19 @@ def device_code(tmp_path_factory):
     sys.path.insert(0, os.path.join(ROOT, "paper_1401_8258_amd"))
     from paper_1401_8258_amd import build
     d = tmp_path_factory.mktemp("codegen")
-    asm = d / "dedisp.s"
     flags = [f for f in build.FLAGS if f not in ("-shared", "-fPIC")]
-    subprocess.run([HIPCC] + flags + ["--cuda-device-only", "-S", "-o", str(asm),
-                                      os.path.join(CSRC, "dedisp.hip")], check=True, capture_output=True)
-    obj = d / "dedisp.o"
-    subprocess.run([MC, "-triple=amdgcn-amd-amdhsa", "-mcpu=gfx950", "-filetype=obj", "-o", str(obj), str(asm)],
-                   check=True, capture_output=True)
-    dis = subprocess.run([OBJDUMP, "-d", "--mcpu=gfx950", str(obj)], check=True, capture_output=True,
-                         text=True).stdout
-    return asm.read_text(), dis
+    asm_all, dis_all = "", ""
+    for name in ("dedisp", "detrend"):  # every device source of the library
+        asm = d / f"{name}.s"
+        subprocess.run([HIPCC] + flags + ["--cuda-device-only", "-S", "-o", str(asm),
+                                          os.path.join(CSRC, f"{name}.hip")], check=True, capture_output=True)
+        obj = d / f"{name}.o"
+        subprocess.run([MC, "-triple=amdgcn-amd-amdhsa", "-mcpu=gfx950", "-filetype=obj", "-o", str(obj),
+                        str(asm)], check=True, capture_output=True)
+        asm_all += asm.read_text()
+        dis_all += subprocess.run([OBJDUMP, "-d", "--mcpu=gfx950", str(obj)], check=True, capture_output=True,
+                                  text=True).stdout
+    return asm_all, dis_all
 
 
 def test_no_packed_fp32_and_no_scratch(device_code):
