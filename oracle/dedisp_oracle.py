@@ -23,6 +23,9 @@ What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
 * Detrending and normalisation, Sec. 3.5 "Signal Post-processing": subtract from each
   dedispersed series its least-squares line (linear regression over the sample index),
   then optionally divide by the residual's population standard deviation.
+* Boxcar smoothing by successively adding adjacent samples (single-pulse detection,
+  Sec. 2; boxcar templates downfactor the series, Sec. 6): level k holds the sums of
+  2^k consecutive samples over sqrt(2^k), non-overlapping.
 
 Pins (tests/test_oracle_pins.py): a literal triple loop on tiny inputs; exact
 rational delays (fractions.Fraction) away from ties; the paper's diagonal-DM
@@ -33,7 +36,9 @@ time-shift equivariance; closed-form statistics; the E1 S/N convention (height
 op-count convention (138e9 ops/s). Detrending (tests/test_oracle_detrend.py): a pure
 line vanishes; the residual satisfies the normal equations; numpy.polyfit's residual;
 invariance under adding a line; unit population RMS after normalisation. No function
-here is "parity unpinned".
+here is "parity unpinned". Boxcar levels (same file): a constant gives c sqrt(2^k); each
+level is the pairwise sum of the one below over sqrt(2); sums are conserved; a top-hat
+of width 2^m aligned to 2^m peaks at h sqrt(2^m) on level m.
 """
 from __future__ import annotations
 
@@ -176,6 +181,22 @@ def detrend(series: np.ndarray, normalise: bool = False):
     if normalise:
         y = np.where(rms[:, None] > 0, y / np.where(rms > 0, rms, 1.0)[:, None], y)
     return y, rms
+
+
+def boxcar_levels(series: np.ndarray, levels: int):
+    """Smoothing by successively adding adjacent samples (Sec. 2 single-pulse detection;
+    the boxcar templates that downfactor a series, Sec. 6): level k (k = 0 .. levels)
+    holds s_k[j] = sum_{i < 2^k} x[j 2^k + i] / sqrt(2^k) for j < floor(n / 2^k), in FP64,
+    so a normalised series keeps unit variance on every level. Returns a list of arrays
+    [nrows][floor(n / 2^k)].
+    """
+    x = np.atleast_2d(np.asarray(series, dtype=np.float64))
+    out = []
+    for k in range(levels + 1):
+        w = 1 << k
+        m = x.shape[1] // w
+        out.append(x[:, : m * w].reshape(x.shape[0], m, w).sum(axis=2) / math.sqrt(w))
+    return out
 
 
 def candidates(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, k_sigma: float,

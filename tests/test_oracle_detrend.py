@@ -56,3 +56,30 @@ def test_normalised_has_unit_population_rms_and_edge_cases():
     # one sample: the line is the sample itself; zero residual, left as is when normalising
     z1, r1 = orc.detrend(np.array([[5.0], [-2.0]]), normalise=True)
     assert np.all(z1 == 0) and np.all(r1 == 0)
+
+
+def test_boxcar_levels_closed_forms():
+    """Boxcar levels: constant input, the pairwise recursion, conservation of sums and a
+    matched top-hat pulse."""
+    n, K = 1000, 6
+    lv = orc.boxcar_levels(np.full((2, n), 3.0), K)
+    for k in range(K + 1):
+        assert lv[k].shape == (2, n >> k)
+        np.testing.assert_allclose(lv[k], 3.0 * np.sqrt(2.0 ** k), rtol=1e-14)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((3, n))
+    lv = orc.boxcar_levels(x, K)
+    np.testing.assert_array_equal(lv[0], x)
+    for k in range(1, K + 1):
+        m = lv[k].shape[1]
+        prev = lv[k - 1][:, : 2 * m]
+        np.testing.assert_allclose(lv[k], (prev[:, 0::2] + prev[:, 1::2]) / np.sqrt(2.0), rtol=1e-12, atol=1e-12)
+        cover = m << k
+        np.testing.assert_allclose(lv[k].sum(axis=1) * np.sqrt(2.0 ** k), x[:, :cover].sum(axis=1), rtol=1e-10,
+                                   atol=1e-9)
+    for m in range(K + 1):
+        w = 1 << m
+        pulse = np.zeros((1, n))
+        pulse[0, 5 * w: 6 * w] = 2.0
+        lv = orc.boxcar_levels(pulse, K)
+        assert np.isclose(lv[m].max(), 2.0 * np.sqrt(w)) and lv[m].argmax() == 5
