@@ -295,6 +295,26 @@ def main():
                "frac": round(dt_bytes / (ms_dt * 1e-3) / 1e9 / 8000.0, 4), "algorithmic_bytes": dt_bytes,
                "bytes_moved": 3 * beam.ndm * nout * 4}
 
+    # boxcar levels 0..6 of the normalised series (widths 1..64): one read of the series,
+    # one write of all levels (level 0 included)
+    print("bench: boxcar timing", file=sys.stderr, flush=True)
+    offs = [0]
+    for kk in range(7):
+        offs.append(offs[-1] + (nout >> kk))
+    bx = torch.empty((beam.ndm, offs[-1]), dtype=torch.float32, device=out.device)
+    _lib.check(lib.dd_boxcar(vp(out), beam.ndm, nout, nout, 6, vp(bx), offs[-1], st))
+    e0.record(stream)
+    for _ in range(3):
+        _lib.check(lib.dd_boxcar(vp(out), beam.ndm, nout, nout, 6, vp(bx), offs[-1], st))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_bx = e0.elapsed_time(e1) / 3
+    bx_bytes = beam.ndm * nout * 4 + beam.ndm * offs[-1] * 4
+    boxcar = {"kernel": "boxcar_rows", "levels": 6, "ms": round(ms_bx, 3), "bound": "hbm", "unit": "GB/s",
+              "achieved": round(bx_bytes / (ms_bx * 1e-3) / 1e9, 1), "peak": 8000.0,
+              "frac": round(bx_bytes / (ms_bx * 1e-3) / 1e9 / 8000.0, 4), "algorithmic_bytes": bx_bytes}
+    del bx
+
     res = {
         "metric": "DM-trial*samples/s",
         "value": beam.ndm * nout / (ms_step * 1e-3),
@@ -310,6 +330,7 @@ def main():
         "real_time_factor": round(nout * beam.tsamp_s / (ms_step * 1e-3), 2),
         "roofline": roof,
         "detrend": detrend,
+        "boxcar": boxcar,
     }
     if args.copy_probe:
         y = torch.empty_like(x)

@@ -238,6 +238,22 @@ int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t i
 int dd_detrend(float* d_series, int64_t nrows, int64_t n, int64_t row_stride, int32_t normalise,
                float* d_rms, void* stream);
 
+/*
+ * Boxcar levels of series, by successive addition of adjacent samples (Ch. 2 single-pulse
+ * detection: the series is smoothed by adding groups of adjacent samples; Ch. 6: boxcar
+ * templates downfactor the series). For k = 0..levels (levels <= 6: boxcars of 1..64
+ * samples), level k of row r is s_k[j] = (x[j 2^k] + ... + x[j 2^k + 2^k - 1]) / sqrt(2^k)
+ * for j < floor(n / 2^k), summed pairwise in FP32; a normalised series (dd_detrend) keeps
+ * unit variance on every level. d_series: [nrows][row_stride] FP32 (first n samples);
+ * d_out: [nrows][out_row_stride] FP32, levels one after another, level k at offset
+ * sum_{i<k} floor(n / 2^i); out_row_stride must hold all levels. Both device,
+ * caller-owned; enqueued on `stream`. Errors: DD_ERR_INVALID_ARG for NULL pointers,
+ * nrows < 1, n < 1, row_stride < n, levels outside 0..6 or a short output row;
+ * DD_ERR_UNSUPPORTED for more than 65535 rows.
+ */
+int dd_boxcar(const float* d_series, int64_t nrows, int64_t n, int64_t row_stride, int32_t levels,
+              float* d_out, int64_t out_row_stride, void* stream);
+
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dd_last_error(void);
 

@@ -69,6 +69,7 @@ SIGNATURES = {
     "dd_batch_query": (C.c_int, [C.POINTER(BatchItem), _I32, C.POINTER(_I64)]),
     "dd_batch_dedisperse": (C.c_int, [C.POINTER(BatchItem), _I32, _P, _I64, _P]),
     "dd_detrend": (C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P]),
+    "dd_boxcar": (C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _I64, _P]),
     "dd_last_error": (C.c_char_p, []),
     "dd_version": (C.c_char_p, []),
 }

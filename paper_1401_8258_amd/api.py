@@ -335,3 +335,25 @@ def detrend(series: torch.Tensor, normalise: bool = True, stream=None) -> torch.
     check(lib.dd_detrend(_vp(series), int(series.shape[0]), int(series.shape[1]), int(series.stride(0)),
                          1 if normalise else 0, _vp(rms), _stream(stream)))
     return rms
+
+
+def boxcar_offsets(n: int, levels: int):
+    """Start of each level inside a dd_boxcar output row, and the row length."""
+    offs = [0]
+    for k in range(levels + 1):
+        offs.append(offs[-1] + (n >> k))
+    return offs
+
+
+def boxcar(series: torch.Tensor, levels: int = 6, stream=None):
+    """Boxcar levels 0..levels of each row (dd_boxcar): level k holds the sums of 2^k
+    adjacent samples over sqrt(2^k). Returns a list of [nrows][n >> k] views of one
+    device buffer."""
+    if series.dim() != 2 or series.dtype != torch.float32 or not series.is_cuda or series.stride(1) != 1:
+        raise ValueError("series must be a [nrows][n] float32 device tensor, time contiguous")
+    nrows, n = int(series.shape[0]), int(series.shape[1])
+    offs = boxcar_offsets(n, levels)
+    out = torch.empty((nrows, offs[-1]), dtype=torch.float32, device=series.device)
+    check(_lib.load().dd_boxcar(_vp(series), nrows, n, int(series.stride(0)), int(levels), _vp(out), offs[-1],
+                                _stream(stream)))
+    return [out[:, offs[k]:offs[k + 1]] for k in range(levels + 1)]

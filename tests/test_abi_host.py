@@ -128,6 +128,11 @@ def test_plan_validation_codes(lib):
     assert lib.dd_detrend(None, 1, 1, 1, 0, None, None) == lib_mod.DD_ERR_INVALID_ARG
     for nrows, n, stride in [(0, 5, 5), (1, 0, 5), (2, 6, 5)]:
         assert lib.dd_detrend(C.c_void_p(256), nrows, n, stride, 1, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    # boxcar levels: bad shapes, levels out of range, an output row too short
+    p256 = C.c_void_p(256)
+    for args in [(None, 1, 8, 8, 2, p256, 100), (p256, 1, 8, 8, 7, p256, 100), (p256, 1, 8, 8, -1, p256, 100),
+                 (p256, 1, 8, 8, 2, p256, 13), (p256, 0, 8, 8, 2, p256, 100), (p256, 1, 8, 7, 2, p256, 100)]:
+        assert lib.dd_boxcar(*args, None) == lib_mod.DD_ERR_INVALID_ARG, args
 
 
 def test_query_too_short_and_sizes(lib):
