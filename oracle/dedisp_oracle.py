@@ -26,6 +26,11 @@ What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
 * Boxcar smoothing by successively adding adjacent samples (single-pulse detection,
   Sec. 2; boxcar templates downfactor the series, Sec. 6): level k holds the sums of
   2^k consecutive samples over sqrt(2^k), non-overlapping.
+* Time binning (Sec. 2 "Direct Dedispersion", Sec. "Computing Larger DMs"): above the
+  diagonal DM (where adjacent channels' delays differ by one sample) the input is
+  downfactored by 2 by summing adjacent samples, again at twice the diagonal, and so on:
+  a DM trial in (2^(k-1) DM_diag, 2^k DM_diag] is dedispersed at factor 2^k, i.e. on the
+  input downfactored k times with sampling time 2^k t_samp.
 
 Pins (tests/test_oracle_pins.py): a literal triple loop on tiny inputs; exact
 rational delays (fractions.Fraction) away from ties; the paper's diagonal-DM
@@ -39,6 +44,11 @@ invariance under adding a line; unit population RMS after normalisation. No func
 here is "parity unpinned". Boxcar levels (same file): a constant gives c sqrt(2^k); each
 level is the pairwise sum of the one below over sqrt(2); sums are conserved; a top-hat
 of width 2^m aligned to 2^m peaks at h sqrt(2^m) on level m.
+Time binning (tests/test_oracle_binning.py): the diagonal DM against the paper's closed
+form dt f0^3 / (8300 df) (Sec. 6) and against a one-sample smear of the bottom channel
+pair; the number of binning stages against the paper's ceil(log2(DM_max / DM_diag)) + 1;
+a ramp's downfactored closed form and conserved sums; an impulse lands at the binned
+index floor(t0 / 2^k) - delay; factor 1 reduces to plain dedispersion.
 """
 from __future__ import annotations
 
@@ -256,3 +266,79 @@ def stream_expected(blocks, delays: np.ndarray):
 def algorithmic_adds(ndm: int, nchan: int, nout: int) -> int:
     """The paper's op convention: one channel-sample add per DM trial (Sec. 3.9, GPU versus FPGA rates)."""
     return int(ndm) * int(nchan) * int(nout)
+
+
+def diagonal_dm(freq_mhz, tsamp_s: float, k_dm: float = K_DM) -> float:
+    """The diagonal DM (Sec. 2 "Direct Dedispersion"): the DM at which the dispersion
+    curve crosses one time sample per channel step. With the channels in frequency order,
+    the delay difference between neighbours a < b is k_DM DM (a^-2 - b^-2) / t_samp
+    samples, largest for the bottom pair of a uniform band; DM_diag is one over the largest
+    per-DM difference. A single channel has no diagonal (infinity). Sec. 6 prints the
+    derivative form of the same limit, dt f0^3 / (8300 df)."""
+    f = np.sort(np.asarray(freq_mhz, dtype=np.float64))
+    if f.size < 2:
+        return math.inf
+    worst = 0.0
+    for a, b in zip(f[:-1], f[1:]):
+        per_dm = (k_dm * (1.0 / (a * a) - 1.0 / (b * b))) / tsamp_s
+        worst = max(worst, per_dm)
+    return math.inf if worst <= 0.0 else 1.0 / worst
+
+
+def binning_factors(freq_mhz, tsamp_s: float, dm, max_log2: int, k_dm: float = K_DM) -> np.ndarray:
+    """log2 of each DM trial's time-binning factor (Sec. 2 time binning): 0 up to the
+    diagonal DM, k for DM in (2^(k-1) DM_diag, 2^k DM_diag], capped at max_log2."""
+    dd = diagonal_dm(freq_mhz, tsamp_s, k_dm)
+    out = np.zeros(len(dm), dtype=np.int32)
+    for i, v in enumerate(np.asarray(dm, dtype=np.float64)):
+        k = 0
+        while k < max_log2 and v > dd * float(1 << k):
+            k += 1
+        out[i] = k
+    return out
+
+
+def binning_segments(freq_mhz, tsamp_s: float, dm, max_log2: int):
+    """Runs of DM trials that share a binning factor, as (log2 factor, d0, d1) with the
+    trials d0 .. d1-1 (DMs are non-decreasing, so each factor is one run)."""
+    f = binning_factors(freq_mhz, tsamp_s, dm, max_log2)
+    segs = []
+    d0 = 0
+    for d in range(1, len(f) + 1):
+        if d == len(f) or f[d] != f[d0]:
+            segs.append((int(f[d0]), d0, d))
+            d0 = d
+    return segs
+
+
+def downfactor(data: np.ndarray) -> np.ndarray:
+    """Downfactor a filterbank in time by 2, summing adjacent samples (Sec. "Computing
+    Larger DMs", step iv): out[c][j] = A[c][2j] + A[c][2j+1] for j < floor(nsamp / 2), in
+    FP64 (u8 codes are summed as raw codes)."""
+    a = np.asarray(data, dtype=np.float64)
+    m = a.shape[1] // 2
+    return a[:, 0:2 * m:2] + a[:, 1:2 * m:2]
+
+
+def dedisperse_binned(data: np.ndarray, freq_mhz, tsamp_s: float, dm, max_log2: int):
+    """Brute-force dedispersion with time binning: each run of DM trials with factor 2^k
+    is dedispersed (Eq. bruteEquation) on the input downfactored k times, with the delay
+    table of sampling time 2^k t_samp. Returns a list of (k, d0, d1, series[d1-d0][nout_k])
+    with nout_k = floor(nsamp / 2^k) - maxshift_k."""
+    dm = np.asarray(dm, dtype=np.float64)
+    level = np.asarray(data, dtype=np.float64)
+    cur = 0
+    res = []
+    for k, d0, d1 in binning_segments(freq_mhz, tsamp_s, dm, max_log2):
+        while cur < k:
+            level = downfactor(level)
+            cur += 1
+        delays = delay_table(freq_mhz, dm[d0:d1], tsamp_s * float(1 << k))
+        res.append((k, d0, d1, dedisperse(level, delays)))
+    return res
+
+
+def binned_adds(segments, nchan: int) -> int:
+    """Algorithmic adds of a binned pass: sum over runs of ndm_k * nchan * nout_k (the
+    downfactoring adds, nchan * nsamp in all, are not counted)."""
+    return sum(int(d1 - d0) * int(nchan) * int(s.shape[1]) for _, d0, d1, s in segments)
