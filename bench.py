@@ -315,6 +315,41 @@ def main():
               "frac": round(bx_bytes / (ms_bx * 1e-3) / 1e9 / 8000.0, 4), "algorithmic_bytes": bx_bytes}
     del bx
 
+    # time binning above the diagonal DM (factor 2^k for DM in (2^(k-1), 2^k] DM_diag, k <= 4):
+    # the downfactored inputs and one plan per run of trials, stats and 6-sigma candidates
+    print("bench: time-binning timing", file=sys.stderr, flush=True)
+    bp = dd.BinnedPlan(beam.freq_mhz, beam.tsamp_s, beam.dm, max_log2=4)
+    for sg in bp.segments:
+        sg.plan.workspace(nsamp >> sg.log2)
+    bp.dedisperse(x, k_sigma=k, cand_cap=cap)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        bp.dedisperse(x, k_sigma=k, cand_cap=cap)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_tb = e0.elapsed_time(e1) / 3
+    dfo = torch.empty((beam.nchan, nsamp // 2), dtype=torch.float32, device=x.device)
+    e0.record(stream)
+    for _ in range(3):
+        _lib.check(lib.dd_downfactor(vp(x), 0, beam.nchan, nsamp, nsamp, vp(dfo), nsamp // 2, st))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_df = e0.elapsed_time(e1) / 3
+    del dfo
+    df_bytes = beam.nchan * nsamp * 4 + beam.nchan * (nsamp // 2) * 4
+    tb_nout = bp.nout(nsamp)
+    time_binning = {
+        "max_log2": 4, "dm_diag": round(bp.dm_diag, 4), "ms": round(ms_tb, 3),
+        "runs": [{"factor": 1 << sg.log2, "ndm": sg.d1 - sg.d0, "nout": n} for sg, n in zip(bp.segments, tb_nout)],
+        "adds": bp.adds(nsamp), "adds_vs_plain": round(bp.adds(nsamp) / adds, 4),
+        "speedup_vs_plain_step": round(ms_step / ms_tb, 3),
+        "dm_trial_samples_per_s_full_res": beam.ndm * nout / (ms_tb * 1e-3),
+        "downfactor": {"kernel": "downfactor_rows", "ms": round(ms_df, 3), "bound": "hbm", "unit": "GB/s",
+                       "achieved": round(df_bytes / (ms_df * 1e-3) / 1e9, 1), "peak": 8000.0,
+                       "frac": round(df_bytes / (ms_df * 1e-3) / 1e9 / 8000.0, 4), "algorithmic_bytes": df_bytes}}
+    del bp
+
     res = {
         "metric": "DM-trial*samples/s",
         "value": beam.ndm * nout / (ms_step * 1e-3),
@@ -331,6 +366,7 @@ def main():
         "roofline": roof,
         "detrend": detrend,
         "boxcar": boxcar,
+        "time_binning": time_binning,
     }
     if args.copy_probe:
         y = torch.empty_like(x)

@@ -47,7 +47,8 @@ extern "C" {
 #endif
 
 #define DD_VERSION_MAJOR 1
-#define DD_VERSION_MINOR 1  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves */
+#define DD_VERSION_MINOR 2  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves;
+                               2: dd_time_binning, dd_downfactor */
 #define DD_CHAN_BLOCK 32
 
 /* Status codes. */
@@ -253,6 +254,41 @@ int dd_detrend(float* d_series, int64_t nrows, int64_t n, int64_t row_stride, in
  */
 int dd_boxcar(const float* d_series, int64_t nrows, int64_t n, int64_t row_stride, int32_t levels,
               float* d_out, int64_t out_row_stride, void* stream);
+
+/*
+ * Time binning above the diagonal DM (Ch. 2 Sec. "Direct Dedispersion": past the DM at
+ * which the dispersion curve crosses one sample per channel, dedisperse at half the
+ * sampling rate, again at twice that DM, and so on; Sec. "Computing Larger DMs" lists the
+ * downfactor-then-dedisperse steps; Ch. 6 gives the same limit as dt f0^3 / (8300 df) and
+ * counts ceil(log2(DM_max / DM_diag)) + 1 stages). Host only, no device memory.
+ *   dm_diag = 1 / max over neighbouring channels a < b (frequency order) of
+ *             (k_DM * (1/(a*a) - 1/(b*b))) / tsamp_s, each double operation rounded once;
+ *             infinity for one channel. Written to *dm_diag_out when it is non-NULL.
+ *   log2_out[d] = 0 for dm[d] <= dm_diag, else the smallest k <= max_log2 with
+ *             dm[d] <= dm_diag * 2^k (max_log2 when none): trial d is dedispersed on the
+ *             input downfactored k times (dd_downfactor) with a plan at sampling time
+ *             2^k tsamp_s. DMs are non-decreasing, so each factor covers one run of trials.
+ * freq_mhz[nchan], dm[ndm] and log2_out[ndm] are host arrays owned by the caller.
+ * Errors: DD_ERR_INVALID_ARG for NULL arrays, nchan or ndm < 1, tsamp_s <= 0, non-finite
+ * or non-positive frequencies, negative, non-finite or decreasing DMs, max_log2 outside
+ * 0..16.
+ */
+int dd_time_binning(const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm, int32_t ndm,
+                    int32_t max_log2, double* dm_diag_out, int32_t* log2_out);
+
+/*
+ * Downfactor a filterbank in time by 2 (Sec. "Computing Larger DMs": sum adjacent
+ * samples): out[c][j] = A[c][2j] + A[c][2j+1] for j < floor(nsamp / 2), one FP32 add per
+ * output after widening (u8 codes and FP16 values sum exactly; FP32 inputs give the
+ * rounded FP32 sum). d_in: [nchan][in_row_stride] of in_dtype (DD_F32, DD_F16 or DD_U8),
+ * nsamp valid per row; d_out: [nchan][out_row_stride] FP32, must not overlap d_in. Both
+ * device, caller-owned; enqueued on `stream`. Repeating the call on its own output
+ * gives the input downfactored 2^k times. Errors: DD_ERR_INVALID_ARG for NULL pointers,
+ * an unknown dtype, nchan < 1, nsamp < 2, in_row_stride < nsamp or out_row_stride <
+ * nsamp / 2; DD_ERR_UNSUPPORTED for more than 65535 channels.
+ */
+int dd_downfactor(const void* d_in, int32_t in_dtype, int64_t nchan, int64_t nsamp, int64_t in_row_stride,
+                  float* d_out, int64_t out_row_stride, void* stream);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dd_last_error(void);

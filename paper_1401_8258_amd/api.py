@@ -357,3 +357,100 @@ def boxcar(series: torch.Tensor, levels: int = 6, stream=None):
     check(_lib.load().dd_boxcar(_vp(series), nrows, n, int(series.stride(0)), int(levels), _vp(out), offs[-1],
                                 _stream(stream)))
     return [out[:, offs[k]:offs[k + 1]] for k in range(levels + 1)]
+
+
+def downfactor(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """Sum adjacent sample pairs of every channel (dd_downfactor; the downfactor step of
+    time binning): [nchan][nsamp] float32/float16/uint8 device tensor, time contiguous ->
+    [nchan][nsamp // 2] float32."""
+    if x.dim() != 2 or x.dtype not in _TORCH_DT or not x.is_cuda or x.stride(1) != 1:
+        raise ValueError("x must be a [nchan][nsamp] float32/float16/uint8 device tensor, time contiguous")
+    nchan, nsamp = int(x.shape[0]), int(x.shape[1])
+    out = torch.empty((nchan, nsamp // 2), dtype=torch.float32, device=x.device)
+    check(_lib.load().dd_downfactor(_vp(x), _TORCH_DT[x.dtype], nchan, nsamp, int(x.stride(0)), _vp(out),
+                                    int(out.stride(0)), _stream(stream)))
+    return out
+
+
+def time_binning(freq_mhz, tsamp_s: float, dm, max_log2: int):
+    """(diagonal DM, log2 binning factor per DM trial) from dd_time_binning."""
+    f = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+    d = np.ascontiguousarray(dm, dtype=np.float64)
+    k = np.empty(d.size, dtype=np.int32)
+    diag = C.c_double()
+    dbl = C.POINTER(C.c_double)
+    check(_lib.load().dd_time_binning(f.ctypes.data_as(dbl), int(f.size), float(tsamp_s), d.ctypes.data_as(dbl),
+                                      int(d.size), int(max_log2), C.byref(diag), k.ctypes.data_as(C.POINTER(C.c_int32))))
+    return float(diag.value), k
+
+
+@dataclasses.dataclass
+class BinnedSegment:
+    log2: int          # this run is dedispersed at 2^log2 times the sampling time
+    d0: int            # first DM trial of the run
+    d1: int            # one past its last trial
+    plan: Plan         # plan over dm[d0:d1] at sampling time 2^log2 * tsamp
+
+
+@dataclasses.dataclass
+class BinnedResult:
+    segments: list     # [(BinnedSegment, Result)]: rows d0..d1-1 at nsamp >> log2 resolution
+
+    def candidates(self) -> Optional[np.ndarray]:
+        """All runs' detections, dm_index global and t in input samples (binned index << log2)."""
+        parts = []
+        for seg, r in self.segments:
+            c = r.candidates()
+            if c is None:
+                return None
+            c = c.copy()
+            c["dm_index"] += seg.d0
+            c["t"] <<= seg.log2
+            parts.append(c)
+        return np.concatenate(parts) if parts else np.empty(0, dtype=CAND_DTYPE)
+
+
+class BinnedPlan:
+    """Brute-force dedispersion with time binning above the diagonal DM (Ch. 2 Sec. "Direct
+    Dedispersion"; Sec. "Computing Larger DMs"): DM trials in (2^(k-1), 2^k] x DM_diag are
+    dedispersed on the input downfactored k times (k <= max_log2), with delays at sampling
+    time 2^k tsamp. Each run of trials is an ordinary plan; runs with k >= 1 take FP32
+    input (the downfactored sums)."""
+
+    def __init__(self, freq_mhz, tsamp_s: float, dm, dtype=torch.float32, max_log2: int = 4, tuning=None):
+        self.freq = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+        self.dm = np.ascontiguousarray(dm, dtype=np.float64)
+        self.tsamp = float(tsamp_s)
+        self.dtype = torch_dtype(dtype)
+        self.max_log2 = int(max_log2)
+        self.dm_diag, self.log2 = time_binning(self.freq, self.tsamp, self.dm, self.max_log2)
+        self.segments = []
+        d0 = 0
+        for d in range(1, self.dm.size + 1):
+            if d == self.dm.size or self.log2[d] != self.log2[d0]:
+                k = int(self.log2[d0])
+                plan = Plan(self.freq, self.tsamp * float(1 << k), self.dm[d0:d], self.dtype if k == 0 else torch.float32,
+                            tuning)
+                self.segments.append(BinnedSegment(k, d0, d, plan))
+                d0 = d
+
+    def nout(self, nsamp: int):
+        """Output samples per run for an nsamp-sample input: (nsamp >> k) - maxdelay_k."""
+        return [(int(nsamp) >> s.log2) - s.plan.maxdelay for s in self.segments]
+
+    def adds(self, nsamp: int) -> int:
+        return sum((s.d1 - s.d0) * s.plan.nchan * n for s, n in zip(self.segments, self.nout(nsamp)))
+
+    def dedisperse(self, x: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True,
+                   stream=None) -> BinnedResult:
+        level, cur, levels = x, 0, [x]
+        out = []
+        for seg in self.segments:
+            while cur < seg.log2:
+                level = downfactor(level, stream)
+                levels.append(level)
+                cur += 1
+            r = seg.plan.dedisperse(level, k_sigma=k_sigma, cand_cap=cand_cap, stats=stats, stream=stream)
+            r._keep = levels  # the downfactored inputs live until the results are dropped
+            out.append((seg, r))
+        return BinnedResult(out)

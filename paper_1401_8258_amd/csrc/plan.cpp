@@ -7,6 +7,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "dd_internal.h"
 
@@ -201,7 +202,7 @@ extern "C" {
 
 const char* dd_last_error(void) { return g_err.c_str(); }
 
-const char* dd_version(void) { return "1.1"; }
+const char* dd_version(void) { return "1.2"; }
 
 int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
                    const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning) {
@@ -383,6 +384,39 @@ int dd_plan_delays(const dd_plan* p, int32_t* host_out) {
   dd::clear_error();
   if (!p || !host_out) return dd::fail(DD_ERR_INVALID_ARG, "plan and host_out must be non-NULL");
   std::memcpy(host_out, p->delays.data(), p->delays.size() * sizeof(int32_t));
+  return DD_OK;
+}
+
+int dd_time_binning(const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm, int32_t ndm,
+                    int32_t max_log2, double* dm_diag_out, int32_t* log2_out) {
+  dd::clear_error();
+  if (!freq_mhz || !dm || !log2_out) return dd::fail(DD_ERR_INVALID_ARG, "freq_mhz, dm and log2_out must be non-NULL");
+  if (nchan < 1 || ndm < 1) return dd::fail(DD_ERR_INVALID_ARG, "nchan and ndm must be >= 1");
+  if (!(tsamp_s > 0.0) || !std::isfinite(tsamp_s)) return dd::fail(DD_ERR_INVALID_ARG, "tsamp must be finite and > 0");
+  if (max_log2 < 0 || max_log2 > 16) return dd::fail(DD_ERR_INVALID_ARG, "max_log2 must be in 0..16");
+  std::vector<double> f(freq_mhz, freq_mhz + nchan);
+  for (double v : f)
+    if (!std::isfinite(v) || !(v > 0.0)) return dd::fail(DD_ERR_INVALID_ARG, "frequencies must be finite and > 0");
+  for (int32_t d = 0; d < ndm; ++d) {
+    if (!std::isfinite(dm[d]) || dm[d] < 0.0) return dd::fail(DD_ERR_INVALID_ARG, "DMs must be finite and >= 0");
+    if (d > 0 && dm[d] < dm[d - 1]) return dd::fail(DD_ERR_INVALID_ARG, "DM trials must be in non-decreasing order");
+  }
+  // Diagonal DM: one over the largest per-DM delay difference (in samples) between
+  // neighbouring channels in frequency order; each double operation rounds once.
+  std::sort(f.begin(), f.end());
+  double worst = 0.0;
+  for (size_t c = 0; c + 1 < f.size(); ++c) {
+    const double a = f[c], b = f[c + 1];
+    const double per_dm = (kDm * (1.0 / (a * a) - 1.0 / (b * b))) / tsamp_s;
+    worst = std::max(worst, per_dm);
+  }
+  const double diag = worst > 0.0 ? 1.0 / worst : std::numeric_limits<double>::infinity();
+  if (dm_diag_out) *dm_diag_out = diag;
+  for (int32_t d = 0; d < ndm; ++d) {
+    int32_t k = 0;
+    while (k < max_log2 && dm[d] > diag * (double)(1 << k)) ++k;
+    log2_out[d] = k;
+  }
   return DD_OK;
 }
 

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
         assert n in lib_mod.SIGNATURES, n
-    assert lib.dd_version().decode() == "1.1"
+    assert lib.dd_version().decode() == "1.2"
 
 
 def _create(lib, freq, dm, tsamp, dtype=0, tuning=None):
@@ -235,3 +235,51 @@ def test_producer_wavefront_plans(lib):
     rc, _ = _create(lib, wide_f, wide_dm, 51.2e-6, 0, (8, 0, 8, 0, 1))
     assert rc == lib_mod.DD_ERR_UNSUPPORTED
     assert _launch_ok(lib, wide_f, wide_dm, 51.2e-6).producer_waves == 0
+
+
+def _binning(lib, freq, tsamp, dms, max_log2):
+    freq = np.ascontiguousarray(freq, dtype=np.float64)
+    dms = np.ascontiguousarray(dms, dtype=np.float64)
+    out = np.full(dms.size, -7, dtype=np.int32)
+    diag = C.c_double()
+    dbl = C.POINTER(C.c_double)
+    rc = lib.dd_time_binning(freq.ctypes.data_as(dbl), int(freq.size), float(tsamp), dms.ctypes.data_as(dbl),
+                             int(dms.size), int(max_log2), C.byref(diag), out.ctypes.data_as(C.POINTER(C.c_int32)))
+    return rc, diag.value, out
+
+
+@pytest.mark.parametrize("f_top,nchan,bw,tsamp,step,ndm,max_log2", [
+    (428.0, 64, 20.0, 51.2e-6, 0.1, 128, 4),
+    (428.0, 1024, 20.0, 51.2e-6, 0.1, 2048, 4),
+    (428.0, 1024, 20.0, 51.2e-6, 0.1, 2048, 2),
+    (180.0, 4096, 60.0, 81.92e-6, 0.05, 4096, 16),
+    (428.0, 256, 20.0, 51.2e-6, 0.2, 700, 0),
+])
+def test_time_binning_matches_oracle(lib, f_top, nchan, bw, tsamp, step, ndm, max_log2):
+    """The planner's diagonal DM and factors equal the oracle's (same FP64 decision)."""
+    freq = fbsynth.channel_freqs(f_top, bw / nchan, nchan)
+    dms = fbsynth.dm_trials(0.0, step, ndm)
+    rc, diag, k = _binning(lib, freq[::-1].copy(), tsamp, dms, max_log2)  # any channel order
+    assert rc == 0
+    assert diag == orc.diagonal_dm(freq, tsamp)
+    np.testing.assert_array_equal(k, orc.binning_factors(freq, tsamp, dms, max_log2))
+    # boundary trials at exactly 2^k DM_diag and one ulp above
+    edge = np.array(sorted({0.0} | {v for j in range(4) for v in (diag * 2 ** j, np.nextafter(diag * 2 ** j, np.inf))}))
+    rc, _, k2 = _binning(lib, freq, tsamp, edge, 10)
+    assert rc == 0
+    np.testing.assert_array_equal(k2, orc.binning_factors(freq, tsamp, edge, 10))
+
+
+def test_time_binning_and_downfactor_arguments(lib):
+    freq = fbsynth.channel_freqs(428.0, 0.3125, 64)
+    assert _binning(lib, [400.0], 1e-4, [0.0, 5.0], 3)[:2] == (0, float("inf"))
+    for f, ts, dms, ml in [(freq, 0.0, [1.0], 2), (freq, 1e-4, [2.0, 1.0], 2), (freq, 1e-4, [-1.0], 2),
+                           (freq, 1e-4, [1.0], 17), (freq, 1e-4, [1.0], -1), ([400.0, float("nan")], 1e-4, [1.0], 2),
+                           ([400.0, 0.0], 1e-4, [1.0], 2)]:
+        assert _binning(lib, f, ts, dms, ml)[0] == lib_mod.DD_ERR_INVALID_ARG, (ts, dms, ml)
+    p256 = C.c_void_p(256)
+    for args in [(None, 0, 4, 8, 8, p256, 4), (p256, 0, 4, 8, 8, None, 4), (p256, 3, 4, 8, 8, p256, 4),
+                 (p256, 0, 0, 8, 8, p256, 4), (p256, 0, 4, 1, 8, p256, 4), (p256, 0, 4, 8, 7, p256, 4),
+                 (p256, 0, 4, 9, 9, p256, 3)]:
+        assert lib.dd_downfactor(*args, None) == lib_mod.DD_ERR_INVALID_ARG, args
+    assert lib.dd_downfactor(p256, 0, 70000, 8, 8, p256, 4, None) == lib_mod.DD_ERR_UNSUPPORTED
