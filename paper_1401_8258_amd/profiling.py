@@ -10,7 +10,9 @@ one with ``--pmc WRITE_SIZE``, each also running one plain device copy of known 
 
 FETCH_SIZE and WRITE_SIZE are KiB per dispatch summed over the L2 channels. Each is
 scaled by bytes / counter of the copy kernel (``__amd_rocclr_copyBuffer``) of the same
-run, which moves ``copy-bytes`` in each direction. The record stores the SHA-256 of the
+run, which moves ``copy-bytes`` in each direction. With ``--largest-grid`` only the
+kernel's dispatches with the largest grid count (the full-size launch, when the same
+command also runs the kernel on smaller inputs). The record stores the SHA-256 of the
 kernel source, so a reader can tell when the kernel has changed since the counters were
 taken.
 """
@@ -33,16 +35,20 @@ def _rows(path: str, counter: str):
     with open(path, newline="") as f:
         for r in csv.DictReader(f):
             if r["Counter_Name"] == counter:
-                yield r["Kernel_Name"], float(r["Counter_Value"])
+                yield r["Kernel_Name"], float(r["Counter_Value"]), int(r.get("Grid_Size") or 0)
 
 
-def _kernel_and_copy(path: str, counter: str, kernel: str):
+def _kernel_and_copy(path: str, counter: str, kernel: str, largest_grid: bool = False):
     ks, cs = [], []
-    for name, v in _rows(path, counter):
+    for name, v, grid in _rows(path, counter):
         if kernel in name:
-            ks.append(v)
+            ks.append((grid, v))
         elif "copyBuffer" in name:
             cs.append(v)
+    if ks and largest_grid:
+        top = max(g for g, _ in ks)
+        ks = [(g, v) for g, v in ks if g == top]
+    ks = [v for _, v in ks]
     if not ks:
         raise SystemExit(f"{path}: no {counter} rows for a kernel named like {kernel!r}")
     if not cs:
@@ -50,9 +56,10 @@ def _kernel_and_copy(path: str, counter: str, kernel: str):
     return ks, max(cs)  # the big copy (the probe); small copies are argument uploads
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, source: str) -> dict:
-    fk, fc = _kernel_and_copy(fetch_csv, "FETCH_SIZE", kernel)
-    wk, wc = _kernel_and_copy(write_csv, "WRITE_SIZE", kernel)
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, source: str,
+            largest_grid: bool = False) -> dict:
+    fk, fc = _kernel_and_copy(fetch_csv, "FETCH_SIZE", kernel, largest_grid)
+    wk, wc = _kernel_and_copy(write_csv, "WRITE_SIZE", kernel, largest_grid)
     f_scale = copy_bytes / (fc * 1024.0)
     w_scale = copy_bytes / (wc * 1024.0)
     fetch = statistics.mean(fk) * 1024.0 * f_scale
@@ -78,8 +85,9 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--source", required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--largest-grid", action="store_true", help="only the dispatches with the largest grid")
     a = ap.parse_args(argv)
-    rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.source)
+    rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.source, a.largest_grid)
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
