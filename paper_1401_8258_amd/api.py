@@ -442,15 +442,24 @@ class BinnedPlan:
         return sum((s.d1 - s.d0) * s.plan.nchan * n for s, n in zip(self.segments, self.nout(nsamp)))
 
     def dedisperse(self, x: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True,
-                   stream=None) -> BinnedResult:
-        level, cur, levels = x, 0, [x]
-        out = []
-        for seg in self.segments:
-            while cur < seg.log2:
-                level = downfactor(level, stream)
-                levels.append(level)
-                cur += 1
-            r = seg.plan.dedisperse(level, k_sigma=k_sigma, cand_cap=cand_cap, stats=stats, stream=stream)
-            r._keep = levels  # the downfactored inputs live until the results are dropped
-            out.append((seg, r))
-        return BinnedResult(out)
+                   stream=None, batched: bool = False) -> BinnedResult:
+        """Every run of trials on its downfactored input. With batched, the runs that share
+        the FP32 input type go through one persistent launch (dd_batch_dedisperse), equal
+        bit for bit to one launch per run."""
+        levels = [x]
+        for _ in range(max(s.log2 for s in self.segments)):
+            levels.append(downfactor(levels[-1], stream))
+        res = [None] * len(self.segments)
+        group = [i for i, s in enumerate(self.segments) if batched and s.plan.dtype == torch.float32]
+        if len(group) > 1:
+            done = batch_dedisperse([(self.segments[i].plan, levels[self.segments[i].log2]) for i in group],
+                                    k_sigma=k_sigma, cand_cap=cand_cap, stats=stats, stream=stream)
+            for i, r in zip(group, done):
+                res[i] = r
+        for i, seg in enumerate(self.segments):
+            if res[i] is None:
+                res[i] = seg.plan.dedisperse(levels[seg.log2], k_sigma=k_sigma, cand_cap=cand_cap, stats=stats,
+                                             stream=stream)
+        for r in res:
+            r._keep = (r._keep, levels)  # the downfactored inputs live until the results are dropped
+        return BinnedResult(list(zip(self.segments, res)))

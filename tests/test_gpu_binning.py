@@ -124,3 +124,18 @@ def test_config2_binned_full_size(torch, dd):
             assert_rows_close(r.out[i:i + 1].cpu().numpy(), want, rms, what=f"run {seg.log2} row {i}")
             assert_stats_close(r.mean[i:i + 1].cpu().numpy(), r.rms[i:i + 1].cpu().numpy(), mean, rms)
             compare_candidates(cands[cands["dm_index"] == i], want, mean, rms, 6.0, row_ids=[i])
+
+
+@pytest.mark.parametrize("dt", ["f32", "u8"])
+def test_binned_batched_equals_per_run(torch, dd, dt):
+    """The runs in one persistent launch equal one launch per run, bit for bit (for u8 the
+    factor-1 run keeps its own launch: the batch needs one input type)."""
+    b = fbsynth.config1()
+    x = torch.from_numpy(np.ascontiguousarray(_stored(b.data, dt))).cuda()
+    bp = dd.BinnedPlan(b.freq_mhz, b.tsamp_s, b.dm, dtype=dt, max_log2=4)
+    a = bp.dedisperse(x, k_sigma=4.0)
+    c = bp.dedisperse(x, k_sigma=4.0, batched=True)
+    torch.cuda.synchronize()
+    for (_, r1), (_, r2) in zip(a.segments, c.segments):
+        assert torch.equal(r1.out, r2.out) and torch.equal(r1.mean, r2.mean) and torch.equal(r1.rms, r2.rms)
+        np.testing.assert_array_equal(r1.candidates(), r2.candidates())
