@@ -31,6 +31,13 @@ What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
   downfactored by 2 by summing adjacent samples, again at twice the diagonal, and so on:
   a DM trial in (2^(k-1) DM_diag, 2^k DM_diag] is dedispersed at factor 2^k, i.e. on the
   input downfactored k times with sampling time 2^k t_samp.
+* RFI mitigation before dedispersion (Sec. 3 "Bandpass Correction", "Channel
+  Thresholding", "Spectrum Thresholding"): the time-averaged bandpass, its least-squares
+  polynomial fit over the channel index and the fit's RMSE; windows of W samples whose
+  mean deviates from the channel's fitted value by more than a threshold are flagged, and
+  each flagged window and its neighbours take the fitted value; then every spectrum whose
+  mean over channels deviates from the fit's mean by more than a threshold takes the
+  fitted bandpass.
 
 Pins (tests/test_oracle_pins.py): a literal triple loop on tiny inputs; exact
 rational delays (fractions.Fraction) away from ties; the paper's diagonal-DM
@@ -49,6 +56,10 @@ form dt f0^3 / (8300 df) (Sec. 6) and against a one-sample smear of the bottom c
 pair; the number of binning stages against the paper's ceil(log2(DM_max / DM_diag)) + 1;
 a ramp's downfactored closed form and conserved sums; an impulse lands at the binned
 index floor(t0 / 2^k) - delay; factor 1 reduces to plain dedispersion.
+RFI mitigation (tests/test_oracle_rfi.py): a polynomial bandpass is fitted exactly with
+zero RMSE; a literal pure-Python loop over windows and spectra on tiny inputs; clean data
+under a high threshold is unchanged; a narrowband burst, a dropout and a broadband spike
+are replaced by the fitted bandpass and nothing else changes.
 """
 from __future__ import annotations
 
@@ -342,3 +353,71 @@ def binned_adds(segments, nchan: int) -> int:
     """Algorithmic adds of a binned pass: sum over runs of ndm_k * nchan * nout_k (the
     downfactoring adds, nchan * nsamp in all, are not counted)."""
     return sum(int(d1 - d0) * int(nchan) * int(s.shape[1]) for _, d0, d1, s in segments)
+
+
+def bandpass_average(data: np.ndarray) -> np.ndarray:
+    """The averaged bandpass (Sec. "Bandpass Correction"): each channel's mean power over
+    the buffer's samples, FP64."""
+    return np.asarray(data, dtype=np.float64).mean(axis=1)
+
+
+def bandpass_fit(avg, order: int):
+    """Least-squares polynomial of the given order fitted to the averaged bandpass over the
+    channel index, mapped to x = 2c/(nchan-1) - 1 (x = 0 for one channel). Returns the
+    fitted bandpass [nchan], the RMSE between fit and average, and the fit's mean over
+    channels. numpy's polynomial least squares is the fitting primitive."""
+    a = np.asarray(avg, dtype=np.float64)
+    n = a.size
+    if order < 0 or order >= n:
+        raise ValueError("need 0 <= order < nchan")
+    x = np.zeros(n) if n == 1 else 2.0 * np.arange(n) / (n - 1) - 1.0
+    coef = np.polynomial.polynomial.polyfit(x, a, order)
+    fit = np.polynomial.polynomial.polyval(x, coef)
+    rmse = float(np.sqrt(np.mean((a - fit) ** 2)))
+    return fit, rmse, float(fit.mean())
+
+
+def channel_clip(data: np.ndarray, fit, threshold: float, window: int):
+    """Channel thresholding (Sec. "Channel Thresholding"): each channel is cut into
+    non-overlapping windows of `window` samples (the last one may be shorter); a window is
+    flagged when its mean differs from the channel's fitted value by more than `threshold`
+    (too high: RFI; too low: lost data). Every flagged window and its two neighbours are
+    replaced by the fitted value. Returns (data as FP64 with replacements, flags[nchan][nwin])."""
+    x = np.array(data, dtype=np.float64)
+    nchan, n = x.shape
+    nwin = -(-n // window)
+    flags = np.zeros((nchan, nwin), dtype=bool)
+    for w in range(nwin):
+        seg = x[:, w * window:(w + 1) * window]
+        flags[:, w] = np.abs(seg.mean(axis=1) - np.asarray(fit)) > threshold
+    spread = flags.copy()
+    spread[:, 1:] |= flags[:, :-1]
+    spread[:, :-1] |= flags[:, 1:]
+    for c in range(nchan):
+        for w in np.nonzero(spread[c])[0]:
+            x[c, w * window:(w + 1) * window] = fit[c]
+    return x, flags
+
+
+def spectrum_clip(data: np.ndarray, fit, fit_mean: float, threshold: float):
+    """Spectrum thresholding (Sec. "Spectrum Thresholding"): a spectrum (all channels at one
+    sample) whose mean over channels differs from the fitted bandpass's mean by more than
+    `threshold` is replaced by the fitted bandpass. Returns (data FP64, flags[nsamp])."""
+    x = np.array(data, dtype=np.float64)
+    m = x.mean(axis=0)
+    flags = np.abs(m - fit_mean) > threshold
+    x[:, flags] = np.asarray(fit, dtype=np.float64)[:, None]
+    return x, flags
+
+
+def rfi_mitigate(data: np.ndarray, order: int, chan_threshold: float, window: int, spec_threshold: float):
+    """The three stages in the paper's order: fit the averaged bandpass, clip channels
+    (when chan_threshold > 0), then clip spectra (when spec_threshold > 0)."""
+    fit, rmse, fit_mean = bandpass_fit(bandpass_average(data), order)
+    x = np.asarray(data, dtype=np.float64)
+    cflags = sflags = None
+    if chan_threshold > 0:
+        x, cflags = channel_clip(x, fit, chan_threshold, window)
+    if spec_threshold > 0:
+        x, sflags = spectrum_clip(x, fit, fit_mean, spec_threshold)
+    return x, fit, rmse, fit_mean, cflags, sflags
