@@ -350,6 +350,45 @@ def main():
                        "frac": round(df_bytes / (ms_df * 1e-3) / 1e9 / 8000.0, 4), "algorithmic_bytes": df_bytes}}
     del bp
 
+    # RFI mitigation before dedispersion (Ch. 3): the averaged bandpass (one read of the
+    # input), then channel thresholding over 256-sample windows and spectrum thresholding,
+    # in place on a copy of the input (the flag pass and the spectrum pass each read it)
+    print("bench: RFI timing", file=sys.stderr, flush=True)
+    xr = x.clone()
+    avg = torch.empty(beam.nchan, dtype=torch.float64, device=x.device)
+    _lib.check(lib.dd_bandpass(vp(xr), beam.nchan, nsamp, nsamp, vp(avg), st))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        _lib.check(lib.dd_bandpass(vp(xr), beam.nchan, nsamp, nsamp, vp(avg), st))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_bp = e0.elapsed_time(e1) / 3
+    fit, rmse_bp, fmean = dd.bandpass_fit(avg.cpu().numpy(), 6)
+    d_fit = torch.from_numpy(fit).cuda()
+    win = 256
+    flg = torch.empty((beam.nchan, -(-nsamp // win)), dtype=torch.int32, device=x.device)
+
+    def clip():
+        _lib.check(lib.dd_rfi_clip(vp(xr), beam.nchan, nsamp, nsamp, vp(d_fit), 0.5, win, vp(flg), fmean, 0.2, st))
+
+    clip()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        clip()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_clip = e0.elapsed_time(e1) / 3
+    in_bytes = beam.nchan * nsamp * 4
+    rfi = {"kernels": "bandpass_rows; chan_flag + chan_apply + spec_clip", "window": win, "order": 6,
+           "chan_threshold": 0.5, "spec_threshold": 0.2,
+           "bandpass_ms": round(ms_bp, 3), "bandpass_gbs": round(in_bytes / (ms_bp * 1e-3) / 1e9, 1),
+           "clip_ms": round(ms_clip, 3),
+           "clip_gbs_two_reads": round(2 * in_bytes / (ms_clip * 1e-3) / 1e9, 1), "peak_gbs": 8000.0,
+           "windows_flagged": int(flg.sum().item())}
+    del xr, flg
+
     res = {
         "metric": "DM-trial*samples/s",
         "value": beam.ndm * nout / (ms_step * 1e-3),
@@ -367,6 +406,7 @@ def main():
         "detrend": detrend,
         "boxcar": boxcar,
         "time_binning": time_binning,
+        "rfi": rfi,
     }
     if args.copy_probe:
         y = torch.empty_like(x)

@@ -48,7 +48,8 @@ extern "C" {
 
 #define DD_VERSION_MAJOR 1
 #define DD_VERSION_MINOR 2  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves;
-                               2: dd_time_binning, dd_downfactor */
+                               2: dd_time_binning, dd_downfactor, dd_bandpass,
+                                  dd_bandpass_fit, dd_rfi_clip */
 #define DD_CHAN_BLOCK 32
 
 /* Status codes. */
@@ -289,6 +290,46 @@ int dd_time_binning(const double* freq_mhz, int32_t nchan, double tsamp_s, const
  */
 int dd_downfactor(const void* d_in, int32_t in_dtype, int64_t nchan, int64_t nsamp, int64_t in_row_stride,
                   float* d_out, int64_t out_row_stride, void* stream);
+
+/*
+ * RFI mitigation before dedispersion (Ch. 3 Sec. "Bandpass Correction", "Channel
+ * Thresholding", "Spectrum Thresholding"), for FP32 filterbanks. A caller runs
+ * dd_bandpass, copies the nchan averages to the host, fits them with dd_bandpass_fit,
+ * uploads the fit and calls dd_rfi_clip.
+ *
+ * dd_bandpass: d_avg[c] = mean over t < nsamp of d_in[c][t] (the averaged bandpass), FP64
+ * sums in a fixed order. d_in [nchan][row_stride] FP32, d_avg [nchan] FP64, both device.
+ * Errors: DD_ERR_INVALID_ARG for NULL pointers, nchan or nsamp < 1, row_stride < nsamp.
+ */
+int dd_bandpass(const float* d_in, int64_t nchan, int64_t nsamp, int64_t row_stride, double* d_avg, void* stream);
+
+/*
+ * dd_bandpass_fit (host only): least-squares polynomial of degree `order` (0..16, below
+ * nchan) in x = 2c/(nchan-1) - 1 (x = 0 for one channel) fitted to avg[nchan]; writes the
+ * fitted values fit[nchan], and when non-NULL the RMSE between fit and avg (*rmse) and the
+ * fit's mean over channels (*fit_mean). Host arrays, caller-owned. Errors:
+ * DD_ERR_INVALID_ARG for NULL avg or fit, nchan < 1, or an order out of range.
+ */
+int dd_bandpass_fit(const double* avg, int32_t nchan, int32_t order, double* fit, double* rmse, double* fit_mean);
+
+/*
+ * dd_rfi_clip, in place on d_data [nchan][row_stride] FP32 (device), with d_fit [nchan]
+ * FP64 (device) the fitted bandpass:
+ *   channel stage (chan_threshold > 0): each channel is cut into windows of `window`
+ *     samples (the last may be shorter); window w is flagged when |mean - fit[c]| >
+ *     chan_threshold (FP64), too high for RFI or too low for lost data. d_flags
+ *     ([nchan][ceil(nsamp/window)] int32, device, caller-owned) receives the flags. Every
+ *     sample of a flagged window or of a flagged window's neighbour becomes (float)fit[c].
+ *   spectrum stage (spec_threshold > 0), after the channel stage: a sample t whose mean
+ *     over channels (FP64, in channel order) differs from fit_mean by more than
+ *     spec_threshold gets (float)fit[c] in every channel.
+ * Enqueued on `stream`. Errors: DD_ERR_INVALID_ARG for NULL data or fit, nchan or nsamp <
+ * 1, row_stride < nsamp, or a channel stage without window >= 1 and flags;
+ * DD_ERR_UNSUPPORTED for more than 65535 channels.
+ */
+int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t row_stride, const double* d_fit,
+                double chan_threshold, int64_t window, int32_t* d_flags, double fit_mean, double spec_threshold,
+                void* stream);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dd_last_error(void);

@@ -463,3 +463,45 @@ class BinnedPlan:
         for r in res:
             r._keep = (r._keep, levels)  # the downfactored inputs live until the results are dropped
         return BinnedResult(list(zip(self.segments, res)))
+
+
+def bandpass(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """The averaged bandpass (dd_bandpass): each channel's mean, [nchan] float64 on the device."""
+    if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda or x.stride(1) != 1:
+        raise ValueError("x must be a [nchan][nsamp] float32 device tensor, time contiguous")
+    avg = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    check(_lib.load().dd_bandpass(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), _vp(avg),
+                                  _stream(stream)))
+    return avg
+
+
+def bandpass_fit(avg, order: int):
+    """Host least-squares polynomial fit of an averaged bandpass (dd_bandpass_fit):
+    (fitted values as a float64 numpy array, RMSE, mean of the fit)."""
+    a = np.ascontiguousarray(avg, dtype=np.float64)
+    fit = np.empty_like(a)
+    rmse, fmean = C.c_double(), C.c_double()
+    dbl = C.POINTER(C.c_double)
+    check(_lib.load().dd_bandpass_fit(a.ctypes.data_as(dbl), int(a.size), int(order), fit.ctypes.data_as(dbl),
+                                      C.byref(rmse), C.byref(fmean)))
+    return fit, float(rmse.value), float(fmean.value)
+
+
+def rfi_mitigate(x: torch.Tensor, order: int, chan_threshold: float, window: int, spec_threshold: float,
+                 stream=None):
+    """RFI mitigation in place on a [nchan][nsamp] float32 device filterbank (Ch. 3): the
+    averaged bandpass on the device, its polynomial fit on the host (the nchan averages
+    cross PCIe, as in the paper), then channel and spectrum thresholding (dd_rfi_clip).
+    Thresholds are absolute deviations from the fit; <= 0 skips a stage. Returns (fit,
+    rmse, fit_mean, channel flags [nchan][nwin] int32 device tensor or None)."""
+    avg = bandpass(x, stream).cpu().numpy()
+    fit, rmse, fmean = bandpass_fit(avg, order)
+    d_fit = torch.from_numpy(fit).to(x.device)
+    flags = None
+    if chan_threshold > 0:
+        nwin = -(-int(x.shape[1]) // int(window))
+        flags = torch.empty((x.shape[0], nwin), dtype=torch.int32, device=x.device)
+    check(_lib.load().dd_rfi_clip(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), _vp(d_fit),
+                                  float(chan_threshold), int(window), _vp(flags), float(fmean), float(spec_threshold),
+                                  _stream(stream)))
+    return fit, rmse, fmean, flags

@@ -8,6 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(PKG, "csrc", "dedisp.hip"), os.path.join(PKG, "csrc", "detrend.hip"),
        os.path.join(PKG, "csrc", "boxcar.hip"), os.path.join(PKG, "csrc", "downfactor.hip"),
+       os.path.join(PKG, "csrc", "rfi.hip"),
        os.path.join(PKG, "csrc", "plan.cpp")]
 LIB = os.path.join(PKG, "libdedisp.so")
 

@@ -283,3 +283,37 @@ def test_time_binning_and_downfactor_arguments(lib):
                  (p256, 0, 4, 9, 9, p256, 3)]:
         assert lib.dd_downfactor(*args, None) == lib_mod.DD_ERR_INVALID_ARG, args
     assert lib.dd_downfactor(p256, 0, 70000, 8, 8, p256, 4, None) == lib_mod.DD_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("nchan,order", [(1, 0), (2, 1), (64, 4), (1024, 8), (4096, 12)])
+def test_bandpass_fit_matches_oracle(lib, nchan, order):
+    """The host fit (Gram-Schmidt projection) equals the oracle's numpy least squares."""
+    rng = np.random.default_rng(nchan + order)
+    c = np.arange(nchan)
+    avg = 10.0 + 3.0 * np.sin(np.pi * c / max(nchan, 1)) + 0.05 * rng.standard_normal(nchan)
+    avg[nchan // 3] += 4.0
+    fit = np.empty(nchan)
+    rmse, fmean = C.c_double(), C.c_double()
+    dbl = C.POINTER(C.c_double)
+    assert lib.dd_bandpass_fit(avg.ctypes.data_as(dbl), nchan, order, fit.ctypes.data_as(dbl), C.byref(rmse),
+                               C.byref(fmean)) == 0
+    want, wr, wm = orc.bandpass_fit(avg, order)
+    np.testing.assert_allclose(fit, want, rtol=0, atol=1e-9)
+    assert abs(rmse.value - wr) < 1e-9 and abs(fmean.value - wm) < 1e-9
+
+
+def test_rfi_arguments(lib):
+    dbl = C.POINTER(C.c_double)
+    a = np.ones(8)
+    f = np.empty(8)
+    for n, order in [(0, 0), (8, 8), (8, -1), (20, 17)]:
+        assert lib.dd_bandpass_fit(a.ctypes.data_as(dbl), n, order, f.ctypes.data_as(dbl), None, None) == \
+            lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_bandpass_fit(None, 8, 1, f.ctypes.data_as(dbl), None, None) == lib_mod.DD_ERR_INVALID_ARG
+    p = C.c_void_p(256)
+    assert lib.dd_bandpass(None, 4, 8, 8, p, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_bandpass(p, 4, 8, 7, p, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 4, 8, 8, None, 1.0, 4, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 0, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 4, None, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 70000, 8, 8, p, 1.0, 4, p, 0.0, 1.0, None) == lib_mod.DD_ERR_UNSUPPORTED

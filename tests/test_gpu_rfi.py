@@ -1,0 +1,120 @@
+"""RFI mitigation on the device (dd_bandpass, dd_bandpass_fit, dd_rfi_clip) against the FP64
+oracle (run on an MI355X with -m gpu). Flags are integer decisions taken in FP64 on both
+sides; each case checks that no oracle mean lies within 1e-6 of its threshold, so the two
+fits (which agree to 1e-9) cannot decide differently."""
+import sys
+
+import numpy as np
+import pytest
+
+import fbsynth
+from oracle import dedisp_oracle as orc
+from tests.gpu_util import cuda
+
+pytestmark = pytest.mark.gpu
+GUARD = 1e-6
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return cuda()
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_1401_8258_amd as dd
+    dd.load_library()
+    return dd
+
+
+def _dirty(nchan, n, seed):
+    rng = np.random.default_rng(seed)
+    c = np.arange(nchan)
+    x = (10.0 + 3.0 * np.sin(np.pi * c / nchan))[:, None] + rng.standard_normal((nchan, n))
+    x = x.astype(np.float32)
+    x[nchan // 7, n // 10: n // 10 + 3 * n // 40] += 5.0       # narrowband burst
+    x[nchan // 3, : n // 50 + 1] = 0.0                          # lost data
+    x[:, n // 2: n // 2 + 3] += 3.0                             # broadband spike
+    return x
+
+
+def _window_margin(x, fit, thr, window):
+    n = x.shape[1]
+    worst = np.inf
+    for w in range(-(-n // window)):
+        m = x[:, w * window:(w + 1) * window].astype(np.float64).mean(axis=1)
+        worst = min(worst, float(np.min(np.abs(np.abs(m - fit) - thr))))
+    return worst
+
+
+@pytest.mark.parametrize("nchan,n,stride,window,order", [
+    (64, 16384, 16384, 64, 4), (5, 1001, 1013, 7, 2), (1, 300, 300, 16, 0), (33, 4099, 4100, 256, 6)])
+def test_rfi_parity(torch, dd, nchan, n, stride, window, order):
+    _say(f"case: rfi {nchan}x{n} stride {stride} window {window} order {order}")
+    full = np.zeros((nchan, stride), np.float32)
+    full[:, :n] = _dirty(nchan, n, nchan * 31 + n)
+    x = full[:, :n]
+    cthr, sthr = 1.0, 1.0
+    want, fit, rmse, fmean, cf, sf = orc.rfi_mitigate(x, order, cthr, window, sthr)
+    assert _window_margin(x, fit, cthr, window) > GUARD
+    after_chan, _ = orc.channel_clip(x, fit, cthr, window)
+    assert float(np.min(np.abs(np.abs(after_chan.mean(axis=0) - fmean) - sthr))) > GUARD
+    dev = torch.from_numpy(full).cuda()[:, :n]
+    avg = dd.bandpass(dev).cpu().numpy()
+    np.testing.assert_allclose(avg, orc.bandpass_average(x), rtol=0, atol=1e-12 * 16)
+    gfit, grmse, gmean, flags = dd.rfi_mitigate(dev, order, cthr, window, sthr)
+    got = dev.cpu().numpy()
+    np.testing.assert_allclose(gfit, fit, rtol=0, atol=1e-9)
+    np.testing.assert_array_equal(flags.cpu().numpy() != 0, cf)
+    same = want == x.astype(np.float64)
+    np.testing.assert_array_equal(got[same], x[same])                  # untouched samples keep their bits
+    # replaced samples hold the FP32 value of each side's fit (the fits agree to 1e-9)
+    np.testing.assert_allclose(got[~same], want[~same], rtol=0, atol=1e-5)
+    assert cf.any() and sf.any()
+
+
+def test_rfi_stages_skip(torch, dd):
+    x = _dirty(16, 2048, 3)
+    dev = torch.from_numpy(x.copy()).cuda()
+    _, _, _, flags = dd.rfi_mitigate(dev, 2, 0.0, 64, 0.0)
+    assert flags is None
+    np.testing.assert_array_equal(dev.cpu().numpy(), x)
+
+
+def test_rfi_full_size(torch, dd):
+    """The full 1024 x 2^20 FP32 filterbank with injected RFI: bandpass, fit, every channel
+    window flag and every spectrum decision against the oracle; sampled rows of the result."""
+    _say("case: rfi full size, generating input")
+    b = fbsynth.config2()
+    x = b.data
+    x[100, 200000:260000] += 2.0
+    x[700, :5000] = -1.0
+    x[:, 500000:500004] += 1.0
+    window, order, cthr, sthr = 256, 6, 0.5, 0.2
+    dev = torch.from_numpy(x).cuda()
+    _say("case: rfi full size, running")
+    gfit, grmse, gmean, flags = dd.rfi_mitigate(dev, order, cthr, window, sthr)
+    torch.cuda.synchronize()
+    _say("case: rfi full size, oracle")
+    fit, rmse, fmean = orc.bandpass_fit(orc.bandpass_average(x), order)
+    np.testing.assert_allclose(gfit, fit, rtol=0, atol=1e-9)
+    nwin = x.shape[1] // window
+    means = x.reshape(x.shape[0], nwin, window).astype(np.float64).mean(axis=2)
+    dist = np.abs(means - fit[:, None])
+    assert float(np.min(np.abs(dist - cthr))) > GUARD
+    np.testing.assert_array_equal(flags.cpu().numpy() != 0, dist > cthr)
+    assert flags[100].sum().item() >= 234 and flags[700, :19].all()
+    got = dev.cpu().numpy()
+    del dev
+    for c in (0, 100, 700, 1023):
+        row, _ = orc.channel_clip(x[c:c + 1], fit[c:c + 1], cthr, window)
+        col = [t for t in range(500000, 500004)]
+        row[0, col] = fit[c]                           # the broadband spike is replaced
+        np.testing.assert_allclose(got[c], row[0], rtol=0, atol=1e-5)
+        kept = row[0] == x[c].astype(np.float64)
+        np.testing.assert_array_equal(got[c][kept], x[c][kept])
