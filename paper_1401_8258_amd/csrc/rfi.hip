@@ -11,10 +11,10 @@
 // * chan_flag: one wavefront per (channel, window) sums the window in FP64 and flags a mean
 //   further than the threshold from the channel's fitted value. chan_apply replaces every
 //   sample of a flagged window or of a flagged window's neighbour by the fitted value.
-// * spec_clip: one lane per sample sums its spectrum over channels in FP64, in channel
-//   order, and replaces the whole spectrum by the fitted bandpass when its mean is further
-//   than the threshold from the fit's mean. Lanes of a wavefront take consecutive samples,
-//   so each channel read is coalesced.
+// * spec_clip: each lane sums the spectra of 4 consecutive samples over channels in FP64,
+//   in channel order, and replaces a whole spectrum by the fitted bandpass when its mean is
+//   further than the threshold from the fit's mean. Lanes of a wavefront take consecutive
+//   samples, so each channel read is one coalesced 1 KB line per wavefront.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,8 +38,17 @@ __global__ __launch_bounds__(kRfiThreads) void bandpass_rows(const float* __rest
                                                              double* __restrict__ avg) {
   __shared__ double red[4];
   const float* row = x + (int64_t)blockIdx.x * stride;
+  // 16-byte loads when the row is aligned; each thread adds its 4 samples in order
+  const int64_t n4 = (reinterpret_cast<uintptr_t>(row) & 15) == 0 ? n / 4 : 0;
   double s = 0.0;
-  for (int64_t t = threadIdx.x; t < n; t += kRfiThreads) s += (double)row[t];
+  for (int64_t i = threadIdx.x; i < n4; i += kRfiThreads) {
+    const float4 v = reinterpret_cast<const float4*>(row)[i];
+    s += (double)v.x;
+    s += (double)v.y;
+    s += (double)v.z;
+    s += (double)v.w;
+  }
+  for (int64_t t = 4 * n4 + threadIdx.x; t < n; t += kRfiThreads) s += (double)row[t];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -64,27 +73,52 @@ __global__ __launch_bounds__(kRfiThreads) void chan_flag(const float* __restrict
   if (lane == 0) flags[c * nwin + w] = fabs(s / (double)len - fit[c]) > thr ? 1 : 0;
 }
 
+// One wavefront per (channel, window), as in chan_flag: a window with no flag on it or its
+// neighbours leaves at once, so clean data costs only the flag reads.
 __global__ __launch_bounds__(kRfiThreads) void chan_apply(float* __restrict__ x, int64_t n, int64_t stride,
                                                           int64_t window, int64_t nwin, const double* __restrict__ fit,
                                                           const int32_t* __restrict__ flags) {
-  const int64_t t = (int64_t)blockIdx.x * kRfiThreads + threadIdx.x;
-  if (t >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (kRfiThreads / 64) + (threadIdx.x >> 6);
+  if (w >= nwin) return;
   const int64_t c = blockIdx.y;
   const int32_t* f = flags + c * nwin;
-  const int64_t w = t / window;
   const bool hit = f[w] != 0 || (w > 0 && f[w - 1] != 0) || (w + 1 < nwin && f[w + 1] != 0);
-  if (hit) x[c * stride + t] = (float)fit[c];
+  if (!hit) return;
+  const int64_t t0 = w * window;
+  const int64_t len = n - t0 < window ? n - t0 : window;
+  const float v = (float)fit[c];
+  float* row = x + c * stride + t0;
+  for (int64_t i = lane; i < len; i += 64) row[i] = v;
 }
 
+// Each lane takes 4 consecutive samples (16-byte loads when every row start is aligned);
+// every sample's spectrum is summed over channels in channel order.
 __global__ __launch_bounds__(kRfiThreads) void spec_clip(float* __restrict__ x, int64_t nchan, int64_t n,
                                                          int64_t stride, const double* __restrict__ fit,
                                                          double center, double thr) {
-  const int64_t t = (int64_t)blockIdx.x * kRfiThreads + threadIdx.x;
-  if (t >= n) return;
-  double s = 0.0;
-  for (int64_t c = 0; c < nchan; ++c) s += (double)x[c * stride + t];
-  if (fabs(s / (double)nchan - center) > thr)
-    for (int64_t c = 0; c < nchan; ++c) x[c * stride + t] = (float)fit[c];
+  const int64_t t0 = ((int64_t)blockIdx.x * kRfiThreads + threadIdx.x) * 4;
+  if (t0 >= n) return;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool vec = t0 + 3 < n && (stride & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  if (vec) {
+    for (int64_t c = 0; c < nchan; ++c) {
+      const float4 v = *reinterpret_cast<const float4*>(x + c * stride + t0);
+      s[0] += (double)v.x;
+      s[1] += (double)v.y;
+      s[2] += (double)v.z;
+      s[3] += (double)v.w;
+    }
+  } else {
+    for (int64_t c = 0; c < nchan; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (t0 + i < n) s[i] += (double)x[c * stride + t0 + i];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (t0 + i < n && fabs(s[i] / (double)nchan - center) > thr)
+      for (int64_t c = 0; c < nchan; ++c) x[c * stride + t0 + i] = (float)fit[c];
 }
 
 hipError_t launched(const char* what) {
@@ -163,17 +197,16 @@ extern "C" int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t 
     if (window < 1 || !d_flags) return dd::fail(DD_ERR_INVALID_ARG, "channel clipping needs window >= 1 and flags");
     const int64_t nwin = (nsamp + window - 1) / window;
     const int64_t wblocks = (nwin + kRfiThreads / 64 - 1) / (kRfiThreads / 64);
-    const int64_t tblocks = (nsamp + kRfiThreads - 1) / kRfiThreads;
-    if (wblocks > 0x7fffffff || tblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
+    if (wblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
     hipLaunchKernelGGL(chan_flag, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
                        row_stride, window, nwin, d_fit, chan_threshold, d_flags);
     if (launched("channel flag") != hipSuccess) return DD_ERR_HIP;
-    hipLaunchKernelGGL(chan_apply, dim3((unsigned)tblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
+    hipLaunchKernelGGL(chan_apply, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
                        row_stride, window, nwin, d_fit, d_flags);
     if (launched("channel apply") != hipSuccess) return DD_ERR_HIP;
   }
   if (spec_threshold > 0.0) {
-    const int64_t tblocks = (nsamp + kRfiThreads - 1) / kRfiThreads;
+    const int64_t tblocks = (nsamp + 4 * kRfiThreads - 1) / (4 * kRfiThreads);
     if (tblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
     hipLaunchKernelGGL(spec_clip, dim3((unsigned)tblocks), dim3(kRfiThreads), 0, st, d_data, nchan, nsamp, row_stride,
                        d_fit, fit_mean, spec_threshold);
