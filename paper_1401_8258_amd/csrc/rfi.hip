@@ -68,18 +68,27 @@ __global__ __launch_bounds__(kRfiThreads) void chan_flag(const float* __restrict
   const int64_t t0 = w * window;
   const int64_t len = n - t0 < window ? n - t0 : window;
   double s = 0.0;
-  for (int64_t i = lane; i < len; i += 64) s += (double)row[t0 + i];
+  // 16-byte loads when windows start on 16-byte boundaries: a wavefront reads 1 KB per step
+  const int64_t len4 = (window & 3) == 0 && (reinterpret_cast<uintptr_t>(row) & 15) == 0 ? len / 4 : 0;
+  const float4* p4 = reinterpret_cast<const float4*>(row + t0);
+  for (int64_t i = lane; i < len4; i += 64) {
+    const float4 v = p4[i];
+    s += (double)v.x;
+    s += (double)v.y;
+    s += (double)v.z;
+    s += (double)v.w;
+  }
+  for (int64_t i = 4 * len4 + lane; i < len; i += 64) s += (double)row[t0 + i];
   s = wave_sum(s);
   if (lane == 0) flags[c * nwin + w] = fabs(s / (double)len - fit[c]) > thr ? 1 : 0;
 }
 
-// One wavefront per (channel, window), as in chan_flag: a window with no flag on it or its
-// neighbours leaves at once, so clean data costs only the flag reads.
+// One lane per (channel, window): a window with no flag on it or its neighbours leaves at
+// once, so clean data costs only the flag reads; a replaced window is written by its lane.
 __global__ __launch_bounds__(kRfiThreads) void chan_apply(float* __restrict__ x, int64_t n, int64_t stride,
                                                           int64_t window, int64_t nwin, const double* __restrict__ fit,
                                                           const int32_t* __restrict__ flags) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * (kRfiThreads / 64) + (threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * kRfiThreads + threadIdx.x;
   if (w >= nwin) return;
   const int64_t c = blockIdx.y;
   const int32_t* f = flags + c * nwin;
@@ -89,7 +98,7 @@ __global__ __launch_bounds__(kRfiThreads) void chan_apply(float* __restrict__ x,
   const int64_t len = n - t0 < window ? n - t0 : window;
   const float v = (float)fit[c];
   float* row = x + c * stride + t0;
-  for (int64_t i = lane; i < len; i += 64) row[i] = v;
+  for (int64_t i = 0; i < len; ++i) row[i] = v;
 }
 
 // Each lane takes 4 consecutive samples (16-byte loads when every row start is aligned);
@@ -201,7 +210,8 @@ extern "C" int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t 
     hipLaunchKernelGGL(chan_flag, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
                        row_stride, window, nwin, d_fit, chan_threshold, d_flags);
     if (launched("channel flag") != hipSuccess) return DD_ERR_HIP;
-    hipLaunchKernelGGL(chan_apply, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
+    const int64_t ablocks = (nwin + kRfiThreads - 1) / kRfiThreads;
+    hipLaunchKernelGGL(chan_apply, dim3((unsigned)ablocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
                        row_stride, window, nwin, d_fit, d_flags);
     if (launched("channel apply") != hipSuccess) return DD_ERR_HIP;
   }
