@@ -31,6 +31,12 @@ What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
   downfactored by 2 by summing adjacent samples, again at twice the diagonal, and so on:
   a DM trial in (2^(k-1) DM_diag, 2^k DM_diag] is dedispersed at factor 2^k, i.e. on the
   input downfactored k times with sampling time 2^k t_samp.
+* Subband dedispersion (Sec. "Subband Dedispersion"): nominal DMs, one per group of
+  consecutive trials; each subband of channels is dedispersed at the nominal DMs with
+  delays relative to the subband's top frequency; each trial then dedisperses the reduced
+  filterbank of its group's subband series with the delays of the subbands' top
+  frequencies. An approximation: the paper defers its error bound to another work, so
+  beyond the pins below its error is "parity unpinned".
 * RFI mitigation before dedispersion (Sec. 3 "Bandpass Correction", "Channel
   Thresholding", "Spectrum Thresholding"): the time-averaged bandpass, its least-squares
   polynomial fit over the channel index and the fit's RMSE; windows of W samples whose
@@ -56,6 +62,11 @@ form dt f0^3 / (8300 df) (Sec. 6) and against a one-sample smear of the bottom c
 pair; the number of binning stages against the paper's ceil(log2(DM_max / DM_diag)) + 1;
 a ramp's downfactored closed form and conserved sums; an impulse lands at the binned
 index floor(t0 / 2^k) - delay; factor 1 reduces to plain dedispersion.
+Subband dedispersion (tests/test_oracle_subband.py): one-channel subbands with one trial per
+group reduce to plain dedispersion exactly; an impulse lands at t0 minus the sum of its
+in-subband delay at the nominal DM and its subband's delay at the trial DM, both from the
+delay law in seconds; the residual against brute force stays within the rounding of those
+two delays.
 RFI mitigation (tests/test_oracle_rfi.py): a polynomial bandpass is fitted exactly with
 zero RMSE; a literal pure-Python loop over windows and spectra on tiny inputs; clean data
 under a high threshold is unchanged; a narrowband burst, a dropout and a broadband spike
@@ -421,3 +432,40 @@ def rfi_mitigate(data: np.ndarray, order: int, chan_threshold: float, window: in
     if spec_threshold > 0:
         x, sflags = spectrum_clip(x, fit, fit_mean, spec_threshold)
     return x, fit, rmse, fit_mean, cflags, sflags
+
+
+def subband_dedisperse(data: np.ndarray, freq_mhz, tsamp_s: float, dm, chans_per_sub: int, dms_per_group: int):
+    """Subband dedispersion (Sec. "Subband Dedispersion"). Subband s holds channels
+    [s n_c, (s+1) n_c) (the last may be shorter) with reference f_s = its largest frequency.
+    Trials are grouped in runs of n_dm consecutive trials; a group's nominal DM is the trial
+    at its middle (index d0 + (len - 1) // 2).
+    Step 1: S[g][s][t] = sum_{c in s} A[c][t + round(k DM_g (f_c^-2 - f_s^-2) / t_samp)]
+    for t < nsamp - max over subbands and groups of the step-1 delays.
+    Step 2: D[d][t] = sum_s S[g(d)][s][t + round(k DM_d (f_s^-2 - f_ref^-2) / t_samp)],
+    f_ref the top of the band, for t < len(S) - the group's largest step-2 delay.
+    Returns a list of (d0, d1, series[d1-d0][nout_g]) per group, in FP64."""
+    f = np.asarray(freq_mhz, dtype=np.float64)
+    dm = np.asarray(dm, dtype=np.float64)
+    a = np.asarray(data, dtype=np.float64)
+    nchan = f.size
+    subs = [list(range(s, min(nchan, s + chans_per_sub))) for s in range(0, nchan, chans_per_sub)]
+    groups = [(d0, min(dm.size, d0 + dms_per_group)) for d0 in range(0, dm.size, dms_per_group)]
+    nominal = np.array([dm[d0 + (d1 - d0 - 1) // 2] for d0, d1 in groups])
+    inner = [delay_table(f[idx], nominal, tsamp_s) for idx in subs]      # relative to f_s
+    m1 = max(int(t.max()) for t in inner)
+    len1 = a.shape[1] - m1
+    if len1 <= 0:
+        raise ValueError("nsamp must exceed the step-1 delays")
+    f_sub = np.array([f[idx].max() for idx in subs])
+    out = []
+    for g, (d0, d1) in enumerate(groups):
+        red = np.empty((len(subs), len1))
+        for s, idx in enumerate(subs):
+            acc = np.zeros(len1)
+            for i, c in enumerate(idx):
+                k = int(inner[s][i, g])
+                acc += a[c, k:k + len1]
+            red[s] = acc
+        # step 2: the delay table of the subbands' top frequencies (max of them = f_ref)
+        out.append((d0, d1, dedisperse(red, delay_table(f_sub, dm[d0:d1], tsamp_s))))
+    return out
