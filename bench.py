@@ -389,6 +389,30 @@ def main():
            "windows_flagged": int(flg.sum().item())}
     del xr, flg
 
+    # subband dedispersion (an approximation: 32-channel subbands, 16 trials per nominal DM)
+    print("bench: subband timing", file=sys.stderr, flush=True)
+    sp = dd.SubbandPlan(beam.freq_mhz, beam.tsamp_s, beam.dm, chans_per_sub=32, dms_per_group=16)
+    sp.dedisperse(x, k_sigma=k, cand_cap=cap)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        sp.dedisperse(x, k_sigma=k, cand_cap=cap)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_sb = e0.elapsed_time(e1) / 3
+    sp.dedisperse(x, k_sigma=k, cand_cap=cap, batched=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        sp.dedisperse(x, k_sigma=k, cand_cap=cap, batched=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_sb_b = e0.elapsed_time(e1) / 3
+    subband = {"ms_batched": round(ms_sb_b, 3), "speedup_batched_vs_plain_step": round(ms_step / ms_sb_b, 3),"chans_per_sub": 32, "dms_per_group": 16, "ms": round(ms_sb, 3), "adds": sp.adds(nsamp),
+               "adds_vs_plain": round(sp.adds(nsamp) / adds, 4), "speedup_vs_plain_step": round(ms_step / ms_sb, 3),
+               "launches": len(sp.step1) + len(sp.step2)}
+    del sp
+
     res = {
         "metric": "DM-trial*samples/s",
         "value": beam.ndm * nout / (ms_step * 1e-3),
@@ -407,6 +431,7 @@ def main():
         "boxcar": boxcar,
         "time_binning": time_binning,
         "rfi": rfi,
+        "subband": subband,
     }
     if args.copy_probe:
         y = torch.empty_like(x)

@@ -6,6 +6,6 @@ streams.
 """
 from ._lib import LibraryMissing, DedispError, load as load_library  # noqa: F401
 from .api import (Plan, Stream, Result, CAND_DTYPE, batch_dedisperse, detrend, boxcar, downfactor,  # noqa: F401
-                  time_binning, BinnedPlan, BinnedResult, bandpass, bandpass_fit, rfi_mitigate)
+                  time_binning, BinnedPlan, BinnedResult, bandpass, bandpass_fit, rfi_mitigate, SubbandPlan)
 
 __version__ = "1.2"

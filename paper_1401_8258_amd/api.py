@@ -505,3 +505,63 @@ def rfi_mitigate(x: torch.Tensor, order: int, chan_threshold: float, window: int
                                   float(chan_threshold), int(window), _vp(flags), float(fmean), float(spec_threshold),
                                   _stream(stream)))
     return fit, rmse, fmean, flags
+
+
+class SubbandPlan:
+    """Subband dedispersion (Sec. "Subband Dedispersion"), an approximation of Eq.
+    bruteEquation at a fraction of the adds. Trials are grouped in runs of dms_per_group;
+    each group's nominal DM is its middle trial.
+    Step 1: each subband of chans_per_sub channels is an ordinary plan over the nominal
+    DMs (delays relative to the subband's top frequency), written into one buffer
+    [nsub][nnominal][L].
+    Step 2: per group, the [nsub][len1] strided view of that buffer is the reduced
+    filterbank of a plan whose channels are the subbands' top frequencies.
+    FP32 input."""
+
+    def __init__(self, freq_mhz, tsamp_s: float, dm, chans_per_sub: int = 32, dms_per_group: int = 16):
+        self.freq = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+        self.dm = np.ascontiguousarray(dm, dtype=np.float64)
+        self.tsamp = float(tsamp_s)
+        nchan, ndm = self.freq.size, self.dm.size
+        self.subs = [(c0, min(nchan, c0 + chans_per_sub)) for c0 in range(0, nchan, chans_per_sub)]
+        self.groups = [(d0, min(ndm, d0 + dms_per_group)) for d0 in range(0, ndm, dms_per_group)]
+        nominal = np.array([self.dm[d0 + (d1 - d0 - 1) // 2] for d0, d1 in self.groups])
+        self.step1 = [Plan(self.freq[c0:c1], self.tsamp, nominal) for c0, c1 in self.subs]
+        f_sub = np.array([self.freq[c0:c1].max() for c0, c1 in self.subs])
+        waves = max(1, min(6, -(-dms_per_group // 8)))
+        self.step2 = [Plan(f_sub, self.tsamp, self.dm[d0:d1], tuning=(8, waves)) for d0, d1 in self.groups]
+        self.maxdelay1 = max(p.maxdelay for p in self.step1)
+
+    def adds(self, nsamp: int) -> int:
+        """Step-1 and step-2 channel-sample adds for an nsamp-sample input."""
+        a1 = sum(p.ndm * p.nchan * (int(nsamp) - p.maxdelay) for p in self.step1)
+        len1 = int(nsamp) - self.maxdelay1
+        return a1 + sum(p.ndm * p.nchan * (len1 - p.maxdelay) for p in self.step2)
+
+    def dedisperse(self, x: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True,
+                   stream=None, batched: bool = False):
+        """Returns [((d0, d1), Result)] per group of trials. With batched, each step is one
+        persistent launch (dd_batch_dedisperse) over its plans, equal bit for bit."""
+        if x.dim() != 2 or x.dtype != torch.float32 or x.shape[0] != self.freq.size or x.stride(1) != 1:
+            raise ValueError("x must be a [nchan][nsamp] float32 device tensor, time contiguous")
+        nsamp = int(x.shape[1])
+        len1 = nsamp - self.maxdelay1
+        if len1 <= 0:
+            raise ValueError("nsamp must exceed the subband delays")
+        width = -(-(nsamp - min(p.maxdelay for p in self.step1)) // 64) * 64  # rows start 256-byte aligned
+        red = torch.empty((len(self.subs), len(self.groups), width), dtype=torch.float32, device=x.device)
+        if batched:
+            batch_dedisperse([(p, x[c0:c1]) for (c0, c1), p in zip(self.subs, self.step1)], stats=False,
+                             stream=stream, outputs=[(red[s], None, None, None, None) for s in range(len(self.subs))])
+            rs = batch_dedisperse([(p, red[:, g, :len1]) for g, p in enumerate(self.step2)], k_sigma=k_sigma,
+                                  cand_cap=cand_cap, stats=stats, stream=stream)
+        else:
+            for s, ((c0, c1), p) in enumerate(zip(self.subs, self.step1)):
+                p.dedisperse(x[c0:c1], stats=False, out=red[s], stream=stream)
+            rs = [p.dedisperse(red[:, g, :len1], k_sigma=k_sigma, cand_cap=cand_cap, stats=stats, stream=stream)
+                  for g, p in enumerate(self.step2)]
+        out = []
+        for grp, r in zip(self.groups, rs):
+            r._keep = (r._keep, red)
+            out.append((grp, r))
+        return out
