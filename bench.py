@@ -421,10 +421,11 @@ def main():
     groups48 = {"dms_per_group": 48, "ms": round(ms_sb48, 3), "adds_vs_plain": round(sp48.adds(nsamp) / adds, 4),
                 "speedup_vs_plain_step": round(ms_step / ms_sb48, 3), "launches": len(sp48.step1) + len(sp48.step2)}
     del sp48
-    subband = {"groups_of_48": groups48,
-               "ms_batched": round(ms_sb_b, 3), "speedup_batched_vs_plain_step": round(ms_step / ms_sb_b, 3),"chans_per_sub": 32, "dms_per_group": 16, "ms": round(ms_sb, 3), "adds": sp.adds(nsamp),
+    subband = {"chans_per_sub": 32, "dms_per_group": 16, "ms": round(ms_sb, 3), "adds": sp.adds(nsamp),
                "adds_vs_plain": round(sp.adds(nsamp) / adds, 4), "speedup_vs_plain_step": round(ms_step / ms_sb, 3),
-               "launches": len(sp.step1) + len(sp.step2)}
+               "launches": len(sp.step1) + len(sp.step2),
+               "ms_batched": round(ms_sb_b, 3), "speedup_batched_vs_plain_step": round(ms_step / ms_sb_b, 3),
+               "groups_of_48": groups48}
     del sp
 
     res = {
