@@ -47,9 +47,10 @@ def parse():
                          "(used only while the kernel source is the one it was measured on)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the input (known bytes) to calibrate HBM counters")
-    ap.add_argument("--mode", choices=("plain", "batch", "serve"), default="plain",
+    ap.add_argument("--mode", choices=("plain", "batch", "serve", "subband"), default="plain",
                     help="plain: the full-size FP32 workload (default); batch: 16 uneven u8 beams in one "
-                         "persistent launch; serve: 64 streaming u8 beams with continuous batching")
+                         "persistent launch; serve: 64 streaming u8 beams with continuous batching; "
+                         "subband: only the subband passes over the full-size FP32 workload (for profiling)")
     ap.add_argument("--serve-blocks", type=int, default=4,
                     help="1 s blocks per beam in the serving run (plain mode appends a serving summary "
                          "when > 0)")
@@ -178,6 +179,34 @@ def batch_run(reps):
             "one_at_a_time_own_best_tiles_ms": round(ms_own, 3), "own_best_tilings": best}
 
 
+def subband_run(dd, beam, steps, warmup):
+    """Times the subband passes alone (32-channel subbands; 16 and 48 trials per nominal DM)
+    over the full-size FP32 workload, with statistics and 6-sigma candidates."""
+    import torch
+    x = torch.from_numpy(beam.data).cuda()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    res = {"workload": "subband dedispersion, full size: FP32 1024 ch 408-428 MHz, tsamp 51.2 us, "
+                       "nsamp 2^20, 2048 DMs 0-204.7 step 0.1, 32-channel subbands", "passes": []}
+    for group in (16, 48):
+        sp = dd.SubbandPlan(beam.freq_mhz, beam.tsamp_s, beam.dm, chans_per_sub=32, dms_per_group=group)
+        for _ in range(max(warmup, 1)):
+            sp.dedisperse(x, k_sigma=6.0, cand_cap=1 << 20)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            sp.dedisperse(x, k_sigma=6.0, cand_cap=1 << 20)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res["passes"].append({"dms_per_group": group, "ms": round(ms, 3), "steps": steps,
+                              "launches": len(sp.step1) + len(sp.step2)})
+        print(f"bench: subband groups of {group}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        del sp
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -205,6 +234,9 @@ def main():
         return
     print("bench: generating workload", file=sys.stderr, flush=True)
     beam = fbsynth.config2()
+    if args.mode == "subband":
+        print(json.dumps(subband_run(dd, beam, args.steps, args.warmup)), flush=True)
+        return
     tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
     plan = dd.Plan(beam.freq_mhz, beam.tsamp_s, beam.dm, tuning=tuning)
     x = torch.from_numpy(beam.data).cuda()

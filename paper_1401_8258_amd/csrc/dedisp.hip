@@ -849,10 +849,25 @@ __global__ __launch_bounds__(256) void stats_finalize(const double* __restrict__
                                                       float* rms, double* stat) {
   const int d = blockIdx.x * 256 + threadIdx.x;
   if (d >= ndm) return;
+  // One thread per series: the loads of 8 tiles are issued together and then added in tile
+  // order, so the sums are the ones a plain sequential loop gives while the loop is no longer
+  // one memory latency per tile (a plan with few series has only a few such threads).
+  const double* pd = part + (int64_t)d * nseg * 2;
   double s = 0.0, ss = 0.0;
-  for (int64_t g = 0; g < nseg; ++g) {
-    s += part[((int64_t)d * nseg + g) * 2];
-    ss += part[((int64_t)d * nseg + g) * 2 + 1];
+  int64_t g = 0;
+  for (; g + 8 <= nseg; g += 8) {
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = pd[g * 2 + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      s += v[2 * j];
+      ss += v[2 * j + 1];
+    }
+  }
+  for (; g < nseg; ++g) {
+    s += pd[g * 2];
+    ss += pd[g * 2 + 1];
   }
   const double n = (double)nout;
   const double m = s / n;
