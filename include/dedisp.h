@@ -47,9 +47,11 @@ extern "C" {
 #endif
 
 #define DD_VERSION_MAJOR 1
-#define DD_VERSION_MINOR 2  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves;
+#define DD_VERSION_MINOR 3  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves;
                                2: dd_time_binning, dd_downfactor, dd_bandpass,
-                                  dd_bandpass_fit, dd_rfi_clip */
+                                  dd_bandpass_fit, dd_rfi_clip;
+                               3: dd_tuning.kernel_form, dd_plan_info.kernel_form and
+                                  window_chunks (the register-window kernel form) */
 #define DD_CHAN_BLOCK 32
 
 /* Status codes. */
@@ -66,6 +68,21 @@ enum {
 
 /* Input storage types. All accumulate in FP32. */
 enum { DD_F32 = 0, DD_F16 = 1, DD_U8 = 2 };
+
+/* Kernel forms of the dedispersion step (dd_tuning.kernel_form). Both compute the same
+   sums in the same order, so their series are identical bit for bit; their statistics
+   partials group the FP64 additions differently (last-bit differences in mean/rms). */
+enum {
+  DD_FORM_AUTO = 0,
+  DD_FORM_LDS = 1,     /* each channel staged in LDS as four copies shifted by 0..3 samples;
+                          every add reads its sample from LDS (all dtypes, any delay spread) */
+  DD_FORM_REGWIN = 2   /* FP32 only: each channel staged once; each lane loads a window of up
+                          to 48 samples into registers and the 8 DM trials of its wavefront
+                          add from it at their (wave-uniform) offsets. Needs the delay spread
+                          of 8 consecutive trials plus 7 to stay within 40 samples in every
+                          channel; groups of 64 trials, tuning fields other than the form
+                          are ignored */
+};
 
 typedef struct dd_plan dd_plan;
 typedef struct dd_stream dd_stream;
@@ -84,6 +101,10 @@ typedef struct dd_tuning {
                                  (every wavefront issues its share of the DMAs), 1..4
                                  (waves + producer_waves <= 8; DD_ERR_UNSUPPORTED when the
                                  windows do not fit) */
+  int32_t kernel_form;        /* DD_FORM_AUTO (the register-window form for FP32 input when the
+                                 delay spread allows and no other field is set, else the LDS
+                                 form), DD_FORM_LDS, or DD_FORM_REGWIN (DD_ERR_UNSUPPORTED for
+                                 other dtypes or a spread that does not fit) */
 } dd_tuning;
 
 typedef struct dd_plan_info {
@@ -101,6 +122,8 @@ typedef struct dd_plan_info {
      workgroup */
   int32_t launch_copies, launch_buf, launch_stage, launch_ring;
   int64_t launch_lds;
+  int32_t kernel_form;              /* DD_FORM_LDS or DD_FORM_REGWIN */
+  int32_t window_chunks;            /* DD_FORM_REGWIN: 4-sample chunks per register window */
 } dd_plan_info;
 
 /* One detection: (time, DM, intensity) of Ch. 3, plus (value - mean) / rms. */

@@ -15,13 +15,14 @@ DD_ERR_WORKSPACE = -4
 DD_ERR_HIP = -5
 DD_ERR_UNSUPPORTED = -6
 DD_F32, DD_F16, DD_U8 = 0, 1, 2
+DD_FORM_AUTO, DD_FORM_LDS, DD_FORM_REGWIN = 0, 1, 2
 CHAN_BLOCK = 32
 
 
 class Tuning(C.Structure):
     _fields_ = [("dms_per_wave", C.c_int32), ("waves", C.c_int32),
                 ("samples_per_lane", C.c_int32), ("chan_stage", C.c_int32),
-                ("producer_waves", C.c_int32)]
+                ("producer_waves", C.c_int32), ("kernel_form", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -32,7 +33,8 @@ class PlanInfo(C.Structure):
                 ("samples_per_lane", C.c_int32), ("max_span", C.c_int32),
                 ("adds", C.c_int64), ("chan_stage", C.c_int32), ("producer_waves", C.c_int32),
                 ("launch_copies", C.c_int32), ("launch_buf", C.c_int32), ("launch_stage", C.c_int32),
-                ("launch_ring", C.c_int32), ("launch_lds", C.c_int64)]
+                ("launch_ring", C.c_int32), ("launch_lds", C.c_int64),
+                ("kernel_form", C.c_int32), ("window_chunks", C.c_int32)]
 
 
 class Cand(C.Structure):

@@ -21,6 +21,9 @@ CAND_DTYPE = np.dtype([("dm_index", "<i4"), ("reserved", "<i4"), ("t", "<i8"), (
                        ("snr", "<f4")])
 _TORCH_DT = {torch.float32: _lib.DD_F32, torch.float16: _lib.DD_F16, torch.uint8: _lib.DD_U8}
 _NAME_DT = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}
+# kernel forms (dd_tuning.kernel_form): "lds" stages four shifted copies per channel and reads
+# one LDS word per add; "regwin" (FP32) stages one copy and adds from register windows
+_FORMS = {"auto": _lib.DD_FORM_AUTO, "lds": _lib.DD_FORM_LDS, "regwin": _lib.DD_FORM_REGWIN}
 
 
 def _vp(t: Optional[torch.Tensor]):
@@ -63,7 +66,7 @@ class Result:
 class Plan:
     """A dedispersion plan: channel frequencies (MHz), sampling time (s), DM trials, input dtype."""
 
-    def __init__(self, freq_mhz, tsamp_s: float, dm, dtype=torch.float32, tuning=None):
+    def __init__(self, freq_mhz, tsamp_s: float, dm, dtype=torch.float32, tuning=None, form: str = "auto"):
         lib = _lib.load()
         self._lib = lib
         self.freq = np.ascontiguousarray(freq_mhz, dtype=np.float64)
@@ -74,11 +77,14 @@ class Plan:
             raise ValueError(f"unsupported input dtype {dtype}")
         h = C.c_void_p()
         tun = None
+        kf = _FORMS[form]
         if tuning is not None:  # (dms_per_wave, waves[, chan_stage[, producer_waves]])
             g, w = int(tuning[0]), int(tuning[1])
             cc = int(tuning[2]) if len(tuning) > 2 else 0
             pw = int(tuning[3]) if len(tuning) > 3 else 0
-            tun = C.byref(_lib.Tuning(g, w, 8, cc, pw))
+            tun = C.byref(_lib.Tuning(g, w, 8, cc, pw, kf))
+        elif kf != _lib.DD_FORM_AUTO:
+            tun = C.byref(_lib.Tuning(0, 0, 0, 0, 0, kf))
         dbl = C.POINTER(C.c_double)
         check(lib.dd_plan_create(C.byref(h), self.freq.ctypes.data_as(dbl), int(self.freq.size), self.tsamp,
                                  self.dm.ctypes.data_as(dbl), int(self.dm.size), _TORCH_DT[self.dtype], tun))
@@ -89,6 +95,7 @@ class Plan:
         self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(info["chan_stage"]))
         self.producer_waves = int(info["producer_waves"])
         self.max_span = int(info["max_span"])
+        self.form = {_lib.DD_FORM_LDS: "lds", _lib.DD_FORM_REGWIN: "regwin"}[int(info["kernel_form"])]
 
     @property
     def handle(self) -> C.c_void_p:

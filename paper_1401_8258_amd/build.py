@@ -6,7 +6,8 @@ import subprocess
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(PKG, "csrc", "dedisp.hip"), os.path.join(PKG, "csrc", "detrend.hip"),
+SRC = [os.path.join(PKG, "csrc", "dedisp.hip"), os.path.join(PKG, "csrc", "regwin.hip"),
+       os.path.join(PKG, "csrc", "detrend.hip"),
        os.path.join(PKG, "csrc", "boxcar.hip"), os.path.join(PKG, "csrc", "downfactor.hip"),
        os.path.join(PKG, "csrc", "rfi.hip"),
        os.path.join(PKG, "csrc", "plan.cpp")]

@@ -1,0 +1,79 @@
+// Device helpers shared by the dedispersion kernels (gfx950, wave64): input views,
+// LDS DMA issue, explicit vmcnt waits, barriers and the fixed wavefront reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dd {
+
+// Input view: linear rows, or a per-channel ring of ring_len samples in which
+// window position p lives at (win0 + p) mod ring_len. A ring row continues past
+// ring_len with a mirror of its start, so a window read from any start in
+// [0, ring_len) is contiguous.
+struct InView {
+  const void* ptr;
+  int64_t row_stride;  // elements between channel rows (ring: ring_len + mirror)
+  int64_t nvalid;      // window positions [0, nvalid) hold data
+  int64_t ring_len;    // 0 for linear input
+  int64_t win0;        // ring only: global sample of window position 0
+};
+
+typedef const __attribute__((address_space(4))) int32_t* ci32_t;
+
+// Wavefront sum in a fixed butterfly (identical for every launch shape).
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ void block_barrier() {
+  compiler_fence();
+  __builtin_amdgcn_s_barrier();
+  compiler_fence();
+}
+
+// s_waitcnt vmcnt(n) with expcnt/lgkmcnt left open (gfx9 encoding), n in [0, 63].
+#define DD_VMCNT(n) ((((n) & 15)) | (7 << 4) | (15 << 8) | ((((n) >> 4) & 3) << 14))
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+#define DD_W4(b)                                                        \
+  case b: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b)); break;               \
+  case b + 1: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b + 1)); break;       \
+  case b + 2: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b + 2)); break;       \
+  case b + 3: __builtin_amdgcn_s_waitcnt(DD_VMCNT(b + 3)); break;
+    DD_W4(0) DD_W4(4) DD_W4(8) DD_W4(12) DD_W4(16) DD_W4(20) DD_W4(24) DD_W4(28)
+    DD_W4(32) DD_W4(36) DD_W4(40) DD_W4(44) DD_W4(48) DD_W4(52) DD_W4(56) DD_W4(60)
+#undef DD_W4
+    default: __builtin_amdgcn_s_waitcnt(DD_VMCNT(0)); break;
+  }
+}
+
+// One LDS DMA: lane i copies the element at base + voff into the 32-bit LDS word at
+// lds + 4i (zero-extended for 1- and 2-byte elements). Issued from asm so the compiler
+// neither serialises later LDS reads behind it nor counts it; the kernels wait for these
+// with explicit vmcnt.
+template <int EB>
+__device__ __forceinline__ void dma(const void* base, unsigned voff, unsigned lds) {
+  if constexpr (EB == 4)
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+  else if constexpr (EB == 2)
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_ushort %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+  else
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_ubyte %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+}
+
+// 16-byte LDS DMA: lane i copies 4 dwords from base + voff (4-byte aligned) to lds + 16i.
+__device__ __forceinline__ void dma_x4(const void* base, unsigned voff, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1" : : "v"(voff), "s"(base), "s"(lds) : "m0");
+}
+
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+}  // namespace dd

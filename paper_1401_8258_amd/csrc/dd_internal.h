@@ -25,6 +25,16 @@ constexpr int kMaxDma = 256;
 // Most 16-byte DMAs one wavefront issues per stage for FP32 input (one descriptor
 // register each); beyond that the 4-byte form is used.
 constexpr int kMaxX4 = 16;
+// Register-window form (FP32): DM trials per workgroup (8 wavefronts of 8) and channels
+// per LDS stage; a wavefront's window holds at most kRwMaxChunks 4-sample chunks.
+constexpr int kRwTrials = 64;
+constexpr int kRwStage = 8;
+constexpr int kRwMaxChunks = 12;
+// Kernel forms (dd_tuning.kernel_form / dd_plan_info.kernel_form).
+constexpr int kFormLds = 1;     // four shifted copies per channel in LDS, one LDS word per add
+constexpr int kFormRegWin = 2;  // one copy per channel, register windows added in VGPR index mode
+// DD_FORM_AUTO picks the register-window form for FP32 plans it fits.
+constexpr bool kAutoRegWin = false;
 
 // Launch geometry of the dedispersion kernel.
 struct Launch {
@@ -38,6 +48,9 @@ struct Launch {
   int64_t lds;  // bytes
   int prod;     // wavefronts that only issue DMAs (0: every wavefront issues its share)
   int ndw;      // DMA instructions per issuing wavefront per stage (the vmcnt unit)
+  int form;     // kFormLds or kFormRegWin; for kFormRegWin, L is the samples a slot's DMAs
+                // cover, nd the 16-byte DMAs per slot, cs = kRwStage
+  int nch;      // kFormRegWin: 4-sample chunks per window (6, 8, 10 or 12)
 };
 Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap, int elem_bytes);
 // FP32 input with nprod producer wavefronts issuing whole channels; nb = 0 if nothing fits.
@@ -111,5 +124,15 @@ int64_t ring_table_bytes(const dd_plan* p);
 inline int64_t ring_mirror(const dd_plan* p) { return (int64_t)p->launch.L + 64; }
 inline int64_t ring_len_for(const dd_plan* p, int64_t block) { return align_up(block + (int64_t)p->maxdelay, 64); }
 int64_t elem_bytes(int32_t dtype);
+// kFormRegWin device table: [ngroups][nchan] group first delays, then from this int32
+// offset [ngroups][nchan][8 wavefronts] int4 {window byte offset, trial indices 0-3, 4-7, 0},
+// followed by kRwStage - 1 channels of zero records.
+bool plan_regwin(dd_plan* p, int64_t lds_cap);
+inline int64_t rw_meta_offset(const dd_plan* p) { return ((int64_t)p->ngroups * p->nchan + 3) / 4 * 4; }
+struct InView;
+// Launch of the register-window kernel for nout outputs (statistics partials into part
+// when non-null); defined with the kernel.
+int launch_regwin(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, float* out,
+                  int64_t out_stride, double* part, void* stream);
 
 }  // namespace dd

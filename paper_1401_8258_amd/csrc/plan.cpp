@@ -196,13 +196,87 @@ Launch choose_launch_prod(int32_t max_span, int nchan, int cs_req, int64_t lds_c
   return best;
 }
 
+// Register-window form: groups of 64 trials (8 wavefronts of 8), one padded copy of each
+// channel per LDS slot. Per (group, channel, wavefront) the table holds the window's LDS byte
+// offset (a = the wavefront's first relative delay rounded down to 8: 12 words per 8
+// samples, so 6a bytes) and the eight trials' register indices (relative delay - a), one
+// byte each. Returns false when some window needs more than kRwMaxChunks chunks or the slots
+// do not fit in LDS.
+bool plan_regwin(dd_plan* p, int64_t lds_cap) {
+  const int G = 8, NW = kRwTrials / 8;
+  const int32_t nchan = p->nchan, ndm = p->ndm;
+  const int ngroups = (ndm + kRwTrials - 1) / kRwTrials;
+  std::vector<int32_t> tab;
+  const int64_t moff = ((int64_t)ngroups * nchan + 3) / 4 * 4;
+  // seven channels of zero records after the last group: a stage reads eight channels' records
+  tab.assign((size_t)(moff + ((int64_t)ngroups * nchan + kRwStage - 1) * NW * 4), 0);
+  int32_t max_idx = 0, max_a = 0, span = 0;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    for (int32_t c = 0; c < nchan; ++c) {
+      const int32_t* row = &p->delays[(size_t)c * ndm];
+      auto dl = [&](int d) { return row[d < ndm ? d : ndm - 1]; };  // padded trials repeat the last DM
+      const int32_t first = dl(gi * kRwTrials);
+      tab[(size_t)gi * nchan + c] = first;
+      span = std::max(span, dl(gi * kRwTrials + kRwTrials - 1) - first);
+      for (int w = 0; w < NW; ++w) {
+        const int d0 = gi * kRwTrials + G * w;
+        const int32_t a = (dl(d0) - first) & ~7;
+        uint32_t pk[2] = {0u, 0u};
+        int32_t wmax = 0;
+        for (int g = 0; g < G; ++g) {
+          const int32_t idx = dl(d0 + g) - first - a;
+          max_idx = std::max(max_idx, idx);
+          wmax = std::max(wmax, idx);
+          if (idx > 4 * kRwMaxChunks - 8) return false;
+          pk[g / 4] |= (uint32_t)idx << (8 * (g % 4));
+        }
+        max_a = std::max(max_a, a);
+        int32_t* m = &tab[(size_t)(moff + (((int64_t)gi * nchan + c) * NW + w) * 4)];
+        m[0] = 6 * a;
+        m[1] = (int32_t)pk[0];
+        m[2] = (int32_t)pk[1];
+        m[3] = (wmax + 8 + 3) / 4;  // chunks this wavefront's window needs in this channel
+      }
+    }
+  }
+  int nch = (max_idx + 8 + 3) / 4;
+  nch = nch <= 6 ? 6 : nch <= 8 ? 8 : nch <= 10 ? 10 : 12;
+  // samples the windows touch (lane 63 reads up to 8 * 63 + a + 4 nch - 1), and the 16-byte
+  // DMAs that cover them: three 16-byte positions per 8 samples (two of data, one of padding)
+  const int64_t need = 8 * 63 + (int64_t)max_a + 4 * nch;
+  const int ndma = (int)((3 * ((need + 7) / 8) + 63) / 64);
+  const int xs = 8 * ((64 * ndma - 1) / 3 + 1);
+  const int64_t stage = (int64_t)kRwStage * 1024 * ndma;
+  int nb = (int)std::min<int64_t>(lds_cap / stage, 8);
+  while (nb > 2 && (int64_t)(nb - 2) * ndma > 63) --nb;  // a wait counts at most 63 DMAs
+  if (nb < 2) return false;
+  Launch l{};
+  l.form = kFormRegWin;
+  l.L = xs;
+  l.cs = kRwStage;
+  l.nb = nb;
+  l.nd = ndma;
+  l.ndw = ndma;
+  l.x4 = 1;
+  l.nch = nch;
+  l.lds = (int64_t)nb * stage;
+  p->launch = l;
+  p->tiles = Tiles{G, NW, 8, kRwStage, -1};
+  p->dms_per_group = kRwTrials;
+  p->ngroups = ngroups;
+  p->ndm_pad = ngroups * kRwTrials;
+  p->max_span = span;
+  p->dev_table.swap(tab);
+  return true;
+}
+
 }  // namespace dd
 
 extern "C" {
 
 const char* dd_last_error(void) { return g_err.c_str(); }
 
-const char* dd_version(void) { return "1.2"; }
+const char* dd_version(void) { return "1.3"; }
 
 int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
                    const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning) {
@@ -230,6 +304,16 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   }
 
   dd::Tiles t{8, 0, 8, 0, 0};
+  const int form_req = tuning ? tuning->kernel_form : DD_FORM_AUTO;
+  if (form_req != DD_FORM_AUTO && form_req != DD_FORM_LDS && form_req != DD_FORM_REGWIN)
+    return dd::fail(DD_ERR_UNSUPPORTED, "unknown kernel_form");
+  if (form_req == DD_FORM_REGWIN && in_dtype != DD_F32)
+    return dd::fail(DD_ERR_UNSUPPORTED, "the register-window form takes FP32 input only");
+  // the register-window form is the FP32 default when no tile field is set
+  const bool tiles_set = tuning && (tuning->dms_per_wave || tuning->waves || tuning->samples_per_lane ||
+                                    tuning->chan_stage || tuning->producer_waves);
+  const bool try_regwin = in_dtype == DD_F32 && (form_req == DD_FORM_REGWIN ||
+                                                 (form_req == DD_FORM_AUTO && !tiles_set && dd::kAutoRegWin));
   if (tuning) {
     if (tuning->dms_per_wave) t.g = tuning->dms_per_wave;
     if (tuning->waves) t.w = tuning->waves;
@@ -271,6 +355,18 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   }
   p->maxdelay = (int32_t)maxd;
 
+  if (try_regwin) {
+    if (dd::plan_regwin(p, dd::kLdsBytes)) {
+      p->id = g_next_id.fetch_add(1);
+      *out = p;
+      return DD_OK;
+    }
+    if (form_req == DD_FORM_REGWIN) {
+      delete p;
+      return dd::fail(DD_ERR_UNSUPPORTED, "the delay spread of 8 consecutive DM trials does not fit the register "
+                                          "window (at most 40 samples with the alignment)");
+    }
+  }
   // FP32 input: by default two producer wavefronts issue every LDS DMA beside six
   // computing ones (the fastest split measured on the full FP32 workload), when one DM
   // group's channel windows fit their 16-byte DMAs. Otherwise, and for other input:
@@ -312,6 +408,7 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
                                             " samples) does not fit in LDS; use fewer DMs per workgroup");
   }
   p->tiles = t;
+  lg.form = dd::kFormLds;
   p->launch = lg;
   p->dms_per_group = t.g * t.w;
   p->ngroups = (ndm + p->dms_per_group - 1) / p->dms_per_group;
@@ -359,7 +456,9 @@ int dd_plan_query(const dd_plan* p, int64_t nsamp, dd_plan_info* info) {
   info->chan_stage = p->tiles.cc;
   info->producer_waves = p->launch.prod;
   info->max_span = p->max_span;
-  info->launch_copies = 4;
+  info->kernel_form = p->launch.form;
+  info->window_chunks = p->launch.form == dd::kFormRegWin ? p->launch.nch : 0;
+  info->launch_copies = p->launch.form == dd::kFormRegWin ? 1 : 4;
   info->launch_buf = p->launch.L;
   info->launch_stage = p->launch.cs;
   info->launch_ring = p->launch.nb;

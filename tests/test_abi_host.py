@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
         assert n in lib_mod.SIGNATURES, n
-    assert lib.dd_version().decode() == "1.2"
+    assert lib.dd_version().decode() == "1.3"
 
 
 def _create(lib, freq, dm, tsamp, dtype=0, tuning=None):
@@ -317,3 +317,45 @@ def test_rfi_arguments(lib):
     assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 0, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
     assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 4, None, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
     assert lib.dd_rfi_clip(p, 70000, 8, 8, p, 1.0, 4, p, 0.0, 1.0, None) == lib_mod.DD_ERR_UNSUPPORTED
+
+
+def _info(lib, h, nsamp=1 << 20):
+    info = lib_mod.PlanInfo()
+    assert lib.dd_plan_query(h, nsamp, C.byref(info)) in (0, -2)
+    return info
+
+
+def test_register_window_form_plan(lib):
+    """DD_FORM_REGWIN: 64-trial groups, one staged copy, windows sized by the delay spread of
+    eight consecutive trials; refused for other dtypes and for spreads past 40 samples."""
+    freq = fbsynth.channel_freqs(428.0, 20.0 / 1024, 1024)
+    dm = fbsynth.dm_trials(0.0, 0.1, 2048)
+    rc, h = _create(lib, freq, dm, 51.2e-6, tuning=(0, 0, 0, 0, 0, lib_mod.DD_FORM_REGWIN))
+    assert rc == 0
+    try:
+        info = _info(lib, h)
+        assert info.kernel_form == lib_mod.DD_FORM_REGWIN and info.launch_copies == 1
+        assert (info.dms_per_wave, info.waves, info.samples_per_lane) == (8, 8, 8)
+        # eight consecutive trials spread at most 7 * 4.44 samples in the bottom channel; with up
+        # to 7 samples of alignment and the lane's 8 outputs a window needs 12 chunks of 4
+        tab = orc.delay_table(freq, dm, 51.2e-6)
+        spread8 = max(int((tab[:, d + 7] - tab[:, d]).max()) for d in range(0, 2048, 8))
+        assert spread8 == 32
+        assert info.window_chunks == 12
+        assert info.launch_lds <= 160 * 1024 and info.launch_ring >= 2
+        np.testing.assert_array_equal(_delays(lib, h, 1024, 2048), tab)
+    finally:
+        lib.dd_plan_destroy(h)
+    # the LDS form is chosen by default and on request
+    rc, h = _create(lib, freq, dm, 51.2e-6, tuning=(0, 0, 0, 0, 0, lib_mod.DD_FORM_LDS))
+    assert rc == 0
+    assert _info(lib, h).kernel_form == lib_mod.DD_FORM_LDS and _info(lib, h).launch_copies == 4
+    lib.dd_plan_destroy(h)
+    # twice the DM step: 8 trials spread 62 samples in the bottom channel
+    rc, h = _create(lib, freq, 2 * dm, 51.2e-6, tuning=(0, 0, 0, 0, 0, lib_mod.DD_FORM_REGWIN))
+    assert rc == lib_mod.DD_ERR_UNSUPPORTED and not h.value
+    assert "register window" in lib.dd_last_error().decode()
+    rc, h = _create(lib, freq, dm, 51.2e-6, dtype=lib_mod.DD_U8, tuning=(0, 0, 0, 0, 0, lib_mod.DD_FORM_REGWIN))
+    assert rc == lib_mod.DD_ERR_UNSUPPORTED
+    rc, h = _create(lib, freq, dm, 51.2e-6, tuning=(0, 0, 0, 0, 0, 7))
+    assert rc == lib_mod.DD_ERR_UNSUPPORTED
