@@ -421,9 +421,19 @@ def spectrum_clip(data: np.ndarray, fit, fit_mean: float, threshold: float):
     return x, flags
 
 
-def rfi_mitigate(data: np.ndarray, order: int, chan_threshold: float, window: int, spec_threshold: float):
-    """The three stages in the paper's order: fit the averaged bandpass, clip channels
-    (when chan_threshold > 0), then clip spectra (when spec_threshold > 0)."""
+def bandpass_correct(data: np.ndarray, fit) -> np.ndarray:
+    """Bandpass correction (Sec. "Bandpass Correction"): the fitted bandpass subtracted from
+    every spectrum, equalising the response and moving each channel's mean to about 0."""
+    return np.asarray(data, dtype=np.float64) - np.asarray(fit, dtype=np.float64)[:, None]
+
+
+def rfi_mitigate(data: np.ndarray, order: int, chan_threshold: float, window: int, spec_threshold: float,
+                 subtract: bool = True):
+    """The RFI stage: fit the averaged bandpass; clip channel windows (when chan_threshold > 0)
+    and then spectra (when spec_threshold > 0), replacing with the fitted bandpass; finally
+    subtract the fitted bandpass from every spectrum (subtract=True), so replaced samples
+    become exactly 0. The clipping compares the uncorrected data with the fit, as the
+    paper's replacement by the fitted value presumes; the subtraction comes last."""
     fit, rmse, fit_mean = bandpass_fit(bandpass_average(data), order)
     x = np.asarray(data, dtype=np.float64)
     cflags = sflags = None
@@ -431,6 +441,8 @@ def rfi_mitigate(data: np.ndarray, order: int, chan_threshold: float, window: in
         x, cflags = channel_clip(x, fit, chan_threshold, window)
     if spec_threshold > 0:
         x, sflags = spectrum_clip(x, fit, fit_mean, spec_threshold)
+    if subtract:
+        x = bandpass_correct(x, fit)
     return x, fit, rmse, fit_mean, cflags, sflags
 
 

@@ -2,9 +2,10 @@
 Thresholding", "Spectrum Thresholding").
 
 Checked against what is fixed outside the oracle's code: an exact polynomial bandpass is
-fitted with zero residual; a literal pure-Python loop over windows and spectra agrees on
-tiny inputs; injected narrowband bursts, dropouts and broadband spikes are replaced by the
-fitted bandpass while every other sample is left as it was.
+fitted with zero residual and corrects to zero; a literal pure-Python loop over windows,
+spectra and the subtraction agrees on tiny inputs; corrected noise has each channel's mean
+near zero; injected narrowband bursts, dropouts and broadband spikes become exactly 0 after
+correction while every other sample loses only its channel's fitted value.
 """
 import numpy as np
 import pytest
@@ -28,6 +29,9 @@ def test_polynomial_bandpass_is_fitted_exactly(order, nchan):
     fit, rmse, fmean = orc.bandpass_fit(avg, order)
     np.testing.assert_allclose(fit, poly, rtol=0, atol=1e-9)
     assert rmse < 1e-9 and abs(fmean - poly.mean()) < 1e-9
+    # a pure bandpass is all response: the corrected spectra are zero (to the fit's residual)
+    out = orc.rfi_mitigate(data, order, 0.0, 1, 0.0)[0]
+    assert np.max(np.abs(out)) < 1e-9
 
 
 def _literal(data, fit, fit_mean, cthr, window, sthr):
@@ -52,6 +56,9 @@ def _literal(data, fit, fit_mean, cthr, window, sthr):
         if abs(m - fit_mean) > sthr:
             for c in range(nchan):
                 y[c][t] = fit[c]
+    for c in range(nchan):
+        for t in range(n):
+            y[c][t] = y[c][t] - fit[c]
     return np.array(y)
 
 
@@ -67,13 +74,26 @@ def test_against_literal_loops():
     assert cf[2, 2] and cf[4, 5] and cf[4, 6] and sf[30]
 
 
-def test_clean_data_unchanged_and_bursts_replaced():
+def test_corrected_noise_has_zero_channel_means():
+    """Noise on a bandpass: after correction every channel's mean is within a few standard
+    errors of 0 (the fit absorbs the response), and no stage flags clean data."""
     rng = np.random.default_rng(5)
     nchan, n, window = 64, 4096, 64
     data = _bandpass(nchan)[:, None] + rng.standard_normal((nchan, n))
     out, fit, rmse, fmean, cf, sf = orc.rfi_mitigate(data, 4, 1.0, window, 1.0)
     assert not cf.any() and not sf.any()
-    np.testing.assert_array_equal(out, data)
+    assert np.max(np.abs(out.mean(axis=1))) < 5.0 / np.sqrt(n)
+    # with no clipping the correction is the data minus the fit, sample by sample
+    np.testing.assert_allclose(out, data - fit[:, None], rtol=0, atol=1e-12)
+    # the uncorrected form (subtract=False) leaves clean data as it was
+    raw = orc.rfi_mitigate(data, 4, 1.0, window, 1.0, subtract=False)[0]
+    np.testing.assert_array_equal(raw, data)
+
+
+def test_bursts_replaced_and_corrected_to_zero():
+    rng = np.random.default_rng(5)
+    nchan, n, window = 64, 4096, 64
+    data = _bandpass(nchan)[:, None] + rng.standard_normal((nchan, n))
     dirty = data.copy()
     dirty[7, 640:830] += 5.0        # narrowband burst across windows 10..12
     dirty[20, 0:64] = 0.0           # lost data in window 0
@@ -81,10 +101,14 @@ def test_clean_data_unchanged_and_bursts_replaced():
     out, fit, rmse, fmean, cf, sf = orc.rfi_mitigate(dirty, 4, 1.0, window, 1.0)
     assert set(np.nonzero(cf[7])[0]) == {10, 11, 12} and list(np.nonzero(cf[20])[0]) == [0]
     assert list(np.nonzero(sf)[0]) == [2000, 2001, 2002]
-    np.testing.assert_array_equal(out[7, 9 * 64:14 * 64], np.full(5 * 64, fit[7]))
-    np.testing.assert_array_equal(out[20, 0:128], np.full(128, fit[20]))
-    np.testing.assert_array_equal(out[:, 2000:2003], np.repeat(fit[:, None], 3, axis=1))
+    np.testing.assert_array_equal(out[7, 9 * 64:14 * 64], 0.0)
+    np.testing.assert_array_equal(out[20, 0:128], 0.0)
+    np.testing.assert_array_equal(out[:, 2000:2003], 0.0)
     keep = np.ones_like(dirty, dtype=bool)
     keep[7, 9 * 64:14 * 64] = keep[20, 0:128] = False
     keep[:, 2000:2003] = False
-    np.testing.assert_array_equal(out[keep], dirty[keep])
+    np.testing.assert_allclose(out[keep], (dirty - fit[:, None])[keep], rtol=0, atol=1e-12)
+    # uncorrected: the replaced samples hold the fitted value, the rest is untouched
+    raw = orc.rfi_mitigate(dirty, 4, 1.0, window, 1.0, subtract=False)[0]
+    np.testing.assert_array_equal(raw[7, 9 * 64:14 * 64], np.full(5 * 64, fit[7]))
+    np.testing.assert_array_equal(raw[keep], dirty[keep])
