@@ -51,7 +51,9 @@ extern "C" {
                                2: dd_time_binning, dd_downfactor, dd_bandpass,
                                   dd_bandpass_fit, dd_rfi_clip;
                                3: dd_tuning.kernel_form, dd_plan_info.kernel_form and
-                                  window_chunks (the register-window kernel form) */
+                                  window_chunks (the register-window kernel form);
+                                  dd_bandpass window means; dd_rfi_clip bandpass
+                                  subtraction (subtract_bandpass) from the window means */
 #define DD_CHAN_BLOCK 32
 
 /* Status codes. */
@@ -321,10 +323,16 @@ int dd_downfactor(const void* d_in, int32_t in_dtype, int64_t nchan, int64_t nsa
  * uploads the fit and calls dd_rfi_clip.
  *
  * dd_bandpass: d_avg[c] = mean over t < nsamp of d_in[c][t] (the averaged bandpass), FP64
- * sums in a fixed order. d_in [nchan][row_stride] FP32, d_avg [nchan] FP64, both device.
- * Errors: DD_ERR_INVALID_ARG for NULL pointers, nchan or nsamp < 1, row_stride < nsamp.
+ * sums in a fixed order. With window >= 1 it also writes d_window_means[c][w], the mean of
+ * samples [w window, (w + 1) window) (the last window may be shorter) for w <
+ * ceil(nsamp / window): the channel stage's statistic, gathered in the same read of the
+ * input (the channel total is then the sum of its window sums). d_in [nchan][row_stride]
+ * FP32, d_avg [nchan] and d_window_means [nchan][ceil(nsamp/window)] FP64, all device.
+ * Errors: DD_ERR_INVALID_ARG for NULL input or average, nchan or nsamp < 1, row_stride <
+ * nsamp, or window and d_window_means not both given (window >= 1) or both absent (0).
  */
-int dd_bandpass(const float* d_in, int64_t nchan, int64_t nsamp, int64_t row_stride, double* d_avg, void* stream);
+int dd_bandpass(const float* d_in, int64_t nchan, int64_t nsamp, int64_t row_stride, int64_t window, double* d_avg,
+                double* d_window_means, void* stream);
 
 /*
  * dd_bandpass_fit (host only): least-squares polynomial of degree `order` (0..16, below
@@ -337,22 +345,29 @@ int dd_bandpass_fit(const double* avg, int32_t nchan, int32_t order, double* fit
 
 /*
  * dd_rfi_clip, in place on d_data [nchan][row_stride] FP32 (device), with d_fit [nchan]
- * FP64 (device) the fitted bandpass:
- *   channel stage (chan_threshold > 0): each channel is cut into windows of `window`
- *     samples (the last may be shorter); window w is flagged when |mean - fit[c]| >
- *     chan_threshold (FP64), too high for RFI or too low for lost data. d_flags
- *     ([nchan][ceil(nsamp/window)] int32, device, caller-owned) receives the flags. Every
- *     sample of a flagged window or of a flagged window's neighbour becomes (float)fit[c].
+ * FP64 (device) the fitted bandpass. The stages compare the uncorrected data with the fit:
+ *   channel stage (chan_threshold > 0): window w of channel c (windows of `window` samples,
+ *     the last may be shorter) is flagged when |d_window_means[c][w] - fit[c]| >
+ *     chan_threshold (FP64), too high for RFI or too low for lost data; the means are
+ *     dd_bandpass's for the same window. d_flags ([nchan][ceil(nsamp/window)] int32,
+ *     device, caller-owned) receives the flags. Every sample of a flagged window or of a
+ *     flagged window's neighbour takes the fitted value.
  *   spectrum stage (spec_threshold > 0), after the channel stage: a sample t whose mean
  *     over channels (FP64, in channel order) differs from fit_mean by more than
- *     spec_threshold gets (float)fit[c] in every channel.
- * Enqueued on `stream`. Errors: DD_ERR_INVALID_ARG for NULL data or fit, nchan or nsamp <
- * 1, row_stride < nsamp, or a channel stage without window >= 1 and flags;
- * DD_ERR_UNSUPPORTED for more than 65535 channels.
+ *     spec_threshold takes the fitted value in every channel.
+ *   bandpass correction (subtract_bandpass != 0, Ch. 3 Sec. "Bandpass Correction"): every
+ *     sample becomes x - (float)fit[c] (one FP32 subtraction), so each channel's mean moves
+ *     to about 0 and a replaced sample becomes exactly 0. Without it, replaced samples hold
+ *     (float)fit[c] and the rest keep their values.
+ * The channel replacement and the correction share one pass (a read and a write of the
+ * filterbank); the spectrum stage reads it once more. With dd_bandpass that is three reads
+ * of the input for the whole stage. Enqueued on `stream`. Errors: DD_ERR_INVALID_ARG for
+ * NULL data or fit, nchan or nsamp < 1, row_stride < nsamp, or a channel stage without
+ * window >= 1, window means and flags; DD_ERR_UNSUPPORTED for more than 65535 channels.
  */
 int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t row_stride, const double* d_fit,
-                double chan_threshold, int64_t window, int32_t* d_flags, double fit_mean, double spec_threshold,
-                void* stream);
+                double chan_threshold, int64_t window, const double* d_window_means, int32_t* d_flags,
+                double fit_mean, double spec_threshold, int32_t subtract_bandpass, void* stream);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dd_last_error(void);

@@ -74,9 +74,10 @@ SIGNATURES = {
     "dd_boxcar": (C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _I64, _P]),
     "dd_downfactor": (C.c_int, [_P, _I32, _I64, _I64, _I64, _P, _I64, _P]),
     "dd_time_binning": (C.c_int, [_P, _I32, C.c_double, _P, _I32, _I32, _P, _P]),
-    "dd_bandpass": (C.c_int, [_P, _I64, _I64, _I64, _P, _P]),
+    "dd_bandpass": (C.c_int, [_P, _I64, _I64, _I64, _I64, _P, _P, _P]),
     "dd_bandpass_fit": (C.c_int, [_P, _I32, _I32, _P, _P, _P]),
-    "dd_rfi_clip": (C.c_int, [_P, _I64, _I64, _I64, _P, C.c_double, _I64, _P, C.c_double, C.c_double, _P]),
+    "dd_rfi_clip": (C.c_int, [_P, _I64, _I64, _I64, _P, C.c_double, _I64, _P, _P, C.c_double, C.c_double, _I32,
+                              _P]),
     "dd_last_error": (C.c_char_p, []),
     "dd_version": (C.c_char_p, []),
 }

@@ -472,14 +472,19 @@ class BinnedPlan:
         return BinnedResult(list(zip(self.segments, res)))
 
 
-def bandpass(x: torch.Tensor, stream=None) -> torch.Tensor:
-    """The averaged bandpass (dd_bandpass): each channel's mean, [nchan] float64 on the device."""
+def bandpass(x: torch.Tensor, window: int = 0, stream=None):
+    """The averaged bandpass (dd_bandpass): each channel's mean, [nchan] float64 on the device.
+    With window >= 1 also the means of every window of that many samples, [nchan][nwin]
+    float64 (returned as a second tensor): the channel stage's statistic, from the same read."""
     if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda or x.stride(1) != 1:
         raise ValueError("x must be a [nchan][nsamp] float32 device tensor, time contiguous")
     avg = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
-    check(_lib.load().dd_bandpass(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), _vp(avg),
-                                  _stream(stream)))
-    return avg
+    means = None
+    if window:
+        means = torch.empty((x.shape[0], -(-int(x.shape[1]) // int(window))), dtype=torch.float64, device=x.device)
+    check(_lib.load().dd_bandpass(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), int(window), _vp(avg),
+                                  _vp(means), _stream(stream)))
+    return (avg, means) if window else avg
 
 
 def bandpass_fit(avg, order: int):
@@ -495,22 +500,26 @@ def bandpass_fit(avg, order: int):
 
 
 def rfi_mitigate(x: torch.Tensor, order: int, chan_threshold: float, window: int, spec_threshold: float,
-                 stream=None):
+                 subtract: bool = True, stream=None):
     """RFI mitigation in place on a [nchan][nsamp] float32 device filterbank (Ch. 3): the
     averaged bandpass on the device, its polynomial fit on the host (the nchan averages
-    cross PCIe, as in the paper), then channel and spectrum thresholding (dd_rfi_clip).
-    Thresholds are absolute deviations from the fit; <= 0 skips a stage. Returns (fit,
-    rmse, fit_mean, channel flags [nchan][nwin] int32 device tensor or None)."""
-    avg = bandpass(x, stream).cpu().numpy()
-    fit, rmse, fmean = bandpass_fit(avg, order)
+    cross PCIe, as in the paper), then channel and spectrum thresholding and the bandpass
+    correction (dd_rfi_clip). Thresholds are absolute deviations from the fit; <= 0 skips a
+    stage. With subtract the fitted bandpass is subtracted from every spectrum. Returns
+    (fit, rmse, fit_mean, channel flags [nchan][nwin] int32 device tensor or None)."""
+    chan = chan_threshold > 0
+    if chan:
+        avg_d, means = bandpass(x, int(window), stream)
+    else:
+        avg_d, means = bandpass(x, 0, stream), None
+    fit, rmse, fmean = bandpass_fit(avg_d.cpu().numpy(), order)
     d_fit = torch.from_numpy(fit).to(x.device)
     flags = None
-    if chan_threshold > 0:
-        nwin = -(-int(x.shape[1]) // int(window))
-        flags = torch.empty((x.shape[0], nwin), dtype=torch.int32, device=x.device)
+    if chan:
+        flags = torch.empty(means.shape, dtype=torch.int32, device=x.device)
     check(_lib.load().dd_rfi_clip(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), _vp(d_fit),
-                                  float(chan_threshold), int(window), _vp(flags), float(fmean), float(spec_threshold),
-                                  _stream(stream)))
+                                  float(chan_threshold), int(window), _vp(means), _vp(flags), float(fmean),
+                                  float(spec_threshold), int(bool(subtract)), _stream(stream)))
     return fit, rmse, fmean, flags
 
 

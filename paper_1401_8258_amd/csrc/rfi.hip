@@ -5,18 +5,29 @@
 // * bandpass_rows: one workgroup per channel sums the channel's samples in FP64 (fixed
 //   order: per thread over strided samples, a butterfly per wavefront, the four wavefronts
 //   in order) and writes the channel mean. One read of the input.
+// * bandpass_windows: the same average together with every window's mean (the channel
+//   stage's statistic), so the channel stage needs no read of its own: each wavefront sums
+//   its windows (four at a time, a butterfly each) and the channel total is the sum of its
+//   window sums in a fixed order.
 // * dd_bandpass_fit (host): least-squares polynomial over x = 2c/(nchan-1) - 1 by modified
 //   Gram-Schmidt on the monomial columns (each orthogonalised twice); the fitted values are
 //   the projection of the average onto their span.
-// * chan_flag: one wavefront per (channel, window) sums the window in FP64 and flags a mean
-//   further than the threshold from the channel's fitted value. chan_apply replaces every
-//   sample of a flagged window or of a flagged window's neighbour by the fitted value.
+// * chan_flag: one thread per window flags a window mean further than the threshold from
+//   the channel's fitted value. chan_apply replaces every sample of a flagged window or of a
+//   flagged window's neighbour by the fitted value (one lane per window, writing only
+//   replaced windows); chan_correct does the same and also subtracts the fitted value from
+//   every sample (a read and a write of the whole filterbank).
 // * spec_clip: each lane sums the spectra of 4 consecutive samples over channels in FP64,
-//   in channel order, and replaces a whole spectrum by the fitted bandpass when its mean is
-//   further than the threshold from the fit's mean. Lanes of a wavefront take consecutive
-//   samples, so each channel read is one coalesced 1 KB line per wavefront.
+//   in channel order (the uncorrected values: corrected samples plus their channel's fitted
+//   value), and replaces a whole spectrum by the fitted bandpass (0 when corrected) when its
+//   mean is further than the threshold from the fit's mean. Lanes of a wavefront take
+//   consecutive samples, so each channel read is one coalesced 1 KB line per wavefront.
+//
+// Order (Ch. 3): channel windows and then spectra are compared, uncorrected, with the fit
+// and replaced by it; the fitted bandpass is subtracted last (in FP32, x - (float)fit).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -55,32 +66,76 @@ __global__ __launch_bounds__(kRfiThreads) void bandpass_rows(const float* __rest
   if (threadIdx.x == 0) avg[blockIdx.x] = ((red[0] + red[1]) + (red[2] + red[3])) / (double)n;
 }
 
-// blockIdx.y = channel; each wavefront takes one window (the window index is uniform across
-// the wavefront, so a wavefront past the last window leaves as a whole).
-__global__ __launch_bounds__(kRfiThreads) void chan_flag(const float* __restrict__ x, int64_t n, int64_t stride,
-                                                         int64_t window, int64_t nwin, const double* __restrict__ fit,
-                                                         double thr, int32_t* __restrict__ flags) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * (kRfiThreads / 64) + (threadIdx.x >> 6);
+// blockIdx.x = channel. Wavefront k takes windows k, k + 4, ... in groups of four (the loads
+// of a group are issued together); lanes take 16-byte chunks (or single samples) strided by
+// 64, and each window's sum closes with a butterfly. Writes each window's mean and the
+// channel mean (the window sums added in window order per wavefront, then the four
+// wavefronts in order).
+constexpr int kGroup = 4;  // windows per wavefront whose loads are in flight together (8 measured slower)
+__global__ __launch_bounds__(kRfiThreads) void bandpass_windows(const float* __restrict__ x, int64_t n,
+                                                                int64_t stride, int64_t window, int64_t nwin,
+                                                                double* __restrict__ avg, double* __restrict__ means) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const float* row = x + (int64_t)blockIdx.x * stride;
+  const bool vec4 = (window & 3) == 0 && (reinterpret_cast<uintptr_t>(row) & 15) == 0;
+  double tot = 0.0;
+  for (int64_t wg = (int64_t)wv; wg < nwin; wg += 4 * kGroup) {
+    double s[kGroup];
+    int64_t len[kGroup];
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      s[k] = 0.0;
+      const int64_t w = wg + 4 * k;
+      const int64_t t0 = w * window;
+      len[k] = w < nwin ? (n - t0 < window ? n - t0 : window) : 0;
+    }
+    const int64_t len4 = vec4 ? window / 4 : 0;
+    for (int64_t i = lane; i < len4; i += 64) {
+      float4 v[kGroup];
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k)
+        if (4 * i + 3 < len[k]) v[k] = reinterpret_cast<const float4*>(row + (wg + 4 * k) * window)[i];
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k)
+        if (4 * i + 3 < len[k]) {
+          s[k] += (double)v[k].x;
+          s[k] += (double)v[k].y;
+          s[k] += (double)v[k].z;
+          s[k] += (double)v[k].w;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      // samples not covered by whole 16-byte chunks (all of them without vec4)
+      const int64_t start = vec4 ? 4 * (len[k] / 4) : 0;
+      for (int64_t i = start + lane; i < len[k]; i += 64) s[k] += (double)row[(wg + 4 * k) * window + i];
+    }
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      if (len[k] == 0) break;
+      const double ws = wave_sum(s[k]);
+      tot += ws;
+      if (lane == 0) means[(int64_t)blockIdx.x * nwin + wg + 4 * k] = ws / (double)len[k];
+    }
+  }
+  if (lane == 0) red[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) avg[blockIdx.x] = ((red[0] + red[1]) + (red[2] + red[3])) / (double)n;
+}
+
+// One thread per (channel, window): flags[c][w] = |mean - fit[c]| > thr.
+__global__ __launch_bounds__(kRfiThreads) void chan_flag(const double* __restrict__ means, int64_t nwin,
+                                                         const double* __restrict__ fit, double thr,
+                                                         int32_t* __restrict__ flags) {
+  const int64_t w = (int64_t)blockIdx.x * kRfiThreads + threadIdx.x;
   if (w >= nwin) return;
   const int64_t c = blockIdx.y;
-  const float* row = x + c * stride;
-  const int64_t t0 = w * window;
-  const int64_t len = n - t0 < window ? n - t0 : window;
-  double s = 0.0;
-  // 16-byte loads when windows start on 16-byte boundaries: a wavefront reads 1 KB per step
-  const int64_t len4 = (window & 3) == 0 && (reinterpret_cast<uintptr_t>(row) & 15) == 0 ? len / 4 : 0;
-  const float4* p4 = reinterpret_cast<const float4*>(row + t0);
-  for (int64_t i = lane; i < len4; i += 64) {
-    const float4 v = p4[i];
-    s += (double)v.x;
-    s += (double)v.y;
-    s += (double)v.z;
-    s += (double)v.w;
-  }
-  for (int64_t i = 4 * len4 + lane; i < len; i += 64) s += (double)row[t0 + i];
-  s = wave_sum(s);
-  if (lane == 0) flags[c * nwin + w] = fabs(s / (double)len - fit[c]) > thr ? 1 : 0;
+  flags[c * nwin + w] = fabs(means[c * nwin + w] - fit[c]) > thr ? 1 : 0;
+}
+
+__device__ __forceinline__ bool replaced(const int32_t* f, int64_t w, int64_t nwin) {
+  return f[w] != 0 || (w > 0 && f[w - 1] != 0) || (w + 1 < nwin && f[w + 1] != 0);
 }
 
 // One lane per (channel, window): a window with no flag on it or its neighbours leaves at
@@ -91,9 +146,7 @@ __global__ __launch_bounds__(kRfiThreads) void chan_apply(float* __restrict__ x,
   const int64_t w = (int64_t)blockIdx.x * kRfiThreads + threadIdx.x;
   if (w >= nwin) return;
   const int64_t c = blockIdx.y;
-  const int32_t* f = flags + c * nwin;
-  const bool hit = f[w] != 0 || (w > 0 && f[w - 1] != 0) || (w + 1 < nwin && f[w + 1] != 0);
-  if (!hit) return;
+  if (!replaced(flags + c * nwin, w, nwin)) return;
   const int64_t t0 = w * window;
   const int64_t len = n - t0 < window ? n - t0 : window;
   const float v = (float)fit[c];
@@ -101,11 +154,52 @@ __global__ __launch_bounds__(kRfiThreads) void chan_apply(float* __restrict__ x,
   for (int64_t i = 0; i < len; ++i) row[i] = v;
 }
 
+// Bandpass correction with the channel stage's replacement: every sample becomes
+// x - (float)fit[c], or 0 in a replaced window. A workgroup takes 1024 consecutive samples
+// of a channel, 4 per thread (16-byte accesses when the row is aligned); the replacement
+// decisions of the windows it touches are taken once into shared memory. flags may be null
+// (no channel stage).
+constexpr int kCorrSamples = 4 * kRfiThreads;
+__global__ __launch_bounds__(kRfiThreads) void chan_correct(float* __restrict__ x, int64_t n, int64_t stride,
+                                                            int64_t window, int64_t nwin,
+                                                            const double* __restrict__ fit,
+                                                            const int32_t* __restrict__ flags) {
+  __shared__ unsigned char rep[kCorrSamples + 2];
+  const int64_t b0 = (int64_t)blockIdx.x * kCorrSamples;
+  const int64_t c = blockIdx.y;
+  float* row = x + c * stride;
+  const int64_t wa = b0 / window;
+  const int64_t wb = ((b0 + kCorrSamples < n ? b0 + kCorrSamples : n) - 1) / window;
+  const int32_t* f = flags ? flags + c * nwin : nullptr;
+  for (int64_t w = wa + threadIdx.x; w <= wb; w += kRfiThreads) rep[w - wa] = f && replaced(f, w, nwin) ? 1 : 0;
+  __syncthreads();
+  const int64_t t0 = b0 + 4 * threadIdx.x;
+  if (t0 >= n) return;
+  const float fv = (float)fit[c];
+  bool hit[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hit[i] = t0 + i < n && rep[(t0 + i) / window - wa] != 0;
+  if (t0 + 3 < n && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+    float4 v = *reinterpret_cast<const float4*>(row + t0);
+    v.x = hit[0] ? 0.f : v.x - fv;
+    v.y = hit[1] ? 0.f : v.y - fv;
+    v.z = hit[2] ? 0.f : v.z - fv;
+    v.w = hit[3] ? 0.f : v.w - fv;
+    *reinterpret_cast<float4*>(row + t0) = v;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (t0 + i < n) row[t0 + i] = hit[i] ? 0.f : row[t0 + i] - fv;
+  }
+}
+
 // Each lane takes 4 consecutive samples (16-byte loads when every row start is aligned);
-// every sample's spectrum is summed over channels in channel order.
+// every sample's spectrum is summed over channels in channel order. With `subtract` the
+// data are corrected already: each value is summed with its channel's FP32 fitted value,
+// giving back the uncorrected spectrum to compare, and a replaced spectrum becomes 0.
 __global__ __launch_bounds__(kRfiThreads) void spec_clip(float* __restrict__ x, int64_t nchan, int64_t n,
                                                          int64_t stride, const double* __restrict__ fit,
-                                                         double center, double thr) {
+                                                         double center, double thr, int subtract) {
   const int64_t t0 = ((int64_t)blockIdx.x * kRfiThreads + threadIdx.x) * 4;
   if (t0 >= n) return;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
@@ -113,21 +207,24 @@ __global__ __launch_bounds__(kRfiThreads) void spec_clip(float* __restrict__ x, 
   if (vec) {
     for (int64_t c = 0; c < nchan; ++c) {
       const float4 v = *reinterpret_cast<const float4*>(x + c * stride + t0);
-      s[0] += (double)v.x;
-      s[1] += (double)v.y;
-      s[2] += (double)v.z;
-      s[3] += (double)v.w;
+      const double b = subtract ? (double)(float)fit[c] : 0.0;
+      s[0] += (double)v.x + b;
+      s[1] += (double)v.y + b;
+      s[2] += (double)v.z + b;
+      s[3] += (double)v.w + b;
     }
   } else {
-    for (int64_t c = 0; c < nchan; ++c)
+    for (int64_t c = 0; c < nchan; ++c) {
+      const double b = subtract ? (double)(float)fit[c] : 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if (t0 + i < n) s[i] += (double)x[c * stride + t0 + i];
+        if (t0 + i < n) s[i] += (double)x[c * stride + t0 + i] + b;
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
     if (t0 + i < n && fabs(s[i] / (double)nchan - center) > thr)
-      for (int64_t c = 0; c < nchan; ++c) x[c * stride + t0 + i] = (float)fit[c];
+      for (int64_t c = 0; c < nchan; ++c) x[c * stride + t0 + i] = subtract ? 0.f : (float)fit[c];
 }
 
 hipError_t launched(const char* what) {
@@ -138,15 +235,21 @@ hipError_t launched(const char* what) {
 
 }  // namespace
 
-extern "C" int dd_bandpass(const float* d_in, int64_t nchan, int64_t nsamp, int64_t row_stride, double* d_avg,
-                           void* stream) {
+extern "C" int dd_bandpass(const float* d_in, int64_t nchan, int64_t nsamp, int64_t row_stride, int64_t window,
+                           double* d_avg, double* d_window_means, void* stream) {
   dd::clear_error();
   if (!d_in || !d_avg) return dd::fail(DD_ERR_INVALID_ARG, "input and average must be non-NULL");
   if (nchan < 1 || nsamp < 1 || row_stride < nsamp)
     return dd::fail(DD_ERR_INVALID_ARG, "need nchan >= 1, nsamp >= 1 and row_stride >= nsamp");
+  if (window < 0 || (window > 0) != (d_window_means != nullptr))
+    return dd::fail(DD_ERR_INVALID_ARG, "window means need window >= 1 and their buffer (or window 0 and NULL)");
   if (nchan > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many channels");
-  hipLaunchKernelGGL(bandpass_rows, dim3((unsigned)nchan), dim3(kRfiThreads), 0, static_cast<hipStream_t>(stream),
-                     d_in, nsamp, row_stride, d_avg);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (window > 0)
+    hipLaunchKernelGGL(bandpass_windows, dim3((unsigned)nchan), dim3(kRfiThreads), 0, st, d_in, nsamp, row_stride,
+                       window, (nsamp + window - 1) / window, d_avg, d_window_means);
+  else
+    hipLaunchKernelGGL(bandpass_rows, dim3((unsigned)nchan), dim3(kRfiThreads), 0, st, d_in, nsamp, row_stride, d_avg);
   return launched("bandpass") == hipSuccess ? DD_OK : DD_ERR_HIP;
 }
 
@@ -194,22 +297,32 @@ extern "C" int dd_bandpass_fit(const double* avg, int32_t nchan, int32_t order, 
 }
 
 extern "C" int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t row_stride, const double* d_fit,
-                           double chan_threshold, int64_t window, int32_t* d_flags, double fit_mean,
-                           double spec_threshold, void* stream) {
+                           double chan_threshold, int64_t window, const double* d_window_means, int32_t* d_flags,
+                           double fit_mean, double spec_threshold, int32_t subtract_bandpass, void* stream) {
   dd::clear_error();
   if (!d_data || !d_fit) return dd::fail(DD_ERR_INVALID_ARG, "data and fit must be non-NULL");
   if (nchan < 1 || nsamp < 1 || row_stride < nsamp)
     return dd::fail(DD_ERR_INVALID_ARG, "need nchan >= 1, nsamp >= 1 and row_stride >= nsamp");
   if (nchan > 65535) return dd::fail(DD_ERR_UNSUPPORTED, "at most 65535 channels per call");
+  const bool chan = chan_threshold > 0.0, sub = subtract_bandpass != 0;
+  if (chan && (window < 1 || !d_flags || !d_window_means))
+    return dd::fail(DD_ERR_INVALID_ARG, "channel clipping needs window >= 1, the window means and flags");
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  if (chan_threshold > 0.0) {
-    if (window < 1 || !d_flags) return dd::fail(DD_ERR_INVALID_ARG, "channel clipping needs window >= 1 and flags");
-    const int64_t nwin = (nsamp + window - 1) / window;
-    const int64_t wblocks = (nwin + kRfiThreads / 64 - 1) / (kRfiThreads / 64);
+  const int64_t nwin = chan ? (nsamp + window - 1) / window : 1;
+  if (chan) {
+    const int64_t wblocks = (nwin + kRfiThreads - 1) / kRfiThreads;
     if (wblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
-    hipLaunchKernelGGL(chan_flag, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
-                       row_stride, window, nwin, d_fit, chan_threshold, d_flags);
+    hipLaunchKernelGGL(chan_flag, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_window_means,
+                       nwin, d_fit, chan_threshold, d_flags);
     if (launched("channel flag") != hipSuccess) return DD_ERR_HIP;
+  }
+  if (sub) {
+    const int64_t tblocks = (nsamp + kCorrSamples - 1) / kCorrSamples;
+    if (tblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
+    hipLaunchKernelGGL(chan_correct, dim3((unsigned)tblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
+                       row_stride, chan ? window : nsamp, nwin, d_fit, chan ? d_flags : nullptr);
+    if (launched("channel correct") != hipSuccess) return DD_ERR_HIP;
+  } else if (chan) {
     const int64_t ablocks = (nwin + kRfiThreads - 1) / kRfiThreads;
     hipLaunchKernelGGL(chan_apply, dim3((unsigned)ablocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data, nsamp,
                        row_stride, window, nwin, d_fit, d_flags);
@@ -219,7 +332,7 @@ extern "C" int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t 
     const int64_t tblocks = (nsamp + 4 * kRfiThreads - 1) / (4 * kRfiThreads);
     if (tblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
     hipLaunchKernelGGL(spec_clip, dim3((unsigned)tblocks), dim3(kRfiThreads), 0, st, d_data, nchan, nsamp, row_stride,
-                       d_fit, fit_mean, spec_threshold);
+                       d_fit, fit_mean, spec_threshold, (int)sub);
     if (launched("spectrum clip") != hipSuccess) return DD_ERR_HIP;
   }
   return DD_OK;

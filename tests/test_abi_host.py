@@ -311,12 +311,15 @@ def test_rfi_arguments(lib):
             lib_mod.DD_ERR_INVALID_ARG
     assert lib.dd_bandpass_fit(None, 8, 1, f.ctypes.data_as(dbl), None, None) == lib_mod.DD_ERR_INVALID_ARG
     p = C.c_void_p(256)
-    assert lib.dd_bandpass(None, 4, 8, 8, p, None) == lib_mod.DD_ERR_INVALID_ARG
-    assert lib.dd_bandpass(p, 4, 8, 7, p, None) == lib_mod.DD_ERR_INVALID_ARG
-    assert lib.dd_rfi_clip(p, 4, 8, 8, None, 1.0, 4, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
-    assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 0, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
-    assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 4, None, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
-    assert lib.dd_rfi_clip(p, 70000, 8, 8, p, 1.0, 4, p, 0.0, 1.0, None) == lib_mod.DD_ERR_UNSUPPORTED
+    assert lib.dd_bandpass(None, 4, 8, 8, 0, p, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_bandpass(p, 4, 8, 7, 0, p, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_bandpass(p, 4, 8, 8, 4, p, None, None) == lib_mod.DD_ERR_INVALID_ARG   # window without means
+    assert lib.dd_bandpass(p, 4, 8, 8, 0, p, p, None) == lib_mod.DD_ERR_INVALID_ARG      # means without window
+    assert lib.dd_rfi_clip(p, 4, 8, 8, None, 1.0, 4, p, p, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 0, p, p, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 4, p, None, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 4, None, p, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip(p, 70000, 8, 8, p, 1.0, 4, p, p, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_UNSUPPORTED
 
 
 def _info(lib, h, nsamp=1 << 20):

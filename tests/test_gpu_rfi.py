@@ -1,7 +1,10 @@
 """RFI mitigation on the device (dd_bandpass, dd_bandpass_fit, dd_rfi_clip) against the FP64
 oracle (run on an MI355X with -m gpu). Flags are integer decisions taken in FP64 on both
 sides; each case checks that no oracle mean lies within 1e-6 of its threshold, so the two
-fits (which agree to 1e-9) cannot decide differently."""
+fits (which agree to 1e-9) cannot decide differently. The corrected output (fitted bandpass
+subtracted, Ch. 3 Sec. "Bandpass Correction") is one FP32 subtraction of the FP32 fit on the
+device: it differs from the FP64 oracle by at most the fit's rounding plus half an ulp of
+the result, and a replaced sample is exactly 0 on both sides."""
 import sys
 
 import numpy as np
@@ -43,6 +46,11 @@ def _dirty(nchan, n, seed):
     return x
 
 
+def _corr_tol(fit, want):
+    """|float32(x - float32(fit)) - (x - fit)| <= ulp(fit)/2 + ulp(result)/2 (x is FP32)."""
+    return 2.0 ** -24 * (np.abs(fit)[:, None] + np.abs(want)) * 1.01 + 1e-30
+
+
 def _window_margin(x, fit, thr, window):
     n = x.shape[1]
     worst = np.inf
@@ -67,23 +75,40 @@ def test_rfi_parity(torch, dd, nchan, n, stride, window, order):
     dev = torch.from_numpy(full).cuda()[:, :n]
     avg = dd.bandpass(dev).cpu().numpy()
     np.testing.assert_allclose(avg, orc.bandpass_average(x), rtol=0, atol=1e-12 * 16)
+    avg2, wmeans = dd.bandpass(dev, window)
+    np.testing.assert_allclose(avg2.cpu().numpy(), orc.bandpass_average(x), rtol=0, atol=1e-12 * 16)
+    want_means = np.array([[x[c, w * window:(w + 1) * window].astype(np.float64).mean()
+                            for w in range(-(-n // window))] for c in range(nchan)])
+    np.testing.assert_allclose(wmeans.cpu().numpy(), want_means, rtol=0, atol=1e-12 * 16)
     gfit, grmse, gmean, flags = dd.rfi_mitigate(dev, order, cthr, window, sthr)
-    got = dev.cpu().numpy()
+    got = dev.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(gfit, fit, rtol=0, atol=1e-9)
     np.testing.assert_array_equal(flags.cpu().numpy() != 0, cf)
-    same = want == x.astype(np.float64)
-    np.testing.assert_array_equal(got[same], x[same])                  # untouched samples keep their bits
-    # replaced samples hold the FP32 value of each side's fit (the fits agree to 1e-9)
-    np.testing.assert_allclose(got[~same], want[~same], rtol=0, atol=1e-5)
-    assert cf.any() and sf.any()
+    replaced = want == 0.0
+    assert replaced.any() and cf.any() and sf.any()
+    np.testing.assert_array_equal(got[replaced], 0.0)        # replaced, then corrected: exactly 0
+    err = np.abs(got - want)
+    assert np.all(err <= _corr_tol(fit, want)), float(np.max(err - _corr_tol(fit, want)))
+    # the uncorrected form: replaced samples hold the FP32 fit, the rest keep their bits
+    dev = torch.from_numpy(full).cuda()[:, :n]
+    dd.rfi_mitigate(dev, order, cthr, window, sthr, subtract=False)
+    raw = dev.cpu().numpy()
+    want_raw = orc.rfi_mitigate(x, order, cthr, window, sthr, subtract=False)[0]
+    same = want_raw == x.astype(np.float64)
+    np.testing.assert_array_equal(raw[same], x[same])
+    np.testing.assert_allclose(raw[~same], want_raw[~same], rtol=0, atol=1e-5)
 
 
 def test_rfi_stages_skip(torch, dd):
     x = _dirty(16, 2048, 3)
     dev = torch.from_numpy(x.copy()).cuda()
-    _, _, _, flags = dd.rfi_mitigate(dev, 2, 0.0, 64, 0.0)
+    _, _, _, flags = dd.rfi_mitigate(dev, 2, 0.0, 64, 0.0, subtract=False)
     assert flags is None
     np.testing.assert_array_equal(dev.cpu().numpy(), x)
+    # correction alone: one FP32 subtraction per sample, bit for bit
+    dev = torch.from_numpy(x.copy()).cuda()
+    fit = dd.rfi_mitigate(dev, 2, 0.0, 64, 0.0)[0]
+    np.testing.assert_array_equal(dev.cpu().numpy(), x - fit.astype(np.float32)[:, None])
 
 
 def test_rfi_full_size(torch, dd):
@@ -111,10 +136,15 @@ def test_rfi_full_size(torch, dd):
     assert flags[100].sum().item() >= 234 and flags[700, :19].all()
     got = dev.cpu().numpy()
     del dev
+    # every channel's corrected mean is near 0 (noise of unit variance over 2^20 samples,
+    # plus the injected RFI that was not replaced)
+    assert np.max(np.abs(got.astype(np.float64).mean(axis=1))) < 0.05
     for c in (0, 100, 700, 1023):
         row, _ = orc.channel_clip(x[c:c + 1], fit[c:c + 1], cthr, window)
         col = [t for t in range(500000, 500004)]
         row[0, col] = fit[c]                           # the broadband spike is replaced
-        np.testing.assert_allclose(got[c], row[0], rtol=0, atol=1e-5)
-        kept = row[0] == x[c].astype(np.float64)
-        np.testing.assert_array_equal(got[c][kept], x[c][kept])
+        want = orc.bandpass_correct(row, fit[c:c + 1])[0]
+        replaced = want == 0.0
+        np.testing.assert_array_equal(got[c][replaced], 0.0)
+        err = np.abs(got[c].astype(np.float64) - want)
+        assert np.all(err <= _corr_tol(fit[c:c + 1], want[None, :])[0])
