@@ -173,14 +173,6 @@ def dedisperse(data: np.ndarray, delays: np.ndarray, rows=None) -> np.ndarray:
     return out
 
 
-def dedisperse_point(data: np.ndarray, delays: np.ndarray, d: int, t: int) -> float:
-    """A single output D[d, t], for sampled checks at sizes where whole rows are too slow."""
-    tot = 0.0
-    for c in range(data.shape[0]):
-        tot += float(data[c, t + int(delays[c, d])])
-    return tot
-
-
 def series_stats(series: np.ndarray):
     """Per-series mean and population standard deviation (Sec. 3.5 normalisation)."""
     s = np.asarray(series, dtype=np.float64)

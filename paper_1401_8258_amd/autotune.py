@@ -1,20 +1,24 @@
-"""Autotuner for the dedispersion tiles (wavefronts per DM group, channels per LDS stage).
+"""Autotuner for the dedispersion tiles (kernel form, wavefronts per DM group, channels per
+LDS stage).
 
 The thesis tuned its kernel by sweeping accumulators per thread and threads per
 block on the target GPU (Ch. 2, Sec. Performance and Benchmarks). Here the
-tunables are the number of wavefronts (8 DM trials each) sharing one LDS ring and
-the channels staged per ring slot. ``tune`` times every candidate on seeded
-random input of the beam's shape and keeps the fastest; ``tune_batch`` picks the
-wavefront count that minimises the summed time of a set of beams (a batched
-launch needs one count for all its items), with each beam's own best stage size.
-Results are cached by (nchan, ndm, dtype, nsamp, delay-spread profile).
+tunables are the kernel form ("lds": every add reads LDS, lanes own 2 x 4 samples,
+DM groups of 8 x waves trials; "regwin", FP32: lanes own 8 consecutive samples held
+in a register window, DM groups of 64 trials), the number of wavefronts (8 DM
+trials each) sharing one LDS ring and the channels staged per ring slot. ``tune``
+times every candidate on seeded random input of the beam's shape and keeps the
+fastest; ``tune_batch`` picks the wavefront count that minimises the summed time
+of a set of beams (a batched launch needs one count for all its items), with each
+beam's own best stage size. The timer is a parameter (``time_plan`` on the
+device by default). Results are cached by (nchan, ndm, dtype, nsamp, DM list hash).
 """
 from __future__ import annotations
 
 import hashlib
 import json
 import os
-from typing import Dict, List, Optional, Sequence, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -23,6 +27,7 @@ from .api import Plan, torch_dtype
 
 WAVES = (8, 4, 2, 1)
 STAGES = (0, 2, 4)
+FORMS = ("lds",)
 
 
 def _key(freq, tsamp, dm, dtype, nsamp) -> str:
@@ -81,29 +86,42 @@ def time_plan(plan: Plan, x: torch.Tensor, reps: int = 3) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+def make_plan(freq, tsamp, dm, dtype, choice: dict) -> Plan:
+    """The plan a tuning result (or one of its trials) describes."""
+    return Plan(freq, tsamp, dm, dtype=dtype, tuning=choice.get("tuning"), form=choice.get("form", "lds"))
+
+
 def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Sequence[int] = STAGES,
-         reps: int = 3, cache: Optional[TuneCache] = None, x: Optional[torch.Tensor] = None) -> dict:
-    """Best (dms_per_wave, waves, chan_stage) for one beam shape."""
-    key = _key(freq, tsamp, dm, str(dtype), nsamp) + f":{tuple(waves)}:{tuple(stages)}"
+         reps: int = 3, cache: Optional[TuneCache] = None, x: Optional[torch.Tensor] = None,
+         forms: Sequence[str] = FORMS, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan) -> dict:
+    """The fastest of the candidate tilings for one beam shape: {"form", "tuning", "ms",
+    "trials"} ("tuning" is (dms_per_wave, waves, chan_stage) for the LDS form, None for the
+    register-window form, whose groups are fixed at 8 x 8 trials)."""
+    key = _key(freq, tsamp, dm, str(dtype), nsamp) + f":{tuple(waves)}:{tuple(stages)}:{tuple(forms)}"
     if cache is not None and cache.get(key):
         return cache.get(key)
     if x is None:
         x = synthetic_input(len(freq), nsamp, dtype)
+    cands = []
+    for form in forms:
+        if form == "regwin":
+            cands.append({"form": "regwin", "tuning": None})
+        else:
+            cands += [{"form": "lds", "tuning": [8, w, cc]} for w in waves for cc in stages]
     trials = []
-    for w in waves:
-        for cc in stages:
-            try:
-                plan = Plan(freq, tsamp, dm, dtype=dtype, tuning=(8, w, cc))
-                ms = time_plan(plan, x, reps)
-            except Exception as e:  # a tiling that does not fit this beam
-                trials.append({"tuning": [8, w, cc], "error": str(e)})
-                continue
-            trials.append({"tuning": [8, w, cc], "ms": ms})
+    for cand in cands:
+        try:
+            plan = make_plan(freq, tsamp, dm, dtype, cand)
+            ms = timer(plan, x, reps)
+        except Exception as e:  # a tiling that does not fit this beam
+            trials.append(dict(cand, error=str(e)))
+            continue
+        trials.append(dict(cand, ms=ms))
     ok = [t for t in trials if "ms" in t]
     if not ok:
         raise RuntimeError("no tiling fits this beam")
     best = min(ok, key=lambda t: t["ms"])
-    res = {"tuning": best["tuning"], "ms": best["ms"], "trials": trials}
+    res = {"form": best["form"], "tuning": best["tuning"], "ms": best["ms"], "trials": trials}
     if cache is not None:
         cache.put(key, res)
     return res
@@ -111,7 +129,7 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
 
 def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequence[int] = STAGES, reps: int = 2,
                cache: Optional[TuneCache] = None, inputs: Optional[List[torch.Tensor]] = None,
-               log=None) -> dict:
+               log=None, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan) -> dict:
     """One wavefront count for a batch; per beam the best stage size under it.
 
     beams: (freq, tsamp, dm, dtype, nsamp) per beam. Returns {"waves": w, "tunings": [...],
@@ -123,7 +141,8 @@ def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequenc
         for i, (freq, tsamp, dm, dtype, nsamp) in enumerate(beams):
             x = inputs[i] if inputs is not None else None
             try:
-                r = tune(freq, tsamp, dm, dtype, nsamp, waves=(w,), stages=stages, reps=reps, cache=cache, x=x)
+                r = tune(freq, tsamp, dm, dtype, nsamp, waves=(w,), stages=stages, reps=reps, cache=cache, x=x,
+                         timer=timer)
             except RuntimeError:
                 per_w[w] = None
                 break

@@ -4,7 +4,7 @@ import pytest
 
 import fbsynth
 from oracle import dedisp_oracle as orc
-from tests.gpu_util import assert_rows_close, compare_candidates, cuda
+from tests.gpu_util import GUARD, assert_rows_close, compare_candidates, cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -57,26 +57,30 @@ def test_batch_equals_single_calls_uneven_u8(torch, dd):
 
 def test_batch_f32_mixed_shapes(torch, dd):
     print("case: batch of f32 beams", flush=True)
-    rng = np.random.default_rng(3)
     jobs, refs = [], []
-    for nchan, ndm, nsamp, step in [(64, 100, 6000, 0.1), (128, 40, 9000, 0.3), (32, 300, 4000, 0.05)]:
+    for i, (nchan, ndm, nsamp, step) in enumerate([(64, 100, 6000, 0.1), (128, 40, 9000, 0.3), (32, 300, 4000, 0.05)]):
         freq = fbsynth.channel_freqs(428.0, 20.0 / nchan, nchan)
         dm = fbsynth.dm_trials(0.0, step, ndm)
-        x = rng.standard_normal((nchan, nsamp)).astype(np.float32)
+        tab = orc.delay_table(freq, dm, 51.2e-6)
+        # a seed whose oracle values keep a margin from their thresholds (candidates compared)
+        for seed in range(100 * i, 100 * i + 50):
+            x = np.random.default_rng(seed).standard_normal((nchan, nsamp)).astype(np.float32)
+            want = orc.dedisperse(x, tab)
+            mean, rms = orc.series_stats(want)
+            if orc.threshold_margin(want, mean, rms, 4.0) > 4 * GUARD:
+                break
+        else:
+            raise AssertionError("no well-conditioned seed in 50")
         p = dd.Plan(freq, 51.2e-6, dm, tuning=(8, 4))
         jobs.append((p, torch.from_numpy(x).cuda()))
-        refs.append((freq, dm, x))
+        refs.append((want, mean, rms))
     res = dd.batch_dedisperse(jobs, k_sigma=4.0)
     torch.cuda.synchronize()
-    for (p, x), r, (freq, dm, xh) in zip(jobs, res, refs):
+    for (p, x), r, (want, mean, rms) in zip(jobs, res, refs):
         s = p.dedisperse(x, k_sigma=4.0)
         np.testing.assert_array_equal(s.out.cpu().numpy(), r.out.cpu().numpy())
-        tab = orc.delay_table(freq, dm, 51.2e-6)
-        want = orc.dedisperse(xh, tab)
-        mean, rms = orc.series_stats(want)
         assert_rows_close(r.out.cpu().numpy(), want, rms, what="batch f32")
-        if orc.threshold_margin(want, mean, rms, 4.0) > 5e-5:
-            compare_candidates(r.candidates(), want, mean, rms, 4.0)
+        compare_candidates(r.candidates(), want, mean, rms, 4.0)
 
 
 def test_batched_stream_windows_equal_push(torch, dd):

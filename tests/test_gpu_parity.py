@@ -6,7 +6,7 @@ import pytest
 
 import fbsynth
 from oracle import dedisp_oracle as orc
-from tests.gpu_util import (RMS_TOL, assert_rows_close, assert_stats_close, compare_candidates, cuda)
+from tests.gpu_util import (GUARD, RMS_TOL, assert_rows_close, assert_stats_close, compare_candidates, cuda)
 
 pytestmark = pytest.mark.gpu
 
@@ -67,23 +67,33 @@ EDGE = [
 ]
 
 
+def _well_conditioned(shape, k, seed0, make, delays):
+    """The first of 50 seeds whose oracle series keep every value at least 4 GUARD rms away
+    from its threshold, so the candidate comparison always runs (FP32 rounding cannot move a
+    value across)."""
+    for seed in range(seed0, seed0 + 50):
+        data = make(np.random.default_rng(seed), shape)
+        want = orc.dedisperse(data, delays)
+        mean, rms = orc.series_stats(want)
+        if orc.threshold_margin(want, mean, rms, k) > 4 * GUARD:
+            return data, want, mean, rms
+    raise AssertionError("no well-conditioned seed in 50")
+
+
 @pytest.mark.parametrize("nchan,ndm,nsamp,tuning,step", EDGE)
 def test_edge_shapes(torch, dd, nchan, ndm, nsamp, tuning, step):
     _say(f"case: edge nchan={nchan} ndm={ndm} nsamp={nsamp} tuning={tuning}")
-    rng = np.random.default_rng(nchan * 1000 + ndm)
     freq = fbsynth.channel_freqs(428.0, 20.0 / 64, nchan)
     dm = fbsynth.dm_trials(0.0, step, ndm)
     tab = orc.delay_table(freq, dm, 51.2e-6)
     if tab.max() >= nsamp:
         pytest.skip("shape leaves no output")
-    data = rng.standard_normal((nchan, nsamp)).astype(np.float32)
-    want = orc.dedisperse(data, tab)
-    mean, rms = orc.series_stats(want)
+    data, want, mean, rms = _well_conditioned(
+        (nchan, nsamp), 3.0, nchan * 1000 + ndm, lambda rng, sh: rng.standard_normal(sh).astype(np.float32), tab)
     plan, r = _run(torch, dd, freq, 51.2e-6, dm, data, k=3.0, tuning=tuning)
     assert_rows_close(r.out.cpu().numpy(), want, rms, what="edge")
     assert_stats_close(r.mean.cpu().numpy(), r.rms.cpu().numpy(), mean, rms)
-    if orc.threshold_margin(want, mean, rms, 3.0) > 5e-5:
-        compare_candidates(r.candidates(), want, mean, rms, 3.0)
+    compare_candidates(r.candidates(), want, mean, rms, 3.0)
 
 
 def test_integer_inputs_bit_exact_and_tuning_invariant(torch, dd):
@@ -110,16 +120,26 @@ def test_fp32_tiling_invariance(torch, dd):
         np.testing.assert_array_equal(o, outs[0])
 
 
-def test_f16_within_tolerance_and_u8_error_table(torch, dd):
-    _say("case: precision variants")
+def test_f16_and_u8_against_oracle_on_the_stored_input(torch, dd):
+    """Config 3: FP16 storage within 1e-5 rms of the FP64 oracle on the same FP16 values, u8
+    storage equal to it bit for bit (integer codes sum exactly); candidates identical to the
+    oracle's on each stored input. The error table against the FP32 original is in
+    test_gpu_precision.py."""
+    _say("case: precision variants against the oracle")
     b, u8, f16 = fbsynth.config3()
     tab = orc.delay_table(b.freq_mhz, b.dm, b.tsamp_s)
-    want16 = orc.dedisperse(f16, tab)
-    m16, r16 = orc.series_stats(want16)
-    _, r = _run(torch, dd, b.freq_mhz, b.tsamp_s, b.dm, f16, k=4.0)
-    got16 = r.out.cpu().numpy()
-    assert_rows_close(got16, want16, r16, what="f16")
-    compare_candidates(r.candidates(), want16, m16, r16, 4.0)
+    for name, x, k in (("f16", f16, 4.0), ("u8", u8, 4.0)):
+        want = orc.dedisperse(x, tab)
+        mean, rms = orc.series_stats(want)
+        assert orc.threshold_margin(want, mean, rms, k) > GUARD
+        _, r = _run(torch, dd, b.freq_mhz, b.tsamp_s, b.dm, x, k=k)
+        got = r.out.cpu().numpy()
+        if name == "u8":
+            np.testing.assert_array_equal(got.astype(np.float64), want)
+        else:
+            assert_rows_close(got, want, rms, what=name)
+        assert_stats_close(r.mean.cpu().numpy(), r.rms.cpu().numpy(), mean, rms)
+        compare_candidates(r.candidates(), want, mean, rms, k)
 
 
 def test_zero_dm_and_impulse(torch, dd):
@@ -141,18 +161,24 @@ def test_zero_dm_and_impulse(torch, dd):
 
 def test_stream_equals_one_shot(torch, dd):
     _say("case: stream vs one shot")
-    rng = np.random.default_rng(21)
     freq = fbsynth.channel_freqs(428.0, 20.0 / 128, 128)
     dm = fbsynth.dm_trials(0.0, 0.1, 96)
     tab = orc.delay_table(freq, dm, 51.2e-6)
     m = int(tab.max())
     block = 700
     sizes = [block] * 6 + [333, block]
-    x = rng.standard_normal((128, sum(sizes))).astype(np.float32)
+    # a seed for which every block's outputs keep a margin from their thresholds
+    for seed in range(21, 71):
+        x = np.random.default_rng(seed).standard_normal((128, sum(sizes))).astype(np.float32)
+        expected = orc.stream_expected(np.split(x, np.cumsum(sizes)[:-1], axis=1), tab)
+        margins = [orc.threshold_margin(w, *orc.series_stats(w), 3.0) for t0, t1, w in expected if t1 > t0]
+        if min(margins) > 4 * GUARD:
+            break
+    else:
+        raise AssertionError("no well-conditioned seed in 50")
     plan = dd.Plan(freq, 51.2e-6, dm)
     s = dd.Stream(plan, block)
     one = plan.dedisperse(torch.from_numpy(x).cuda()).out.cpu().numpy()
-    expected = orc.stream_expected(np.split(x, np.cumsum(sizes)[:-1], axis=1), tab)
     pos = 0
     produced = 0
     for j, n in enumerate(sizes):
@@ -168,8 +194,7 @@ def test_stream_equals_one_shot(torch, dd):
         np.testing.assert_array_equal(got, one[:, t0:t1])
         mean, rms = orc.series_stats(want)
         assert_stats_close(r.mean.cpu().numpy(), r.rms.cpu().numpy(), mean, rms)
-        if orc.threshold_margin(want, mean, rms, 3.0) > 5e-5:
-            compare_candidates(r.candidates(), want, mean, rms, 3.0, t_offset=t0)
+        compare_candidates(r.candidates(), want, mean, rms, 3.0, t_offset=t0)
         produced = t1
     assert produced == sum(sizes) - m
 
@@ -215,12 +240,16 @@ def test_error_paths(torch, dd):
     assert e.value.code == _lib.DD_ERR_SEQUENCE
 
 
-@pytest.mark.parametrize("rows", [[0, 777, 2047]])
-def test_config2_full_size_sampled(torch, dd, rows):
+def test_config2_full_size_sampled(torch, dd):
     """Full 1024 x 2^20 x 2048 workload in the benchmark's launch configuration; the oracle
-    recomputes whole sampled rows (and their statistics and candidates)."""
+    recomputes whole sampled rows (and their statistics and candidates): both ends, a middle
+    row, and the trials nearest the four brightest injected pulses, where the series reach
+    their largest values and FP32 accumulation error peaks."""
     _say("case: config2 full size, generating input")
     b = fbsynth.config2()
+    bright = sorted(b.pulses, key=lambda p: -p.amp)[:4]
+    rows = sorted({0, 777, 2047} | {int(np.argmin(np.abs(b.dm - p.dm))) for p in bright})
+    _say(f"case: config2 rows {rows}")
     tab = orc.delay_table(b.freq_mhz, b.dm, b.tsamp_s)
     plan = dd.Plan(b.freq_mhz, b.tsamp_s, b.dm)
     np.testing.assert_array_equal(plan.delays(), tab)
