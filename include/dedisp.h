@@ -53,13 +53,16 @@ extern "C" {
                                3: dd_tuning.kernel_form, dd_plan_info.kernel_form and
                                   window_chunks (the register-window kernel form);
                                   dd_bandpass window means; dd_rfi_clip bandpass
-                                  subtraction (subtract_bandpass) from the window means */
+                                  subtraction (subtract_bandpass) from the window means;
+                                  DD_WARN_CAND_OVERFLOW, dd_candidates_check,
+                                  dd_stream_set_gap_fill */
 #define DD_CHAN_BLOCK 32
 
 /* Status codes. */
 enum {
   DD_OK = 0,
   DD_FILLING = 1,            /* stream push accepted, no output yet (ring still filling) */
+  DD_WARN_CAND_OVERFLOW = 2, /* dd_candidates_check: more candidates qualified than cand_cap */
   DD_ERR_INVALID_ARG = -1,   /* a pointer, size or value is out of range */
   DD_ERR_TOO_SHORT = -2,     /* nsamp <= maxdelay: no output sample can be formed */
   DD_ERR_SEQUENCE = -3,      /* stream push out of order (seq must grow by one) */
@@ -178,7 +181,8 @@ int dd_plan_upload(const dd_plan* plan, void* d_workspace, int64_t ws_bytes, voi
  *   k_sigma     threshold in units of rms; <= 0 (or d_ncand NULL) skips candidates
  *   d_cand      cand_cap entries; d_ncand (device int64) receives the total count.
  *               If the count exceeds cand_cap only the first cand_cap (in (d, t)
- *               order) are written; the caller compares *d_ncand with cand_cap.
+ *               order) are written, *d_ncand keeps the true count, and the next
+ *               synchronising call, dd_candidates_check, returns DD_WARN_CAND_OVERFLOW.
  *   d_workspace prepared by dd_plan_upload, ws_bytes at least the queried size
  * Strides are in elements; in_row_stride >= nsamp, out_row_stride >= nout.
  */
@@ -217,6 +221,28 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
 void dd_stream_destroy(dd_stream* s);
 
 /*
+ * Sequence gaps (Ch. 4 Sec. "Packet Receiver": lost packets leave zero-filled gaps that RFI
+ * clipping then absorbs). With enable != 0, a push or append whose seq is larger than the
+ * next expected one treats the missing blocks as block_nsamp samples of value 0 each: the
+ * ring receives the zeros (only the last ring length of them is written) and the stream
+ * time advances past them. Outputs made computable by the zero span alone are not
+ * dedispersed: the window of that push is the last block_nsamp of the computable outputs,
+ * so *t0_out jumps over the gap. A seq below the expected one is DD_ERR_SEQUENCE either way.
+ * Default off (any gap is DD_ERR_SEQUENCE). Host only.
+ */
+int dd_stream_set_gap_fill(dd_stream* s, int32_t enable);
+
+/*
+ * Synchronise `stream` and read a candidate count written by dd_dedisperse, dd_stream_push
+ * or dd_batch_dedisperse (d_ncand, device int64): *ncand_out (may be NULL) receives it.
+ * Returns DD_WARN_CAND_OVERFLOW when it exceeds cand_cap (only the first cand_cap
+ * candidates, in (d, t) order, were written), else DD_OK; DD_ERR_INVALID_ARG for a NULL
+ * count; DD_ERR_HIP if the copy or the synchronisation fails (a fault of earlier work on
+ * the stream surfaces here).
+ */
+int dd_candidates_check(const int64_t* d_ncand, int64_t cand_cap, void* stream, int64_t* ncand_out);
+
+/*
  * Batched launch (uneven beams in one persistent launch). Each item names a plan,
  * an input already resident on the device, and its outputs; or a stream whose
  * block has already been appended with dd_stream_append. All items run in one
@@ -240,7 +266,11 @@ typedef struct dd_batch_item {
   dd_stream* stream_item;      /* non-NULL: dedisperse this stream's pending window */
 } dd_batch_item;
 
-/* Workspace bytes the batch needs beyond the per-item plan workspaces. */
+/* Workspace bytes the batch needs beyond the per-item plan workspaces. Each item's
+   d_plan_workspace must be its own: items whose workspaces overlap are rejected with
+   DD_ERR_INVALID_ARG (the statistics partials, candidate counts and u8 input-tail copy of
+   one item would overwrite another's). For the same reason one workspace (or stream ring)
+   must not serve two calls in flight at once, on one HIP stream or several. */
 int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes);
 
 int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace, int64_t ws_bytes,

@@ -8,6 +8,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdedisp.s
 
 DD_OK = 0
 DD_FILLING = 1
+DD_WARN_CAND_OVERFLOW = 2
 DD_ERR_INVALID_ARG = -1
 DD_ERR_TOO_SHORT = -2
 DD_ERR_SEQUENCE = -3
@@ -78,6 +79,8 @@ SIGNATURES = {
     "dd_bandpass_fit": (C.c_int, [_P, _I32, _I32, _P, _P, _P]),
     "dd_rfi_clip": (C.c_int, [_P, _I64, _I64, _I64, _P, C.c_double, _I64, _P, _P, C.c_double, C.c_double, _I32,
                               _P]),
+    "dd_stream_set_gap_fill": (C.c_int, [_P, _I32]),
+    "dd_candidates_check": (C.c_int, [_P, _I64, _P, C.POINTER(_I64)]),
     "dd_last_error": (C.c_char_p, []),
     "dd_version": (C.c_char_p, []),
 }

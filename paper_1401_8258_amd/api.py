@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import dataclasses
+import warnings
 from typing import Optional
 
 import numpy as np
@@ -39,6 +40,10 @@ def torch_dtype(dtype) -> torch.dtype:
     return _NAME_DT[dtype] if isinstance(dtype, str) else dtype
 
 
+class CandidateOverflow(UserWarning):
+    """More candidates qualified than the buffer held (DD_WARN_CAND_OVERFLOW)."""
+
+
 @dataclasses.dataclass
 class Result:
     out: torch.Tensor                 # [ndm][nout] float32 (a view when out_row_stride > nout)
@@ -50,17 +55,28 @@ class Result:
     cand_cap: int = 0
     _keep: object = None
 
-    def candidates(self) -> Optional[np.ndarray]:
-        """Detections as a structured numpy array (synchronises the device)."""
+    def _check(self, stream=None):
+        n = C.c_int64()
+        rc = check(_lib.load().dd_candidates_check(_vp(self._ncand), int(self.cand_cap), _stream(stream), C.byref(n)),
+                   (_lib.DD_OK, _lib.DD_WARN_CAND_OVERFLOW))
+        return int(n.value), rc == _lib.DD_WARN_CAND_OVERFLOW
+
+    def candidates(self, stream=None) -> Optional[np.ndarray]:
+        """Detections as a structured numpy array (synchronises the stream). When more
+        qualified than cand_cap, the first cand_cap in (d, t) order are returned and a
+        CandidateOverflow warning names the true count (dd_candidates_check)."""
         if self._ncand is None:
             return None
-        n = int(self._ncand.item())
+        n, over = self._check(stream)
+        if over:
+            warnings.warn(f"{n} candidates qualified; the first {self.cand_cap} were kept", CandidateOverflow)
         keep = min(n, self.cand_cap)
         raw = self._cand[: keep * CAND_DTYPE.itemsize].cpu().numpy()
         return raw.view(CAND_DTYPE)
 
-    def ncand(self) -> Optional[int]:
-        return None if self._ncand is None else int(self._ncand.item())
+    def ncand(self, stream=None) -> Optional[int]:
+        """The true number of candidates (may exceed cand_cap)."""
+        return None if self._ncand is None else self._check(stream)[0]
 
 
 class Plan:
@@ -172,7 +188,7 @@ class Plan:
 class Stream:
     """A beam's stream: device ring of maxdelay + block samples per channel (Ch. 3, buffer overlap)."""
 
-    def __init__(self, plan: Plan, block_nsamp: int, device=None, stream=None):
+    def __init__(self, plan: Plan, block_nsamp: int, device=None, stream=None, gap_fill: bool = False):
         self.plan = plan
         self._lib = plan._lib
         self.block = int(block_nsamp)
@@ -186,14 +202,20 @@ class Stream:
                                          _stream(stream), C.byref(h)))
         self._h = h
         self.seq = 0
+        if gap_fill:
+            check(self._lib.dd_stream_set_gap_fill(h, 1))
 
     @property
     def handle(self) -> C.c_void_p:
         return self._h
 
     def push(self, block: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 14, stats: bool = True,
-             out: Optional[torch.Tensor] = None, stream=None) -> Optional[Result]:
-        """Append a block; returns the newly computable outputs, or None while the ring fills."""
+             out: Optional[torch.Tensor] = None, stream=None, seq: Optional[int] = None) -> Optional[Result]:
+        """Append a block; returns the newly computable outputs, or None while the ring fills.
+        seq defaults to the next in order; a larger one (with gap_fill) zero-fills the blocks
+        in between."""
+        if seq is not None:
+            self.seq = int(seq)
         p = self.plan
         if block.dim() != 2 or block.shape[0] != p.nchan or block.dtype != p.dtype or block.stride(1) != 1:
             raise ValueError("block must be [nchan][n] of the plan dtype, time contiguous")
@@ -281,6 +303,7 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
     items = (_lib.BatchItem * len(jobs))()
     keep = []
     results = []
+    used_ws = set()
     for i, (obj, arg) in enumerate(jobs):
         it = items[i]
         given = outputs[i] if outputs is not None else None
@@ -302,6 +325,10 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
             t0 = 0
             out, mean, rms, cand, ncand = given or _outputs(plan.ndm, cols, x.device, k_sigma, cand_cap, stats)
             ws = plan.workspace(nsamp, x.device, stream)
+            if ws.data_ptr() in used_ws:  # the same plan twice at one length: a workspace of its own
+                ws = torch.empty(ws.numel(), dtype=torch.uint8, device=x.device)
+                check(lib.dd_plan_upload(plan.handle, _vp(ws), ws.numel(), _stream(stream)))
+            used_ws.add(ws.data_ptr())
             it.plan = plan.handle.value
             it.d_in = x.data_ptr()
             it.nsamp = nsamp

@@ -96,6 +96,7 @@ struct dd_stream {
   int64_t next_seq = 0;
   int64_t emitted = 0;      // global output times already produced ([0, emitted))
   int64_t pending_t0 = 0, pending_n = 0;  // window appended but not yet dedispersed
+  bool gap_fill = false;    // missing blocks become zeros instead of DD_ERR_SEQUENCE
 };
 
 namespace dd {

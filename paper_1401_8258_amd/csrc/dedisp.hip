@@ -928,6 +928,21 @@ __global__ __launch_bounds__(256) void ring_append(const TIn* __restrict__ blk, 
   }
 }
 
+// Zeros for samples [pos0, pos0 + n) of every row of a stream's ring (positions modulo
+// ring_len, mirrored like ring_append); n <= ring_len.
+template <typename TIn>
+__global__ __launch_bounds__(256) void ring_zero(TIn* __restrict__ ring, int64_t ring_row, int64_t ring_len,
+                                                 int64_t mirror, int64_t pos0, int64_t n) {
+  const int c = blockIdx.y;
+  TIn* r = ring + (int64_t)c * ring_row;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    int64_t p = pos0 + j;
+    if (p >= ring_len) p -= ring_len;
+    r[p] = TIn(0);
+    if (p < mirror) r[ring_len + p] = TIn(0);
+  }
+}
+
 // ------------------------------------------------------------------ host side
 
 using KernFn = void (*)(KParams);
@@ -1173,18 +1188,42 @@ int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t i
   if (t0_out) *t0_out = 0;
   if (nout_out) *nout_out = 0;
   if (!s || !d_block) return dd::fail(DD_ERR_INVALID_ARG, "stream and block must be non-NULL");
-  if (seq != s->next_seq)
+  if (seq != s->next_seq && !(s->gap_fill && seq > s->next_seq))
     return dd::fail(DD_ERR_SEQUENCE, "expected seq " + std::to_string(s->next_seq) + ", got " + std::to_string(seq));
   if (nsamp < 1 || nsamp > s->block) return dd::fail(DD_ERR_INVALID_ARG, "block size out of range");
   if (in_row_stride < nsamp) return dd::fail(DD_ERR_INVALID_ARG, "in_row_stride < nsamp");
   if (s->pending_n > 0) return dd::fail(DD_ERR_SEQUENCE, "previous window not dedispersed yet");
   const dd_plan* p = s->plan;
   char* ring = static_cast<char*>(s->ring) + dd::ring_table_bytes(p);
-  const int64_t pos0 = s->received % s->ring_len;
   const int64_t mirror = s->ring_row - s->ring_len;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (seq > s->next_seq) {
+    // lost blocks: block samples of zeros each; only the last ring length of them can still
+    // be read, so only those are written
+    const int64_t missing = (seq - s->next_seq) * s->block;
+    const int64_t nz = std::min<int64_t>(missing, s->ring_len);
+    const int64_t zpos = (s->received + missing - nz) % s->ring_len;
+    dim3 zgrid((unsigned)std::min<int64_t>((nz + 255) / 256, 1024), (unsigned)p->nchan);
+    if (p->dtype == DD_F32)
+      hipLaunchKernelGGL(ring_zero<float>, zgrid, dim3(256), 0, st, reinterpret_cast<float*>(ring), s->ring_row,
+                         s->ring_len, mirror, zpos, nz);
+    else if (p->dtype == DD_F16)
+      hipLaunchKernelGGL(ring_zero<__half>, zgrid, dim3(256), 0, st, reinterpret_cast<__half*>(ring), s->ring_row,
+                         s->ring_len, mirror, zpos, nz);
+    else
+      hipLaunchKernelGGL(ring_zero<uint8_t>, zgrid, dim3(256), 0, st, reinterpret_cast<uint8_t*>(ring), s->ring_row,
+                         s->ring_len, mirror, zpos, nz);
+    hipError_t ez = hipGetLastError();
+    if (ez != hipSuccess) return hip_fail(ez, "ring_zero launch");
+    s->received += missing;
+    s->next_seq = seq;
+    // outputs computable from the zeros and this block beyond the last block's worth are
+    // skipped: this push's window is at most one block long
+    s->emitted = std::max(s->emitted, s->received + nsamp - p->maxdelay - s->block);
+  }
+  const int64_t pos0 = s->received % s->ring_len;
   const unsigned gx = (unsigned)std::min<int64_t>((nsamp + 255) / 256, 1024);
   dim3 grid(gx, (unsigned)p->nchan);
-  hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == DD_F32)
     hipLaunchKernelGGL(ring_append<float>, grid, dim3(256), 0, st, static_cast<const float*>(d_block), in_row_stride,
                        nsamp, reinterpret_cast<float*>(ring), s->ring_row, s->ring_len, mirror, pos0);
@@ -1208,6 +1247,26 @@ int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t i
   if (t0_out) *t0_out = s->pending_t0;
   if (nout_out) *nout_out = s->pending_n;
   return DD_OK;
+}
+
+int dd_stream_set_gap_fill(dd_stream* s, int32_t enable) {
+  dd::clear_error();
+  if (!s) return dd::fail(DD_ERR_INVALID_ARG, "stream is NULL");
+  s->gap_fill = enable != 0;
+  return DD_OK;
+}
+
+int dd_candidates_check(const int64_t* d_ncand, int64_t cand_cap, void* stream, int64_t* ncand_out) {
+  dd::clear_error();
+  if (ncand_out) *ncand_out = 0;
+  if (!d_ncand) return dd::fail(DD_ERR_INVALID_ARG, "d_ncand is NULL");
+  int64_t n = 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&n, d_ncand, sizeof(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "candidate count");
+  if (ncand_out) *ncand_out = n;
+  return n > cand_cap ? DD_WARN_CAND_OVERFLOW : DD_OK;
 }
 
 int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_row_stride, int64_t seq,
@@ -1297,6 +1356,16 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
                        it.cand_cap, it.d_ncand);
     if (rc) return dd::fail(rc, "batch item " + std::to_string(i) + ": " + dd_last_error());
     lays[i] = dd::workspace_layout(p, lay_n);
+    // every item writes statistics partials, candidate counts and (u8) an input-tail copy into
+    // its workspace, so two items sharing workspace bytes would overwrite each other; checked
+    // before anything is enqueued
+    for (int32_t j = 0; j < i; ++j) {
+      const char* a0 = static_cast<const char*>(it.d_plan_workspace);
+      const char* b0 = static_cast<const char*>(items[j].d_plan_workspace);
+      if (a0 < b0 + lays[j].total && b0 < a0 + lays[i].total)
+        return dd::fail(DD_ERR_INVALID_ARG, "batch items " + std::to_string(j) + " and " + std::to_string(i) +
+                                                " share workspace memory; each item needs its own");
+    }
     outs[i] = Outputs{it.d_out, it.out_row_stride, it.d_mean, it.d_rms, it.k_sigma, it.d_cand, it.cand_cap,
                       it.d_ncand, t_base};
     nouts[i] = nout;

@@ -138,3 +138,55 @@ def test_batch_mixed_dma_forms_and_f16(torch, dd):
             want = orc.dedisperse(xh, orc.delay_table(freq, dm, 51.2e-6))
             _, rms = orc.series_stats(want)
             assert_rows_close(r.out.cpu().numpy(), want, rms, what=f"batch {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_batch_same_plan_twice(torch, dd, dtype):
+    """One plan, two inputs of the same length in one batch: each item gets a workspace of its
+    own, so statistics, candidates and (u8) the input-tail copy equal the single calls."""
+    print(f"case: batch with one {dtype} plan twice", flush=True)
+    freq = fbsynth.channel_freqs(428.0, 20.0 / 64, 64)
+    dm = fbsynth.dm_trials(0.0, 0.1, 96)
+    rng = np.random.default_rng(77)
+    xs = []
+    for _ in range(2):
+        x = fbsynth.noise(rng, 64, 5000)
+        xs.append(torch.from_numpy(fbsynth.to_u8(x) if dtype == "u8" else x).cuda())
+    plan = dd.Plan(freq, 51.2e-6, dm, dtype=dtype, tuning=(8, 4))
+    singles = [plan.dedisperse(x, k_sigma=3.0) for x in xs]
+    torch.cuda.synchronize()
+    single_out = [(s.out.cpu().numpy(), s.mean.cpu().numpy(), s.rms.cpu().numpy(), s.candidates()) for s in singles]
+    batched = dd.batch_dedisperse([(plan, xs[0]), (plan, xs[1])], k_sigma=3.0)
+    torch.cuda.synchronize()
+    for (o, m, r, c), b in zip(single_out, batched):
+        np.testing.assert_array_equal(b.out.cpu().numpy(), o)
+        np.testing.assert_array_equal(b.mean.cpu().numpy(), m)
+        np.testing.assert_array_equal(b.rms.cpu().numpy(), r)
+        np.testing.assert_array_equal(b.candidates(), c)
+
+
+def test_batch_rejects_shared_workspace(torch, dd):
+    """The C ABI refuses two items whose workspaces overlap."""
+    import ctypes as C
+    from paper_1401_8258_amd import _lib
+    freq = fbsynth.channel_freqs(428.0, 20.0 / 64, 64)
+    dm = fbsynth.dm_trials(0.0, 0.1, 96)
+    plan = dd.Plan(freq, 51.2e-6, dm, tuning=(8, 4))
+    x = torch.zeros((64, 3000), device="cuda")
+    ws = plan.workspace(3000)
+    out = torch.empty((96, 3000), device="cuda")
+    items = (_lib.BatchItem * 2)()
+    for it in items:
+        it.plan = plan.handle.value
+        it.d_in = x.data_ptr()
+        it.nsamp = 3000
+        it.in_row_stride = 3000
+        it.d_out = out.data_ptr()
+        it.out_row_stride = 3000
+        it.d_plan_workspace = ws.data_ptr()
+    bws = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    lib = _lib.load()
+    rc = lib.dd_batch_dedisperse(items, 2, C.c_void_p(bws.data_ptr()), bws.numel(),
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == _lib.DD_ERR_INVALID_ARG
+    assert "share workspace" in lib.dd_last_error().decode()

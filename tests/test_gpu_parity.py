@@ -199,6 +199,48 @@ def test_stream_equals_one_shot(torch, dd):
     assert produced == sum(sizes) - m
 
 
+def test_stream_gap_fill(torch, dd):
+    """Lost blocks (a seq jump) with gap fill on: the ring receives zeros for them, and every
+    output the stream then emits equals the one-shot result on the input with zeros in place
+    of the lost blocks, at the same global times; without gap fill the jump is refused."""
+    _say("case: stream gap fill")
+    freq = fbsynth.channel_freqs(428.0, 20.0 / 128, 128)
+    dm = fbsynth.dm_trials(0.0, 0.1, 96)
+    block = 700
+    nblk = 9
+    lost = {3, 4}
+    x = np.random.default_rng(5).standard_normal((128, block * nblk)).astype(np.float32)
+    for dtype in ("f32", "u8"):
+        xs = fbsynth.to_u8(x) if dtype == "u8" else x
+        fs = xs.copy()
+        for j in lost:
+            fs[:, j * block:(j + 1) * block] = 0
+        plan = dd.Plan(freq, 51.2e-6, dm, dtype=dtype)
+        one = plan.dedisperse(torch.from_numpy(fs).cuda()).out.cpu().numpy()
+        s = dd.Stream(plan, block, gap_fill=True)
+        strict = dd.Stream(plan, block)
+        seen = []
+        for j in range(nblk):
+            if j in lost:
+                continue
+            blk = torch.from_numpy(np.ascontiguousarray(xs[:, j * block:(j + 1) * block])).cuda()
+            r = s.push(blk, seq=j)
+            if j == min(lost) + len(lost):  # the first block after the gap
+                with pytest.raises(dd.DedispError) as e:
+                    strict.push(blk, seq=j)
+                assert e.value.code == -3
+            elif j < min(lost):
+                strict.push(blk, seq=j)
+            if r is None:
+                continue
+            got = r.out.cpu().numpy()
+            np.testing.assert_array_equal(got, one[:, r.t0:r.t0 + got.shape[1]])
+            seen.append((r.t0, got.shape[1]))
+        # the window after the gap starts past outputs that only the zeros made computable
+        starts = [t for t, n in seen]
+        assert starts == sorted(starts) and seen[-1][0] + seen[-1][1] == nblk * block - plan.maxdelay
+
+
 def test_candidate_overflow(torch, dd):
     _say("case: candidate overflow")
     b = fbsynth.config1()
@@ -210,7 +252,16 @@ def test_candidate_overflow(torch, dd):
     assert n > 100
     _, r = _run(torch, dd, b.freq_mhz, b.tsamp_s, b.dm, b.data, k=2.5, cap=37)
     assert r.ncand() == n
-    got = r.candidates()
+    # the synchronising check reports the overflow (DD_WARN_CAND_OVERFLOW) and the true count
+    import ctypes as C
+    from paper_1401_8258_amd import _lib
+    cnt = C.c_int64()
+    rc = _lib.load().dd_candidates_check(C.c_void_p(r._ncand.data_ptr()), 37,
+                                         C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(cnt))
+    assert rc == _lib.DD_WARN_CAND_OVERFLOW and cnt.value == n
+    assert _lib.load().dd_candidates_check(C.c_void_p(r._ncand.data_ptr()), n, None, C.byref(cnt)) == _lib.DD_OK
+    with pytest.warns(dd.CandidateOverflow):
+        got = r.candidates()
     assert got.size == 37
     np.testing.assert_array_equal(got["dm_index"], full["dm_index"][:37])
     np.testing.assert_array_equal(got["t"], full["t"][:37])
