@@ -192,6 +192,23 @@ int dd_dedisperse(const dd_plan* plan, const void* d_in, int64_t nsamp, int64_t 
                   void* d_workspace, int64_t ws_bytes, void* stream);
 
 /*
+ * dd_dedisperse for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation,
+ * arguments and errors, with the delay table passed in (d_table: a buffer prepared once by
+ * dd_plan_upload, read only) and the rest of the workspace (statistics partials,
+ * thresholds, candidate counts and offsets, the u8 input-tail copy) taken from a static
+ * device array of 96 MiB inside the library. The call makes no hipMalloc, hipFree or other
+ * allocation. Each device the library runs on holds its own copy of the array until the
+ * process ends; every call on a device shares it, so calls that overlap on one device
+ * (on one stream or several) race and must not be issued. Nothing in the array needs to
+ * start at zero. DD_ERR_UNSUPPORTED when the shape needs more scratch than the array holds
+ * (the full 1024-channel, 2^20-sample, 2048-trial FP32 workload needs 67 MiB).
+ */
+int dd_dedisperse_noalloc(const dd_plan* plan, const void* d_in, int64_t nsamp, int64_t in_row_stride,
+                          float* d_out, int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma,
+                          dd_cand* d_cand, int64_t cand_cap, int64_t* d_ncand, const void* d_table, void* stream);
+
+/*
  * Streaming (Ch. 3 Sec. "Dedispersion": the last maxshift spectra of a buffer are
  * carried into the next). A stream keeps a per-channel device ring of the last
  * maxdelay + block_nsamp samples (rounded up to 64), each row followed by a mirror of

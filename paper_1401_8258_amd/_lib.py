@@ -64,6 +64,7 @@ SIGNATURES = {
     "dd_plan_delays": (C.c_int, [_P, C.POINTER(_I32)]),
     "dd_plan_upload": (C.c_int, [_P, _P, _I64, _P]),
     "dd_dedisperse": (C.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, _P, _F32, _P, _I64, _P, _P, _I64, _P]),
+    "dd_dedisperse_noalloc": (C.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, _P, _F32, _P, _I64, _P, _P, _P]),
     "dd_stream_create": (C.c_int, [_P, _I64, _P, _I64, _P, C.POINTER(_P)]),
     "dd_stream_push": (C.c_int, [_P, _P, _I64, _I64, _I64, _P, _I64, _P, _P, _F32, _P, _I64, _P, _P, _I64,
                                  _P, C.POINTER(_I64), C.POINTER(_I64)]),

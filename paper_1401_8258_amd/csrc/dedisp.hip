@@ -27,6 +27,7 @@
 #include <vector>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "dd_internal.h"
@@ -943,6 +944,13 @@ __global__ __launch_bounds__(256) void ring_zero(TIn* __restrict__ ring, int64_t
   }
 }
 
+// Scratch of the entry point that allocates nothing (dd_dedisperse_noalloc): the statistics
+// partials, thresholds, candidate counts and offsets and the u8 input-tail copy that
+// dd_dedisperse keeps in the caller's workspace. Each device the library runs on holds one
+// copy until the process ends; every call on that device shares it.
+constexpr int64_t kScratchBytes = int64_t(96) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 // ------------------------------------------------------------------ host side
 
 using KernFn = void (*)(KParams);
@@ -1149,6 +1157,55 @@ int dd_dedisperse(const dd_plan* p, const void* d_in, int64_t nsamp, int64_t in_
   Outputs o{d_out, out_row_stride, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand, 0};
   char* ws = static_cast<char*>(d_workspace);
   return run_pipeline(p, in, reinterpret_cast<const int32_t*>(ws + l.table_off), nout, o, ws, l,
+                      static_cast<hipStream_t>(stream));
+}
+
+int dd_dedisperse_noalloc(const dd_plan* p, const void* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
+                          int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,
+                          int64_t cand_cap, int64_t* d_ncand, const void* d_table, void* stream) {
+  dd::clear_error();
+  if (!p || !d_in || !d_table) return dd::fail(DD_ERR_INVALID_ARG, "plan, input and device table are required");
+  if (nsamp <= p->maxdelay)
+    return dd::fail(DD_ERR_TOO_SHORT, "nsamp must exceed maxdelay (" + std::to_string(p->maxdelay) + ")");
+  if (in_row_stride < nsamp) return dd::fail(DD_ERR_INVALID_ARG, "in_row_stride < nsamp");
+  const int64_t nout = nsamp - p->maxdelay;
+  int rc = check_outputs(p, d_out, out_row_stride, nout, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand);
+  if (rc) return rc;
+  // the workspace regions after the delay table, moved to the start of the scratch array
+  dd::WsLayout l = dd::workspace_layout(p, nsamp);
+  const int64_t base = l.part_off;
+  if (l.total - base > kScratchBytes)
+    return dd::fail(DD_ERR_UNSUPPORTED, "this call needs " + std::to_string(l.total - base) +
+                                            " bytes of scratch; the static scratch holds " +
+                                            std::to_string(kScratchBytes));
+  l.part_off -= base;
+  l.thr_off -= base;
+  l.cnt_off -= base;
+  l.offs_off -= base;
+  l.tail_off -= base;
+  l.total -= base;
+  // the array's device address, looked up once per device with that device current (the
+  // array's name is a host-side stand-in, not a device address)
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return dd::fail(DD_ERR_UNSUPPORTED, "device index beyond 63");
+  void* sp = nullptr;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+      void* a = nullptr;
+      e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !a) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+      addr[dev] = a;
+    }
+    sp = addr[dev];
+  }
+  InView in{d_in, in_row_stride, nsamp, 0, 0};
+  Outputs o{d_out, out_row_stride, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand, 0};
+  return run_pipeline(p, in, static_cast<const int32_t*>(d_table), nout, o, static_cast<char*>(sp), l,
                       static_cast<hipStream_t>(stream));
 }
 
