@@ -137,7 +137,7 @@ def batch_run(reps):
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     tb = autotune.tune_batch(beams, waves=(8, 4, 2, 1), stages=(0,), reps=1, inputs=xs, log=log)
     t_tune = time.perf_counter() - t_tune
-    plans = [dd.Plan(f, ts, dm, dtype="u8", tuning=tuple(t)) for (f, ts, dm, _, _), t in zip(beams, tb["tunings"])]
+    plans = [autotune.make_plan(f, ts, dm, "u8", c) for (f, ts, dm, _, _), c in zip(beams, tb["choices"])]
     outs = [dd.api.alloc_outputs(p.ndm, x.shape[1] - p.maxdelay, x.device, 6.0, 1 << 16) for p, x in zip(plans, xs)]
     jobs = list(zip(plans, xs))
 
@@ -162,8 +162,9 @@ def batch_run(reps):
     ms_batch = timed(batched)
     # each beam alone with its own best tiles (any wavefront count)
     log("batch: per-beam best tiles")
-    best = [autotune.tune(*b, waves=(8, 4, 2, 1), stages=(0,), reps=1, x=x)["tuning"] for b, x in zip(beams, xs)]
-    own = [dd.Plan(f, ts, dm, dtype="u8", tuning=tuple(t)) for (f, ts, dm, _, _), t in zip(beams, best)]
+    best = [autotune.tune(*b, waves=(8, 4, 2, 1), stages=(0,), reps=1, x=x) for b, x in zip(beams, xs)]
+    best = [{"form": r["form"], "tuning": r["tuning"]} for r in best]
+    own = [autotune.make_plan(f, ts, dm, "u8", c) for (f, ts, dm, _, _), c in zip(beams, best)]
     ms_own = timed(lambda: singles(own))
     ms_same = timed(lambda: singles(plans))
     trials_samples = sum(p.ndm * (x.shape[1] - p.maxdelay) for p, x in zip(plans, xs))
@@ -173,7 +174,7 @@ def batch_run(reps):
             "higher_is_better": True, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "16 uneven u8 beams (nchan 256/512/1024/4096, 500-4096 DMs, nsamp 2^16-2^19) "
                                    "in one persistent launch, stats + 6-sigma candidates",
-                       "common_waves": tb["waves"], "tunings": tb["tunings"], "tune_s": round(t_tune, 1)},
+                       "common_waves": tb["waves"], "tunings": tb["choices"], "tune_s": round(t_tune, 1)},
             "adds_per_s": adds / (ms_batch * 1e-3),
             "one_at_a_time_same_tiles_ms": round(ms_same, 3),
             "one_at_a_time_own_best_tiles_ms": round(ms_own, 3), "own_best_tilings": best}

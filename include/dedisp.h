@@ -74,19 +74,31 @@ enum {
 /* Input storage types. All accumulate in FP32. */
 enum { DD_F32 = 0, DD_F16 = 1, DD_U8 = 2 };
 
-/* Kernel forms of the dedispersion step (dd_tuning.kernel_form). Both compute the same
-   sums in the same order, so their series are identical bit for bit; their statistics
-   partials group the FP64 additions differently (last-bit differences in mean/rms). */
+/* Kernel forms of the dedispersion step (dd_tuning.kernel_form). All compute the same
+   sums in the same order (for 8-bit input the sums are exact integers), so their series
+   are identical bit for bit; their statistics partials may group the FP64 additions
+   differently (last-bit differences in mean/rms for FP32 and FP16 input). */
 enum {
   DD_FORM_AUTO = 0,
   DD_FORM_LDS = 1,     /* each channel staged in LDS as four copies shifted by 0..3 samples;
                           every add reads its sample from LDS (all dtypes, any delay spread) */
-  DD_FORM_REGWIN = 2   /* FP32 only: each channel staged once; each lane loads a window of up
+  DD_FORM_REGWIN = 2,  /* FP32 only: each channel staged once; each lane loads a window of up
                           to 48 samples into registers and the 8 DM trials of its wavefront
                           add from it at their (wave-uniform) offsets. Needs the delay spread
                           of 8 consecutive trials plus 7 to stay within 40 samples in every
                           channel; groups of 64 trials, tuning fields other than the form
                           are ignored */
+  DD_FORM_DIRECT = 3   /* 8-bit input only: nothing staged in LDS; the input is held as four
+                          copies shifted by 0..3 samples (in the workspace for dd_dedisperse,
+                          in the ring for streams: 4x the bytes of one copy), and per channel
+                          each wavefront reads its trials' 1024-byte windows straight through
+                          the L1/L2 caches (16 bytes per lane per trial, 4-byte aligned) and
+                          sums them as exact integers. Suits beams whose delays grow by many
+                          samples per trial (low frequencies, wide bands), where an LDS window
+                          is shared by few trials. dms_per_wave 1, 2 or 4 (default 2), waves
+                          1..8 (default 4), samples_per_lane 16; chan_stage and
+                          producer_waves are ignored. Batched items of this form run in one
+                          launch beside the LDS-form items' launch */
 };
 
 typedef struct dd_plan dd_plan;
@@ -106,10 +118,11 @@ typedef struct dd_tuning {
                                  (every wavefront issues its share of the DMAs), 1..4
                                  (waves + producer_waves <= 8; DD_ERR_UNSUPPORTED when the
                                  windows do not fit) */
-  int32_t kernel_form;        /* DD_FORM_AUTO (the register-window form for FP32 input when the
-                                 delay spread allows and no other field is set, else the LDS
-                                 form), DD_FORM_LDS, or DD_FORM_REGWIN (DD_ERR_UNSUPPORTED for
-                                 other dtypes or a spread that does not fit) */
+  int32_t kernel_form;        /* DD_FORM_AUTO (the direct-read form for 8-bit input when no
+                                 LDS-form tile field is set, else the LDS form), DD_FORM_LDS,
+                                 DD_FORM_REGWIN (DD_ERR_UNSUPPORTED for
+                                 other dtypes or a spread that does not fit) or DD_FORM_DIRECT
+                                 (DD_ERR_UNSUPPORTED for other than 8-bit input) */
 } dd_tuning;
 
 typedef struct dd_plan_info {
@@ -127,8 +140,11 @@ typedef struct dd_plan_info {
      workgroup */
   int32_t launch_copies, launch_buf, launch_stage, launch_ring;
   int64_t launch_lds;
-  int32_t kernel_form;              /* DD_FORM_LDS or DD_FORM_REGWIN */
+  int32_t kernel_form;              /* DD_FORM_LDS, DD_FORM_REGWIN or DD_FORM_DIRECT */
   int32_t window_chunks;            /* DD_FORM_REGWIN: 4-sample chunks per register window */
+  int64_t stream_workspace_bytes;   /* for dd_stream_push on a stream of block_nsamp = nsamp
+                                       (at most workspace_bytes: the direct-read form's copies
+                                       of a plain call's input live in a stream's ring) */
 } dd_plan_info;
 
 /* One detection: (time, DM, intensity) of Ch. 3, plus (value - mean) / rms. */

@@ -8,4 +8,4 @@ from ._lib import LibraryMissing, DedispError, load as load_library  # noqa: F40
 from .api import (Plan, Stream, Result, CandidateOverflow, CAND_DTYPE, batch_dedisperse, detrend, boxcar, downfactor,  # noqa: F401
                   time_binning, BinnedPlan, BinnedResult, bandpass, bandpass_fit, rfi_mitigate, SubbandPlan)
 
-__version__ = "1.3"
+__version__ = "1.4"

@@ -16,7 +16,7 @@ DD_ERR_WORKSPACE = -4
 DD_ERR_HIP = -5
 DD_ERR_UNSUPPORTED = -6
 DD_F32, DD_F16, DD_U8 = 0, 1, 2
-DD_FORM_AUTO, DD_FORM_LDS, DD_FORM_REGWIN = 0, 1, 2
+DD_FORM_AUTO, DD_FORM_LDS, DD_FORM_REGWIN, DD_FORM_DIRECT = 0, 1, 2, 3
 CHAN_BLOCK = 32
 
 
@@ -35,7 +35,8 @@ class PlanInfo(C.Structure):
                 ("adds", C.c_int64), ("chan_stage", C.c_int32), ("producer_waves", C.c_int32),
                 ("launch_copies", C.c_int32), ("launch_buf", C.c_int32), ("launch_stage", C.c_int32),
                 ("launch_ring", C.c_int32), ("launch_lds", C.c_int64),
-                ("kernel_form", C.c_int32), ("window_chunks", C.c_int32)]
+                ("kernel_form", C.c_int32), ("window_chunks", C.c_int32),
+                ("stream_workspace_bytes", C.c_int64)]
 
 
 class Cand(C.Structure):

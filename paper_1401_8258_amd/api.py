@@ -23,8 +23,11 @@ CAND_DTYPE = np.dtype([("dm_index", "<i4"), ("reserved", "<i4"), ("t", "<i8"), (
 _TORCH_DT = {torch.float32: _lib.DD_F32, torch.float16: _lib.DD_F16, torch.uint8: _lib.DD_U8}
 _NAME_DT = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}
 # kernel forms (dd_tuning.kernel_form): "lds" stages four shifted copies per channel and reads
-# one LDS word per add; "regwin" (FP32) stages one copy and adds from register windows
-_FORMS = {"auto": _lib.DD_FORM_AUTO, "lds": _lib.DD_FORM_LDS, "regwin": _lib.DD_FORM_REGWIN}
+# one LDS word per add; "regwin" (FP32) stages one copy and adds from register windows;
+# "direct" (8-bit) reads each trial's window through the caches with no LDS staging
+_FORMS = {"auto": _lib.DD_FORM_AUTO, "lds": _lib.DD_FORM_LDS, "regwin": _lib.DD_FORM_REGWIN,
+          "direct": _lib.DD_FORM_DIRECT}
+_FORM_NAMES = {v: k for k, v in _FORMS.items()}
 
 
 def _vp(t: Optional[torch.Tensor]):
@@ -98,7 +101,7 @@ class Plan:
             g, w = int(tuning[0]), int(tuning[1])
             cc = int(tuning[2]) if len(tuning) > 2 else 0
             pw = int(tuning[3]) if len(tuning) > 3 else 0
-            tun = C.byref(_lib.Tuning(g, w, 8, cc, pw, kf))
+            tun = C.byref(_lib.Tuning(g, w, 0, cc, pw, kf))
         elif kf != _lib.DD_FORM_AUTO:
             tun = C.byref(_lib.Tuning(0, 0, 0, 0, 0, kf))
         dbl = C.POINTER(C.c_double)
@@ -111,7 +114,7 @@ class Plan:
         self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(info["chan_stage"]))
         self.producer_waves = int(info["producer_waves"])
         self.max_span = int(info["max_span"])
-        self.form = {_lib.DD_FORM_LDS: "lds", _lib.DD_FORM_REGWIN: "regwin"}[int(info["kernel_form"])]
+        self.form = _FORM_NAMES[int(info["kernel_form"])]
 
     @property
     def handle(self) -> C.c_void_p:
@@ -196,7 +199,7 @@ class Stream:
         self.device = device
         info = plan.query(self.block, allow_short=True)
         self.ring = torch.empty(int(info["ring_bytes"]), dtype=torch.uint8, device=device)
-        self.ws = torch.empty(int(info["workspace_bytes"]), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(int(info["stream_workspace_bytes"]), dtype=torch.uint8, device=device)
         h = C.c_void_p()
         check(self._lib.dd_stream_create(plan.handle, self.block, _vp(self.ring), int(self.ring.numel()),
                                          _stream(stream), C.byref(h)))

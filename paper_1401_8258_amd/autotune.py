@@ -1,12 +1,14 @@
 """Autotuner for the dedispersion tiles (kernel form, wavefronts per DM group, channels per
-LDS stage).
+LDS stage, DM trials per wavefront).
 
 The thesis tuned its kernel by sweeping accumulators per thread and threads per
 block on the target GPU (Ch. 2, Sec. Performance and Benchmarks). Here the
 tunables are the kernel form ("lds": every add reads LDS, lanes own 2 x 4 samples,
 DM groups of 8 x waves trials; "regwin", FP32: lanes own 8 consecutive samples held
-in a register window, DM groups of 64 trials), the number of wavefronts (8 DM
-trials each) sharing one LDS ring and the channels staged per ring slot. ``tune``
+in a register window, DM groups of 64 trials; "direct", 8-bit: lanes own 16
+samples read through the caches, DM groups of g x waves trials with g in 1, 2, 4),
+the number of wavefronts sharing one LDS ring or workgroup and the channels staged
+per ring slot. ``tune``
 times every candidate on seeded random input of the beam's shape and keeps the
 fastest; ``tune_batch`` picks the wavefront count that minimises the summed time
 of a set of beams (a batched launch needs one count for all its items), with each
@@ -27,7 +29,8 @@ from .api import Plan, torch_dtype
 
 WAVES = (8, 4, 2, 1)
 STAGES = (0, 2, 4)
-FORMS = ("lds",)
+FORMS = ("lds", "direct")
+DIRECT_G = (1, 2, 4)  # DM trials per wavefront of the direct-read form
 
 
 def _key(freq, tsamp, dm, dtype, nsamp) -> str:
@@ -95,17 +98,22 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
          reps: int = 3, cache: Optional[TuneCache] = None, x: Optional[torch.Tensor] = None,
          forms: Sequence[str] = FORMS, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan) -> dict:
     """The fastest of the candidate tilings for one beam shape: {"form", "tuning", "ms",
-    "trials"} ("tuning" is (dms_per_wave, waves, chan_stage) for the LDS form, None for the
-    register-window form, whose groups are fixed at 8 x 8 trials)."""
+    "trials"} ("tuning" is (dms_per_wave, waves, chan_stage) for the LDS form, (dms_per_wave,
+    waves) for the direct-read form, None for the register-window form, whose groups are
+    fixed at 8 x 8 trials)."""
     key = _key(freq, tsamp, dm, str(dtype), nsamp) + f":{tuple(waves)}:{tuple(stages)}:{tuple(forms)}"
     if cache is not None and cache.get(key):
         return cache.get(key)
     if x is None:
         x = synthetic_input(len(freq), nsamp, dtype)
     cands = []
+    u8 = torch_dtype(dtype) == torch.uint8
     for form in forms:
         if form == "regwin":
             cands.append({"form": "regwin", "tuning": None})
+        elif form == "direct":
+            if u8:  # the direct-read form takes 8-bit input only
+                cands += [{"form": "direct", "tuning": [g, w]} for w in waves for g in DIRECT_G]
         else:
             cands += [{"form": "lds", "tuning": [8, w, cc]} for w in waves for cc in stages]
     trials = []
@@ -132,8 +140,9 @@ def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequenc
                log=None, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan) -> dict:
     """One wavefront count for a batch; per beam the best stage size under it.
 
-    beams: (freq, tsamp, dm, dtype, nsamp) per beam. Returns {"waves": w, "tunings": [...],
-    "total_ms": t, "by_waves": {w: t}}.
+    beams: (freq, tsamp, dm, dtype, nsamp) per beam. Returns {"waves": w, "choices": [...],
+    "tunings": [...], "total_ms": t, "by_waves": {w: t}}: per beam its choice ({"form",
+    "tuning"}, what make_plan takes) and the tuning alone.
     """
     per_w: Dict[int, List[dict]] = {}
     for w in waves:
@@ -153,5 +162,5 @@ def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequenc
     if not totals:
         raise RuntimeError("no common wavefront count fits every beam")
     wbest = min(totals, key=totals.get)
-    return {"waves": wbest, "tunings": [r["tuning"] for r in per_w[wbest]], "total_ms": totals[wbest],
-            "by_waves": totals}
+    return {"waves": wbest, "choices": [{"form": r["form"], "tuning": r["tuning"]} for r in per_w[wbest]],
+            "tunings": [r["tuning"] for r in per_w[wbest]], "total_ms": totals[wbest], "by_waves": totals}

@@ -7,6 +7,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(PKG, "csrc", "dedisp.hip"), os.path.join(PKG, "csrc", "regwin.hip"),
+       os.path.join(PKG, "csrc", "direct.hip"),
        os.path.join(PKG, "csrc", "detrend.hip"),
        os.path.join(PKG, "csrc", "boxcar.hip"), os.path.join(PKG, "csrc", "downfactor.hip"),
        os.path.join(PKG, "csrc", "rfi.hip"),

@@ -6,19 +6,10 @@
 
 #include <cstdint>
 
+#include "dd_internal.h"
+
 namespace dd {
 
-// Input view: linear rows, or a per-channel ring of ring_len samples in which
-// window position p lives at (win0 + p) mod ring_len. A ring row continues past
-// ring_len with a mirror of its start, so a window read from any start in
-// [0, ring_len) is contiguous.
-struct InView {
-  const void* ptr;
-  int64_t row_stride;  // elements between channel rows (ring: ring_len + mirror)
-  int64_t nvalid;      // window positions [0, nvalid) hold data
-  int64_t ring_len;    // 0 for linear input
-  int64_t win0;        // ring only: global sample of window position 0
-};
 
 typedef const __attribute__((address_space(4))) int32_t* ci32_t;
 

@@ -15,6 +15,8 @@ constexpr int64_t kAlign = 256;
 // the per-series statistics partials (fixed, so the reduction tree does not
 // depend on the launch shape or on batching).
 constexpr int64_t kTile = 512;
+// Output samples per tile of the direct-read form (16 per lane): two statistics segments.
+constexpr int64_t kDirectTile = 1024;
 // Output samples per candidate-compaction segment.
 constexpr int64_t kStatSeg = 8192;
 // LDS of one gfx950 workgroup.
@@ -33,6 +35,7 @@ constexpr int kRwMaxChunks = 12;
 // Kernel forms (dd_tuning.kernel_form / dd_plan_info.kernel_form).
 constexpr int kFormLds = 1;     // four shifted copies per channel in LDS, one LDS word per add
 constexpr int kFormRegWin = 2;  // one copy per channel, register windows added in VGPR index mode
+constexpr int kFormDirect = 3;  // 8-bit input read per trial through the caches, no LDS
 // DD_FORM_AUTO picks the register-window form for FP32 plans it fits.
 constexpr bool kAutoRegWin = false;
 
@@ -48,8 +51,9 @@ struct Launch {
   int64_t lds;  // bytes
   int prod;     // wavefronts that only issue DMAs (0: every wavefront issues its share)
   int ndw;      // DMA instructions per issuing wavefront per stage (the vmcnt unit)
-  int form;     // kFormLds or kFormRegWin; for kFormRegWin, L is the samples a slot's DMAs
-                // cover, nd the 16-byte DMAs per slot, cs = kRwStage
+  int form;     // kFormLds, kFormRegWin or kFormDirect; for kFormRegWin, L is the samples a
+                // slot's DMAs cover, nd the 16-byte DMAs per slot, cs = kRwStage; for
+                // kFormDirect, L is the samples one wavefront load spans (the tile)
   int nch;      // kFormRegWin: 4-sample chunks per window (6, 8, 10 or 12)
 };
 Launch choose_launch(int32_t max_span, int nw, int nchan, int cs_req, int64_t lds_cap, int elem_bytes);
@@ -114,26 +118,70 @@ struct WsLayout {
   int64_t offs_off;    // int64 [ndm][nseg]
   int64_t tail_off;    // 8-bit input: copy of the last tail_bytes of the input, then as many
   int64_t tail_bytes;  // bytes of padding (a window starting in the copy reads at most that far)
+  int64_t quad_off;    // direct-read form, linear input: the four shifted copies of the input
+  int64_t quad_bytes;
   int64_t nseg;        // candidate segments
   int64_t ntile;       // statistics segments
   int64_t total;
 };
-WsLayout workspace_layout(const dd_plan* p, int64_t nout);
+// Workspace of a call on n samples: linear input (dd_dedisperse) or a stream push of at
+// most n samples (no region for the direct-read form's copies, which the ring holds).
+WsLayout workspace_layout(const dd_plan* p, int64_t n, bool linear = true);
 int64_t ring_table_bytes(const dd_plan* p);
 // Samples after a ring row's R that mirror its start, so no channel window the kernel
 // reads (at most launch.L + 3 samples from any start in [0, R)) wraps.
 inline int64_t ring_mirror(const dd_plan* p) { return (int64_t)p->launch.L + 64; }
 inline int64_t ring_len_for(const dd_plan* p, int64_t block) { return align_up(block + (int64_t)p->maxdelay, 64); }
+// Rows a stream's ring keeps per channel: the direct-read form keeps its four shifted copies.
+inline int64_t ring_copies(const dd_plan* p) { return p->launch.form == kFormDirect ? 4 : 1; }
 int64_t elem_bytes(int32_t dtype);
 // kFormRegWin device table: [ngroups][nchan] group first delays, then from this int32
 // offset [ngroups][nchan][8 wavefronts] int4 {window byte offset, trial indices 0-3, 4-7, 0},
 // followed by kRwStage - 1 channels of zero records.
 bool plan_regwin(dd_plan* p, int64_t lds_cap);
 inline int64_t rw_meta_offset(const dd_plan* p) { return ((int64_t)p->ngroups * p->nchan + 3) / 4 * 4; }
-struct InView;
+// Input view: linear rows, or a per-channel ring of ring_len samples in which
+// window position p lives at (win0 + p) mod ring_len. A ring row continues past
+// ring_len with a mirror of its start, so a window read from any start in
+// [0, ring_len) is contiguous.
+struct InView {
+  const void* ptr;
+  int64_t row_stride;  // elements between channel rows (ring: ring_len + mirror)
+  int64_t nvalid;      // window positions [0, nvalid) hold data
+  int64_t ring_len;    // 0 for linear input
+  int64_t win0;        // ring only: global sample of window position 0
+};
 // Launch of the register-window kernel for nout outputs (statistics partials into part
 // when non-null); defined with the kernel.
 int launch_regwin(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, float* out,
                   int64_t out_stride, double* part, void* stream);
+// Direct-read form (8-bit input): device table [nchan][ndm_pad] of plain delays (padded trials
+// repeat the last DM). Fills the plan's tiles, groups, launch and table.
+int plan_direct(dd_plan* p, const Tiles& t);
+// Bytes per copy row of the direct-read form's copies of an nsamp-sample linear input: the
+// last tile's windows read at most kDirectTile bytes past the last sample's position.
+inline int64_t direct_quad_row(int64_t nsamp) { return align_up(nsamp + kDirectTile + 64, 64); }
+// Linear input: writes the copies into quad_ws first. Ring input: in.ptr is the ring's
+// copies, in.row_stride their row length.
+int launch_direct(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, float* out,
+                  int64_t out_stride, double* part, void* quad_ws, void* stream);
+// One item of a batched direct-read launch (what launch_direct takes).
+struct DirectItem {
+  const dd_plan* plan;
+  InView in;
+  const int32_t* table;
+  int64_t nout;
+  float* out;
+  int64_t out_stride;
+  double* part;
+  void* quad_ws;
+};
+// Bytes of device descriptors a batched direct-read launch of n items uploads.
+int64_t direct_batch_desc_bytes(int32_t n);
+int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int64_t desc_bytes, void* stream);
+// n samples of a block (zeros when blk is null) into a direct-read stream ring of copy rows
+// of lq bytes, starting at ring position pos0.
+int append_direct(const dd_plan* p, const void* blk, int64_t in_stride, int64_t n, void* ring, int64_t lq,
+                  int64_t ring_len, int64_t pos0, void* stream);
 
 }  // namespace dd

@@ -1090,9 +1090,11 @@ int set_lds(const void* k, int64_t lds) {
 // Dedisperse nout outputs of a prepared input view, then stats and candidates.
 int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, const Outputs& o,
                  char* ws, const dd::WsLayout& l, hipStream_t st) {
-  if (p->launch.form == dd::kFormRegWin) {
+  if (p->launch.form == dd::kFormRegWin || p->launch.form == dd::kFormDirect) {
     double* part = (o.mean && o.rms) ? reinterpret_cast<double*>(ws + l.part_off) : nullptr;
-    int rc = dd::launch_regwin(p, in, d_table, nout, o.out, o.out_stride, part, st);
+    int rc = p->launch.form == dd::kFormRegWin
+                 ? dd::launch_regwin(p, in, d_table, nout, o.out, o.out_stride, part, st)
+                 : dd::launch_direct(p, in, d_table, nout, o.out, o.out_stride, part, ws + l.quad_off, st);
     if (rc) return rc;
     return launch_tail(p, nout, o, ws, l, st);
   }
@@ -1183,6 +1185,7 @@ int dd_dedisperse_noalloc(const dd_plan* p, const void* d_in, int64_t nsamp, int
   l.cnt_off -= base;
   l.offs_off -= base;
   l.tail_off -= base;
+  l.quad_off -= base;
   l.total -= base;
   // the array's device address, looked up once per device with that device current (the
   // array's name is a host-side stand-in, not a device address)
@@ -1254,6 +1257,7 @@ int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t i
   char* ring = static_cast<char*>(s->ring) + dd::ring_table_bytes(p);
   const int64_t mirror = s->ring_row - s->ring_len;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool quad = p->launch.form == dd::kFormDirect;
   if (seq > s->next_seq) {
     // lost blocks: block samples of zeros each; only the last ring length of them can still
     // be read, so only those are written
@@ -1261,7 +1265,10 @@ int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t i
     const int64_t nz = std::min<int64_t>(missing, s->ring_len);
     const int64_t zpos = (s->received + missing - nz) % s->ring_len;
     dim3 zgrid((unsigned)std::min<int64_t>((nz + 255) / 256, 1024), (unsigned)p->nchan);
-    if (p->dtype == DD_F32)
+    if (quad) {
+      int rz = dd::append_direct(p, nullptr, 0, nz, ring, s->ring_row, s->ring_len, zpos, st);
+      if (rz) return rz;
+    } else if (p->dtype == DD_F32)
       hipLaunchKernelGGL(ring_zero<float>, zgrid, dim3(256), 0, st, reinterpret_cast<float*>(ring), s->ring_row,
                          s->ring_len, mirror, zpos, nz);
     else if (p->dtype == DD_F16)
@@ -1281,7 +1288,10 @@ int dd_stream_append(dd_stream* s, const void* d_block, int64_t nsamp, int64_t i
   const int64_t pos0 = s->received % s->ring_len;
   const unsigned gx = (unsigned)std::min<int64_t>((nsamp + 255) / 256, 1024);
   dim3 grid(gx, (unsigned)p->nchan);
-  if (p->dtype == DD_F32)
+  if (quad) {
+    int ra = dd::append_direct(p, d_block, in_row_stride, nsamp, ring, s->ring_row, s->ring_len, pos0, st);
+    if (ra) return ra;
+  } else if (p->dtype == DD_F32)
     hipLaunchKernelGGL(ring_append<float>, grid, dim3(256), 0, st, static_cast<const float*>(d_block), in_row_stride,
                        nsamp, reinterpret_cast<float*>(ring), s->ring_row, s->ring_len, mirror, pos0);
   else if (p->dtype == DD_F16)
@@ -1337,7 +1347,7 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
   const dd_plan* p = s->plan;
   int rc = check_outputs(p, d_out, out_row_stride, s->block, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand);
   if (rc) return rc;
-  const dd::WsLayout l = dd::workspace_layout(p, s->block);
+  const dd::WsLayout l = dd::workspace_layout(p, s->block, false);
   if (ws_bytes < l.total) return dd::fail(DD_ERR_WORKSPACE, "workspace smaller than dd_plan_query asks for");
   int64_t t0 = 0, n = 0;
   rc = dd_stream_append(s, d_block, nsamp, in_row_stride, seq, stream, &t0, &n);
@@ -1356,7 +1366,9 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
 int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes) {
   dd::clear_error();
   if (!ws_bytes || n < 1 || !items) return dd::fail(DD_ERR_INVALID_ARG, "need items, n >= 1 and ws_bytes");
-  *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * (n + 1) * 8);
+  // descriptors of the LDS-form launch, then of the direct-read launch
+  *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * (n + 1) * 8) +
+              dd::direct_batch_desc_bytes(n);
   return DD_OK;
 }
 
@@ -1367,8 +1379,8 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   if (rc) return rc;
   if (!d_workspace || ws_bytes < need) return dd::fail(DD_ERR_WORKSPACE, "batch workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  std::vector<KParams> P((size_t)n);
-  std::vector<int64_t> start((size_t)8 * (n + 1), 0);  // [xcd][item]
+  std::vector<KParams> P;  // LDS-form items
+  std::vector<dd::DirectItem> direct;  // direct-read items
   std::vector<Outputs> outs((size_t)n);
   std::vector<int64_t> nouts((size_t)n);
   std::vector<dd::WsLayout> lays((size_t)n);
@@ -1383,10 +1395,13 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     if (p->launch.form == dd::kFormRegWin)
       return dd::fail(DD_ERR_UNSUPPORTED, "batch item " + std::to_string(i) +
                                               ": register-window plans are not batched; use DD_FORM_LDS");
-    if (dtype < 0) dtype = p->dtype, waves = p->tiles.w, prod = p->launch.prod;
-    if (p->dtype != dtype || p->tiles.w != waves || p->launch.prod != prod)
-      return dd::fail(DD_ERR_UNSUPPORTED, "batch items must share the input dtype, the DM trials per workgroup "
-                                          "and the producer wavefront count");
+    const bool is_direct = p->launch.form == dd::kFormDirect;
+    if (!is_direct) {
+      if (dtype < 0) dtype = p->dtype, waves = p->tiles.w, prod = p->launch.prod;
+      if (p->dtype != dtype || p->tiles.w != waves || p->launch.prod != prod)
+        return dd::fail(DD_ERR_UNSUPPORTED, "LDS-form batch items must share the input dtype, the DM trials per "
+                                            "workgroup and the producer wavefront count");
+    }
     InView in;
     const int32_t* table;
     int64_t nout, t_base = 0, lay_n;
@@ -1412,7 +1427,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     rc = check_outputs(p, it.d_out, it.out_row_stride, nout, it.d_mean, it.d_rms, it.k_sigma, it.d_cand,
                        it.cand_cap, it.d_ncand);
     if (rc) return dd::fail(rc, "batch item " + std::to_string(i) + ": " + dd_last_error());
-    lays[i] = dd::workspace_layout(p, lay_n);
+    lays[i] = dd::workspace_layout(p, lay_n, sp == nullptr);
     // every item writes statistics partials, candidate counts and (u8) an input-tail copy into
     // its workspace, so two items sharing workspace bytes would overwrite each other; checked
     // before anything is enqueued
@@ -1426,46 +1441,60 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     outs[i] = Outputs{it.d_out, it.out_row_stride, it.d_mean, it.d_rms, it.k_sigma, it.d_cand, it.cand_cap,
                       it.d_ncand, t_base};
     nouts[i] = nout;
+    if (is_direct) {
+      double* part = (it.d_mean && it.d_rms) ? reinterpret_cast<double*>(ws + lays[i].part_off) : nullptr;
+      direct.push_back(dd::DirectItem{p, in, table, nout, it.d_out, it.out_row_stride, part, ws + lays[i].quad_off});
+      continue;
+    }
     dd::Launch g;
-    rc = build_params(p, in, table, nout, outs[i], ws, lays[i], &P[i], &g);
+    KParams kp;
+    rc = build_params(p, in, table, nout, outs[i], ws, lays[i], &kp, &g);
     if (rc) return rc;
-    rc = copy_tail(P[i], st);
+    rc = copy_tail(kp, st);
     if (rc) return rc;
+    P.push_back(kp);
     lds = std::max(lds, g.lds);
   }
-  int64_t units = 0;
-  for (int x = 0; x < 8; ++x) {
-    int64_t* sx = &start[(size_t)x * (n + 1)];
-    for (int32_t i = 0; i < n; ++i) {
-      const int64_t ntiles = P[i].nitems / P[i].ngroups;
-      const int64_t mine = ntiles > x ? (ntiles - x + 7) / 8 : 0;  // tiles x, x + 8, ...
-      sx[i + 1] = sx[i] + mine * P[i].ngroups;
-    }
-    units = std::max(units, sx[n]);
-  }
   char* bw = static_cast<char*>(d_workspace);
-  KParams* dP = reinterpret_cast<KParams*>(bw);
-  int64_t* dS = reinterpret_cast<int64_t*>(bw + dd::align_up((int64_t)n * (int64_t)sizeof(KParams)));
-  hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(KParams), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dS, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch descriptors)");
-  int form = -1;
-  for (int32_t i = 0; i < n; ++i) {
-    const int f = P[i].nprod > 0 ? kProd : P[i].x4 ? kX4 : kX1;
-    form = form < 0 || form == f ? f : kAny;  // producer counts already agree across items
+  const int64_t lds_desc = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * (n + 1) * 8);
+  if (!P.empty()) {
+    const int32_t m = (int32_t)P.size();
+    std::vector<int64_t> start((size_t)8 * (m + 1), 0);  // [xcd][item]
+    int64_t units = 0;
+    for (int x = 0; x < 8; ++x) {
+      int64_t* sx = &start[(size_t)x * (m + 1)];
+      for (int32_t i = 0; i < m; ++i) {
+        const int64_t ntiles = P[i].nitems / P[i].ngroups;
+        const int64_t mine = ntiles > x ? (ntiles - x + 7) / 8 : 0;  // tiles x, x + 8, ...
+        sx[i + 1] = sx[i] + mine * P[i].ngroups;
+      }
+      units = std::max(units, sx[m]);
+    }
+    KParams* dP = reinterpret_cast<KParams*>(bw);
+    int64_t* dS = reinterpret_cast<int64_t*>(bw + dd::align_up((int64_t)n * (int64_t)sizeof(KParams)));
+    hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(KParams), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dS, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch descriptors)");
+    int form = -1;
+    for (int32_t i = 0; i < m; ++i) {
+      const int f = P[i].nprod > 0 ? kProd : P[i].x4 ? kX4 : kX1;
+      form = form < 0 || form == f ? f : kAny;  // producer counts already agree across items
+    }
+    BatchFn k = pick_batch_kernel(dtype, form);
+    rc = set_lds((const void*)k, lds);
+    if (rc) return rc;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
+    // `units` is the largest per-XCD share
+    const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, units * 8) / 8 * 8);
+    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (waves + prod)), (size_t)lds, st, (const KParams*)dP,
+                       (const int64_t*)dS, (int)m);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "dedisp_batch launch");
   }
-  BatchFn k = pick_batch_kernel(dtype, form);
-  rc = set_lds((const void*)k, lds);
+  rc = dd::launch_direct_batch(direct, bw + lds_desc, ws_bytes - lds_desc, st);
   if (rc) return rc;
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
-  // `units` is the largest per-XCD share
-  const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, units * 8) / 8 * 8);
-  hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (waves + prod)), (size_t)lds, st, (const KParams*)dP,
-                     (const int64_t*)dS, (int)n);
-  e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "dedisp_batch launch");
   for (int32_t i = 0; i < n; ++i) {
     const dd_batch_item& it = items[i];
     const dd_plan* p = it.stream_item ? it.stream_item->plan : it.plan;

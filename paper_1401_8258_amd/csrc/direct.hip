@@ -1,0 +1,404 @@
+// Direct-read form of the dedispersion kernel for 8-bit input: gfx950, wave64.
+//
+// Eq. bruteEquation, D[d][t] = sum_c A[c][t + delay(c, d)], over one (1024-sample time
+// tile, group of G W DM trials) per workgroup of W wavefronts. Wavefront w owns trials
+// dg + G w .. dg + G w + G - 1; lane l owns output samples t0 + 16 l .. t0 + 16 l + 15.
+//
+// Nothing is staged in LDS. The input is held as four copies per channel, copy m shifted
+// by m samples (copy m at position p holds sample p + m), so a trial whose window starts
+// at sample s reads copy s & 3 at the 4-byte aligned position s - (s & 3). Per channel a
+// wavefront then reads, per trial, one aligned 16-byte buffer load per lane (1 KB per
+// wavefront) served by the L1 and L2 caches: the trials of a group and the groups of a
+// tile read overlapping windows. (Loads at byte-aligned offsets move about a quarter of
+// the bytes per clock that 4-byte aligned ones do, whatever their width.) This suits
+// beams whose delays grow by many samples per DM trial (low frequencies, wide bands),
+// where a window staged in LDS is shared by few trials. The loads of the next channel are
+// in flight while the current one is summed.
+//
+// Sums: each dword of four codes splits into the 16-bit pairs (s0, s2) and (s1, s3) with a
+// mask and a shift (plain VALU operations that issue at full rate); the pairs add with
+// 32-bit adds and fold into 32-bit sums every 256 channels (255 * 256 < 2^16), so the sums
+// are exact integers, equal to every other form's. The FP64 statistics partials of a
+// (trial, 512-sample segment) are sums of exact integers below 2^53, so they do not depend
+// on the order either.
+//
+// The copies: for a plain call a prep kernel writes them into the workspace, zero past the
+// input's end and long enough for every window of the last tile; a stream's ring holds
+// them directly (ring_append_quad), each copy a ring of the stream's ring length with a
+// mirror of at least a tile past its end, so no window wraps.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dd_internal.h"
+#include "dd_device.h"
+
+namespace {
+
+constexpr int kDrLane = 16;                // output samples per lane
+constexpr int kDrTile = 64 * kDrLane;      // output samples per tile
+static_assert(kDrTile == 2 * dd::kTile, "a tile is two statistics segments");
+static_assert(kDrTile == dd::kDirectTile, "tile disagrees with the plan");
+// Buffer resource word 3 for raw (unswizzled, stride 0) buffers on gfx9-family devices.
+constexpr int kRsrcWord3 = 0x00020000;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct DRParams {
+  const uint8_t* quad;  // [nchan][4][lq]: copy m of channel c at quad + (4 c + m) lq
+  int64_t lq;           // bytes per copy row
+  int64_t ring_len;     // stream ring length (0: linear input, no wrap)
+  int64_t w0;           // stream: ring position of window position 0
+  const int32_t* dtab;  // [nchan][ndm_pad] delay of each trial (padded trials repeat the last DM)
+  float* out;
+  double* part;         // [ndm][nseg][2] per 512-sample segment, or null
+  int64_t out_stride, nout, nitems, nseg;
+  int nchan, ndm, ndm_pad, ngroups;
+  int nw;               // wavefronts per workgroup
+  int tiles_g;          // DM trials per wavefront
+};
+static_assert(sizeof(DRParams) % 4 == 0, "DRParams is copied as dwords");
+
+template <int G>
+struct DirectTile {
+  uint32_t pr[G][8];    // 16-bit pairs: (s0, s2), (s1, s3) of dwords 0..3
+  uint32_t acc[G][16];  // per sample
+
+  __device__ __forceinline__ void fold() {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t a = pr[g][2 * k], b = pr[g][2 * k + 1];
+        acc[g][4 * k] += a & 0xffffu;
+        acc[g][4 * k + 2] += a >> 16;
+        acc[g][4 * k + 1] += b & 0xffffu;
+        acc[g][4 * k + 3] += b >> 16;
+        pr[g][2 * k] = 0u;
+        pr[g][2 * k + 1] = 0u;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void add(const u32x4 (&v)[G]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t x = v[g][k];
+        pr[g][2 * k] += x & 0x00ff00ffu;
+        pr[g][2 * k + 1] += (x >> 8) & 0x00ff00ffu;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void load(const DRParams& P, int c, int t0w, int lane, dd::ci32_t tab,
+                                       u32x4 (&v)[G]) {
+    const int64_t row4 = 4 * P.lq;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(P.quad + (int64_t)c * row4), (short)0, (int)row4, kRsrcWord3);
+    const dd::ci32_t drow = tab + (int64_t)c * P.ndm_pad;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      int s = t0w + drow[g];
+      if (P.ring_len && s >= (int)P.ring_len) s -= (int)P.ring_len;
+      const int m = s & 3;
+      v[g] = __builtin_amdgcn_raw_buffer_load_b128(rs, kDrLane * lane, m * (int)P.lq + (s - m), 0);
+    }
+  }
+
+  __device__ __forceinline__ void run(const DRParams& P, int64_t tile, int grp) {
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = tile * kDrTile;
+    const int dw = grp * G * P.nw + w * G;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[g][q] = 0u;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) acc[g][s] = 0u;
+    }
+    const dd::ci32_t tab = (dd::ci32_t)(P.dtab + dw);
+    const int t0w = (int)(t0 + P.w0);  // window position 0 of this tile (ring: < ring_len + tile)
+    const int nchan = P.nchan;
+    u32x4 va[G], vb[G];
+    load(P, 0, t0w, lane, tab, va);
+    // channel pairs (c, c + 1): the loads of the next channel are issued before the adds
+    for (int c = 0; c < nchan; c += 2) {
+      if (c + 1 < nchan) load(P, c + 1, t0w, lane, tab, vb);
+      if ((c & 255) == 0 && c != 0) fold();
+      add(va);
+      if (c + 1 >= nchan) break;
+      if (c + 2 < nchan) load(P, c + 2, t0w, lane, tab, va);
+      add(vb);
+    }
+    fold();
+
+    const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
+    const int64_t tb = t0 + kDrLane * lane;
+    const int64_t seg = 2 * tile + (lane >> 5);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int d = dw + g;
+      if (d >= P.ndm) break;
+      float x[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) x[s] = (float)acc[g][s];
+      float* orow = P.out + (int64_t)d * P.out_stride;
+      if (vec_ok && tb + 15 < P.nout) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<float4*>(orow + tb + 4 * q) = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+          if (tb + s < P.nout) orow[tb + s] = x[s];
+      }
+      if (P.part) {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          if (tb + s < P.nout) {
+            const double y = x[s];
+            s1 += y;
+            s2 += y * y;
+          }
+        }
+        // each half wavefront covers one 512-sample segment
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+          s1 += __shfl_xor(s1, off, 64);
+          s2 += __shfl_xor(s2, off, 64);
+        }
+        if ((lane & 31) == 0 && seg < P.nseg) {
+          P.part[((int64_t)d * P.nseg + seg) * 2] = s1;
+          P.part[((int64_t)d * P.nseg + seg) * 2 + 1] = s2;
+        }
+      }
+    }
+  }
+};
+
+// One work unit per workgroup; each XCD (workgroups lin, lin + 8, ...) takes a contiguous
+// run of units, tile-major, so the DM groups of a tile share that XCD's L2.
+template <int G>
+__global__ __launch_bounds__(512) void dedisp_direct(DRParams P) {
+  const int64_t lin = blockIdx.x;
+  const int64_t per = (P.nitems + 7) / 8;
+  const int64_t item = (lin & 7) * per + (lin >> 3);
+  if (item >= P.nitems) return;
+  const int64_t tile = item / P.ngroups;
+  const int grp = (int)(item - tile * P.ngroups);
+  DirectTile<G> k;
+  k.run(P, tile, grp);
+}
+
+// Several beams in one launch: unit q of the flattened list [item][tile][group] (each XCD
+// taking a contiguous run, as above) belongs to the item whose unit range holds it; the
+// item's parameters are read through the scalar cache.
+template <int G>
+__global__ __launch_bounds__(512) void dedisp_direct_batch(const DRParams* __restrict__ items,
+                                                           const int64_t* __restrict__ start, int nitems) {
+  typedef const __attribute__((address_space(4))) int64_t* ci64_t;
+  const ci64_t st = (ci64_t)start;
+  const int64_t total = st[nitems];
+  const int64_t lin = blockIdx.x;
+  const int64_t per = (total + 7) / 8;
+  const int64_t q = (lin & 7) * per + (lin >> 3);
+  if (q >= total) return;
+  int lo = 0, hi = nitems - 1;  // the last item whose range starts at or before q
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  // wave-uniform copy of the item's record through scalar loads
+  typedef const __attribute__((address_space(4))) uint32_t* cu32_t;
+  const cu32_t src = (cu32_t)(items + lo);
+  uint32_t wv[sizeof(DRParams) / 4];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(DRParams) / 4); ++k) wv[k] = src[k];
+  DRParams P;
+  __builtin_memcpy(&P, wv, sizeof(DRParams));
+  if (P.tiles_g != G) return;  // the host launches every item's own tile shape separately
+  const int64_t local = q - st[lo];
+  const int64_t tile = local / P.ngroups;
+  const int grp = (int)(local - tile * P.ngroups);
+  DirectTile<G> k;
+  k.run(P, tile, grp);
+}
+
+// The four shifted copies of a linear input: copy m of row c at position p holds
+// in[c][p + m], or 0 from nsamp on. One thread per 16 positions of all four copies.
+__global__ __launch_bounds__(256) void quad_prep(const uint8_t* __restrict__ in, int64_t in_stride, int64_t nsamp,
+                                                 uint8_t* __restrict__ quad, int64_t lq) {
+  const int c = blockIdx.y;
+  const int64_t p0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+  if (p0 >= lq) return;
+  const uint8_t* row = in + (int64_t)c * in_stride;
+  uint32_t b[19];
+#pragma unroll
+  for (int k = 0; k < 19; ++k) b[k] = p0 + k < nsamp ? (uint32_t)row[p0 + k] : 0u;
+  uint8_t* q = quad + (int64_t)c * 4 * lq + p0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    uint4 v;
+    v.x = b[m] | (b[m + 1] << 8) | (b[m + 2] << 16) | (b[m + 3] << 24);
+    v.y = b[m + 4] | (b[m + 5] << 8) | (b[m + 6] << 16) | (b[m + 7] << 24);
+    v.z = b[m + 8] | (b[m + 9] << 8) | (b[m + 10] << 16) | (b[m + 11] << 24);
+    v.w = b[m + 12] | (b[m + 13] << 8) | (b[m + 14] << 16) | (b[m + 15] << 24);
+    *reinterpret_cast<uint4*>(q + (int64_t)m * lq) = v;
+  }
+}
+
+// A block of n samples (or zeros when blk is null) written into a stream ring of four
+// shifted copies: sample j sits at ring position q = (pos0 + j) mod ring_len, and copy m
+// holds ring position (p + m) mod ring_len at every p < lq, so the sample goes to
+// p = (q - m) mod ring_len and its mirror images p + k ring_len below lq.
+__global__ __launch_bounds__(256) void ring_append_quad(const uint8_t* __restrict__ blk, int64_t in_stride,
+                                                        int64_t n, uint8_t* __restrict__ ring, int64_t lq,
+                                                        int64_t ring_len, int64_t pos0) {
+  const int c = blockIdx.y;
+  uint8_t* r = ring + (int64_t)c * 4 * lq;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    const uint8_t v = blk ? blk[(int64_t)c * in_stride + j] : (uint8_t)0;
+    const int64_t q = (pos0 + j) % ring_len;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      int64_t p = q - m;
+      if (p < 0) p += ring_len;
+      for (; p < lq; p += ring_len) r[(int64_t)m * lq + p] = v;
+    }
+  }
+}
+
+template <int G>
+void launch_g(const DRParams& P, int64_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((dedisp_direct<G>), dim3((unsigned)nblocks), dim3(64 * P.nw), 0, st, P);
+}
+
+}  // namespace
+
+namespace dd {
+
+namespace {
+
+// Parameters of one direct-read launch; for linear input the prep kernel that writes the
+// copies is enqueued first.
+int prepare(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, float* out,
+            int64_t out_stride, double* part, void* quad_ws, hipStream_t st, DRParams* P) {
+  *P = DRParams{};
+  if (in.ring_len > 0) {
+    // a stream ring already holds the copies; row_stride is the copy row length
+    P->quad = static_cast<const uint8_t*>(in.ptr);
+    P->lq = in.row_stride;
+    P->ring_len = in.ring_len;
+    P->w0 = in.win0 % in.ring_len;
+  } else {
+    P->lq = direct_quad_row(in.nvalid);
+    P->quad = static_cast<const uint8_t*>(quad_ws);
+  }
+  // buffer offsets are 32-bit: four copy rows per channel, and ring positions below 2^31
+  if (4 * P->lq >= ((int64_t)1 << 31) || P->ring_len + kDirectTile >= ((int64_t)1 << 31))
+    return fail(DD_ERR_UNSUPPORTED, "rows of 2^29 samples or more are not supported by the direct-read form");
+  if (p->tiles.g != 1 && p->tiles.g != 2 && p->tiles.g != 4)
+    return fail(DD_ERR_UNSUPPORTED, "direct-read form: dms_per_wave must be 1, 2 or 4");
+  if (in.ring_len == 0) {
+    const dim3 grid((unsigned)((P->lq / 16 + 255) / 256), (unsigned)p->nchan);
+    hipLaunchKernelGGL(quad_prep, grid, dim3(256), 0, st, static_cast<const uint8_t*>(in.ptr), in.row_stride,
+                       in.nvalid, const_cast<uint8_t*>(P->quad), P->lq);
+  }
+  const int64_t ntiles = (nout + kDirectTile - 1) / kDirectTile;
+  P->dtab = d_table;
+  P->out = out;
+  P->part = part;
+  P->out_stride = out_stride;
+  P->nout = nout;
+  P->nseg = (nout + kTile - 1) / kTile;
+  P->nitems = ntiles * p->ngroups;
+  P->nchan = p->nchan;
+  P->ndm = p->ndm;
+  P->ndm_pad = p->ndm_pad;
+  P->ngroups = p->ngroups;
+  P->nw = p->tiles.w;
+  P->tiles_g = p->tiles.g;
+  return DD_OK;
+}
+
+}  // namespace
+
+int launch_direct(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, float* out,
+                  int64_t out_stride, double* part, void* quad_ws, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DRParams P;
+  int rc = prepare(p, in, d_table, nout, out, out_stride, part, quad_ws, st, &P);
+  if (rc) return rc;
+  const int64_t nblocks = (P.nitems + 7) / 8 * 8;
+  if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
+  if (nblocks == 0) return DD_OK;
+  switch (P.tiles_g) {
+    case 1: launch_g<1>(P, nblocks, st); break;
+    case 2: launch_g<2>(P, nblocks, st); break;
+    default: launch_g<4>(P, nblocks, st); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("dedisp_direct launch: ") + hipGetErrorString(e));
+  return DD_OK;
+}
+
+int64_t direct_batch_desc_bytes(int32_t n) {
+  return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * (n + 1));
+}
+
+int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int64_t desc_bytes, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int32_t n = (int32_t)items.size();
+  if (n == 0) return DD_OK;
+  if (desc_bytes < direct_batch_desc_bytes(n)) return fail(DD_ERR_WORKSPACE, "batch workspace too small");
+  std::vector<DRParams> P((size_t)n);
+  std::vector<int64_t> start((size_t)n + 1, 0);
+  int waves = -1, gmask = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const DirectItem& it = items[i];
+    int rc = prepare(it.plan, it.in, it.table, it.nout, it.out, it.out_stride, it.part, it.quad_ws, st, &P[i]);
+    if (rc) return rc;
+    if (waves < 0) waves = P[i].nw;
+    if (P[i].nw != waves)
+      return fail(DD_ERR_UNSUPPORTED, "batched direct-read items must share the wavefronts per workgroup");
+    gmask |= 1 << P[i].tiles_g;
+    start[i + 1] = start[i] + P[i].nitems;
+  }
+  char* bw = static_cast<char*>(d_desc);
+  DRParams* dP = reinterpret_cast<DRParams*>(bw);
+  int64_t* dS = reinterpret_cast<int64_t*>(bw + align_up((int64_t)n * (int64_t)sizeof(DRParams)));
+  hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(DRParams), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dS, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("hipMemcpyAsync (batch descriptors): ") + hipGetErrorString(e));
+  const int64_t nblocks = (start[n] + 7) / 8 * 8;
+  if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
+  if (nblocks == 0) return DD_OK;
+  // one launch per tile shape present (usually one); each skips the other shapes' units
+  const dim3 grid((unsigned)nblocks), block((unsigned)(64 * waves));
+  if (gmask & 2) hipLaunchKernelGGL(dedisp_direct_batch<1>, grid, block, 0, st, (const DRParams*)dP, (const int64_t*)dS, n);
+  if (gmask & 4) hipLaunchKernelGGL(dedisp_direct_batch<2>, grid, block, 0, st, (const DRParams*)dP, (const int64_t*)dS, n);
+  if (gmask & 16) hipLaunchKernelGGL(dedisp_direct_batch<4>, grid, block, 0, st, (const DRParams*)dP, (const int64_t*)dS, n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("dedisp_direct_batch launch: ") + hipGetErrorString(e));
+  return DD_OK;
+}
+
+int append_direct(const dd_plan* p, const void* blk, int64_t in_stride, int64_t n, void* ring, int64_t lq,
+                  int64_t ring_len, int64_t pos0, void* stream) {
+  const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(ring_append_quad, dim3(gx, (unsigned)p->nchan), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const uint8_t*>(blk), in_stride, n, static_cast<uint8_t*>(ring), lq, ring_len,
+                     pos0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("ring_append_quad launch: ") + hipGetErrorString(e));
+  return DD_OK;
+}
+
+}  // namespace dd

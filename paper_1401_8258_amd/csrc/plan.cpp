@@ -55,7 +55,7 @@ void clear_error() { g_err.clear(); }
 
 int64_t elem_bytes(int32_t dtype) { return dtype == DD_F32 ? 4 : dtype == DD_F16 ? 2 : 1; }
 
-WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
+WsLayout workspace_layout(const dd_plan* p, int64_t nout, bool linear) {
   WsLayout l{};
   l.table_off = 0;
   l.table_bytes = (int64_t)p->dev_table.size() * 4;
@@ -71,8 +71,11 @@ WsLayout workspace_layout(const dd_plan* p, int64_t nout) {
   l.offs_off = o;
   o = align_up(o + (int64_t)p->ndm * l.nseg * 8 + 8);
   l.tail_off = o;
-  l.tail_bytes = p->dtype == DD_U8 ? (int64_t)p->launch.L + 64 : 0;
+  l.tail_bytes = p->dtype == DD_U8 && p->launch.form == kFormLds ? (int64_t)p->launch.L + 64 : 0;
   o = align_up(o + 2 * l.tail_bytes);
+  l.quad_off = o;
+  l.quad_bytes = linear && p->launch.form == kFormDirect ? 4 * (int64_t)p->nchan * direct_quad_row(nout) : 0;
+  o = align_up(o + l.quad_bytes);
   l.total = o;
   return l;
 }
@@ -270,13 +273,39 @@ bool plan_regwin(dd_plan* p, int64_t lds_cap) {
   return true;
 }
 
+// Direct-read form: t.g trials per wavefront, t.w wavefronts per workgroup; the table is the
+// plain delays per (channel, padded trial). A wavefront load spans one 1024-sample tile, so a
+// ring's mirror of launch.L + 64 samples covers every window that starts before the ring's end.
+int plan_direct(dd_plan* p, const Tiles& t) {
+  if (t.g != 1 && t.g != 2 && t.g != 4)
+    return fail(DD_ERR_UNSUPPORTED, "the direct-read form takes dms_per_wave 1, 2 or 4");
+  if (t.w < 1 || t.w > 8) return fail(DD_ERR_UNSUPPORTED, "the direct-read form takes waves 1..8");
+  const int32_t nchan = p->nchan, ndm = p->ndm;
+  p->tiles = Tiles{t.g, t.w, 16, 0, -1};
+  p->dms_per_group = t.g * t.w;
+  p->ngroups = (ndm + p->dms_per_group - 1) / p->dms_per_group;
+  p->ndm_pad = p->ngroups * p->dms_per_group;
+  p->max_span = compute_span(p->delays, nchan, ndm, p->dms_per_group);
+  Launch l{};
+  l.form = kFormDirect;
+  l.L = (int)kDirectTile;
+  p->launch = l;
+  p->dev_table.assign((size_t)nchan * p->ndm_pad, 0);
+  for (int32_t c = 0; c < nchan; ++c) {
+    const int32_t* row = &p->delays[(size_t)c * ndm];
+    int32_t* drow = &p->dev_table[(size_t)c * p->ndm_pad];
+    for (int32_t d = 0; d < p->ndm_pad; ++d) drow[d] = row[d < ndm ? d : ndm - 1];
+  }
+  return DD_OK;
+}
+
 }  // namespace dd
 
 extern "C" {
 
 const char* dd_last_error(void) { return g_err.c_str(); }
 
-const char* dd_version(void) { return "1.3"; }
+const char* dd_version(void) { return "1.4"; }
 
 int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
                    const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning) {
@@ -305,10 +334,13 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
 
   dd::Tiles t{8, 0, 8, 0, 0};
   const int form_req = tuning ? tuning->kernel_form : DD_FORM_AUTO;
-  if (form_req != DD_FORM_AUTO && form_req != DD_FORM_LDS && form_req != DD_FORM_REGWIN)
+  if (form_req != DD_FORM_AUTO && form_req != DD_FORM_LDS && form_req != DD_FORM_REGWIN &&
+      form_req != DD_FORM_DIRECT)
     return dd::fail(DD_ERR_UNSUPPORTED, "unknown kernel_form");
   if (form_req == DD_FORM_REGWIN && in_dtype != DD_F32)
     return dd::fail(DD_ERR_UNSUPPORTED, "the register-window form takes FP32 input only");
+  if (form_req == DD_FORM_DIRECT && in_dtype != DD_U8)
+    return dd::fail(DD_ERR_UNSUPPORTED, "the direct-read form takes 8-bit input only");
   // the register-window form is the FP32 default when no tile field is set
   const bool tiles_set = tuning && (tuning->dms_per_wave || tuning->waves || tuning->samples_per_lane ||
                                     tuning->chan_stage || tuning->producer_waves);
@@ -321,8 +353,18 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
     t.cc = tuning->chan_stage;
     t.pw = tuning->producer_waves;
   }
-  if (!valid_tiles(t)) return dd::fail(DD_ERR_UNSUPPORTED, "unsupported tuning");
-  if (t.pw > 0 && in_dtype != DD_F32)
+  // 8-bit input takes the direct-read form unless the caller asks for another form or sets
+  // an LDS-form tile field
+  const bool direct = form_req == DD_FORM_DIRECT || (form_req == DD_FORM_AUTO && in_dtype == DD_U8 && !tiles_set);
+  if (direct) {
+    t.g = tuning && tuning->dms_per_wave ? tuning->dms_per_wave : 2;
+    t.w = tuning && tuning->waves ? tuning->waves : 4;
+    if (tuning && tuning->samples_per_lane && tuning->samples_per_lane != 16)
+      return dd::fail(DD_ERR_UNSUPPORTED, "the direct-read form takes samples_per_lane 16");
+  } else if (!valid_tiles(t)) {
+    return dd::fail(DD_ERR_UNSUPPORTED, "unsupported tuning");
+  }
+  if (t.pw > 0 && in_dtype != DD_F32 && !direct)
     return dd::fail(DD_ERR_UNSUPPORTED, "producer wavefronts are available for FP32 input only");
 
   dd_plan* p = new (std::nothrow) dd_plan();
@@ -355,6 +397,16 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   }
   p->maxdelay = (int32_t)maxd;
 
+  if (direct) {
+    const int rc = dd::plan_direct(p, t);
+    if (rc) {
+      delete p;
+      return rc;
+    }
+    p->id = g_next_id.fetch_add(1);
+    *out = p;
+    return DD_OK;
+  }
   if (try_regwin) {
     if (dd::plan_regwin(p, dd::kLdsBytes)) {
       p->id = g_next_id.fetch_add(1);
@@ -458,18 +510,19 @@ int dd_plan_query(const dd_plan* p, int64_t nsamp, dd_plan_info* info) {
   info->max_span = p->max_span;
   info->kernel_form = p->launch.form;
   info->window_chunks = p->launch.form == dd::kFormRegWin ? p->launch.nch : 0;
-  info->launch_copies = p->launch.form == dd::kFormRegWin ? 1 : 4;
+  info->launch_copies = p->launch.form == dd::kFormLds ? 4 : p->launch.form == dd::kFormRegWin ? 1 : 0;
   info->launch_buf = p->launch.L;
   info->launch_stage = p->launch.cs;
   info->launch_ring = p->launch.nb;
   info->launch_lds = p->launch.lds;
   if (nsamp <= 0) return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be > 0");
   const int64_t ring_row = dd::ring_len_for(p, nsamp) + dd::ring_mirror(p);
-  info->ring_bytes = dd::ring_table_bytes(p) + dd::align_up(ring_row * p->nchan * dd::elem_bytes(p->dtype));
+  info->ring_bytes = dd::ring_table_bytes(p) +
+                     dd::align_up(ring_row * p->nchan * dd::ring_copies(p) * dd::elem_bytes(p->dtype));
   const int64_t nout = nsamp - p->maxdelay;
   // sized for nsamp outputs: covers a plain call (nout < nsamp) and a stream push (<= block)
-  const dd::WsLayout l = dd::workspace_layout(p, nsamp);
-  info->workspace_bytes = l.total;
+  info->workspace_bytes = dd::workspace_layout(p, nsamp).total;
+  info->stream_workspace_bytes = dd::workspace_layout(p, nsamp, false).total;
   if (nout <= 0) {
     info->nout = 0;
     return dd::fail(DD_ERR_TOO_SHORT, "nsamp must exceed maxdelay (" + std::to_string(p->maxdelay) + ")");

@@ -273,7 +273,7 @@ class LibraryExecutor(Executor):
     """
 
     def __init__(self, k_sigma: float = 6.0, cand_cap: int = 1 << 14, device="cuda", stream=None,
-                 tunings: Optional[Dict[str, tuple]] = None, keep: bool = False):
+                 tunings: Optional[Dict[str, object]] = None, keep: bool = False):
         import torch
 
         from . import api
@@ -292,8 +292,12 @@ class LibraryExecutor(Executor):
     def plan(self, spec: BeamSpec):
         p = self._plans.get(spec.name)
         if p is None:
-            p = self._api.Plan(spec.freq_mhz, spec.tsamp_s, spec.dm, dtype=spec.dtype,
-                               tuning=self.tunings.get(spec.name))
+            # a tuning is an LDS-form tile tuple or an autotuner choice {"form", "tuning"}
+            t = self.tunings.get(spec.name)
+            form = "auto"
+            if isinstance(t, dict):
+                form, t = t.get("form", "auto"), t.get("tuning")
+            p = self._api.Plan(spec.freq_mhz, spec.tsamp_s, spec.dm, dtype=spec.dtype, tuning=t, form=form)
             self._plans[spec.name] = p
         return p
 
@@ -301,7 +305,7 @@ class LibraryExecutor(Executor):
         p = self.plan(spec)
         q = p.query(spec.block, allow_short=True)
         outs = p.ndm * spec.block * 4 + 2 * p.ndm * 4 + self.cand_cap * 24 + 8
-        return int(q["ring_bytes"] + q["workspace_bytes"] + 2 * outs)
+        return int(q["ring_bytes"] + q["stream_workspace_bytes"] + 2 * outs)
 
     def open(self, beam: int, spec: BeamSpec) -> None:
         p = self.plan(spec)

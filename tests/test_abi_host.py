@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
         assert n in lib_mod.SIGNATURES, n
-    assert lib.dd_version().decode() == "1.3"
+    assert lib.dd_version().decode() == "1.4"
 
 
 def _create(lib, freq, dm, tsamp, dtype=0, tuning=None):
@@ -189,6 +189,14 @@ def test_every_workload_has_a_launch_geometry(lib):
         cases.append((f, fbsynth.dm_trials(sp["dm0"], sp["step"], sp["ndm"]), sp["tsamp"], 2, None))
     for freq, dm, tsamp, dt, tun in cases:
         info = _launch_ok(lib, freq, dm, tsamp, dt, tun)
+        if dt == 2 and tun is None:
+            # 8-bit input takes the direct-read form by default: no LDS, 1024-sample tiles
+            assert info.kernel_form == lib_mod.DD_FORM_DIRECT
+            assert info.launch_lds == 0 and info.launch_buf == 1024 and info.samples_per_lane == 16
+            assert (info.dms_per_wave, info.waves) == (2, 4)
+            # the same beam in the LDS form must also fit
+            info = _launch_ok(lib, freq, dm, tsamp, dt, (0, 0, 0, 0, 0, lib_mod.DD_FORM_LDS))
+            assert info.kernel_form == lib_mod.DD_FORM_LDS
         assert info.launch_ring >= 2 and 0 < info.launch_lds <= 160 * 1024, (len(freq), len(dm), tun)
         assert info.launch_buf % 64 == 0 and info.launch_copies == 4
 

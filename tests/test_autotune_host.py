@@ -83,4 +83,26 @@ def test_tune_batch_one_wave_count_for_all(at):
                         timer=clock)
     assert res["waves"] == 4
     assert res["tunings"] == [[8, 4, 2], [8, 4, 2]]
+    assert res["choices"] == [{"form": "lds", "tuning": [8, 4, 2]}] * 2
     assert res["by_waves"] == pytest.approx({8: 5.4, 4: 3.15, 2: 4.32})
+
+
+def test_tune_offers_the_direct_form_for_8bit_beams(at):
+    """8-bit beams: direct-read candidates (g trials per wavefront, waves) beside the LDS
+    ones; other dtypes get none."""
+    class Clock(FakeClock):
+        def __call__(self, plan, x, reps):
+            self.calls += 1
+            g, w, cc = plan.tiles
+            if plan.form == "direct":
+                return {1: 1.0, 2: 0.4, 4: 0.7}[g] * (1.0 if w == 4 else 1.5)
+            return 2.0
+    clock = Clock({}, {})
+    freq, tsamp, dm, _, nsamp = _beam(64, 96)
+    r = at.tune(freq, tsamp, dm, "u8", nsamp, waves=(8, 4), stages=(0,), x=object(), timer=clock)
+    assert r["form"] == "direct" and r["tuning"] == [2, 4] and r["ms"] == pytest.approx(0.4)
+    forms = [t["form"] for t in r["trials"]]
+    assert forms.count("direct") == 6 and forms.count("lds") == 2
+    assert at.make_plan(freq, tsamp, dm, "u8", r).form == "direct"
+    r = at.tune(freq, tsamp, dm, "f32", nsamp, waves=(8, 4), stages=(0,), x=object(), timer=clock)
+    assert all(t["form"] == "lds" for t in r["trials"])

@@ -58,8 +58,9 @@ def test_tune_batch_u8_beams_exact(torch, at):
         data.append(bm)
     res = at.tune_batch(beams, waves=(8, 4, 2), stages=(0,), reps=1, inputs=xs)
     assert res["waves"] in (8, 4, 2) and len(res["tunings"]) == 3
-    for bm, tun, x in zip(data, res["tunings"], xs):
-        plan = at.make_plan(bm.freq_mhz, bm.tsamp_s, bm.dm, "u8", {"tuning": tun})
+    for bm, choice, x in zip(data, res["choices"], xs):
+        plan = at.make_plan(bm.freq_mhz, bm.tsamp_s, bm.dm, "u8", choice)
+        assert plan.form == choice["form"]
         got = plan.dedisperse(x).out.cpu().numpy()
         rows = [0, bm.ndm // 2, bm.ndm - 1]
         want = orc.dedisperse(bm.data, orc.delay_table(bm.freq_mhz, bm.dm, bm.tsamp_s), rows=rows)
