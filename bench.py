@@ -7,8 +7,10 @@ before timing starts. One step = one dd_dedisperse call (dedispersion kernel,
 statistics and candidate kernels).
 
 Prints one JSON line: the whole-step throughput in DM-trial*samples/s, the
-dedispersion kernel's own duration against the FP32 add roofline, and the FP64
-oracle timed on a bounded sample of the same workload on the host.
+dedispersion kernel's own duration against the published FP32 vector peak (and the
+add issue rate), the FP64 oracle timed on a bounded sample of the same workload on
+the host (one core and all cores), the 16-beam u8 batch (config 4: batched against
+one at a time) and the 64-beam u8 serving run (config 5).
 """
 from __future__ import annotations
 
@@ -22,16 +24,21 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 2.4 GHz. The FP32 vector peak of 157.3 TFLOP/s counts a fused
-# multiply-add as two flops on 128 lanes/clk/CU; an add is one flop per lane, so the
-# add roofline is 256 x 2.4e9 x 128 = 78.6e12 adds/s (v_add_f32 issues at that rate).
+# MI355X: 256 CUs x 2.4 GHz. The published FP32 vector peak of 157.3 TFLOP/s counts a
+# fused multiply-add as two flops on 128 lanes/clk/CU (256 x 2.4e9 x 128 x 2). A plain add
+# is one flop per lane, so the add issue rate is half of it, 256 x 2.4e9 x 128 = 78.6e12
+# adds/s (v_add_f32 issues at ~118 lanes/clk/CU measured). The roofline reports achieved
+# adds/s against the published peak; the add-rate fraction is printed beside it.
+PEAK_FP32_TFLOPS = 157.3
 PEAK_ADD_TFLOPS = 256 * 2.4e9 * 128 / 1e12
 # The kernel's own ceiling: every add consumes one 4-byte LDS word, and ds_read_b128
 # delivers ~221 B/clk/CU, so at most 256 x 2.4e9 x 221 / 4 = 33.9e12 adds/s.
 LDS_CEILING_TADDS = 256 * 2.4e9 * 221 / 4 / 1e12
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dedisp_tile_full_fp32_1024ch_2048dm_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1401_8258_amd", "csrc", "dedisp.hip")
+_CSRC = os.path.join(ROOT, "paper_1401_8258_amd", "csrc")
+# what the LDS-form kernel's counters depend on: its device code and the launch geometry
+KERNEL_SOURCES = [os.path.join(_CSRC, f) for f in ("dedisp.hip", "dd_device.h", "dd_internal.h", "plan.cpp")]
 
 
 def parse():
@@ -51,14 +58,44 @@ def parse():
                     help="plain: the full-size FP32 workload (default); batch: 16 uneven u8 beams in one "
                          "persistent launch; serve: 64 streaming u8 beams with continuous batching; "
                          "subband: only the subband passes over the full-size FP32 workload (for profiling)")
-    ap.add_argument("--serve-blocks", type=int, default=4,
-                    help="1 s blocks per beam in the serving run (plain mode appends a serving summary "
-                         "when > 0)")
+    ap.add_argument("--serve-blocks", type=int, default=60,
+                    help="1 s blocks per beam after the ring fill in the serving run (plain mode appends a "
+                         "serving summary when > 0)")
+    ap.add_argument("--batch-reps", type=int, default=3,
+                    help="timed repetitions of the config-4 batch (plain mode appends it when > 0)")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="processes of the all-core oracle leg (at most the host's cores)")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serving admission budget")
     return ap.parse_args()
 
 
-def cpu_baseline(beam, rows):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORC = {}
+
+
+def _oracle_rows(rows):
+    """One worker's share of the all-core leg (the beam and delay table come by fork)."""
+    from oracle import dedisp_oracle as orc
+    out = orc.dedisperse(_ORC["data"], _ORC["tab"], rows=rows)
+    orc.series_stats(out)
+    return out.shape[0] * out.shape[1]
+
+
+def cpu_baseline(beam, rows, workers):
+    """The FP64 oracle on the host: evenly spaced DM rows on one core, then on `workers`
+    processes (fork, the input shared copy-on-write) with `rows` rows each."""
+    import multiprocessing as mp
+
     from oracle import dedisp_oracle as orc
     tab = orc.delay_table(beam.freq_mhz, beam.dm, beam.tsamp_s)
     sel = [int(r) for r in np.linspace(0, beam.ndm - 1, rows)]
@@ -67,9 +104,28 @@ def cpu_baseline(beam, rows):
     orc.series_stats(out)
     dt = time.perf_counter() - t
     nout = out.shape[1]
-    return {"value": len(sel) * nout / dt, "unit": "DM-trial*samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(sel)} of {beam.ndm} DM rows (evenly spaced) x {nout} output samples x "
-                      f"{beam.nchan} channels, FP64 NumPy, single thread; {dt:.1f} s"}
+    one = {"value": len(sel) * nout / dt, "unit": "DM-trial*samples/s", "cores": 1, "kind": "oracle",
+           "sample": f"{len(sel)} of {beam.ndm} DM rows (evenly spaced) x {nout} output samples x "
+                     f"{beam.nchan} channels, FP64 NumPy, single thread; {dt:.1f} s"}
+    ncpu = os.cpu_count() or 1
+    nw = max(1, min(workers, ncpu))
+    res = dict(one)
+    res["single_core"] = dict(one)
+    res["cpu_model"] = _cpu_model()
+    res["host_cpus"] = ncpu
+    if nw > 1:
+        _ORC["data"], _ORC["tab"] = beam.data, tab
+        allrows = [int(r) for r in np.linspace(0, beam.ndm - 1, nw * rows)]
+        shares = [allrows[i::nw] for i in range(nw)]
+        ctx = mp.get_context("fork")
+        t = time.perf_counter()
+        with ctx.Pool(nw) as pool:
+            done = sum(pool.map(_oracle_rows, shares))
+        dt_all = time.perf_counter() - t
+        res.update({"value": done / dt_all, "cores": nw,
+                    "sample": f"{nw * rows} of {beam.ndm} DM rows (evenly spaced) x {nout} output samples x "
+                              f"{beam.nchan} channels, FP64 NumPy, {nw} processes x 1 thread; {dt_all:.1f} s"})
+    return res
 
 
 def serve_run(nblocks, budget_bytes, seed=5):
@@ -110,6 +166,7 @@ def serve_run(nblocks, budget_bytes, seed=5):
     sched = [b for b in sched if b.beam in srv.active]
     st = srv.run(sched)
     out = st.summary()
+    out["batch_vs_single"] = _serve_batch_vs_single(ex, specs, admitted, pool, nfill, nblocks)
     out.update({"beams": len(specs), "blocks_per_beam": nblocks,
                 "workload": "48 x 1024-ch (408-428 MHz, 51.2 us, 2048 DMs) + 16 x 4096-ch (120-180 MHz, "
                             "81.92 us, 4096 DMs step 0.05) u8 beams, 1 s blocks, Poisson arrival jitter "
@@ -117,9 +174,58 @@ def serve_run(nblocks, budget_bytes, seed=5):
     return out
 
 
+def _serve_batch_vs_single(ex, specs, beams, pool, nfill, nblocks, rounds=3):
+    """After the serving run: every admitted beam's next 1 s block, all of them in one
+    batched call (ring appends, then one dedispersion launch and one launch per statistics /
+    candidate step), against the same blocks pushed one beam at a time; device time per
+    round of blocks, alternating the two ways."""
+    import torch
+
+    from paper_1401_8258_amd import api
+    streams = {i: ex._beams[i]["stream"] for i in beams}
+    outs = {i: api.alloc_outputs(streams[i].plan.ndm, specs[i].block, ex.device, ex.k_sigma, ex.cand_cap)
+            for i in beams}
+    seqk = {i: nfill.get(i, 0) + nblocks for i in beams}
+
+    def block(i):
+        sp = specs[i]
+        b = pool[(len(sp.freq_mhz), sp.block)][seqk[i] % 3]
+        seqk[i] += 1
+        return b
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms_b, ms_s = [], []
+    for _ in range(rounds):
+        torch.cuda.synchronize()
+        e0.record(ex.stream)
+        jobs, o = [], []
+        for i in beams:
+            w = streams[i].append(block(i), stream=ex.stream)
+            jobs.append((streams[i], w))
+            o.append(outs[i])
+        api.batch_dedisperse(jobs, k_sigma=ex.k_sigma, cand_cap=ex.cand_cap, stream=ex.stream, outputs=o)
+        e1.record(ex.stream)
+        torch.cuda.synchronize()
+        ms_b.append(e0.elapsed_time(e1))
+        e0.record(ex.stream)
+        for i in beams:
+            w = streams[i].append(block(i), stream=ex.stream)
+            api.batch_dedisperse([(streams[i], w)], k_sigma=ex.k_sigma, cand_cap=ex.cand_cap, stream=ex.stream,
+                                 outputs=[outs[i]])
+        e1.record(ex.stream)
+        torch.cuda.synchronize()
+        ms_s.append(e0.elapsed_time(e1))
+    return {"beams": len(beams), "rounds": rounds, "batched_ms": round(float(np.median(ms_b)), 3),
+            "one_at_a_time_ms": round(float(np.median(ms_s)), 3),
+            "batched_speedup": round(float(np.median(ms_s)) / float(np.median(ms_b)), 3)}
+
+
 def batch_run(reps):
-    """Config-4 batch: 16 uneven u8 beams (N(128,16) codes drawn on the device), tiles from
-    the autotuner, one persistent launch, against the beams one at a time."""
+    """Config-4 batch: 16 uneven u8 beams (N(128,16) codes drawn on the device) with
+    direct-read tiles from the autotuner (each beam's best under one common wavefront count)
+    in one batched call (one launch per trials-per-wavefront value, then one launch per
+    statistics/candidate step for all beams), against each beam alone with its own best
+    tiles over all wavefront counts."""
     import torch
 
     import fbsynth
@@ -135,18 +241,20 @@ def batch_run(reps):
         xs.append(autotune.synthetic_input(sp["nchan"], sp["nsamp"], "u8", seed=i))
     t_tune = time.perf_counter()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    tb = autotune.tune_batch(beams, waves=(8, 4, 2, 1), stages=(0,), reps=1, inputs=xs, log=log)
+    tb = autotune.tune_batch(beams, waves=(8, 4, 2, 1), stages=(0,), reps=1, inputs=xs, log=log,
+                             forms=("direct",))
     t_tune = time.perf_counter() - t_tune
+    # batched: each beam's best tiles under the one wavefront count that minimises the sum
     plans = [autotune.make_plan(f, ts, dm, "u8", c) for (f, ts, dm, _, _), c in zip(beams, tb["choices"])]
+    # one at a time: each beam's own best tiles over all wavefront counts
+    own = [autotune.make_plan(f, ts, dm, "u8", c) for (f, ts, dm, _, _), c in zip(beams, tb["own_best"])]
     outs = [dd.api.alloc_outputs(p.ndm, x.shape[1] - p.maxdelay, x.device, 6.0, 1 << 16) for p, x in zip(plans, xs)]
     jobs = list(zip(plans, xs))
+    for p, x in jobs + list(zip(own, xs)):  # workspaces allocated before timing
+        p.workspace(x.shape[1], x.device)
 
     def batched():
         dd.batch_dedisperse(jobs, k_sigma=6.0, cand_cap=1 << 16, outputs=outs)
-
-    def singles(ps):
-        for p, x, o in zip(ps, xs, outs):
-            dd.batch_dedisperse([(p, x)], k_sigma=6.0, cand_cap=1 << 16, outputs=[o])
 
     def timed(fn):
         fn()
@@ -160,24 +268,27 @@ def batch_run(reps):
         return e0.elapsed_time(e1) / reps
 
     ms_batch = timed(batched)
-    # each beam alone with its own best tiles (any wavefront count)
-    log("batch: per-beam best tiles")
-    best = [autotune.tune(*b, waves=(8, 4, 2, 1), stages=(0,), reps=1, x=x) for b, x in zip(beams, xs)]
-    best = [{"form": r["form"], "tuning": r["tuning"]} for r in best]
-    own = [autotune.make_plan(f, ts, dm, "u8", c) for (f, ts, dm, _, _), c in zip(beams, best)]
-    ms_own = timed(lambda: singles(own))
-    ms_same = timed(lambda: singles(plans))
-    trials_samples = sum(p.ndm * (x.shape[1] - p.maxdelay) for p, x in zip(plans, xs))
-    adds = sum(p.ndm * p.nchan * (x.shape[1] - p.maxdelay) for p, x in zip(plans, xs))
+    # each beam alone with its own best tiles, timed one by one
+    per_beam = []
+    for p, x, o in zip(own, xs, outs):
+        ms = timed(lambda: dd.batch_dedisperse([(p, x)], k_sigma=6.0, cand_cap=1 << 16, outputs=[o]))
+        nout = x.shape[1] - p.maxdelay
+        per_beam.append({"nchan": p.nchan, "ndm": p.ndm, "nout": nout, "form": p.form, "tiles": list(p.tiles[:2]),
+                         "ms": round(ms, 3), "adds_per_s": p.ndm * p.nchan * nout / (ms * 1e-3)})
+    ms_single = sum(b["ms"] for b in per_beam)
+    trials_samples = sum(p.ndm * (x.shape[1] - p.maxdelay) for p, x in jobs)
+    adds = sum(p.ndm * p.nchan * (x.shape[1] - p.maxdelay) for p, x in jobs)
     return {"metric": "DM-trial*samples/s", "value": trials_samples / (ms_batch * 1e-3),
             "unit": "DM-trial*samples/s", "n_gpus": 1, "steps": reps, "ms_per_step": round(ms_batch, 3),
             "higher_is_better": True, "dtype": "u8", "data": "synthetic",
-            "config": {"workload": "16 uneven u8 beams (nchan 256/512/1024/4096, 500-4096 DMs, nsamp 2^16-2^19) "
-                                   "in one persistent launch, stats + 6-sigma candidates",
-                       "common_waves": tb["waves"], "tunings": tb["choices"], "tune_s": round(t_tune, 1)},
+            "config": {"workload": "16 uneven u8 beams (nchan 256/512/1024/4096, 500-4096 DMs, nsamp 2^16-2^19), "
+                                   "batched, stats + 6-sigma candidates",
+                       "common_waves": tb["waves"], "tunings": tb["choices"], "own_best_tunings": tb["own_best"],
+                       "tune_s": round(t_tune, 1)},
             "adds_per_s": adds / (ms_batch * 1e-3),
-            "one_at_a_time_same_tiles_ms": round(ms_same, 3),
-            "one_at_a_time_own_best_tiles_ms": round(ms_own, 3), "own_best_tilings": best}
+            "one_at_a_time_ms": round(ms_single, 3),
+            "batched_speedup": round(ms_single / ms_batch, 3),
+            "per_beam_alone": per_beam}
 
 
 def subband_run(dd, beam, steps, warmup):
@@ -297,17 +408,22 @@ def main():
         from paper_1401_8258_amd.profiling import source_digest
         with open(args.traffic) as f:
             rec = json.load(f)
-        if rec.get("kernel_source_sha256") == source_digest(KERNEL_SOURCE):
+        if rec.get("kernel_source_sha256") == source_digest(KERNEL_SOURCES):
             traffic = rec["hbm_bytes_per_launch"]
             traffic_note = (f"FETCH_SIZE x {rec['fetch_scale']} + WRITE_SIZE x {rec['write_scale']} "
                             f"(copy-kernel calibration), {os.path.relpath(args.traffic, ROOT)}")
         else:
             traffic_note = "kernel changed since the counters were taken"
     algo_bytes = beam.nchan * nsamp * 4 + beam.ndm * nout * 4
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ADD_TFLOPS, 2),
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_ADD_TFLOPS, 4), "traffic": traffic,
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
             "traffic_note": traffic_note, "algorithmic_bytes": algo_bytes,
             "kernel": "dedisp_tile", "kernel_ms": round(ms_kernel, 3),
+            "achieved_note": "one FP32 add per (DM trial, channel, output sample) = one flop",
+            "peak_note": "published FP32 vector peak: 256 CU x 2.4 GHz x 128 lanes x 2 (FMA)",
+            "add_issue_rate": round(PEAK_ADD_TFLOPS, 2),
+            "frac_of_add_issue_rate": round(achieved / PEAK_ADD_TFLOPS, 4),
+            "add_issue_rate_note": "256 CU x 2.4 GHz x 128 lanes x 1 (an add is one flop per lane)",
             "frac_of_lds_ceiling": round(achieved / LDS_CEILING_TADDS, 4),
             "algorithmic_hbm_gbs": round(algo_bytes / (ms_kernel * 1e-3) / 1e9, 1)}
 
@@ -493,13 +609,18 @@ def main():
         del y
     del x
     del out
+    if args.batch_reps > 0:
+        print("bench: config-4 batch (autotune, batched, one at a time)", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        res["batch"] = batch_run(args.batch_reps)
+        torch.cuda.empty_cache()
     if args.serve_blocks > 0:
-        print("bench: serving run", file=sys.stderr, flush=True)
+        print(f"bench: serving run ({args.serve_blocks} blocks per beam)", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         res["serving"] = serve_run(args.serve_blocks, int(args.hbm_budget_gb * 1e9))
     if not args.no_cpu:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(beam, args.cpu_rows)
+        res["cpu_baseline"] = cpu_baseline(beam, args.cpu_rows, args.cpu_workers)
     print(json.dumps(res), flush=True)
 
 

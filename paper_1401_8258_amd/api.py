@@ -297,8 +297,10 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
     """Dedisperse several inputs in one persistent launch (dd_batch_dedisperse).
 
     jobs: a list of (Plan, tensor) pairs and/or (Stream, (t0, nout)) pairs, the latter
-    after Stream.append returned a pending window. All plans must share the input dtype
-    and DM trials per workgroup. ``outputs`` optionally gives, per job, buffers from
+    after Stream.append returned a pending window. Direct-read plans may have any tiles
+    (one launch per trials-per-wavefront value); LDS-form plans must share the input dtype,
+    DM trials per workgroup and producer count (one persistent launch). Statistics and
+    candidates of all jobs run in one launch per step. ``outputs`` optionally gives, per job, buffers from
     alloc_outputs (with ``stats`` and ``k_sigma`` matching) to write into instead of new
     ones. Returns one Result per job, equal bit for bit to the one-at-a-time calls.
     """

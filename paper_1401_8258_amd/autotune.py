@@ -10,9 +10,10 @@ samples read through the caches, DM groups of g x waves trials with g in 1, 2, 4
 the number of wavefronts sharing one LDS ring or workgroup and the channels staged
 per ring slot. ``tune``
 times every candidate on seeded random input of the beam's shape and keeps the
-fastest; ``tune_batch`` picks the wavefront count that minimises the summed time
-of a set of beams (a batched launch needs one count for all its items), with each
-beam's own best stage size. The timer is a parameter (``time_plan`` on the
+fastest; ``tune_batch`` tunes a set of beams at every wavefront count and returns
+either the count that minimises their summed time (LDS-form items of one batched
+launch share a count) with each beam's best under it, or each beam's own best
+(direct-read items may differ). The timer is a parameter (``time_plan`` on the
 device by default). Results are cached by (nchan, ndm, dtype, nsamp, DM list hash).
 """
 from __future__ import annotations
@@ -137,12 +138,17 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
 
 def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequence[int] = STAGES, reps: int = 2,
                cache: Optional[TuneCache] = None, inputs: Optional[List[torch.Tensor]] = None,
-               log=None, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan) -> dict:
-    """One wavefront count for a batch; per beam the best stage size under it.
+               log=None, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan,
+               forms: Sequence[str] = FORMS, common_waves: bool = True) -> dict:
+    """Tiles for a batch of beams.
 
-    beams: (freq, tsamp, dm, dtype, nsamp) per beam. Returns {"waves": w, "choices": [...],
-    "tunings": [...], "total_ms": t, "by_waves": {w: t}}: per beam its choice ({"form",
-    "tuning"}, what make_plan takes) and the tuning alone.
+    beams: (freq, tsamp, dm, dtype, nsamp) per beam. Every beam is tuned at each wavefront
+    count. Returns {"waves": w, "choices": [...], "tunings": [...], "own_best": [...],
+    "total_ms": t, "by_waves": {w: t}}: ``w`` is the count that minimises the summed time,
+    ``own_best`` each beam's fastest choice over all counts ({"form", "tuning", "ms"}), and
+    ``choices`` (what make_plan takes) the per-beam best under ``w`` when ``common_waves``
+    (LDS-form items of one batched launch share a count), else ``own_best`` (direct-read
+    items may differ).
     """
     per_w: Dict[int, List[dict]] = {}
     for w in waves:
@@ -151,16 +157,24 @@ def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequenc
             x = inputs[i] if inputs is not None else None
             try:
                 r = tune(freq, tsamp, dm, dtype, nsamp, waves=(w,), stages=stages, reps=reps, cache=cache, x=x,
-                         timer=timer)
+                         timer=timer, forms=forms)
             except RuntimeError:
                 per_w[w] = None
                 break
             per_w[w].append(r)
             if log is not None:
-                log(f"tune: waves {w} beam {i}: {r['tuning']} {r['ms']:.2f} ms")
+                log(f"tune: waves {w} beam {i}: {r['form']} {r['tuning']} {r['ms']:.2f} ms")
     totals = {w: sum(r["ms"] for r in rs) for w, rs in per_w.items() if rs is not None}
     if not totals:
         raise RuntimeError("no common wavefront count fits every beam")
     wbest = min(totals, key=totals.get)
-    return {"waves": wbest, "choices": [{"form": r["form"], "tuning": r["tuning"]} for r in per_w[wbest]],
-            "tunings": [r["tuning"] for r in per_w[wbest]], "total_ms": totals[wbest], "by_waves": totals}
+    own = []
+    for i in range(len(beams)):
+        r = min((rs[i] for rs in per_w.values() if rs is not None), key=lambda t: t["ms"])
+        own.append({"form": r["form"], "tuning": r["tuning"], "ms": r["ms"]})
+    if common_waves:
+        choices = [{"form": r["form"], "tuning": r["tuning"]} for r in per_w[wbest]]
+    else:
+        choices = [{"form": r["form"], "tuning": r["tuning"]} for r in own]
+    return {"waves": wbest, "choices": choices, "tunings": [c["tuning"] for c in choices], "own_best": own,
+            "total_ms": totals[wbest], "by_waves": totals}

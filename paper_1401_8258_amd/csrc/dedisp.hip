@@ -788,11 +788,8 @@ __device__ double block_sum256(double v, double* red) {
 }
 
 // stat[d] = {mean, rms, threshold} in FP64; mean/rms also as FP32 outputs.
-__global__ __launch_bounds__(256) void stats_finalize(const double* __restrict__ part, int64_t nseg,
-                                                      int ndm, int64_t nout, double k, float* mean,
-                                                      float* rms, double* stat) {
-  const int d = blockIdx.x * 256 + threadIdx.x;
-  if (d >= ndm) return;
+__device__ __forceinline__ void finalize_series(const double* __restrict__ part, int64_t nseg, int d, int64_t nout,
+                                                double k, float* mean, float* rms, double* stat) {
   // One thread per series: the loads of 8 tiles are issued together and then added in tile
   // order, so the sums are the ones a plain sequential loop gives while the loop is no longer
   // one memory latency per tile (a plan with few series has only a few such threads).
@@ -825,12 +822,10 @@ __global__ __launch_bounds__(256) void stats_finalize(const double* __restrict__
   stat[d * 3 + 2] = m + k * r;
 }
 
-__global__ __launch_bounds__(256) void cand_count(const float* __restrict__ out, int64_t stride, int64_t nout,
-                                                  int64_t nseg, const double* __restrict__ stat,
-                                                  int32_t* __restrict__ cnt) {
-  __shared__ double red[4];
-  const int64_t seg = blockIdx.x;
-  const int d = blockIdx.y;
+// Values above the threshold in one kStatSeg segment of series d (a 256-thread block).
+__device__ __forceinline__ void count_segment(const float* __restrict__ out, int64_t stride, int64_t nout,
+                                              int64_t nseg, const double* __restrict__ stat,
+                                              int32_t* __restrict__ cnt, int64_t seg, int d, double* red) {
   const float* row = out + (int64_t)d * stride;
   const double thr = stat[d * 3 + 2];
   const int64_t b = seg * dd::kStatSeg;
@@ -842,9 +837,8 @@ __global__ __launch_bounds__(256) void cand_count(const float* __restrict__ out,
 }
 
 // Exclusive scan of n counts by one 1024-thread block; total to *ncand.
-__global__ __launch_bounds__(1024) void cand_scan(const int32_t* __restrict__ cnt, int64_t n,
-                                                  int64_t* __restrict__ offs, int64_t* __restrict__ ncand) {
-  __shared__ int64_t part[1024];
+__device__ __forceinline__ void scan_counts(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ offs,
+                                            int64_t* __restrict__ ncand, int64_t* part) {
   const int tid = threadIdx.x;
   const int64_t chunk = (n + 1023) / 1024;
   const int64_t b = min(n, tid * chunk), e = min(n, b + chunk);
@@ -866,14 +860,12 @@ __global__ __launch_bounds__(1024) void cand_scan(const int32_t* __restrict__ cn
   if (tid == 1023) *ncand = part[1023];
 }
 
-__global__ __launch_bounds__(256) void cand_write(const float* __restrict__ out, int64_t stride, int64_t nout,
-                                                  int64_t nseg, const double* __restrict__ stat,
-                                                  const int32_t* __restrict__ cnt,
-                                                  const int64_t* __restrict__ offs, dd_cand* __restrict__ cand,
-                                                  int64_t cap, int64_t t_base) {
-  __shared__ int wtot[4];
-  const int64_t seg = blockIdx.x;
-  const int d = blockIdx.y;
+// The detections of one segment of series d, in time order, at their scanned offsets.
+__device__ __forceinline__ void write_segment(const float* __restrict__ out, int64_t stride, int64_t nout,
+                                              int64_t nseg, const double* __restrict__ stat,
+                                              const int32_t* __restrict__ cnt, const int64_t* __restrict__ offs,
+                                              dd_cand* __restrict__ cand, int64_t cap, int64_t t_base, int64_t seg,
+                                              int d, int* wtot) {
   const int64_t idx = (int64_t)d * nseg + seg;
   if (cnt[idx] == 0) return;
   int64_t off = offs[idx];
@@ -908,6 +900,95 @@ __global__ __launch_bounds__(256) void cand_write(const float* __restrict__ out,
     }
     off += total;
   }
+}
+
+__global__ __launch_bounds__(256) void stats_finalize(const double* __restrict__ part, int64_t nseg,
+                                                      int ndm, int64_t nout, double k, float* mean,
+                                                      float* rms, double* stat) {
+  const int d = blockIdx.x * 256 + threadIdx.x;
+  if (d >= ndm) return;
+  finalize_series(part, nseg, d, nout, k, mean, rms, stat);
+}
+
+__global__ __launch_bounds__(256) void cand_count(const float* __restrict__ out, int64_t stride, int64_t nout,
+                                                  int64_t nseg, const double* __restrict__ stat,
+                                                  int32_t* __restrict__ cnt) {
+  __shared__ double red[4];
+  count_segment(out, stride, nout, nseg, stat, cnt, blockIdx.x, blockIdx.y, red);
+}
+
+__global__ __launch_bounds__(1024) void cand_scan(const int32_t* __restrict__ cnt, int64_t n,
+                                                  int64_t* __restrict__ offs, int64_t* __restrict__ ncand) {
+  __shared__ int64_t part[1024];
+  scan_counts(cnt, n, offs, ncand, part);
+}
+
+__global__ __launch_bounds__(256) void cand_write(const float* __restrict__ out, int64_t stride, int64_t nout,
+                                                  int64_t nseg, const double* __restrict__ stat,
+                                                  const int32_t* __restrict__ cnt,
+                                                  const int64_t* __restrict__ offs, dd_cand* __restrict__ cand,
+                                                  int64_t cap, int64_t t_base) {
+  __shared__ int wtot[4];
+  write_segment(out, stride, nout, nseg, stat, cnt, offs, cand, cap, t_base, blockIdx.x, blockIdx.y, wtot);
+}
+
+// The same four steps for every item of a batch in one launch each. An item's series are
+// [ser0, ser0 + ndm) of the flattened list, its (series, segment) units [unit0, unit0 +
+// ndm * nseg) (items without candidates own none); blocks find their item by binary search.
+struct TailItem {
+  const double* part;  // statistics partials [ndm][ntiles][2]
+  double* stat;        // [ndm][3]
+  float *mean, *rms;
+  const float* out;
+  int32_t* cnt;        // [ndm][nseg]
+  int64_t* offs;       // [ndm][nseg]
+  int64_t* ncand;
+  dd_cand* cand;
+  int64_t ntiles, nout, stride, nseg, cap, t_base, ser0, unit0;
+  double k;
+  int32_t ndm, pad;
+};
+
+template <typename F>
+__device__ __forceinline__ int find_item(const TailItem* items, int n, int64_t key, F first) {
+  int lo = 0, hi = n - 1;  // the last item whose range starts at or before key
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first(items[mid]) <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void stats_finalize_batch(const TailItem* __restrict__ items, int n, int64_t nser) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nser) return;
+  const TailItem& it = items[find_item(items, n, i, [](const TailItem& t) { return t.ser0; })];
+  finalize_series(it.part, it.ntiles, (int)(i - it.ser0), it.nout, it.k, it.mean, it.rms, it.stat);
+}
+
+__global__ __launch_bounds__(256) void cand_count_batch(const TailItem* __restrict__ items, int n) {
+  __shared__ double red[4];
+  const int64_t u = blockIdx.x;
+  const TailItem& it = items[find_item(items, n, u, [](const TailItem& t) { return t.unit0; })];
+  const int64_t local = u - it.unit0;
+  count_segment(it.out, it.stride, it.nout, it.nseg, it.stat, it.cnt, local % it.nseg, (int)(local / it.nseg), red);
+}
+
+// one block per item with candidates (items[blockIdx.x] of the candidate list)
+__global__ __launch_bounds__(1024) void cand_scan_batch(const TailItem* __restrict__ items) {
+  __shared__ int64_t part[1024];
+  const TailItem& it = items[blockIdx.x];
+  scan_counts(it.cnt, (int64_t)it.ndm * it.nseg, it.offs, it.ncand, part);
+}
+
+__global__ __launch_bounds__(256) void cand_write_batch(const TailItem* __restrict__ items, int n) {
+  __shared__ int wtot[4];
+  const int64_t u = blockIdx.x;
+  const TailItem& it = items[find_item(items, n, u, [](const TailItem& t) { return t.unit0; })];
+  const int64_t local = u - it.unit0;
+  write_segment(it.out, it.stride, it.nout, it.nseg, it.stat, it.cnt, it.offs, it.cand, it.cap, it.t_base,
+                local % it.nseg, (int)(local / it.nseg), wtot);
 }
 
 // Row c of the ring holds sample t at (t mod ring_len); positions below `mirror` are
@@ -1368,7 +1449,7 @@ int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes) {
   if (!ws_bytes || n < 1 || !items) return dd::fail(DD_ERR_INVALID_ARG, "need items, n >= 1 and ws_bytes");
   // descriptors of the LDS-form launch, then of the direct-read launch
   *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * (n + 1) * 8) +
-              dd::direct_batch_desc_bytes(n);
+              dd::direct_batch_desc_bytes(n) + 2 * dd::align_up((int64_t)n * (int64_t)sizeof(TailItem));
   return DD_OK;
 }
 
@@ -1493,15 +1574,68 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "dedisp_batch launch");
   }
-  rc = dd::launch_direct_batch(direct, bw + lds_desc, ws_bytes - lds_desc, st);
+  const int64_t direct_desc = dd::direct_batch_desc_bytes(n);
+  rc = dd::launch_direct_batch(direct, bw + lds_desc, direct_desc, st);
   if (rc) return rc;
+  // statistics and candidates of every item: one launch per step for the whole batch
+  std::vector<TailItem> tails, cands;
+  int64_t nser = 0, nunit = 0;
   for (int32_t i = 0; i < n; ++i) {
     const dd_batch_item& it = items[i];
     const dd_plan* p = it.stream_item ? it.stream_item->plan : it.plan;
-    rc = launch_tail(p, nouts[i], outs[i], static_cast<char*>(it.d_plan_workspace), lays[i], st);
-    if (rc) return rc;
-    if (it.stream_item) it.stream_item->pending_n = 0;
+    const Outputs& o = outs[i];
+    if (!(o.mean && o.rms)) continue;
+    char* ws = static_cast<char*>(it.d_plan_workspace);
+    const dd::WsLayout& l = lays[i];
+    TailItem t{};
+    t.part = reinterpret_cast<const double*>(ws + l.part_off);
+    t.stat = reinterpret_cast<double*>(ws + l.thr_off);
+    t.mean = o.mean;
+    t.rms = o.rms;
+    t.out = o.out;
+    t.stride = o.out_stride;
+    t.ntiles = (nouts[i] + kTile - 1) / kTile;
+    t.nout = nouts[i];
+    t.k = (double)o.k;
+    t.ndm = p->ndm;
+    t.ser0 = nser;
+    nser += p->ndm;
+    tails.push_back(t);
+    if (o.k > 0.f && o.ncand) {
+      t.nseg = (nouts[i] + dd::kStatSeg - 1) / dd::kStatSeg;
+      t.cnt = reinterpret_cast<int32_t*>(ws + l.cnt_off);
+      t.offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
+      t.ncand = o.ncand;
+      t.cand = o.cand;
+      t.cap = o.cand ? o.cap : 0;
+      t.t_base = o.t_base;
+      t.unit0 = nunit;
+      nunit += (int64_t)p->ndm * t.nseg;
+      cands.push_back(t);
+    }
   }
+  if (!tails.empty()) {
+    const int64_t tail_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(TailItem));
+    TailItem* dT = reinterpret_cast<TailItem*>(bw + lds_desc + direct_desc);
+    TailItem* dC = reinterpret_cast<TailItem*>(bw + lds_desc + direct_desc + tail_bytes);
+    hipError_t e = hipMemcpyAsync(dT, tails.data(), tails.size() * sizeof(TailItem), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !cands.empty())
+      e = hipMemcpyAsync(dC, cands.data(), cands.size() * sizeof(TailItem), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch statistics descriptors)");
+    hipLaunchKernelGGL(stats_finalize_batch, dim3((unsigned)((nser + 255) / 256)), dim3(256), 0, st,
+                       (const TailItem*)dT, (int)tails.size(), nser);
+    if (nunit > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many candidate segments in one batch");
+    if (!cands.empty() && nunit > 0) {
+      const int nc = (int)cands.size();
+      hipLaunchKernelGGL(cand_count_batch, dim3((unsigned)nunit), dim3(256), 0, st, (const TailItem*)dC, nc);
+      hipLaunchKernelGGL(cand_scan_batch, dim3((unsigned)nc), dim3(1024), 0, st, (const TailItem*)dC);
+      hipLaunchKernelGGL(cand_write_batch, dim3((unsigned)nunit), dim3(256), 0, st, (const TailItem*)dC, nc);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batched statistics/candidate launch");
+  }
+  for (int32_t i = 0; i < n; ++i)
+    if (items[i].stream_item) items[i].stream_item->pending_n = 0;
   return DD_OK;
 }
 

@@ -28,6 +28,7 @@
 // mirror of at least a tile past its end, so no window wraps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -114,6 +115,7 @@ struct DirectTile {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = tile * kDrTile;
     const int dw = grp * G * P.nw + w * G;
+    if (dw >= P.ndm_pad) return;  // a batched item regrouped to more wavefronts than its plan's
 #pragma unroll
     for (int g = 0; g < G; ++g) {
 #pragma unroll
@@ -196,23 +198,28 @@ __global__ __launch_bounds__(512) void dedisp_direct(DRParams P) {
   k.run(P, tile, grp);
 }
 
-// Several beams in one launch: unit q of the flattened list [item][tile][group] (each XCD
-// taking a contiguous run, as above) belongs to the item whose unit range holds it; the
-// item's parameters are read through the scalar cache.
+// Several beams in one launch. XCD x (workgroups lin = x, x + 8, ...) walks the items in
+// order and takes the x-th eighth of each item's units [item][tile][group] (a contiguous,
+// tile-major run, as in a single launch), so at any time every XCD works on the same item
+// and their reads of its input meet in the shared last-level cache, as they do when the
+// items are launched one at a time. run[x][i] is the first of XCD x's workgroups on item
+// i (run[x][n] the count); the item's own units begin at its offset plus x/8 of its units.
+// The item's parameters are read through the scalar cache. Every item's trials are
+// regrouped into workgroups of the launch's wavefront count (a trial's sum does not depend
+// on which workgroup computes it); the count is the one whose items carry the most work.
 template <int G>
 __global__ __launch_bounds__(512) void dedisp_direct_batch(const DRParams* __restrict__ items,
-                                                           const int64_t* __restrict__ start, int nitems) {
+                                                           const int64_t* __restrict__ run, int nitems) {
   typedef const __attribute__((address_space(4))) int64_t* ci64_t;
-  const ci64_t st = (ci64_t)start;
-  const int64_t total = st[nitems];
   const int64_t lin = blockIdx.x;
-  const int64_t per = (total + 7) / 8;
-  const int64_t q = (lin & 7) * per + (lin >> 3);
-  if (q >= total) return;
-  int lo = 0, hi = nitems - 1;  // the last item whose range starts at or before q
+  const int x = (int)(lin & 7);
+  const ci64_t rx = (ci64_t)(run + (int64_t)x * (nitems + 1));
+  const int64_t k = lin >> 3;
+  if (k >= rx[nitems]) return;
+  int lo = 0, hi = nitems - 1;  // the last item whose run starts at or before k
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (st[mid] <= q) lo = mid;
+    if (rx[mid] <= k) lo = mid;
     else hi = mid - 1;
   }
   // wave-uniform copy of the item's record through scalar loads
@@ -220,15 +227,15 @@ __global__ __launch_bounds__(512) void dedisp_direct_batch(const DRParams* __res
   const cu32_t src = (cu32_t)(items + lo);
   uint32_t wv[sizeof(DRParams) / 4];
 #pragma unroll
-  for (int k = 0; k < (int)(sizeof(DRParams) / 4); ++k) wv[k] = src[k];
+  for (int j = 0; j < (int)(sizeof(DRParams) / 4); ++j) wv[j] = src[j];
   DRParams P;
   __builtin_memcpy(&P, wv, sizeof(DRParams));
-  if (P.tiles_g != G) return;  // the host launches every item's own tile shape separately
-  const int64_t local = q - st[lo];
+  if (P.tiles_g != G) return;  // a launch holds the items of one trials-per-wavefront value
+  const int64_t local = (P.nitems * x) / 8 + (k - rx[lo]);
   const int64_t tile = local / P.ngroups;
   const int grp = (int)(local - tile * P.ngroups);
-  DirectTile<G> k;
-  k.run(P, tile, grp);
+  DirectTile<G> tk;
+  tk.run(P, tile, grp);
 }
 
 // The four shifted copies of a linear input: copy m of row c at position p holds
@@ -350,7 +357,8 @@ int launch_direct(const dd_plan* p, const InView& in, const int32_t* d_table, in
 }
 
 int64_t direct_batch_desc_bytes(int32_t n) {
-  return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * (n + 1));
+  // the records, then per trials-per-wavefront value (at most three) the XCD runs [8][items + 1]
+  return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * 8 * (n + 3));
 }
 
 int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int64_t desc_bytes, void* stream) {
@@ -358,33 +366,68 @@ int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int6
   const int32_t n = (int32_t)items.size();
   if (n == 0) return DD_OK;
   if (desc_bytes < direct_batch_desc_bytes(n)) return fail(DD_ERR_WORKSPACE, "batch workspace too small");
-  std::vector<DRParams> P((size_t)n);
-  std::vector<int64_t> start((size_t)n + 1, 0);
-  int waves = -1, gmask = 0;
+  std::vector<DRParams> all((size_t)n);
   for (int32_t i = 0; i < n; ++i) {
     const DirectItem& it = items[i];
-    int rc = prepare(it.plan, it.in, it.table, it.nout, it.out, it.out_stride, it.part, it.quad_ws, st, &P[i]);
+    int rc = prepare(it.plan, it.in, it.table, it.nout, it.out, it.out_stride, it.part, it.quad_ws, st, &all[i]);
     if (rc) return rc;
-    if (waves < 0) waves = P[i].nw;
-    if (P[i].nw != waves)
-      return fail(DD_ERR_UNSUPPORTED, "batched direct-read items must share the wavefronts per workgroup");
-    gmask |= 1 << P[i].tiles_g;
-    start[i + 1] = start[i] + P[i].nitems;
+  }
+  // records grouped by trials per wavefront (one kernel instantiation each), then per group
+  // the XCD runs after all the records
+  std::vector<DRParams> P;
+  std::vector<int64_t> run;
+  struct Group { int g, first, count, waves; int64_t run_at, longest; };
+  std::vector<Group> groups;
+  for (int g : {1, 2, 4}) {
+    // the launch's wavefront count: the one whose items carry the most work (units x
+    // channels); other items are regrouped to it
+    double work[9] = {0};
+    for (const DRParams& r : all)
+      if (r.tiles_g == g) work[r.nw] += (double)r.nitems * r.nchan * r.nw;
+    Group gr{g, (int)P.size(), 0, 0, 0, 0};
+    for (int w = 1; w <= 8; ++w)
+      if (work[w] > 0.0 && (gr.waves == 0 || work[w] > work[gr.waves])) gr.waves = w;
+    if (gr.waves == 0) continue;
+    for (DRParams r : all) {
+      if (r.tiles_g != g) continue;
+      // groups of g x waves trials over the item's padded table (trials past it leave)
+      const int64_t ntiles = r.nitems / r.ngroups;
+      r.nw = gr.waves;
+      r.ngroups = (r.ndm_pad + g * gr.waves - 1) / (g * gr.waves);
+      r.nitems = ntiles * r.ngroups;
+      P.push_back(r);
+      ++gr.count;
+    }
+    gr.run_at = (int64_t)run.size();
+    for (int x = 0; x < 8; ++x) {
+      int64_t k = 0;
+      run.push_back(0);
+      for (int i = 0; i < gr.count; ++i) {
+        const int64_t u = P[gr.first + i].nitems;
+        k += (u * (x + 1)) / 8 - (u * x) / 8;  // XCD x's eighth of item i
+        run.push_back(k);
+      }
+      gr.longest = std::max(gr.longest, k);
+    }
+    groups.push_back(gr);
   }
   char* bw = static_cast<char*>(d_desc);
   DRParams* dP = reinterpret_cast<DRParams*>(bw);
   int64_t* dS = reinterpret_cast<int64_t*>(bw + align_up((int64_t)n * (int64_t)sizeof(DRParams)));
   hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(DRParams), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dS, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dS, run.data(), run.size() * 8, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("hipMemcpyAsync (batch descriptors): ") + hipGetErrorString(e));
-  const int64_t nblocks = (start[n] + 7) / 8 * 8;
-  if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
-  if (nblocks == 0) return DD_OK;
-  // one launch per tile shape present (usually one); each skips the other shapes' units
-  const dim3 grid((unsigned)nblocks), block((unsigned)(64 * waves));
-  if (gmask & 2) hipLaunchKernelGGL(dedisp_direct_batch<1>, grid, block, 0, st, (const DRParams*)dP, (const int64_t*)dS, n);
-  if (gmask & 4) hipLaunchKernelGGL(dedisp_direct_batch<2>, grid, block, 0, st, (const DRParams*)dP, (const int64_t*)dS, n);
-  if (gmask & 16) hipLaunchKernelGGL(dedisp_direct_batch<4>, grid, block, 0, st, (const DRParams*)dP, (const int64_t*)dS, n);
+  for (const Group& gr : groups) {
+    const int64_t nblocks = 8 * gr.longest;
+    if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
+    if (nblocks == 0) continue;
+    const dim3 grid((unsigned)nblocks), block((unsigned)(64 * gr.waves));
+    const DRParams* rec = dP + gr.first;
+    const int64_t* rn = dS + gr.run_at;
+    if (gr.g == 1) hipLaunchKernelGGL(dedisp_direct_batch<1>, grid, block, 0, st, rec, rn, gr.count);
+    if (gr.g == 2) hipLaunchKernelGGL(dedisp_direct_batch<2>, grid, block, 0, st, rec, rn, gr.count);
+    if (gr.g == 4) hipLaunchKernelGGL(dedisp_direct_batch<4>, grid, block, 0, st, rec, rn, gr.count);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("dedisp_direct_batch launch: ") + hipGetErrorString(e));
   return DD_OK;

@@ -5,7 +5,7 @@ one with ``--pmc WRITE_SIZE``, each also running one plain device copy of known 
 
     python -m paper_1401_8258_amd.profiling traffic \
         --fetch <dir>/bench_counter_collection.csv --write <dir>/bench_counter_collection.csv \
-        --kernel dedisp_tile --copy-bytes N --source paper_1401_8258_amd/csrc/dedisp.hip \
+        --kernel dedisp_tile --copy-bytes N --source <comma-separated kernel sources> \
         --out profiles/<kernel>_<workload>_traffic.json
 
 FETCH_SIZE and WRITE_SIZE are KiB per dispatch summed over the L2 channels. Each is
@@ -14,7 +14,7 @@ run, which moves ``copy-bytes`` in each direction. With ``--largest-grid`` only 
 kernel's dispatches with the largest grid count (the full-size launch, when the same
 command also runs the kernel on smaller inputs). The record stores the SHA-256 of the
 kernel source, so a reader can tell when the kernel has changed since the counters were
-taken.
+taken (``source_digest``: the device code of the listed files).
 """
 from __future__ import annotations
 
@@ -26,9 +26,23 @@ import statistics
 import sys
 
 
-def source_digest(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+# Host code of a .hip file starts after this line; the digest of a kernel covers only the
+# device code above it (and every other file it names in full), so edits to host-side
+# launch plumbing do not void a counter record.
+HOST_MARKER = b"// ------------------------------------------------------------------ host side"
+
+
+def source_digest(paths) -> str:
+    """SHA-256 over the device part of each file (all of it when it has no host marker)."""
+    if isinstance(paths, str):
+        paths = paths.split(",")
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            text = f.read()
+        cut = text.find(HOST_MARKER)
+        h.update(text if cut < 0 else text[:cut])
+    return h.hexdigest()
 
 
 def _rows(path: str, counter: str):

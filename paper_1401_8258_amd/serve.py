@@ -90,6 +90,9 @@ class Executor:
     def results(self, handle) -> List[dict]:              # per block: t0, nout, ncand, filling (after done)
         raise NotImplementedError
 
+    def gpu_seconds(self, handle) -> float:               # device time of a finished launch (0 if unknown)
+        return 0.0
+
 
 @dataclasses.dataclass
 class ServeStats:
@@ -103,6 +106,8 @@ class ServeStats:
     admitted_in_run: int = 0   # beams admitted while the run was going (freed slots and memory)
     wall_s: float = 0.0
     data_s: float = 0.0
+    gpu_busy_s: float = 0.0    # device time of every launch (ring appends, dedispersion, tails)
+    stream_s: float = 0.0      # seconds of stream time served: the data of the busiest beam
     latencies: List[float] = dataclasses.field(default_factory=list)
     batch_sizes: List[int] = dataclasses.field(default_factory=list)
 
@@ -117,6 +122,10 @@ class ServeStats:
             "latency_max_s": float(lat.max()), "deadline_misses": self.deadline_misses,
             "admitted_in_run": self.admitted_in_run,
             "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "data_s": self.data_s, "stream_s": self.stream_s, "gpu_busy_s": self.gpu_busy_s,
+            # device seconds per second of stream time (all beams together): below 1 the GPU
+            # keeps up with every beam in real time, and 1 - this is the real-time margin
+            "gpu_busy_s_per_stream_s": self.gpu_busy_s / self.stream_s if self.stream_s > 0 else 0.0,
         }
 
 
@@ -202,6 +211,7 @@ class Server:
         inflight: collections.deque = collections.deque()
         start = self.clock()
         data_s = 0.0
+        beam_s: Dict[int, float] = collections.defaultdict(float)
         while pending or any(ready.values()) or inflight:
             now = self.clock() - start
             while pending and pending[0].arrival <= now:
@@ -211,12 +221,14 @@ class Server:
             while inflight and self.ex.done(inflight[0][0]):
                 h, blocks = inflight.popleft()
                 t_done = self.clock() - start
+                self.stats.gpu_busy_s += self.ex.gpu_seconds(h)
                 for blk, r in zip(blocks, self.ex.results(h)):
                     br = BlockResult(blk.beam, blk.seq, blk.arrival, t_done, r["t0"], r["nout"], r["ncand"],
                                      r["filling"])
                     self.results.append(br)
                     self.stats.blocks += 1
                     data_s += self.specs[blk.beam].block_s
+                    beam_s[blk.beam] += self.specs[blk.beam].block_s
                     if br.filling or (fill is not None and fill(blk.beam)):
                         self.stats.fill_blocks += 1
                         continue
@@ -259,13 +271,14 @@ class Server:
                     break
         self.stats.wall_s = self.clock() - start
         self.stats.data_s = data_s
+        self.stats.stream_s = max(beam_s.values()) if beam_s else 0.0
         return self.stats
 
 
 class LibraryExecutor(Executor):
     """Device side on libdedisp: one Stream (device ring with the maxdelay overlap) per
-    admitted beam, and per submitted set of blocks one batched launch per group of beams
-    that share the input dtype and wavefronts per workgroup.
+    admitted beam, and per submitted set of blocks one batched call per group of beams that
+    can share it (all direct-read beams; LDS-form beams of one dtype and wavefront count).
 
     Each beam owns two output sets (dedispersed block, mean, rms, candidates), used by
     alternate blocks, so a block's results stay intact while the next block of the same
@@ -331,6 +344,10 @@ class LibraryExecutor(Executor):
         return filling
 
     def submit(self, blocks: List[Block]):
+        # the stream runs launches in order, so the time between these two events is this
+        # launch's own device time even when it was queued behind the previous one
+        ev0 = self._torch.cuda.Event(enable_timing=True)
+        ev0.record(self.stream)
         pend = []
         for blk in blocks:
             b = self._beams[blk.beam]
@@ -339,7 +356,10 @@ class LibraryExecutor(Executor):
         for i, (blk, w) in enumerate(zip(blocks, pend)):
             if w is not None:
                 plan = self._beams[blk.beam]["stream"].plan
-                groups[(plan.dtype, plan.tiles[1], plan.producer_waves)].append(i)
+                # direct-read plans of any tiles share a call; LDS-form plans need one dtype,
+                # wavefront count and producer count per call
+                key = ("direct",) if plan.form == "direct" else (plan.dtype, plan.tiles[1], plan.producer_waves)
+                groups[key].append(i)
         res: List[object] = [None] * len(blocks)
         for idx in groups.values():
             jobs, outs = [], []
@@ -354,15 +374,18 @@ class LibraryExecutor(Executor):
         for blk, w in zip(blocks, pend):
             if w is not None:
                 self._beams[blk.beam]["n"] += 1
-        ev = self._torch.cuda.Event()
+        ev = self._torch.cuda.Event(enable_timing=True)
         ev.record(self.stream)
-        return ev, list(blocks), res
+        return ev, list(blocks), res, ev0
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
+    def gpu_seconds(self, handle) -> float:
+        return handle[3].elapsed_time(handle[0]) * 1e-3
+
     def results(self, handle) -> List[dict]:
-        _, blocks, res = handle
+        _, blocks, res, _ = handle
         out = []
         for blk, r in zip(blocks, res):
             if r is None:

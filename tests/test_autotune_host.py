@@ -84,6 +84,11 @@ def test_tune_batch_one_wave_count_for_all(at):
     assert res["waves"] == 4
     assert res["tunings"] == [[8, 4, 2], [8, 4, 2]]
     assert res["choices"] == [{"form": "lds", "tuning": [8, 4, 2]}] * 2
+    # each beam's own best over all counts
+    assert [o["tuning"] for o in res["own_best"]] == [[8, 8, 2], [8, 2, 2]]
+    free = at.tune_batch([_beam(64, 96), _beam(128, 64)], waves=(8, 4, 2), stages=(0, 2),
+                         inputs=[object(), object()], timer=clock, common_waves=False)
+    assert free["choices"] == [{"form": "lds", "tuning": [8, 8, 2]}, {"form": "lds", "tuning": [8, 2, 2]}]
     assert res["by_waves"] == pytest.approx({8: 5.4, 4: 3.15, 2: 4.32})
 
 

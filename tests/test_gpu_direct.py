@@ -172,18 +172,21 @@ def test_stream_ring_shorter_than_a_tile(torch, dd):
 
 
 def test_batch_mixes_direct_and_lds_items(torch, dd):
-    """One batch call: direct-read items of different channel counts and DM ranges (one of
-    them a stream window) and an LDS-form item; each equals its own single call."""
+    """One batch call: direct-read items of different channel counts, DM ranges and tiles
+    (one of them a stream window) and an LDS-form item; each equals its own single call,
+    statistics and candidates included (those run once for the whole batch)."""
     _say("case: direct batch with an LDS item")
     rng = np.random.default_rng(11)
-    shapes = [(256, 428.0, 20.0, 51.2e-6, 300, 0.1, 12000),
-              (1024, 180.0, 60.0, 81.92e-6, 100, 0.05, 30000),
-              (64, 428.0, 20.0, 51.2e-6, 77, 0.2, 4000)]
+    # different channel counts, DM ranges and tiles (trials per wavefront, wavefronts)
+    shapes = [(256, 428.0, 20.0, 51.2e-6, 300, 0.1, 12000, None),
+              (1024, 180.0, 60.0, 81.92e-6, 100, 0.05, 30000, (1, 8)),
+              (64, 428.0, 20.0, 51.2e-6, 77, 0.2, 4000, (4, 2)),
+              (200, 428.0, 20.0, 51.2e-6, 130, 0.1, 9000, (2, 7))]
     jobs, singles = [], []
-    for nchan, ftop, bw, ts, ndm, step, nsamp in shapes:
+    for nchan, ftop, bw, ts, ndm, step, nsamp, tun in shapes:
         freq = fbsynth.channel_freqs(ftop, bw / nchan, nchan)
         dm = fbsynth.dm_trials(0.0, step, ndm)
-        p = dd.Plan(freq, ts, dm, dtype="u8")
+        p = dd.Plan(freq, ts, dm, dtype="u8", form="direct", tuning=tun)
         assert p.form == "direct"
         x = torch.from_numpy(_codes(rng, nchan, nsamp)).cuda()
         jobs.append((p, x))
