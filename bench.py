@@ -37,8 +37,11 @@ LDS_CEILING_TADDS = 256 * 2.4e9 * 221 / 4 / 1e12
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dedisp_tile_full_fp32_1024ch_2048dm_traffic.json")
 _CSRC = os.path.join(ROOT, "paper_1401_8258_amd", "csrc")
-# what the LDS-form kernel's counters depend on: its device code and the launch geometry
-KERNEL_SOURCES = [os.path.join(_CSRC, f) for f in ("dedisp.hip", "dd_device.h", "dd_internal.h", "plan.cpp")]
+# what the LDS-form kernel's counters depend on: its device code (and the launch geometry,
+# compared separately)
+KERNEL_SOURCES = [os.path.join(_CSRC, f) for f in ("dedisp.hip", "dd_device.h")]
+GEOMETRY_KEYS = ("dms_per_wave", "waves", "producer_waves", "launch_buf", "launch_stage", "launch_ring",
+                 "launch_lds")
 
 
 def parse():
@@ -54,10 +57,12 @@ def parse():
                          "(used only while the kernel source is the one it was measured on)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the input (known bytes) to calibrate HBM counters")
-    ap.add_argument("--mode", choices=("plain", "batch", "serve", "subband"), default="plain",
+    ap.add_argument("--mode", choices=("plain", "batch", "serve", "subband", "u8beam"), default="plain",
                     help="plain: the full-size FP32 workload (default); batch: 16 uneven u8 beams in one "
-                         "persistent launch; serve: 64 streaming u8 beams with continuous batching; "
-                         "subband: only the subband passes over the full-size FP32 workload (for profiling)")
+                         "batched call; serve: 64 streaming u8 beams with continuous batching; "
+                         "subband: only the subband passes over the full-size FP32 workload; u8beam: the "
+                         "largest 4096-channel u8 beam of the batch in its default (direct-read) plan "
+                         "(both last two for profiling)")
     ap.add_argument("--serve-blocks", type=int, default=60,
                     help="1 s blocks per beam after the ring fill in the serving run (plain mode appends a "
                          "serving summary when > 0)")
@@ -291,6 +296,44 @@ def batch_run(reps):
             "per_beam_alone": per_beam}
 
 
+def u8beam_run(steps, warmup):
+    """The 4096-channel 120-180 MHz u8 beam of config 4 with the most work, default plan
+    (direct-read form): kernel-only launches (no statistics), then whole steps."""
+    import torch
+
+    import fbsynth
+    import paper_1401_8258_amd as dd
+    from paper_1401_8258_amd import autotune
+
+    specs = [sp for sp in fbsynth.config4_specs() if sp["nchan"] == 4096]
+    sp = max(specs, key=lambda s: s["ndm"] * s["nsamp"])
+    freq = fbsynth.channel_freqs(sp["f_top"], sp["bw"] / sp["nchan"], sp["nchan"])
+    dms = fbsynth.dm_trials(sp["dm0"], sp["step"], sp["ndm"])
+    x = autotune.synthetic_input(sp["nchan"], sp["nsamp"], "u8", seed=3)
+    plan = dd.Plan(freq, sp["tsamp"], dms, dtype="u8")
+    nout = sp["nsamp"] - plan.maxdelay
+    out = torch.empty((plan.ndm, nout), dtype=torch.float32, device="cuda")
+    ws = plan.workspace(sp["nsamp"])
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for stats in (False, True):
+        for _ in range(warmup):
+            plan.dedisperse(x, stats=stats, k_sigma=6.0 if stats else 0.0, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.dedisperse(x, stats=stats, k_sigma=6.0 if stats else 0.0, out=out, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["step_ms" if stats else "prep_and_kernel_ms"] = round(e0.elapsed_time(e1) / steps, 3)
+    adds = plan.ndm * plan.nchan * nout
+    return {"workload": f"u8 beam: {plan.nchan} ch 120-180 MHz, tsamp 81.92 us, nsamp {sp['nsamp']}, "
+                        f"{plan.ndm} DMs step {sp['step']}, maxdelay {plan.maxdelay}",
+            "form": plan.form, "tiles": list(plan.tiles[:2]), "nout": nout, "adds": adds,
+            "adds_per_s_prep_and_kernel": adds / (res["prep_and_kernel_ms"] * 1e-3), **res}
+
+
 def subband_run(dd, beam, steps, warmup):
     """Times the subband passes alone (32-channel subbands; 16 and 48 trials per nominal DM)
     over the full-size FP32 workload, with statistics and 6-sigma candidates."""
@@ -337,6 +380,9 @@ def main():
     dd.load_library()
     if args.mode == "batch":
         print(json.dumps(batch_run(args.steps)), flush=True)
+        return
+    if args.mode == "u8beam":
+        print(json.dumps(u8beam_run(args.steps, args.warmup)), flush=True)
         return
     if args.mode == "serve":
         res = serve_run(max(args.serve_blocks, 1), int(args.hbm_budget_gb * 1e9))
@@ -403,12 +449,14 @@ def main():
 
     adds = beam.ndm * beam.nchan * nout
     achieved = adds / (ms_kernel * 1e-3) / 1e12
+    info = plan.query(nsamp)
+    geometry = {k: int(info[k]) for k in GEOMETRY_KEYS}
     traffic, traffic_note = None, "no counter record"
     if args.traffic and os.path.exists(args.traffic):
         from paper_1401_8258_amd.profiling import source_digest
         with open(args.traffic) as f:
             rec = json.load(f)
-        if rec.get("kernel_source_sha256") == source_digest(KERNEL_SOURCES):
+        if rec.get("kernel_source_sha256") == source_digest(KERNEL_SOURCES) and rec.get("geometry") == geometry:
             traffic = rec["hbm_bytes_per_launch"]
             traffic_note = (f"FETCH_SIZE x {rec['fetch_scale']} + WRITE_SIZE x {rec['write_scale']} "
                             f"(copy-kernel calibration), {os.path.relpath(args.traffic, ROOT)}")
@@ -418,7 +466,7 @@ def main():
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
             "traffic_note": traffic_note, "algorithmic_bytes": algo_bytes,
-            "kernel": "dedisp_tile", "kernel_ms": round(ms_kernel, 3),
+            "kernel": "dedisp_tile", "kernel_ms": round(ms_kernel, 3), "geometry": geometry,
             "achieved_note": "one FP32 add per (DM trial, channel, output sample) = one flop",
             "peak_note": "published FP32 vector peak: 256 CU x 2.4 GHz x 128 lanes x 2 (FMA)",
             "add_issue_rate": round(PEAK_ADD_TFLOPS, 2),

@@ -97,7 +97,11 @@ class Plan:
         h = C.c_void_p()
         tun = None
         kf = _FORMS[form]
-        if tuning is not None:  # (dms_per_wave, waves[, chan_stage[, producer_waves]])
+        if tuning is not None and kf == _lib.DD_FORM_DIRECT:  # (dms_per_wave, waves[, samples_per_lane])
+            g, w = int(tuning[0]), int(tuning[1])
+            spl = int(tuning[2]) if len(tuning) > 2 else 0
+            tun = C.byref(_lib.Tuning(g, w, spl, 0, 0, kf))
+        elif tuning is not None:  # (dms_per_wave, waves[, chan_stage[, producer_waves]])
             g, w = int(tuning[0]), int(tuning[1])
             cc = int(tuning[2]) if len(tuning) > 2 else 0
             pw = int(tuning[3]) if len(tuning) > 3 else 0
@@ -111,10 +115,13 @@ class Plan:
         self._ws = {}
         info = self.query(1, allow_short=True)
         self.maxdelay = int(info["maxdelay"])
-        self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(info["chan_stage"]))
+        self.form = _FORM_NAMES[int(info["kernel_form"])]
+        # (dms_per_wave, waves, chan_stage); the direct-read form has no stages and reports
+        # its samples per lane third
+        third = info["samples_per_lane"] if self.form == "direct" else info["chan_stage"]
+        self.tiles = (int(info["dms_per_wave"]), int(info["waves"]), int(third))
         self.producer_waves = int(info["producer_waves"])
         self.max_span = int(info["max_span"])
-        self.form = _FORM_NAMES[int(info["kernel_form"])]
 
     @property
     def handle(self) -> C.c_void_p:

@@ -5,8 +5,8 @@ The thesis tuned its kernel by sweeping accumulators per thread and threads per
 block on the target GPU (Ch. 2, Sec. Performance and Benchmarks). Here the
 tunables are the kernel form ("lds": every add reads LDS, lanes own 2 x 4 samples,
 DM groups of 8 x waves trials; "regwin", FP32: lanes own 8 consecutive samples held
-in a register window, DM groups of 64 trials; "direct", 8-bit: lanes own 16
-samples read through the caches, DM groups of g x waves trials with g in 1, 2, 4),
+in a register window, DM groups of 64 trials; "direct", 8-bit: lanes own 16 or
+32 samples read through the caches, DM groups of g x waves trials with g in 1, 2, 4),
 the number of wavefronts sharing one LDS ring or workgroup and the channels staged
 per ring slot. ``tune``
 times every candidate on seeded random input of the beam's shape and keeps the
@@ -31,7 +31,8 @@ from .api import Plan, torch_dtype
 WAVES = (8, 4, 2, 1)
 STAGES = (0, 2, 4)
 FORMS = ("lds", "direct")
-DIRECT_G = (1, 2, 4)  # DM trials per wavefront of the direct-read form
+# (DM trials per wavefront, samples per lane) of the direct-read form
+DIRECT_SHAPES = ((1, 16), (2, 16), (4, 16), (1, 32), (2, 32))
 
 
 def _key(freq, tsamp, dm, dtype, nsamp) -> str:
@@ -100,8 +101,8 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
          forms: Sequence[str] = FORMS, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan) -> dict:
     """The fastest of the candidate tilings for one beam shape: {"form", "tuning", "ms",
     "trials"} ("tuning" is (dms_per_wave, waves, chan_stage) for the LDS form, (dms_per_wave,
-    waves) for the direct-read form, None for the register-window form, whose groups are
-    fixed at 8 x 8 trials)."""
+    waves, samples_per_lane) for the direct-read form, None for the register-window form,
+    whose groups are fixed at 8 x 8 trials)."""
     key = _key(freq, tsamp, dm, str(dtype), nsamp) + f":{tuple(waves)}:{tuple(stages)}:{tuple(forms)}"
     if cache is not None and cache.get(key):
         return cache.get(key)
@@ -114,7 +115,7 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
             cands.append({"form": "regwin", "tuning": None})
         elif form == "direct":
             if u8:  # the direct-read form takes 8-bit input only
-                cands += [{"form": "direct", "tuning": [g, w]} for w in waves for g in DIRECT_G]
+                cands += [{"form": "direct", "tuning": [g, w, spl]} for w in waves for g, spl in DIRECT_SHAPES]
         else:
             cands += [{"form": "lds", "tuning": [8, w, cc]} for w in waves for cc in stages]
     trials = []

@@ -159,8 +159,9 @@ int launch_regwin(const dd_plan* p, const InView& in, const int32_t* d_table, in
 // repeat the last DM). Fills the plan's tiles, groups, launch and table.
 int plan_direct(dd_plan* p, const Tiles& t);
 // Bytes per copy row of the direct-read form's copies of an nsamp-sample linear input: the
-// last tile's windows read at most kDirectTile bytes past the last sample's position.
-inline int64_t direct_quad_row(int64_t nsamp) { return align_up(nsamp + kDirectTile + 64, 64); }
+// last tile's windows (two sub-tiles at most) read at most 2 kDirectTile bytes past the
+// last sample's position.
+inline int64_t direct_quad_row(int64_t nsamp) { return align_up(nsamp + 2 * kDirectTile + 64, 64); }
 // Linear input: writes the copies into quad_ws first. Ring input: in.ptr is the ring's
 // copies, in.row_stride their row length.
 int launch_direct(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, float* out,

@@ -1,8 +1,10 @@
 // Direct-read form of the dedispersion kernel for 8-bit input: gfx950, wave64.
 //
-// Eq. bruteEquation, D[d][t] = sum_c A[c][t + delay(c, d)], over one (1024-sample time
+// Eq. bruteEquation, D[d][t] = sum_c A[c][t + delay(c, d)], over one (S x 1024-sample time
 // tile, group of G W DM trials) per workgroup of W wavefronts. Wavefront w owns trials
-// dg + G w .. dg + G w + G - 1; lane l owns output samples t0 + 16 l .. t0 + 16 l + 15.
+// dg + G w .. dg + G w + G - 1; lane l owns output samples t0 + 1024 u + 16 l .. + 15 of
+// each sub-tile u < S. A second sub-tile reuses each trial's scalar offset work and halves
+// the re-reads of a channel's delay range per output (one per 2048-sample tile).
 //
 // Nothing is staged in LDS. The input is held as four copies per channel, copy m shifted
 // by m samples (copy m at position p holds sample p + m), so a trial whose window starts
@@ -38,10 +40,10 @@
 
 namespace {
 
-constexpr int kDrLane = 16;                // output samples per lane
-constexpr int kDrTile = 64 * kDrLane;      // output samples per tile
-static_assert(kDrTile == 2 * dd::kTile, "a tile is two statistics segments");
-static_assert(kDrTile == dd::kDirectTile, "tile disagrees with the plan");
+constexpr int kDrLane = 16;                // output samples per lane and sub-tile
+constexpr int kDrTile = 64 * kDrLane;      // output samples per sub-tile
+static_assert(kDrTile == 2 * dd::kTile, "a sub-tile is two statistics segments");
+static_assert(kDrTile == dd::kDirectTile, "sub-tile disagrees with the plan");
 // Buffer resource word 3 for raw (unswizzled, stride 0) buffers on gfx9-family devices.
 constexpr int kRsrcWord3 = 0x00020000;
 
@@ -59,44 +61,54 @@ struct DRParams {
   int nchan, ndm, ndm_pad, ngroups;
   int nw;               // wavefronts per workgroup
   int tiles_g;          // DM trials per wavefront
+  int tiles_s;          // 1024-sample sub-tiles per wavefront tile
+  int pad_;
 };
 static_assert(sizeof(DRParams) % 4 == 0, "DRParams is copied as dwords");
 
-template <int G>
+template <int G, int S>
 struct DirectTile {
-  uint32_t pr[G][8];    // 16-bit pairs: (s0, s2), (s1, s3) of dwords 0..3
-  uint32_t acc[G][16];  // per sample
+  uint32_t pr[G][S][8];    // 16-bit pairs: (s0, s2), (s1, s3) of dwords 0..3
+  uint32_t acc[G][S][16];  // per sample
 
   __device__ __forceinline__ void fold() {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t a = pr[g][2 * k], b = pr[g][2 * k + 1];
-        acc[g][4 * k] += a & 0xffffu;
-        acc[g][4 * k + 2] += a >> 16;
-        acc[g][4 * k + 1] += b & 0xffffu;
-        acc[g][4 * k + 3] += b >> 16;
-        pr[g][2 * k] = 0u;
-        pr[g][2 * k + 1] = 0u;
+      for (int u = 0; u < S; ++u) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t a = pr[g][u][2 * k], b = pr[g][u][2 * k + 1];
+          acc[g][u][4 * k] += a & 0xffffu;
+          acc[g][u][4 * k + 2] += a >> 16;
+          acc[g][u][4 * k + 1] += b & 0xffffu;
+          acc[g][u][4 * k + 3] += b >> 16;
+          pr[g][u][2 * k] = 0u;
+          pr[g][u][2 * k + 1] = 0u;
+        }
       }
     }
   }
 
-  __device__ __forceinline__ void add(const u32x4 (&v)[G]) {
+  __device__ __forceinline__ void add(const u32x4 (&v)[G][S]) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t x = v[g][k];
-        pr[g][2 * k] += x & 0x00ff00ffu;
-        pr[g][2 * k + 1] += (x >> 8) & 0x00ff00ffu;
+      for (int u = 0; u < S; ++u) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t x = v[g][u][k];
+          pr[g][u][2 * k] += x & 0x00ff00ffu;
+          pr[g][u][2 * k + 1] += (x >> 8) & 0x00ff00ffu;
+        }
       }
     }
   }
 
+  // the sub-tiles of a trial read consecutive 1 KB windows at one scalar offset (the
+  // instruction's immediate offset adds 1024 per sub-tile)
   __device__ __forceinline__ void load(const DRParams& P, int c, int t0w, int lane, dd::ci32_t tab,
-                                       u32x4 (&v)[G]) {
+                                       u32x4 (&v)[G][S]) {
     const int64_t row4 = 4 * P.lq;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(P.quad + (int64_t)c * row4), (short)0, (int)row4, kRsrcWord3);
@@ -106,27 +118,32 @@ struct DirectTile {
       int s = t0w + drow[g];
       if (P.ring_len && s >= (int)P.ring_len) s -= (int)P.ring_len;
       const int m = s & 3;
-      v[g] = __builtin_amdgcn_raw_buffer_load_b128(rs, kDrLane * lane, m * (int)P.lq + (s - m), 0);
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+        v[g][u] = __builtin_amdgcn_raw_buffer_load_b128(rs, kDrLane * lane + kDrTile * u, m * (int)P.lq + (s - m), 0);
     }
   }
 
   __device__ __forceinline__ void run(const DRParams& P, int64_t tile, int grp) {
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = tile * kDrTile;
+    const int64_t t0 = tile * (kDrTile * S);
     const int dw = grp * G * P.nw + w * G;
     if (dw >= P.ndm_pad) return;  // a batched item regrouped to more wavefronts than its plan's
 #pragma unroll
     for (int g = 0; g < G; ++g) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) pr[g][q] = 0u;
+      for (int u = 0; u < S; ++u) {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) acc[g][s] = 0u;
+        for (int q = 0; q < 8; ++q) pr[g][u][q] = 0u;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[g][u][q] = 0u;
+      }
     }
     const dd::ci32_t tab = (dd::ci32_t)(P.dtab + dw);
     const int t0w = (int)(t0 + P.w0);  // window position 0 of this tile (ring: < ring_len + tile)
     const int nchan = P.nchan;
-    u32x4 va[G], vb[G];
+    u32x4 va[G][S], vb[G][S];
     load(P, 0, t0w, lane, tab, va);
     // channel pairs (c, c + 1): the loads of the next channel are issued before the adds
     for (int c = 0; c < nchan; c += 2) {
@@ -140,44 +157,48 @@ struct DirectTile {
     fold();
 
     const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
-    const int64_t tb = t0 + kDrLane * lane;
-    const int64_t seg = 2 * tile + (lane >> 5);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int d = dw + g;
       if (d >= P.ndm) break;
-      float x[16];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) x[s] = (float)acc[g][s];
       float* orow = P.out + (int64_t)d * P.out_stride;
-      if (vec_ok && tb + 15 < P.nout) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          *reinterpret_cast<float4*>(orow + tb + 4 * q) = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-      } else {
+      for (int u = 0; u < S; ++u) {
+        const int64_t tb = t0 + kDrTile * u + kDrLane * lane;
+        const int64_t seg = (t0 + kDrTile * u) / dd::kTile + (lane >> 5);
+        float x[16];
 #pragma unroll
-        for (int s = 0; s < 16; ++s)
-          if (tb + s < P.nout) orow[tb + s] = x[s];
-      }
-      if (P.part) {
-        double s1 = 0.0, s2 = 0.0;
+        for (int q = 0; q < 16; ++q) x[q] = (float)acc[g][u][q];
+        if (vec_ok && tb + 15 < P.nout) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          if (tb + s < P.nout) {
-            const double y = x[s];
-            s1 += y;
-            s2 += y * y;
+          for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<float4*>(orow + tb + 4 * q) =
+                make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            if (tb + q < P.nout) orow[tb + q] = x[q];
+        }
+        if (P.part) {
+          double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            if (tb + q < P.nout) {
+              const double y = x[q];
+              s1 += y;
+              s2 += y * y;
+            }
           }
-        }
-        // each half wavefront covers one 512-sample segment
+          // each half wavefront covers one 512-sample segment
 #pragma unroll
-        for (int off = 16; off > 0; off >>= 1) {
-          s1 += __shfl_xor(s1, off, 64);
-          s2 += __shfl_xor(s2, off, 64);
-        }
-        if ((lane & 31) == 0 && seg < P.nseg) {
-          P.part[((int64_t)d * P.nseg + seg) * 2] = s1;
-          P.part[((int64_t)d * P.nseg + seg) * 2 + 1] = s2;
+          for (int off = 16; off > 0; off >>= 1) {
+            s1 += __shfl_xor(s1, off, 64);
+            s2 += __shfl_xor(s2, off, 64);
+          }
+          if ((lane & 31) == 0 && seg < P.nseg) {
+            P.part[((int64_t)d * P.nseg + seg) * 2] = s1;
+            P.part[((int64_t)d * P.nseg + seg) * 2 + 1] = s2;
+          }
         }
       }
     }
@@ -186,7 +207,7 @@ struct DirectTile {
 
 // One work unit per workgroup; each XCD (workgroups lin, lin + 8, ...) takes a contiguous
 // run of units, tile-major, so the DM groups of a tile share that XCD's L2.
-template <int G>
+template <int G, int S>
 __global__ __launch_bounds__(512) void dedisp_direct(DRParams P) {
   const int64_t lin = blockIdx.x;
   const int64_t per = (P.nitems + 7) / 8;
@@ -194,7 +215,7 @@ __global__ __launch_bounds__(512) void dedisp_direct(DRParams P) {
   if (item >= P.nitems) return;
   const int64_t tile = item / P.ngroups;
   const int grp = (int)(item - tile * P.ngroups);
-  DirectTile<G> k;
+  DirectTile<G, S> k;
   k.run(P, tile, grp);
 }
 
@@ -207,7 +228,7 @@ __global__ __launch_bounds__(512) void dedisp_direct(DRParams P) {
 // The item's parameters are read through the scalar cache. Every item's trials are
 // regrouped into workgroups of the launch's wavefront count (a trial's sum does not depend
 // on which workgroup computes it); the count is the one whose items carry the most work.
-template <int G>
+template <int G, int S>
 __global__ __launch_bounds__(512) void dedisp_direct_batch(const DRParams* __restrict__ items,
                                                            const int64_t* __restrict__ run, int nitems) {
   typedef const __attribute__((address_space(4))) int64_t* ci64_t;
@@ -230,11 +251,11 @@ __global__ __launch_bounds__(512) void dedisp_direct_batch(const DRParams* __res
   for (int j = 0; j < (int)(sizeof(DRParams) / 4); ++j) wv[j] = src[j];
   DRParams P;
   __builtin_memcpy(&P, wv, sizeof(DRParams));
-  if (P.tiles_g != G) return;  // a launch holds the items of one trials-per-wavefront value
+  if (P.tiles_g != G || P.tiles_s != S) return;  // a launch holds the items of one tile shape
   const int64_t local = (P.nitems * x) / 8 + (k - rx[lo]);
   const int64_t tile = local / P.ngroups;
   const int grp = (int)(local - tile * P.ngroups);
-  DirectTile<G> tk;
+  DirectTile<G, S> tk;
   tk.run(P, tile, grp);
 }
 
@@ -282,10 +303,19 @@ __global__ __launch_bounds__(256) void ring_append_quad(const uint8_t* __restric
   }
 }
 
-template <int G>
-void launch_g(const DRParams& P, int64_t nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((dedisp_direct<G>), dim3((unsigned)nblocks), dim3(64 * P.nw), 0, st, P);
+template <int G, int S>
+void launch_gs(const DRParams& P, int64_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((dedisp_direct<G, S>), dim3((unsigned)nblocks), dim3(64 * P.nw), 0, st, P);
 }
+
+template <int G, int S>
+void launch_batch_gs(const DRParams* rec, const int64_t* run, int count, int64_t nblocks, int waves,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((dedisp_direct_batch<G, S>), dim3((unsigned)nblocks), dim3(64 * waves), 0, st, rec, run, count);
+}
+
+// The tile shapes the kernels are built for: (trials per wavefront, sub-tiles).
+bool shape_ok(int g, int sub) { return (g == 1 || g == 2 || g == 4) && (sub == 1 || (sub == 2 && g <= 2)); }
 
 }  // namespace
 
@@ -311,14 +341,15 @@ int prepare(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t 
   // buffer offsets are 32-bit: four copy rows per channel, and ring positions below 2^31
   if (4 * P->lq >= ((int64_t)1 << 31) || P->ring_len + kDirectTile >= ((int64_t)1 << 31))
     return fail(DD_ERR_UNSUPPORTED, "rows of 2^29 samples or more are not supported by the direct-read form");
-  if (p->tiles.g != 1 && p->tiles.g != 2 && p->tiles.g != 4)
-    return fail(DD_ERR_UNSUPPORTED, "direct-read form: dms_per_wave must be 1, 2 or 4");
+  const int sub = p->tiles.s / kDrLane;
+  if (!shape_ok(p->tiles.g, sub))
+    return fail(DD_ERR_UNSUPPORTED, "direct-read form: unsupported (dms_per_wave, samples_per_lane)");
   if (in.ring_len == 0) {
     const dim3 grid((unsigned)((P->lq / 16 + 255) / 256), (unsigned)p->nchan);
     hipLaunchKernelGGL(quad_prep, grid, dim3(256), 0, st, static_cast<const uint8_t*>(in.ptr), in.row_stride,
                        in.nvalid, const_cast<uint8_t*>(P->quad), P->lq);
   }
-  const int64_t ntiles = (nout + kDirectTile - 1) / kDirectTile;
+  const int64_t ntiles = (nout + kDirectTile * sub - 1) / (kDirectTile * sub);
   P->dtab = d_table;
   P->out = out;
   P->part = part;
@@ -332,6 +363,7 @@ int prepare(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t 
   P->ngroups = p->ngroups;
   P->nw = p->tiles.w;
   P->tiles_g = p->tiles.g;
+  P->tiles_s = sub;
   return DD_OK;
 }
 
@@ -346,10 +378,13 @@ int launch_direct(const dd_plan* p, const InView& in, const int32_t* d_table, in
   const int64_t nblocks = (P.nitems + 7) / 8 * 8;
   if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
   if (nblocks == 0) return DD_OK;
-  switch (P.tiles_g) {
-    case 1: launch_g<1>(P, nblocks, st); break;
-    case 2: launch_g<2>(P, nblocks, st); break;
-    default: launch_g<4>(P, nblocks, st); break;
+  const int shape = P.tiles_g * 10 + P.tiles_s;
+  switch (shape) {
+    case 11: launch_gs<1, 1>(P, nblocks, st); break;
+    case 21: launch_gs<2, 1>(P, nblocks, st); break;
+    case 41: launch_gs<4, 1>(P, nblocks, st); break;
+    case 12: launch_gs<1, 2>(P, nblocks, st); break;
+    default: launch_gs<2, 2>(P, nblocks, st); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("dedisp_direct launch: ") + hipGetErrorString(e));
@@ -357,8 +392,8 @@ int launch_direct(const dd_plan* p, const InView& in, const int32_t* d_table, in
 }
 
 int64_t direct_batch_desc_bytes(int32_t n) {
-  // the records, then per trials-per-wavefront value (at most three) the XCD runs [8][items + 1]
-  return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * 8 * (n + 3));
+  // the records, then per tile shape (at most five) the XCD runs [8][items + 1]
+  return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * 8 * (n + 5));
 }
 
 int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int64_t desc_bytes, void* stream) {
@@ -376,20 +411,21 @@ int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int6
   // the XCD runs after all the records
   std::vector<DRParams> P;
   std::vector<int64_t> run;
-  struct Group { int g, first, count, waves; int64_t run_at, longest; };
+  struct Group { int g, sub, first, count, waves; int64_t run_at, longest; };
   std::vector<Group> groups;
-  for (int g : {1, 2, 4}) {
+  for (int shape : {11, 21, 41, 12, 22}) {
+    const int g = shape / 10, sub = shape % 10;
     // the launch's wavefront count: the one whose items carry the most work (units x
     // channels); other items are regrouped to it
     double work[9] = {0};
     for (const DRParams& r : all)
-      if (r.tiles_g == g) work[r.nw] += (double)r.nitems * r.nchan * r.nw;
-    Group gr{g, (int)P.size(), 0, 0, 0, 0};
+      if (r.tiles_g == g && r.tiles_s == sub) work[r.nw] += (double)r.nitems * r.nchan * r.nw;
+    Group gr{g, sub, (int)P.size(), 0, 0, 0, 0};
     for (int w = 1; w <= 8; ++w)
       if (work[w] > 0.0 && (gr.waves == 0 || work[w] > work[gr.waves])) gr.waves = w;
     if (gr.waves == 0) continue;
     for (DRParams r : all) {
-      if (r.tiles_g != g) continue;
+      if (r.tiles_g != g || r.tiles_s != sub) continue;
       // groups of g x waves trials over the item's padded table (trials past it leave)
       const int64_t ntiles = r.nitems / r.ngroups;
       r.nw = gr.waves;
@@ -421,12 +457,15 @@ int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int6
     const int64_t nblocks = 8 * gr.longest;
     if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
     if (nblocks == 0) continue;
-    const dim3 grid((unsigned)nblocks), block((unsigned)(64 * gr.waves));
     const DRParams* rec = dP + gr.first;
     const int64_t* rn = dS + gr.run_at;
-    if (gr.g == 1) hipLaunchKernelGGL(dedisp_direct_batch<1>, grid, block, 0, st, rec, rn, gr.count);
-    if (gr.g == 2) hipLaunchKernelGGL(dedisp_direct_batch<2>, grid, block, 0, st, rec, rn, gr.count);
-    if (gr.g == 4) hipLaunchKernelGGL(dedisp_direct_batch<4>, grid, block, 0, st, rec, rn, gr.count);
+    switch (gr.g * 10 + gr.sub) {
+      case 11: launch_batch_gs<1, 1>(rec, rn, gr.count, nblocks, gr.waves, st); break;
+      case 21: launch_batch_gs<2, 1>(rec, rn, gr.count, nblocks, gr.waves, st); break;
+      case 41: launch_batch_gs<4, 1>(rec, rn, gr.count, nblocks, gr.waves, st); break;
+      case 12: launch_batch_gs<1, 2>(rec, rn, gr.count, nblocks, gr.waves, st); break;
+      default: launch_batch_gs<2, 2>(rec, rn, gr.count, nblocks, gr.waves, st); break;
+    }
   }
   e = hipGetLastError();
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("dedisp_direct_batch launch: ") + hipGetErrorString(e));

@@ -274,21 +274,25 @@ bool plan_regwin(dd_plan* p, int64_t lds_cap) {
 }
 
 // Direct-read form: t.g trials per wavefront, t.w wavefronts per workgroup; the table is the
-// plain delays per (channel, padded trial). A wavefront load spans one 1024-sample tile, so a
-// ring's mirror of launch.L + 64 samples covers every window that starts before the ring's end.
+// plain delays per (channel, padded trial). A wavefront's loads span at most two 1024-sample
+// sub-tiles, so a ring's mirror of launch.L + 64 samples covers every window that starts
+// before the ring's end.
 int plan_direct(dd_plan* p, const Tiles& t) {
   if (t.g != 1 && t.g != 2 && t.g != 4)
     return fail(DD_ERR_UNSUPPORTED, "the direct-read form takes dms_per_wave 1, 2 or 4");
   if (t.w < 1 || t.w > 8) return fail(DD_ERR_UNSUPPORTED, "the direct-read form takes waves 1..8");
+  if (t.s != 16 && !(t.s == 32 && t.g <= 2))
+    return fail(DD_ERR_UNSUPPORTED, "the direct-read form takes samples_per_lane 16, or 32 with dms_per_wave "
+                                    "1 or 2");
   const int32_t nchan = p->nchan, ndm = p->ndm;
-  p->tiles = Tiles{t.g, t.w, 16, 0, -1};
+  p->tiles = Tiles{t.g, t.w, t.s, 0, -1};
   p->dms_per_group = t.g * t.w;
   p->ngroups = (ndm + p->dms_per_group - 1) / p->dms_per_group;
   p->ndm_pad = p->ngroups * p->dms_per_group;
   p->max_span = compute_span(p->delays, nchan, ndm, p->dms_per_group);
   Launch l{};
   l.form = kFormDirect;
-  l.L = (int)kDirectTile;
+  l.L = (int)(2 * kDirectTile);  // the widest wavefront tile (two sub-tiles)
   p->launch = l;
   p->dev_table.assign((size_t)nchan * p->ndm_pad, 0);
   for (int32_t c = 0; c < nchan; ++c) {
@@ -359,8 +363,7 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   if (direct) {
     t.g = tuning && tuning->dms_per_wave ? tuning->dms_per_wave : 2;
     t.w = tuning && tuning->waves ? tuning->waves : 4;
-    if (tuning && tuning->samples_per_lane && tuning->samples_per_lane != 16)
-      return dd::fail(DD_ERR_UNSUPPORTED, "the direct-read form takes samples_per_lane 16");
+    t.s = tuning && tuning->samples_per_lane ? tuning->samples_per_lane : 16;
   } else if (!valid_tiles(t)) {
     return dd::fail(DD_ERR_UNSUPPORTED, "unsupported tuning");
   }

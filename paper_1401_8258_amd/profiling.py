@@ -13,8 +13,9 @@ scaled by bytes / counter of the copy kernel (``__amd_rocclr_copyBuffer``) of th
 run, which moves ``copy-bytes`` in each direction. With ``--largest-grid`` only the
 kernel's dispatches with the largest grid count (the full-size launch, when the same
 command also runs the kernel on smaller inputs). The record stores the SHA-256 of the
-kernel source, so a reader can tell when the kernel has changed since the counters were
-taken (``source_digest``: the device code of the listed files).
+kernel source and the launch geometry of the profiled plan, so a reader can tell when the
+kernel has changed since the counters were taken (``source_digest``: the device code of the
+listed files).
 """
 from __future__ import annotations
 
@@ -71,7 +72,7 @@ def _kernel_and_copy(path: str, counter: str, kernel: str, largest_grid: bool = 
 
 
 def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, source: str,
-            largest_grid: bool = False) -> dict:
+            largest_grid: bool = False, geometry: dict = None) -> dict:
     fk, fc = _kernel_and_copy(fetch_csv, "FETCH_SIZE", kernel, largest_grid)
     wk, wc = _kernel_and_copy(write_csv, "WRITE_SIZE", kernel, largest_grid)
     f_scale = copy_bytes / (fc * 1024.0)
@@ -86,6 +87,8 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, source
         "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
         "copy_bytes": copy_bytes, "launches": len(fk),
         "kernel_source_sha256": source_digest(source),
+        # the launch geometry the counters were taken with (the plan's tiles and LDS ring)
+        "geometry": geometry,
     }
 
 
@@ -100,8 +103,11 @@ def main(argv=None):
     t.add_argument("--source", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--largest-grid", action="store_true", help="only the dispatches with the largest grid")
+    t.add_argument("--geometry", default=None,
+                   help="JSON object: the launch geometry of the profiled plan (bench.py prints it)")
     a = ap.parse_args(argv)
-    rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.source, a.largest_grid)
+    geo = json.loads(a.geometry) if a.geometry else None
+    rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.source, a.largest_grid, geo)
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")

@@ -192,7 +192,7 @@ def test_every_workload_has_a_launch_geometry(lib):
         if dt == 2 and tun is None:
             # 8-bit input takes the direct-read form by default: no LDS, 1024-sample tiles
             assert info.kernel_form == lib_mod.DD_FORM_DIRECT
-            assert info.launch_lds == 0 and info.launch_buf == 1024 and info.samples_per_lane == 16
+            assert info.launch_lds == 0 and info.launch_buf == 2048 and info.samples_per_lane == 16
             assert (info.dms_per_wave, info.waves) == (2, 4)
             # the same beam in the LDS form must also fit
             info = _launch_ok(lib, freq, dm, tsamp, dt, (0, 0, 0, 0, 0, lib_mod.DD_FORM_LDS))

@@ -99,15 +99,15 @@ def test_tune_offers_the_direct_form_for_8bit_beams(at):
         def __call__(self, plan, x, reps):
             self.calls += 1
             g, w, cc = plan.tiles
-            if plan.form == "direct":
-                return {1: 1.0, 2: 0.4, 4: 0.7}[g] * (1.0 if w == 4 else 1.5)
+            if plan.form == "direct":  # tiles = (g, w, samples_per_lane)
+                return {1: 1.0, 2: 0.4, 4: 0.7}[g] * (1.0 if w == 4 else 1.5) * (0.9 if cc == 32 else 1.0)
             return 2.0
     clock = Clock({}, {})
     freq, tsamp, dm, _, nsamp = _beam(64, 96)
     r = at.tune(freq, tsamp, dm, "u8", nsamp, waves=(8, 4), stages=(0,), x=object(), timer=clock)
-    assert r["form"] == "direct" and r["tuning"] == [2, 4] and r["ms"] == pytest.approx(0.4)
+    assert r["form"] == "direct" and r["tuning"] == [2, 4, 32] and r["ms"] == pytest.approx(0.36)
     forms = [t["form"] for t in r["trials"]]
-    assert forms.count("direct") == 6 and forms.count("lds") == 2
+    assert forms.count("direct") == 10 and forms.count("lds") == 2
     assert at.make_plan(freq, tsamp, dm, "u8", r).form == "direct"
     r = at.tune(freq, tsamp, dm, "f32", nsamp, waves=(8, 4), stages=(0,), x=object(), timer=clock)
     assert all(t["form"] == "lds" for t in r["trials"])

@@ -68,13 +68,15 @@ def test_default_form_for_u8_and_config3_bit_exact(torch, dd):
 
 
 # nchan, f_top, channel width (MHz), tsamp, ndm, DM step, nsamp, input row padding,
-# output row padding, (dms_per_wave, waves) or None
+# output row padding, (dms_per_wave, waves[, samples_per_lane]) or None
 EDGES = [
     (1, 428.0, 0.3125, 51.2e-6, 1, 0.1, 300, 0, 0, None),        # one channel, one trial
     (64, 428.0, 0.3125, 51.2e-6, 128, 0.1, 556, 0, 0, None),     # nout = 1
     (64, 428.0, 0.3125, 51.2e-6, 128, 0.1, 1500, 3, 1, (1, 8)),  # nout < one tile, odd paddings
     (37, 428.0, 0.5, 51.2e-6, 33, 0.1, 3000, 1, 0, (4, 2)),      # odd channels, partial group
     (300, 428.0, 0.06, 51.2e-6, 70, 0.1, 5001, 0, 4, (2, 8)),    # one pair fold, ragged tail
+    (300, 428.0, 0.06, 51.2e-6, 70, 0.1, 5001, 0, 4, (2, 8, 32)),  # the same, 2048-sample tiles
+    (64, 428.0, 0.3125, 51.2e-6, 50, 0.1, 3100, 3, 1, (1, 4, 32)),  # ragged second sub-tile
     (513, 428.0, 20.0 / 513, 51.2e-6, 40, 0.1, 4097, 0, 0, (4, 1)),  # folds at 256 and 512
     (257, 180.0, 60.0 / 257, 81.92e-6, 24, 0.05, 26000, 0, 0, None),  # low band, large shifts
 ]
@@ -102,7 +104,7 @@ def test_edges_bit_exact(torch, dd, nchan, ftop, df, tsamp, ndm, step, nsamp, pa
     p = dd.Plan(freq, tsamp, dm, dtype="u8", form="direct", tuning=tun)
     q = dd.Plan(freq, tsamp, dm, dtype="u8", form="lds")
     if tun is not None:
-        assert p.tiles[:2] == tuple(tun)
+        assert p.tiles[:len(tun)] == tuple(tun)
     xt = torch.from_numpy(full).cuda()[:, :nsamp]
     o1 = torch.full((ndm, nout + opad), -7.0, device="cuda")
     r1 = p.dedisperse(xt, k_sigma=k, out=o1)
@@ -116,10 +118,11 @@ def test_edges_bit_exact(torch, dd, nchan, ftop, df, tsamp, ndm, step, nsamp, pa
     compare_candidates(r1.candidates(), want, mean, rms, k)
 
 
-def test_stream_ragged_blocks_equal_one_shot_and_oracle(torch, dd):
+@pytest.mark.parametrize("tun", [None, (1, 4, 32)])
+def test_stream_ragged_blocks_equal_one_shot_and_oracle(torch, dd, tun):
     """A stream of ragged blocks on a low-band beam: each window equals the one-shot result
     and the oracle's definition of a stream (the ring holds the shifted copies)."""
-    _say("case: direct stream, low band")
+    _say(f"case: direct stream, low band, tun={tun}")
     freq = fbsynth.channel_freqs(180.0, 60.0 / 512, 512)
     dm = fbsynth.dm_trials(0.0, 0.05, 40)
     tsamp = 81.92e-6
@@ -128,7 +131,7 @@ def test_stream_ragged_blocks_equal_one_shot_and_oracle(torch, dd):
     sizes = [block, block, 1111, block, 1, block, 2500, block, block, block]
     x = _codes(np.random.default_rng(77), 512, sum(sizes))
     expected = orc.stream_expected(np.split(x, np.cumsum(sizes)[:-1], axis=1), tab)
-    plan = dd.Plan(freq, tsamp, dm, dtype="u8")
+    plan = dd.Plan(freq, tsamp, dm, dtype="u8", form="direct", tuning=tun)
     assert plan.form == "direct"
     one = plan.dedisperse(torch.from_numpy(x).cuda()).out
     s = dd.Stream(plan, block)
@@ -148,14 +151,15 @@ def test_stream_ragged_blocks_equal_one_shot_and_oracle(torch, dd):
     assert emitted == sum(sizes) - int(tab.max())
 
 
-def test_stream_ring_shorter_than_a_tile(torch, dd):
+@pytest.mark.parametrize("tun", [None, (2, 4, 32)])
+def test_stream_ring_shorter_than_a_tile(torch, dd, tun):
     """Blocks of 40 samples and a maximum delay of 8: the ring (64 samples) is shorter than
-    the 1024-sample tile, so every window reads the copies' mirror, many times over."""
-    _say("case: direct stream, tiny ring")
+    the 1024- or 2048-sample tile, so every window reads the copies' mirror, many times over."""
+    _say(f"case: direct stream, tiny ring, tun={tun}")
     freq = fbsynth.channel_freqs(428.0, 0.3125, 16)
     dm = fbsynth.dm_trials(0.0, 0.1, 9)
     x = _codes(np.random.default_rng(3), 16, 3000)
-    plan = dd.Plan(freq, 51.2e-6, dm, dtype="u8")
+    plan = dd.Plan(freq, 51.2e-6, dm, dtype="u8", form="direct", tuning=tun)
     one = plan.dedisperse(torch.from_numpy(x).cuda()).out
     s = dd.Stream(plan, 40)
     pos = seen = 0
@@ -181,7 +185,9 @@ def test_batch_mixes_direct_and_lds_items(torch, dd):
     shapes = [(256, 428.0, 20.0, 51.2e-6, 300, 0.1, 12000, None),
               (1024, 180.0, 60.0, 81.92e-6, 100, 0.05, 30000, (1, 8)),
               (64, 428.0, 20.0, 51.2e-6, 77, 0.2, 4000, (4, 2)),
-              (200, 428.0, 20.0, 51.2e-6, 130, 0.1, 9000, (2, 7))]
+              (200, 428.0, 20.0, 51.2e-6, 130, 0.1, 9000, (2, 7)),
+              (512, 180.0, 60.0, 81.92e-6, 60, 0.05, 20000, (2, 4, 32)),
+              (128, 428.0, 20.0, 51.2e-6, 40, 0.1, 7000, (1, 2, 32))]
     jobs, singles = [], []
     for nchan, ftop, bw, ts, ndm, step, nsamp, tun in shapes:
         freq = fbsynth.channel_freqs(ftop, bw / nchan, nchan)
@@ -219,13 +225,14 @@ def test_batch_mixes_direct_and_lds_items(torch, dd):
 
 
 def test_tilings_equal(torch, dd):
-    """Every (dms_per_wave, waves) tiling of the direct-read form gives the same bits."""
+    """Every (dms_per_wave, waves[, samples_per_lane]) tiling of the direct-read form gives the
+    same bits."""
     _say("case: direct tilings")
     freq = fbsynth.channel_freqs(180.0, 60.0 / 300, 300)
     dm = fbsynth.dm_trials(0.0, 0.1, 53)
     x = torch.from_numpy(_codes(np.random.default_rng(8), 300, 30000)).cuda()
     base = dd.Plan(freq, 81.92e-6, dm, dtype="u8").dedisperse(x)
-    for tun in [(1, 1), (1, 8), (2, 2), (4, 4), (4, 8), (2, 5)]:
+    for tun in [(1, 1), (1, 8), (2, 2), (4, 4), (4, 8), (2, 5), (1, 8, 32), (2, 4, 32), (2, 3, 32)]:
         r = dd.Plan(freq, 81.92e-6, dm, dtype="u8", form="direct", tuning=tun).dedisperse(x)
         assert torch.equal(r.out, base.out), tun
         assert torch.equal(r.mean, base.mean) and torch.equal(r.rms, base.rms), tun
