@@ -26,6 +26,11 @@ What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
 * Boxcar smoothing by successively adding adjacent samples (single-pulse detection,
   Sec. 2; boxcar templates downfactor the series, Sec. 6): level k holds the sums of
   2^k consecutive samples over sqrt(2^k), non-overlapping.
+* Boxcar template matching (Sec. 6 "Transient Surveys": boxcars of varying width
+  convolved with each dedispersed series, then thresholded; Sec. 2 Eq. pulseSNREquation:
+  S/N grows as the square root of the samples a matched boxcar adds): for widths
+  w = 2^j, the sum of w samples at every start offset, its S/N about the series mean in
+  units of rms sqrt(w), and a detection wherever the best width's S/N exceeds k.
 * Time binning (Sec. 2 "Direct Dedispersion", Sec. "Computing Larger DMs"): above the
   diagonal DM (where adjacent channels' delays differ by one sample) the input is
   downfactored by 2 by summing adjacent samples, again at twice the diagonal, and so on:
@@ -221,6 +226,73 @@ def boxcar_levels(series: np.ndarray, levels: int):
         m = x.shape[1] // w
         out.append(x[:, : m * w].reshape(x.shape[0], m, w).sum(axis=2) / math.sqrt(w))
     return out
+
+
+def boxcar_snr(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, max_log2: int):
+    """S/N of every boxcar (Sec. 6 template matching, at every start offset): for width
+    w = 2^j (j = 0 .. max_log2), B_w[d, t] = sum_{i < w} x[d, t + i] for t + w <= n, and
+    S/N_w = (B_w - w mean_d) / (rms_d sqrt(w)), in FP64. Returns a list over j of arrays
+    [nrows][n - w + 1] (rows with rms <= 0 hold -inf: no detection is defined there).
+    """
+    x = np.atleast_2d(np.asarray(series, dtype=np.float64))
+    m = np.asarray(mean, np.float64)[:, None]
+    r = np.asarray(rms, np.float64)[:, None]
+    out = []
+    for j in range(max_log2 + 1):
+        w = 1 << j
+        if x.shape[1] < w:
+            out.append(np.full((x.shape[0], 0), -np.inf))
+            continue
+        b = np.lib.stride_tricks.sliding_window_view(x, w, axis=1).sum(axis=2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            snr = np.where(r > 0, (b - w * m) / (r * math.sqrt(w)), -np.inf)
+        out.append(snr)
+    return out
+
+
+def boxcar_search(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, max_log2: int, k_sigma: float):
+    """Boxcar template matching and thresholding (Sec. 6; Sec. 3.6 n-sigma detections):
+    at each start t of row d, the width with the largest S/N among those defined there
+    (t + w <= n; the smallest such width on ties); a detection when that S/N exceeds
+    k_sigma strictly. Ascending (d, t). Returns a dict of arrays: row, t, width, value
+    (the boxcar sum B_w) and snr."""
+    x = np.atleast_2d(np.asarray(series, dtype=np.float64))
+    n = x.shape[1]
+    snrs = boxcar_snr(x, mean, rms, max_log2)
+    best = np.full(x.shape, -np.inf)
+    bestj = np.zeros(x.shape, np.int64)
+    for j, s in enumerate(snrs):
+        better = s > best[:, : s.shape[1]]  # strictly larger: a wider width must beat a narrower one
+        best[:, : s.shape[1]] = np.where(better, s, best[:, : s.shape[1]])
+        bestj[:, : s.shape[1]] = np.where(better, j, bestj[:, : s.shape[1]])
+    d, t = np.nonzero(best > k_sigma)
+    width = (1 << bestj[d, t]).astype(np.int64)
+    value = np.array([x[di, ti:ti + wi].sum() for di, ti, wi in zip(d, t, width)], dtype=np.float64)
+    return {"row": d.astype(np.int64), "t": t.astype(np.int64), "width": width, "value": value,
+            "snr": best[d, t] if d.size else np.zeros(0)}
+
+
+def boxcar_margin(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, max_log2: int, k_sigma: float):
+    """How far the boxcar search's decisions are from flipping: the smallest, over every
+    (d, t), of |best S/N - k|, and, where a detection is made, the gap between the best and
+    the second-best width's S/N (the width a detection reports). A plain FP32 evaluation
+    agrees with this oracle wherever the margin exceeds its rounding."""
+    snrs = boxcar_snr(series, mean, rms, max_log2)
+    x = np.atleast_2d(np.asarray(series))
+    first = np.full(x.shape, -np.inf)
+    second = np.full(x.shape, -np.inf)
+    for s in snrs:
+        f, sc = first[:, : s.shape[1]], second[:, : s.shape[1]]
+        second[:, : s.shape[1]] = np.maximum(sc, np.minimum(f, s))
+        first[:, : s.shape[1]] = np.maximum(f, s)
+    ok = np.isfinite(first)
+    if not np.any(ok):
+        return float("inf")
+    m = float(np.min(np.abs(first[ok] - k_sigma)))
+    det = ok & (first > k_sigma) & np.isfinite(second)
+    if np.any(det):
+        m = min(m, float(np.min(first[det] - second[det])))
+    return m
 
 
 def candidates(series: np.ndarray, mean: np.ndarray, rms: np.ndarray, k_sigma: float,
