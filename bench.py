@@ -512,6 +512,37 @@ def main():
               "frac": round(bx_bytes / (ms_bx * 1e-3) / 1e9 / 8000.0, 4), "algorithmic_bytes": bx_bytes}
     del bx
 
+    # boxcar template matching at every start (widths 1..64) with 6.5-sigma detections and
+    # their widths: a counting and a writing pass, each reading the series once
+    print("bench: boxcar search timing", file=sys.stderr, flush=True)
+    # the series as dedispersed (the detrend above normalised `out` in place): fresh output
+    step(True)
+    nws = C.c_int64()
+    _lib.check(lib.dd_boxcar_search_workspace(beam.ndm, nout, C.byref(nws)))
+    sws = torch.empty(int(nws.value), dtype=torch.uint8, device=out.device)
+    pcap = 1 << 22
+    pulses = torch.empty(pcap * 24, dtype=torch.uint8, device=out.device)
+    npulse = torch.zeros(1, dtype=torch.int64, device=out.device)
+
+    def search():
+        _lib.check(lib.dd_boxcar_search(vp(out), beam.ndm, nout, nout, vp(mean), vp(rms), 6, 6.5, vp(pulses), pcap,
+                                        vp(npulse), vp(sws), sws.numel(), st))
+    search()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        search()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_bs = e0.elapsed_time(e1) / 3
+    bs_bytes = 2 * beam.ndm * nout * 4
+    boxcar_search = {"kernels": "boxcar_count + boxcar_scan + boxcar_write", "max_width": 64, "k_sigma": 6.5,
+                     "ms": round(ms_bs, 3), "bound": "hbm", "unit": "GB/s",
+                     "achieved": round(bs_bytes / (ms_bs * 1e-3) / 1e9, 1), "peak": 8000.0,
+                     "frac": round(bs_bytes / (ms_bs * 1e-3) / 1e9 / 8000.0, 4),
+                     "algorithmic_bytes": bs_bytes, "detections": int(npulse.item())}
+    del pulses, sws
+
     # time binning above the diagonal DM (factor 2^k for DM in (2^(k-1), 2^k] DM_diag, k <= 4):
     # the downfactored inputs and one plan per run of trials, stats and 6-sigma candidates
     print("bench: time-binning timing", file=sys.stderr, flush=True)
@@ -645,6 +676,7 @@ def main():
         "roofline": roof,
         "detrend": detrend,
         "boxcar": boxcar,
+        "boxcar_search": boxcar_search,
         "time_binning": time_binning,
         "rfi": rfi,
         "subband": subband,

@@ -344,6 +344,44 @@ int dd_detrend(float* d_series, int64_t nrows, int64_t n, int64_t row_stride, in
 int dd_boxcar(const float* d_series, int64_t nrows, int64_t n, int64_t row_stride, int32_t levels,
               float* d_out, int64_t out_row_stride, void* stream);
 
+/* One boxcar detection: row, start sample t, width (samples), boxcar sum, S/N. */
+typedef struct dd_pulse {
+  int32_t row;
+  int32_t width;
+  int64_t t;
+  float value;
+  float snr;
+} dd_pulse;
+
+/*
+ * Boxcar template matching with thresholding (Ch. 6 Sec. "Transient Surveys": boxcar
+ * templates of varying width convolved with each dedispersed series, then thresholded;
+ * Ch. 2 Eq. pulseSNREquation: a matched boxcar's S/N grows as sqrt(width)). For widths
+ * w = 2^j, j = 0 .. max_log2 (<= 6: 1..64 samples), at every start t of a row with
+ * t + w <= n:
+ *   B_w[t] = x[t] + ... + x[t + w - 1]            (FP32, pairwise: B_2w[t] = B_w[t] + B_w[t + w])
+ *   S/N_w[t] = (B_w[t] - w mean) / (rms sqrt(w))  (FP64)
+ * A detection at (row, t) when the largest S/N_w[t] over the widths defined there exceeds
+ * k_sigma (the smallest width on ties); it is written as {row, w, t, B_w[t], S/N} in
+ * ascending (row, t) order. Rows with rms <= 0 have no detections.
+ * d_series: [nrows][row_stride] FP32 on the device (any [rows][n] array, e.g. the output
+ * of dd_dedisperse); d_mean, d_rms: [nrows] FP32 (dd_dedisperse's statistics), or both
+ * NULL for normalised rows (mean 0, rms 1, e.g. after dd_detrend with normalise).
+ * d_pulse[cap] receives the detections; *d_npulse (device int64) their true count, which
+ * may exceed cap (dd_candidates_check reads it and reports DD_WARN_CAND_OVERFLOW).
+ * d_workspace: at least dd_boxcar_search_workspace bytes of device memory. Every buffer is
+ * caller-owned; enqueued on `stream`, returns without waiting. The series is read twice
+ * (a counting pass and a writing pass).
+ * Errors: DD_ERR_INVALID_ARG for NULL series, count or workspace, nrows or n < 1,
+ * row_stride < n, only one of d_mean/d_rms, max_log2 outside 0..6, non-finite k_sigma,
+ * cap < 0 or cap > 0 with NULL d_pulse; DD_ERR_WORKSPACE for a short workspace;
+ * DD_ERR_UNSUPPORTED for more than 65535 rows.
+ */
+int dd_boxcar_search_workspace(int64_t nrows, int64_t n, int64_t* ws_bytes);
+int dd_boxcar_search(const float* d_series, int64_t nrows, int64_t n, int64_t row_stride, const float* d_mean,
+                     const float* d_rms, int32_t max_log2, float k_sigma, dd_pulse* d_pulse, int64_t cap,
+                     int64_t* d_npulse, void* d_workspace, int64_t ws_bytes, void* stream);
+
 /*
  * Time binning above the diagonal DM (Ch. 2 Sec. "Direct Dedispersion": past the DM at
  * which the dispersion curve crosses one sample per channel, dedisperse at half the

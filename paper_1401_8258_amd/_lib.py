@@ -75,6 +75,8 @@ SIGNATURES = {
     "dd_batch_dedisperse": (C.c_int, [C.POINTER(BatchItem), _I32, _P, _I64, _P]),
     "dd_detrend": (C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P]),
     "dd_boxcar": (C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _I64, _P]),
+    "dd_boxcar_search_workspace": (C.c_int, [_I64, _I64, C.POINTER(_I64)]),
+    "dd_boxcar_search": (C.c_int, [_P, _I64, _I64, _I64, _P, _P, _I32, C.c_float, _P, _I64, _P, _P, _I64, _P]),
     "dd_downfactor": (C.c_int, [_P, _I32, _I64, _I64, _I64, _P, _I64, _P]),
     "dd_time_binning": (C.c_int, [_P, _I32, C.c_double, _P, _I32, _I32, _P, _P]),
     "dd_bandpass": (C.c_int, [_P, _I64, _I64, _I64, _I64, _P, _P, _P]),

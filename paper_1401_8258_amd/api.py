@@ -20,6 +20,7 @@ from ._lib import check
 
 CAND_DTYPE = np.dtype([("dm_index", "<i4"), ("reserved", "<i4"), ("t", "<i8"), ("value", "<f4"),
                        ("snr", "<f4")])
+PULSE_DTYPE = np.dtype([("row", "<i4"), ("width", "<i4"), ("t", "<i8"), ("value", "<f4"), ("snr", "<f4")])
 _TORCH_DT = {torch.float32: _lib.DD_F32, torch.float16: _lib.DD_F16, torch.uint8: _lib.DD_U8}
 _NAME_DT = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}
 # kernel forms (dd_tuning.kernel_form): "lds" stages four shifted copies per channel and reads
@@ -381,6 +382,40 @@ def detrend(series: torch.Tensor, normalise: bool = True, stream=None) -> torch.
     check(lib.dd_detrend(_vp(series), int(series.shape[0]), int(series.shape[1]), int(series.stride(0)),
                          1 if normalise else 0, _vp(rms), _stream(stream)))
     return rms
+
+
+def boxcar_search(series: torch.Tensor, mean: Optional[torch.Tensor] = None, rms: Optional[torch.Tensor] = None,
+                  max_log2: int = 6, k_sigma: float = 6.0, cap: int = 1 << 16, stream=None) -> np.ndarray:
+    """Boxcar template matching with thresholding (dd_boxcar_search): at every start of each
+    row, the boxcar of width 2^j (j <= max_log2) with the best S/N about the row's mean in
+    units of rms sqrt(width); detections above k_sigma as a structured array (PULSE_DTYPE:
+    row, width, t, value, snr) in (row, t) order. mean and rms default to 0 and 1
+    (normalised rows). Synchronises the stream; warns CandidateOverflow when more than cap
+    qualified (the first cap are returned)."""
+    if series.dim() != 2 or series.dtype != torch.float32 or not series.is_cuda or series.stride(1) != 1:
+        raise ValueError("series must be a [nrows][n] float32 device tensor, time contiguous")
+    if (mean is None) != (rms is None):
+        raise ValueError("give both mean and rms, or neither")
+    lib = _lib.load()
+    nrows, n = int(series.shape[0]), int(series.shape[1])
+    need = C.c_int64()
+    check(lib.dd_boxcar_search_workspace(nrows, n, C.byref(need)))
+    dev = series.device
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(max(int(cap), 1) * PULSE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    m = mean.to(torch.float32).contiguous() if mean is not None else None
+    r = rms.to(torch.float32).contiguous() if rms is not None else None
+    check(lib.dd_boxcar_search(_vp(series), nrows, n, int(series.stride(0)), _vp(m), _vp(r), int(max_log2),
+                               float(k_sigma), _vp(out), int(cap), _vp(cnt), _vp(ws), int(ws.numel()),
+                               _stream(stream)))
+    total = C.c_int64()
+    rc = check(lib.dd_candidates_check(_vp(cnt), int(cap), _stream(stream), C.byref(total)),
+               (_lib.DD_OK, _lib.DD_WARN_CAND_OVERFLOW))
+    if rc == _lib.DD_WARN_CAND_OVERFLOW:
+        warnings.warn(f"{total.value} boxcar detections qualified; the first {cap} were kept", CandidateOverflow)
+    keep = min(int(total.value), int(cap))
+    return out[: keep * PULSE_DTYPE.itemsize].cpu().numpy().view(PULSE_DTYPE)
 
 
 def boxcar_offsets(n: int, levels: int):

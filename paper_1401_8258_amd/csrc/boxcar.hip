@@ -1,7 +1,8 @@
 // Boxcar smoothing of (normalised) dedispersed series by successive addition of adjacent
 // samples: the single-pulse search's smoothing, which downfactors the series by the
 // boxcar width (Ch. 2 single-pulse detection; Ch. 6 template matching). C-ABI entry
-// point dd_boxcar.
+// point dd_boxcar. Then boxcar template matching at every start offset with
+// thresholding (dd_boxcar_search), below.
 //
 // Level k of a row holds s_k[j] = (x[j 2^k] + ... + x[j 2^k + 2^k - 1]) / sqrt(2^k) for
 // j < floor(n / 2^k); levels are stored one after another in the output row, level k at
@@ -17,6 +18,7 @@
 #include <string>
 
 #include "dd_internal.h"
+#include "dd_device.h"
 
 namespace {
 
@@ -71,7 +73,211 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_rows(const float* __restri
   }
 }
 
+// ------------------------------------------------------------------ boxcar search
+//
+// Template matching (Ch. 6 "Transient Surveys": boxcars of varying width convolved with each
+// dedispersed series, then thresholded): for w = 2^j, j <= max_log2 <= 6, B_w[t] = x[t] +
+// ... + x[t + w - 1] at every start t with t + w <= n, S/N_w[t] = (B_w[t] - w mean) /
+// (rms sqrt(w)); a detection at (row, t) when the best width's S/N exceeds k (the smallest
+// width on ties), reported with that width, B_w and S/N, rows in order and t ascending.
+//
+// One 256-thread workgroup per (row, segment of kSearchSeg starts): the segment and 64
+// samples past it are read once into LDS (zeros past n, which no defined boxcar reads).
+// Level j is formed from level j - 1 in the other LDS buffer by B_2w[t] = B_w[t] +
+// B_w[t + w] (a pairwise FP32 tree, the same order at every start); after each level every
+// thread updates the best S/N of its 16 starts (t = q 256 + thread, conflict-free LDS reads).
+// A counting pass, a scan of the counts and a writing pass that recomputes the segment
+// place the detections; each pass reads the series once (HBM-bound).
+constexpr int kSearchSeg = 4096;
+constexpr int kSearchPer = kSearchSeg / kBoxThreads;  // starts per thread
+constexpr int kSearchBuf = kSearchSeg + 64;
+
+struct SearchArgs {
+  const float* x;
+  int64_t n, stride;
+  const float* mean;  // null: 0 (normalised series)
+  const float* rms;   // null: 1
+  int max_log2;
+  double k;
+};
+
+// The best S/N over the widths (and its width index and boxcar sum) for this thread's
+// starts of segment seg of row d; false when the row has no variance.
+__device__ bool search_segment(const SearchArgs& A, int d, int64_t seg, float* buf0, float* buf1, double* best,
+                               int* bj, float* bval) {
+  const int tid = threadIdx.x;
+  const int64_t b = seg * kSearchSeg;
+  const float* row = A.x + (int64_t)d * A.stride;
+  const double m = A.mean ? (double)A.mean[d] : 0.0;
+  const double r = A.rms ? (double)A.rms[d] : 1.0;
+  if (!(r > 0.0)) return false;
+  for (int i = tid; i < kSearchBuf; i += kBoxThreads) buf0[i] = b + i < A.n ? row[b + i] : 0.0f;
+#pragma unroll
+  for (int q = 0; q < kSearchPer; ++q) {
+    best[q] = -INFINITY;
+    bj[q] = 0;
+    bval[q] = 0.0f;
+  }
+  __syncthreads();
+  float* src = buf0;
+  float* dst = buf1;
+  for (int j = 0; j <= A.max_log2; ++j) {
+    const int w = 1 << j;
+    if (j > 0) {
+      const int h = w >> 1;
+      for (int i = tid; i < kSearchBuf - w; i += kBoxThreads) dst[i] = src[i] + src[i + h];
+      __syncthreads();
+      float* t = src;
+      src = dst;
+      dst = t;
+    }
+    const double inv = 1.0 / (r * sqrt((double)w));
+    const double mw = (double)w * m;
+#pragma unroll
+    for (int q = 0; q < kSearchPer; ++q) {
+      const int tl = q * kBoxThreads + tid;
+      const int64_t t = b + tl;
+      if (t + w <= A.n) {
+        const float v = src[tl];
+        const double snr = ((double)v - mw) * inv;
+        if (snr > best[q]) {
+          best[q] = snr;
+          bj[q] = j;
+          bval[q] = v;
+        }
+      }
+    }
+    // the next level overwrites the other buffer only after every thread read this one
+    __syncthreads();
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kBoxThreads) void boxcar_count(SearchArgs A, int64_t nseg, int32_t* __restrict__ cnt) {
+  __shared__ float buf0[kSearchBuf], buf1[kSearchBuf];
+  __shared__ int total;
+  const int d = blockIdx.y;
+  const int64_t seg = blockIdx.x;
+  double best[kSearchPer];
+  int bj[kSearchPer];
+  float bval[kSearchPer];
+  if (threadIdx.x == 0) total = 0;
+  __syncthreads();
+  if (search_segment(A, d, seg, buf0, buf1, best, bj, bval)) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kSearchPer; ++q) c += best[q] > A.k ? 1 : 0;
+    atomicAdd(&total, c);  // integer sum: order-free
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[(int64_t)d * nseg + seg] = total;
+}
+
+__global__ __launch_bounds__(1024) void boxcar_scan(const int32_t* __restrict__ cnt, int64_t n,
+                                                    int64_t* __restrict__ offs, int64_t* __restrict__ total) {
+  __shared__ int64_t part[1024];
+  dd::scan_counts(cnt, n, offs, total, part);
+}
+
+__global__ __launch_bounds__(kBoxThreads) void boxcar_write(SearchArgs A, int64_t nseg, const int32_t* __restrict__ cnt,
+                                                            const int64_t* __restrict__ offs, dd_pulse* __restrict__ out,
+                                                            int64_t cap) {
+  __shared__ float buf0[kSearchBuf], buf1[kSearchBuf];
+  __shared__ int wtot[kBoxThreads / 64];
+  const int d = blockIdx.y;
+  const int64_t seg = blockIdx.x;
+  const int64_t idx = (int64_t)d * nseg + seg;
+  if (cnt[idx] == 0) return;  // the whole workgroup leaves together
+  double best[kSearchPer];
+  int bj[kSearchPer];
+  float bval[kSearchPer];
+  search_segment(A, d, seg, buf0, buf1, best, bj, bval);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t off = offs[idx];
+#pragma unroll
+  for (int q = 0; q < kSearchPer; ++q) {
+    // starts q 256 .. q 256 + 255 of the segment: ballot orders them by thread (= by t)
+    const bool hit = best[q] > A.k;
+    const uint64_t mask = __ballot(hit);
+    const int below = __popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) wtot[w] = __popcll(mask);
+    __syncthreads();
+    int before = 0;
+    for (int i = 0; i < w; ++i) before += wtot[i];
+    const int tot = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    if (hit) {
+      const int64_t pos = off + before + below;
+      if (pos < cap) {
+        dd_pulse o;
+        o.row = d;
+        o.width = 1 << bj[q];
+        o.t = seg * kSearchSeg + q * kBoxThreads + threadIdx.x;
+        o.value = bval[q];
+        o.snr = (float)best[q];
+        out[pos] = o;
+      }
+    }
+    off += tot;
+  }
+}
+
+struct SearchLayout {
+  int64_t nseg, cnt_off, offs_off, total;
+};
+
+SearchLayout search_layout(int64_t nrows, int64_t n) {
+  SearchLayout l{};
+  l.nseg = (n + kSearchSeg - 1) / kSearchSeg;
+  l.cnt_off = 0;
+  l.offs_off = dd::align_up(nrows * l.nseg * 4);
+  l.total = l.offs_off + dd::align_up(nrows * l.nseg * 8);
+  return l;
+}
+
 }  // namespace
+
+extern "C" int dd_boxcar_search_workspace(int64_t nrows, int64_t n, int64_t* ws_bytes) {
+  dd::clear_error();
+  if (!ws_bytes) return dd::fail(DD_ERR_INVALID_ARG, "ws_bytes is NULL");
+  *ws_bytes = 0;
+  if (nrows < 1 || n < 1) return dd::fail(DD_ERR_INVALID_ARG, "need nrows >= 1 and n >= 1");
+  *ws_bytes = search_layout(nrows, n).total;
+  return DD_OK;
+}
+
+extern "C" int dd_boxcar_search(const float* d_series, int64_t nrows, int64_t n, int64_t row_stride,
+                                const float* d_mean, const float* d_rms, int32_t max_log2, float k_sigma,
+                                dd_pulse* d_pulse, int64_t cap, int64_t* d_npulse, void* d_workspace,
+                                int64_t ws_bytes, void* stream) {
+  dd::clear_error();
+  if (!d_series || !d_npulse || !d_workspace)
+    return dd::fail(DD_ERR_INVALID_ARG, "series, count and workspace must be non-NULL");
+  if (nrows < 1 || n < 1 || row_stride < n)
+    return dd::fail(DD_ERR_INVALID_ARG, "need nrows >= 1, n >= 1 and row_stride >= n");
+  if ((d_mean == nullptr) != (d_rms == nullptr))
+    return dd::fail(DD_ERR_INVALID_ARG, "d_mean and d_rms must both be given or both be NULL");
+  if (max_log2 < 0 || max_log2 > kMaxLevel)
+    return dd::fail(DD_ERR_INVALID_ARG, "max_log2 must be in 0..6 (boxcars of 1..64 samples)");
+  if (!std::isfinite(k_sigma)) return dd::fail(DD_ERR_INVALID_ARG, "k_sigma must be finite");
+  if (cap < 0 || (cap > 0 && !d_pulse)) return dd::fail(DD_ERR_INVALID_ARG, "bad detection buffer");
+  if (nrows > 65535) return dd::fail(DD_ERR_UNSUPPORTED, "at most 65535 rows per call");
+  const SearchLayout l = search_layout(nrows, n);
+  if (ws_bytes < l.total) return dd::fail(DD_ERR_WORKSPACE, "workspace smaller than dd_boxcar_search_workspace");
+  if (l.nseg > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(d_workspace);
+  int32_t* cnt = reinterpret_cast<int32_t*>(ws + l.cnt_off);
+  int64_t* offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
+  const SearchArgs A{d_series, n, row_stride, d_mean, d_rms, (int)max_log2, (double)k_sigma};
+  const dim3 grid((unsigned)l.nseg, (unsigned)nrows);
+  hipLaunchKernelGGL(boxcar_count, grid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt);
+  hipLaunchKernelGGL(boxcar_scan, dim3(1), dim3(1024), 0, st, cnt, nrows * l.nseg, offs, d_npulse);
+  hipLaunchKernelGGL(boxcar_write, grid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt, offs, d_pulse, cap);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return dd::fail(DD_ERR_HIP, std::string("boxcar search launch: ") + hipGetErrorString(e));
+  return DD_OK;
+}
 
 extern "C" int dd_boxcar(const float* d_series, int64_t nrows, int64_t n, int64_t row_stride, int32_t levels,
                          float* d_out, int64_t out_row_stride, void* stream) {

@@ -20,6 +20,31 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
   return v;
 }
 
+// Exclusive scan of n counts by one 1024-thread block (part: 1024 int64 of LDS); the total
+// to *total. Serves every candidate compaction (threshold and boxcar detections).
+__device__ __forceinline__ void scan_counts(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ offs,
+                                            int64_t* __restrict__ total, int64_t* part) {
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t b = min(n, tid * chunk), e = min(n, b + chunk);
+  int64_t local = 0;
+  for (int64_t i = b; i < e; ++i) local += cnt[i];
+  part[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = part[tid] - local;
+  for (int64_t i = b; i < e; ++i) {
+    offs[i] = run;
+    run += cnt[i];
+  }
+  if (tid == 1023) *total = part[1023];
+}
+
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
 __device__ __forceinline__ void block_barrier() {

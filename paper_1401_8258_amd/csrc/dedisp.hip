@@ -836,30 +836,6 @@ __device__ __forceinline__ void count_segment(const float* __restrict__ out, int
   if (threadIdx.x == 0) cnt[(int64_t)d * nseg + seg] = (int32_t)tot;
 }
 
-// Exclusive scan of n counts by one 1024-thread block; total to *ncand.
-__device__ __forceinline__ void scan_counts(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ offs,
-                                            int64_t* __restrict__ ncand, int64_t* part) {
-  const int tid = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t b = min(n, tid * chunk), e = min(n, b + chunk);
-  int64_t local = 0;
-  for (int64_t i = b; i < e; ++i) local += cnt[i];
-  part[tid] = local;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int64_t v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int64_t run = part[tid] - local;
-  for (int64_t i = b; i < e; ++i) {
-    offs[i] = run;
-    run += cnt[i];
-  }
-  if (tid == 1023) *ncand = part[1023];
-}
-
 // The detections of one segment of series d, in time order, at their scanned offsets.
 __device__ __forceinline__ void write_segment(const float* __restrict__ out, int64_t stride, int64_t nout,
                                               int64_t nseg, const double* __restrict__ stat,
@@ -920,7 +896,7 @@ __global__ __launch_bounds__(256) void cand_count(const float* __restrict__ out,
 __global__ __launch_bounds__(1024) void cand_scan(const int32_t* __restrict__ cnt, int64_t n,
                                                   int64_t* __restrict__ offs, int64_t* __restrict__ ncand) {
   __shared__ int64_t part[1024];
-  scan_counts(cnt, n, offs, ncand, part);
+  dd::scan_counts(cnt, n, offs, ncand, part);
 }
 
 __global__ __launch_bounds__(256) void cand_write(const float* __restrict__ out, int64_t stride, int64_t nout,
@@ -979,7 +955,7 @@ __global__ __launch_bounds__(256) void cand_count_batch(const TailItem* __restri
 __global__ __launch_bounds__(1024) void cand_scan_batch(const TailItem* __restrict__ items) {
   __shared__ int64_t part[1024];
   const TailItem& it = items[blockIdx.x];
-  scan_counts(it.cnt, (int64_t)it.ndm * it.nseg, it.offs, it.ncand, part);
+  dd::scan_counts(it.cnt, (int64_t)it.ndm * it.nseg, it.offs, it.ncand, part);
 }
 
 __global__ __launch_bounds__(256) void cand_write_batch(const TailItem* __restrict__ items, int n) {

@@ -330,6 +330,33 @@ def test_rfi_arguments(lib):
     assert lib.dd_rfi_clip(p, 70000, 8, 8, p, 1.0, 4, p, p, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_UNSUPPORTED
 
 
+def test_boxcar_search_arguments(lib):
+    """Workspace sizes and every refused argument of dd_boxcar_search (checked before any launch)."""
+    ws = C.c_int64()
+    assert lib.dd_boxcar_search_workspace(3, 10000, C.byref(ws)) == 0
+    # counts int32 and offsets int64 per (row, 4096-start segment), each region 256-aligned
+    assert ws.value == 256 + 256
+    assert lib.dd_boxcar_search_workspace(2048, 1 << 20, C.byref(ws)) == 0 and ws.value == 2048 * 256 * 12
+    assert lib.dd_boxcar_search_workspace(0, 10, C.byref(ws)) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_boxcar_search_workspace(1, 10, None) == lib_mod.DD_ERR_INVALID_ARG
+    p = C.c_void_p(256)
+    ok = dict(series=p, nrows=4, n=100, stride=100, mean=p, rms=p, ml=6, k=5.0, out=p, cap=8, cnt=p, ws=p,
+              wsb=1 << 20)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.dd_boxcar_search(a["series"], a["nrows"], a["n"], a["stride"], a["mean"], a["rms"], a["ml"],
+                                    a["k"], a["out"], a["cap"], a["cnt"], a["ws"], a["wsb"], None)
+
+    bad = lib_mod.DD_ERR_INVALID_ARG
+    for kw in [dict(series=None), dict(cnt=None), dict(ws=None), dict(nrows=0), dict(n=0), dict(stride=99),
+               dict(mean=None), dict(rms=None), dict(ml=7), dict(ml=-1), dict(k=float("nan")), dict(k=float("inf")),
+               dict(cap=-1), dict(out=None)]:
+        assert call(**kw) == bad, kw
+    assert call(wsb=100) == lib_mod.DD_ERR_WORKSPACE
+    assert call(nrows=70000) == lib_mod.DD_ERR_UNSUPPORTED
+
+
 def _info(lib, h, nsamp=1 << 20):
     info = lib_mod.PlanInfo()
     assert lib.dd_plan_query(h, nsamp, C.byref(info)) in (0, -2)
