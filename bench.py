@@ -356,7 +356,7 @@ def subband_run(dd, beam, steps, warmup):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         res["passes"].append({"dms_per_group": group, "ms": round(ms, 3), "steps": steps,
-                              "launches": len(sp.step1) + len(sp.step2)})
+                              "launches": sp.launches})
         print(f"bench: subband groups of {group}: {ms:.3f} ms", file=sys.stderr, flush=True)
         del sp
     return res
@@ -547,8 +547,7 @@ def main():
     # the downfactored inputs and one plan per run of trials, stats and 6-sigma candidates
     print("bench: time-binning timing", file=sys.stderr, flush=True)
     bp = dd.BinnedPlan(beam.freq_mhz, beam.tsamp_s, beam.dm, max_log2=4)
-    for sg in bp.segments:
-        sg.plan.workspace(nsamp >> sg.log2)
+    bp.workspace(nsamp)
     bp.dedisperse(x, k_sigma=k, cand_cap=cap)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -651,11 +650,11 @@ def main():
     torch.cuda.synchronize()
     ms_sb48 = e0.elapsed_time(e1) / 3
     groups48 = {"dms_per_group": 48, "ms": round(ms_sb48, 3), "adds_vs_plain": round(sp48.adds(nsamp) / adds, 4),
-                "speedup_vs_plain_step": round(ms_step / ms_sb48, 3), "launches": len(sp48.step1) + len(sp48.step2)}
+                "speedup_vs_plain_step": round(ms_step / ms_sb48, 3), "launches": sp48.launches}
     del sp48
     subband = {"chans_per_sub": 32, "dms_per_group": 16, "ms": round(ms_sb, 3), "adds": sp.adds(nsamp),
                "adds_vs_plain": round(sp.adds(nsamp) / adds, 4), "speedup_vs_plain_step": round(ms_step / ms_sb, 3),
-               "launches": len(sp.step1) + len(sp.step2),
+               "launches": sp.launches,
                "ms_batched": round(ms_sb_b, 3), "speedup_batched_vs_plain_step": round(ms_step / ms_sb_b, 3),
                "groups_of_48": groups48}
     del sp

@@ -418,6 +418,77 @@ int dd_downfactor(const void* d_in, int32_t in_dtype, int64_t nchan, int64_t nsa
                   float* d_out, int64_t out_row_stride, void* stream);
 
 /*
+ * Time-binned plan: brute-force dedispersion with time binning above the diagonal DM (Ch. 2
+ * Sec. "Direct Dedispersion"; Sec. "Computing Larger DMs"). The trials are split into runs
+ * by dd_time_binning; run k (trials whose factor is 2^k) is an ordinary plan at sampling
+ * time 2^k tsamp_s over the input downfactored k times (dd_downfactor: FP32 sums; the
+ * factor-1 run reads the input in in_dtype). A tuning applies to every run, except that the
+ * 8-bit direct-read form (DD_FORM_DIRECT) applies to the factor-1 run only. Host object,
+ * immutable after creation; the caller keeps its arrays. Errors as dd_time_binning and
+ * dd_plan_create.
+ */
+typedef struct dd_binned dd_binned;
+typedef struct dd_binned_run {
+  int32_t log2;        /* the run's factor is 2^log2 */
+  int32_t d0, d1;      /* trials [d0, d1) */
+  int32_t maxdelay;    /* in samples of the run (2^log2 tsamp_s) */
+  int64_t nout;        /* (nsamp >> log2) - maxdelay for the queried nsamp */
+  int32_t kernel_form, dms_per_wave, waves;
+} dd_binned_run;
+int dd_binned_create(dd_binned** out, const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm,
+                     int32_t ndm, int32_t in_dtype, int32_t max_log2, const dd_tuning* tuning);
+/* The runs (*nruns; up to runs_cap of them into runs[] when runs is non-NULL), the
+   workspace an nsamp-sample call needs and the diagonal DM. DD_ERR_TOO_SHORT when some run
+   would have no output (then *workspace_bytes is 0; the runs are still reported). */
+int dd_binned_query(const dd_binned* b, int64_t nsamp, int32_t* nruns, dd_binned_run* runs, int32_t runs_cap,
+                    int64_t* workspace_bytes, double* dm_diag);
+/* Copies every run's delay table into a workspace for nsamp-sample calls. */
+int dd_binned_upload(const dd_binned* b, int64_t nsamp, void* d_workspace, int64_t ws_bytes, void* stream);
+/* One call over all runs. d_out: [ndm][out_row_stride] FP32; row d holds the nout of its
+   run (samples at that run's sampling time), out_row_stride >= the largest run nout.
+   d_mean/d_rms [ndm] as dd_dedisperse. Candidates of all runs form one list in ascending
+   (trial, time) order: dm_index is the global trial, t the input sample where the binned
+   sample starts (binned index << log2); *d_ncand the true count (as dd_dedisperse).
+   batched != 0 runs the runs' dedispersion through one dd_batch_dedisperse call (then
+   LDS-form runs must share the wavefront and producer counts, else DD_ERR_UNSUPPORTED);
+   the results are the same bit for bit. The workspace comes from dd_binned_upload for this
+   nsamp. Errors as dd_dedisperse. */
+int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
+                         int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,
+                         int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace, int64_t ws_bytes,
+                         void* stream);
+void dd_binned_destroy(dd_binned* b);
+
+/*
+ * Subband plan: subband dedispersion (Ch. 2 Sec. "Subband Dedispersion"), an approximation of
+ * Eq. bruteEquation. Trials are grouped in runs of dms_per_group; each group's nominal DM
+ * is its middle trial. Step 1: each subband of chans_per_sub consecutive channels is
+ * dedispersed at the nominal DMs (delays relative to the subband's highest frequency) into
+ * a reduced filterbank [nsub][ngroups][width] in the workspace. Step 2: each group's trials
+ * dedisperse its [nsub] rows of the reduced filterbank, the subbands standing at their
+ * highest frequencies, over len1 = nsamp - (largest step-1 delay) samples (groups of up to 48
+ * trials share a workgroup). FP32 input. Errors as dd_plan_create, and DD_ERR_INVALID_ARG
+ * for chans_per_sub or dms_per_group < 1.
+ */
+typedef struct dd_subband dd_subband;
+int dd_subband_create(dd_subband** out, const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm,
+                      int32_t ndm, int32_t chans_per_sub, int32_t dms_per_group);
+/* Workspace bytes for nsamp-sample calls, each trial's nout (nout_per_dm[ndm], optional,
+   host), the channel-sample adds of both steps and the subband and group counts.
+   DD_ERR_TOO_SHORT when a group would have no output. */
+int dd_subband_query(const dd_subband* sp, int64_t nsamp, int64_t* workspace_bytes, int64_t* nout_per_dm,
+                     int64_t* adds, int32_t* nsub, int32_t* ngroups);
+int dd_subband_upload(const dd_subband* sp, int64_t nsamp, void* d_workspace, int64_t ws_bytes, void* stream);
+/* One call over both steps; outputs and candidates as dd_binned_dedisperse (row d holds
+   its group's nout; times in input samples). batched != 0 runs each step through one
+   dd_batch_dedisperse call (same results bit for bit). */
+int dd_subband_dedisperse(const dd_subband* sp, const float* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
+                          int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,
+                          int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace, int64_t ws_bytes,
+                          void* stream);
+void dd_subband_destroy(dd_subband* sp);
+
+/*
  * RFI mitigation before dedispersion (Ch. 3 Sec. "Bandpass Correction", "Channel
  * Thresholding", "Spectrum Thresholding"), for FP32 filterbanks. A caller runs
  * dd_bandpass, copies the nchan averages to the host, fits them with dd_bandpass_fit,

@@ -26,6 +26,11 @@ class Tuning(C.Structure):
                 ("producer_waves", C.c_int32), ("kernel_form", C.c_int32)]
 
 
+class BinnedRun(C.Structure):
+    _fields_ = [("log2", C.c_int32), ("d0", C.c_int32), ("d1", C.c_int32), ("maxdelay", C.c_int32),
+                ("nout", C.c_int64), ("kernel_form", C.c_int32), ("dms_per_wave", C.c_int32), ("waves", C.c_int32)]
+
+
 class PlanInfo(C.Structure):
     _fields_ = [("nchan", C.c_int32), ("ndm", C.c_int32), ("in_dtype", C.c_int32),
                 ("maxdelay", C.c_int32), ("nsamp", C.c_int64), ("nout", C.c_int64),
@@ -76,6 +81,21 @@ SIGNATURES = {
     "dd_detrend": (C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P]),
     "dd_boxcar": (C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _I64, _P]),
     "dd_boxcar_search_workspace": (C.c_int, [_I64, _I64, C.POINTER(_I64)]),
+    "dd_binned_create": (C.c_int, [C.POINTER(_P), C.POINTER(_F64), _I32, _F64, C.POINTER(_F64), _I32, _I32, _I32,
+                                   C.POINTER(Tuning)]),
+    "dd_binned_query": (C.c_int, [_P, _I64, C.POINTER(_I32), C.POINTER(BinnedRun), _I32, C.POINTER(_I64),
+                                  C.POINTER(_F64)]),
+    "dd_binned_upload": (C.c_int, [_P, _I64, _P, _I64, _P]),
+    "dd_binned_dedisperse": (C.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, _P, C.c_float, _P, _I64, _P, _I32, _P, _I64,
+                                       _P]),
+    "dd_binned_destroy": (None, [_P]),
+    "dd_subband_create": (C.c_int, [C.POINTER(_P), C.POINTER(_F64), _I32, _F64, C.POINTER(_F64), _I32, _I32, _I32]),
+    "dd_subband_query": (C.c_int, [_P, _I64, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32),
+                                   C.POINTER(_I32)]),
+    "dd_subband_upload": (C.c_int, [_P, _I64, _P, _I64, _P]),
+    "dd_subband_dedisperse": (C.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, _P, C.c_float, _P, _I64, _P, _I32, _P,
+                                        _I64, _P]),
+    "dd_subband_destroy": (None, [_P]),
     "dd_boxcar_search": (C.c_int, [_P, _I64, _I64, _I64, _P, _P, _I32, C.c_float, _P, _I64, _P, _P, _I64, _P]),
     "dd_downfactor": (C.c_int, [_P, _I32, _I64, _I64, _I64, _P, _I64, _P]),
     "dd_time_binning": (C.c_int, [_P, _I32, C.c_double, _P, _I32, _I32, _P, _P]),

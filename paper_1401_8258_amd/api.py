@@ -31,6 +31,23 @@ _FORMS = {"auto": _lib.DD_FORM_AUTO, "lds": _lib.DD_FORM_LDS, "regwin": _lib.DD_
 _FORM_NAMES = {v: k for k, v in _FORMS.items()}
 
 
+def _tuning(tuning, form: str):
+    """The dd_tuning a (tuning tuple, form name) pair describes, by reference, or None."""
+    kf = _FORMS[form]
+    if tuning is not None and kf == _lib.DD_FORM_DIRECT:  # (dms_per_wave, waves[, samples_per_lane])
+        g, w = int(tuning[0]), int(tuning[1])
+        spl = int(tuning[2]) if len(tuning) > 2 else 0
+        return C.byref(_lib.Tuning(g, w, spl, 0, 0, kf))
+    if tuning is not None:  # (dms_per_wave, waves[, chan_stage[, producer_waves]])
+        g, w = int(tuning[0]), int(tuning[1])
+        cc = int(tuning[2]) if len(tuning) > 2 else 0
+        pw = int(tuning[3]) if len(tuning) > 3 else 0
+        return C.byref(_lib.Tuning(g, w, 0, cc, pw, kf))
+    if kf != _lib.DD_FORM_AUTO:
+        return C.byref(_lib.Tuning(0, 0, 0, 0, 0, kf))
+    return None
+
+
 def _vp(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -96,19 +113,7 @@ class Plan:
         if self.dtype not in _TORCH_DT:
             raise ValueError(f"unsupported input dtype {dtype}")
         h = C.c_void_p()
-        tun = None
-        kf = _FORMS[form]
-        if tuning is not None and kf == _lib.DD_FORM_DIRECT:  # (dms_per_wave, waves[, samples_per_lane])
-            g, w = int(tuning[0]), int(tuning[1])
-            spl = int(tuning[2]) if len(tuning) > 2 else 0
-            tun = C.byref(_lib.Tuning(g, w, spl, 0, 0, kf))
-        elif tuning is not None:  # (dms_per_wave, waves[, chan_stage[, producer_waves]])
-            g, w = int(tuning[0]), int(tuning[1])
-            cc = int(tuning[2]) if len(tuning) > 2 else 0
-            pw = int(tuning[3]) if len(tuning) > 3 else 0
-            tun = C.byref(_lib.Tuning(g, w, 0, cc, pw, kf))
-        elif kf != _lib.DD_FORM_AUTO:
-            tun = C.byref(_lib.Tuning(0, 0, 0, 0, 0, kf))
+        tun = _tuning(tuning, form)
         dbl = C.POINTER(C.c_double)
         check(lib.dd_plan_create(C.byref(h), self.freq.ctypes.data_as(dbl), int(self.freq.size), self.tsamp,
                                  self.dm.ctypes.data_as(dbl), int(self.dm.size), _TORCH_DT[self.dtype], tun))
@@ -470,50 +475,96 @@ class BinnedSegment:
     log2: int          # this run is dedispersed at 2^log2 times the sampling time
     d0: int            # first DM trial of the run
     d1: int            # one past its last trial
-    plan: Plan         # plan over dm[d0:d1] at sampling time 2^log2 * tsamp
+    plan: "Plan"       # host-side plan of the run (delay table, maximum delay), for inspection
+
+
+class _PartResult(Result):
+    """Rows [d0, d1) of a composite call: views of its output and statistics; candidates are
+    the composite's merged list restricted to these trials, with dm_index local and t in
+    this part's own samples (t >> log2)."""
+
+    def __init__(self, parent, out, mean, rms, d0: int, d1: int, log2: int = 0):
+        super().__init__(out, mean, rms, 0, None, parent._ncand, parent.cand_cap)
+        self._parent, self._d0, self._d1, self._log2 = parent, d0, d1, log2
+
+    def candidates(self, stream=None) -> Optional[np.ndarray]:
+        c = self._parent.candidates(stream)
+        if c is None:
+            return None
+        c = c[(c["dm_index"] >= self._d0) & (c["dm_index"] < self._d1)].copy()
+        c["dm_index"] -= self._d0
+        c["t"] >>= self._log2
+        return c
+
+    def ncand(self, stream=None) -> Optional[int]:
+        c = self.candidates(stream)
+        return None if c is None else int(c.size)
 
 
 @dataclasses.dataclass
 class BinnedResult:
     segments: list     # [(BinnedSegment, Result)]: rows d0..d1-1 at nsamp >> log2 resolution
+    merged: Result     # the whole [ndm][nout_max] output and the merged candidate list
 
     def candidates(self) -> Optional[np.ndarray]:
-        """All runs' detections, dm_index global and t in input samples (binned index << log2)."""
-        parts = []
-        for seg, r in self.segments:
-            c = r.candidates()
-            if c is None:
-                return None
-            c = c.copy()
-            c["dm_index"] += seg.d0
-            c["t"] <<= seg.log2
-            parts.append(c)
-        return np.concatenate(parts) if parts else np.empty(0, dtype=CAND_DTYPE)
+        """All runs' detections in one list from the library: dm_index global and t in input
+        samples (binned index << log2)."""
+        return self.merged.candidates()
 
 
-class BinnedPlan:
+class _Composite:
+    """Marshalling shared by the time-binned and subband plans (C objects with a per-nsamp
+    workspace and one call over all their parts)."""
+
+    def _workspace(self, nsamp: int, device, stream, query_bytes, upload):
+        device = torch.device(device if device is not None else "cuda")
+        nbytes = int(query_bytes(nsamp))
+        key = (device.index if device.index is not None else torch.cuda.current_device(), nsamp)
+        ws = self._ws.get(key)
+        if ws is None:
+            ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+            check(upload(self._h, int(nsamp), _vp(ws), nbytes, _stream(stream)))
+            self._ws[key] = ws
+        return ws
+
+
+class BinnedPlan(_Composite):
     """Brute-force dedispersion with time binning above the diagonal DM (Ch. 2 Sec. "Direct
-    Dedispersion"; Sec. "Computing Larger DMs"): DM trials in (2^(k-1), 2^k] x DM_diag are
-    dedispersed on the input downfactored k times (k <= max_log2), with delays at sampling
-    time 2^k tsamp. Each run of trials is an ordinary plan; runs with k >= 1 take FP32
-    input (the downfactored sums)."""
+    Dedispersion"; Sec. "Computing Larger DMs"), a dd_binned object: DM trials in
+    (2^(k-1), 2^k] x DM_diag are dedispersed on the input downfactored k times (k <=
+    max_log2), with delays at sampling time 2^k tsamp, all in one library call."""
 
-    def __init__(self, freq_mhz, tsamp_s: float, dm, dtype=torch.float32, max_log2: int = 4, tuning=None):
+    def __init__(self, freq_mhz, tsamp_s: float, dm, dtype=torch.float32, max_log2: int = 4, tuning=None,
+                 form: str = "auto"):
+        lib = _lib.load()
+        self._lib = lib
         self.freq = np.ascontiguousarray(freq_mhz, dtype=np.float64)
         self.dm = np.ascontiguousarray(dm, dtype=np.float64)
         self.tsamp = float(tsamp_s)
         self.dtype = torch_dtype(dtype)
         self.max_log2 = int(max_log2)
-        self.dm_diag, self.log2 = time_binning(self.freq, self.tsamp, self.dm, self.max_log2)
+        dbl = C.POINTER(C.c_double)
+        h = C.c_void_p()
+        check(lib.dd_binned_create(C.byref(h), self.freq.ctypes.data_as(dbl), int(self.freq.size), self.tsamp,
+                                   self.dm.ctypes.data_as(dbl), int(self.dm.size), _TORCH_DT[self.dtype],
+                                   self.max_log2, _tuning(tuning, form)))
+        self._h = h
+        self._ws = {}
+        n = C.c_int32()
+        diag = C.c_double()
+        check(lib.dd_binned_query(h, 0, C.byref(n), None, 0, None, C.byref(diag)), (_lib.DD_ERR_INVALID_ARG,))
+        runs = (_lib.BinnedRun * n.value)()
+        check(lib.dd_binned_query(h, 0, None, runs, n.value, None, None), (_lib.DD_ERR_INVALID_ARG,))
+        self.dm_diag = float(diag.value)
+        self.log2 = np.zeros(self.dm.size, dtype=np.int32)
         self.segments = []
-        d0 = 0
-        for d in range(1, self.dm.size + 1):
-            if d == self.dm.size or self.log2[d] != self.log2[d0]:
-                k = int(self.log2[d0])
-                plan = Plan(self.freq, self.tsamp * float(1 << k), self.dm[d0:d], self.dtype if k == 0 else torch.float32,
-                            tuning)
-                self.segments.append(BinnedSegment(k, d0, d, plan))
-                d0 = d
+        for r in runs:
+            k, d0, d1 = int(r.log2), int(r.d0), int(r.d1)
+            self.log2[d0:d1] = k
+            # the run's plan on the host, for its delay table and maximum delay
+            host = Plan(self.freq, self.tsamp * float(1 << k), self.dm[d0:d1], self.dtype if k == 0 else torch.float32,
+                        tuning if (k == 0 or form != "direct") else None, form if (k == 0 or form != "direct") else "auto")
+            self.segments.append(BinnedSegment(k, d0, d1, host))
 
     def nout(self, nsamp: int):
         """Output samples per run for an nsamp-sample input: (nsamp >> k) - maxdelay_k."""
@@ -522,28 +573,48 @@ class BinnedPlan:
     def adds(self, nsamp: int) -> int:
         return sum((s.d1 - s.d0) * s.plan.nchan * n for s, n in zip(self.segments, self.nout(nsamp)))
 
+    def workspace(self, nsamp: int, device=None, stream=None) -> torch.Tensor:
+        """A device workspace for nsamp-sample inputs with every run's delay table (cached)."""
+        def query(ns):
+            b = C.c_int64()
+            check(self._lib.dd_binned_query(self._h, int(ns), None, None, 0, C.byref(b), None))
+            return b.value
+        return self._workspace(nsamp, device, stream, query, self._lib.dd_binned_upload)
+
     def dedisperse(self, x: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True,
                    stream=None, batched: bool = False) -> BinnedResult:
-        """Every run of trials on its downfactored input. With batched, the runs that share
-        the FP32 input type go through one persistent launch (dd_batch_dedisperse), equal
-        bit for bit to one launch per run."""
-        levels = [x]
-        for _ in range(max(s.log2 for s in self.segments)):
-            levels.append(downfactor(levels[-1], stream))
-        res = [None] * len(self.segments)
-        group = [i for i, s in enumerate(self.segments) if batched and s.plan.dtype == torch.float32]
-        if len(group) > 1:
-            done = batch_dedisperse([(self.segments[i].plan, levels[self.segments[i].log2]) for i in group],
-                                    k_sigma=k_sigma, cand_cap=cand_cap, stats=stats, stream=stream)
-            for i, r in zip(group, done):
-                res[i] = r
-        for i, seg in enumerate(self.segments):
-            if res[i] is None:
-                res[i] = seg.plan.dedisperse(levels[seg.log2], k_sigma=k_sigma, cand_cap=cand_cap, stats=stats,
-                                             stream=stream)
-        for r in res:
-            r._keep = (r._keep, levels)  # the downfactored inputs live until the results are dropped
-        return BinnedResult(list(zip(self.segments, res)))
+        """Every run of trials on its downfactored input (dd_binned_dedisperse). With batched,
+        the runs go through one dd_batch_dedisperse call, equal bit for bit."""
+        if x.dim() != 2 or x.shape[0] != self.freq.size or x.dtype != self.dtype or x.stride(1) != 1:
+            raise ValueError(f"x must be a [nchan={self.freq.size}][nsamp] {self.dtype} tensor, time contiguous")
+        nsamp = int(x.shape[1])
+        nouts = self.nout(nsamp)
+        ncols = max(nouts)
+        out, mean, rms, cand, ncand = _outputs(self.dm.size, ncols, x.device, k_sigma, cand_cap, stats)
+        ws = self.workspace(nsamp, x.device, stream)
+        check(self._lib.dd_binned_dedisperse(self._h, _vp(x), nsamp, int(x.stride(0)), _vp(out), int(out.stride(0)),
+                                             _vp(mean), _vp(rms), float(k_sigma), _vp(cand),
+                                             int(cand_cap if cand is not None else 0), _vp(ncand), 1 if batched else 0,
+                                             _vp(ws), int(ws.numel()), _stream(stream)))
+        merged = Result(out, mean, rms, 0, cand, ncand, cand_cap)
+        merged._keep = ws
+        parts = []
+        for seg, n in zip(self.segments, nouts):
+            r = _PartResult(merged, out[seg.d0:seg.d1, :n], mean[seg.d0:seg.d1] if mean is not None else None,
+                            rms[seg.d0:seg.d1] if rms is not None else None, seg.d0, seg.d1, seg.log2)
+            parts.append((seg, r))
+        return BinnedResult(parts, merged)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dd_binned_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def bandpass(x: torch.Tensor, window: int = 0, stream=None):
@@ -597,61 +668,79 @@ def rfi_mitigate(x: torch.Tensor, order: int, chan_threshold: float, window: int
     return fit, rmse, fmean, flags
 
 
-class SubbandPlan:
+class SubbandPlan(_Composite):
     """Subband dedispersion (Sec. "Subband Dedispersion"), an approximation of Eq.
-    bruteEquation at a fraction of the adds. Trials are grouped in runs of dms_per_group;
-    each group's nominal DM is its middle trial.
-    Step 1: each subband of chans_per_sub channels is an ordinary plan over the nominal
-    DMs (delays relative to the subband's top frequency), written into one buffer
-    [nsub][nnominal][L].
-    Step 2: per group, the [nsub][len1] strided view of that buffer is the reduced
-    filterbank of a plan whose channels are the subbands' top frequencies.
-    FP32 input."""
+    bruteEquation at a fraction of the adds, a dd_subband object. Trials are grouped in runs
+    of dms_per_group; each group's nominal DM is its middle trial. Step 1 dedisperses each
+    subband of chans_per_sub channels at the nominal DMs into a reduced filterbank; step 2
+    dedisperses each group's trials over its subband series. FP32 input; one library call."""
 
     def __init__(self, freq_mhz, tsamp_s: float, dm, chans_per_sub: int = 32, dms_per_group: int = 16):
+        lib = _lib.load()
+        self._lib = lib
         self.freq = np.ascontiguousarray(freq_mhz, dtype=np.float64)
         self.dm = np.ascontiguousarray(dm, dtype=np.float64)
         self.tsamp = float(tsamp_s)
         nchan, ndm = self.freq.size, self.dm.size
+        dbl = C.POINTER(C.c_double)
+        h = C.c_void_p()
+        check(lib.dd_subband_create(C.byref(h), self.freq.ctypes.data_as(dbl), nchan, self.tsamp,
+                                    self.dm.ctypes.data_as(dbl), ndm, int(chans_per_sub), int(dms_per_group)))
+        self._h = h
+        self._ws = {}
         self.subs = [(c0, min(nchan, c0 + chans_per_sub)) for c0 in range(0, nchan, chans_per_sub)]
         self.groups = [(d0, min(ndm, d0 + dms_per_group)) for d0 in range(0, ndm, dms_per_group)]
-        nominal = np.array([self.dm[d0 + (d1 - d0 - 1) // 2] for d0, d1 in self.groups])
-        self.step1 = [Plan(self.freq[c0:c1], self.tsamp, nominal) for c0, c1 in self.subs]
-        f_sub = np.array([self.freq[c0:c1].max() for c0, c1 in self.subs])
-        waves = max(1, min(6, -(-dms_per_group // 8)))
-        self.step2 = [Plan(f_sub, self.tsamp, self.dm[d0:d1], tuning=(8, waves)) for d0, d1 in self.groups]
-        self.maxdelay1 = max(p.maxdelay for p in self.step1)
+
+    @property
+    def launches(self) -> int:
+        """Dedispersion launches of an unbatched call: one per subband and one per group."""
+        return len(self.subs) + len(self.groups)
+
+    def _query(self, nsamp: int):
+        ws = C.c_int64()
+        adds = C.c_int64()
+        nout = np.zeros(self.dm.size, dtype=np.int64)
+        check(self._lib.dd_subband_query(self._h, int(nsamp), C.byref(ws), nout.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         C.byref(adds), None, None))
+        return ws.value, nout, adds.value
 
     def adds(self, nsamp: int) -> int:
         """Step-1 and step-2 channel-sample adds for an nsamp-sample input."""
-        a1 = sum(p.ndm * p.nchan * (int(nsamp) - p.maxdelay) for p in self.step1)
-        len1 = int(nsamp) - self.maxdelay1
-        return a1 + sum(p.ndm * p.nchan * (len1 - p.maxdelay) for p in self.step2)
+        return self._query(nsamp)[2]
+
+    def workspace(self, nsamp: int, device=None, stream=None) -> torch.Tensor:
+        return self._workspace(nsamp, device, stream, lambda ns: self._query(ns)[0], self._lib.dd_subband_upload)
 
     def dedisperse(self, x: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True,
                    stream=None, batched: bool = False):
-        """Returns [((d0, d1), Result)] per group of trials. With batched, each step is one
-        persistent launch (dd_batch_dedisperse) over its plans, equal bit for bit."""
+        """Returns [((d0, d1), Result)] per group of trials (dd_subband_dedisperse). With
+        batched, each step goes through one dd_batch_dedisperse call, equal bit for bit."""
         if x.dim() != 2 or x.dtype != torch.float32 or x.shape[0] != self.freq.size or x.stride(1) != 1:
             raise ValueError("x must be a [nchan][nsamp] float32 device tensor, time contiguous")
         nsamp = int(x.shape[1])
-        len1 = nsamp - self.maxdelay1
-        if len1 <= 0:
-            raise ValueError("nsamp must exceed the subband delays")
-        width = -(-(nsamp - min(p.maxdelay for p in self.step1)) // 64) * 64  # rows start 256-byte aligned
-        red = torch.empty((len(self.subs), len(self.groups), width), dtype=torch.float32, device=x.device)
-        if batched:
-            batch_dedisperse([(p, x[c0:c1]) for (c0, c1), p in zip(self.subs, self.step1)], stats=False,
-                             stream=stream, outputs=[(red[s], None, None, None, None) for s in range(len(self.subs))])
-            rs = batch_dedisperse([(p, red[:, g, :len1]) for g, p in enumerate(self.step2)], k_sigma=k_sigma,
-                                  cand_cap=cand_cap, stats=stats, stream=stream)
-        else:
-            for s, ((c0, c1), p) in enumerate(zip(self.subs, self.step1)):
-                p.dedisperse(x[c0:c1], stats=False, out=red[s], stream=stream)
-            rs = [p.dedisperse(red[:, g, :len1], k_sigma=k_sigma, cand_cap=cand_cap, stats=stats, stream=stream)
-                  for g, p in enumerate(self.step2)]
-        out = []
-        for grp, r in zip(self.groups, rs):
-            r._keep = (r._keep, red)
-            out.append((grp, r))
-        return out
+        _, nout, _ = self._query(nsamp)
+        out, mean, rms, cand, ncand = _outputs(self.dm.size, int(nout.max()), x.device, k_sigma, cand_cap, stats)
+        ws = self.workspace(nsamp, x.device, stream)
+        check(self._lib.dd_subband_dedisperse(self._h, _vp(x), nsamp, int(x.stride(0)), _vp(out), int(out.stride(0)),
+                                              _vp(mean), _vp(rms), float(k_sigma), _vp(cand),
+                                              int(cand_cap if cand is not None else 0), _vp(ncand), 1 if batched else 0,
+                                              _vp(ws), int(ws.numel()), _stream(stream)))
+        merged = Result(out, mean, rms, 0, cand, ncand, cand_cap)
+        merged._keep = ws
+        res = []
+        for d0, d1 in self.groups:
+            n = int(nout[d0])
+            res.append(((d0, d1), _PartResult(merged, out[d0:d1, :n], mean[d0:d1] if mean is not None else None,
+                                              rms[d0:d1] if rms is not None else None, d0, d1)))
+        return res
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dd_subband_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

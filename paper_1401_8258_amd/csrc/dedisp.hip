@@ -27,6 +27,7 @@
 #include <vector>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 
@@ -837,11 +838,13 @@ __device__ __forceinline__ void count_segment(const float* __restrict__ out, int
 }
 
 // The detections of one segment of series d, in time order, at their scanned offsets.
+// dm_index = d_base + d and t = t_base + (t << t_shift) (time-binned runs report times in
+// input samples).
 __device__ __forceinline__ void write_segment(const float* __restrict__ out, int64_t stride, int64_t nout,
                                               int64_t nseg, const double* __restrict__ stat,
                                               const int32_t* __restrict__ cnt, const int64_t* __restrict__ offs,
                                               dd_cand* __restrict__ cand, int64_t cap, int64_t t_base, int64_t seg,
-                                              int d, int* wtot) {
+                                              int d, int* wtot, int d_base = 0, int t_shift = 0) {
   const int64_t idx = (int64_t)d * nseg + seg;
   if (cnt[idx] == 0) return;
   int64_t off = offs[idx];
@@ -866,9 +869,9 @@ __device__ __forceinline__ void write_segment(const float* __restrict__ out, int
       const int64_t pos = off + before + below;
       if (pos < cap) {
         dd_cand o;
-        o.dm_index = d;
+        o.dm_index = d_base + d;
         o.reserved = 0;
-        o.t = t_base + t;
+        o.t = t_base + (t << t_shift);
         o.value = x;
         o.snr = r > 0.0 ? (float)(((double)x - m) / r) : 0.f;
         cand[pos] = o;
@@ -922,7 +925,9 @@ struct TailItem {
   dd_cand* cand;
   int64_t ntiles, nout, stride, nseg, cap, t_base, ser0, unit0;
   double k;
-  int32_t ndm, pad;
+  int32_t ndm;
+  int32_t d_base, t_shift;  // candidates report dm_index d_base + d and t t_base + (t << t_shift)
+  int32_t pad;
 };
 
 template <typename F>
@@ -964,7 +969,7 @@ __global__ __launch_bounds__(256) void cand_write_batch(const TailItem* __restri
   const TailItem& it = items[find_item(items, n, u, [](const TailItem& t) { return t.unit0; })];
   const int64_t local = u - it.unit0;
   write_segment(it.out, it.stride, it.nout, it.nseg, it.stat, it.cnt, it.offs, it.cand, it.cap, it.t_base,
-                local % it.nseg, (int)(local / it.nseg), wtot);
+                local % it.nseg, (int)(local / it.nseg), wtot, it.d_base, it.t_shift);
 }
 
 // Row c of the ring holds sample t at (t mod ring_len); positions below `mirror` are
@@ -1146,14 +1151,14 @@ int set_lds(const void* k, int64_t lds) {
 
 // Dedisperse nout outputs of a prepared input view, then stats and candidates.
 int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int64_t nout, const Outputs& o,
-                 char* ws, const dd::WsLayout& l, hipStream_t st) {
+                 char* ws, const dd::WsLayout& l, hipStream_t st, bool tail) {
   if (p->launch.form == dd::kFormRegWin || p->launch.form == dd::kFormDirect) {
     double* part = (o.mean && o.rms) ? reinterpret_cast<double*>(ws + l.part_off) : nullptr;
     int rc = p->launch.form == dd::kFormRegWin
                  ? dd::launch_regwin(p, in, d_table, nout, o.out, o.out_stride, part, st)
                  : dd::launch_direct(p, in, d_table, nout, o.out, o.out_stride, part, ws + l.quad_off, st);
     if (rc) return rc;
-    return launch_tail(p, nout, o, ws, l, st);
+    return tail ? launch_tail(p, nout, o, ws, l, st) : DD_OK;
   }
   KParams P;
   dd::Launch g;
@@ -1169,7 +1174,7 @@ int run_pipeline(const dd_plan* p, const InView& in, const int32_t* d_table, int
   hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (P.nw + P.nprod)), (size_t)g.lds, st, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "dedisp_tile launch");
-  return launch_tail(p, nout, o, ws, l, st);
+  return tail ? launch_tail(p, nout, o, ws, l, st) : DD_OK;
 }
 
 int check_outputs(const dd_plan* p, float* d_out, int64_t out_stride, int64_t nout, float* d_mean, float* d_rms,
@@ -1181,6 +1186,71 @@ int check_outputs(const dd_plan* p, float* d_out, int64_t out_stride, int64_t no
   if (k > 0.f && d_ncand && !d_mean) return dd::fail(DD_ERR_INVALID_ARG, "candidates need d_mean and d_rms");
   if (cap < 0 || (cap > 0 && !d_cand)) return dd::fail(DD_ERR_INVALID_ARG, "bad candidate buffer");
   (void)p;
+  return DD_OK;
+}
+
+
+// ------------------------------------------------------------------ composite plans
+//
+// A time-binned plan (runs of trials on the input downfactored 2^k times) and a subband plan
+// (step-1 plans per subband at nominal DMs, step-2 plans per group of trials over the
+// reduced filterbank) are made of ordinary plans. Their statistics come from each run's own
+// pipeline; their candidates go through one merged pass: counts of every run's (series,
+// segment) units, one scan over all of them, and one writing launch, so the detections of all
+// runs form one list in (global trial, time) order.
+
+// One run's part of a merged candidate pass.
+struct MergedRun {
+  const float* out;     // the run's first row
+  int64_t stride, nout;
+  const double* stat;   // [ndm][3] from the run's statistics
+  int32_t ndm, d0, shift;
+};
+
+int64_t merged_cand_bytes(const std::vector<MergedRun>& runs) {
+  int64_t units = 0;
+  for (const MergedRun& r : runs) units += (int64_t)r.ndm * ((r.nout + dd::kStatSeg - 1) / dd::kStatSeg);
+  return dd::align_up(units * 4) + dd::align_up(units * 8) + dd::align_up((int64_t)runs.size() * sizeof(TailItem));
+}
+
+int merged_candidates(const std::vector<MergedRun>& runs, float k, dd_cand* cand, int64_t cap, int64_t* ncand,
+                      char* region, hipStream_t st) {
+  int64_t units = 0;
+  for (const MergedRun& r : runs) units += (int64_t)r.ndm * ((r.nout + dd::kStatSeg - 1) / dd::kStatSeg);
+  int32_t* cnt = reinterpret_cast<int32_t*>(region);
+  int64_t* offs = reinterpret_cast<int64_t*>(region + dd::align_up(units * 4));
+  TailItem* dT = reinterpret_cast<TailItem*>(region + dd::align_up(units * 4) + dd::align_up(units * 8));
+  std::vector<TailItem> items;
+  int64_t u0 = 0;
+  for (const MergedRun& r : runs) {
+    TailItem t{};
+    t.stat = const_cast<double*>(r.stat);
+    t.out = r.out;
+    t.stride = r.stride;
+    t.nout = r.nout;
+    t.k = (double)k;
+    t.ndm = r.ndm;
+    t.nseg = (r.nout + dd::kStatSeg - 1) / dd::kStatSeg;
+    t.cnt = cnt + u0;
+    t.offs = offs + u0;
+    t.ncand = ncand;
+    t.cand = cand;
+    t.cap = cand ? cap : 0;
+    t.unit0 = u0;
+    t.d_base = r.d0;
+    t.t_shift = r.shift;
+    u0 += (int64_t)r.ndm * t.nseg;
+    items.push_back(t);
+  }
+  if (units > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many candidate segments");
+  hipError_t e = hipMemcpyAsync(dT, items.data(), items.size() * sizeof(TailItem), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (candidate descriptors)");
+  const int n = (int)items.size();
+  hipLaunchKernelGGL(cand_count_batch, dim3((unsigned)units), dim3(256), 0, st, (const TailItem*)dT, n);
+  hipLaunchKernelGGL(cand_scan, dim3(1), dim3(1024), 0, st, (const int32_t*)cnt, units, offs, ncand);
+  hipLaunchKernelGGL(cand_write_batch, dim3((unsigned)units), dim3(256), 0, st, (const TailItem*)dT, n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "merged candidate launch");
   return DD_OK;
 }
 
@@ -1216,7 +1286,7 @@ int dd_dedisperse(const dd_plan* p, const void* d_in, int64_t nsamp, int64_t in_
   Outputs o{d_out, out_row_stride, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand, 0};
   char* ws = static_cast<char*>(d_workspace);
   return run_pipeline(p, in, reinterpret_cast<const int32_t*>(ws + l.table_off), nout, o, ws, l,
-                      static_cast<hipStream_t>(stream));
+                      static_cast<hipStream_t>(stream), true);
 }
 
 int dd_dedisperse_noalloc(const dd_plan* p, const void* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
@@ -1266,7 +1336,7 @@ int dd_dedisperse_noalloc(const dd_plan* p, const void* d_in, int64_t nsamp, int
   InView in{d_in, in_row_stride, nsamp, 0, 0};
   Outputs o{d_out, out_row_stride, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand, 0};
   return run_pipeline(p, in, static_cast<const int32_t*>(d_table), nout, o, static_cast<char*>(sp), l,
-                      static_cast<hipStream_t>(stream));
+                      static_cast<hipStream_t>(stream), true);
 }
 
 int dd_stream_create(const dd_plan* p, int64_t block_nsamp, void* d_ring, int64_t ring_bytes, void* stream,
@@ -1413,7 +1483,7 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
   InView in{static_cast<char*>(s->ring) + dd::ring_table_bytes(p), s->ring_row, n + p->maxdelay, s->ring_len, t0};
   Outputs o{d_out, out_row_stride, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand, t0};
   rc = run_pipeline(p, in, static_cast<const int32_t*>(s->ring), n, o, static_cast<char*>(d_workspace), l,
-                    static_cast<hipStream_t>(stream));
+                    static_cast<hipStream_t>(stream), true);
   if (rc) return rc;
   if (t0_out) *t0_out = t0;
   if (nout_out) *nout_out = n;
@@ -1612,6 +1682,496 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   }
   for (int32_t i = 0; i < n; ++i)
     if (items[i].stream_item) items[i].stream_item->pending_n = 0;
+  return DD_OK;
+}
+
+
+// ------------------------------------------------------------------ time-binned plans
+
+}  // extern "C"
+
+struct dd_binned {
+  int32_t nchan = 0, ndm = 0, dtype = DD_F32, max_log2 = 0;
+  double tsamp = 0.0, dm_diag = 0.0;
+  struct Run {
+    int32_t k, d0, d1;
+    dd_plan* plan;
+  };
+  std::vector<Run> runs;
+  ~dd_binned() {
+    for (Run& r : runs) dd_plan_destroy(r.plan);
+  }
+};
+
+namespace {
+
+// Workspace of a time-binned call on nsamp samples: the downfactored inputs (levels 1 .. K,
+// FP32, rows of 64-sample multiples), each run's plan workspace (its delay table first, as
+// dd_plan_upload places it), the batch descriptors and the merged candidate region.
+struct BinnedLayout {
+  int64_t level_off[17] = {0}, level_row[17] = {0};
+  std::vector<int64_t> run_off, nout;
+  std::vector<dd::WsLayout> run_l;
+  int64_t batch_off = 0, cand_off = 0, total = 0;
+};
+
+int binned_layout(const dd_binned* b, int64_t nsamp, BinnedLayout* L) {
+  int64_t o = 0;
+  int kmax = 0;
+  for (const dd_binned::Run& r : b->runs) kmax = std::max(kmax, r.k);
+  for (int k = 1; k <= kmax; ++k) {
+    L->level_row[k] = dd::align_up(nsamp >> k, 64);
+    L->level_off[k] = o;
+    o += dd::align_up((int64_t)b->nchan * L->level_row[k] * 4);
+  }
+  std::vector<MergedRun> mr;
+  for (const dd_binned::Run& r : b->runs) {
+    const int64_t nk = nsamp >> r.k;
+    const int64_t nout = nk - r.plan->maxdelay;
+    if (nout < 1)
+      return dd::fail(DD_ERR_TOO_SHORT, "nsamp too short for the run at factor " + std::to_string(1 << r.k) +
+                                            " (needs more than " + std::to_string(r.plan->maxdelay) + " samples there)");
+    const dd::WsLayout l = dd::workspace_layout(r.plan, nk, true);
+    L->run_off.push_back(o);
+    L->run_l.push_back(l);
+    L->nout.push_back(nout);
+    o += dd::align_up(l.total);
+    mr.push_back(MergedRun{nullptr, 0, nout, nullptr, r.d1 - r.d0, r.d0, r.k});
+  }
+  std::vector<dd_batch_item> none((size_t)b->runs.size());
+  int64_t bq = 0;
+  dd_batch_query(none.data(), (int32_t)none.size(), &bq);
+  L->batch_off = o;
+  o += dd::align_up(bq);
+  L->cand_off = o;
+  o += merged_cand_bytes(mr);
+  L->total = o;
+  return DD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dd_binned_create(dd_binned** out, const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm,
+                     int32_t ndm, int32_t in_dtype, int32_t max_log2, const dd_tuning* tuning) {
+  dd::clear_error();
+  if (!out) return dd::fail(DD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!dm || ndm < 1) return dd::fail(DD_ERR_INVALID_ARG, "dm must be non-NULL with ndm >= 1");
+  std::vector<int32_t> lg((size_t)ndm);
+  double diag = 0.0;
+  int rc = dd_time_binning(freq_mhz, nchan, tsamp_s, dm, ndm, max_log2, &diag, lg.data());
+  if (rc) return rc;
+  dd_binned* b = new (std::nothrow) dd_binned();
+  if (!b) return dd::fail(DD_ERR_INVALID_ARG, "out of host memory");
+  b->nchan = nchan;
+  b->ndm = ndm;
+  b->dtype = in_dtype;
+  b->max_log2 = max_log2;
+  b->tsamp = tsamp_s;
+  b->dm_diag = diag;
+  // runs with k >= 1 read FP32 sums; a tuning of the 8-bit direct-read form applies to the
+  // factor-1 run only
+  const bool direct = tuning && tuning->kernel_form == DD_FORM_DIRECT;
+  for (int32_t d0 = 0, d = 1; d <= ndm; ++d) {
+    if (d < ndm && lg[d] == lg[d0]) continue;
+    const int32_t k = lg[d0];
+    dd_plan* p = nullptr;
+    rc = dd_plan_create(&p, freq_mhz, nchan, tsamp_s * (double)(1 << k), dm + d0, d - d0, k == 0 ? in_dtype : DD_F32,
+                        k == 0 || !direct ? tuning : nullptr);
+    if (rc) {
+      delete b;
+      return rc;
+    }
+    b->runs.push_back(dd_binned::Run{k, d0, d, p});
+    d0 = d;
+  }
+  *out = b;
+  return DD_OK;
+}
+
+void dd_binned_destroy(dd_binned* b) { delete b; }
+
+int dd_binned_query(const dd_binned* b, int64_t nsamp, int32_t* nruns, dd_binned_run* runs, int32_t runs_cap,
+                    int64_t* workspace_bytes, double* dm_diag) {
+  dd::clear_error();
+  if (!b) return dd::fail(DD_ERR_INVALID_ARG, "plan is NULL");
+  if (nruns) *nruns = (int32_t)b->runs.size();
+  if (dm_diag) *dm_diag = b->dm_diag;
+  if (runs) {
+    for (int32_t i = 0; i < runs_cap && i < (int32_t)b->runs.size(); ++i) {
+      const dd_binned::Run& r = b->runs[i];
+      dd_binned_run o{};
+      o.log2 = r.k;
+      o.d0 = r.d0;
+      o.d1 = r.d1;
+      o.maxdelay = r.plan->maxdelay;
+      o.nout = nsamp > 0 ? (nsamp >> r.k) - r.plan->maxdelay : 0;
+      o.kernel_form = r.plan->launch.form;
+      o.dms_per_wave = r.plan->tiles.g;
+      o.waves = r.plan->tiles.w;
+      runs[i] = o;
+    }
+  }
+  if (workspace_bytes) *workspace_bytes = 0;
+  if (nsamp <= 0) return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be > 0");
+  BinnedLayout L;
+  const int rc = binned_layout(b, nsamp, &L);
+  if (rc) return rc;
+  if (workspace_bytes) *workspace_bytes = L.total;
+  return DD_OK;
+}
+
+int dd_binned_upload(const dd_binned* b, int64_t nsamp, void* d_workspace, int64_t ws_bytes, void* stream) {
+  dd::clear_error();
+  if (!b || !d_workspace) return dd::fail(DD_ERR_INVALID_ARG, "plan and workspace must be non-NULL");
+  BinnedLayout L;
+  int rc = binned_layout(b, nsamp, &L);
+  if (rc) return rc;
+  if (ws_bytes < L.total) return dd::fail(DD_ERR_WORKSPACE, "workspace smaller than dd_binned_query asks for");
+  for (size_t i = 0; i < b->runs.size(); ++i) {
+    rc = dd_plan_upload(b->runs[i].plan, static_cast<char*>(d_workspace) + L.run_off[i], L.run_l[i].total, stream);
+    if (rc) return rc;
+  }
+  return DD_OK;
+}
+
+int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
+                         int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,
+                         int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace, int64_t ws_bytes,
+                         void* stream) {
+  dd::clear_error();
+  if (!b || !d_in || !d_workspace) return dd::fail(DD_ERR_INVALID_ARG, "plan, input and workspace are required");
+  if (in_row_stride < nsamp) return dd::fail(DD_ERR_INVALID_ARG, "in_row_stride < nsamp");
+  BinnedLayout L;
+  int rc = binned_layout(b, nsamp, &L);
+  if (rc) return rc;
+  if (ws_bytes < L.total) return dd::fail(DD_ERR_WORKSPACE, "workspace smaller than dd_binned_query asks for");
+  const int64_t nout_max = *std::max_element(L.nout.begin(), L.nout.end());
+  rc = check_outputs(b->runs[0].plan, d_out, out_row_stride, nout_max, d_mean, d_rms, k_sigma, d_cand, cand_cap,
+                     d_ncand);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(d_workspace);
+  // the downfactored inputs, each level from the one below
+  int kmax = 0;
+  for (const dd_binned::Run& r : b->runs) kmax = std::max(kmax, r.k);
+  const void* lvl = d_in;
+  int32_t lvl_dtype = b->dtype;
+  int64_t lvl_stride = in_row_stride;
+  std::vector<const void*> level_ptr(kmax + 1, d_in);
+  std::vector<int64_t> level_stride(kmax + 1, in_row_stride);
+  for (int k = 1; k <= kmax; ++k) {
+    float* dst = reinterpret_cast<float*>(ws + L.level_off[k]);
+    rc = dd_downfactor(lvl, lvl_dtype, b->nchan, nsamp >> (k - 1), lvl_stride, dst, L.level_row[k], stream);
+    if (rc) return rc;
+    level_ptr[k] = dst;
+    level_stride[k] = L.level_row[k];
+    lvl = dst;
+    lvl_dtype = DD_F32;
+    lvl_stride = L.level_row[k];
+  }
+  const bool stats = d_mean && d_rms;
+  if (batched) {
+    std::vector<dd_batch_item> items(b->runs.size());
+    for (size_t i = 0; i < b->runs.size(); ++i) {
+      const dd_binned::Run& r = b->runs[i];
+      dd_batch_item& it = items[i];
+      it = dd_batch_item{};
+      it.plan = r.plan;
+      it.d_in = level_ptr[r.k];
+      it.nsamp = nsamp >> r.k;
+      it.in_row_stride = level_stride[r.k];
+      it.d_out = d_out + (int64_t)r.d0 * out_row_stride;
+      it.out_row_stride = out_row_stride;
+      it.d_mean = stats ? d_mean + r.d0 : nullptr;
+      it.d_rms = stats ? d_rms + r.d0 : nullptr;
+      it.k_sigma = k_sigma;  // thresholds for the merged pass; no candidate buffers here
+      it.d_plan_workspace = ws + L.run_off[i];
+    }
+    rc = dd_batch_dedisperse(items.data(), (int32_t)items.size(), ws + L.batch_off, L.cand_off - L.batch_off, stream);
+    if (rc) return rc;
+  } else {
+    for (size_t i = 0; i < b->runs.size(); ++i) {
+      const dd_binned::Run& r = b->runs[i];
+      char* rw = ws + L.run_off[i];
+      const InView in{level_ptr[r.k], level_stride[r.k], nsamp >> r.k, 0, 0};
+      // k sets the thresholds the merged candidate pass reads; no candidate buffers here
+      const Outputs o{d_out + (int64_t)r.d0 * out_row_stride, out_row_stride, stats ? d_mean + r.d0 : nullptr,
+                      stats ? d_rms + r.d0 : nullptr, k_sigma, nullptr, 0, nullptr, 0};
+      rc = run_pipeline(r.plan, in, reinterpret_cast<const int32_t*>(rw + L.run_l[i].table_off), L.nout[i], o, rw,
+                        L.run_l[i], st, true);
+      if (rc) return rc;
+    }
+  }
+  if (stats && k_sigma > 0.f && d_ncand) {
+    std::vector<MergedRun> mr;
+    for (size_t i = 0; i < b->runs.size(); ++i) {
+      const dd_binned::Run& r = b->runs[i];
+      mr.push_back(MergedRun{d_out + (int64_t)r.d0 * out_row_stride, out_row_stride, L.nout[i],
+                             reinterpret_cast<const double*>(ws + L.run_off[i] + L.run_l[i].thr_off), r.d1 - r.d0,
+                             r.d0, r.k});
+    }
+    rc = merged_candidates(mr, k_sigma, d_cand, cand_cap, d_ncand, ws + L.cand_off, st);
+    if (rc) return rc;
+  }
+  return DD_OK;
+}
+
+// ------------------------------------------------------------------ subband plans
+
+}  // extern "C"
+
+struct dd_subband {
+  int32_t nchan = 0, ndm = 0, chans_per_sub = 0, dms_per_group = 0;
+  double tsamp = 0.0;
+  std::vector<std::pair<int32_t, int32_t>> subs, groups;
+  std::vector<dd_plan*> step1, step2;
+  int32_t maxdelay1 = 0, min_maxdelay1 = 0;
+  ~dd_subband() {
+    for (dd_plan* p : step1) dd_plan_destroy(p);
+    for (dd_plan* p : step2) dd_plan_destroy(p);
+  }
+};
+
+namespace {
+
+// Workspace of a subband call: the reduced filterbank [nsub][ngroups][width] (step-1
+// outputs; width a 64-sample multiple), each step-1 and step-2 plan's workspace, the batch
+// descriptors and the merged candidate region.
+struct SubbandLayout {
+  int64_t width = 0, len1 = 0, red_off = 0, batch_off = 0, cand_off = 0, total = 0;
+  std::vector<int64_t> off1, off2, nout1, nout2;
+  std::vector<dd::WsLayout> l1, l2;
+};
+
+int subband_layout(const dd_subband* sp, int64_t nsamp, SubbandLayout* L) {
+  L->len1 = nsamp - sp->maxdelay1;
+  if (L->len1 < 1) return dd::fail(DD_ERR_TOO_SHORT, "nsamp must exceed the subband delays");
+  L->width = dd::align_up(nsamp - sp->min_maxdelay1, 64);
+  int64_t o = 0;
+  L->red_off = o;
+  o += dd::align_up((int64_t)sp->subs.size() * sp->groups.size() * L->width * 4);
+  for (dd_plan* p : sp->step1) {
+    const dd::WsLayout l = dd::workspace_layout(p, nsamp, true);
+    L->off1.push_back(o);
+    L->l1.push_back(l);
+    L->nout1.push_back(nsamp - p->maxdelay);
+    o += dd::align_up(l.total);
+  }
+  std::vector<MergedRun> mr;
+  for (size_t g = 0; g < sp->step2.size(); ++g) {
+    dd_plan* p = sp->step2[g];
+    const int64_t nout = L->len1 - p->maxdelay;
+    if (nout < 1) return dd::fail(DD_ERR_TOO_SHORT, "nsamp must exceed the subband and group delays");
+    const dd::WsLayout l = dd::workspace_layout(p, L->len1, true);
+    L->off2.push_back(o);
+    L->l2.push_back(l);
+    L->nout2.push_back(nout);
+    o += dd::align_up(l.total);
+    mr.push_back(MergedRun{nullptr, 0, nout, nullptr, p->ndm, sp->groups[g].first, 0});
+  }
+  const int32_t nb = (int32_t)std::max(sp->step1.size(), sp->step2.size());
+  std::vector<dd_batch_item> none((size_t)nb);
+  int64_t bq = 0;
+  dd_batch_query(none.data(), nb, &bq);
+  L->batch_off = o;
+  o += dd::align_up(bq);
+  L->cand_off = o;
+  o += merged_cand_bytes(mr);
+  L->total = o;
+  return DD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dd_subband_create(dd_subband** out, const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm,
+                      int32_t ndm, int32_t chans_per_sub, int32_t dms_per_group) {
+  dd::clear_error();
+  if (!out) return dd::fail(DD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!freq_mhz || !dm || nchan < 1 || ndm < 1)
+    return dd::fail(DD_ERR_INVALID_ARG, "freq_mhz and dm must be non-NULL with nchan, ndm >= 1");
+  if (chans_per_sub < 1 || dms_per_group < 1)
+    return dd::fail(DD_ERR_INVALID_ARG, "chans_per_sub and dms_per_group must be >= 1");
+  dd_subband* sp = new (std::nothrow) dd_subband();
+  if (!sp) return dd::fail(DD_ERR_INVALID_ARG, "out of host memory");
+  sp->nchan = nchan;
+  sp->ndm = ndm;
+  sp->chans_per_sub = chans_per_sub;
+  sp->dms_per_group = dms_per_group;
+  sp->tsamp = tsamp_s;
+  for (int32_t c0 = 0; c0 < nchan; c0 += chans_per_sub) sp->subs.push_back({c0, std::min(nchan, c0 + chans_per_sub)});
+  for (int32_t d0 = 0; d0 < ndm; d0 += dms_per_group) sp->groups.push_back({d0, std::min(ndm, d0 + dms_per_group)});
+  // each group's nominal DM is its middle trial
+  std::vector<double> nominal;
+  for (const auto& g : sp->groups) nominal.push_back(dm[g.first + (g.second - g.first - 1) / 2]);
+  std::vector<double> fsub;
+  int rc = DD_OK;
+  for (const auto& s : sp->subs) {
+    dd_plan* p = nullptr;
+    rc = dd_plan_create(&p, freq_mhz + s.first, s.second - s.first, tsamp_s, nominal.data(), (int32_t)nominal.size(),
+                        DD_F32, nullptr);
+    if (rc) break;
+    sp->step1.push_back(p);
+    fsub.push_back(*std::max_element(freq_mhz + s.first, freq_mhz + s.second));
+  }
+  // step 2: groups of dms_per_group trials share a workgroup (8 trials per wavefront)
+  dd_tuning t2{};
+  t2.dms_per_wave = 8;
+  t2.waves = std::max(1, std::min(6, (dms_per_group + 7) / 8));
+  t2.kernel_form = DD_FORM_LDS;
+  for (size_t g = 0; rc == DD_OK && g < sp->groups.size(); ++g) {
+    dd_plan* p = nullptr;
+    rc = dd_plan_create(&p, fsub.data(), (int32_t)fsub.size(), tsamp_s, dm + sp->groups[g].first,
+                        sp->groups[g].second - sp->groups[g].first, DD_F32, &t2);
+    if (rc) break;
+    sp->step2.push_back(p);
+  }
+  if (rc) {
+    delete sp;
+    return rc;
+  }
+  sp->maxdelay1 = 0;
+  sp->min_maxdelay1 = std::numeric_limits<int32_t>::max();
+  for (dd_plan* p : sp->step1) {
+    sp->maxdelay1 = std::max(sp->maxdelay1, p->maxdelay);
+    sp->min_maxdelay1 = std::min(sp->min_maxdelay1, p->maxdelay);
+  }
+  *out = sp;
+  return DD_OK;
+}
+
+void dd_subband_destroy(dd_subband* sp) { delete sp; }
+
+int dd_subband_query(const dd_subband* sp, int64_t nsamp, int64_t* workspace_bytes, int64_t* nout_per_dm,
+                     int64_t* adds, int32_t* nsub, int32_t* ngroups) {
+  dd::clear_error();
+  if (!sp) return dd::fail(DD_ERR_INVALID_ARG, "plan is NULL");
+  if (nsub) *nsub = (int32_t)sp->subs.size();
+  if (ngroups) *ngroups = (int32_t)sp->groups.size();
+  if (workspace_bytes) *workspace_bytes = 0;
+  if (nsamp <= 0) return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be > 0");
+  SubbandLayout L;
+  const int rc = subband_layout(sp, nsamp, &L);
+  if (rc) return rc;
+  if (workspace_bytes) *workspace_bytes = L.total;
+  int64_t a = 0;
+  for (size_t s = 0; s < sp->step1.size(); ++s) a += (int64_t)sp->step1[s]->ndm * sp->step1[s]->nchan * L.nout1[s];
+  for (size_t g = 0; g < sp->step2.size(); ++g) {
+    a += (int64_t)sp->step2[g]->ndm * sp->step2[g]->nchan * L.nout2[g];
+    if (nout_per_dm)
+      for (int32_t d = sp->groups[g].first; d < sp->groups[g].second; ++d) nout_per_dm[d] = L.nout2[g];
+  }
+  if (adds) *adds = a;
+  return DD_OK;
+}
+
+int dd_subband_upload(const dd_subband* sp, int64_t nsamp, void* d_workspace, int64_t ws_bytes, void* stream) {
+  dd::clear_error();
+  if (!sp || !d_workspace) return dd::fail(DD_ERR_INVALID_ARG, "plan and workspace must be non-NULL");
+  SubbandLayout L;
+  int rc = subband_layout(sp, nsamp, &L);
+  if (rc) return rc;
+  if (ws_bytes < L.total) return dd::fail(DD_ERR_WORKSPACE, "workspace smaller than dd_subband_query asks for");
+  char* ws = static_cast<char*>(d_workspace);
+  for (size_t s = 0; s < sp->step1.size() && rc == DD_OK; ++s)
+    rc = dd_plan_upload(sp->step1[s], ws + L.off1[s], L.l1[s].total, stream);
+  for (size_t g = 0; g < sp->step2.size() && rc == DD_OK; ++g)
+    rc = dd_plan_upload(sp->step2[g], ws + L.off2[g], L.l2[g].total, stream);
+  return rc;
+}
+
+int dd_subband_dedisperse(const dd_subband* sp, const float* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
+                          int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,
+                          int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace, int64_t ws_bytes,
+                          void* stream) {
+  dd::clear_error();
+  if (!sp || !d_in || !d_workspace) return dd::fail(DD_ERR_INVALID_ARG, "plan, input and workspace are required");
+  if (in_row_stride < nsamp) return dd::fail(DD_ERR_INVALID_ARG, "in_row_stride < nsamp");
+  SubbandLayout L;
+  int rc = subband_layout(sp, nsamp, &L);
+  if (rc) return rc;
+  if (ws_bytes < L.total) return dd::fail(DD_ERR_WORKSPACE, "workspace smaller than dd_subband_query asks for");
+  const int64_t nout_max = *std::max_element(L.nout2.begin(), L.nout2.end());
+  rc = check_outputs(sp->step2[0], d_out, out_row_stride, nout_max, d_mean, d_rms, k_sigma, d_cand, cand_cap, d_ncand);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(d_workspace);
+  float* red = reinterpret_cast<float*>(ws + L.red_off);
+  const int64_t ngrp = (int64_t)sp->groups.size();
+  const bool stats = d_mean && d_rms;
+  // step 1: subband s at the nominal DMs into red[s][g][:]
+  if (batched) {
+    std::vector<dd_batch_item> items(sp->step1.size());
+    for (size_t s = 0; s < sp->step1.size(); ++s) {
+      dd_batch_item& it = items[s];
+      it = dd_batch_item{};
+      it.plan = sp->step1[s];
+      it.d_in = d_in + (int64_t)sp->subs[s].first * in_row_stride;
+      it.nsamp = nsamp;
+      it.in_row_stride = in_row_stride;
+      it.d_out = red + (int64_t)s * ngrp * L.width;
+      it.out_row_stride = L.width;
+      it.d_plan_workspace = ws + L.off1[s];
+    }
+    rc = dd_batch_dedisperse(items.data(), (int32_t)items.size(), ws + L.batch_off, L.cand_off - L.batch_off, stream);
+    if (rc) return rc;
+  } else {
+    for (size_t s = 0; s < sp->step1.size(); ++s) {
+      char* rw = ws + L.off1[s];
+      const InView in{d_in + (int64_t)sp->subs[s].first * in_row_stride, in_row_stride, nsamp, 0, 0};
+      const Outputs o{red + (int64_t)s * ngrp * L.width, L.width, nullptr, nullptr, 0.f, nullptr, 0, nullptr, 0};
+      rc = run_pipeline(sp->step1[s], in, reinterpret_cast<const int32_t*>(rw + L.l1[s].table_off), L.nout1[s], o, rw,
+                        L.l1[s], st, true);
+      if (rc) return rc;
+    }
+  }
+  // step 2: group g over the reduced filterbank red[:][g][0 .. len1)
+  if (batched) {
+    std::vector<dd_batch_item> items(sp->step2.size());
+    for (size_t g = 0; g < sp->step2.size(); ++g) {
+      dd_batch_item& it = items[g];
+      it = dd_batch_item{};
+      it.plan = sp->step2[g];
+      it.d_in = red + (int64_t)g * L.width;
+      it.nsamp = L.len1;
+      it.in_row_stride = ngrp * L.width;
+      it.d_out = d_out + (int64_t)sp->groups[g].first * out_row_stride;
+      it.out_row_stride = out_row_stride;
+      it.d_mean = stats ? d_mean + sp->groups[g].first : nullptr;
+      it.d_rms = stats ? d_rms + sp->groups[g].first : nullptr;
+      it.k_sigma = k_sigma;
+      it.d_plan_workspace = ws + L.off2[g];
+    }
+    rc = dd_batch_dedisperse(items.data(), (int32_t)items.size(), ws + L.batch_off, L.cand_off - L.batch_off, stream);
+    if (rc) return rc;
+  } else {
+    for (size_t g = 0; g < sp->step2.size(); ++g) {
+      char* rw = ws + L.off2[g];
+      const int32_t d0 = sp->groups[g].first;
+      const InView in{red + (int64_t)g * L.width, ngrp * L.width, L.len1, 0, 0};
+      const Outputs o{d_out + (int64_t)d0 * out_row_stride, out_row_stride, stats ? d_mean + d0 : nullptr,
+                      stats ? d_rms + d0 : nullptr, k_sigma, nullptr, 0, nullptr, 0};
+      rc = run_pipeline(sp->step2[g], in, reinterpret_cast<const int32_t*>(rw + L.l2[g].table_off), L.nout2[g], o, rw,
+                        L.l2[g], st, true);
+      if (rc) return rc;
+    }
+  }
+  if (stats && k_sigma > 0.f && d_ncand) {
+    std::vector<MergedRun> mr;
+    for (size_t g = 0; g < sp->step2.size(); ++g) {
+      const int32_t d0 = sp->groups[g].first;
+      mr.push_back(MergedRun{d_out + (int64_t)d0 * out_row_stride, out_row_stride, L.nout2[g],
+                             reinterpret_cast<const double*>(ws + L.off2[g] + L.l2[g].thr_off), sp->step2[g]->ndm, d0,
+                             0});
+    }
+    rc = merged_candidates(mr, k_sigma, d_cand, cand_cap, d_ncand, ws + L.cand_off, st);
+    if (rc) return rc;
+  }
   return DD_OK;
 }
 
