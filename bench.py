@@ -57,12 +57,13 @@ def parse():
                          "(used only while the kernel source is the one it was measured on)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the input (known bytes) to calibrate HBM counters")
-    ap.add_argument("--mode", choices=("plain", "batch", "serve", "subband", "u8beam"), default="plain",
+    ap.add_argument("--mode", choices=("plain", "batch", "serve", "subband", "u8beam", "binstream"), default="plain",
                     help="plain: the full-size FP32 workload (default); batch: 16 uneven u8 beams in one "
                          "batched call; serve: 64 streaming u8 beams with continuous batching; "
                          "subband: only the subband passes over the full-size FP32 workload; u8beam: the "
                          "largest 4096-channel u8 beam of the batch in its default (direct-read) plan "
-                         "(both last two for profiling)")
+                         "(both for profiling); binstream: a 4096-channel serving beam streamed plain and "
+                         "with time binning")
     ap.add_argument("--serve-blocks", type=int, default=60,
                     help="1 s blocks per beam after the ring fill in the serving run (plain mode appends a "
                          "serving summary when > 0)")
@@ -296,6 +297,77 @@ def batch_run(reps):
             "per_beam_alone": per_beam}
 
 
+def binned_stream_run(nblocks):
+    """One 4096-channel serving beam (120-180 MHz, 81.92 us, 4096 u8 DMs step 0.05, maxdelay
+    ~400k samples) streamed in blocks of 12208 samples (1.0001 s, a multiple of 16): a plain
+    stream against a time-binned one (factors up to 16, one ring per run at its binned
+    sampling time). Both are filled first; then the device time of nblocks pushes (ring
+    appends, dedispersion, statistics and 6-sigma candidates) by HIP events, and the ring
+    bytes each keeps."""
+    import torch
+
+    import fbsynth
+    import paper_1401_8258_amd as dd
+    from paper_1401_8258_amd import api
+
+    sp = fbsynth.config5_specs()[48]
+    assert sp["nchan"] == 4096
+    freq = fbsynth.channel_freqs(sp["f_top"], sp["bw"] / sp["nchan"], sp["nchan"])
+    dms = fbsynth.dm_trials(sp["dm0"], sp["step"], sp["ndm"])
+    block = 12208
+    g = torch.Generator(device="cuda")
+    g.manual_seed(9)
+    pool = [torch.clamp(torch.round(128.0 + 16.0 * torch.randn((sp["nchan"], block), generator=g, device="cuda")),
+                        0, 255).to(torch.uint8) for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"workload": f"u8 beam: 4096 ch 120-180 MHz, tsamp 81.92 us, {sp['ndm']} DMs step {sp['step']}, "
+                       f"blocks of {block} samples, stats + 6-sigma candidates", "blocks_timed": nblocks}
+    plan = dd.Plan(freq, sp["tsamp"], dms, dtype="u8")
+    st = dd.Stream(plan, block)
+    nf = plan.maxdelay // block
+    for k in range(nf):
+        st.append(pool[k % 3])
+    out = api.alloc_outputs(plan.ndm, block, "cuda", 6.0, 1 << 16)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(nblocks):
+        w = st.append(pool[(nf + k) % 3])
+        dd.batch_dedisperse([(st, w)], k_sigma=6.0, cand_cap=1 << 16, outputs=[out])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / nblocks
+    res["plain"] = {"ring_bytes": int(st.ring.numel()), "maxdelay": plan.maxdelay, "form": plan.form,
+                    "ms_per_block": round(ms_plain, 3), "adds_per_block": plan.ndm * plan.nchan * block}
+    del st
+    torch.cuda.empty_cache()
+    bp = dd.BinnedPlan(freq, sp["tsamp"], dms, dtype="u8", max_log2=4)
+    bs = dd.BinnedStream(bp, block)
+    outs = api.alloc_outputs(bp.dm.size, block, "cuda", 6.0, 1 << 16)
+    nfb = -(-bp.fill_nsamp // block)
+    for k in range(nfb):
+        bs.push(pool[k % 3], stats=False, batched=bp.batchable)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(nblocks):
+        r = bs.push(pool[(nfb + k) % 3], k_sigma=6.0, outputs=outs, batched=bp.batchable)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / nblocks
+    assert r is not None and all(x is not None for _, _, x in r.segments)
+    adds_b = sum((sg.d1 - sg.d0) * bp.freq.size * (block >> sg.log2) for sg in bp.segments)
+    res["binned"] = {"ring_bytes": bs.ring_bytes, "max_log2": 4, "dm_diag": round(bp.dm_diag, 4),
+                     "runs": [{"factor": 1 << sg.log2, "ndm": sg.d1 - sg.d0, "maxdelay": sg.plan.maxdelay,
+                               "form": sg.plan.form} for sg in bp.segments],
+                     "batched_runs": bp.batchable, "ms_per_block": round(ms_b, 3), "adds_per_block": adds_b}
+    res["ring_bytes_ratio"] = round(res["plain"]["ring_bytes"] / bs.ring_bytes, 2)
+    res["speedup_per_block"] = round(ms_plain / ms_b, 3)
+    res["block_s"] = block * sp["tsamp"]
+    del bs
+    torch.cuda.empty_cache()
+    return res
+
+
 def u8beam_run(steps, warmup):
     """The 4096-channel 120-180 MHz u8 beam of config 4 with the most work, default plan
     (direct-read form): kernel-only launches (no statistics), then whole steps."""
@@ -383,6 +455,9 @@ def main():
         return
     if args.mode == "u8beam":
         print(json.dumps(u8beam_run(args.steps, args.warmup)), flush=True)
+        return
+    if args.mode == "binstream":
+        print(json.dumps(binned_stream_run(max(args.steps, 1))), flush=True)
         return
     if args.mode == "serve":
         res = serve_run(max(args.serve_blocks, 1), int(args.hbm_budget_gb * 1e9))
@@ -694,6 +769,9 @@ def main():
         res["batch"] = batch_run(args.batch_reps)
         torch.cuda.empty_cache()
     if args.serve_blocks > 0:
+        print("bench: binned stream of a 4096-channel serving beam", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        res["binned_stream"] = binned_stream_run(8)
         print(f"bench: serving run ({args.serve_blocks} blocks per beam)", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         res["serving"] = serve_run(args.serve_blocks, int(args.hbm_budget_gb * 1e9))

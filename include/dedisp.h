@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define DD_VERSION_MAJOR 1
-#define DD_VERSION_MINOR 3  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves;
+#define DD_VERSION_MINOR 5  /* 1: dd_tuning.producer_waves, dd_plan_info.producer_waves;
                                2: dd_time_binning, dd_downfactor, dd_bandpass,
                                   dd_bandpass_fit, dd_rfi_clip;
                                3: dd_tuning.kernel_form, dd_plan_info.kernel_form and
@@ -55,7 +55,10 @@ extern "C" {
                                   dd_bandpass window means; dd_rfi_clip bandpass
                                   subtraction (subtract_bandpass) from the window means;
                                   DD_WARN_CAND_OVERFLOW, dd_candidates_check,
-                                  dd_stream_set_gap_fill */
+                                  dd_stream_set_gap_fill;
+                               4: DD_FORM_DIRECT, dd_plan_info.stream_workspace_bytes,
+                                  dd_boxcar_search, dd_binned_*, dd_subband_*;
+                               5: dd_binned_stream_*, dd_bandpass_u8, dd_rfi_clip_u8 */
 #define DD_CHAN_BLOCK 32
 
 /* Status codes. */
@@ -422,10 +425,13 @@ int dd_downfactor(const void* d_in, int32_t in_dtype, int64_t nchan, int64_t nsa
  * Sec. "Direct Dedispersion"; Sec. "Computing Larger DMs"). The trials are split into runs
  * by dd_time_binning; run k (trials whose factor is 2^k) is an ordinary plan at sampling
  * time 2^k tsamp_s over the input downfactored k times (dd_downfactor: FP32 sums; the
- * factor-1 run reads the input in in_dtype). A tuning applies to every run, except that the
- * 8-bit direct-read form (DD_FORM_DIRECT) applies to the factor-1 run only. Host object,
- * immutable after creation; the caller keeps its arrays. Errors as dd_time_binning and
- * dd_plan_create.
+ * factor-1 run reads the input in in_dtype). A tuning of the 8-bit direct-read form
+ * (DD_FORM_DIRECT) applies to the factor-1 run only; DD_FORM_LDS and DD_FORM_REGWIN to every
+ * run; DD_FORM_AUTO with tile fields to every run except an 8-bit factor-1 run, which keeps
+ * the direct-read form. Without a tuning each run takes the planner's choice for its own
+ * trials (runs on different tiles cannot share a batched call; see dd_binned_dedisperse).
+ * Host object, immutable after creation; the caller keeps its arrays. Errors as
+ * dd_time_binning and dd_plan_create.
  */
 typedef struct dd_binned dd_binned;
 typedef struct dd_binned_run {
@@ -434,6 +440,7 @@ typedef struct dd_binned_run {
   int32_t maxdelay;    /* in samples of the run (2^log2 tsamp_s) */
   int64_t nout;        /* (nsamp >> log2) - maxdelay for the queried nsamp */
   int32_t kernel_form, dms_per_wave, waves;
+  int32_t producer_waves;  /* the run plan's producer wavefronts (LDS form; 0 otherwise) */
 } dd_binned_run;
 int dd_binned_create(dd_binned** out, const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm,
                      int32_t ndm, int32_t in_dtype, int32_t max_log2, const dd_tuning* tuning);
@@ -458,6 +465,47 @@ int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, in
                          int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace, int64_t ws_bytes,
                          void* stream);
 void dd_binned_destroy(dd_binned* b);
+
+/*
+ * Streaming over a time-binned plan (Ch. 2 Sec. "Direct Dedispersion": time binning keeps
+ * the long delays of low frequencies affordable; Ch. 3 Sec. "Dedispersion": the last
+ * maxshift spectra of a buffer are carried into the next). Each run keeps its own stream
+ * ring (as dd_stream_create) of the input downfactored 2^log2 times, so a run holds its
+ * maxdelay at its own sampling time. block_nsamp and every pushed nsamp must be multiples of
+ * 2^K, K the largest run log2: no pair of samples then straddles two blocks, and each run's
+ * outputs equal those of dd_binned_dedisperse over the concatenated blocks, bit for bit.
+ * dd_binned_stream_query gives the ring bytes (all runs' rings and delay tables, caller-owned
+ * device memory) and the workspace one push needs; DD_ERR_INVALID_ARG for a block_nsamp that
+ * is not a positive multiple of 2^K.
+ */
+typedef struct dd_binned_stream dd_binned_stream;
+int dd_binned_stream_query(const dd_binned* b, int64_t block_nsamp, int64_t* ring_bytes, int64_t* workspace_bytes);
+/* The binned plan must outlive the stream. Uploads every run's delay table into d_ring on
+   `stream`. */
+int dd_binned_stream_create(const dd_binned* b, int64_t block_nsamp, void* d_ring, int64_t ring_bytes, void* stream,
+                            dd_binned_stream** out);
+/*
+ * Append one block (seq = 0, 1, 2, ...; nsamp <= block_nsamp samples in
+ * [nchan][in_row_stride] of the plan's input dtype, nsamp a multiple of 2^K) and dedisperse
+ * what became computable in each run: run i (in dd_binned_query order) writes outputs at
+ * its own global output times [t0_out[i], t0_out[i] + nout_out[i]) (samples of that run's
+ * sampling time) into d_out rows d0 .. d1-1 from column 0; nout_out[i] = 0 while that run
+ * fills (its rows, mean and rms are then left alone). t0_out and nout_out hold one entry per
+ * run and may be NULL. d_out needs block_nsamp columns. Statistics cover each run's window;
+ * candidates of all runs with outputs form one list in (trial, time) order with dm_index
+ * the global trial and t the input sample where the binned sample starts. Returns
+ * DD_FILLING (nothing written, d_ncand untouched) while every run fills, DD_ERR_SEQUENCE
+ * for a wrong seq (nothing changes), DD_ERR_UNSUPPORTED for batched != 0 when the runs
+ * cannot share one batched launch (as dd_binned_dedisperse). Not thread-safe per stream.
+ */
+int dd_binned_stream_push(dd_binned_stream* s, const void* d_block, int64_t nsamp, int64_t in_row_stride, int64_t seq,
+                          float* d_out, int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma,
+                          dd_cand* d_cand, int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace,
+                          int64_t ws_bytes, void* stream, int64_t* t0_out, int64_t* nout_out);
+/* Zero-filled sequence gaps on every run, as dd_stream_set_gap_fill. */
+int dd_binned_stream_set_gap_fill(dd_binned_stream* s, int32_t enable);
+/* Free the host state (the ring is the caller's). NULL is a no-op. */
+void dd_binned_stream_destroy(dd_binned_stream* s);
 
 /*
  * Subband plan: subband dedispersion (Ch. 2 Sec. "Subband Dedispersion"), an approximation of
@@ -540,6 +588,26 @@ int dd_bandpass_fit(const double* avg, int32_t nchan, int32_t order, double* fit
 int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t row_stride, const double* d_fit,
                 double chan_threshold, int64_t window, const double* d_window_means, int32_t* d_flags,
                 double fit_mean, double spec_threshold, int32_t subtract_bandpass, void* stream);
+
+/*
+ * The same stage for 8-bit filterbanks (the codes of the serving beams). dd_bandpass_u8 is
+ * dd_bandpass over d_in [nchan][row_stride] uint8: its sums are exact integers, so each
+ * average and window mean is the exact sum divided once (FP64), in any summation order.
+ * dd_rfi_clip_u8 is dd_rfi_clip on d_data [nchan][row_stride] uint8 in place, with the
+ * replacement value of channel c the nearest code to fit[c] (halves away from zero),
+ * clamped to 0..255, and the spectrum means exact sums over channels divided by nchan. It
+ * makes no bandpass correction: an 8-bit sample cannot hold x - fit[c]. Subtracting a
+ * per-channel constant from every sample lowers every dedispersed sample (Eq.
+ * bruteEquation sums each channel once) by the same sum over channels of fit[c], which
+ * moves each series' mean and leaves its RMS and its n-sigma candidates as they are; a
+ * caller who wants the corrected values subtracts that constant from the outputs. Errors
+ * as dd_bandpass and dd_rfi_clip.
+ */
+int dd_bandpass_u8(const uint8_t* d_in, int64_t nchan, int64_t nsamp, int64_t row_stride, int64_t window,
+                   double* d_avg, double* d_window_means, void* stream);
+int dd_rfi_clip_u8(uint8_t* d_data, int64_t nchan, int64_t nsamp, int64_t row_stride, const double* d_fit,
+                   double chan_threshold, int64_t window, const double* d_window_means, int32_t* d_flags,
+                   double fit_mean, double spec_threshold, void* stream);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dd_last_error(void);

@@ -48,7 +48,8 @@ What it computes, in the paper's notation (Magro 2013, Ch. 2 and 3):
   mean deviates from the channel's fitted value by more than a threshold are flagged, and
   each flagged window and its neighbours take the fitted value; then every spectrum whose
   mean over channels deviates from the fit's mean by more than a threshold takes the
-  fitted bandpass.
+  fitted bandpass; last the fitted bandpass is subtracted from every spectrum. For 8-bit
+  codes the replacement is the nearest code of the fit and there is no subtraction.
 
 Pins (tests/test_oracle_pins.py): a literal triple loop on tiny inputs; exact
 rational delays (fractions.Fraction) away from ties; the paper's diagonal-DM
@@ -75,7 +76,10 @@ two delays.
 RFI mitigation (tests/test_oracle_rfi.py): a polynomial bandpass is fitted exactly with
 zero RMSE; a literal pure-Python loop over windows and spectra on tiny inputs; clean data
 under a high threshold is unchanged; a narrowband burst, a dropout and a broadband spike
-are replaced by the fitted bandpass and nothing else changes.
+are replaced by the fitted bandpass and nothing else changes. The 8-bit stage: literal
+integer loops; nearest-code rounding; equality with the float stage where the fit is
+integral; and the constant-offset identity (subtracting a per-channel constant lowers every
+dedispersed sample by its sum, leaving RMS and candidates) that lets it skip the correction.
 """
 from __future__ import annotations
 
@@ -509,6 +513,47 @@ def rfi_mitigate(data: np.ndarray, order: int, chan_threshold: float, window: in
         x = bandpass_correct(x, fit)
     return x, fit, rmse, fit_mean, cflags, sflags
 
+
+
+def fit_codes(fit) -> np.ndarray:
+    """The fitted bandpass as 8-bit codes: nearest integer, halves away from zero (the fit is
+    a power level, so halves round up), clamped to 0..255."""
+    f = np.asarray(fit, dtype=np.float64)
+    return np.clip(np.floor(f + 0.5), 0.0, 255.0).astype(np.uint8)
+
+
+def rfi_mitigate_codes(data: np.ndarray, order: int, chan_threshold: float, window: int, spec_threshold: float):
+    """The RFI stage on 8-bit codes (reading: the paper's replacement by the fitted bandpass,
+    with the replacement value the nearest code, since the samples stay 8-bit). The same fit,
+    channel and spectrum decisions as rfi_mitigate on the codes as numbers, the replaced
+    samples taking fit_codes(fit). No bandpass subtraction: an 8-bit sample cannot hold
+    x - fit, and since Eq. bruteEquation sums each channel once, subtracting fit[c] from
+    every sample of channel c lowers every dedispersed sample by sum(fit) and changes
+    neither RMS nor candidates (pinned by a test). Returns (codes uint8, fit, rmse,
+    fit_mean, channel flags, spectrum flags)."""
+    codes = np.asarray(data)
+    if codes.dtype != np.uint8:
+        raise ValueError("8-bit codes expected")
+    fit, rmse, fit_mean = bandpass_fit(bandpass_average(codes), order)
+    rep = fit_codes(fit).astype(np.float64)
+    x = codes.astype(np.float64)
+    cflags = sflags = None
+    if chan_threshold > 0:
+        nchan, n = x.shape
+        nwin = -(-n // window)
+        cflags = np.zeros((nchan, nwin), dtype=bool)
+        for w in range(nwin):
+            cflags[:, w] = np.abs(x[:, w * window:(w + 1) * window].mean(axis=1) - fit) > chan_threshold
+        spread = cflags.copy()
+        spread[:, 1:] |= cflags[:, :-1]
+        spread[:, :-1] |= cflags[:, 1:]
+        for c in range(nchan):
+            for w in np.nonzero(spread[c])[0]:
+                x[c, w * window:(w + 1) * window] = rep[c]
+    if spec_threshold > 0:
+        sflags = np.abs(x.mean(axis=0) - fit_mean) > spec_threshold
+        x[:, sflags] = rep[:, None]
+    return x.astype(np.uint8), fit, rmse, fit_mean, cflags, sflags
 
 def subband_dedisperse(data: np.ndarray, freq_mhz, tsamp_s: float, dm, chans_per_sub: int, dms_per_group: int):
     """Subband dedispersion (Sec. "Subband Dedispersion"). Subband s holds channels

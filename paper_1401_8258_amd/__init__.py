@@ -5,8 +5,9 @@ this package is its ctypes binding plus torch plumbing for device memory and
 streams.
 """
 from ._lib import LibraryMissing, DedispError, load as load_library  # noqa: F401
-from .api import (Plan, Stream, Result, CandidateOverflow, CAND_DTYPE, PULSE_DTYPE, batch_dedisperse, detrend, boxcar,
-                  boxcar_search, downfactor,  # noqa: F401
-                  time_binning, BinnedPlan, BinnedResult, bandpass, bandpass_fit, rfi_mitigate, SubbandPlan)
+from .api import (Plan, Stream, Result, CandidateOverflow, CAND_DTYPE, PULSE_DTYPE,  # noqa: F401
+                  batch_dedisperse, detrend, boxcar, boxcar_search, downfactor, time_binning,
+                  BinnedPlan, BinnedResult, BinnedStream, BinnedStreamResult, bandpass, bandpass_fit,
+                  rfi_mitigate, SubbandPlan)
 
-__version__ = "1.4"
+__version__ = "1.5"

@@ -28,7 +28,8 @@ class Tuning(C.Structure):
 
 class BinnedRun(C.Structure):
     _fields_ = [("log2", C.c_int32), ("d0", C.c_int32), ("d1", C.c_int32), ("maxdelay", C.c_int32),
-                ("nout", C.c_int64), ("kernel_form", C.c_int32), ("dms_per_wave", C.c_int32), ("waves", C.c_int32)]
+                ("nout", C.c_int64), ("kernel_form", C.c_int32), ("dms_per_wave", C.c_int32), ("waves", C.c_int32),
+                ("producer_waves", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -89,6 +90,12 @@ SIGNATURES = {
     "dd_binned_dedisperse": (C.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, _P, C.c_float, _P, _I64, _P, _I32, _P, _I64,
                                        _P]),
     "dd_binned_destroy": (None, [_P]),
+    "dd_binned_stream_query": (C.c_int, [_P, _I64, C.POINTER(_I64), C.POINTER(_I64)]),
+    "dd_binned_stream_create": (C.c_int, [_P, _I64, _P, _I64, _P, C.POINTER(_P)]),
+    "dd_binned_stream_push": (C.c_int, [_P, _P, _I64, _I64, _I64, _P, _I64, _P, _P, C.c_float, _P, _I64, _P, _I32,
+                                        _P, _I64, _P, C.POINTER(_I64), C.POINTER(_I64)]),
+    "dd_binned_stream_set_gap_fill": (C.c_int, [_P, _I32]),
+    "dd_binned_stream_destroy": (None, [_P]),
     "dd_subband_create": (C.c_int, [C.POINTER(_P), C.POINTER(_F64), _I32, _F64, C.POINTER(_F64), _I32, _I32, _I32]),
     "dd_subband_query": (C.c_int, [_P, _I64, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32),
                                    C.POINTER(_I32)]),
@@ -103,6 +110,8 @@ SIGNATURES = {
     "dd_bandpass_fit": (C.c_int, [_P, _I32, _I32, _P, _P, _P]),
     "dd_rfi_clip": (C.c_int, [_P, _I64, _I64, _I64, _P, C.c_double, _I64, _P, _P, C.c_double, C.c_double, _I32,
                               _P]),
+    "dd_bandpass_u8": (C.c_int, [_P, _I64, _I64, _I64, _I64, _P, _P, _P]),
+    "dd_rfi_clip_u8": (C.c_int, [_P, _I64, _I64, _I64, _P, C.c_double, _I64, _P, _P, C.c_double, C.c_double, _P]),
     "dd_stream_set_gap_fill": (C.c_int, [_P, _I32]),
     "dd_candidates_check": (C.c_int, [_P, _I64, _P, C.POINTER(_I64)]),
     "dd_last_error": (C.c_char_p, []),

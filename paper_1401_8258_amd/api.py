@@ -561,9 +561,18 @@ class BinnedPlan(_Composite):
         for r in runs:
             k, d0, d1 = int(r.log2), int(r.d0), int(r.d1)
             self.log2[d0:d1] = k
-            # the run's plan on the host, for its delay table and maximum delay
+            # the run's plan on the host, with the form and tiles the library chose for it, for
+            # its delay table, maximum delay and launch shape
+            kf = int(r.kernel_form)
+            if kf == _lib.DD_FORM_DIRECT:
+                t, f = (int(r.dms_per_wave), int(r.waves)), "direct"
+            elif kf == _lib.DD_FORM_REGWIN:
+                t, f = None, "regwin"
+            else:
+                t, f = (int(r.dms_per_wave), int(r.waves), 0,
+                        int(r.producer_waves) if r.producer_waves > 0 else -1), "lds"
             host = Plan(self.freq, self.tsamp * float(1 << k), self.dm[d0:d1], self.dtype if k == 0 else torch.float32,
-                        tuning if (k == 0 or form != "direct") else None, form if (k == 0 or form != "direct") else "auto")
+                        t, f)
             self.segments.append(BinnedSegment(k, d0, d1, host))
 
     def nout(self, nsamp: int):
@@ -572,6 +581,26 @@ class BinnedPlan(_Composite):
 
     def adds(self, nsamp: int) -> int:
         return sum((s.d1 - s.d0) * s.plan.nchan * n for s, n in zip(self.segments, self.nout(nsamp)))
+
+    @property
+    def batchable(self) -> bool:
+        """Whether the runs can share one batched call: the LDS-form runs need one input
+        dtype, DM trials per workgroup and producer count (direct-read runs join any)."""
+        keys = {(s.plan.dtype, s.plan.tiles[1], s.plan.producer_waves) for s in self.segments
+                if s.plan.form != "direct"}
+        return len(keys) <= 1 and all(s.plan.form != "regwin" for s in self.segments)
+
+    @property
+    def fill_nsamp(self) -> int:
+        """Input samples a stream needs before every run emits: max over runs of
+        (maxdelay + 1) << log2."""
+        return max((s.plan.maxdelay + 1) << s.log2 for s in self.segments)
+
+    def stream_sizes(self, block_nsamp: int):
+        """(ring bytes, workspace bytes) of a BinnedStream of block_nsamp-sample blocks."""
+        rb, wb = C.c_int64(), C.c_int64()
+        check(self._lib.dd_binned_stream_query(self._h, int(block_nsamp), C.byref(rb), C.byref(wb)))
+        return int(rb.value), int(wb.value)
 
     def workspace(self, nsamp: int, device=None, stream=None) -> torch.Tensor:
         """A device workspace for nsamp-sample inputs with every run's delay table (cached)."""
@@ -617,18 +646,111 @@ class BinnedPlan(_Composite):
             pass
 
 
+
+@dataclasses.dataclass
+class BinnedStreamResult:
+    segments: list     # [(BinnedSegment, t0, Result or None)]: None while that run fills; t0 and the
+                       # candidates' t in the run's own samples (input samples >> log2)
+    merged: Result     # the [ndm][block] output and the merged candidate list (t in input samples)
+
+    def candidates(self) -> Optional[np.ndarray]:
+        return self.merged.candidates()
+
+
+class BinnedStream:
+    """A beam's stream over a time-binned plan (dd_binned_stream): each run keeps a ring of
+    the input downfactored 2^log2 times, so the long delays of the high DMs are held at
+    their binned sampling time. Blocks must be multiples of 2^K samples (K the largest
+    log2)."""
+
+    def __init__(self, plan: BinnedPlan, block_nsamp: int, device=None, stream=None, gap_fill: bool = False):
+        self.plan = plan
+        self._lib = plan._lib
+        self.block = int(block_nsamp)
+        device = torch.device(device if device is not None else "cuda")
+        self.device = device
+        self.ring_bytes, ws_bytes = plan.stream_sizes(self.block)
+        self.batchable = plan.batchable
+        self.ring = torch.empty(max(self.ring_bytes, 1), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        check(self._lib.dd_binned_stream_create(plan._h, self.block, _vp(self.ring), int(self.ring.numel()),
+                                                _stream(stream), C.byref(h)))
+        self._h = h
+        self.seq = 0
+        if gap_fill:
+            check(self._lib.dd_binned_stream_set_gap_fill(h, 1))
+
+    def push(self, block: torch.Tensor, k_sigma: float = 0.0, cand_cap: int = 1 << 14, stats: bool = True,
+             out: Optional[torch.Tensor] = None, stream=None, seq: Optional[int] = None,
+             batched: bool = False, outputs=None) -> Optional[BinnedStreamResult]:
+        """Append a block; returns each run's newly computable outputs, or None while every
+        run fills. seq defaults to the next in order. ``outputs`` optionally gives buffers
+        from alloc_outputs(ndm, block, ...) to write into (``out`` then is ignored)."""
+        if seq is not None:
+            self.seq = int(seq)
+        bp = self.plan
+        if block.dim() != 2 or block.shape[0] != bp.freq.size or block.dtype != bp.dtype or block.stride(1) != 1:
+            raise ValueError("block must be [nchan][n] of the plan dtype, time contiguous")
+        dev = block.device
+        ndm = bp.dm.size
+        if outputs is not None:
+            out, mean, rms, cand, ncand = outputs
+            if ncand is not None:
+                cand_cap = cand.numel() // CAND_DTYPE.itemsize
+        else:
+            if out is None:
+                out = torch.empty((ndm, self.block), dtype=torch.float32, device=dev)
+            _, mean, rms, cand, ncand = _outputs(ndm, 1, dev, k_sigma, cand_cap, stats)
+        nr = len(bp.segments)
+        t0 = (C.c_int64 * nr)()
+        n = (C.c_int64 * nr)()
+        rc = check(self._lib.dd_binned_stream_push(
+            self._h, _vp(block), int(block.shape[1]), int(block.stride(0)), self.seq, _vp(out), int(out.stride(0)),
+            _vp(mean), _vp(rms), float(k_sigma), _vp(cand), int(cand_cap if cand is not None else 0), _vp(ncand),
+            1 if batched else 0, _vp(self.ws), int(self.ws.numel()), _stream(stream), t0, n),
+            (_lib.DD_OK, _lib.DD_FILLING))
+        self.seq += 1
+        if rc == _lib.DD_FILLING:
+            return None
+        merged = Result(out, mean, rms, 0, cand, ncand, cand_cap)
+        parts = []
+        for i, seg in enumerate(bp.segments):
+            if n[i] == 0:
+                parts.append((seg, 0, None))
+                continue
+            r = _PartResult(merged, out[seg.d0:seg.d1, :n[i]], mean[seg.d0:seg.d1] if mean is not None else None,
+                            rms[seg.d0:seg.d1] if rms is not None else None, seg.d0, seg.d1, seg.log2)
+            r.t0 = int(t0[i])
+            parts.append((seg, int(t0[i]), r))
+        return BinnedStreamResult(parts, merged)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dd_binned_stream_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 def bandpass(x: torch.Tensor, window: int = 0, stream=None):
-    """The averaged bandpass (dd_bandpass): each channel's mean, [nchan] float64 on the device.
-    With window >= 1 also the means of every window of that many samples, [nchan][nwin]
-    float64 (returned as a second tensor): the channel stage's statistic, from the same read."""
-    if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda or x.stride(1) != 1:
-        raise ValueError("x must be a [nchan][nsamp] float32 device tensor, time contiguous")
+    """The averaged bandpass (dd_bandpass, dd_bandpass_u8 for 8-bit codes): each channel's
+    mean, [nchan] float64 on the device. With window >= 1 also the means of every window of
+    that many samples, [nchan][nwin] float64 (returned as a second tensor): the channel
+    stage's statistic, from the same read."""
+    if x.dim() != 2 or x.dtype not in (torch.float32, torch.uint8) or not x.is_cuda or x.stride(1) != 1:
+        raise ValueError("x must be a [nchan][nsamp] float32 or uint8 device tensor, time contiguous")
     avg = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
     means = None
     if window:
         means = torch.empty((x.shape[0], -(-int(x.shape[1]) // int(window))), dtype=torch.float64, device=x.device)
-    check(_lib.load().dd_bandpass(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), int(window), _vp(avg),
-                                  _vp(means), _stream(stream)))
+    lib = _lib.load()
+    fn = lib.dd_bandpass_u8 if x.dtype == torch.uint8 else lib.dd_bandpass
+    check(fn(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), int(window), _vp(avg), _vp(means),
+             _stream(stream)))
     return (avg, means) if window else avg
 
 
@@ -645,13 +767,22 @@ def bandpass_fit(avg, order: int):
 
 
 def rfi_mitigate(x: torch.Tensor, order: int, chan_threshold: float, window: int, spec_threshold: float,
-                 subtract: bool = True, stream=None):
-    """RFI mitigation in place on a [nchan][nsamp] float32 device filterbank (Ch. 3): the
-    averaged bandpass on the device, its polynomial fit on the host (the nchan averages
+                 subtract: Optional[bool] = None, stream=None):
+    """RFI mitigation in place on a [nchan][nsamp] float32 or uint8 device filterbank (Ch. 3):
+    the averaged bandpass on the device, its polynomial fit on the host (the nchan averages
     cross PCIe, as in the paper), then channel and spectrum thresholding and the bandpass
-    correction (dd_rfi_clip). Thresholds are absolute deviations from the fit; <= 0 skips a
-    stage. With subtract the fitted bandpass is subtracted from every spectrum. Returns
-    (fit, rmse, fit_mean, channel flags [nchan][nwin] int32 device tensor or None)."""
+    correction (dd_rfi_clip, dd_rfi_clip_u8). Thresholds are absolute deviations from the
+    fit; <= 0 skips a stage. With subtract (the default for float32) the fitted bandpass is
+    subtracted from every spectrum. 8-bit codes take the nearest code of the fit where
+    replaced and cannot be corrected in place (subtract must be false): the correction is
+    then the constant -sum(fit) on every dedispersed sample. Returns (fit, rmse, fit_mean,
+    channel flags [nchan][nwin] int32 device tensor or None)."""
+    u8 = x.dtype == torch.uint8
+    if subtract is None:
+        subtract = not u8
+    if u8 and subtract:
+        raise ValueError("8-bit codes cannot hold the corrected values; subtract sum(fit) from the dedispersed "
+                         "series instead")
     chan = chan_threshold > 0
     if chan:
         avg_d, means = bandpass(x, int(window), stream)
@@ -662,9 +793,15 @@ def rfi_mitigate(x: torch.Tensor, order: int, chan_threshold: float, window: int
     flags = None
     if chan:
         flags = torch.empty(means.shape, dtype=torch.int32, device=x.device)
-    check(_lib.load().dd_rfi_clip(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), _vp(d_fit),
-                                  float(chan_threshold), int(window), _vp(means), _vp(flags), float(fmean),
-                                  float(spec_threshold), int(bool(subtract)), _stream(stream)))
+    lib = _lib.load()
+    if u8:
+        check(lib.dd_rfi_clip_u8(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), _vp(d_fit),
+                                 float(chan_threshold), int(window), _vp(means), _vp(flags), float(fmean),
+                                 float(spec_threshold), _stream(stream)))
+    else:
+        check(lib.dd_rfi_clip(_vp(x), int(x.shape[0]), int(x.shape[1]), int(x.stride(0)), _vp(d_fit),
+                              float(chan_threshold), int(window), _vp(means), _vp(flags), float(fmean),
+                              float(spec_threshold), int(bool(subtract)), _stream(stream)))
     return fit, rmse, fmean, flags
 
 

@@ -1205,6 +1205,7 @@ struct MergedRun {
   int64_t stride, nout;
   const double* stat;   // [ndm][3] from the run's statistics
   int32_t ndm, d0, shift;
+  int64_t t_base = 0;   // candidate t = t_base + (output index << shift)
 };
 
 int64_t merged_cand_bytes(const std::vector<MergedRun>& runs) {
@@ -1239,6 +1240,7 @@ int merged_candidates(const std::vector<MergedRun>& runs, float k, dd_cand* cand
     t.unit0 = u0;
     t.d_base = r.d0;
     t.t_shift = r.shift;
+    t.t_base = r.t_base;
     u0 += (int64_t)r.ndm * t.nseg;
     items.push_back(t);
   }
@@ -1771,21 +1773,41 @@ int dd_binned_create(dd_binned** out, const double* freq_mhz, int32_t nchan, dou
   b->max_log2 = max_log2;
   b->tsamp = tsamp_s;
   b->dm_diag = diag;
-  // runs with k >= 1 read FP32 sums; a tuning of the 8-bit direct-read form applies to the
-  // factor-1 run only
-  const bool direct = tuning && tuning->kernel_form == DD_FORM_DIRECT;
+  // Runs with k >= 1 read FP32 sums. Which runs a tuning applies to:
+  //  * DD_FORM_DIRECT: the factor-1 run only (8-bit input);
+  //  * DD_FORM_LDS or DD_FORM_REGWIN: every run;
+  //  * DD_FORM_AUTO with tile fields: every FP32 run, and an 8-bit factor-1 run keeps the
+  //    direct-read form (the tiles are LDS-form tiles; an 8-bit LDS factor-1 run could not
+  //    share a batched call with the FP32 runs anyway).
+  // Without a tuning each run takes the planner's tiles for its own trials: a common tiling
+  // that every run can take (fewer trials per workgroup for the runs at small factors, whose
+  // DM groups spread over more samples) was slower on the 4096-channel beams than separate
+  // launches on each run's own tiles.
+  const int form = tuning ? tuning->kernel_form : DD_FORM_AUTO;
+  const bool u8_direct0 = in_dtype == DD_U8 && (form == DD_FORM_DIRECT || form == DD_FORM_AUTO);
+  std::vector<std::pair<int32_t, int32_t>> spans;
   for (int32_t d0 = 0, d = 1; d <= ndm; ++d) {
     if (d < ndm && lg[d] == lg[d0]) continue;
+    spans.push_back({d0, d});
+    d0 = d;
+  }
+  auto make = [&](int32_t d0, int32_t d1, const dd_tuning* t, dd_plan** p) {
     const int32_t k = lg[d0];
+    return dd_plan_create(p, freq_mhz, nchan, tsamp_s * (double)(1 << k), dm + d0, d1 - d0,
+                          k == 0 ? in_dtype : DD_F32, t);
+  };
+  auto tuning_for = [&](int32_t k) -> const dd_tuning* {
+    if (k == 0) return u8_direct0 && form == DD_FORM_AUTO ? nullptr : tuning;
+    return form == DD_FORM_DIRECT ? nullptr : tuning;
+  };
+  for (const auto& sp : spans) {
     dd_plan* p = nullptr;
-    rc = dd_plan_create(&p, freq_mhz, nchan, tsamp_s * (double)(1 << k), dm + d0, d - d0, k == 0 ? in_dtype : DD_F32,
-                        k == 0 || !direct ? tuning : nullptr);
+    rc = make(sp.first, sp.second, tuning_for(lg[sp.first]), &p);
     if (rc) {
       delete b;
       return rc;
     }
-    b->runs.push_back(dd_binned::Run{k, d0, d, p});
-    d0 = d;
+    b->runs.push_back(dd_binned::Run{lg[sp.first], sp.first, sp.second, p});
   }
   *out = b;
   return DD_OK;
@@ -1811,6 +1833,7 @@ int dd_binned_query(const dd_binned* b, int64_t nsamp, int32_t* nruns, dd_binned
       o.kernel_form = r.plan->launch.form;
       o.dms_per_wave = r.plan->tiles.g;
       o.waves = r.plan->tiles.w;
+      o.producer_waves = r.plan->launch.prod;
       runs[i] = o;
     }
   }
@@ -1915,6 +1938,273 @@ int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, in
     }
     rc = merged_candidates(mr, k_sigma, d_cand, cand_cap, d_ncand, ws + L.cand_off, st);
     if (rc) return rc;
+  }
+  return DD_OK;
+}
+
+// ------------------------------------------------------------------ time-binned streams
+
+}  // extern "C"
+
+// A stream over a time-binned plan: one ordinary stream per run, run k's ring holding the
+// input downfactored k times (block_nsamp >> k samples per block), so every run keeps only
+// its own maxdelay at its own sampling time.
+struct dd_binned_stream {
+  const dd_binned* b = nullptr;
+  int64_t block = 0;
+  int32_t kmax = 0;
+  std::vector<dd_stream*> runs;
+  ~dd_binned_stream() {
+    for (dd_stream* s : runs) dd_stream_destroy(s);
+  }
+};
+
+namespace {
+
+int binned_kmax(const dd_binned* b) {
+  int k = 0;
+  for (const dd_binned::Run& r : b->runs) k = std::max(k, r.k);
+  return k;
+}
+
+// Ring of a binned stream: each run's stream ring (its delay table first), 256-byte aligned.
+int64_t binned_ring_layout(const dd_binned* b, int64_t block, std::vector<int64_t>* off) {
+  int64_t o = 0;
+  for (const dd_binned::Run& r : b->runs) {
+    dd_plan_info info;
+    dd_plan_query(r.plan, block >> r.k, &info);
+    if (off) off->push_back(o);
+    o += dd::align_up(info.ring_bytes);
+  }
+  dd::clear_error();
+  return o;
+}
+
+// Workspace of one push: the downfactored block (levels 1 .. K), each run's stream
+// workspace, the batch descriptors and the merged candidate region.
+struct BinnedStreamLayout {
+  int64_t level_off[17] = {0}, level_row[17] = {0};
+  std::vector<int64_t> run_off;
+  std::vector<dd::WsLayout> run_l;
+  int64_t batch_off = 0, cand_off = 0, total = 0;
+};
+
+BinnedStreamLayout binned_stream_layout(const dd_binned* b, int64_t block) {
+  BinnedStreamLayout L;
+  int64_t o = 0;
+  const int kmax = binned_kmax(b);
+  for (int k = 1; k <= kmax; ++k) {
+    L.level_row[k] = dd::align_up(block >> k, 64);
+    L.level_off[k] = o;
+    o += dd::align_up((int64_t)b->nchan * L.level_row[k] * 4);
+  }
+  std::vector<MergedRun> mr;
+  for (const dd_binned::Run& r : b->runs) {
+    const dd::WsLayout l = dd::workspace_layout(r.plan, block >> r.k, false);
+    L.run_off.push_back(o);
+    L.run_l.push_back(l);
+    o += dd::align_up(l.total);
+    mr.push_back(MergedRun{nullptr, 0, block >> r.k, nullptr, r.d1 - r.d0, r.d0, r.k});
+  }
+  std::vector<dd_batch_item> none((size_t)b->runs.size());
+  int64_t bq = 0;
+  dd_batch_query(none.data(), (int32_t)none.size(), &bq);
+  L.batch_off = o;
+  o += dd::align_up(bq);
+  L.cand_off = o;
+  o += merged_cand_bytes(mr);
+  L.total = o;
+  return L;
+}
+
+// The batched path's condition on LDS-form runs (shared dtype, trials per workgroup and
+// producer count), checked before anything is appended.
+bool binned_batchable(const dd_binned* b) {
+  const dd_plan* first = nullptr;
+  for (const dd_binned::Run& r : b->runs) {
+    const dd_plan* p = r.plan;
+    if (p->launch.form == dd::kFormRegWin) return false;
+    if (p->launch.form == dd::kFormDirect) continue;
+    if (!first) first = p;
+    if (p->dtype != first->dtype || p->tiles.w != first->tiles.w || p->launch.prod != first->launch.prod)
+      return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dd_binned_stream_query(const dd_binned* b, int64_t block_nsamp, int64_t* ring_bytes, int64_t* workspace_bytes) {
+  dd::clear_error();
+  if (ring_bytes) *ring_bytes = 0;
+  if (workspace_bytes) *workspace_bytes = 0;
+  if (!b) return dd::fail(DD_ERR_INVALID_ARG, "plan is NULL");
+  const int kmax = binned_kmax(b);
+  if (block_nsamp < (1 << kmax) || block_nsamp % (1 << kmax) != 0)
+    return dd::fail(DD_ERR_INVALID_ARG, "block_nsamp must be a positive multiple of " + std::to_string(1 << kmax) +
+                                            " (the largest binning factor)");
+  if (ring_bytes) *ring_bytes = binned_ring_layout(b, block_nsamp, nullptr);
+  if (workspace_bytes) *workspace_bytes = binned_stream_layout(b, block_nsamp).total;
+  return DD_OK;
+}
+
+int dd_binned_stream_create(const dd_binned* b, int64_t block_nsamp, void* d_ring, int64_t ring_bytes, void* stream,
+                            dd_binned_stream** out) {
+  dd::clear_error();
+  if (!out) return dd::fail(DD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!b || !d_ring) return dd::fail(DD_ERR_INVALID_ARG, "plan and ring must be non-NULL");
+  int64_t need = 0;
+  int rc = dd_binned_stream_query(b, block_nsamp, &need, nullptr);
+  if (rc) return rc;
+  if (ring_bytes < need) return dd::fail(DD_ERR_WORKSPACE, "ring smaller than dd_binned_stream_query asks for");
+  std::vector<int64_t> off;
+  binned_ring_layout(b, block_nsamp, &off);
+  dd_binned_stream* s = new (std::nothrow) dd_binned_stream();
+  if (!s) return dd::fail(DD_ERR_INVALID_ARG, "out of host memory");
+  s->b = b;
+  s->block = block_nsamp;
+  s->kmax = binned_kmax(b);
+  for (size_t i = 0; i < b->runs.size(); ++i) {
+    const dd_binned::Run& r = b->runs[i];
+    dd_plan_info info;
+    dd_plan_query(r.plan, block_nsamp >> r.k, &info);
+    dd_stream* rs = nullptr;
+    rc = dd_stream_create(r.plan, block_nsamp >> r.k, static_cast<char*>(d_ring) + off[i], info.ring_bytes, stream,
+                          &rs);
+    if (rc) {
+      delete s;
+      return rc;
+    }
+    s->runs.push_back(rs);
+  }
+  *out = s;
+  return DD_OK;
+}
+
+void dd_binned_stream_destroy(dd_binned_stream* s) { delete s; }
+
+int dd_binned_stream_set_gap_fill(dd_binned_stream* s, int32_t enable) {
+  dd::clear_error();
+  if (!s) return dd::fail(DD_ERR_INVALID_ARG, "stream is NULL");
+  for (dd_stream* r : s->runs) r->gap_fill = enable != 0;
+  return DD_OK;
+}
+
+int dd_binned_stream_push(dd_binned_stream* s, const void* d_block, int64_t nsamp, int64_t in_row_stride, int64_t seq,
+                          float* d_out, int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma,
+                          dd_cand* d_cand, int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace,
+                          int64_t ws_bytes, void* stream, int64_t* t0_out, int64_t* nout_out) {
+  dd::clear_error();
+  if (!s) return dd::fail(DD_ERR_INVALID_ARG, "stream is NULL");
+  const dd_binned* b = s->b;
+  const size_t nr = b->runs.size();
+  for (size_t i = 0; i < nr; ++i) {
+    if (t0_out) t0_out[i] = 0;
+    if (nout_out) nout_out[i] = 0;
+  }
+  if (!d_block || !d_workspace) return dd::fail(DD_ERR_INVALID_ARG, "block and workspace must be non-NULL");
+  if (nsamp < 1 || nsamp > s->block) return dd::fail(DD_ERR_INVALID_ARG, "block size out of range");
+  if (nsamp % (1 << s->kmax) != 0)
+    return dd::fail(DD_ERR_INVALID_ARG, "nsamp must be a multiple of " + std::to_string(1 << s->kmax) +
+                                            " (the largest binning factor)");
+  if (in_row_stride < nsamp) return dd::fail(DD_ERR_INVALID_ARG, "in_row_stride < nsamp");
+  int rc = check_outputs(b->runs[0].plan, d_out, out_row_stride, s->block, d_mean, d_rms, k_sigma, d_cand, cand_cap,
+                         d_ncand);
+  if (rc) return rc;
+  const BinnedStreamLayout L = binned_stream_layout(b, s->block);
+  if (ws_bytes < L.total) return dd::fail(DD_ERR_WORKSPACE, "workspace smaller than dd_binned_stream_query asks for");
+  // every run's stream expects the same seq; checked once, before anything is enqueued
+  const dd_stream* s0 = s->runs[0];
+  if (seq != s0->next_seq && !(s0->gap_fill && seq > s0->next_seq))
+    return dd::fail(DD_ERR_SEQUENCE, "expected seq " + std::to_string(s0->next_seq) + ", got " + std::to_string(seq));
+  if (batched && !binned_batchable(b))
+    return dd::fail(DD_ERR_UNSUPPORTED, "batched runs need LDS-form runs that share the input dtype, the DM trials "
+                                        "per workgroup and the producer wavefront count");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(d_workspace);
+  // the block downfactored 1 .. K times; blocks are multiples of 2^K samples, so no pair of
+  // samples straddles two blocks and each level equals the whole stream's downfactored input
+  std::vector<const void*> level_ptr((size_t)s->kmax + 1, d_block);
+  std::vector<int64_t> level_stride((size_t)s->kmax + 1, in_row_stride);
+  for (int k = 1; k <= s->kmax; ++k) {
+    float* dst = reinterpret_cast<float*>(ws + L.level_off[k]);
+    rc = dd_downfactor(level_ptr[k - 1], k == 1 ? b->dtype : DD_F32, b->nchan, nsamp >> (k - 1),
+                       level_stride[k - 1], dst, L.level_row[k], stream);
+    if (rc) return rc;
+    level_ptr[k] = dst;
+    level_stride[k] = L.level_row[k];
+  }
+  std::vector<int64_t> t0((size_t)nr, 0), n((size_t)nr, 0);
+  bool any = false;
+  for (size_t i = 0; i < nr; ++i) {
+    const int k = b->runs[i].k;
+    rc = dd_stream_append(s->runs[i], level_ptr[k], nsamp >> k, level_stride[k], seq, stream, &t0[i], &n[i]);
+    if (rc == DD_FILLING) {
+      n[i] = 0;
+      continue;
+    }
+    if (rc) {
+      for (dd_stream* r : s->runs) r->pending_n = 0;
+      return rc;
+    }
+    any = true;
+  }
+  if (!any) return DD_FILLING;
+  const bool stats = d_mean && d_rms;
+  if (batched) {
+    std::vector<dd_batch_item> items;
+    for (size_t i = 0; i < nr; ++i) {
+      if (n[i] == 0) continue;
+      const dd_binned::Run& r = b->runs[i];
+      dd_batch_item it{};
+      it.d_out = d_out + (int64_t)r.d0 * out_row_stride;
+      it.out_row_stride = out_row_stride;
+      it.d_mean = stats ? d_mean + r.d0 : nullptr;
+      it.d_rms = stats ? d_rms + r.d0 : nullptr;
+      it.k_sigma = k_sigma;  // thresholds for the merged pass; no candidate buffers here
+      it.d_plan_workspace = ws + L.run_off[i];
+      it.stream_item = s->runs[i];
+      items.push_back(it);
+    }
+    rc = dd_batch_dedisperse(items.data(), (int32_t)items.size(), ws + L.batch_off, L.cand_off - L.batch_off, stream);
+  } else {
+    for (size_t i = 0; i < nr && rc == DD_OK; ++i) {
+      if (n[i] == 0) continue;
+      const dd_binned::Run& r = b->runs[i];
+      dd_stream* rs = s->runs[i];
+      const dd_plan* p = r.plan;
+      const InView in{static_cast<char*>(rs->ring) + dd::ring_table_bytes(p), rs->ring_row, n[i] + p->maxdelay,
+                      rs->ring_len, t0[i]};
+      const Outputs o{d_out + (int64_t)r.d0 * out_row_stride, out_row_stride, stats ? d_mean + r.d0 : nullptr,
+                      stats ? d_rms + r.d0 : nullptr, k_sigma, nullptr, 0, nullptr, t0[i]};
+      rc = run_pipeline(p, in, static_cast<const int32_t*>(rs->ring), n[i], o, ws + L.run_off[i], L.run_l[i], st,
+                        true);
+      rs->pending_n = 0;
+    }
+  }
+  if (rc) {
+    for (dd_stream* r : s->runs) r->pending_n = 0;
+    return rc;
+  }
+  if (stats && k_sigma > 0.f && d_ncand) {
+    std::vector<MergedRun> mr;
+    for (size_t i = 0; i < nr; ++i) {
+      if (n[i] == 0) continue;
+      const dd_binned::Run& r = b->runs[i];
+      MergedRun m{d_out + (int64_t)r.d0 * out_row_stride, out_row_stride, n[i],
+                  reinterpret_cast<const double*>(ws + L.run_off[i] + L.run_l[i].thr_off), r.d1 - r.d0, r.d0, r.k};
+      m.t_base = t0[i] << r.k;
+      mr.push_back(m);
+    }
+    rc = merged_candidates(mr, k_sigma, d_cand, cand_cap, d_ncand, ws + L.cand_off, st);
+    if (rc) return rc;
+  }
+  for (size_t i = 0; i < nr; ++i) {
+    if (t0_out) t0_out[i] = t0[i];
+    if (nout_out) nout_out[i] = n[i];
   }
   return DD_OK;
 }

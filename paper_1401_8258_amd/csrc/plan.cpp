@@ -309,7 +309,7 @@ extern "C" {
 
 const char* dd_last_error(void) { return g_err.c_str(); }
 
-const char* dd_version(void) { return "1.4"; }
+const char* dd_version(void) { return "1.5"; }
 
 int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
                    const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning) {

@@ -1,6 +1,8 @@
 // RFI mitigation of a filterbank before dedispersion (Ch. 3 Sec. "Bandpass Correction",
 // "Channel Thresholding", "Spectrum Thresholding"). C-ABI entry points dd_bandpass,
-// dd_bandpass_fit (host) and dd_rfi_clip.
+// dd_bandpass_fit (host) and dd_rfi_clip for FP32 filterbanks; dd_bandpass_u8 and
+// dd_rfi_clip_u8 for 8-bit codes (exact integer sums, replacement by the nearest code of
+// the fit, no in-place correction: an 8-bit sample cannot hold x - fit).
 //
 // * bandpass_rows: one workgroup per channel sums the channel's samples in FP64 (fixed
 //   order: per thread over strided samples, a butterfly per wavefront, the four wavefronts
@@ -227,6 +229,117 @@ __global__ __launch_bounds__(kRfiThreads) void spec_clip(float* __restrict__ x, 
       for (int64_t c = 0; c < nchan; ++c) x[c * stride + t0 + i] = subtract ? 0.f : (float)fit[c];
 }
 
+// ---- 8-bit codes. Sums of codes are exact integers, so every channel, window and spectrum
+// mean is the exact sum divided once in FP64, whatever the order of the additions; the
+// replacement value is the fitted bandpass rounded to the nearest code (halves away from
+// zero) and clamped to 0..255.
+
+__device__ __forceinline__ uint8_t fit_code(double f) {
+  const double r = floor(f + 0.5);
+  return (uint8_t)(r < 0.0 ? 0.0 : (r > 255.0 ? 255.0 : r));
+}
+
+// Sum of bytes [a, a + len) of a row: 16-byte loads (four v_sad_u8 each) where the span is
+// 16-byte aligned, single bytes at its ragged ends; lanes strided by 64 chunks.
+__device__ __forceinline__ uint64_t row_bytes_sum(const uint8_t* __restrict__ row, int64_t a, int64_t len,
+                                                  int lane) {
+  const uint8_t* p = row + a;
+  int64_t head = (int64_t)((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15);
+  if (head > len) head = len;
+  const int64_t nv = (len - head) / 16;
+  uint64_t s = 0;
+  if (lane < head) s += p[lane];
+  const uint4* v = reinterpret_cast<const uint4*>(p + head);
+  for (int64_t i = lane; i < nv; i += 64) {
+    const uint4 q = v[i];
+    unsigned acc = __builtin_amdgcn_sad_u8(q.x, 0u, 0u);
+    acc = __builtin_amdgcn_sad_u8(q.y, 0u, acc);
+    acc = __builtin_amdgcn_sad_u8(q.z, 0u, acc);
+    acc = __builtin_amdgcn_sad_u8(q.w, 0u, acc);
+    s += acc;
+  }
+  for (int64_t i = head + 16 * nv + lane; i < len; i += 64) s += p[i];
+  return s;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// blockIdx.x = channel; wavefront k takes windows k, k + 4, ... (window = n with no window
+// means); the channel mean is its exact total over n.
+__global__ __launch_bounds__(kRfiThreads) void bandpass_windows_u8(const uint8_t* __restrict__ x, int64_t n,
+                                                                   int64_t stride, int64_t window, int64_t nwin,
+                                                                   double* __restrict__ avg,
+                                                                   double* __restrict__ means) {
+  __shared__ uint64_t red[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint8_t* row = x + (int64_t)blockIdx.x * stride;
+  uint64_t tot = 0;
+  for (int64_t w = wv; w < nwin; w += 4) {
+    const int64_t t0 = w * window;
+    const int64_t len = n - t0 < window ? n - t0 : window;
+    const uint64_t ws = wave_sum_u64(row_bytes_sum(row, t0, len, lane));
+    tot += ws;
+    if (means && lane == 0) means[(int64_t)blockIdx.x * nwin + w] = (double)ws / (double)len;
+  }
+  if (lane == 0) red[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) avg[blockIdx.x] = (double)(red[0] + red[1] + red[2] + red[3]) / (double)n;
+}
+
+// One lane per (channel, window), as chan_apply, writing the fitted code.
+__global__ __launch_bounds__(kRfiThreads) void chan_apply_u8(uint8_t* __restrict__ x, int64_t n, int64_t stride,
+                                                             int64_t window, int64_t nwin,
+                                                             const double* __restrict__ fit,
+                                                             const int32_t* __restrict__ flags) {
+  const int64_t w = (int64_t)blockIdx.x * kRfiThreads + threadIdx.x;
+  if (w >= nwin) return;
+  const int64_t c = blockIdx.y;
+  if (!replaced(flags + c * nwin, w, nwin)) return;
+  const int64_t t0 = w * window;
+  const int64_t len = n - t0 < window ? n - t0 : window;
+  const uint8_t v = fit_code(fit[c]);
+  uint8_t* row = x + c * stride + t0;
+  for (int64_t i = 0; i < len; ++i) row[i] = v;
+}
+
+// Each lane takes 16 consecutive samples (one 16-byte load per channel when every row start
+// is aligned, so a wavefront reads 1 KB of a channel at once) and sums their spectra over
+// channels in exact integers; a spectrum whose mean is further than the threshold from the
+// fit's mean takes the fitted codes.
+__global__ __launch_bounds__(kRfiThreads) void spec_clip_u8(uint8_t* __restrict__ x, int64_t nchan, int64_t n,
+                                                            int64_t stride, const double* __restrict__ fit,
+                                                            double center, double thr) {
+  const int64_t t0 = ((int64_t)blockIdx.x * kRfiThreads + threadIdx.x) * 16;
+  if (t0 >= n) return;
+  unsigned s[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s[i] = 0;
+  const bool vec = t0 + 15 < n && (stride & 15) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  if (vec) {
+    for (int64_t c = 0; c < nchan; ++c) {
+      const uint4 q = *reinterpret_cast<const uint4*>(x + c * stride + t0);
+      const unsigned w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) s[4 * j + b] += (w4[j] >> (8 * b)) & 0xffu;
+    }
+  } else {
+    for (int64_t c = 0; c < nchan; ++c)
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (t0 + i < n) s[i] += x[c * stride + t0 + i];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (t0 + i < n && fabs((double)s[i] / (double)nchan - center) > thr)
+      for (int64_t c = 0; c < nchan; ++c) x[c * stride + t0 + i] = fit_code(fit[c]);
+}
+
 hipError_t launched(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) dd::fail(DD_ERR_HIP, std::string(what) + " launch: " + hipGetErrorString(e));
@@ -334,6 +447,54 @@ extern "C" int dd_rfi_clip(float* d_data, int64_t nchan, int64_t nsamp, int64_t 
     hipLaunchKernelGGL(spec_clip, dim3((unsigned)tblocks), dim3(kRfiThreads), 0, st, d_data, nchan, nsamp, row_stride,
                        d_fit, fit_mean, spec_threshold, (int)sub);
     if (launched("spectrum clip") != hipSuccess) return DD_ERR_HIP;
+  }
+  return DD_OK;
+}
+
+extern "C" int dd_bandpass_u8(const uint8_t* d_in, int64_t nchan, int64_t nsamp, int64_t row_stride, int64_t window,
+                              double* d_avg, double* d_window_means, void* stream) {
+  dd::clear_error();
+  if (!d_in || !d_avg) return dd::fail(DD_ERR_INVALID_ARG, "input and average must be non-NULL");
+  if (nchan < 1 || nsamp < 1 || row_stride < nsamp)
+    return dd::fail(DD_ERR_INVALID_ARG, "need nchan >= 1, nsamp >= 1 and row_stride >= nsamp");
+  if (window < 0 || (window > 0) != (d_window_means != nullptr))
+    return dd::fail(DD_ERR_INVALID_ARG, "window means need window >= 1 and their buffer (or window 0 and NULL)");
+  if (nchan > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many channels");
+  const int64_t win = window > 0 ? window : nsamp;
+  hipLaunchKernelGGL(bandpass_windows_u8, dim3((unsigned)nchan), dim3(kRfiThreads), 0, static_cast<hipStream_t>(stream),
+                     d_in, nsamp, row_stride, win, (nsamp + win - 1) / win, d_avg, d_window_means);
+  return launched("bandpass (8-bit)") == hipSuccess ? DD_OK : DD_ERR_HIP;
+}
+
+extern "C" int dd_rfi_clip_u8(uint8_t* d_data, int64_t nchan, int64_t nsamp, int64_t row_stride, const double* d_fit,
+                              double chan_threshold, int64_t window, const double* d_window_means, int32_t* d_flags,
+                              double fit_mean, double spec_threshold, void* stream) {
+  dd::clear_error();
+  if (!d_data || !d_fit) return dd::fail(DD_ERR_INVALID_ARG, "data and fit must be non-NULL");
+  if (nchan < 1 || nsamp < 1 || row_stride < nsamp)
+    return dd::fail(DD_ERR_INVALID_ARG, "need nchan >= 1, nsamp >= 1 and row_stride >= nsamp");
+  if (nchan > 65535) return dd::fail(DD_ERR_UNSUPPORTED, "at most 65535 channels per call");
+  const bool chan = chan_threshold > 0.0;
+  if (chan && (window < 1 || !d_flags || !d_window_means))
+    return dd::fail(DD_ERR_INVALID_ARG, "channel clipping needs window >= 1, the window means and flags");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (chan) {
+    const int64_t nwin = (nsamp + window - 1) / window;
+    const int64_t wblocks = (nwin + kRfiThreads - 1) / kRfiThreads;
+    if (wblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
+    hipLaunchKernelGGL(chan_flag, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_window_means,
+                       nwin, d_fit, chan_threshold, d_flags);
+    if (launched("channel flag") != hipSuccess) return DD_ERR_HIP;
+    hipLaunchKernelGGL(chan_apply_u8, dim3((unsigned)wblocks, (unsigned)nchan), dim3(kRfiThreads), 0, st, d_data,
+                       nsamp, row_stride, window, nwin, d_fit, d_flags);
+    if (launched("channel apply (8-bit)") != hipSuccess) return DD_ERR_HIP;
+  }
+  if (spec_threshold > 0.0) {
+    const int64_t tblocks = (nsamp + 16 * kRfiThreads - 1) / (16 * kRfiThreads);
+    if (tblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
+    hipLaunchKernelGGL(spec_clip_u8, dim3((unsigned)tblocks), dim3(kRfiThreads), 0, st, d_data, nchan, nsamp,
+                       row_stride, d_fit, fit_mean, spec_threshold);
+    if (launched("spectrum clip (8-bit)") != hipSuccess) return DD_ERR_HIP;
   }
   return DD_OK;
 }

@@ -39,6 +39,8 @@ class BeamSpec:
     dtype: str              # "u8", "f16" or "f32"
     block: int              # samples per block
     k_sigma: float = 6.0
+    max_log2: int = 0       # > 0: time binning above the diagonal DM up to factor 2^max_log2
+                            # (block must then be a multiple of 2^K, K the largest run factor)
 
     @property
     def block_s(self) -> float:
@@ -279,6 +281,8 @@ class LibraryExecutor(Executor):
     """Device side on libdedisp: one Stream (device ring with the maxdelay overlap) per
     admitted beam, and per submitted set of blocks one batched call per group of beams that
     can share it (all direct-read beams; LDS-form beams of one dtype and wavefront count).
+    A beam with time binning (``max_log2 > 0``) has a BinnedStream instead, one ring per run
+    at its binned sampling time, and is pushed on its own after the batched calls.
 
     Each beam owns two output sets (dedispersed block, mean, rms, candidates), used by
     alternate blocks, so a block's results stay intact while the next block of the same
@@ -310,22 +314,35 @@ class LibraryExecutor(Executor):
             form = "auto"
             if isinstance(t, dict):
                 form, t = t.get("form", "auto"), t.get("tuning")
-            p = self._api.Plan(spec.freq_mhz, spec.tsamp_s, spec.dm, dtype=spec.dtype, tuning=t, form=form)
+            if spec.max_log2 > 0:
+                p = self._api.BinnedPlan(spec.freq_mhz, spec.tsamp_s, spec.dm, dtype=spec.dtype,
+                                         max_log2=spec.max_log2, tuning=t, form=form)
+            else:
+                p = self._api.Plan(spec.freq_mhz, spec.tsamp_s, spec.dm, dtype=spec.dtype, tuning=t, form=form)
             self._plans[spec.name] = p
         return p
 
     def footprint(self, spec: BeamSpec) -> int:
         p = self.plan(spec)
+        ndm = len(spec.dm)
+        outs = ndm * spec.block * 4 + 2 * ndm * 4 + self.cand_cap * 24 + 8
+        if spec.max_log2 > 0:
+            ring, ws = p.stream_sizes(spec.block)
+            return int(ring + ws + 2 * outs)
         q = p.query(spec.block, allow_short=True)
-        outs = p.ndm * spec.block * 4 + 2 * p.ndm * 4 + self.cand_cap * 24 + 8
         return int(q["ring_bytes"] + q["stream_workspace_bytes"] + 2 * outs)
 
     def open(self, beam: int, spec: BeamSpec) -> None:
         p = self.plan(spec)
-        st = self._api.Stream(p, spec.block, device=self.device, stream=self.stream)
-        outs = [self._api.alloc_outputs(p.ndm, spec.block, self.device, self.k_sigma, self.cand_cap)
+        ndm = len(spec.dm)
+        if spec.max_log2 > 0:
+            st = self._api.BinnedStream(p, spec.block, device=self.device, stream=self.stream)
+        else:
+            st = self._api.Stream(p, spec.block, device=self.device, stream=self.stream)
+        outs = [self._api.alloc_outputs(ndm, spec.block, self.device, self.k_sigma, self.cand_cap)
                 for _ in range(2)]
-        self._beams[beam] = {"stream": st, "outs": outs, "n": 0, "spec": spec}
+        self._beams[beam] = {"stream": st, "outs": outs, "n": 0, "spec": spec,
+                             "binned": spec.max_log2 > 0}
 
     def close(self, beam: int) -> None:
         self._beams.pop(beam, None)
@@ -336,10 +353,15 @@ class LibraryExecutor(Executor):
         b = self._beams[beam]
         filling = 0
         for x in blocks:
-            w = b["stream"].append(x, stream=self.stream)
+            if b["binned"]:
+                # no append without dedispersion here: runs past their own fill dedisperse
+                # (without statistics), the others only fill
+                w = b["stream"].push(x, stats=False, stream=self.stream)
+            else:
+                w = b["stream"].append(x, stream=self.stream)
             if w is None:
                 filling += 1
-            else:
+            elif not b["binned"]:
                 raise ValueError("prefill went past the ring fill; use fewer blocks")
         return filling
 
@@ -351,7 +373,7 @@ class LibraryExecutor(Executor):
         pend = []
         for blk in blocks:
             b = self._beams[blk.beam]
-            pend.append(b["stream"].append(blk.data, stream=self.stream))
+            pend.append(None if b["binned"] else b["stream"].append(blk.data, stream=self.stream))
         groups: Dict[tuple, List[int]] = collections.defaultdict(list)
         for i, (blk, w) in enumerate(zip(blocks, pend)):
             if w is not None:
@@ -371,6 +393,14 @@ class LibraryExecutor(Executor):
                                             outputs=outs)
             for i, r in zip(idx, rs):
                 res[i] = r
+        for i, blk in enumerate(blocks):
+            b = self._beams[blk.beam]
+            if b["binned"]:
+                res[i] = b["stream"].push(blk.data, k_sigma=self.k_sigma, cand_cap=self.cand_cap,
+                                          outputs=b["outs"][b["n"] & 1], stream=self.stream,
+                                          batched=b["stream"].batchable)
+                if res[i] is not None:
+                    b["n"] += 1
         for blk, w in zip(blocks, pend):
             if w is not None:
                 self._beams[blk.beam]["n"] += 1
@@ -390,6 +420,18 @@ class LibraryExecutor(Executor):
         for blk, r in zip(blocks, res):
             if r is None:
                 out.append({"t0": 0, "nout": 0, "ncand": 0, "filling": True})
+                continue
+            if isinstance(r, self._api.BinnedStreamResult):
+                # a binned beam: t0 of its factor-1 run, outputs summed over the runs
+                m = r.merged
+                n = int(m.ncand()) if m._ncand is not None else 0
+                nout = sum(int(x.out.shape[1]) for _, _, x in r.segments if x is not None)
+                out.append({"t0": int(r.segments[0][1]), "nout": nout, "ncand": n, "filling": False})
+                if self.keep:
+                    self.kept[(blk.beam, blk.seq)] = {
+                        "runs": [(t0, None if x is None else x.out.clone(), None if x is None else x.mean.clone(),
+                                  None if x is None else x.rms.clone()) for _, t0, x in r.segments],
+                        "cand": m.candidates()}
                 continue
             n = int(r.ncand()) if r._ncand is not None else 0
             out.append({"t0": int(r.t0), "nout": int(r.out.shape[1]), "ncand": n, "filling": False})

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
         assert n in lib_mod.SIGNATURES, n
-    assert lib.dd_version().decode() == "1.4"
+    assert lib.dd_version().decode() == "1.5"
 
 
 def _create(lib, freq, dm, tsamp, dtype=0, tuning=None):
@@ -293,6 +293,68 @@ def test_time_binning_and_downfactor_arguments(lib):
     assert lib.dd_downfactor(p256, 0, 70000, 8, 8, p256, 4, None) == lib_mod.DD_ERR_UNSUPPORTED
 
 
+
+def _binned(lib, freq, tsamp, dms, dtype, max_log2):
+    h = C.c_void_p()
+    f = np.ascontiguousarray(freq, np.float64)
+    d = np.ascontiguousarray(dms, np.float64)
+    dbl = C.POINTER(C.c_double)
+    rc = lib.dd_binned_create(C.byref(h), f.ctypes.data_as(dbl), f.size, tsamp, d.ctypes.data_as(dbl), d.size,
+                              dtype, max_log2, None)
+    assert rc == 0
+    n = C.c_int32()
+    assert lib.dd_binned_query(h, 0, C.byref(n), None, 0, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    runs = (lib_mod.BinnedRun * n.value)()
+    lib.dd_binned_query(h, 0, None, runs, n.value, None, None)
+    return h, list(runs)
+
+
+def test_binned_runs_and_stream_sizes(lib):
+    """Binned runs follow the oracle's factors; a binned stream's ring is every run's stream
+    ring (each at block >> log2 samples, 256-byte aligned) and its blocks must be multiples
+    of the largest factor."""
+    freq = fbsynth.channel_freqs(428.0, 20.0 / 1024, 1024)
+    dms = fbsynth.dm_trials(0.0, 0.1, 2048)
+    h, runs = _binned(lib, freq, 51.2e-6, dms, 0, 4)
+    try:
+        k = orc.binning_factors(freq, 51.2e-6, dms, 4)
+        assert [(r.log2, r.d0, r.d1) for r in runs] == [
+            (int(k[d0]), d0, d1) for d0, d1 in zip([0] + [i for i in range(1, k.size) if k[i] != k[i - 1]],
+                                                   [i for i in range(1, k.size) if k[i] != k[i - 1]] + [k.size])]
+        kmax = max(r.log2 for r in runs)
+        assert kmax == 4
+        block = 19536  # a multiple of 16
+        rb, wb = C.c_int64(), C.c_int64()
+        assert lib.dd_binned_stream_query(h, block, C.byref(rb), C.byref(wb)) == 0
+        want = 0
+        for r in runs:
+            rc, p = _create(lib, freq, dms[r.d0:r.d1], 51.2e-6 * (1 << r.log2))
+            assert rc == 0
+            info = lib_mod.PlanInfo()
+            lib.dd_plan_query(p, block >> r.log2, C.byref(info))
+            want += -(-info.ring_bytes // 256) * 256
+            lib.dd_plan_destroy(p)
+        assert rb.value == want
+        assert wb.value > 0
+        for bad in (0, -16, 8, 19537, 19528):
+            assert lib.dd_binned_stream_query(h, bad, C.byref(rb), C.byref(wb)) == lib_mod.DD_ERR_INVALID_ARG, bad
+            assert rb.value == 0 and wb.value == 0
+        assert lib.dd_binned_stream_query(None, block, None, None) == lib_mod.DD_ERR_INVALID_ARG
+        out = C.c_void_p(1)
+        assert lib.dd_binned_stream_create(h, block, None, 1 << 40, None, C.byref(out)) == lib_mod.DD_ERR_INVALID_ARG
+        assert out.value is None
+        assert lib.dd_binned_stream_create(h, block, C.c_void_p(256), rb.value - 1, None,
+                                           C.byref(out)) == lib_mod.DD_ERR_WORKSPACE
+        assert lib.dd_binned_stream_create(h, 8, C.c_void_p(256), 1 << 40, None,
+                                           C.byref(out)) == lib_mod.DD_ERR_INVALID_ARG
+        t0 = (C.c_int64 * len(runs))(*([7] * len(runs)))
+        assert lib.dd_binned_stream_push(None, None, 16, 16, 0, None, 16, None, None, 0.0, None, 0, None, 0, None, 0,
+                                         None, t0, None) == lib_mod.DD_ERR_INVALID_ARG
+        assert lib.dd_binned_stream_set_gap_fill(None, 1) == lib_mod.DD_ERR_INVALID_ARG
+        lib.dd_binned_stream_destroy(None)
+    finally:
+        lib.dd_binned_destroy(h)
+
 @pytest.mark.parametrize("nchan,order", [(1, 0), (2, 1), (64, 4), (1024, 8), (4096, 12)])
 def test_bandpass_fit_matches_oracle(lib, nchan, order):
     """The host fit (Gram-Schmidt projection) equals the oracle's numpy least squares."""
@@ -328,6 +390,16 @@ def test_rfi_arguments(lib):
     assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 4, p, None, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_INVALID_ARG
     assert lib.dd_rfi_clip(p, 4, 8, 8, p, 1.0, 4, None, p, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_INVALID_ARG
     assert lib.dd_rfi_clip(p, 70000, 8, 8, p, 1.0, 4, p, p, 0.0, 1.0, 1, None) == lib_mod.DD_ERR_UNSUPPORTED
+    # the 8-bit forms validate the same way (no correction argument)
+    assert lib.dd_bandpass_u8(None, 4, 8, 8, 0, p, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_bandpass_u8(p, 4, 8, 7, 0, p, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_bandpass_u8(p, 4, 8, 8, 4, p, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_bandpass_u8(p, 0, 8, 8, 0, p, None, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip_u8(p, 4, 8, 8, None, 1.0, 4, p, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip_u8(p, 4, 8, 8, p, 1.0, 0, p, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip_u8(p, 4, 8, 8, p, 1.0, 4, p, None, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip_u8(p, 4, 0, 8, p, 0.0, 4, p, p, 0.0, 1.0, None) == lib_mod.DD_ERR_INVALID_ARG
+    assert lib.dd_rfi_clip_u8(p, 70000, 8, 8, p, 1.0, 4, p, p, 0.0, 1.0, None) == lib_mod.DD_ERR_UNSUPPORTED
 
 
 def test_boxcar_search_arguments(lib):

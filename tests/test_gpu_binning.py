@@ -7,7 +7,7 @@ import pytest
 
 import fbsynth
 from oracle import dedisp_oracle as orc
-from tests.gpu_util import assert_rows_close, assert_stats_close, compare_candidates, cuda
+from tests.gpu_util import GUARD, assert_rows_close, assert_stats_close, compare_candidates, cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -128,8 +128,8 @@ def test_config2_binned_full_size(torch, dd):
 
 @pytest.mark.parametrize("dt", ["f32", "u8"])
 def test_binned_batched_equals_per_run(torch, dd, dt):
-    """The runs in one persistent launch equal one launch per run, bit for bit (for u8 the
-    factor-1 run keeps its own launch: the batch needs one input type)."""
+    """The runs in one batched call equal one launch per run, bit for bit (for u8 the factor-1
+    run is a direct-read item beside the FP32 LDS-form runs of the same call)."""
     b = fbsynth.config1()
     x = torch.from_numpy(np.ascontiguousarray(_stored(b.data, dt))).cuda()
     bp = dd.BinnedPlan(b.freq_mhz, b.tsamp_s, b.dm, dtype=dt, max_log2=4)
@@ -139,3 +139,126 @@ def test_binned_batched_equals_per_run(torch, dd, dt):
     for (_, r1), (_, r2) in zip(a.segments, c.segments):
         assert torch.equal(r1.out, r2.out) and torch.equal(r1.mean, r2.mean) and torch.equal(r1.rms, r2.rms)
         np.testing.assert_array_equal(r1.candidates(), r2.candidates())
+
+
+def _binned_stream_case(dt, sizes, k_sigma, gap=None):
+    """A seed whose stream windows (every run, every push) keep their candidates a margin
+    from the threshold; returns (freq, tsamp, dm, stored input, per-run oracle series of the
+    input with zeros in place of the lost block, push results expected as run windows)."""
+    freq = fbsynth.channel_freqs(428.0, 0.3125, 64)
+    tsamp = 51.2e-6
+    dm = fbsynth.dm_trials(0.0, 0.1, 128)
+    for seed in range(300, 340):
+        x32 = np.random.default_rng(seed).standard_normal((64, sum(sizes))).astype(np.float32)
+        x = np.ascontiguousarray(_stored(x32, dt))
+        xz = x.copy()
+        if gap is not None:
+            a = sum(sizes[:gap])
+            xz[:, a:a + sizes[gap]] = 0
+        runs = orc.dedisperse_binned(xz, freq, tsamp, dm, 4)
+        if gap is not None:  # outputs only are compared
+            return freq, tsamp, dm, x, xz, runs
+        ok = True
+        for k, d0, d1, s in runs:
+            maxdelay = (sum(sizes) >> k) - s.shape[1]
+            received = emitted = 0
+            for n in sizes:  # the windows a stream emits: outputs made computable by each block
+                received += n >> k
+                t1 = received - maxdelay
+                if t1 > emitted:
+                    w = s[:, emitted:t1]
+                    ok = ok and orc.threshold_margin(w, *orc.series_stats(w), k_sigma) > 4 * GUARD
+                    emitted = t1
+        if ok:
+            return freq, tsamp, dm, x, xz, runs
+    raise AssertionError("no well-conditioned seed in 40")
+
+
+@pytest.mark.parametrize("dt,batched", [("f32", False), ("f32", True), ("u8", False), ("u8", True),
+                                        ("f16", False)])
+def test_binned_stream_equals_one_shot(torch, dd, dt, batched):
+    """A time-binned stream over 1024-sample blocks and a ragged last block of 336 (each a
+    multiple of 16, the largest factor): every run emits, per push, the outputs its own ring
+    made computable, equal bit for bit to the one-shot binned call over the concatenated
+    input at the same run times; each window's statistics and the merged 4-sigma candidates
+    against the oracle; all outputs of every run emitted once. Each run holds its own ring at
+    its binned sampling time."""
+    _say(f"case: binned stream {dt} batched={batched}")
+    sizes = [1024] * 13 + [336]
+    freq, tsamp, dm, x, _, runs = _binned_stream_case(dt, sizes, 4.0)
+    bp = dd.BinnedPlan(freq, tsamp, dm, dtype=dt, max_log2=4)
+    assert [s.log2 for s in bp.segments] == [0, 1, 2, 3, 4]
+    one = bp.dedisperse(torch.from_numpy(x).cuda())
+    one = [r.out.cpu().numpy() for _, r in one.segments]
+    st = dd.BinnedStream(bp, 1024)
+    emitted = [0] * len(runs)
+    pos = 0
+    for j, n in enumerate(sizes):
+        blk = torch.from_numpy(np.ascontiguousarray(x[:, pos:pos + n])).cuda()
+        pos += n
+        res = st.push(blk, k_sigma=4.0, batched=batched)
+        if res is None:  # only while every run fills
+            assert all(e == 0 for e in emitted)
+            continue
+        merged = res.candidates()
+        total = 0
+        for i, ((seg, t0, r), (k, d0, d1, s)) in enumerate(zip(res.segments, runs)):
+            if r is None:
+                continue
+            nk = r.out.shape[1]
+            assert t0 == emitted[i], (k, t0, emitted[i])
+            emitted[i] = t0 + nk
+            np.testing.assert_array_equal(r.out.cpu().numpy(), one[i][:, t0:t0 + nk])
+            w = s[:, t0:t0 + nk]
+            mean, rms = orc.series_stats(w)
+            assert_stats_close(r.mean.cpu().numpy(), r.rms.cpu().numpy(), mean, rms)
+            c = r.candidates()
+            compare_candidates(c, w, mean, rms, 4.0, t_offset=t0)
+            total += c.size
+        assert merged.size == total
+        assert np.all(np.diff(merged["dm_index"].astype(np.int64) * (1 << 40) + merged["t"]) > 0)
+    assert emitted == [o.shape[1] for o in one]
+    assert emitted == [(sum(sizes) >> s.log2) - s.plan.maxdelay for s in bp.segments]
+
+
+def test_binned_stream_gap_fill_and_refusals(torch, dd):
+    """A lost block with gap fill on: every run's outputs equal the one-shot binned call over
+    the input with zeros in place of the lost block, at the same run times. A block that is
+    not a multiple of 16 samples, a wrong seq (gap fill off) and a batched push whose runs
+    cannot share one call (FP16 factor-1 run beside FP32 runs) are refused before anything
+    changes, and the stream continues."""
+    _say("case: binned stream gap fill")
+    sizes = [1024] * 12
+    freq, tsamp, dm, x, xz, runs = _binned_stream_case("f32", sizes, 4.0, gap=7)
+    bp = dd.BinnedPlan(freq, tsamp, dm, max_log2=4)
+    one = [r.out.cpu().numpy() for _, r in bp.dedisperse(torch.from_numpy(xz).cuda()).segments]
+    st = dd.BinnedStream(bp, 1024, gap_fill=True)
+    seen = 0
+    for j in range(len(sizes)):
+        if j == 7:
+            continue
+        blk = torch.from_numpy(np.ascontiguousarray(x[:, 1024 * j:1024 * (j + 1)])).cuda()
+        res = st.push(blk, seq=j, k_sigma=4.0)
+        if res is None:
+            continue
+        for i, (seg, t0, r) in enumerate(res.segments):
+            if r is not None:
+                np.testing.assert_array_equal(r.out.cpu().numpy(), one[i][:, t0:t0 + r.out.shape[1]])
+                seen += 1
+    assert seen > 20
+    plain = dd.BinnedStream(bp, 1024)
+    blk = torch.from_numpy(np.ascontiguousarray(x[:, :1024])).cuda()
+    with pytest.raises(dd.DedispError):
+        plain.push(blk[:, :1000])
+    with pytest.raises(dd.DedispError):
+        plain.push(blk, seq=1)
+    plain.push(blk, seq=0)
+    assert plain.seq == 1
+    bp16 = dd.BinnedPlan(freq, tsamp, dm, dtype="f16", max_log2=4)
+    s16 = dd.BinnedStream(bp16, 1024)
+    b16 = torch.from_numpy(fbsynth.to_f16(x[:, :1024])).cuda()
+    with pytest.raises(dd.DedispError):
+        s16.push(b16, batched=True)
+    assert s16.seq == 0
+    s16.push(b16)
+    assert s16.seq == 1

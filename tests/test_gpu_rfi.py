@@ -148,3 +148,63 @@ def test_rfi_full_size(torch, dd):
         np.testing.assert_array_equal(got[c][replaced], 0.0)
         err = np.abs(got[c].astype(np.float64) - want)
         assert np.all(err <= _corr_tol(fit[c:c + 1], want[None, :])[0])
+
+
+def _codes_dirty(nchan, n, seed):
+    rng = np.random.default_rng(seed)
+    c = np.arange(nchan)
+    x = (100.0 + 30.0 * np.sin(np.pi * c / nchan))[:, None] + 8.0 * rng.standard_normal((nchan, n))
+    x[nchan // 7, n // 10: n // 10 + 3 * n // 40] += 60.0      # narrowband burst
+    x[nchan // 3, : n // 50 + 1] = 0.0                          # lost data
+    x[:, n // 2: n // 2 + 3] += 40.0                            # broadband spike
+    return np.clip(np.floor(x + 0.5), 0, 255).astype(np.uint8)
+
+
+@pytest.mark.parametrize("nchan,n,stride,window,order", [
+    (64, 16384, 16384, 64, 4), (5, 1001, 1013, 7, 2), (1, 300, 300, 16, 0), (33, 4099, 4112, 256, 6),
+    (4096, 12207, 12207, 256, 6)])
+def test_rfi_u8_parity(torch, dd, nchan, n, stride, window, order):
+    """8-bit codes (dd_bandpass_u8, dd_rfi_clip_u8): averages and window means are exact sums
+    divided once, equal to the oracle's bit for bit; every flag and every replaced code
+    equals the oracle's (no decision and no fitted value within 1e-6 of flipping); rows
+    unaligned (stride 1013) and ragged windows included; the last case is a 1 s block of a
+    4096-channel serving beam."""
+    _say(f"case: rfi u8 {nchan}x{n} stride {stride} window {window} order {order}")
+    full = np.zeros((nchan, stride), np.uint8)
+    full[:, :n] = _codes_dirty(nchan, n, nchan * 37 + n)
+    x = full[:, :n]
+    cthr, sthr = 20.0, 20.0
+    want, fit, rmse, fmean, cf, sf = orc.rfi_mitigate_codes(x, order, cthr, window, sthr)
+    assert _window_margin(x, fit, cthr, window) > GUARD
+    after_chan = orc.rfi_mitigate_codes(x, order, cthr, window, 0.0)[0]
+    assert float(np.min(np.abs(np.abs(after_chan.astype(np.float64).mean(axis=0) - fmean) - sthr))) > GUARD
+    assert float(np.min(np.abs(fit - np.floor(fit) - 0.5))) > GUARD
+    dev = torch.from_numpy(full).cuda()[:, :n]
+    np.testing.assert_array_equal(dd.bandpass(dev).cpu().numpy(), orc.bandpass_average(x))
+    avg2, wmeans = dd.bandpass(dev, window)
+    np.testing.assert_array_equal(avg2.cpu().numpy(), orc.bandpass_average(x))
+    want_means = np.array([[x[c, w * window:(w + 1) * window].astype(np.float64).mean()
+                            for w in range(-(-n // window))] for c in range(nchan)])
+    np.testing.assert_array_equal(wmeans.cpu().numpy(), want_means)
+    with pytest.raises(ValueError):
+        dd.rfi_mitigate(dev, order, cthr, window, sthr, subtract=True)
+    gfit, grmse, gmean, flags = dd.rfi_mitigate(dev, order, cthr, window, sthr)
+    np.testing.assert_allclose(gfit, fit, rtol=0, atol=1e-9)
+    np.testing.assert_array_equal(flags.cpu().numpy() != 0, cf)
+    assert cf.any() and sf.any()
+    np.testing.assert_array_equal(dev.cpu().numpy(), want)
+    assert np.array_equal(full[:, n:], np.zeros((nchan, stride - n), np.uint8))
+
+
+def test_rfi_u8_stages_skip(torch, dd):
+    """Thresholds <= 0 leave the codes as they are; the spectrum stage alone replaces the
+    spike's spectra only."""
+    x = _codes_dirty(16, 2048, 4)
+    dev = torch.from_numpy(x.copy()).cuda()
+    _, _, _, flags = dd.rfi_mitigate(dev, 2, 0.0, 64, 0.0)
+    assert flags is None
+    np.testing.assert_array_equal(dev.cpu().numpy(), x)
+    want, fit, _, fmean, _, sf = orc.rfi_mitigate_codes(x, 2, 0.0, 64, 20.0)
+    assert list(np.nonzero(sf)[0]) == [1024, 1025, 1026]
+    dd.rfi_mitigate(dev, 2, 0.0, 64, 20.0)
+    np.testing.assert_array_equal(dev.cpu().numpy(), want)

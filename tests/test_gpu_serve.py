@@ -140,3 +140,55 @@ def test_queued_beam_admitted_mid_run_equals_alone(torch):
     assert set(ex.kept) == set(want)
     for key, out in want.items():
         np.testing.assert_array_equal(ex.kept[key]["out"].cpu().numpy(), out)
+
+
+def test_server_with_a_binned_beam_equals_alone(torch):
+    """A beam with time binning (BinnedStream: one ring per run at its binned sampling time)
+    served beside two plain beams: per block, its runs' outputs, statistics and merged
+    candidates equal those of its own BinnedStream pushed alone, and its footprint is its
+    binned ring and workspace plus two output sets."""
+    import paper_1401_8258_amd as dd
+    dd.load_library()
+    specs = _specs()[:2] + [serve.BeamSpec("binned", fbsynth.channel_freqs(428.0, 0.3125, 64), 51.2e-6,
+                                           fbsynth.dm_trials(0.0, 0.1, 128), "u8", 1024, k_sigma=6.0,
+                                           max_log2=4)]
+    nblocks = 4
+    host = [_blocks(sp, nblocks, 300 + i) for i, sp in enumerate(specs)]
+    dev = [[torch.from_numpy(b).cuda() for b in bs] for bs in host]
+    sp = specs[2]
+    bp = dd.BinnedPlan(sp.freq_mhz, sp.tsamp_s, sp.dm, dtype="u8", max_log2=4)
+    assert len(bp.segments) == 5
+    st = dd.BinnedStream(bp, sp.block)
+    alone = {}
+    for k, x in enumerate(dev[2]):
+        r = st.push(x, k_sigma=6.0)
+        if r is not None:
+            alone[k] = ([(t0, None if x is None else (x.out.cpu().numpy(), x.mean.cpu().numpy(),
+                                                      x.rms.cpu().numpy())) for _, t0, x in r.segments],
+                        r.candidates())
+    torch.cuda.synchronize()
+    assert alone
+    print("case: server with a binned beam beside two plain u8 beams", flush=True)
+    ex = serve.LibraryExecutor(k_sigma=6.0, keep=True)
+    ring, ws = bp.stream_sizes(sp.block)
+    outs = 128 * sp.block * 4 + 2 * 128 * 4 + ex.cand_cap * 24 + 8
+    assert ex.footprint(sp) == ring + ws + 2 * outs
+    srv = serve.Server(specs, ex, hbm_budget=1 << 40, max_inflight=2)
+    assert [srv.request(i) for i in range(3)] == ["admitted"] * 3
+    sched = serve.poisson_schedule(specs, nblocks, seed=11, jitter_mean_s=0.01, phases=[0.0, 0.001, 0.002],
+                                   make_data=lambda i, k: dev[i][k], time_scale=0.02)
+    stats = srv.run(sched)
+    torch.cuda.synchronize()
+    assert stats.blocks == 3 * nblocks
+    got = {k: v for (i, k), v in ex.kept.items() if i == 2}
+    assert set(got) == set(alone)
+    for k, (runs, cand) in alone.items():
+        g = got[k]
+        assert [t0 for t0, _, _, _ in g["runs"]] == [t0 for t0, _ in runs]
+        for (t0, o, m, r), (_, want) in zip(g["runs"], runs):
+            assert (o is None) == (want is None)
+            if want is not None:
+                np.testing.assert_array_equal(o.cpu().numpy(), want[0])
+                np.testing.assert_array_equal(m.cpu().numpy(), want[1])
+                np.testing.assert_array_equal(r.cpu().numpy(), want[2])
+        np.testing.assert_array_equal(g["cand"], cand)
