@@ -734,6 +734,28 @@ def main():
                "groups_of_48": groups48}
     del sp
 
+    # the same workload stored as 8-bit codes (clip(rint(128 + 16 x), 0, 255), made on the
+    # device), in the 8-bit default plan (direct-read form, exact integer sums): the kernel
+    # with its copy preparation alone, then whole steps with statistics and candidates
+    print("bench: 8-bit storage of the same workload", file=sys.stderr, flush=True)
+    x8 = torch.clamp(torch.round(128.0 + 16.0 * x), 0, 255).to(torch.uint8)
+    plan8 = dd.Plan(beam.freq_mhz, beam.tsamp_s, beam.dm, dtype="u8")
+    ws8 = plan8.workspace(nsamp)
+    u8res = {}
+    for full in (False, True):
+        plan8.dedisperse(x8, stats=full, k_sigma=k if full else 0.0, cand_cap=cap, out=out, workspace=ws8)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            plan8.dedisperse(x8, stats=full, k_sigma=k if full else 0.0, cand_cap=cap, out=out, workspace=ws8)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        u8res["step_ms" if full else "prep_and_kernel_ms"] = round(e0.elapsed_time(e1) / 3, 3)
+    u8 = {"form": plan8.form, "tiles": list(plan8.tiles[:2]), **u8res,
+          "adds_per_s_prep_and_kernel": adds / (u8res["prep_and_kernel_ms"] * 1e-3),
+          "dm_trial_samples_per_s": beam.ndm * nout / (u8res["step_ms"] * 1e-3)}
+    del x8, ws8, plan8
+
     res = {
         "metric": "DM-trial*samples/s",
         "value": beam.ndm * nout / (ms_step * 1e-3),
@@ -748,6 +770,7 @@ def main():
                    "tiles": list(plan.tiles), "producer_waves": plan.producer_waves, "candidates_found": n_found},
         "real_time_factor": round(nout * beam.tsamp_s / (ms_step * 1e-3), 2),
         "roofline": roof,
+        "u8_storage": u8,
         "detrend": detrend,
         "boxcar": boxcar,
         "boxcar_search": boxcar_search,

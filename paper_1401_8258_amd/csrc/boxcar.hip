@@ -81,16 +81,24 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_rows(const float* __restri
 // (rms sqrt(w)); a detection at (row, t) when the best width's S/N exceeds k (the smallest
 // width on ties), reported with that width, B_w and S/N, rows in order and t ascending.
 //
-// One 256-thread workgroup per (row, segment of kSearchSeg starts): the segment and 64
-// samples past it are read once into LDS (zeros past n, which no defined boxcar reads).
-// Level j is formed from level j - 1 in the other LDS buffer by B_2w[t] = B_w[t] +
-// B_w[t + w] (a pairwise FP32 tree, the same order at every start); after each level every
-// thread updates the best S/N of its 16 starts (t = q 256 + thread, conflict-free LDS reads).
-// A counting pass, a scan of the counts and a writing pass that recomputes the segment
-// place the detections; each pass reads the series once (HBM-bound).
+// One 256-thread workgroup per (row, segment of kSearchSeg starts). The segment and 64
+// samples past it are read once into LDS with 16-byte loads (zeros past n, which no
+// defined boxcar reads), 4 padding words after every 16 samples. Thread i then owns the 16
+// consecutive starts 16 i .. 16 i + 15 and copies the 80 samples they need into registers
+// (20 conflict-free ds_read_b128: threads 20 words apart cover all 64 banks per 16 lanes).
+// Level j is formed in place from level j - 1 by B_2w[t] = B_w[t] + B_w[t + w] (a pairwise
+// FP32 tree, the same order at every start), and after each level the thread updates the
+// best S/N of its starts. S/N is FP32: w * mean is exact (w is a power of two), so the
+// difference is rounded once, and the reciprocal 1 / (rms sqrt(w)) is formed in FP64 and
+// rounded once. A counting pass, a scan of the counts and a writing pass that recomputes
+// the segment place the detections; each pass reads the series once (HBM-bound).
 constexpr int kSearchSeg = 4096;
-constexpr int kSearchPer = kSearchSeg / kBoxThreads;  // starts per thread
-constexpr int kSearchBuf = kSearchSeg + 64;
+constexpr int kSearchPer = kSearchSeg / kBoxThreads;  // consecutive starts per thread
+constexpr int kSearchWin = kSearchPer + 64;           // samples a thread's starts need (80)
+constexpr int kSearchSamples = kSearchSeg + 64;       // samples a segment needs
+constexpr int kSearchLds = kSearchSamples / 16 * 20;  // LDS words with the padding
+
+__device__ __forceinline__ int pad_pos(int a) { return a + 4 * (a >> 4); }
 
 struct SearchArgs {
   const float* x;
@@ -98,72 +106,103 @@ struct SearchArgs {
   const float* mean;  // null: 0 (normalised series)
   const float* rms;   // null: 1
   int max_log2;
-  double k;
+  float k;
 };
 
+// Levels 0 .. max_log2 of one thread's window, in place, and the best S/N of its starts:
+// start q takes width w when q + w <= lim (CHECKED; otherwise every width fits). The
+// updates are selects, not branches: a start's best changes only on a strictly larger S/N,
+// so ties keep the smaller width.
+template <bool CHECKED>
+__device__ __forceinline__ void search_levels(float (&x)[kSearchWin], float (&best)[kSearchPer],
+                                              int (&bj)[kSearchPer], float (&bval)[kSearchPer], int lim, float m,
+                                              double r, int max_log2) {
+#pragma unroll
+  for (int j = 0; j <= kMaxLevel; ++j) {
+    if (j > max_log2) break;
+    const int w = 1 << j;
+    if (j > 0) {
+      // in place, ascending: B_w[t] for t + w <= kSearchWin from B_{w/2}[t], B_{w/2}[t + w/2]
+#pragma unroll
+      for (int t = 0; t + w <= kSearchWin; ++t) x[t] = x[t] + x[t + (w >> 1)];
+    }
+    const float mw = m * (float)w;
+    const float inv = (float)(1.0 / (r * sqrt((double)w)));
+#pragma unroll
+    for (int q = 0; q < kSearchPer; ++q) {
+      const float snr = (x[q] - mw) * inv;
+      const bool up = snr > best[q] && (!CHECKED || q + w <= lim);
+      bval[q] = up ? x[q] : bval[q];
+      bj[q] = up ? j : bj[q];
+      best[q] = up ? snr : best[q];
+    }
+  }
+}
+
 // The best S/N over the widths (and its width index and boxcar sum) for this thread's
-// starts of segment seg of row d; false when the row has no variance.
-__device__ bool search_segment(const SearchArgs& A, int d, int64_t seg, float* buf0, float* buf1, double* best,
-                               int* bj, float* bval) {
+// starts of segment seg of row d; false when the row has no variance (the same for every
+// thread of the workgroup, before any barrier).
+__device__ __forceinline__ bool search_segment(const SearchArgs& A, int d, int64_t seg, float* buf,
+                                               float (&best)[kSearchPer], int (&bj)[kSearchPer],
+                                               float (&bval)[kSearchPer]) {
   const int tid = threadIdx.x;
   const int64_t b = seg * kSearchSeg;
-  const float* row = A.x + (int64_t)d * A.stride;
-  const double m = A.mean ? (double)A.mean[d] : 0.0;
+  const float* row = A.x + (int64_t)d * A.stride + b;
+  const float m = A.mean ? A.mean[d] : 0.0f;
   const double r = A.rms ? (double)A.rms[d] : 1.0;
-  if (!(r > 0.0)) return false;
-  for (int i = tid; i < kSearchBuf; i += kBoxThreads) buf0[i] = b + i < A.n ? row[b + i] : 0.0f;
 #pragma unroll
   for (int q = 0; q < kSearchPer; ++q) {
     best[q] = -INFINITY;
     bj[q] = 0;
     bval[q] = 0.0f;
   }
-  __syncthreads();
-  float* src = buf0;
-  float* dst = buf1;
-  for (int j = 0; j <= A.max_log2; ++j) {
-    const int w = 1 << j;
-    if (j > 0) {
-      const int h = w >> 1;
-      for (int i = tid; i < kSearchBuf - w; i += kBoxThreads) dst[i] = src[i] + src[i + h];
-      __syncthreads();
-      float* t = src;
-      src = dst;
-      dst = t;
+  if (!(r > 0.0)) return false;
+  const int64_t navail = A.n - b;  // samples of the row from the segment start on
+  const bool vec = (reinterpret_cast<uintptr_t>(row) & 15) == 0;
+  for (int i = tid; i < kSearchSamples / 4; i += kBoxThreads) {
+    const int a = 4 * i;
+    float4 v;
+    if (vec && a + 3 < navail) {
+      v = *reinterpret_cast<const float4*>(row + a);
+    } else {
+      v.x = a < navail ? row[a] : 0.0f;
+      v.y = a + 1 < navail ? row[a + 1] : 0.0f;
+      v.z = a + 2 < navail ? row[a + 2] : 0.0f;
+      v.w = a + 3 < navail ? row[a + 3] : 0.0f;
     }
-    const double inv = 1.0 / (r * sqrt((double)w));
-    const double mw = (double)w * m;
-#pragma unroll
-    for (int q = 0; q < kSearchPer; ++q) {
-      const int tl = q * kBoxThreads + tid;
-      const int64_t t = b + tl;
-      if (t + w <= A.n) {
-        const float v = src[tl];
-        const double snr = ((double)v - mw) * inv;
-        if (snr > best[q]) {
-          best[q] = snr;
-          bj[q] = j;
-          bval[q] = v;
-        }
-      }
-    }
-    // the next level overwrites the other buffer only after every thread read this one
-    __syncthreads();
+    *reinterpret_cast<float4*>(buf + pad_pos(a)) = v;
   }
+  __syncthreads();
+  float x[kSearchWin];
+  const int a0 = kSearchPer * tid;
+#pragma unroll
+  for (int c = 0; c < kSearchWin / 4; ++c) {
+    const float4 v = *reinterpret_cast<const float4*>(buf + pad_pos(a0 + 4 * c));
+    x[4 * c] = v.x;
+    x[4 * c + 1] = v.y;
+    x[4 * c + 2] = v.z;
+    x[4 * c + 3] = v.w;
+  }
+  // every start of every width lies inside the row unless this is the row's last segment
+  const int lim = (int)min<int64_t>(A.n - (b + a0), (int64_t)kSearchWin);
+  if (lim >= kSearchWin)
+    search_levels<false>(x, best, bj, bval, lim, m, r, A.max_log2);
+  else
+    search_levels<true>(x, best, bj, bval, lim, m, r, A.max_log2);
   return true;
 }
 
 __global__ __launch_bounds__(kBoxThreads) void boxcar_count(SearchArgs A, int64_t nseg, int32_t* __restrict__ cnt) {
-  __shared__ float buf0[kSearchBuf], buf1[kSearchBuf];
+  __shared__ __align__(16) float buf[kSearchLds];
   __shared__ int total;
   const int d = blockIdx.y;
   const int64_t seg = blockIdx.x;
-  double best[kSearchPer];
+  float best[kSearchPer];
   int bj[kSearchPer];
   float bval[kSearchPer];
   if (threadIdx.x == 0) total = 0;
   __syncthreads();
-  if (search_segment(A, d, seg, buf0, buf1, best, bj, bval)) {
+  if (search_segment(A, d, seg, buf, best, bj, bval)) {
     int c = 0;
 #pragma unroll
     for (int q = 0; q < kSearchPer; ++q) c += best[q] > A.k ? 1 : 0;
@@ -179,46 +218,52 @@ __global__ __launch_bounds__(1024) void boxcar_scan(const int32_t* __restrict__ 
   dd::scan_counts(cnt, n, offs, total, part);
 }
 
+// Detections in ascending t: thread i's starts precede thread i + 1's, so a thread's slot
+// is the segment offset plus the exclusive prefix sum of the hit counts over threads
+// (inclusive scan inside each wavefront, the wavefront totals through LDS).
 __global__ __launch_bounds__(kBoxThreads) void boxcar_write(SearchArgs A, int64_t nseg, const int32_t* __restrict__ cnt,
                                                             const int64_t* __restrict__ offs, dd_pulse* __restrict__ out,
                                                             int64_t cap) {
-  __shared__ float buf0[kSearchBuf], buf1[kSearchBuf];
+  __shared__ __align__(16) float buf[kSearchLds];
   __shared__ int wtot[kBoxThreads / 64];
   const int d = blockIdx.y;
   const int64_t seg = blockIdx.x;
   const int64_t idx = (int64_t)d * nseg + seg;
   if (cnt[idx] == 0) return;  // the whole workgroup leaves together
-  double best[kSearchPer];
+  float best[kSearchPer];
   int bj[kSearchPer];
   float bval[kSearchPer];
-  search_segment(A, d, seg, buf0, buf1, best, bj, bval);
+  search_segment(A, d, seg, buf, best, bj, bval);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int64_t off = offs[idx];
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < kSearchPer; ++q) c += best[q] > A.k ? 1 : 0;
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wtot[w] = incl;
+  __syncthreads();
+  int before = incl - c;
+  for (int i = 0; i < w; ++i) before += wtot[i];
+  int64_t pos = offs[idx] + before;
+  const int64_t t0 = seg * kSearchSeg + kSearchPer * threadIdx.x;
 #pragma unroll
   for (int q = 0; q < kSearchPer; ++q) {
-    // starts q 256 .. q 256 + 255 of the segment: ballot orders them by thread (= by t)
-    const bool hit = best[q] > A.k;
-    const uint64_t mask = __ballot(hit);
-    const int below = __popcll(mask & ((1ull << lane) - 1ull));
-    __syncthreads();
-    if (lane == 0) wtot[w] = __popcll(mask);
-    __syncthreads();
-    int before = 0;
-    for (int i = 0; i < w; ++i) before += wtot[i];
-    const int tot = wtot[0] + wtot[1] + wtot[2] + wtot[3];
-    if (hit) {
-      const int64_t pos = off + before + below;
+    if (best[q] > A.k) {
       if (pos < cap) {
         dd_pulse o;
         o.row = d;
         o.width = 1 << bj[q];
-        o.t = seg * kSearchSeg + q * kBoxThreads + threadIdx.x;
+        o.t = t0 + q;
         o.value = bval[q];
-        o.snr = (float)best[q];
+        o.snr = best[q];
         out[pos] = o;
       }
+      ++pos;
     }
-    off += tot;
   }
 }
 
@@ -269,7 +314,7 @@ extern "C" int dd_boxcar_search(const float* d_series, int64_t nrows, int64_t n,
   char* ws = static_cast<char*>(d_workspace);
   int32_t* cnt = reinterpret_cast<int32_t*>(ws + l.cnt_off);
   int64_t* offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
-  const SearchArgs A{d_series, n, row_stride, d_mean, d_rms, (int)max_log2, (double)k_sigma};
+  const SearchArgs A{d_series, n, row_stride, d_mean, d_rms, (int)max_log2, k_sigma};
   const dim3 grid((unsigned)l.nseg, (unsigned)nrows);
   hipLaunchKernelGGL(boxcar_count, grid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt);
   hipLaunchKernelGGL(boxcar_scan, dim3(1), dim3(1024), 0, st, cnt, nrows * l.nseg, offs, d_npulse);

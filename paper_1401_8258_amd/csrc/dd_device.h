@@ -20,29 +20,44 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
   return v;
 }
 
-// Exclusive scan of n counts by one 1024-thread block (part: 1024 int64 of LDS); the total
-// to *total. Serves every candidate compaction (threshold and boxcar detections).
+// Exclusive scan of n counts by one 1024-thread block (part: at least 16 int64 of LDS); the
+// total to *total. Serves every candidate compaction (threshold and boxcar detections).
+// Tiles of 4096 counts in order, each thread taking 4 consecutive ones, so every load and
+// store of a wavefront covers one contiguous span; a tile is scanned by wavefront shuffles
+// and the 16 wavefront totals in LDS, and carries its total into the next.
 __device__ __forceinline__ void scan_counts(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ offs,
                                             int64_t* __restrict__ total, int64_t* part) {
-  const int tid = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t b = min(n, tid * chunk), e = min(n, b + chunk);
-  int64_t local = 0;
-  for (int64_t i = b; i < e; ++i) local += cnt[i];
-  part[tid] = local;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int64_t v = tid >= off ? part[tid - off] : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += 4096) {
+    const int64_t i0 = base + 4 * tid;
+    int c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = i0 + k < n ? cnt[i0 + k] : 0;
+    const int64_t s = (int64_t)c[0] + c[1] + c[2] + c[3];
+    int64_t incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) part[wv] = incl;
     __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+    int64_t run = carry + incl - s, tile = 0;
+    for (int k = 0; k < 16; ++k) {
+      const int64_t p = part[k];
+      run += k < wv ? p : 0;
+      tile += p;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < n) offs[i0 + k] = run;
+      run += c[k];
+    }
+    carry += tile;
+    __syncthreads();  // every thread has read part before the next tile writes it
   }
-  int64_t run = part[tid] - local;
-  for (int64_t i = b; i < e; ++i) {
-    offs[i] = run;
-    run += cnt[i];
-  }
-  if (tid == 1023) *total = part[1023];
+  if (tid == 0) *total = carry;
 }
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }

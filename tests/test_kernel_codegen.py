@@ -29,7 +29,7 @@ def device_code(tmp_path_factory):
     d = tmp_path_factory.mktemp("codegen")
     flags = [f for f in build.FLAGS if f not in ("-shared", "-fPIC")]
     asm_all, dis_all = "", ""
-    for name in ("dedisp", "detrend", "boxcar", "downfactor", "rfi"):  # every device source of the library
+    for name in ("dedisp", "direct", "regwin", "detrend", "boxcar", "downfactor", "rfi"):  # every device source
         asm = d / f"{name}.s"
         subprocess.run([HIPCC] + flags + ["--cuda-device-only", "-S", "-o", str(asm),
                                           os.path.join(CSRC, f"{name}.hip")], check=True, capture_output=True)
