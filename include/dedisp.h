@@ -363,7 +363,9 @@ typedef struct dd_pulse {
  * w = 2^j, j = 0 .. max_log2 (<= 6: 1..64 samples), at every start t of a row with
  * t + w <= n:
  *   B_w[t] = x[t] + ... + x[t + w - 1]            (FP32, pairwise: B_2w[t] = B_w[t] + B_w[t + w])
- *   S/N_w[t] = (B_w[t] - w mean) / (rms sqrt(w))  (FP64)
+ *   S/N_w[t] = (B_w[t] - w mean) / (rms sqrt(w))  (FP32: w mean is exact, so the difference
+ *                                                  is rounded once; 1 / (rms sqrt(w)) is formed
+ *                                                  in FP64 and rounded once)
  * A detection at (row, t) when the largest S/N_w[t] over the widths defined there exceeds
  * k_sigma (the smallest width on ties); it is written as {row, w, t, B_w[t], S/N} in
  * ascending (row, t) order. Rows with rms <= 0 have no detections.

@@ -404,9 +404,22 @@ class LibraryExecutor(Executor):
         for blk, w in zip(blocks, pend):
             if w is not None:
                 self._beams[blk.beam]["n"] += 1
+        # candidate counts to pinned host memory on the serving stream, before the completion
+        # event: once the event has completed they are there, and retiring this launch does
+        # not wait for the next launch in flight on the stream
+        counts = []
+        with self._torch.cuda.stream(self.stream):
+            for r in res:
+                m = r.merged if isinstance(r, self._api.BinnedStreamResult) else r
+                if m is None or m._ncand is None:
+                    counts.append(None)
+                    continue
+                h = self._torch.empty(1, dtype=self._torch.int64, pin_memory=True)
+                h.copy_(m._ncand, non_blocking=True)
+                counts.append(h)
         ev = self._torch.cuda.Event(enable_timing=True)
         ev.record(self.stream)
-        return ev, list(blocks), res, ev0
+        return ev, list(blocks), res, ev0, counts
 
     def done(self, handle) -> bool:
         return handle[0].query()
@@ -415,16 +428,16 @@ class LibraryExecutor(Executor):
         return handle[3].elapsed_time(handle[0]) * 1e-3
 
     def results(self, handle) -> List[dict]:
-        _, blocks, res, _ = handle
+        _, blocks, res, _, counts = handle
         out = []
-        for blk, r in zip(blocks, res):
+        for blk, r, h in zip(blocks, res, counts):
             if r is None:
                 out.append({"t0": 0, "nout": 0, "ncand": 0, "filling": True})
                 continue
+            n = int(h[0]) if h is not None else 0  # copied before the launch's event
             if isinstance(r, self._api.BinnedStreamResult):
                 # a binned beam: t0 of its factor-1 run, outputs summed over the runs
                 m = r.merged
-                n = int(m.ncand()) if m._ncand is not None else 0
                 nout = sum(int(x.out.shape[1]) for _, _, x in r.segments if x is not None)
                 out.append({"t0": int(r.segments[0][1]), "nout": nout, "ncand": n, "filling": False})
                 if self.keep:
@@ -433,7 +446,6 @@ class LibraryExecutor(Executor):
                                   None if x is None else x.rms.clone()) for _, t0, x in r.segments],
                         "cand": m.candidates()}
                 continue
-            n = int(r.ncand()) if r._ncand is not None else 0
             out.append({"t0": int(r.t0), "nout": int(r.out.shape[1]), "ncand": n, "filling": False})
             if self.keep:
                 self.kept[(blk.beam, blk.seq)] = {
