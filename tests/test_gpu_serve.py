@@ -77,6 +77,9 @@ def test_server_results_equal_alone_and_oracle(torch):
         np.testing.assert_array_equal(got["mean"].cpu().numpy(), mean)
         np.testing.assert_array_equal(got["rms"].cpu().numpy(), rms)
         np.testing.assert_array_equal(got["cand"], cand)
+    # the counts the server reports (read from pinned copies taken before each launch's event)
+    reported = {(br.beam, br.seq): br.ncand for br in srv.results if not br.filling}
+    assert reported == {key: int(v[4].size) for key, v in alone.items()}
 
     # beam 0 against the oracle on the concatenated blocks
     sp = specs[0]
