@@ -109,9 +109,14 @@ typedef struct dd_stream dd_stream;
 
 /* Optional tile choice; zero fields take the library default. */
 typedef struct dd_tuning {
-  int32_t dms_per_wave;       /* DM trials each wavefront accumulates: 8 */
+  int32_t dms_per_wave;       /* DM trials each wavefront accumulates: 8, or 4 (FP32 input with
+                                 producer wavefronts: up to 14 computing wavefronts in a
+                                 1024-thread workgroup); 0 with waves 0: automatic (4 for FP32
+                                 input when one DM group's windows fit the producers' DMAs,
+                                 else 8) */
   int32_t waves;              /* computing wavefronts per workgroup, each on its own DMs
-                                 (1..8, at most 8 - producer_waves) */
+                                 (1..8, at most 8 - producer_waves; with 4 trials per
+                                 wavefront 1..14, at most 16 - producer_waves) */
   int32_t samples_per_lane;   /* output samples per lane: 8 (the tile is 512 samples) */
   int32_t chan_stage;         /* channels per LDS stage (0..8; without a producer rounded
                                  down to a divisor of waves; 0 = automatic) */

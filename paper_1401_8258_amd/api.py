@@ -586,7 +586,7 @@ class BinnedPlan(_Composite):
     def batchable(self) -> bool:
         """Whether the runs can share one batched call: the LDS-form runs need one input
         dtype, DM trials per workgroup and producer count (direct-read runs join any)."""
-        keys = {(s.plan.dtype, s.plan.tiles[1], s.plan.producer_waves) for s in self.segments
+        keys = {(s.plan.dtype, s.plan.tiles[0], s.plan.tiles[1], s.plan.producer_waves) for s in self.segments
                 if s.plan.form != "direct"}
         return len(keys) <= 1 and all(s.plan.form != "regwin" for s in self.segments)
 

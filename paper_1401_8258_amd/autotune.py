@@ -28,7 +28,7 @@ import torch
 
 from .api import Plan, torch_dtype
 
-WAVES = (8, 4, 2, 1)
+WAVES = (14, 8, 4, 2, 1)  # 14: 4 trials per wavefront beside 2 producers (FP32 LDS form only)
 STAGES = (0, 2, 4)
 FORMS = ("lds", "direct")
 # (DM trials per wavefront, samples per lane) of the direct-read form
@@ -115,9 +115,12 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
             cands.append({"form": "regwin", "tuning": None})
         elif form == "direct":
             if u8:  # the direct-read form takes 8-bit input only
-                cands += [{"form": "direct", "tuning": [g, w, spl]} for w in waves for g, spl in DIRECT_SHAPES]
+                cands += [{"form": "direct", "tuning": [g, w, spl]} for w in waves if w <= 8
+                          for g, spl in DIRECT_SHAPES]
         else:
-            cands += [{"form": "lds", "tuning": [8, w, cc]} for w in waves for cc in stages]
+            # up to 8 wavefronts: 8 trials each; more (FP32 only): the 4-trial producer form
+            cands += [{"form": "lds", "tuning": [8 if w <= 8 else 4, w, cc]} for w in waves for cc in stages
+                      if w <= 8 or torch_dtype(dtype) == torch.float32]
     trials = []
     for cand in cands:
         try:

@@ -100,6 +100,8 @@ struct KParams {
   // input bytes [tail_base, in_bytes) followed by in_bytes - tail_base bytes of padding
   const uint8_t* tail;
   int64_t tail_base, in_bytes;
+  int g;        // DM trials per computing wavefront (8; 4 in the 16-wavefront producer form)
+  int pad_;
 };
 
 // LDS layout (4-byte words): the ring's channel slots (buf, cc), each holding the four
@@ -231,12 +233,13 @@ __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, un
 
 // Epilogue: the tile's sums to the output rows (float4 stores when aligned) and the
 // tile's FP64 statistics partials (fixed wavefront reduction tree).
-__device__ __forceinline__ void store_tile(const KParams& P, const float (&acc)[kG][8], int dw, int64_t t0,
+template <int G>
+__device__ __forceinline__ void store_tile(const KParams& P, const float (&acc)[G][8], int dw, int64_t t0,
                                            int64_t tile, int lane) {
   const bool vec_ok = ((P.out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0);
   const int64_t nseg = (P.nout + kTile - 1) / kTile;
 #pragma unroll
-  for (int g = 0; g < kG; ++g) {
+  for (int g = 0; g < G; ++g) {
     const int d = dw + g;
     if (d >= P.ndm) break;
     float* orow = P.out + (int64_t)d * P.out_stride;
@@ -560,12 +563,19 @@ __device__ __forceinline__ void tile_body_u8(const KParams& P, int64_t tile, int
 // stalls until the DMA path takes them; here only the producers do, while the computing
 // wavefronts keep the LDS busy. The sums are those of the all-wavefront form: same
 // offsets, same channel order, same DD_CHAN_BLOCK folding.
-template <bool RING>
+// Producer form: wavefronts nw .. nw + nprod - 1 issue every DMA; each computing wavefront
+// owns G trials (G = 8 with up to 6 computing wavefronts in 512 threads; G = 4 with up to
+// 14 in 1024 threads, which halves each wavefront's registers so that four wavefronts share
+// a SIMD: a stage's time is set by each wavefront's serial chain of reads and adds, so more
+// computing wavefronts per stage do more trials in the same time).
+template <bool RING, int G>
 __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, int grp, float* smem) {
+  static_assert(G == 4 || G == 8, "4 or 8 trials per computing wavefront");
+  constexpr int H = G / 2;  // trials per half
   const int nw = P.nw;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gw = kG * nw;
+  const int gw = G * nw;
   const int64_t t0 = tile * kTile;
   const int dg = grp * gw;
   const unsigned sbase = lds_addr(smem);
@@ -589,33 +599,35 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
     }
     return;
   }
-  const int dw = dg + w * kG;
-  float acc[kG][8];
-  float sub[kG][8];
+  const int dw = dg + w * G;
+  float acc[G][8];
+  float sub[G][8];
 #pragma unroll
-  for (int g = 0; g < kG; ++g)
+  for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc[g][s] = 0.f, sub[g][s] = 0.f;
   const int* lds_i = reinterpret_cast<const int*>(smem);
   const unsigned lane16 = 16u * (unsigned)lane;
-  const int offw = kCopies * P.L + w * kG;  // this wavefront's 8 offsets inside a slot
+  const int offw = kCopies * P.L + w * G;  // this wavefront's G offsets inside a slot
   const int slot_bytes = 4 * (kCopies * P.L + 64);
-  // A channel's trials are read and added in two halves (trials 0-3, 4-7): the next
-  // channel's first half is read while this channel's second half is added, so eight
-  // LDS reads stay in flight during the adds; the trial offsets are read two channels
-  // ahead. Each sum still takes its channels in order.
-  auto read_half = [&](const char* cb, const int4 o, uint4 (&v)[kG]) {
-    const int off[4] = {o.x, o.y, o.z, o.w};
+  // A channel's trials are read and added in two halves: the next channel's first half is
+  // read while this channel's second half is added, so G LDS reads stay in flight during
+  // the adds; the trial offsets are read two channels ahead. Each sum still takes its
+  // channels in order.
+  struct Half {
+    int o[H];
+  };
+  auto read_half = [&](const char* cb, const Half& o, uint4 (&v)[G]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const uint4* a = reinterpret_cast<const uint4*>(cb + off[t]);
+    for (int t = 0; t < H; ++t) {
+      const uint4* a = reinterpret_cast<const uint4*>(cb + o.o[t]);
       v[2 * t] = a[0];
       v[2 * t + 1] = a[64];
     }
   };
-  auto add_half = [&](const uint4 (&v)[kG], int g0) {
+  auto add_half = [&](const uint4 (&v)[G], int g0) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < H; ++t) {
       const uint32_t x[8] = {v[2 * t].x,     v[2 * t].y,     v[2 * t].z,     v[2 * t].w,
                              v[2 * t + 1].x, v[2 * t + 1].y, v[2 * t + 1].z, v[2 * t + 1].w};
 #pragma unroll
@@ -624,7 +636,7 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
     // the half's sums exist before any later LDS read issues: the next reads then reuse
     // these registers instead of taking a second set
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < H; ++t)
       asm volatile("" : "+v"(sub[g0 + t][0]), "+v"(sub[g0 + t][1]), "+v"(sub[g0 + t][2]), "+v"(sub[g0 + t][3]),
                    "+v"(sub[g0 + t][4]), "+v"(sub[g0 + t][5]), "+v"(sub[g0 + t][6]), "+v"(sub[g0 + t][7])
                    :
@@ -635,25 +647,31 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
     const int buf = st % P.nb;
     const int n_here = min(P.cs, P.nchan - st * P.cs);
     const char* cb0 = reinterpret_cast<const char*>(lds_i + slot_word(P, buf, 0)) + lane16;
-    const int4* op = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, 0) + offw);
     const int last = n_here - 1;
-    auto offsets = [&](int cc, int4& a, int4& b) {  // offsets of stage channel min(cc, last)
+    auto offsets = [&](int cc, Half& a, Half& b) {  // offsets of stage channel min(cc, last)
       const int4* q = reinterpret_cast<const int4*>(lds_i + slot_word(P, buf, min(cc, last)) + offw);
-      a = q[0];
-      b = q[1];
+      if constexpr (G == 8) {
+        const int4 x = q[0], y = q[1];
+        a = Half{{x.x, x.y, x.z, x.w}};
+        b = Half{{y.x, y.y, y.z, y.w}};
+      } else {
+        const int4 x = q[0];
+        a = Half{{x.x, x.y}};
+        b = Half{{x.z, x.w}};
+      }
     };
     auto fold = [&](int cc) {
       const int c = st * P.cs + cc;
       if ((c & (DD_CHAN_BLOCK - 1)) == 0 && c != 0) {
 #pragma unroll
-        for (int g = 0; g < kG; ++g)
+        for (int g = 0; g < G; ++g)
 #pragma unroll
           for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s], sub[g][s] = 0.f;
       }
     };
-    int4 oa, ob, na, nb;  // offsets of the channel being read, of the next one
+    Half oa, ob, na, nb;  // offsets of the channel being read, of the next one
     offsets(0, oa, ob);
-    uint4 va[kG], vb[kG];
+    uint4 va[G], vb[G];
     read_half(cb0, oa, va);
     offsets(1, na, nb);
     read_half(cb0, ob, vb);
@@ -662,38 +680,38 @@ __device__ __forceinline__ void tile_body_prod(const KParams& P, int64_t tile, i
     for (int cc = 0; cc < last; ++cc) {
       fold(cc);
       const char* cbn = cb0 + (cc + 1) * slot_bytes;
-      int4 na2, nb2;
+      Half na2, nb2;
       add_half(va, 0);
       read_half(cbn, na, va);
       offsets(cc + 2, na2, nb2);
-      add_half(vb, 4);
+      add_half(vb, H);
       read_half(cbn, nb, vb);
       na = na2;
       nb = nb2;
     }
     fold(last);
     add_half(va, 0);
-    add_half(vb, 4);
+    add_half(vb, H);
   }
 #pragma unroll
-  for (int g = 0; g < kG; ++g)
+  for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc[g][s] += sub[g][s];
-  store_tile(P, acc, dw, t0, tile, lane);
+  store_tile<G>(P, acc, dw, t0, tile, lane);
 }
 
 // How a kernel instantiation moves input into LDS. Each instantiation carries only the
 // DMA code it runs (the 4-byte form's descriptor tables and loop would cost the 16-byte
 // form registers); kAny picks per item, for batches that mix the two.
-enum Form { kX1 = 0, kX4 = 1, kProd = 2, kAny = 3 };
+enum Form { kX1 = 0, kX4 = 1, kProd = 2, kAny = 3, kProd4 = 4 };
 
 template <typename TIn, bool RING, int F>
 __device__ __forceinline__ void tile_body_ring(const KParams& P, int64_t tile, int grp, float* smem) {
   if constexpr (std::is_same<TIn, uint8_t>::value) {
     tile_body_u8<RING>(P, tile, grp, smem);
-  } else if constexpr (F == kProd) {
+  } else if constexpr (F == kProd || F == kProd4) {
     static_assert(std::is_same<TIn, float>::value, "producer wavefronts carry FP32 input");
-    tile_body_prod<RING>(P, tile, grp, smem);
+    tile_body_prod<RING, F == kProd4 ? 4 : 8>(P, tile, grp, smem);
   } else if constexpr (F == kX4) {
     tile_body_impl<TIn, RING, true>(P, tile, grp, smem);
   } else if constexpr (F == kAny && std::is_same<TIn, float>::value) {
@@ -716,8 +734,11 @@ __device__ __forceinline__ void tile_body(const KParams& P, int64_t tile, int gr
 
 // Plain launch: one work unit per workgroup; each XCD (workgroups lin, lin + 8, ...)
 // takes a contiguous run of units, tile-major, so the DM groups of a tile share L2.
+// Threads per workgroup a form may launch: 16 wavefronts for the 4-trial producer form.
+constexpr int max_threads(int F) { return F == kProd4 ? 1024 : kMaxThreads; }
+
 template <typename TIn, int F>
-__global__ __launch_bounds__(kMaxThreads) void dedisp_tile(KParams P) {
+__global__ __launch_bounds__(max_threads(F)) void dedisp_tile(KParams P) {
   extern __shared__ __align__(16) float smem[];
   const int64_t lin = blockIdx.x;
   const int64_t per = (P.nitems + 7) / 8;
@@ -750,7 +771,8 @@ __device__ __forceinline__ KParams load_params(const KParams* items, int i) {
 }
 
 template <typename TIn, int F>
-__global__ __launch_bounds__(kMaxThreads) void dedisp_batch(const KParams* items, const int64_t* start, int nitems) {
+__global__ __launch_bounds__(max_threads(F)) void dedisp_batch(const KParams* items, const int64_t* start,
+                                                              int nitems) {
   extern __shared__ __align__(16) float smem[];
   const int x = blockIdx.x & 7;
   ci64_t st_c = (ci64_t)(start + (int64_t)x * (nitems + 1));
@@ -1019,7 +1041,8 @@ using KernFn = void (*)(KParams);
 
 KernFn pick_kernel(int dtype, const KParams& P) {
   if (dtype == DD_F32)
-    return P.nprod > 0 ? dedisp_tile<float, kProd> : P.x4 ? dedisp_tile<float, kX4> : dedisp_tile<float, kX1>;
+    return P.nprod > 0 ? (P.g == 4 ? dedisp_tile<float, kProd4> : dedisp_tile<float, kProd>)
+                       : P.x4 ? dedisp_tile<float, kX4> : dedisp_tile<float, kX1>;
   if (dtype == DD_F16) return dedisp_tile<__half, kX1>;
   return dedisp_tile<uint8_t, kX1>;
 }
@@ -1030,6 +1053,7 @@ using BatchFn = void (*)(const KParams*, const int64_t*, int);
 BatchFn pick_batch_kernel(int dtype, int form) {
   if (dtype == DD_F32) {
     if (form == kProd) return dedisp_batch<float, kProd>;
+    if (form == kProd4) return dedisp_batch<float, kProd4>;
     if (form == kX4) return dedisp_batch<float, kX4>;
     if (form == kX1) return dedisp_batch<float, kX1>;
     return dedisp_batch<float, kAny>;
@@ -1095,6 +1119,7 @@ int build_params(const dd_plan* p, const InView& in, const int32_t* d_table, int
   P->nstages = (p->nchan + g.cs - 1) / g.cs;
   P->x4 = g.x4;
   P->nw = p->tiles.w;
+  P->g = p->tiles.g;
   P->nprod = g.prod;
   P->ndw = g.ndw;
   if (p->dtype == DD_U8 && in.ring_len == 0) {
@@ -1513,7 +1538,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   std::vector<Outputs> outs((size_t)n);
   std::vector<int64_t> nouts((size_t)n);
   std::vector<dd::WsLayout> lays((size_t)n);
-  int32_t dtype = -1, waves = -1, prod = -1;
+  int32_t dtype = -1, waves = -1, prod = -1, per_wave = -1;
   int64_t lds = 0;
   for (int32_t i = 0; i < n; ++i) {
     const dd_batch_item& it = items[i];
@@ -1526,8 +1551,8 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
                                               ": register-window plans are not batched; use DD_FORM_LDS");
     const bool is_direct = p->launch.form == dd::kFormDirect;
     if (!is_direct) {
-      if (dtype < 0) dtype = p->dtype, waves = p->tiles.w, prod = p->launch.prod;
-      if (p->dtype != dtype || p->tiles.w != waves || p->launch.prod != prod)
+      if (dtype < 0) dtype = p->dtype, waves = p->tiles.w, prod = p->launch.prod, per_wave = p->tiles.g;
+      if (p->dtype != dtype || p->tiles.w != waves || p->launch.prod != prod || p->tiles.g != per_wave)
         return dd::fail(DD_ERR_UNSUPPORTED, "LDS-form batch items must share the input dtype, the DM trials per "
                                             "workgroup and the producer wavefront count");
     }
@@ -1606,7 +1631,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch descriptors)");
     int form = -1;
     for (int32_t i = 0; i < m; ++i) {
-      const int f = P[i].nprod > 0 ? kProd : P[i].x4 ? kX4 : kX1;
+      const int f = P[i].nprod > 0 ? (P[i].g == 4 ? kProd4 : kProd) : P[i].x4 ? kX4 : kX1;
       form = form < 0 || form == f ? f : kAny;  // producer counts already agree across items
     }
     BatchFn k = pick_batch_kernel(dtype, form);

@@ -380,7 +380,8 @@ class LibraryExecutor(Executor):
                 plan = self._beams[blk.beam]["stream"].plan
                 # direct-read plans of any tiles share a call; LDS-form plans need one dtype,
                 # wavefront count and producer count per call
-                key = ("direct",) if plan.form == "direct" else (plan.dtype, plan.tiles[1], plan.producer_waves)
+                key = ("direct",) if plan.form == "direct" else (plan.dtype, plan.tiles[0], plan.tiles[1],
+                                                                 plan.producer_waves)
                 groups[key].append(i)
         res: List[object] = [None] * len(blocks)
         for idx in groups.values():

@@ -202,7 +202,9 @@ def test_every_workload_has_a_launch_geometry(lib):
 
 
 def test_producer_wavefront_plans(lib):
-    """Producer wavefronts (FP32 only, opt-in): tuning checks and the ring bounds they need.
+    """Producer wavefronts (FP32 only; the default there): tuning checks and the ring bounds
+    they need. The automatic FP32 plan is the 4-trial form, 14 computing wavefronts beside 2
+    producers.
 
     Each producer issues whole stage channels: L/64 16-byte DMAs for the four copies and
     one for the trial offsets, so (cs / producers) * (L/64 + 1) per stage, and with nb - 1
@@ -211,7 +213,10 @@ def test_producer_wavefront_plans(lib):
     freq = fbsynth.channel_freqs(428.0, 20 / 1024, 1024)
     dm = fbsynth.dm_trials(0, 0.1, 2048)
     auto = _launch_ok(lib, freq, dm, 51.2e-6)
-    assert (auto.waves, auto.producer_waves, auto.launch_stage, auto.launch_ring) == (6, 2, 6, 2)
+    assert (auto.dms_per_wave, auto.waves, auto.producer_waves, auto.launch_stage, auto.launch_ring) == \
+        (4, 14, 2, 6, 2)
+    eight = _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 0, 8, 0, 0))
+    assert (eight.dms_per_wave, eight.waves, eight.producer_waves, eight.launch_stage) == (8, 6, 2, 6)
     plain = _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 0, 8, 0, -1))
     assert plain.producer_waves == 0 and plain.waves == 8  # every wavefront issues its share
     assert _launch_ok(lib, freq, dm, 51.2e-6, 0, (8, 8, 8, 0, 0)).producer_waves == 0  # no room beside 8
@@ -255,6 +260,29 @@ def _binning(lib, freq, tsamp, dms, max_log2):
                              int(dms.size), int(max_log2), C.byref(diag), out.ctypes.data_as(C.POINTER(C.c_int32)))
     return rc, diag.value, out
 
+
+
+def test_four_trial_producer_plans(lib):
+    """4 DM trials per computing wavefront: FP32 producer form only, at most 14 computing
+    wavefronts and 16 in all (1024 threads); other dtypes, no producer, or too many
+    wavefronts are refused."""
+    freq = fbsynth.channel_freqs(428.0, 20.0 / 1024, 1024)
+    dms = fbsynth.dm_trials(0.0, 0.1, 2048)
+    info = lib_mod.PlanInfo()
+    for tun, waves in [((4, 14, 8, 0, 2, 0), 14), ((4, 0, 8, 0, 2, 0), 14), ((4, 7, 8, 3, 1, 0), 7)]:
+        rc, h = _create(lib, freq, dms, 51.2e-6, 0, tun)
+        assert rc == 0, lib.dd_last_error()
+        lib.dd_plan_query(h, 1 << 20, C.byref(info))
+        assert (info.dms_per_wave, info.waves) == (4, waves)
+        assert info.producer_waves == tun[4] and info.kernel_form == lib_mod.DD_FORM_LDS
+        assert 4 * waves <= 64  # one DMA of 64 lanes carries a group's trial offsets
+        lib.dd_plan_destroy(h)
+    for dtype, tun in [(0, (4, 15, 8, 0, 1, 0)), (0, (4, 14, 8, 0, 3, 0)), (0, (4, 8, 8, 0, -1, 0)),
+                       (1, (4, 8, 8, 0, 0, 0)), (2, (4, 8, 8, 0, 0, lib_mod.DD_FORM_LDS)),
+                       (0, (6, 8, 8, 0, 2, 0))]:
+        rc, h = _create(lib, freq, dms, 51.2e-6, dtype, tun)
+        assert rc == lib_mod.DD_ERR_UNSUPPORTED, (dtype, tun)
+        assert not h.value
 
 @pytest.mark.parametrize("f_top,nchan,bw,tsamp,step,ndm,max_log2", [
     (428.0, 64, 20.0, 51.2e-6, 0.1, 128, 4),

@@ -51,9 +51,11 @@ def test_no_packed_fp32_and_no_scratch(device_code):
         assert int(m.group(1)) == 0
 
 
-# FP32 kernels by DMA form: 16-byte DMAs from every wavefront, and producer wavefronts
+# FP32 kernels by DMA form: 16-byte DMAs from every wavefront, and producer wavefronts (8 and 4
+# trials per computing wavefront)
 FP32_KERNELS = ["_ZN12_GLOBAL__N_111dedisp_tileIfLi1EEEvNS_7KParamsE",
-                "_ZN12_GLOBAL__N_111dedisp_tileIfLi2EEEvNS_7KParamsE"]
+                "_ZN12_GLOBAL__N_111dedisp_tileIfLi2EEEvNS_7KParamsE",
+                "_ZN12_GLOBAL__N_111dedisp_tileIfLi4EEEvNS_7KParamsE"]
 
 
 @pytest.mark.parametrize("sym", FP32_KERNELS)
