@@ -1638,7 +1638,9 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     rc = set_lds((const void*)k, lds);
     if (rc) return rc;
     int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
     // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
     // `units` is the largest per-XCD share
     const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, units * 8) / 8 * 8);
