@@ -757,7 +757,41 @@ def main():
     u8 = {"form": plan8.form, "tiles": list(plan8.tiles[:2]), **u8res,
           "adds_per_s_prep_and_kernel": adds / (u8res["prep_and_kernel_ms"] * 1e-3),
           "dm_trial_samples_per_s": beam.ndm * nout / (u8res["step_ms"] * 1e-3)}
-    del x8, ws8, plan8
+    # RFI mitigation of the 8-bit codes in place (window 256, order 6): the bandpass and
+    # window means (one read), the host fit, then channel and spectrum clipping (a read for
+    # the spectra; windows are written only where replaced)
+    x8r = torch.empty_like(x8)
+    win8 = 256
+    avg8 = torch.empty(beam.nchan, dtype=torch.float64, device=x.device)
+    wm8 = torch.empty((beam.nchan, -(-nsamp // win8)), dtype=torch.float64, device=x.device)
+    fl8 = torch.empty((beam.nchan, -(-nsamp // win8)), dtype=torch.int32, device=x.device)
+    ms_bp8 = ms_cl8 = 0.0
+    for rep in range(4):  # the first run warms up
+        x8r.copy_(x8)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        _lib.check(lib.dd_bandpass_u8(vp(x8r), beam.nchan, nsamp, nsamp, win8, vp(avg8), vp(wm8), st))
+        e1.record(stream)
+        fit8, _, fmean8 = dd.bandpass_fit(avg8.cpu().numpy(), 6)
+        d_fit8 = torch.from_numpy(fit8).cuda()
+        e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        _lib.check(lib.dd_rfi_clip_u8(vp(x8r), beam.nchan, nsamp, nsamp, vp(d_fit8), 8.0, win8, vp(wm8), vp(fl8),
+                                      fmean8, 3.2, st))
+        e3.record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            ms_bp8 += e0.elapsed_time(e1) / 3
+            ms_cl8 += e2.elapsed_time(e3) / 3
+    u8["rfi"] = {"kernels": "bandpass_windows_u8; chan_flag + chan_apply_u8 + spec_clip_u8", "window": win8,
+                 "order": 6, "chan_threshold": 8.0, "spec_threshold": 3.2,
+                 "bandpass_ms": round(ms_bp8, 3),
+                 "bandpass_gbs": round(beam.nchan * nsamp / (ms_bp8 * 1e-3) / 1e9, 1),
+                 "clip_ms": round(ms_cl8, 3),
+                 "clip_gbs_one_read": round(beam.nchan * nsamp / (ms_cl8 * 1e-3) / 1e9, 1),
+                 "windows_flagged": int(fl8.sum().item())}
+    del x8, x8r, ws8, plan8
 
     res = {
         "metric": "DM-trial*samples/s",

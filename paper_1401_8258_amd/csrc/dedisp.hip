@@ -810,29 +810,23 @@ __device__ double block_sum256(double v, double* red) {
   return r;
 }
 
-// stat[d] = {mean, rms, threshold} in FP64; mean/rms also as FP32 outputs.
+// stat[d] = {mean, rms, threshold} in FP64; mean/rms also as FP32 outputs. Called by a whole
+// wavefront for its series: lane l sums the partials of tiles l, l + 64, l + 128, ... in
+// that order (each step a coalesced 1 KB read of the wavefront), then the 64 lane sums meet
+// in a fixed butterfly. The order depends on the number of tiles only, so every launch,
+// batch and kernel form gives the same bits.
 __device__ __forceinline__ void finalize_series(const double* __restrict__ part, int64_t nseg, int d, int64_t nout,
                                                 double k, float* mean, float* rms, double* stat) {
-  // One thread per series: the loads of 8 tiles are issued together and then added in tile
-  // order, so the sums are the ones a plain sequential loop gives while the loop is no longer
-  // one memory latency per tile (a plan with few series has only a few such threads).
+  const int lane = threadIdx.x & 63;
   const double* pd = part + (int64_t)d * nseg * 2;
   double s = 0.0, ss = 0.0;
-  int64_t g = 0;
-  for (; g + 8 <= nseg; g += 8) {
-    double v[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = pd[g * 2 + j];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      s += v[2 * j];
-      ss += v[2 * j + 1];
-    }
-  }
-  for (; g < nseg; ++g) {
+  for (int64_t g = lane; g < nseg; g += 64) {
     s += pd[g * 2];
     ss += pd[g * 2 + 1];
   }
+  s = wave_sum_fixed(s);
+  ss = wave_sum_fixed(ss);
+  if (lane != 0) return;
   const double n = (double)nout;
   const double m = s / n;
   double var = ss / n - m * m;
@@ -903,11 +897,12 @@ __device__ __forceinline__ void write_segment(const float* __restrict__ out, int
   }
 }
 
+// One wavefront per series (four per 256-thread block).
 __global__ __launch_bounds__(256) void stats_finalize(const double* __restrict__ part, int64_t nseg,
                                                       int ndm, int64_t nout, double k, float* mean,
                                                       float* rms, double* stat) {
-  const int d = blockIdx.x * 256 + threadIdx.x;
-  if (d >= ndm) return;
+  const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (d >= ndm) return;  // uniform for the wavefront
   finalize_series(part, nseg, d, nout, k, mean, rms, stat);
 }
 
@@ -964,7 +959,7 @@ __device__ __forceinline__ int find_item(const TailItem* items, int n, int64_t k
 }
 
 __global__ __launch_bounds__(256) void stats_finalize_batch(const TailItem* __restrict__ items, int n, int64_t nser) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // one wavefront per series
   if (i >= nser) return;
   const TailItem& it = items[find_item(items, n, i, [](const TailItem& t) { return t.ser0; })];
   finalize_series(it.part, it.ntiles, (int)(i - it.ser0), it.nout, it.k, it.mean, it.rms, it.stat);
@@ -1149,7 +1144,7 @@ int launch_tail(const dd_plan* p, int64_t nout, const Outputs& o, char* ws, cons
   const int64_t ntiles = (nout + kTile - 1) / kTile;
   double* part = reinterpret_cast<double*>(ws + l.part_off);
   double* stat = reinterpret_cast<double*>(ws + l.thr_off);
-  hipLaunchKernelGGL(stats_finalize, dim3((unsigned)((p->ndm + 255) / 256)), dim3(256), 0, st, part, ntiles,
+  hipLaunchKernelGGL(stats_finalize, dim3((unsigned)((p->ndm + 3) / 4)), dim3(256), 0, st, part, ntiles,
                      p->ndm, nout, (double)o.k, o.mean, o.rms, stat);
   if (o.k > 0.f && o.ncand) {
     const int64_t nseg = (nout + dd::kStatSeg - 1) / dd::kStatSeg;
@@ -1697,7 +1692,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     if (e == hipSuccess && !cands.empty())
       e = hipMemcpyAsync(dC, cands.data(), cands.size() * sizeof(TailItem), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch statistics descriptors)");
-    hipLaunchKernelGGL(stats_finalize_batch, dim3((unsigned)((nser + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(stats_finalize_batch, dim3((unsigned)((nser + 3) / 4)), dim3(256), 0, st,
                        (const TailItem*)dT, (int)tails.size(), nser);
     if (nunit > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many candidate segments in one batch");
     if (!cands.empty() && nunit > 0) {
