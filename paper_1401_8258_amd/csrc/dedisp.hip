@@ -10,12 +10,14 @@
 //                  input is staged as 32-bit words, 8-bit input as bytes (own tile
 //                  body). One instantiation per DMA form: 4-byte DMAs, 16-byte DMAs
 //                  issued by every wavefront, or producer wavefronts that issue them
-//                  all (the FP32 default). The epilogue writes the tile and its FP64
-//                  statistics partials.
+//                  all, beside computing wavefronts of 8 trials (512 threads) or of 4
+//                  (1024 threads: the FP32 default). The epilogue writes the tile and
+//                  its FP64 statistics partials.
 //   dedisp_batch   the same tile bodies in one persistent launch over many inputs.
 //   stats_finalize per-series mean and standard deviation from the FP64 partial sums
 //                  (sum x, sum x^2) that dedisp_tile writes per 512-sample tile with a
-//                  fixed wavefront reduction tree; tiles are summed in order.
+//                  fixed wavefront reduction tree; one wavefront per series adds them in
+//                  a fixed lane-strided order and butterfly.
 //   cand_*         n-sigma detections: per-segment counts, one exclusive scan, and an
 //                  ordered ballot compaction, so candidates come out in (d, t) order.
 //   ring_append    copies a block into a stream's per-channel ring and its mirror.
@@ -50,9 +52,10 @@ constexpr int kMaxThreads = 512;
 
 // ------------------------------------------------------------------ dedispersion kernel
 //
-// Work unit = (512-sample time tile, group of W*8 DM trials). Wavefront w of the
-// workgroup owns trials dg + 8w .. dg + 8w + 7; lane l owns output samples
-// t0 + 4l .. t0 + 4l + 3 and t0 + 256 + 4l .. t0 + 256 + 4l + 3 of the tile.
+// Work unit = (512-sample time tile, group of W*G DM trials; G = 8, or 4 in the 16-wavefront
+// producer form). Computing wavefront w of the workgroup owns trials dg + Gw .. dg + Gw +
+// G - 1; lane l owns output samples t0 + 4l .. t0 + 4l + 3 and t0 + 256 + 4l .. t0 + 256 +
+// 4l + 3 of the tile.
 //
 // Channel vectors (tile plus the group's delay spread, Eq. channelDispersionEquation)
 // reach LDS by DMA (global_load_lds) through a ring of nb stages of cs channels,

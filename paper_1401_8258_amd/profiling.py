@@ -15,7 +15,7 @@ kernel's dispatches with the largest grid count (the full-size launch, when the 
 command also runs the kernel on smaller inputs). The record stores the SHA-256 of the
 kernel source and the launch geometry of the profiled plan, so a reader can tell when the
 kernel has changed since the counters were taken (``source_digest``: the device code of the
-listed files).
+listed files, comments and layout aside).
 """
 from __future__ import annotations
 
@@ -23,6 +23,7 @@ import argparse
 import csv
 import hashlib
 import json
+import re
 import statistics
 import sys
 
@@ -33,8 +34,18 @@ import sys
 HOST_MARKER = b"// ------------------------------------------------------------------ host side"
 
 
+def _code_only(text: bytes) -> bytes:
+    """The code of a C++ source without its comments, blank lines and indentation, so that a
+    counter record only goes stale when the code changes (the device sources carry no
+    comment markers inside string literals)."""
+    t = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
+    t = re.sub(rb"//[^\n]*", b"", t)
+    return b"\n".join(line.strip() for line in t.splitlines() if line.strip())
+
+
 def source_digest(paths) -> str:
-    """SHA-256 over the device part of each file (all of it when it has no host marker)."""
+    """SHA-256 over the code of the device part of each file (all of it when it has no host
+    marker), comments and layout aside."""
     if isinstance(paths, str):
         paths = paths.split(",")
     h = hashlib.sha256()
@@ -42,7 +53,7 @@ def source_digest(paths) -> str:
         with open(path, "rb") as f:
             text = f.read()
         cut = text.find(HOST_MARKER)
-        h.update(text if cut < 0 else text[:cut])
+        h.update(_code_only(text if cut < 0 else text[:cut]))
     return h.hexdigest()
 
 
