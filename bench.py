@@ -228,10 +228,9 @@ def _serve_batch_vs_single(ex, specs, beams, pool, nfill, nblocks, rounds=3):
 
 def batch_run(reps):
     """Config-4 batch: 16 uneven u8 beams (N(128,16) codes drawn on the device) with
-    direct-read tiles from the autotuner (each beam's best under one common wavefront count)
-    in one batched call (one launch per trials-per-wavefront value, then one launch per
-    statistics/candidate step for all beams), against each beam alone with its own best
-    tiles over all wavefront counts."""
+    direct-read tiles from the autotuner (each beam's own best) in one batched call (one
+    launch per distinct tile shape and wavefront count, then one launch per
+    statistics/candidate step for all beams), against each beam alone on the same tiles."""
     import torch
 
     import fbsynth
@@ -250,13 +249,11 @@ def batch_run(reps):
     tb = autotune.tune_batch(beams, waves=(8, 4, 2, 1), stages=(0,), reps=1, inputs=xs, log=log,
                              forms=("direct",))
     t_tune = time.perf_counter() - t_tune
-    # batched: each beam's best tiles under the one wavefront count that minimises the sum
+    # each beam's own best tiles over all wavefront counts, batched and one at a time
     plans = [autotune.make_plan(f, ts, dm, "u8", c) for (f, ts, dm, _, _), c in zip(beams, tb["choices"])]
-    # one at a time: each beam's own best tiles over all wavefront counts
-    own = [autotune.make_plan(f, ts, dm, "u8", c) for (f, ts, dm, _, _), c in zip(beams, tb["own_best"])]
     outs = [dd.api.alloc_outputs(p.ndm, x.shape[1] - p.maxdelay, x.device, 6.0, 1 << 16) for p, x in zip(plans, xs)]
     jobs = list(zip(plans, xs))
-    for p, x in jobs + list(zip(own, xs)):  # workspaces allocated before timing
+    for p, x in jobs:  # workspaces allocated before timing
         p.workspace(x.shape[1], x.device)
 
     def batched():
@@ -276,7 +273,7 @@ def batch_run(reps):
     ms_batch = timed(batched)
     # each beam alone with its own best tiles, timed one by one
     per_beam = []
-    for p, x, o in zip(own, xs, outs):
+    for p, x, o in zip(plans, xs, outs):
         ms = timed(lambda: dd.batch_dedisperse([(p, x)], k_sigma=6.0, cand_cap=1 << 16, outputs=[o]))
         nout = x.shape[1] - p.maxdelay
         per_beam.append({"nchan": p.nchan, "ndm": p.ndm, "nout": nout, "form": p.form, "tiles": list(p.tiles[:2]),
@@ -289,7 +286,8 @@ def batch_run(reps):
             "higher_is_better": True, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "16 uneven u8 beams (nchan 256/512/1024/4096, 500-4096 DMs, nsamp 2^16-2^19), "
                                    "batched, stats + 6-sigma candidates",
-                       "common_waves": tb["waves"], "tunings": tb["choices"], "own_best_tunings": tb["own_best"],
+                       "tunings": tb["choices"],
+                       "kernel_launches": len({(c["form"], tuple(c["tuning"])) for c in tb["choices"]}),
                        "tune_s": round(t_tune, 1)},
             "adds_per_s": adds / (ms_batch * 1e-3),
             "one_at_a_time_ms": round(ms_single, 3),
@@ -346,20 +344,25 @@ def binned_stream_run(nblocks):
     outs = api.alloc_outputs(bp.dm.size, block, "cuda", 6.0, 1 << 16)
     nfb = -(-bp.fill_nsamp // block)
     for k in range(nfb):
-        bs.push(pool[k % 3], stats=False, batched=bp.batchable)
+        bs.push(pool[k % 3], stats=False)
     torch.cuda.synchronize()
-    e0.record(stream)
-    for k in range(nblocks):
-        r = bs.push(pool[(nfb + k) % 3], k_sigma=6.0, outputs=outs, batched=bp.batchable)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_b = e0.elapsed_time(e1) / nblocks
-    assert r is not None and all(x is not None for _, _, x in r.segments)
+    ms_by = {}
+    for batched in (False, True) if bp.batchable else (False,):  # the runs one launch each, then batched
+        e0.record(stream)
+        for k in range(nblocks):
+            r = bs.push(pool[(nfb + k) % 3], k_sigma=6.0, outputs=outs, batched=batched)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_by[batched] = e0.elapsed_time(e1) / nblocks
+        assert r is not None and all(x is not None for _, _, x in r.segments)
+    ms_b = min(ms_by.values())
     adds_b = sum((sg.d1 - sg.d0) * bp.freq.size * (block >> sg.log2) for sg in bp.segments)
     res["binned"] = {"ring_bytes": bs.ring_bytes, "max_log2": 4, "dm_diag": round(bp.dm_diag, 4),
                      "runs": [{"factor": 1 << sg.log2, "ndm": sg.d1 - sg.d0, "maxdelay": sg.plan.maxdelay,
                                "form": sg.plan.form} for sg in bp.segments],
-                     "batched_runs": bp.batchable, "ms_per_block": round(ms_b, 3), "adds_per_block": adds_b}
+                     "ms_per_block": round(ms_b, 3), "ms_per_block_unbatched": round(ms_by[False], 3),
+                     "ms_per_block_batched": round(ms_by[True], 3) if True in ms_by else None,
+                     "adds_per_block": adds_b}
     res["ring_bytes_ratio"] = round(res["plain"]["ring_bytes"] / bs.ring_bytes, 2)
     res["speedup_per_block"] = round(ms_plain / ms_b, 3)
     res["block_s"] = block * sp["tsamp"]

@@ -284,11 +284,15 @@ int dd_stream_set_gap_fill(dd_stream* s, int32_t enable);
 int dd_candidates_check(const int64_t* d_ncand, int64_t cand_cap, void* stream, int64_t* ncand_out);
 
 /*
- * Batched launch (uneven beams in one persistent launch). Each item names a plan,
- * an input already resident on the device, and its outputs; or a stream whose
- * block has already been appended with dd_stream_append. All items run in one
- * kernel launch that walks a device queue of (item, DM group, time tile) work;
- * the results equal those of one dd_dedisperse per item, bit for bit.
+ * Batched launch (uneven beams in few persistent launches). Each item names a plan, an
+ * input already resident on the device, and its outputs; or a stream whose block has
+ * already been appended with dd_stream_append. Items on the same kernel and workgroup shape
+ * (LDS form: input dtype, computing and producer wavefronts, DM trials per wavefront;
+ * direct-read form: DM trials per wavefront, samples per lane, wavefronts) run in one
+ * launch that walks a device queue of (item, DM group, time tile) work, one launch per
+ * distinct shape, each item on its own plan's tiles; then the statistics and candidates of
+ * all items take one launch per step. The results equal those of one dd_dedisperse per
+ * item, bit for bit. Register-window plans are refused (DD_ERR_UNSUPPORTED).
  */
 typedef struct dd_batch_item {
   const dd_plan* plan;
@@ -436,7 +440,7 @@ int dd_downfactor(const void* d_in, int32_t in_dtype, int64_t nchan, int64_t nsa
  * (DD_FORM_DIRECT) applies to the factor-1 run only; DD_FORM_LDS and DD_FORM_REGWIN to every
  * run; DD_FORM_AUTO with tile fields to every run except an 8-bit factor-1 run, which keeps
  * the direct-read form. Without a tuning each run takes the planner's choice for its own
- * trials (runs on different tiles cannot share a batched call; see dd_binned_dedisperse).
+ * trials.
  * Host object, immutable after creation; the caller keeps its arrays. Errors as
  * dd_time_binning and dd_plan_create.
  */
@@ -463,9 +467,9 @@ int dd_binned_upload(const dd_binned* b, int64_t nsamp, void* d_workspace, int64
    d_mean/d_rms [ndm] as dd_dedisperse. Candidates of all runs form one list in ascending
    (trial, time) order: dm_index is the global trial, t the input sample where the binned
    sample starts (binned index << log2); *d_ncand the true count (as dd_dedisperse).
-   batched != 0 runs the runs' dedispersion through one dd_batch_dedisperse call (then
-   LDS-form runs must share the wavefront and producer counts, else DD_ERR_UNSUPPORTED);
-   the results are the same bit for bit. The workspace comes from dd_binned_upload for this
+   batched != 0 runs the runs' dedispersion through one dd_batch_dedisperse call
+   (DD_ERR_UNSUPPORTED when a run is in the register-window form); the results are the same
+   bit for bit. The workspace comes from dd_binned_upload for this
    nsamp. Errors as dd_dedisperse. */
 int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
                          int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,
@@ -502,8 +506,8 @@ int dd_binned_stream_create(const dd_binned* b, int64_t block_nsamp, void* d_rin
  * candidates of all runs with outputs form one list in (trial, time) order with dm_index
  * the global trial and t the input sample where the binned sample starts. Returns
  * DD_FILLING (nothing written, d_ncand untouched) while every run fills, DD_ERR_SEQUENCE
- * for a wrong seq (nothing changes), DD_ERR_UNSUPPORTED for batched != 0 when the runs
- * cannot share one batched launch (as dd_binned_dedisperse). Not thread-safe per stream.
+ * for a wrong seq (nothing changes), DD_ERR_UNSUPPORTED for batched != 0 when a run is in
+ * the register-window form (as dd_binned_dedisperse). Not thread-safe per stream.
  */
 int dd_binned_stream_push(dd_binned_stream* s, const void* d_block, int64_t nsamp, int64_t in_row_stride, int64_t seq,
                           float* d_out, int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma,

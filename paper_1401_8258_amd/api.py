@@ -310,10 +310,10 @@ def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats:
     """Dedisperse several inputs in one persistent launch (dd_batch_dedisperse).
 
     jobs: a list of (Plan, tensor) pairs and/or (Stream, (t0, nout)) pairs, the latter
-    after Stream.append returned a pending window. Direct-read plans may have any tiles
-    (one launch per trials-per-wavefront value); LDS-form plans must share the input dtype,
-    DM trials per workgroup and producer count (one persistent launch). Statistics and
-    candidates of all jobs run in one launch per step. ``outputs`` optionally gives, per job, buffers from
+    after Stream.append returned a pending window. Plans of any tiles and forms mix, except
+    the register-window form; the jobs on one kernel and workgroup shape share a persistent
+    launch, each on its own tiles. Statistics and candidates of all jobs run in one launch
+    per step. ``outputs`` optionally gives, per job, buffers from
     alloc_outputs (with ``stats`` and ``k_sigma`` matching) to write into instead of new
     ones. Returns one Result per job, equal bit for bit to the one-at-a-time calls.
     """
@@ -584,11 +584,8 @@ class BinnedPlan(_Composite):
 
     @property
     def batchable(self) -> bool:
-        """Whether the runs can share one batched call: the LDS-form runs need one input
-        dtype, DM trials per workgroup and producer count (direct-read runs join any)."""
-        keys = {(s.plan.dtype, s.plan.tiles[0], s.plan.tiles[1], s.plan.producer_waves) for s in self.segments
-                if s.plan.form != "direct"}
-        return len(keys) <= 1 and all(s.plan.form != "regwin" for s in self.segments)
+        """Whether the runs can share one batched call: none is in the register-window form."""
+        return all(s.plan.form != "regwin" for s in self.segments)
 
     @property
     def fill_nsamp(self) -> int:

@@ -10,10 +10,10 @@ in a register window, DM groups of 64 trials; "direct", 8-bit: lanes own 16 or
 the number of wavefronts sharing one LDS ring or workgroup and the channels staged
 per ring slot. ``tune``
 times every candidate on seeded random input of the beam's shape and keeps the
-fastest; ``tune_batch`` tunes a set of beams at every wavefront count and returns
-either the count that minimises their summed time (LDS-form items of one batched
-launch share a count) with each beam's best under it, or each beam's own best
-(direct-read items may differ). The timer is a parameter (``time_plan`` on the
+fastest; ``tune_batch`` tunes a set of beams at every wavefront count and returns each
+beam's own best (a batched call runs every beam on its own tiles, one launch per kernel
+shape), or on request each beam's best under the one count that minimises their summed
+time (fewer launches). The timer is a parameter (``time_plan`` on the
 device by default). Results are cached by (nchan, ndm, dtype, nsamp, DM list hash).
 """
 from __future__ import annotations
@@ -143,18 +143,19 @@ def tune(freq, tsamp, dm, dtype, nsamp, waves: Sequence[int] = WAVES, stages: Se
 def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequence[int] = STAGES, reps: int = 2,
                cache: Optional[TuneCache] = None, inputs: Optional[List[torch.Tensor]] = None,
                log=None, timer: Callable[[Plan, torch.Tensor, int], float] = time_plan,
-               forms: Sequence[str] = FORMS, common_waves: bool = True) -> dict:
+               forms: Sequence[str] = FORMS, common_waves: bool = False) -> dict:
     """Tiles for a batch of beams.
 
     beams: (freq, tsamp, dm, dtype, nsamp) per beam. Every beam is tuned at each wavefront
     count. Returns {"waves": w, "choices": [...], "tunings": [...], "own_best": [...],
-    "total_ms": t, "by_waves": {w: t}}: ``w`` is the count that minimises the summed time,
-    ``own_best`` each beam's fastest choice over all counts ({"form", "tuning", "ms"}), and
-    ``choices`` (what make_plan takes) the per-beam best under ``w`` when ``common_waves``
-    (LDS-form items of one batched launch share a count), else ``own_best`` (direct-read
-    items may differ).
+    "total_ms": t, "by_waves": {w: t}}: ``own_best`` is each beam's fastest choice over all
+    counts ({"form", "tuning", "ms"}); ``w`` the count that minimises the summed time over
+    the counts every beam fits (None if there is none), ``total_ms`` that sum. ``choices``
+    (what make_plan takes) is ``own_best``, or with ``common_waves`` each beam's best under
+    ``w`` (a batched call then needs one launch per tile shape instead of one per distinct
+    tiling).
     """
-    per_w: Dict[int, List[dict]] = {}
+    per_w: Dict[int, List[Optional[dict]]] = {}
     for w in waves:
         per_w[w] = []
         for i, (freq, tsamp, dm, dtype, nsamp) in enumerate(beams):
@@ -163,22 +164,24 @@ def tune_batch(beams: List[Tuple], waves: Sequence[int] = WAVES, stages: Sequenc
                 r = tune(freq, tsamp, dm, dtype, nsamp, waves=(w,), stages=stages, reps=reps, cache=cache, x=x,
                          timer=timer, forms=forms)
             except RuntimeError:
-                per_w[w] = None
-                break
+                r = None  # no tiling with w wavefronts fits this beam
             per_w[w].append(r)
-            if log is not None:
+            if log is not None and r is not None:
                 log(f"tune: waves {w} beam {i}: {r['form']} {r['tuning']} {r['ms']:.2f} ms")
-    totals = {w: sum(r["ms"] for r in rs) for w, rs in per_w.items() if rs is not None}
-    if not totals:
-        raise RuntimeError("no common wavefront count fits every beam")
-    wbest = min(totals, key=totals.get)
+    totals = {w: sum(r["ms"] for r in rs) for w, rs in per_w.items() if all(r is not None for r in rs)}
+    wbest = min(totals, key=totals.get) if totals else None
     own = []
     for i in range(len(beams)):
-        r = min((rs[i] for rs in per_w.values() if rs is not None), key=lambda t: t["ms"])
+        fits = [rs[i] for rs in per_w.values() if rs[i] is not None]
+        if not fits:
+            raise RuntimeError(f"no tiling fits beam {i}")
+        r = min(fits, key=lambda t: t["ms"])
         own.append({"form": r["form"], "tuning": r["tuning"], "ms": r["ms"]})
     if common_waves:
+        if wbest is None:
+            raise RuntimeError("no common wavefront count fits every beam")
         choices = [{"form": r["form"], "tuning": r["tuning"]} for r in per_w[wbest]]
     else:
         choices = [{"form": r["form"], "tuning": r["tuning"]} for r in own]
     return {"waves": wbest, "choices": choices, "tunings": [c["tuning"] for c in choices], "own_best": own,
-            "total_ms": totals[wbest], "by_waves": totals}
+            "total_ms": totals.get(wbest), "by_waves": totals}

@@ -753,11 +753,12 @@ __global__ __launch_bounds__(max_threads(F)) void dedisp_tile(KParams P) {
 }
 
 // Batched persistent launch over several plans/inputs. XCD x (workgroups x, x + 8, ...)
-// takes time tiles x, x + 8, x + 16, ... of every item, each with all its DM groups, so
-// every XCD gets an even share of every item, however uneven the items are, and the
-// groups of a tile still share that XCD's L2. start[x * (n + 1) + i] is the first of
-// XCD x's units that belongs to item i (units of an item: tile-major, group fastest).
-// The result of every unit is the one the plain launch computes for it.
+// takes the x-th eighth of every item's units (tile-major, DM group fastest): a contiguous
+// run, as in the plain launch, so that neighbouring DM groups, whose channel windows
+// overlap, share that XCD's L2, and every XCD gets an even share of every item whatever
+// its numbers of tiles and groups. start[x * (n + 1) + i] is the first of XCD x's units
+// that belongs to item i. The result of every unit is the one the plain launch computes
+// for it.
 typedef const __attribute__((address_space(4))) uint32_t* cu32_t;
 typedef const __attribute__((address_space(4))) int64_t* ci64_t;
 static_assert(sizeof(KParams) % 4 == 0, "KParams is copied as dwords");
@@ -785,11 +786,11 @@ __global__ __launch_bounds__(max_threads(F)) void dedisp_batch(const KParams* it
   for (int64_t q = blockIdx.x >> 3; q < total; q += nslot) {
     while (it + 1 < nitems && st_c[it + 1] <= q) ++it;
     const KParams P = load_params(items, it);
-    const int64_t local = q - st_c[it];
-    const int64_t tl = local / P.ngroups;
-    const int grp = (int)(local - tl * P.ngroups);
+    const int64_t local = (P.nitems * x) / 8 + (q - st_c[it]);
+    const int64_t tile = local / P.ngroups;
+    const int grp = (int)(local - tile * P.ngroups);
     block_barrier();  // the previous unit's LDS reads are done before new DMAs land
-    tile_body<TIn, F>(P, x + 8 * tl, grp, smem);
+    tile_body<TIn, F>(P, tile, grp, smem);
   }
 }
 
@@ -1518,8 +1519,10 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
 int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes) {
   dd::clear_error();
   if (!ws_bytes || n < 1 || !items) return dd::fail(DD_ERR_INVALID_ARG, "need items, n >= 1 and ws_bytes");
-  // descriptors of the LDS-form launch, then of the direct-read launch
-  *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * (n + 1) * 8) +
+  // descriptors of the LDS-form launches (the records, then per launch the XCD runs
+  // [8][items + 1]: at most 8 * 2n entries over at most n launches), then of the direct-read
+  // launches
+  *ws_bytes = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * 8 * 2 * n) +
               dd::direct_batch_desc_bytes(n) + 2 * dd::align_up((int64_t)n * (int64_t)sizeof(TailItem));
   return DD_OK;
 }
@@ -1532,12 +1535,20 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   if (!d_workspace || ws_bytes < need) return dd::fail(DD_ERR_WORKSPACE, "batch workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<KParams> P;  // LDS-form items
+  // per LDS-form item: the launch it joins (input dtype, computing and producer wavefronts,
+  // trials per wavefront: one kernel instantiation and workgroup shape) and its LDS bytes
+  struct LdsKey {
+    int32_t dtype, waves, prod, per_wave;
+    bool operator==(const LdsKey& o) const {
+      return dtype == o.dtype && waves == o.waves && prod == o.prod && per_wave == o.per_wave;
+    }
+  };
+  std::vector<LdsKey> keys;
+  std::vector<int64_t> ldss;
   std::vector<dd::DirectItem> direct;  // direct-read items
   std::vector<Outputs> outs((size_t)n);
   std::vector<int64_t> nouts((size_t)n);
   std::vector<dd::WsLayout> lays((size_t)n);
-  int32_t dtype = -1, waves = -1, prod = -1, per_wave = -1;
-  int64_t lds = 0;
   for (int32_t i = 0; i < n; ++i) {
     const dd_batch_item& it = items[i];
     dd_stream* sp = it.stream_item;
@@ -1548,12 +1559,6 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
       return dd::fail(DD_ERR_UNSUPPORTED, "batch item " + std::to_string(i) +
                                               ": register-window plans are not batched; use DD_FORM_LDS");
     const bool is_direct = p->launch.form == dd::kFormDirect;
-    if (!is_direct) {
-      if (dtype < 0) dtype = p->dtype, waves = p->tiles.w, prod = p->launch.prod, per_wave = p->tiles.g;
-      if (p->dtype != dtype || p->tiles.w != waves || p->launch.prod != prod || p->tiles.g != per_wave)
-        return dd::fail(DD_ERR_UNSUPPORTED, "LDS-form batch items must share the input dtype, the DM trials per "
-                                            "workgroup and the producer wavefront count");
-    }
     InView in;
     const int32_t* table;
     int64_t nout, t_base = 0, lay_n;
@@ -1605,47 +1610,72 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
     rc = copy_tail(kp, st);
     if (rc) return rc;
     P.push_back(kp);
-    lds = std::max(lds, g.lds);
+    keys.push_back(LdsKey{p->dtype, p->tiles.w, p->launch.prod, p->tiles.g});
+    ldss.push_back(g.lds);
   }
   char* bw = static_cast<char*>(d_workspace);
-  const int64_t lds_desc = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * (n + 1) * 8);
+  const int64_t lds_desc = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * 8 * 2 * n);
   if (!P.empty()) {
-    const int32_t m = (int32_t)P.size();
-    std::vector<int64_t> start((size_t)8 * (m + 1), 0);  // [xcd][item]
-    int64_t units = 0;
-    for (int x = 0; x < 8; ++x) {
-      int64_t* sx = &start[(size_t)x * (m + 1)];
-      for (int32_t i = 0; i < m; ++i) {
-        const int64_t ntiles = P[i].nitems / P[i].ngroups;
-        const int64_t mine = ntiles > x ? (ntiles - x + 7) / 8 : 0;  // tiles x, x + 8, ...
-        sx[i + 1] = sx[i] + mine * P[i].ngroups;
+    // one persistent launch per distinct key, in order of first appearance; each launch's
+    // records are contiguous, then its XCD runs [xcd][item + 1]
+    struct Group {
+      LdsKey key;
+      int first, count;
+      int64_t run_at, units, lds;
+    };
+    std::vector<Group> groups;
+    std::vector<KParams> rec;
+    std::vector<int64_t> start;
+    for (size_t i = 0; i < P.size(); ++i) {
+      bool seen = false;
+      for (const Group& gr : groups) seen = seen || gr.key == keys[i];
+      if (seen) continue;
+      Group gr{keys[i], (int)rec.size(), 0, 0, 0, 0};
+      for (size_t j = i; j < P.size(); ++j)
+        if (keys[j] == keys[i]) {
+          rec.push_back(P[j]);
+          gr.lds = std::max(gr.lds, ldss[j]);
+          ++gr.count;
+        }
+      gr.run_at = (int64_t)start.size();
+      start.resize(start.size() + (size_t)8 * (gr.count + 1), 0);
+      for (int x = 0; x < 8; ++x) {
+        int64_t* sx = &start[(size_t)gr.run_at + (size_t)x * (gr.count + 1)];
+        for (int j = 0; j < gr.count; ++j) {
+          const int64_t u = rec[(size_t)gr.first + j].nitems;
+          sx[j + 1] = sx[j] + (u * (x + 1)) / 8 - (u * x) / 8;  // XCD x's eighth of item j
+        }
+        gr.units = std::max(gr.units, sx[gr.count]);
       }
-      units = std::max(units, sx[m]);
+      groups.push_back(gr);
     }
     KParams* dP = reinterpret_cast<KParams*>(bw);
     int64_t* dS = reinterpret_cast<int64_t*>(bw + dd::align_up((int64_t)n * (int64_t)sizeof(KParams)));
-    hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(KParams), hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(dP, rec.data(), rec.size() * sizeof(KParams), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dS, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch descriptors)");
-    int form = -1;
-    for (int32_t i = 0; i < m; ++i) {
-      const int f = P[i].nprod > 0 ? (P[i].g == 4 ? kProd4 : kProd) : P[i].x4 ? kX4 : kX1;
-      form = form < 0 || form == f ? f : kAny;  // producer counts already agree across items
-    }
-    BatchFn k = pick_batch_kernel(dtype, form);
-    rc = set_lds((const void*)k, lds);
-    if (rc) return rc;
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
       ncu = 256;
-    // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
-    // `units` is the largest per-XCD share
-    const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, units * 8) / 8 * 8);
-    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (waves + prod)), (size_t)lds, st, (const KParams*)dP,
-                       (const int64_t*)dS, (int)m);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "dedisp_batch launch");
+    for (const Group& gr : groups) {
+      int form = -1;
+      for (int j = 0; j < gr.count; ++j) {
+        const KParams& q = rec[(size_t)gr.first + j];
+        const int f = q.nprod > 0 ? (q.g == 4 ? kProd4 : kProd) : q.x4 ? kX4 : kX1;
+        form = form < 0 || form == f ? f : kAny;  // producer counts agree within a launch
+      }
+      BatchFn k = pick_batch_kernel(gr.key.dtype, form);
+      rc = set_lds((const void*)k, gr.lds);
+      if (rc) return rc;
+      // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
+      // `units` is the largest per-XCD share
+      const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, gr.units * 8) / 8 * 8);
+      hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (gr.key.waves + gr.key.prod)), (size_t)gr.lds, st,
+                         (const KParams*)(dP + gr.first), (const int64_t*)(dS + gr.run_at), (int)gr.count);
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "dedisp_batch launch");
+    }
   }
   const int64_t direct_desc = dd::direct_batch_desc_bytes(n);
   rc = dd::launch_direct_batch(direct, bw + lds_desc, direct_desc, st);
@@ -1802,8 +1832,8 @@ int dd_binned_create(dd_binned** out, const double* freq_mhz, int32_t nchan, dou
   //  * DD_FORM_DIRECT: the factor-1 run only (8-bit input);
   //  * DD_FORM_LDS or DD_FORM_REGWIN: every run;
   //  * DD_FORM_AUTO with tile fields: every FP32 run, and an 8-bit factor-1 run keeps the
-  //    direct-read form (the tiles are LDS-form tiles; an 8-bit LDS factor-1 run could not
-  //    share a batched call with the FP32 runs anyway).
+  //    direct-read form (the tiles are LDS-form tiles; the direct-read form is the 8-bit
+  //    default).
   // Without a tuning each run takes the planner's tiles for its own trials: a common tiling
   // that every run can take (fewer trials per workgroup for the runs at small factors, whose
   // DM groups spread over more samples) was slower on the 4096-channel beams than separate
@@ -2042,18 +2072,11 @@ BinnedStreamLayout binned_stream_layout(const dd_binned* b, int64_t block) {
   return L;
 }
 
-// The batched path's condition on LDS-form runs (shared dtype, trials per workgroup and
-// producer count), checked before anything is appended.
+// The batched path's condition (no register-window run: that form is not batched), checked
+// before anything is appended.
 bool binned_batchable(const dd_binned* b) {
-  const dd_plan* first = nullptr;
-  for (const dd_binned::Run& r : b->runs) {
-    const dd_plan* p = r.plan;
-    if (p->launch.form == dd::kFormRegWin) return false;
-    if (p->launch.form == dd::kFormDirect) continue;
-    if (!first) first = p;
-    if (p->dtype != first->dtype || p->tiles.w != first->tiles.w || p->launch.prod != first->launch.prod)
-      return false;
-  }
+  for (const dd_binned::Run& r : b->runs)
+    if (r.plan->launch.form == dd::kFormRegWin) return false;
   return true;
 }
 
@@ -2146,8 +2169,7 @@ int dd_binned_stream_push(dd_binned_stream* s, const void* d_block, int64_t nsam
   if (seq != s0->next_seq && !(s0->gap_fill && seq > s0->next_seq))
     return dd::fail(DD_ERR_SEQUENCE, "expected seq " + std::to_string(s0->next_seq) + ", got " + std::to_string(seq));
   if (batched && !binned_batchable(b))
-    return dd::fail(DD_ERR_UNSUPPORTED, "batched runs need LDS-form runs that share the input dtype, the DM trials "
-                                        "per workgroup and the producer wavefront count");
+    return dd::fail(DD_ERR_UNSUPPORTED, "register-window runs are not batched; use DD_FORM_LDS or batched = 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(d_workspace);
   // the block downfactored 1 .. K times; blocks are multiples of 2^K samples, so no pair of

@@ -225,9 +225,8 @@ __global__ __launch_bounds__(512) void dedisp_direct(DRParams P) {
 // and their reads of its input meet in the shared last-level cache, as they do when the
 // items are launched one at a time. run[x][i] is the first of XCD x's workgroups on item
 // i (run[x][n] the count); the item's own units begin at its offset plus x/8 of its units.
-// The item's parameters are read through the scalar cache. Every item's trials are
-// regrouped into workgroups of the launch's wavefront count (a trial's sum does not depend
-// on which workgroup computes it); the count is the one whose items carry the most work.
+// The item's parameters are read through the scalar cache. A launch holds the items of one
+// tile shape and wavefront count, each on its own plan's DM groups.
 template <int G, int S>
 __global__ __launch_bounds__(512) void dedisp_direct_batch(const DRParams* __restrict__ items,
                                                            const int64_t* __restrict__ run, int nitems) {
@@ -392,8 +391,9 @@ int launch_direct(const dd_plan* p, const InView& in, const int32_t* d_table, in
 }
 
 int64_t direct_batch_desc_bytes(int32_t n) {
-  // the records, then per tile shape (at most five) the XCD runs [8][items + 1]
-  return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * 8 * (n + 5));
+  // the records, then per launch (a tile shape and wavefront count: at most n launches) the
+  // XCD runs [8][items + 1]
+  return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * 8 * 2 * n);
 }
 
 int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int64_t desc_bytes, void* stream) {
@@ -407,45 +407,36 @@ int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int6
     int rc = prepare(it.plan, it.in, it.table, it.nout, it.out, it.out_stride, it.part, it.quad_ws, st, &all[i]);
     if (rc) return rc;
   }
-  // records grouped by trials per wavefront (one kernel instantiation each), then per group
-  // the XCD runs after all the records
+  // records grouped by tile shape and wavefront count (one kernel instantiation and
+  // workgroup size per launch: every item keeps its own tiles), then per group the XCD runs
+  // after all the records
   std::vector<DRParams> P;
   std::vector<int64_t> run;
   struct Group { int g, sub, first, count, waves; int64_t run_at, longest; };
   std::vector<Group> groups;
   for (int shape : {11, 21, 41, 12, 22}) {
     const int g = shape / 10, sub = shape % 10;
-    // the launch's wavefront count: the one whose items carry the most work (units x
-    // channels); other items are regrouped to it
-    double work[9] = {0};
-    for (const DRParams& r : all)
-      if (r.tiles_g == g && r.tiles_s == sub) work[r.nw] += (double)r.nitems * r.nchan * r.nw;
-    Group gr{g, sub, (int)P.size(), 0, 0, 0, 0};
-    for (int w = 1; w <= 8; ++w)
-      if (work[w] > 0.0 && (gr.waves == 0 || work[w] > work[gr.waves])) gr.waves = w;
-    if (gr.waves == 0) continue;
-    for (DRParams r : all) {
-      if (r.tiles_g != g || r.tiles_s != sub) continue;
-      // groups of g x waves trials over the item's padded table (trials past it leave)
-      const int64_t ntiles = r.nitems / r.ngroups;
-      r.nw = gr.waves;
-      r.ngroups = (r.ndm_pad + g * gr.waves - 1) / (g * gr.waves);
-      r.nitems = ntiles * r.ngroups;
-      P.push_back(r);
-      ++gr.count;
-    }
-    gr.run_at = (int64_t)run.size();
-    for (int x = 0; x < 8; ++x) {
-      int64_t k = 0;
-      run.push_back(0);
-      for (int i = 0; i < gr.count; ++i) {
-        const int64_t u = P[gr.first + i].nitems;
-        k += (u * (x + 1)) / 8 - (u * x) / 8;  // XCD x's eighth of item i
-        run.push_back(k);
+    for (int w = 1; w <= 8; ++w) {
+      Group gr{g, sub, (int)P.size(), 0, w, 0, 0};
+      for (const DRParams& r : all)
+        if (r.tiles_g == g && r.tiles_s == sub && r.nw == w) {
+          P.push_back(r);
+          ++gr.count;
+        }
+      if (gr.count == 0) continue;
+      gr.run_at = (int64_t)run.size();
+      for (int x = 0; x < 8; ++x) {
+        int64_t k = 0;
+        run.push_back(0);
+        for (int i = 0; i < gr.count; ++i) {
+          const int64_t u = P[gr.first + i].nitems;
+          k += (u * (x + 1)) / 8 - (u * x) / 8;  // XCD x's eighth of item i
+          run.push_back(k);
+        }
+        gr.longest = std::max(gr.longest, k);
       }
-      gr.longest = std::max(gr.longest, k);
+      groups.push_back(gr);
     }
-    groups.push_back(gr);
   }
   char* bw = static_cast<char*>(d_desc);
   DRParams* dP = reinterpret_cast<DRParams*>(bw);

@@ -279,8 +279,8 @@ class Server:
 
 class LibraryExecutor(Executor):
     """Device side on libdedisp: one Stream (device ring with the maxdelay overlap) per
-    admitted beam, and per submitted set of blocks one batched call per group of beams that
-    can share it (all direct-read beams; LDS-form beams of one dtype and wavefront count).
+    admitted beam, and per submitted set of blocks one batched call over all of them (one
+    persistent launch per kernel shape, each beam on its own tiles).
     A beam with time binning (``max_log2 > 0``) has a BinnedStream instead, one ring per run
     at its binned sampling time, and is pushed on its own after the batched calls.
 
@@ -374,17 +374,10 @@ class LibraryExecutor(Executor):
         for blk in blocks:
             b = self._beams[blk.beam]
             pend.append(None if b["binned"] else b["stream"].append(blk.data, stream=self.stream))
-        groups: Dict[tuple, List[int]] = collections.defaultdict(list)
-        for i, (blk, w) in enumerate(zip(blocks, pend)):
-            if w is not None:
-                plan = self._beams[blk.beam]["stream"].plan
-                # direct-read plans of any tiles share a call; LDS-form plans need one dtype,
-                # wavefront count and producer count per call
-                key = ("direct",) if plan.form == "direct" else (plan.dtype, plan.tiles[0], plan.tiles[1],
-                                                                 plan.producer_waves)
-                groups[key].append(i)
+        # plans of any tiles share one batched call (one launch per kernel shape)
+        idx = [i for i, w in enumerate(pend) if w is not None]
         res: List[object] = [None] * len(blocks)
-        for idx in groups.values():
+        if idx:
             jobs, outs = [], []
             for i in idx:
                 b = self._beams[blocks[i].beam]
@@ -399,7 +392,7 @@ class LibraryExecutor(Executor):
             if b["binned"]:
                 res[i] = b["stream"].push(blk.data, k_sigma=self.k_sigma, cand_cap=self.cand_cap,
                                           outputs=b["outs"][b["n"] & 1], stream=self.stream,
-                                          batched=b["stream"].batchable)
+                                          batched=False)  # one launch per run: measured faster
                 if res[i] is not None:
                     b["n"] += 1
         for blk, w in zip(blocks, pend):

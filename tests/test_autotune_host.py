@@ -70,7 +70,7 @@ def test_tune_records_tilings_that_do_not_fit(at):
     assert r["form"] == "lds" and "ms" in next(t for t in r["trials"] if t.get("tuning") == r["tuning"])
 
 
-def test_tune_batch_one_wave_count_for_all(at):
+def test_tune_batch_own_best_or_one_wave_count(at):
     # per wave count: beam A prefers 8 waves, beam B 2; summed, 4 waves is best
     class Clock(FakeClock):
         def __call__(self, plan, x, reps):
@@ -80,16 +80,33 @@ def test_tune_batch_one_wave_count_for_all(at):
             return table[plan.nchan][w] * (0.9 if cc == 2 else 1.0)
     clock = Clock({}, {})
     res = at.tune_batch([_beam(64, 96), _beam(128, 64)], waves=(8, 4, 2), stages=(0, 2), inputs=[object(), object()],
-                        timer=clock)
+                        timer=clock, common_waves=True)
     assert res["waves"] == 4
     assert res["tunings"] == [[8, 4, 2], [8, 4, 2]]
     assert res["choices"] == [{"form": "lds", "tuning": [8, 4, 2]}] * 2
     # each beam's own best over all counts
     assert [o["tuning"] for o in res["own_best"]] == [[8, 8, 2], [8, 2, 2]]
     free = at.tune_batch([_beam(64, 96), _beam(128, 64)], waves=(8, 4, 2), stages=(0, 2),
-                         inputs=[object(), object()], timer=clock, common_waves=False)
+                         inputs=[object(), object()], timer=clock)
     assert free["choices"] == [{"form": "lds", "tuning": [8, 8, 2]}, {"form": "lds", "tuning": [8, 2, 2]}]
+    assert free["waves"] == 4 and free["total_ms"] == pytest.approx(3.15)
     assert res["by_waves"] == pytest.approx({8: 5.4, 4: 3.15, 2: 4.32})
+
+
+def test_tune_batch_beam_that_misses_a_wave_count(at):
+    """A beam that fits no tiling at one wavefront count keeps its own best over the others;
+    that count drops out of the common-count sums."""
+    class Clock(FakeClock):
+        def __call__(self, plan, x, reps):
+            self.calls += 1
+            g, w, cc = plan.tiles
+            if plan.nchan == 128 and w == 8:
+                raise RuntimeError("does not fit")
+            return {8: 1.0, 4: 2.0, 2: 3.0}[w] * (2.0 if plan.nchan == 128 else 1.0)
+    res = at.tune_batch([_beam(64, 96), _beam(128, 64)], waves=(8, 4, 2), stages=(0,), inputs=[object(), object()],
+                        timer=Clock({}, {}))
+    assert [c["tuning"] for c in res["choices"]] == [[8, 8, 0], [8, 4, 0]]
+    assert set(res["by_waves"]) == {4, 2} and res["waves"] == 4
 
 
 def test_tune_offers_the_direct_form_for_8bit_beams(at):

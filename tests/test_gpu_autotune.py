@@ -58,6 +58,14 @@ def test_tune_batch_u8_beams_exact(torch, at):
         data.append(bm)
     res = at.tune_batch(beams, waves=(8, 4, 2), stages=(0,), reps=1, inputs=xs)
     assert res["waves"] in (8, 4, 2) and len(res["tunings"]) == 3
+    # the chosen plans (each beam's own best) in one batched call equal their single calls
+    plans = [at.make_plan(bm.freq_mhz, bm.tsamp_s, bm.dm, "u8", c) for bm, c in zip(data, res["choices"])]
+    import paper_1401_8258_amd as dd
+    batched = dd.batch_dedisperse(list(zip(plans, xs)), k_sigma=6.0)
+    for p, x, r in zip(plans, xs, batched):
+        s = p.dedisperse(x, k_sigma=6.0)
+        np.testing.assert_array_equal(s.out.cpu().numpy(), r.out.cpu().numpy())
+        np.testing.assert_array_equal(s.candidates(), r.candidates())
     for bm, choice, x in zip(data, res["choices"], xs):
         plan = at.make_plan(bm.freq_mhz, bm.tsamp_s, bm.dm, "u8", choice)
         assert plan.form == choice["form"]

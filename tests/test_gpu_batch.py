@@ -190,3 +190,77 @@ def test_batch_rejects_shared_workspace(torch, dd):
                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == _lib.DD_ERR_INVALID_ARG
     assert "share workspace" in lib.dd_last_error().decode()
+
+
+def test_batch_mixes_every_kernel_shape(torch, dd):
+    """One batched call over items on every kernel shape: FP32 with 8 and with 4 trials per
+    computing wavefront beside producers, FP32 without producers, FP16, 8-bit in the LDS form
+    and 8-bit in the direct-read form at two tile shapes and wavefront counts. Each shape
+    gets its own launch; every item equals its single call bit for bit (outputs, statistics,
+    candidates) and the oracle."""
+    print("case: batch mixing every kernel shape", flush=True)
+    nchan, ndm, nsamp = 64, 128, 6000
+    freq = fbsynth.channel_freqs(428.0, 20.0 / nchan, nchan)
+    dm = fbsynth.dm_trials(0.0, 0.1, ndm)
+    tab = orc.delay_table(freq, dm, 51.2e-6)
+    rng = np.random.default_rng(31)
+    x32 = fbsynth.noise(rng, nchan, nsamp)
+    inputs = {"f32": x32, "f16": fbsynth.to_f16(x32), "u8": fbsynth.to_u8(x32)}
+    cases = [("f32", (8, 6, 0, 2), "lds"), ("f32", (4, 14, 0, 2), "lds"), ("f32", (8, 4, 0, -1), "lds"),
+             ("f16", (8, 2), "lds"), ("u8", (8, 4), "lds"), ("u8", (2, 4, 16), "direct"),
+             ("u8", (1, 8, 32), "direct")]
+    jobs = []
+    for dtype, tun, form in cases:
+        p = dd.Plan(freq, 51.2e-6, dm, dtype=dtype, tuning=tun, form=form)
+        assert p.form == form, (dtype, tun, p.form)
+        jobs.append((p, torch.from_numpy(np.ascontiguousarray(inputs[dtype])).cuda()))
+    assert jobs[0][0].tiles[:2] == (8, 6) and jobs[1][0].tiles[:2] == (4, 14)
+    assert jobs[0][0].producer_waves == 2 and jobs[2][0].producer_waves == 0
+    res = dd.batch_dedisperse(jobs, k_sigma=4.0)
+    torch.cuda.synchronize()
+    rows = [0, 57, ndm - 1]
+    for (dtype, tun, form), (p, x), r in zip(cases, jobs, res):
+        s = p.dedisperse(x, k_sigma=4.0)
+        torch.cuda.synchronize()
+        got = r.out.cpu().numpy()
+        np.testing.assert_array_equal(s.out.cpu().numpy(), got)
+        np.testing.assert_array_equal(s.mean.cpu().numpy(), r.mean.cpu().numpy())
+        np.testing.assert_array_equal(s.rms.cpu().numpy(), r.rms.cpu().numpy())
+        np.testing.assert_array_equal(s.candidates(), r.candidates())
+        want = orc.dedisperse(inputs[dtype].astype(np.float64), tab, rows=rows)
+        if dtype == "u8":
+            np.testing.assert_array_equal(got[rows].astype(np.float64), want)
+        else:
+            full = orc.dedisperse(inputs[dtype].astype(np.float64), tab)
+            _, rms = orc.series_stats(full)
+            assert_rows_close(got, full, rms, what=f"batch {dtype} {tun}")
+
+
+@pytest.mark.parametrize("tuning", [(4, 14, 0, 2), (8, 4, 0, -1)])
+def test_batch_short_window_many_groups(torch, dd, tuning):
+    """An item with two time tiles and many DM groups (its units spread over the XCDs by DM
+    group) beside one with many tiles (spread by tile), in one launch: both equal their
+    single calls bit for bit, and the oracle."""
+    print(f"case: batch, short window over many DM groups, tuning {tuning}", flush=True)
+    nchan, ndm = 64, 700
+    freq = fbsynth.channel_freqs(428.0, 20.0 / nchan, nchan)
+    dm = fbsynth.dm_trials(0.0, 0.05, ndm)
+    tab = orc.delay_table(freq, dm, 51.2e-6)
+    plan = dd.Plan(freq, 51.2e-6, dm, tuning=tuning)
+    rng = np.random.default_rng(41)
+    xs = [fbsynth.noise(rng, nchan, plan.maxdelay + n) for n in (700, 40000)]
+    jobs = [(plan, torch.from_numpy(x).cuda()) for x in xs]
+    res = dd.batch_dedisperse(jobs, k_sigma=4.0)
+    torch.cuda.synchronize()
+    for (p, x), r, xh in zip(jobs, res, xs):
+        s = p.dedisperse(x, k_sigma=4.0)
+        torch.cuda.synchronize()
+        got = r.out.cpu().numpy()
+        np.testing.assert_array_equal(s.out.cpu().numpy(), got)
+        np.testing.assert_array_equal(s.mean.cpu().numpy(), r.mean.cpu().numpy())
+        np.testing.assert_array_equal(s.rms.cpu().numpy(), r.rms.cpu().numpy())
+        np.testing.assert_array_equal(s.candidates(), r.candidates())
+        rows = list(range(0, ndm, 97)) + [ndm - 1]
+        want = orc.dedisperse(xh, tab, rows=rows)
+        rms = np.sqrt(np.mean((want - want.mean(axis=1, keepdims=True)) ** 2, axis=1))
+        assert_rows_close(got[rows], want, rms, what=f"batch short window {tuning}")

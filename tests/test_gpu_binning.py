@@ -224,9 +224,10 @@ def test_binned_stream_equals_one_shot(torch, dd, dt, batched):
 def test_binned_stream_gap_fill_and_refusals(torch, dd):
     """A lost block with gap fill on: every run's outputs equal the one-shot binned call over
     the input with zeros in place of the lost block, at the same run times. A block that is
-    not a multiple of 16 samples, a wrong seq (gap fill off) and a batched push whose runs
-    cannot share one call (FP16 factor-1 run beside FP32 runs) are refused before anything
-    changes, and the stream continues."""
+    not a multiple of 16 samples, a wrong seq (gap fill off) and a batched push of
+    register-window runs (a form that is not batched) are refused before anything changes,
+    and the stream continues. An FP16 factor-1 run beside FP32 runs (different kernels and
+    tiles) pushes batched, equal to the unbatched push."""
     _say("case: binned stream gap fill")
     sizes = [1024] * 12
     freq, tsamp, dm, x, xz, runs = _binned_stream_case("f32", sizes, 4.0, gap=7)
@@ -254,11 +255,27 @@ def test_binned_stream_gap_fill_and_refusals(torch, dd):
         plain.push(blk, seq=1)
     plain.push(blk, seq=0)
     assert plain.seq == 1
-    bp16 = dd.BinnedPlan(freq, tsamp, dm, dtype="f16", max_log2=4)
-    s16 = dd.BinnedStream(bp16, 1024)
-    b16 = torch.from_numpy(fbsynth.to_f16(x[:, :1024])).cuda()
+    brw = dd.BinnedPlan(freq, tsamp, dm, max_log2=4, form="regwin")
+    assert not brw.batchable
+    srw = dd.BinnedStream(brw, 1024)
     with pytest.raises(dd.DedispError):
-        s16.push(b16, batched=True)
-    assert s16.seq == 0
-    s16.push(b16)
-    assert s16.seq == 1
+        srw.push(blk, batched=True)
+    assert srw.seq == 0
+    bp16 = dd.BinnedPlan(freq, tsamp, dm, dtype="f16", max_log2=4)
+    assert bp16.batchable and bp16.segments[0].plan.tiles != bp16.segments[1].plan.tiles
+    s16, u16 = dd.BinnedStream(bp16, 1024), dd.BinnedStream(bp16, 1024)
+    for j in range(len(sizes)):
+        b16 = torch.from_numpy(fbsynth.to_f16(x[:, 1024 * j:1024 * (j + 1)])).cuda()
+        rb = s16.push(b16, k_sigma=4.0, batched=True)
+        ru = u16.push(b16, k_sigma=4.0)
+        assert (rb is None) == (ru is None)
+        if rb is None:
+            continue
+        for (_, tb, b), (_, tu, u) in zip(rb.segments, ru.segments):
+            assert tb == tu and (b is None) == (u is None)
+            if b is not None:
+                np.testing.assert_array_equal(b.out.cpu().numpy(), u.out.cpu().numpy())
+        np.testing.assert_array_equal(rb.candidates(), ru.candidates())
+    assert s16.seq == u16.seq == len(sizes)
+    srw.push(blk)
+    assert srw.seq == 1
