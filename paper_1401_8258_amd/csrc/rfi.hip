@@ -11,6 +11,10 @@
 //   stage's statistic), so the channel stage needs no read of its own: each wavefront sums
 //   its windows (four at a time, a butterfly each) and the channel total is the sum of its
 //   window sums in a fixed order.
+// * bandpass_windows_u8: exact integer sums (v_sad_u8 over 16-byte loads). A 16-byte
+//   aligned row whose window is 16 L bytes (L = 1, 2, ..., 64) is read in 1 KB lines, one
+//   window per group of L lanes, four lines in flight per lane; other rows one window per
+//   wavefront.
 // * dd_bandpass_fit (host): least-squares polynomial over x = 2c/(nchan-1) - 1 by modified
 //   Gram-Schmidt on the monomial columns (each orthogonalised twice); the fitted values are
 //   the projection of the average onto their span.
@@ -268,8 +272,47 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
-// blockIdx.x = channel; wavefront k takes windows k, k + 4, ... (window = n with no window
-// means); the channel mean is its exact total over n.
+// Sums of the whole windows of a 16-byte aligned row whose window is 16 L bytes (L a power
+// of two up to 64): lane groups of L lanes each own one window of every 1 KB line, and each
+// lane keeps kLines lines' loads in flight. A window's sum (at most 1024 x 255) closes with
+// a 32-bit butterfly inside its group; its first lane writes the mean (when means is not
+// null) and adds the sum to `tot`. Lines are taken by the four wavefronts in turn.
+constexpr int kLines = 4;
+template <int L>
+__device__ __forceinline__ void windows_aligned_u8(const uint8_t* __restrict__ row, int64_t nfull, int lane, int wv,
+                                                   double* __restrict__ means, uint64_t& tot) {
+  const uint4* v = reinterpret_cast<const uint4*>(row);
+  const int64_t nchunk = nfull * L;  // 16-byte chunks of the whole windows
+  const int64_t nline = (nchunk + 63) / 64;
+  for (int64_t l0 = wv; l0 < nline; l0 += 4 * kLines) {
+    uint4 q[kLines];
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      const int64_t ci = (l0 + 4 * u) * 64 + lane;
+      q[u] = ci < nchunk ? v[ci] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      unsigned sum = __builtin_amdgcn_sad_u8(q[u].x, 0u, 0u);
+      sum = __builtin_amdgcn_sad_u8(q[u].y, 0u, sum);
+      sum = __builtin_amdgcn_sad_u8(q[u].z, 0u, sum);
+      sum = __builtin_amdgcn_sad_u8(q[u].w, 0u, sum);
+#pragma unroll
+      for (int off = L / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+      const int64_t ci = (l0 + 4 * u) * 64 + lane;
+      if ((lane & (L - 1)) == 0 && ci < nchunk) {
+        tot += sum;
+        if (means) means[ci / L] = (double)sum / (double)(16 * L);
+      }
+    }
+  }
+}
+
+// blockIdx.x = channel; the channel mean is its exact total over n. With window means
+// (means not null): a 16-byte aligned row whose window is 16 L bytes (L a power of two up to
+// 64) takes its whole windows through windows_aligned_u8 and its ragged last window through
+// wavefront 0; any other row has wavefront k take windows k, k + 4, ... With no window
+// means the total of an aligned row comes from 1 KB windows the same way.
 __global__ __launch_bounds__(kRfiThreads) void bandpass_windows_u8(const uint8_t* __restrict__ x, int64_t n,
                                                                    int64_t stride, int64_t window, int64_t nwin,
                                                                    double* __restrict__ avg,
@@ -277,13 +320,39 @@ __global__ __launch_bounds__(kRfiThreads) void bandpass_windows_u8(const uint8_t
   __shared__ uint64_t red[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint8_t* row = x + (int64_t)blockIdx.x * stride;
+  double* mrow = means ? means + (int64_t)blockIdx.x * nwin : nullptr;
   uint64_t tot = 0;
-  for (int64_t w = wv; w < nwin; w += 4) {
-    const int64_t t0 = w * window;
-    const int64_t len = n - t0 < window ? n - t0 : window;
-    const uint64_t ws = wave_sum_u64(row_bytes_sum(row, t0, len, lane));
-    tot += ws;
-    if (means && lane == 0) means[(int64_t)blockIdx.x * nwin + w] = (double)ws / (double)len;
+  const int64_t win = means ? window : 1024;  // the windows the aligned path walks
+  const int64_t L = win / 16;
+  const bool aligned = (reinterpret_cast<uintptr_t>(row) & 15) == 0 && win % 16 == 0 && L <= 64 && (L & (L - 1)) == 0;
+  if (aligned) {
+    const int64_t nfull = n / win;
+    switch (L) {
+      case 1: windows_aligned_u8<1>(row, nfull, lane, wv, mrow, tot); break;
+      case 2: windows_aligned_u8<2>(row, nfull, lane, wv, mrow, tot); break;
+      case 4: windows_aligned_u8<4>(row, nfull, lane, wv, mrow, tot); break;
+      case 8: windows_aligned_u8<8>(row, nfull, lane, wv, mrow, tot); break;
+      case 16: windows_aligned_u8<16>(row, nfull, lane, wv, mrow, tot); break;
+      case 32: windows_aligned_u8<32>(row, nfull, lane, wv, mrow, tot); break;
+      default: windows_aligned_u8<64>(row, nfull, lane, wv, mrow, tot); break;
+    }
+    const int64_t t0 = nfull * win;
+    if (wv == 0 && t0 < n) {  // the ragged last window
+      const uint64_t ws = wave_sum_u64(row_bytes_sum(row, t0, n - t0, lane));
+      if (lane == 0) {
+        tot += ws;
+        if (mrow) mrow[nfull] = (double)ws / (double)(n - t0);
+      }
+    }
+    tot = wave_sum_u64(tot);  // the group sums sit in their first lanes
+  } else {
+    for (int64_t w = wv; w < nwin; w += 4) {
+      const int64_t t0 = w * window;
+      const int64_t len = n - t0 < window ? n - t0 : window;
+      const uint64_t ws = wave_sum_u64(row_bytes_sum(row, t0, len, lane));
+      tot += ws;
+      if (mrow && lane == 0) mrow[w] = (double)ws / (double)len;
+    }
   }
   if (lane == 0) red[wv] = tot;
   __syncthreads();
@@ -308,32 +377,53 @@ __global__ __launch_bounds__(kRfiThreads) void chan_apply_u8(uint8_t* __restrict
 
 // Each lane takes 16 consecutive samples (one 16-byte load per channel when every row start
 // is aligned, so a wavefront reads 1 KB of a channel at once) and sums their spectra over
-// channels in exact integers; a spectrum whose mean is further than the threshold from the
-// fit's mean takes the fitted codes.
+// channels in exact integers: the four wavefronts of a workgroup take the same samples and
+// every fourth channel each (four loads in flight per lane), and the first adds the others'
+// sums from LDS. A spectrum whose mean is further than the threshold from the fit's mean
+// takes the fitted codes.
 __global__ __launch_bounds__(kRfiThreads) void spec_clip_u8(uint8_t* __restrict__ x, int64_t nchan, int64_t n,
                                                             int64_t stride, const double* __restrict__ fit,
                                                             double center, double thr) {
-  const int64_t t0 = ((int64_t)blockIdx.x * kRfiThreads + threadIdx.x) * 16;
-  if (t0 >= n) return;
+  __shared__ unsigned part[3][16][64];  // the partial sums of wavefronts 1..3
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t t0 = ((int64_t)blockIdx.x * 64 + lane) * 16;
   unsigned s[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) s[i] = 0;
-  const bool vec = t0 + 15 < n && (stride & 15) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
-  if (vec) {
-    for (int64_t c = 0; c < nchan; ++c) {
-      const uint4 q = *reinterpret_cast<const uint4*>(x + c * stride + t0);
-      const unsigned w4[4] = {q.x, q.y, q.z, q.w};
+  auto add16 = [&](const uint4 q) {
+    const unsigned w4[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) s[4 * j + b] += (w4[j] >> (8 * b)) & 0xffu;
+      for (int b = 0; b < 4; ++b) s[4 * j + b] += (w4[j] >> (8 * b)) & 0xffu;
+  };
+  if (t0 < n) {
+    // wavefront wv sums channels wv, wv + 4, ...: exact integers, so the order is free
+    const bool vec = t0 + 15 < n && (stride & 15) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    if (vec) {
+      int64_t c = wv;
+      for (; c + 12 < nchan; c += 16) {  // four loads in flight
+        uint4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = *reinterpret_cast<const uint4*>(x + (c + 4 * u) * stride + t0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add16(q[u]);
+      }
+      for (; c < nchan; c += 4) add16(*reinterpret_cast<const uint4*>(x + c * stride + t0));
+    } else {
+      for (int64_t c = wv; c < nchan; c += 4)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (t0 + i < n) s[i] += x[c * stride + t0 + i];
     }
-  } else {
-    for (int64_t c = 0; c < nchan; ++c)
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-        if (t0 + i < n) s[i] += x[c * stride + t0 + i];
   }
+  if (wv > 0)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) part[wv - 1][i][lane] = s[i];
+  __syncthreads();  // every wavefront has read its channels before any spectrum is replaced
+  if (wv != 0 || t0 >= n) return;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s[i] += part[0][i][lane] + part[1][i][lane] + part[2][i][lane];
 #pragma unroll
   for (int i = 0; i < 16; ++i)
     if (t0 + i < n && fabs((double)s[i] / (double)nchan - center) > thr)
@@ -490,7 +580,7 @@ extern "C" int dd_rfi_clip_u8(uint8_t* d_data, int64_t nchan, int64_t nsamp, int
     if (launched("channel apply (8-bit)") != hipSuccess) return DD_ERR_HIP;
   }
   if (spec_threshold > 0.0) {
-    const int64_t tblocks = (nsamp + 16 * kRfiThreads - 1) / (16 * kRfiThreads);
+    const int64_t tblocks = (nsamp + 16 * 64 - 1) / (16 * 64);  // 16 samples per lane of a wavefront
     if (tblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "series too long");
     hipLaunchKernelGGL(spec_clip_u8, dim3((unsigned)tblocks), dim3(kRfiThreads), 0, st, d_data, nchan, nsamp,
                        row_stride, d_fit, fit_mean, spec_threshold);

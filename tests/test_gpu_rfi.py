@@ -162,13 +162,15 @@ def _codes_dirty(nchan, n, seed):
 
 @pytest.mark.parametrize("nchan,n,stride,window,order", [
     (64, 16384, 16384, 64, 4), (5, 1001, 1013, 7, 2), (1, 300, 300, 16, 0), (33, 4099, 4112, 256, 6),
-    (4096, 12207, 12207, 256, 6)])
+    (4096, 12207, 12207, 256, 6), (16, 5000, 5008, 1024, 3), (8, 2000, 2000, 32, 2), (24, 3000, 3008, 512, 3),
+    (12, 2500, 2512, 128, 2), (16, 4096, 4096, 16, 2)])
 def test_rfi_u8_parity(torch, dd, nchan, n, stride, window, order):
     """8-bit codes (dd_bandpass_u8, dd_rfi_clip_u8): averages and window means are exact sums
     divided once, equal to the oracle's bit for bit; every flag and every replaced code
     equals the oracle's (no decision and no fitted value within 1e-6 of flipping); rows
-    unaligned (stride 1013) and ragged windows included; the last case is a 1 s block of a
-    4096-channel serving beam."""
+    unaligned (strides 1013, 12207) and ragged windows included; 16-byte aligned rows take
+    windows of 16 x 2^k bytes (k = 0..6, with and without a ragged last window) through the
+    lane-group path; the fifth case is a 1 s block of a 4096-channel serving beam."""
     _say(f"case: rfi u8 {nchan}x{n} stride {stride} window {window} order {order}")
     full = np.zeros((nchan, stride), np.uint8)
     full[:, :n] = _codes_dirty(nchan, n, nchan * 37 + n)
