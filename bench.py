@@ -617,7 +617,7 @@ def main():
     # algorithmic bytes: one read of the series and the detections written (the counting
     # pass reads every segment, the writing pass again only the segments with detections)
     bs_bytes = beam.ndm * nout * 4 + int(npulse.item()) * 24
-    boxcar_search = {"kernels": "boxcar_count + boxcar_scan + boxcar_write", "max_width": 64, "k_sigma": 6.5,
+    boxcar_search = {"kernels": "boxcar_count + count scan (3 launches) + boxcar_write", "max_width": 64, "k_sigma": 6.5,
                      "ms": round(ms_bs, 3), "bound": "hbm", "unit": "GB/s",
                      "achieved": round(bs_bytes / (ms_bs * 1e-3) / 1e9, 1), "peak": 8000.0,
                      "frac": round(bs_bytes / (ms_bs * 1e-3) / 1e9 / 8000.0, 4),

@@ -212,12 +212,6 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_count(SearchArgs A, int64_
   if (threadIdx.x == 0) cnt[(int64_t)d * nseg + seg] = total;
 }
 
-__global__ __launch_bounds__(1024) void boxcar_scan(const int32_t* __restrict__ cnt, int64_t n,
-                                                    int64_t* __restrict__ offs, int64_t* __restrict__ total) {
-  __shared__ int64_t part[1024];
-  dd::scan_counts(cnt, n, offs, total, part);
-}
-
 // Detections in ascending t: thread i's starts precede thread i + 1's, so a thread's slot
 // is the segment offset plus the exclusive prefix sum of the hit counts over threads
 // (inclusive scan inside each wavefront, the wavefront totals through LDS).
@@ -317,7 +311,8 @@ extern "C" int dd_boxcar_search(const float* d_series, int64_t nrows, int64_t n,
   const SearchArgs A{d_series, n, row_stride, d_mean, d_rms, (int)max_log2, k_sigma};
   const dim3 grid((unsigned)l.nseg, (unsigned)nrows);
   hipLaunchKernelGGL(boxcar_count, grid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt);
-  hipLaunchKernelGGL(boxcar_scan, dim3(1), dim3(1024), 0, st, cnt, nrows * l.nseg, offs, d_npulse);
+  const int rc = dd::launch_count_scan(cnt, nrows * l.nseg, offs, d_npulse, st);
+  if (rc) return rc;
   hipLaunchKernelGGL(boxcar_write, grid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt, offs, d_pulse, cap);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return dd::fail(DD_ERR_HIP, std::string("boxcar search launch: ") + hipGetErrorString(e));

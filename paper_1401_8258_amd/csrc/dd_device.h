@@ -20,44 +20,113 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
   return v;
 }
 
-// Exclusive scan of n counts by one 1024-thread block (part: at least 16 int64 of LDS); the
-// total to *total. Serves every candidate compaction (threshold and boxcar detections).
-// Tiles of 4096 counts in order, each thread taking 4 consecutive ones, so every load and
-// store of a wavefront covers one contiguous span; a tile is scanned by wavefront shuffles
-// and the 16 wavefront totals in LDS, and carries its total into the next.
+// Exclusive scan of counts in tiles of 4096 by a 1024-thread block, each thread taking 4
+// consecutive ones, so every load and store of a wavefront covers one contiguous span. A
+// tile is scanned by wavefront shuffles and the 16 wavefront totals in LDS (part: at least
+// 16 int64): offs[base + i] = carry + the counts before base + i in the tile. Returns the
+// tile's total (in every thread).
+constexpr int64_t kScanTile = 4096;
+__device__ __forceinline__ int64_t scan_tile(const int32_t* __restrict__ cnt, int64_t n, int64_t base, int64_t carry,
+                                             int64_t* __restrict__ offs, int64_t* part) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t i0 = base + 4 * tid;
+  int c[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = i0 + k < n ? cnt[i0 + k] : 0;
+  const int64_t s = (int64_t)c[0] + c[1] + c[2] + c[3];
+  int64_t incl = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) part[wv] = incl;
+  __syncthreads();
+  int64_t run = carry + incl - s, tile = 0;
+  for (int k = 0; k < 16; ++k) {
+    const int64_t p = part[k];
+    run += k < wv ? p : 0;
+    tile += p;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < n) offs[i0 + k] = run;
+    run += c[k];
+  }
+  __syncthreads();  // every thread has read part before it is written again
+  return tile;
+}
+
+// Exclusive scan of n counts by one 1024-thread block, tile after tile; the total to *total.
 __device__ __forceinline__ void scan_counts(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ offs,
                                             int64_t* __restrict__ total, int64_t* part) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int64_t carry = 0;
-  for (int64_t base = 0; base < n; base += 4096) {
-    const int64_t i0 = base + 4 * tid;
-    int c[4];
+  for (int64_t base = 0; base < n; base += kScanTile) carry += scan_tile(cnt, n, base, carry, offs, part);
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// The same scan by many blocks, in three launches and no memory beyond offs (every
+// candidate and detection compaction uses it; the offsets equal scan_counts's):
+//  1. scan_tile_totals: block b parks the total of tile b in offs[4096 b];
+//  2. scan_tile_bases (one block): an exclusive scan of those totals in place, the grand
+//     total to *total;
+//  3. scan_tile_apply: block b scans tile b from the base in offs[4096 b], rewriting that
+//     slot with the same value.
+__device__ __forceinline__ void scan_tile_totals(const int32_t* __restrict__ cnt, int64_t n,
+                                                 int64_t* __restrict__ offs, int64_t* part) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int64_t i0 = base + 4 * tid;
+  int64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = i0 + k < n ? cnt[i0 + k] : 0;
-    const int64_t s = (int64_t)c[0] + c[1] + c[2] + c[3];
-    int64_t incl = s;
+  for (int k = 0; k < 4; ++k) s += i0 + k < n ? cnt[i0 + k] : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) part[wv] = s;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t t = 0;
+    for (int k = 0; k < 16; ++k) t += part[k];
+    offs[base] = t;
+  }
+}
+
+__device__ __forceinline__ void scan_tile_bases(int64_t n, int64_t* __restrict__ offs, int64_t* __restrict__ total,
+                                                int64_t* part) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += 1024) {
+    const int64_t k = c0 + tid;
+    const int64_t v = k < ntiles ? offs[k * kScanTile] : 0;
+    int64_t incl = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int64_t v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
+      const int64_t u = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += u;
     }
     if (lane == 63) part[wv] = incl;
     __syncthreads();
-    int64_t run = carry + incl - s, tile = 0;
-    for (int k = 0; k < 16; ++k) {
-      const int64_t p = part[k];
-      run += k < wv ? p : 0;
-      tile += p;
+    int64_t run = carry + incl - v, chunk = 0;
+    for (int j = 0; j < 16; ++j) {
+      const int64_t p = part[j];
+      run += j < wv ? p : 0;
+      chunk += p;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i0 + k < n) offs[i0 + k] = run;
-      run += c[k];
-    }
-    carry += tile;
-    __syncthreads();  // every thread has read part before the next tile writes it
+    if (k < ntiles) offs[k * kScanTile] = run;
+    carry += chunk;
+    __syncthreads();
   }
   if (tid == 0) *total = carry;
+}
+
+__device__ __forceinline__ void scan_tile_apply(const int32_t* __restrict__ cnt, int64_t n,
+                                                int64_t* __restrict__ offs, int64_t* part) {
+  __shared__ int64_t base_off;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (threadIdx.x == 0) base_off = offs[base];
+  __syncthreads();  // read before the tile's own offsets overwrite it
+  scan_tile(cnt, n, base, base_off, offs, part);
 }
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }

@@ -184,5 +184,8 @@ int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int6
 // of lq bytes, starting at ring position pos0.
 int append_direct(const dd_plan* p, const void* blk, int64_t in_stride, int64_t n, void* ring, int64_t lq,
                   int64_t ring_len, int64_t pos0, void* stream);
+// Exclusive scan of n int32 counts into offs[n] (int64) and their total into *total, by
+// many blocks in three launches that use no memory beyond offs (csrc/dedisp.hip).
+int launch_count_scan(const int32_t* cnt, int64_t n, int64_t* offs, int64_t* total, void* stream);
 
 }  // namespace dd

@@ -846,15 +846,31 @@ __device__ __forceinline__ void finalize_series(const double* __restrict__ part,
 // Values above the threshold in one kStatSeg segment of series d (a 256-thread block).
 __device__ __forceinline__ void count_segment(const float* __restrict__ out, int64_t stride, int64_t nout,
                                               int64_t nseg, const double* __restrict__ stat,
-                                              int32_t* __restrict__ cnt, int64_t seg, int d, double* red) {
+                                              int32_t* __restrict__ cnt, int64_t seg, int d, int* red) {
   const float* row = out + (int64_t)d * stride;
   const double thr = stat[d * 3 + 2];
   const int64_t b = seg * dd::kStatSeg;
   const int64_t e = min(nout, b + dd::kStatSeg);
   int n = 0;
-  for (int64_t t = b + threadIdx.x; t < e; t += 256) n += ((double)row[t] > thr) ? 1 : 0;
-  const double tot = block_sum256((double)n, red);
-  if (threadIdx.x == 0) cnt[(int64_t)d * nseg + seg] = (int32_t)tot;
+  if (e - b == dd::kStatSeg && (reinterpret_cast<uintptr_t>(row + b) & 15) == 0) {
+    // a whole aligned segment: eight 16-byte loads per thread, all in flight together
+    constexpr int kPer = dd::kStatSeg / 4 / 256;
+    const float4* v = reinterpret_cast<const float4*>(row + b);
+    float4 q[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) q[k] = v[threadIdx.x + 256 * k];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      n += ((double)q[k].x > thr) + ((double)q[k].y > thr) + ((double)q[k].z > thr) + ((double)q[k].w > thr);
+  } else {
+    for (int64_t t = b + threadIdx.x; t < e; t += 256) n += ((double)row[t] > thr) ? 1 : 0;
+  }
+  // integer sum over the block: wavefront butterflies, then the four wavefront totals
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[(int64_t)d * nseg + seg] = red[0] + red[1] + red[2] + red[3];
 }
 
 // The detections of one segment of series d, in time order, at their scanned offsets.
@@ -913,14 +929,26 @@ __global__ __launch_bounds__(256) void stats_finalize(const double* __restrict__
 __global__ __launch_bounds__(256) void cand_count(const float* __restrict__ out, int64_t stride, int64_t nout,
                                                   int64_t nseg, const double* __restrict__ stat,
                                                   int32_t* __restrict__ cnt) {
-  __shared__ double red[4];
+  __shared__ int red[4];
   count_segment(out, stride, nout, nseg, stat, cnt, blockIdx.x, blockIdx.y, red);
 }
 
-__global__ __launch_bounds__(1024) void cand_scan(const int32_t* __restrict__ cnt, int64_t n,
-                                                  int64_t* __restrict__ offs, int64_t* __restrict__ ncand) {
-  __shared__ int64_t part[1024];
-  dd::scan_counts(cnt, n, offs, ncand, part);
+// The three passes of the block-parallel count scan (dd_device.h), one 1024-thread block per
+// tile of 4096 counts in the first and last.
+__global__ __launch_bounds__(1024) void scan_totals_k(const int32_t* __restrict__ cnt, int64_t n,
+                                                      int64_t* __restrict__ offs) {
+  __shared__ int64_t part[16];
+  dd::scan_tile_totals(cnt, n, offs, part);
+}
+__global__ __launch_bounds__(1024) void scan_bases_k(int64_t n, int64_t* __restrict__ offs,
+                                                     int64_t* __restrict__ total) {
+  __shared__ int64_t part[16];
+  dd::scan_tile_bases(n, offs, total, part);
+}
+__global__ __launch_bounds__(1024) void scan_apply_k(const int32_t* __restrict__ cnt, int64_t n,
+                                                     int64_t* __restrict__ offs) {
+  __shared__ int64_t part[16];
+  dd::scan_tile_apply(cnt, n, offs, part);
 }
 
 __global__ __launch_bounds__(256) void cand_write(const float* __restrict__ out, int64_t stride, int64_t nout,
@@ -970,7 +998,7 @@ __global__ __launch_bounds__(256) void stats_finalize_batch(const TailItem* __re
 }
 
 __global__ __launch_bounds__(256) void cand_count_batch(const TailItem* __restrict__ items, int n) {
-  __shared__ double red[4];
+  __shared__ int red[4];
   const int64_t u = blockIdx.x;
   const TailItem& it = items[find_item(items, n, u, [](const TailItem& t) { return t.unit0; })];
   const int64_t local = u - it.unit0;
@@ -1156,7 +1184,8 @@ int launch_tail(const dd_plan* p, int64_t nout, const Outputs& o, char* ws, cons
     int64_t* offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
     hipLaunchKernelGGL(cand_count, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out, o.out_stride,
                        nout, nseg, stat, cnt);
-    hipLaunchKernelGGL(cand_scan, dim3(1), dim3(1024), 0, st, cnt, nseg * p->ndm, offs, o.ncand);
+    int rc = dd::launch_count_scan(cnt, nseg * p->ndm, offs, o.ncand, st);
+    if (rc) return rc;
     hipLaunchKernelGGL(cand_write, dim3((unsigned)nseg, (unsigned)p->ndm), dim3(256), 0, st, o.out, o.out_stride,
                        nout, nseg, stat, cnt, offs, o.cand, o.cand ? o.cap : 0, o.t_base);
   }
@@ -1273,7 +1302,8 @@ int merged_candidates(const std::vector<MergedRun>& runs, float k, dd_cand* cand
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (candidate descriptors)");
   const int n = (int)items.size();
   hipLaunchKernelGGL(cand_count_batch, dim3((unsigned)units), dim3(256), 0, st, (const TailItem*)dT, n);
-  hipLaunchKernelGGL(cand_scan, dim3(1), dim3(1024), 0, st, (const int32_t*)cnt, units, offs, ncand);
+  int rc = dd::launch_count_scan(cnt, units, offs, ncand, st);
+  if (rc) return rc;
   hipLaunchKernelGGL(cand_write_batch, dim3((unsigned)units), dim3(256), 0, st, (const TailItem*)dT, n);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "merged candidate launch");
@@ -1281,6 +1311,22 @@ int merged_candidates(const std::vector<MergedRun>& runs, float k, dd_cand* cand
 }
 
 }  // namespace
+
+namespace dd {
+
+int launch_count_scan(const int32_t* cnt, int64_t n, int64_t* offs, int64_t* total, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  if (ntiles > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many counts to scan");
+  if (ntiles > 0) hipLaunchKernelGGL(scan_totals_k, dim3((unsigned)ntiles), dim3(1024), 0, st, cnt, n, offs);
+  hipLaunchKernelGGL(scan_bases_k, dim3(1), dim3(1024), 0, st, n, offs, total);
+  if (ntiles > 0) hipLaunchKernelGGL(scan_apply_k, dim3((unsigned)ntiles), dim3(1024), 0, st, cnt, n, offs);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("count scan launch: ") + hipGetErrorString(e));
+  return DD_OK;
+}
+
+}  // namespace dd
 
 extern "C" {
 
