@@ -112,8 +112,10 @@ struct SearchArgs {
 // Levels 0 .. max_log2 of one thread's window, in place, and the best S/N of its starts:
 // start q takes width w when q + w <= lim (CHECKED; otherwise every width fits). The
 // updates are selects, not branches: a start's best changes only on a strictly larger S/N,
-// so ties keep the smaller width.
-template <bool CHECKED>
+// so ties keep the smaller width. COUNT: only the best S/N, as a maximum over the same S/N
+// values (the counting pass needs neither the width nor the sum; the maximum decides
+// "best > k" exactly as the selects do).
+template <bool CHECKED, bool COUNT>
 __device__ __forceinline__ void search_levels(float (&x)[kSearchWin], float (&best)[kSearchPer],
                                               int (&bj)[kSearchPer], float (&bval)[kSearchPer], int lim, float m,
                                               double r, int max_log2) {
@@ -131,17 +133,22 @@ __device__ __forceinline__ void search_levels(float (&x)[kSearchWin], float (&be
 #pragma unroll
     for (int q = 0; q < kSearchPer; ++q) {
       const float snr = (x[q] - mw) * inv;
-      const bool up = snr > best[q] && (!CHECKED || q + w <= lim);
-      bval[q] = up ? x[q] : bval[q];
-      bj[q] = up ? j : bj[q];
-      best[q] = up ? snr : best[q];
+      if constexpr (COUNT) {
+        if (!CHECKED || q + w <= lim) best[q] = __builtin_fmaxf(best[q], snr);
+      } else {
+        const bool up = snr > best[q] && (!CHECKED || q + w <= lim);
+        bval[q] = up ? x[q] : bval[q];
+        bj[q] = up ? j : bj[q];
+        best[q] = up ? snr : best[q];
+      }
     }
   }
 }
 
-// The best S/N over the widths (and its width index and boxcar sum) for this thread's
-// starts of segment seg of row d; false when the row has no variance (the same for every
-// thread of the workgroup, before any barrier).
+// The best S/N over the widths (and, unless COUNT, its width index and boxcar sum) for this
+// thread's starts of segment seg of row d; false when the row has no variance (the same for
+// every thread of the workgroup, before any barrier).
+template <bool COUNT>
 __device__ __forceinline__ bool search_segment(const SearchArgs& A, int d, int64_t seg, float* buf,
                                                float (&best)[kSearchPer], int (&bj)[kSearchPer],
                                                float (&bval)[kSearchPer]) {
@@ -186,9 +193,9 @@ __device__ __forceinline__ bool search_segment(const SearchArgs& A, int d, int64
   // every start of every width lies inside the row unless this is the row's last segment
   const int lim = (int)min<int64_t>(A.n - (b + a0), (int64_t)kSearchWin);
   if (lim >= kSearchWin)
-    search_levels<false>(x, best, bj, bval, lim, m, r, A.max_log2);
+    search_levels<false, COUNT>(x, best, bj, bval, lim, m, r, A.max_log2);
   else
-    search_levels<true>(x, best, bj, bval, lim, m, r, A.max_log2);
+    search_levels<true, COUNT>(x, best, bj, bval, lim, m, r, A.max_log2);
   return true;
 }
 
@@ -202,7 +209,7 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_count(SearchArgs A, int64_
   float bval[kSearchPer];
   if (threadIdx.x == 0) total = 0;
   __syncthreads();
-  if (search_segment(A, d, seg, buf, best, bj, bval)) {
+  if (search_segment<true>(A, d, seg, buf, best, bj, bval)) {
     int c = 0;
 #pragma unroll
     for (int q = 0; q < kSearchPer; ++q) c += best[q] > A.k ? 1 : 0;
@@ -227,7 +234,7 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_write(SearchArgs A, int64_
   float best[kSearchPer];
   int bj[kSearchPer];
   float bval[kSearchPer];
-  search_segment(A, d, seg, buf, best, bj, bval);
+  search_segment<false>(A, d, seg, buf, best, bj, bval);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int c = 0;
 #pragma unroll
