@@ -108,6 +108,10 @@ namespace dd {
 // Thread-local error message helpers (implemented in plan.cpp).
 int fail(int code, const std::string& msg);
 void clear_error();
+// dd_plan_create with the LDS bytes one workgroup may take (csrc/plan.cpp); dd_plan_create
+// passes kLdsBytes.
+int plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm,
+                int32_t ndm, int32_t in_dtype, const dd_tuning* tuning, int64_t lds_cap);
 
 // Workspace layout for one dd_dedisperse call.
 struct WsLayout {

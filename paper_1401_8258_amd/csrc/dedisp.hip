@@ -2402,15 +2402,33 @@ int dd_subband_create(dd_subband** out, const double* freq_mhz, int32_t nchan, d
     sp->step1.push_back(p);
     fsub.push_back(*std::max_element(freq_mhz + s.first, freq_mhz + s.second));
   }
-  // step 2: groups of dms_per_group trials share a workgroup (8 trials per wavefront)
+  // step 2: groups of dms_per_group trials share a workgroup, 4 trials per computing
+  // wavefront beside 2 producers. A step-2 plan walks only the subbands, so its units are
+  // short: the LDS budget lets as many workgroups share a CU as its 16 wavefront slots
+  // hold (two for groups of 16), and each takes the budget's share of the LDS.
   dd_tuning t2{};
-  t2.dms_per_wave = 8;
-  t2.waves = std::max(1, std::min(6, (dms_per_group + 7) / 8));
+  t2.dms_per_wave = 4;
+  t2.waves = std::max(1, std::min(14, (dms_per_group + 3) / 4));
+  t2.producer_waves = 2;
   t2.kernel_form = DD_FORM_LDS;
+  const int64_t share = std::max(1, 16 / (t2.waves + t2.producer_waves));
   for (size_t g = 0; rc == DD_OK && g < sp->groups.size(); ++g) {
     dd_plan* p = nullptr;
-    rc = dd_plan_create(&p, fsub.data(), (int32_t)fsub.size(), tsamp_s, dm + sp->groups[g].first,
-                        sp->groups[g].second - sp->groups[g].first, DD_F32, &t2);
+    // the budget's share, or the whole LDS when one group's windows need more; 8 trials per
+    // wavefront when they do not fit the producers' DMAs at all
+    const int32_t d0 = sp->groups[g].first, nd = sp->groups[g].second - sp->groups[g].first;
+    for (int64_t div = share; div >= 1; div = div > 1 ? 1 : 0) {
+      rc = dd::plan_create(&p, fsub.data(), (int32_t)fsub.size(), tsamp_s, dm + d0, nd, DD_F32, &t2,
+                           dd::kLdsBytes / div);
+      if (rc != DD_ERR_UNSUPPORTED) break;
+    }
+    if (rc == DD_ERR_UNSUPPORTED) {
+      dd_tuning t8{};
+      t8.dms_per_wave = 8;
+      t8.waves = std::max(1, std::min(6, (dms_per_group + 7) / 8));
+      t8.kernel_form = DD_FORM_LDS;
+      rc = dd_plan_create(&p, fsub.data(), (int32_t)fsub.size(), tsamp_s, dm + d0, nd, DD_F32, &t8);
+    }
     if (rc) break;
     sp->step2.push_back(p);
   }

@@ -314,8 +314,14 @@ const char* dd_last_error(void) { return g_err.c_str(); }
 
 const char* dd_version(void) { return "1.5"; }
 
-int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
-                   const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning) {
+}  // extern "C"
+
+namespace dd {
+
+// dd_plan_create with the LDS bytes one workgroup may take (the ring and slots are sized
+// within it; a smaller budget lets several workgroups share a CU).
+int plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s, const double* dm,
+                int32_t ndm, int32_t in_dtype, const dd_tuning* tuning, int64_t lds_cap) {
   dd::clear_error();
   if (!out) return dd::fail(DD_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -416,7 +422,7 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
     return DD_OK;
   }
   if (try_regwin) {
-    if (dd::plan_regwin(p, dd::kLdsBytes)) {
+    if (dd::plan_regwin(p, lds_cap)) {
       p->id = g_next_id.fetch_add(1);
       *out = p;
       return DD_OK;
@@ -451,7 +457,7 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
     for (int oi = 0; oi < 5 && !placed; ++oi) {
       const int nw = t.w ? t.w : std::min(wp_opts[oi], maxw - npw);
       const int32_t sp = compute_span(p->delays, nchan, ndm, g * nw);
-      const dd::Launch l = dd::choose_launch_prod(sp, nchan, t.cc, dd::kLdsBytes, npw);
+      const dd::Launch l = dd::choose_launch_prod(sp, nchan, t.cc, lds_cap, npw);
       if (l.nb >= 2) t.g = g, t.w = nw, span = sp, lg = l, placed = true;  // the most wavefronts that fit
       if (t.w) break;
     }
@@ -468,7 +474,7 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   for (int oi = 0; oi < 4 && !placed; ++oi) {
     const int nw = t.w ? t.w : w_opts[oi];
     span = compute_span(p->delays, nchan, ndm, t.g * nw);
-    lg = dd::choose_launch(span, nw, nchan, t.cc, dd::kLdsBytes, (int)dd::elem_bytes(in_dtype));
+    lg = dd::choose_launch(span, nw, nchan, t.cc, lds_cap, (int)dd::elem_bytes(in_dtype));
     if (t.w || (lg.nb >= 2 && (int64_t)lg.nb * lg.cs >= std::min(8, nchan + 1)) || nw == 1) {
       t.w = nw;
       break;
@@ -509,6 +515,15 @@ int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double 
   p->id = g_next_id.fetch_add(1);
   *out = p;
   return DD_OK;
+}
+
+}  // namespace dd
+
+extern "C" {
+
+int dd_plan_create(dd_plan** out, const double* freq_mhz, int32_t nchan, double tsamp_s,
+                   const double* dm, int32_t ndm, int32_t in_dtype, const dd_tuning* tuning) {
+  return dd::plan_create(out, freq_mhz, nchan, tsamp_s, dm, ndm, in_dtype, tuning, dd::kLdsBytes);
 }
 
 void dd_plan_destroy(dd_plan* plan) { delete plan; }
