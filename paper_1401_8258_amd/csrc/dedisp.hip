@@ -1714,9 +1714,14 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
       BatchFn k = pick_batch_kernel(gr.key.dtype, form);
       rc = set_lds((const void*)k, gr.lds);
       if (rc) return rc;
-      // one resident workgroup per CU (the LDS ring fills a CU), in whole XCD groups of 8;
-      // `units` is the largest per-XCD share
-      const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu, gr.units * 8) / 8 * 8);
+      // as many resident workgroups per CU as the LDS and the wavefront slots hold (four
+      // wavefronts per SIMD at the 4-trial form's registers, two at the 8-trial form's;
+      // one workgroup when its ring fills the LDS), in whole XCD groups of 8; `units` is
+      // the largest per-XCD share
+      const int64_t wg_waves = gr.key.waves + gr.key.prod;
+      const int64_t per_cu = std::max<int64_t>(
+          1, std::min<int64_t>(dd::kLdsBytes / std::max<int64_t>(gr.lds, 1), (gr.key.per_wave == 4 ? 16 : 8) / wg_waves));
+      const int64_t nblocks = std::max<int64_t>(8, std::min<int64_t>((int64_t)ncu * per_cu, gr.units * 8) / 8 * 8);
       hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (gr.key.waves + gr.key.prod)), (size_t)gr.lds, st,
                          (const KParams*)(dP + gr.first), (const int64_t*)(dS + gr.run_at), (int)gr.count);
       e = hipGetLastError();
