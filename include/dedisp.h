@@ -101,7 +101,8 @@ enum {
                           is shared by few trials. dms_per_wave 1, 2 or 4 (default 2), waves
                           1..8 (default 4), samples_per_lane 16; chan_stage and
                           producer_waves are ignored. Batched items of this form run in one
-                          launch beside the LDS-form items' launch */
+                          launch per tile shape and wavefront count, beside the LDS-form
+                          items' launches */
 };
 
 typedef struct dd_plan dd_plan;

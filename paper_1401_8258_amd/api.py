@@ -307,7 +307,8 @@ def alloc_outputs(ndm: int, ncols: int, device, k_sigma: float = 0.0, cand_cap: 
 
 def batch_dedisperse(jobs, k_sigma: float = 0.0, cand_cap: int = 1 << 16, stats: bool = True, stream=None,
                      outputs=None):
-    """Dedisperse several inputs in one persistent launch (dd_batch_dedisperse).
+    """Dedisperse several inputs in one batched call (dd_batch_dedisperse): one persistent
+    launch per kernel shape.
 
     jobs: a list of (Plan, tensor) pairs and/or (Stream, (t0, nout)) pairs, the latter
     after Stream.append returned a pending window. Plans of any tiles and forms mix, except
