@@ -48,17 +48,27 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_rows(const float* __restri
 #pragma unroll
     for (int i = 0; i < 4; ++i) v[i] = s0 + i < n ? row[s0 + i] : 0.0f;
   }
-  // level 0 is the series itself
+  // level 0 is the series itself; whole 4-sample chunks of an aligned output row are
+  // stored with one 16-byte (level 0) and one 8-byte (level 1, n even) store
+  const bool ovec = (reinterpret_cast<uintptr_t>(orow) & 15) == 0 && s0 + 3 < n;
+  if (ovec) {
+    *reinterpret_cast<float4*>(orow + s0) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (s0 + i < n) orow[s0 + i] = v[i];
+    for (int i = 0; i < 4; ++i)
+      if (s0 + i < n) orow[s0 + i] = v[i];
+  }
   if (levels >= 1) {
     const int64_t off = n;
     const float norm = 0.70710678118654752f;
     const float a = v[0] + v[1], b = v[2] + v[3];
     const int64_t j = s0 >> 1;
-    if (((j + 1) << 1) <= n) orow[off + j] = a * norm;
-    if (((j + 2) << 1) <= n) orow[off + j + 1] = b * norm;
+    if (ovec && (n & 1) == 0) {
+      *reinterpret_cast<float2*>(orow + off + j) = make_float2(a * norm, b * norm);
+    } else {
+      if (((j + 1) << 1) <= n) orow[off + j] = a * norm;
+      if (((j + 2) << 1) <= n) orow[off + j + 1] = b * norm;
+    }
     float s = a + b;  // level 2: 4 samples
     if (levels >= 2 && ((s0 >> 2) + 1) << 2 <= n) orow[level_offset(n, 2) + (s0 >> 2)] = s * 0.5f;
     // levels 3 .. 6: the 8-, 16-, 32- and 64-sample windows span 2, 4, 8 and 16 lanes
