@@ -141,7 +141,11 @@ __global__ __launch_bounds__(kRfiThreads) void chan_flag(const double* __restric
 }
 
 __device__ __forceinline__ bool replaced(const int32_t* f, int64_t w, int64_t nwin) {
-  return f[w] != 0 || (w > 0 && f[w - 1] != 0) || (w + 1 < nwin && f[w + 1] != 0);
+  // the three flags are loaded together (indices clamped into the row, then masked)
+  const int32_t self = f[w];
+  const int32_t prev = f[w > 0 ? w - 1 : w];
+  const int32_t next = f[w + 1 < nwin ? w + 1 : w];
+  return (self | (w > 0 ? prev : 0) | (w + 1 < nwin ? next : 0)) != 0;
 }
 
 // One lane per (channel, window): a window with no flag on it or its neighbours leaves at
@@ -177,16 +181,20 @@ __global__ __launch_bounds__(kRfiThreads) void chan_correct(float* __restrict__ 
   const int64_t wa = b0 / window;
   const int64_t wb = ((b0 + kCorrSamples < n ? b0 + kCorrSamples : n) - 1) / window;
   const int32_t* f = flags ? flags + c * nwin : nullptr;
+  // the samples' load is issued before the window decisions are gathered, so its latency
+  // overlaps theirs
+  const int64_t t0 = b0 + 4 * threadIdx.x;
+  const bool vec = t0 + 3 < n && (reinterpret_cast<uintptr_t>(row) & 15) == 0;
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (vec) v = *reinterpret_cast<const float4*>(row + t0);
   for (int64_t w = wa + threadIdx.x; w <= wb; w += kRfiThreads) rep[w - wa] = f && replaced(f, w, nwin) ? 1 : 0;
   __syncthreads();
-  const int64_t t0 = b0 + 4 * threadIdx.x;
   if (t0 >= n) return;
   const float fv = (float)fit[c];
   bool hit[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) hit[i] = t0 + i < n && rep[(t0 + i) / window - wa] != 0;
-  if (t0 + 3 < n && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
-    float4 v = *reinterpret_cast<const float4*>(row + t0);
+  if (vec) {
     v.x = hit[0] ? 0.f : v.x - fv;
     v.y = hit[1] ? 0.f : v.y - fv;
     v.z = hit[2] ? 0.f : v.z - fv;
