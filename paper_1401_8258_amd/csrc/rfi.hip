@@ -9,8 +9,8 @@
 //   in order) and writes the channel mean. One read of the input.
 // * bandpass_windows: the same average together with every window's mean (the channel
 //   stage's statistic), so the channel stage needs no read of its own: each wavefront sums
-//   its windows (four at a time, a butterfly each) and the channel total is the sum of its
-//   window sums in a fixed order.
+//   its windows four at a time (closed together by one transposing reduction) and the
+//   channel total is the sum of its window sums in a fixed order.
 // * bandpass_windows_u8: exact integer sums (v_sad_u8 over 16-byte loads). A 16-byte
 //   aligned row whose window is 16 L bytes (L = 1, 2, ..., 64) is read in 1 KB lines, one
 //   window per group of L lanes, four lines in flight per lane; other rows one window per
@@ -117,14 +117,25 @@ __global__ __launch_bounds__(kRfiThreads) void bandpass_windows(const float* __r
       const int64_t start = vec4 ? 4 * (len[k] / 4) : 0;
       for (int64_t i = start + lane; i < len[k]; i += 64) s[k] += (double)row[(wg + 4 * k) * window + i];
     }
+    // the four window sums in 7 shuffles instead of 4 x 6: across 32 lanes the lower half
+    // keeps windows 0 and 1 and the upper half 2 and 3, across 16 lanes each quarter keeps
+    // one, then a 16-lane butterfly; window k's sum ends in lanes 16k .. 16k + 15
+    static_assert(kGroup == 4, "the transposing reduction takes four windows");
+    const bool hi32 = (lane & 32) != 0, hi16 = (lane & 16) != 0;
+    double k0 = hi32 ? s[2] : s[0], k1 = hi32 ? s[3] : s[1];
+    k0 += __shfl_xor(hi32 ? s[0] : s[2], 32, 64);
+    k1 += __shfl_xor(hi32 ? s[1] : s[3], 32, 64);
+    double ws = (hi16 ? k1 : k0) + __shfl_xor(hi16 ? k0 : k1, 16, 64);
 #pragma unroll
-    for (int k = 0; k < kGroup; ++k) {
-      if (len[k] == 0) break;
-      const double ws = wave_sum(s[k]);
+    for (int off = 8; off > 0; off >>= 1) ws += __shfl_xor(ws, off, 64);
+    const int mine = lane >> 4;  // the window this lane's sum belongs to
+    const int64_t lm = mine == 0 ? len[0] : mine == 1 ? len[1] : mine == 2 ? len[2] : len[3];
+    if ((lane & 15) == 0 && lm > 0) {
       tot += ws;
-      if (lane == 0) means[(int64_t)blockIdx.x * nwin + wg + 4 * k] = ws / (double)len[k];
+      means[(int64_t)blockIdx.x * nwin + wg + 4 * mine] = ws / (double)lm;
     }
   }
+  tot = wave_sum(tot);  // the window sums sit in lanes 0, 16, 32 and 48
   if (lane == 0) red[wv] = tot;
   __syncthreads();
   if (threadIdx.x == 0) avg[blockIdx.x] = ((red[0] + red[1]) + (red[2] + red[3])) / (double)n;
