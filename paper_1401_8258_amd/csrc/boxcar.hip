@@ -138,8 +138,11 @@ __device__ __forceinline__ void search_levels(float (&x)[kSearchWin], float (&be
 #pragma unroll
       for (int t = 0; t + w <= kSearchWin; ++t) x[t] = x[t] + x[t + (w >> 1)];
     }
-    const float mw = m * (float)w;
-    const float inv = (float)(1.0 / (r * sqrt((double)w)));
+    // wave-uniform constants of the width, kept in scalar registers (readfirstlane of a
+    // uniform value is exact), so a caller's loop does not hold them in vector registers
+    const float mw = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m * (float)w)));
+    const float inv =
+        __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)(1.0 / (r * sqrt((double)w))))));
 #pragma unroll
     for (int q = 0; q < kSearchPer; ++q) {
       const float snr = (x[q] - mw) * inv;
@@ -209,24 +212,87 @@ __device__ __forceinline__ bool search_segment(const SearchArgs& A, int d, int64
   return true;
 }
 
+// Counting pass: workgroup (g, d) counts segments kCountSegs g .. of row d. A segment that
+// lies wholly inside the row reaches LDS by DMA (one wavefront instruction per 64-sample
+// run, 4 padding words after each run), double-buffered: the next segment's DMAs are in
+// flight while this one is searched. A row's last, partial segment is loaded through
+// registers. Each segment's count is the same integer sum as before, so the decisions and
+// counts equal the writing pass's.
+constexpr int kCountSegs = 4;                                 // segments per counting workgroup
+constexpr int kRun = 64;                                      // samples per DMA instruction
+constexpr int kRunPad = 4;                                    // LDS words after each run
+constexpr int kRuns = kSearchSamples / kRun;                  // 65 runs per segment
+constexpr int kRunWords = kRuns * (kRun + kRunPad);           // one buffer
+static_assert(kSearchSamples % kRun == 0, "a segment is whole runs");
+__device__ __forceinline__ int pad_run(int a) { return a + kRunPad * (a >> 6); }
+
 __global__ __launch_bounds__(kBoxThreads) void boxcar_count(SearchArgs A, int64_t nseg, int32_t* __restrict__ cnt) {
-  __shared__ __align__(16) float buf[kSearchLds];
-  __shared__ int total;
+  __shared__ __align__(16) float buf[2][kRunWords];
+  __shared__ int wsum[2][kBoxThreads / 64];
   const int d = blockIdx.y;
-  const int64_t seg = blockIdx.x;
-  float best[kSearchPer];
-  int bj[kSearchPer];
-  float bval[kSearchPer];
-  if (threadIdx.x == 0) total = 0;
-  __syncthreads();
-  if (search_segment<true>(A, d, seg, buf, best, bj, bval)) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the DMAs' LDS address is scalar
+  const int64_t seg0 = (int64_t)blockIdx.x * kCountSegs;
+  const int nmine = (int)min<int64_t>(kCountSegs, nseg - seg0);  // >= 1: the grid covers nseg
+  const float* row = A.x + (int64_t)d * A.stride;
+  const float m = A.mean ? A.mean[d] : 0.0f;
+  const double r = A.rms ? (double)A.rms[d] : 1.0;
+  if (!(r > 0.0)) {  // no variance: no detections (the same for the whole workgroup)
+    if (tid < nmine) cnt[(int64_t)d * nseg + seg0 + tid] = 0;
+    return;
+  }
+  const int ndma = (kRuns - wv + 3) / 4;  // this wavefront's DMAs per segment: runs wv, wv + 4, ...
+  auto full = [&](int64_t seg) { return A.n - seg * kSearchSeg >= kSearchSamples; };
+  auto issue = [&](int64_t seg, int b) {  // a whole segment: every sample it reads is inside the row
+    const float* src = row + seg * kSearchSeg;
+    const unsigned lb = dd::lds_addr(&buf[b][0]);
+    for (int rr = wv; rr < kRuns; rr += 4)
+      dd::dma<4>(src, (unsigned)(4 * (rr * kRun + lane)),
+                 __builtin_amdgcn_readfirstlane(lb + 4u * (unsigned)(rr * (kRun + kRunPad))));
+  };
+  // the row's last segment, through registers: -inf past the row, so that every window
+  // reaching past it sums to -inf (or NaN) and never wins the maximum, the count the writing
+  // pass's bound check gives
+  auto load_regs = [&](int64_t seg, int b) {
+    const int64_t navail = A.n - seg * kSearchSeg;
+    const float* src = row + seg * kSearchSeg;
+    for (int a = tid; a < kSearchSamples; a += kBoxThreads) buf[b][pad_run(a)] = a < navail ? src[a] : -INFINITY;
+  };
+  if (full(seg0)) issue(seg0, 0);
+  else load_regs(seg0, 0);
+  for (int j = 0; j < nmine; ++j) {
+    const int64_t seg = seg0 + j;
+    const int b = j & 1;
+    const bool next_dma = j + 1 < nmine && full(seg + 1);
+    if (next_dma) issue(seg + 1, b ^ 1);  // buffer b ^ 1 was last read before the previous barrier
+    dd::wait_vm(next_dma ? ndma : 0);     // this segment's DMAs have landed (the next ones may not)
+    __syncthreads();                      // ... for every wavefront; register-loaded samples too
+    float x[kSearchWin];
+    const int a0 = kSearchPer * tid;
+#pragma unroll
+    for (int c = 0; c < kSearchWin / 4; ++c) {
+      const float4 v = *reinterpret_cast<const float4*>(&buf[b][pad_run(a0 + 4 * c)]);
+      x[4 * c] = v.x;
+      x[4 * c + 1] = v.y;
+      x[4 * c + 2] = v.z;
+      x[4 * c + 3] = v.w;
+    }
+    float best[kSearchPer];
+    int bj[kSearchPer];
+    float bval[kSearchPer];
+#pragma unroll
+    for (int q = 0; q < kSearchPer; ++q) best[q] = -INFINITY, bj[q] = 0, bval[q] = 0.0f;
+    search_levels<false, true>(x, best, bj, bval, kSearchWin, m, r, A.max_log2);
     int c = 0;
 #pragma unroll
     for (int q = 0; q < kSearchPer; ++q) c += best[q] > A.k ? 1 : 0;
-    atomicAdd(&total, c);  // integer sum: order-free
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) wsum[b][wv] = c;
+    __syncthreads();  // every wavefront is done with buffer b; the four counts are in LDS
+    if (tid == 0) cnt[(int64_t)d * nseg + seg] = wsum[b][0] + wsum[b][1] + wsum[b][2] + wsum[b][3];
+    if (j + 1 < nmine && !next_dma) load_regs(seg + 1, b ^ 1);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) cnt[(int64_t)d * nseg + seg] = total;
 }
 
 // Detections in ascending t: thread i's starts precede thread i + 1's, so a thread's slot
@@ -327,7 +393,8 @@ extern "C" int dd_boxcar_search(const float* d_series, int64_t nrows, int64_t n,
   int64_t* offs = reinterpret_cast<int64_t*>(ws + l.offs_off);
   const SearchArgs A{d_series, n, row_stride, d_mean, d_rms, (int)max_log2, k_sigma};
   const dim3 grid((unsigned)l.nseg, (unsigned)nrows);
-  hipLaunchKernelGGL(boxcar_count, grid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt);
+  const dim3 cgrid((unsigned)((l.nseg + kCountSegs - 1) / kCountSegs), (unsigned)nrows);
+  hipLaunchKernelGGL(boxcar_count, cgrid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt);
   const int rc = dd::launch_count_scan(cnt, nrows * l.nseg, offs, d_npulse, st);
   if (rc) return rc;
   hipLaunchKernelGGL(boxcar_write, grid, dim3(kBoxThreads), 0, st, A, l.nseg, cnt, offs, d_pulse, cap);
