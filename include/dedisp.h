@@ -291,8 +291,9 @@ int dd_candidates_check(const int64_t* d_ncand, int64_t cand_cap, void* stream, 
  * (LDS form: input dtype, computing and producer wavefronts, DM trials per wavefront;
  * direct-read form: DM trials per wavefront, samples per lane, wavefronts) run in one
  * launch that walks a device queue of (item, DM group, time tile) work, one launch per
- * distinct shape, each item on its own plan's tiles; then the statistics and candidates of
- * all items take one launch per step. The results equal those of one dd_dedisperse per
+ * distinct shape, each item on its own plan's tiles (an item of many units takes its plain
+ * launch instead); then the statistics and candidates of all items take one launch per
+ * step. The results equal those of one dd_dedisperse per
  * item, bit for bit. Register-window plans are refused (DD_ERR_UNSUPPORTED).
  */
 typedef struct dd_batch_item {

@@ -1562,6 +1562,15 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
   return DD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// LDS-form batch items with at least this many (tile, DM group) units take a plain launch
+constexpr int64_t kBatchPlainUnits = 4096;
+}  // namespace
+
+extern "C" {
+
 int dd_batch_query(const dd_batch_item* items, int32_t n, int64_t* ws_bytes) {
   dd::clear_error();
   if (!ws_bytes || n < 1 || !items) return dd::fail(DD_ERR_INVALID_ARG, "need items, n >= 1 and ws_bytes");
@@ -1661,6 +1670,26 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   }
   char* bw = static_cast<char*>(d_workspace);
   const int64_t lds_desc = dd::align_up((int64_t)n * (int64_t)sizeof(KParams)) + dd::align_up((int64_t)8 * 8 * 2 * n);
+  // An item with many units takes the plain launch of its own: the persistent loop pays
+  // off for many small items, and a large one fills the GPU by itself (same tile body,
+  // same results).
+  for (size_t i = 0; i < P.size();) {
+    if (P[i].nitems < kBatchPlainUnits) {
+      ++i;
+      continue;
+    }
+    KernFn k = pick_kernel(keys[i].dtype, P[i]);
+    rc = set_lds((const void*)k, ldss[i]);
+    if (rc) return rc;
+    const int64_t nblocks = (P[i].nitems + 7) / 8 * 8;
+    if (nblocks > 0x7fffffff) return dd::fail(DD_ERR_UNSUPPORTED, "too many work items");
+    hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(64 * (P[i].nw + P[i].nprod)), (size_t)ldss[i], st, P[i]);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "dedisp_tile launch");
+    P.erase(P.begin() + (std::ptrdiff_t)i);
+    keys.erase(keys.begin() + (std::ptrdiff_t)i);
+    ldss.erase(ldss.begin() + (std::ptrdiff_t)i);
+  }
   if (!P.empty()) {
     // one persistent launch per distinct key, in order of first appearance; each launch's
     // records are contiguous, then its XCD runs [xcd][item + 1]

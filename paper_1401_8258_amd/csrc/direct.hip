@@ -396,6 +396,9 @@ int64_t direct_batch_desc_bytes(int32_t n) {
   return align_up((int64_t)n * (int64_t)sizeof(DRParams)) + align_up((int64_t)8 * 8 * 2 * n);
 }
 
+// Direct-read batch items with at least this many (tile, DM group) units take a plain launch.
+constexpr int64_t kDirectPlainUnits = 12288;
+
 int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int64_t desc_bytes, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int32_t n = (int32_t)items.size();
@@ -407,6 +410,25 @@ int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int6
     int rc = prepare(it.plan, it.in, it.table, it.nout, it.out, it.out_stride, it.part, it.quad_ws, st, &all[i]);
     if (rc) return rc;
   }
+  // An item with many units takes the plain launch of its own (a large beam fills the GPU
+  // by itself; the persistent loop pays off for many small items, such as serving blocks).
+  std::vector<DRParams> rest;
+  for (const DRParams& r : all) {
+    if (r.nitems < kDirectPlainUnits) {
+      rest.push_back(r);
+      continue;
+    }
+    const int64_t nblocks = (r.nitems + 7) / 8 * 8;
+    if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
+    switch (r.tiles_g * 10 + r.tiles_s) {
+      case 11: launch_gs<1, 1>(r, nblocks, st); break;
+      case 21: launch_gs<2, 1>(r, nblocks, st); break;
+      case 41: launch_gs<4, 1>(r, nblocks, st); break;
+      case 12: launch_gs<1, 2>(r, nblocks, st); break;
+      default: launch_gs<2, 2>(r, nblocks, st); break;
+    }
+  }
+  all.swap(rest);
   // records grouped by tile shape and wavefront count (one kernel instantiation and
   // workgroup size per launch: every item keeps its own tiles), then per group the XCD runs
   // after all the records
@@ -441,9 +463,13 @@ int launch_direct_batch(const std::vector<DirectItem>& items, void* d_desc, int6
   char* bw = static_cast<char*>(d_desc);
   DRParams* dP = reinterpret_cast<DRParams*>(bw);
   int64_t* dS = reinterpret_cast<int64_t*>(bw + align_up((int64_t)n * (int64_t)sizeof(DRParams)));
-  hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(DRParams), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dS, run.data(), run.size() * 8, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("hipMemcpyAsync (batch descriptors): ") + hipGetErrorString(e));
+  hipError_t e = hipSuccess;
+  if (!P.empty()) {
+    e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(DRParams), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dS, run.data(), run.size() * 8, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess)
+      return fail(DD_ERR_HIP, std::string("hipMemcpyAsync (batch descriptors): ") + hipGetErrorString(e));
+  }
   for (const Group& gr : groups) {
     const int64_t nblocks = 8 * gr.longest;
     if (nblocks > 0x7fffffff) return fail(DD_ERR_UNSUPPORTED, "too many work items");
