@@ -1565,8 +1565,10 @@ int dd_stream_push(dd_stream* s, const void* d_block, int64_t nsamp, int64_t in_
 }  // extern "C"
 
 namespace {
-// LDS-form batch items with at least this many (tile, DM group) units take a plain launch
+// LDS-form batch items with at least this many (tile, DM group) units, or units times
+// channels, take a plain launch
 constexpr int64_t kBatchPlainUnits = 4096;
+constexpr int64_t kBatchPlainWork = (int64_t)1 << 20;
 }  // namespace
 
 extern "C" {
@@ -1674,7 +1676,7 @@ int dd_batch_dedisperse(const dd_batch_item* items, int32_t n, void* d_workspace
   // off for many small items, and a large one fills the GPU by itself (same tile body,
   // same results).
   for (size_t i = 0; i < P.size();) {
-    if (P[i].nitems < kBatchPlainUnits) {
+    if (P[i].nitems < kBatchPlainUnits && P[i].nitems * P[i].nchan < kBatchPlainWork) {
       ++i;
       continue;
     }
