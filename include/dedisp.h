@@ -494,7 +494,12 @@ void dd_binned_destroy(dd_binned* b);
 typedef struct dd_binned_stream dd_binned_stream;
 int dd_binned_stream_query(const dd_binned* b, int64_t block_nsamp, int64_t* ring_bytes, int64_t* workspace_bytes);
 /* The binned plan must outlive the stream. Uploads every run's delay table into d_ring on
-   `stream`. */
+   `stream`. The object also creates, on the current device, one HIP stream (default
+   priority) and one event per run, plus one more event: an unbatched push runs each run's
+   dedispersion on its own stream, after the block's appends on the caller's stream, which
+   then waits for all of them before the merged candidates. Use the object on the device
+   it was created on; dd_binned_stream_destroy releases these as well. DD_ERR_HIP if they
+   cannot be created. */
 int dd_binned_stream_create(const dd_binned* b, int64_t block_nsamp, void* d_ring, int64_t ring_bytes, void* stream,
                             dd_binned_stream** out);
 /*

@@ -2091,8 +2091,18 @@ struct dd_binned_stream {
   int64_t block = 0;
   int32_t kmax = 0;
   std::vector<dd_stream*> runs;
+  // one side stream per run (default priority) and the events that order them after the
+  // block's appends and before the merged candidates: the runs' dedispersion is
+  // independent (own rings, workspaces and output rows), and each run alone leaves most of
+  // the GPU idle
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> done;
+  hipEvent_t ready = nullptr;
   ~dd_binned_stream() {
     for (dd_stream* s : runs) dd_stream_destroy(s);
+    for (hipStream_t x : side) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : done) (void)hipEventDestroy(e);
+    if (ready) (void)hipEventDestroy(ready);
   }
 };
 
@@ -2210,6 +2220,19 @@ int dd_binned_stream_create(const dd_binned* b, int64_t block_nsamp, void* d_rin
     }
     s->runs.push_back(rs);
   }
+  hipError_t e = hipEventCreateWithFlags(&s->ready, hipEventDisableTiming);
+  for (size_t i = 0; e == hipSuccess && i < b->runs.size(); ++i) {
+    hipStream_t x = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+    if (e == hipSuccess) s->side.push_back(x);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) s->done.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "binned stream: side streams and events");
+  }
   *out = s;
   return DD_OK;
 }
@@ -2300,6 +2323,9 @@ int dd_binned_stream_push(dd_binned_stream* s, const void* d_block, int64_t nsam
     }
     rc = dd_batch_dedisperse(items.data(), (int32_t)items.size(), ws + L.batch_off, L.cand_off - L.batch_off, stream);
   } else {
+    // each run on its own side stream, after the appends and before the merged candidates
+    hipError_t e = hipEventRecord(s->ready, st);
+    if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord (binned stream)");
     for (size_t i = 0; i < nr && rc == DD_OK; ++i) {
       if (n[i] == 0) continue;
       const dd_binned::Run& r = b->runs[i];
@@ -2309,9 +2335,18 @@ int dd_binned_stream_push(dd_binned_stream* s, const void* d_block, int64_t nsam
                       rs->ring_len, t0[i]};
       const Outputs o{d_out + (int64_t)r.d0 * out_row_stride, out_row_stride, stats ? d_mean + r.d0 : nullptr,
                       stats ? d_rms + r.d0 : nullptr, k_sigma, nullptr, 0, nullptr, t0[i]};
-      rc = run_pipeline(p, in, static_cast<const int32_t*>(rs->ring), n[i], o, ws + L.run_off[i], L.run_l[i], st,
-                        true);
+      e = hipStreamWaitEvent(s->side[i], s->ready, 0);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "hipStreamWaitEvent (binned stream)");
+        break;
+      }
+      rc = run_pipeline(p, in, static_cast<const int32_t*>(rs->ring), n[i], o, ws + L.run_off[i], L.run_l[i],
+                        s->side[i], true);
       rs->pending_n = 0;
+      if (rc) break;
+      e = hipEventRecord(s->done[i], s->side[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, s->done[i], 0);
+      if (e != hipSuccess) rc = hip_fail(e, "binned stream: joining a run");
     }
   }
   if (rc) {
