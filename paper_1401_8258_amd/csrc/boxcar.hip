@@ -213,12 +213,11 @@ __device__ __forceinline__ bool search_segment(const SearchArgs& A, int d, int64
 }
 
 // Counting pass: workgroup (g, d) counts segments kCountSegs g .. kCountSegs (g + 1) - 1 of
-// row d. A segment that
-// lies wholly inside the row reaches LDS by DMA (one wavefront instruction per 64-sample
-// run, 4 padding words after each run), double-buffered: the next segment's DMAs are in
-// flight while this one is searched. A row's last, partial segment is loaded through
-// registers. Each segment's count is the same integer sum as before, so the decisions and
-// counts equal the writing pass's.
+// row d. A segment that lies wholly inside the row reaches LDS by DMA (one wavefront
+// instruction per 64-sample run, 4 padding words after each run), double-buffered: the
+// next segment's DMAs are in flight while this one is searched. A row's last, partial
+// segment is loaded through registers. Each segment's count is the integer number of its
+// starts whose best S/N exceeds k, decided as in the writing pass.
 constexpr int kCountSegs = 8;                                 // segments per counting workgroup
 constexpr int kRun = 64;                                      // samples per DMA instruction
 constexpr int kRunPad = 4;                                    // LDS words after each run
