@@ -471,7 +471,10 @@ int dd_binned_upload(const dd_binned* b, int64_t nsamp, void* d_workspace, int64
    sample starts (binned index << log2); *d_ncand the true count (as dd_dedisperse).
    batched != 0 runs the runs' dedispersion through one dd_batch_dedisperse call
    (DD_ERR_UNSUPPORTED when a run is in the register-window form); the results are the same
-   bit for bit. The workspace comes from dd_binned_upload for this
+   bit for bit. Unbatched, each run runs on a side stream of its own as soon as its
+   downfactored input exists, and `stream` waits for all of them. These side streams and
+   their events (default priority) belong to the calling host thread and the current
+   device, are created on first use and kept until the process ends. The workspace comes from dd_binned_upload for this
    nsamp. Errors as dd_dedisperse. */
 int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
                          int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,

@@ -1854,6 +1854,43 @@ struct BinnedLayout {
   int64_t batch_off = 0, cand_off = 0, total = 0;
 };
 
+// Side streams (default priority) and events that let a binned plan's runs overlap, per
+// host thread and device: a plan is an immutable object that several threads may share.
+// Created on first use and kept for the life of the process.
+struct SidePool {
+  int dev = -1;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+};
+int side_pool(size_t nstreams, size_t nevents, SidePool** out) {
+  thread_local std::vector<SidePool> pools;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  SidePool* p = nullptr;
+  for (SidePool& q : pools)
+    if (q.dev == dev) p = &q;
+  if (!p) {
+    pools.push_back(SidePool{});
+    p = &pools.back();
+    p->dev = dev;
+  }
+  while (p->streams.size() < nstreams) {
+    hipStream_t x = nullptr;
+    e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags (binned runs)");
+    p->streams.push_back(x);
+  }
+  while (p->events.size() < nevents) {
+    hipEvent_t x = nullptr;
+    e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags (binned runs)");
+    p->events.push_back(x);
+  }
+  *out = p;
+  return DD_OK;
+}
+
 int binned_layout(const dd_binned* b, int64_t nsamp, BinnedLayout* L) {
   int64_t o = 0;
   int kmax = 0;
@@ -2022,10 +2059,23 @@ int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, in
   int64_t lvl_stride = in_row_stride;
   std::vector<const void*> level_ptr(kmax + 1, d_in);
   std::vector<int64_t> level_stride(kmax + 1, in_row_stride);
+  // unbatched: each run on a side stream of its own, started as soon as its level exists
+  // (events 0 .. kmax: the levels; then one per run), joined before the merged candidates
+  SidePool* sp = nullptr;
+  if (!batched) {
+    rc = side_pool(b->runs.size(), (size_t)kmax + 1 + b->runs.size(), &sp);
+    if (rc) return rc;
+    const hipError_t e = hipEventRecord(sp->events[0], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord (binned levels)");
+  }
   for (int k = 1; k <= kmax; ++k) {
     float* dst = reinterpret_cast<float*>(ws + L.level_off[k]);
     rc = dd_downfactor(lvl, lvl_dtype, b->nchan, nsamp >> (k - 1), lvl_stride, dst, L.level_row[k], stream);
     if (rc) return rc;
+    if (sp) {
+      const hipError_t e = hipEventRecord(sp->events[(size_t)k], st);
+      if (e != hipSuccess) return hip_fail(e, "hipEventRecord (binned levels)");
+    }
     level_ptr[k] = dst;
     level_stride[k] = L.level_row[k];
     lvl = dst;
@@ -2060,9 +2110,16 @@ int dd_binned_dedisperse(const dd_binned* b, const void* d_in, int64_t nsamp, in
       // k sets the thresholds the merged candidate pass reads; no candidate buffers here
       const Outputs o{d_out + (int64_t)r.d0 * out_row_stride, out_row_stride, stats ? d_mean + r.d0 : nullptr,
                       stats ? d_rms + r.d0 : nullptr, k_sigma, nullptr, 0, nullptr, 0};
+      hipStream_t side = sp->streams[i];
+      hipEvent_t done = sp->events[(size_t)kmax + 1 + i];
+      hipError_t e = hipStreamWaitEvent(side, sp->events[(size_t)r.k], 0);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent (binned run)");
       rc = run_pipeline(r.plan, in, reinterpret_cast<const int32_t*>(rw + L.run_l[i].table_off), L.nout[i], o, rw,
-                        L.run_l[i], st, true);
+                        L.run_l[i], side, true);
       if (rc) return rc;
+      e = hipEventRecord(done, side);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, done, 0);
+      if (e != hipSuccess) return hip_fail(e, "binned pass: joining a run");
     }
   }
   if (stats && k_sigma > 0.f && d_ncand) {
