@@ -550,7 +550,9 @@ int dd_subband_query(const dd_subband* sp, int64_t nsamp, int64_t* workspace_byt
 int dd_subband_upload(const dd_subband* sp, int64_t nsamp, void* d_workspace, int64_t ws_bytes, void* stream);
 /* One call over both steps; outputs and candidates as dd_binned_dedisperse (row d holds
    its group's nout; times in input samples). batched != 0 runs each step through one
-   dd_batch_dedisperse call (same results bit for bit). */
+   dd_batch_dedisperse call (same results bit for bit). Unbatched, the step-2 plans run on
+   four side streams of the calling host thread (as dd_binned_dedisperse's) and `stream`
+   waits for them. */
 int dd_subband_dedisperse(const dd_subband* sp, const float* d_in, int64_t nsamp, int64_t in_row_stride, float* d_out,
                           int64_t out_row_stride, float* d_mean, float* d_rms, float k_sigma, dd_cand* d_cand,
                           int64_t cand_cap, int64_t* d_ncand, int32_t batched, void* d_workspace, int64_t ws_bytes,

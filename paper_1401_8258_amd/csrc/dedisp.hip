@@ -2679,6 +2679,16 @@ int dd_subband_dedisperse(const dd_subband* sp, const float* d_in, int64_t nsamp
     rc = dd_batch_dedisperse(items.data(), (int32_t)items.size(), ws + L.batch_off, L.cand_off - L.batch_off, stream);
     if (rc) return rc;
   } else {
+    // the step-2 plans are independent once step 1 is done and each is a short launch: they
+    // go round-robin over a few side streams (the per-thread pool of the binned plans),
+    // joined before the merged candidates
+    constexpr size_t kSides = 4;
+    SidePool* pool = nullptr;
+    rc = side_pool(kSides, kSides + 1, &pool);
+    if (rc) return rc;
+    hipError_t e = hipEventRecord(pool->events[0], st);
+    for (size_t x = 0; e == hipSuccess && x < kSides; ++x) e = hipStreamWaitEvent(pool->streams[x], pool->events[0], 0);
+    if (e != hipSuccess) return hip_fail(e, "subband step 2: side streams");
     for (size_t g = 0; g < sp->step2.size(); ++g) {
       char* rw = ws + L.off2[g];
       const int32_t d0 = sp->groups[g].first;
@@ -2686,9 +2696,14 @@ int dd_subband_dedisperse(const dd_subband* sp, const float* d_in, int64_t nsamp
       const Outputs o{d_out + (int64_t)d0 * out_row_stride, out_row_stride, stats ? d_mean + d0 : nullptr,
                       stats ? d_rms + d0 : nullptr, k_sigma, nullptr, 0, nullptr, 0};
       rc = run_pipeline(sp->step2[g], in, reinterpret_cast<const int32_t*>(rw + L.l2[g].table_off), L.nout2[g], o, rw,
-                        L.l2[g], st, true);
+                        L.l2[g], pool->streams[g % kSides], true);
       if (rc) return rc;
     }
+    for (size_t x = 0; e == hipSuccess && x < kSides; ++x) {
+      e = hipEventRecord(pool->events[1 + x], pool->streams[x]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, pool->events[1 + x], 0);
+    }
+    if (e != hipSuccess) return hip_fail(e, "subband step 2: joining the side streams");
   }
   if (stats && k_sigma > 0.f && d_ncand) {
     std::vector<MergedRun> mr;
