@@ -1,4 +1,5 @@
-"""FP32 with producer wavefronts (the default for FP32 input, two of them; here also one):
+"""FP32 with producer wavefronts (the default for FP32 input, two of them; here also one,
+three and four):
 these wavefronts issue every LDS DMA while the others only compute. Results must equal the oracle to the FP32 tolerance on
 the edge shapes, on ragged stream pushes (ring input), and in a batched launch, where they
 must also equal the plan's own single calls bit for bit. Each case prints its shape first.
@@ -210,3 +211,45 @@ def test_four_trial_form_full_size_equals_default(torch, dd):
     assert torch.equal(r4.out, r8.out)
     assert torch.equal(r4.mean, r8.mean) and torch.equal(r4.rms, r8.rms)
     np.testing.assert_array_equal(r4.candidates(), r8.candidates())
+
+
+@pytest.mark.parametrize("tun", [(4, 13, 0, 3), (4, 12, 0, 4), (8, 5, 0, 3), (8, 4, 0, 4)])
+@pytest.mark.parametrize("nchan,df,ndm,step,nsamp,tuning,pad", NARROW)
+def test_three_and_four_producers_edges(torch, dd, tun, nchan, df, ndm, step, nsamp, tuning, pad):
+    """3 or 4 producer wavefronts, each taking whole channels of a stage (stage widths a
+    multiple of the producer count, channels past the last one repeating it): the oracle to
+    the FP32 tolerance, and the same trials with 2 producers bit for bit."""
+    print(f"case: f32 producers tuning={tun} nchan={nchan} ndm={ndm} step={step} nsamp={nsamp} pad={pad}",
+          flush=True)
+    freq = fbsynth.channel_freqs(428.0, df, nchan)
+    dm = fbsynth.dm_trials(0.0, step, ndm)
+    tab = orc.delay_table(freq, dm, 51.2e-6)
+    if nsamp <= int(tab.max()):
+        pytest.skip("shape shorter than the delay spread")
+    try:
+        plan = dd.Plan(freq, 51.2e-6, dm, tuning=tun)
+    except DedispError as e:
+        # a group of this many trials spans windows beyond the producers' 1024-word limit
+        assert "do not fit" in str(e)
+        return
+    ref_plan = dd.Plan(freq, 51.2e-6, dm, tuning=(tun[0], 0, 0, 2))
+    assert plan.producer_waves == tun[3] and plan.tiles[0] == tun[0]
+    for seed in range(nchan * 11 + ndm, nchan * 11 + ndm + 50):
+        rng = np.random.default_rng(seed)
+        full = np.zeros((nchan, nsamp + pad), np.float32)
+        full[:, :nsamp] = fbsynth.noise(rng, nchan, nsamp)
+        data = np.ascontiguousarray(full[:, :nsamp])
+        want = orc.dedisperse(data, tab)
+        mean, rms = orc.series_stats(want)
+        if orc.threshold_margin(want, mean, rms, 3.0) > 4 * GUARD:
+            break
+    xt = torch.from_numpy(full).cuda()[:, :nsamp]
+    res = plan.dedisperse(xt, k_sigma=3.0)
+    ref = ref_plan.dedisperse(xt, k_sigma=3.0)
+    torch.cuda.synchronize()
+    assert_rows_close(res.out.cpu().numpy(), want, rms, what=f"f32 producers {tun}")
+    assert_stats_close(res.mean.cpu().numpy(), res.rms.cpu().numpy(), mean, rms)
+    compare_candidates(res.candidates(), want, mean, rms, 3.0)
+    np.testing.assert_array_equal(res.out.cpu().numpy(), ref.out.cpu().numpy())
+    np.testing.assert_array_equal(res.mean.cpu().numpy(), ref.mean.cpu().numpy())
+    np.testing.assert_array_equal(res.rms.cpu().numpy(), ref.rms.cpu().numpy())
