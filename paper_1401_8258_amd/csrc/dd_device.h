@@ -20,6 +20,33 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
   return v;
 }
 
+// One DPP move of a double (both halves), from the lane that CTRL names within the row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_double(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over a whole wavefront (every lane active), valid in lane 0 only, with no LDS
+// instruction: a butterfly over each 16-lane row by DPP moves, then lane 0 adds the four
+// row sums. Row rotation by 8 pairs lane l with l ^ 8; after that step each row repeats
+// with period 8, so rotation by 4 pairs l with a copy of l ^ 4, and quad permutations
+// give xor 2 and xor 1. Lane 0 ends with the xor butterfly in the order 8, 4, 2, 1, 16,
+// 32: (row 0 + row 1) + (row 2 + row 3). A fixed tree, so results depend on the inputs only.
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+  v += dpp_double<0x128>(v);  // row_ror:8
+  v += dpp_double<0x124>(v);  // row_ror:4
+  v += dpp_double<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_double<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  return (v + readlane_double(v, 16)) + (readlane_double(v, 32) + readlane_double(v, 48));
+}
+
 // Exclusive scan of counts in tiles of 4096 by a 1024-thread block, each thread taking 4
 // consecutive ones, so every load and store of a wavefront covers one contiguous span. A
 // tile is scanned by wavefront shuffles and the 16 wavefront totals in LDS (part: at least

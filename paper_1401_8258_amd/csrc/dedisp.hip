@@ -235,7 +235,8 @@ __device__ __forceinline__ void stage_dma(const KParams& P, const DmaDesc& D, un
 }
 
 // Epilogue: the tile's sums to the output rows (float4 stores when aligned) and the
-// tile's FP64 statistics partials (fixed wavefront reduction tree).
+// tile's FP64 statistics partials (a fixed wavefront reduction tree of DPP moves, so the
+// LDS, which bounds the tile body, carries none of it).
 template <int G>
 __device__ __forceinline__ void store_tile(const KParams& P, const float (&acc)[G][8], int dw, int64_t t0,
                                            int64_t tile, int lane) {
@@ -268,8 +269,8 @@ __device__ __forceinline__ void store_tile(const KParams& P, const float (&acc)[
       }
     }
     if (P.part) {
-      s1 = wave_sum_fixed(s1);
-      s2 = wave_sum_fixed(s2);
+      s1 = dd::wave_sum_lane0(s1);
+      s2 = dd::wave_sum_lane0(s2);
       if (lane == 0) {
         P.part[((int64_t)d * nseg + tile) * 2] = s1;
         P.part[((int64_t)d * nseg + tile) * 2 + 1] = s2;
